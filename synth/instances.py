@@ -1,0 +1,374 @@
+"""Seeded synthetic instances of the per-day DODE non-negative least-squares problem.
+
+Every array here is an *input*: the static link/OD incidence pattern, the lag
+ratios of each cluster's assignment matrix, the planted demand, the observed
+link counts and the per-epoch row permutations.  Nothing in this module runs any
+step of the SPGD solver (no residual, gradient, step or projection); the
+observation model x = rho q* + noise is data synthesis, done with dense-block
+BLAS products or, for small cases, element loops in a fixed order.
+
+Shapes follow the paper's discretisation (section "Tensor representation",
+Table "DODE framework variable vectorization"): per day the OD vector is
+q[t][p] (interval-major, OD-minor), the link vector is x[h][a].  The
+assignment matrix of cluster c is stored as lag-band blocks: entry
+rho[(t+l)*L + a, t*P + p] = W_c[l][t][nz] where nz indexes the (a, p) pair in
+the incidence pattern (CSR, rows = links, sorted columns).  Blocks with
+t + l >= H are absent (midnight spill-over dropped, section "Estimate the
+dynamic OD demand").
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+import math
+
+import numpy as np
+
+BASE_SEED = 190109266
+
+# Synthetic workloads.  Sizes, densities and hyper-parameters follow the five
+# benchmark configurations; constants that the paper leaves open are listed in
+# DESIGN.md ("Input recipe").
+CONFIGS = {
+    1: dict(P=4, L=6, T=12, K=3, sizes=(7,), inc=0.5, pattern="bernoulli",
+            demand="uniform50", noise="add1", x_dtype="f64",
+            optimizer="fixed", epochs=200, batch_rows=8192, eta=None),
+    2: dict(P=50, L=200, T=288, K=6, sizes=(365,), inc=0.10, pattern="corridor",
+            demand="gamma", noise="mult5", x_dtype="f32",
+            optimizer="adagrad", epochs=300, batch_rows=8192, eta=5.0, day_tile=32),
+    3: dict(P=150, L=500, T=288, K=6, sizes=(400, 250, 150, 120, 80, 50, 30, 15),
+            inc=0.08, pattern="corridor", demand="gamma", noise="mult5", x_dtype="f32",
+            optimizer="adagrad", epochs=300, batch_rows=8192, eta=5.0),
+    5: dict(P=400, L=1500, T=288, K=6,
+            sizes=(300, 200, 150, 110, 90, 70, 50, 40, 30, 25, 20, 10),
+            inc=0.08, pattern="corridor", demand="gamma", noise="mult5", x_dtype="f32",
+            optimizer="adagrad", epochs=300, batch_rows=8192, eta=5.0),
+}
+
+
+@dataclass
+class Instance:
+    P: int
+    L: int
+    T: int
+    H: int
+    K: int
+    sizes: tuple
+    day_cluster: np.ndarray      # int32 [D]
+    row_ptr: np.ndarray          # int32 [L+1]   incidence pattern, CSR by link
+    col_idx: np.ndarray          # int32 [nnz]   OD index of each pattern entry
+    W: list                      # per cluster float64 [K][T][nnz] lag-band values
+    qstar: np.ndarray            # float64 [D][T][P] planted demand
+    x0: object                   # float64 [D][H][L] noiseless observations (None for large instances)
+    x: np.ndarray                # [D][H][L] observations (float64 or float32)
+    seed: int
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def D(self) -> int:
+        return int(self.day_cluster.shape[0])
+
+    @property
+    def C(self) -> int:
+        return len(self.sizes)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col_idx.shape[0])
+
+    def row_of_nz(self) -> np.ndarray:
+        return np.repeat(np.arange(self.L, dtype=np.int32), np.diff(self.row_ptr))
+
+    def dense_blocks(self, c: int) -> np.ndarray:
+        """[K][T][L][P] dense copy of cluster c's lag blocks (small instances only)."""
+        B = np.zeros((self.K, self.T, self.L, self.P))
+        rows = self.row_of_nz()
+        B[:, :, rows, self.col_idx] = self.W[c]
+        return B
+
+    def days_of(self, c: int) -> np.ndarray:
+        return np.nonzero(self.day_cluster == c)[0].astype(np.int32)
+
+
+@dataclass
+class RouteInstance:
+    """Path-level description for the route-choice parameterisation.
+
+    Path k serves OD path_od[k] and crosses links pair_link[pair_ptr[k]:pair_ptr[k+1]];
+    R[c][l][t][m] is the lag ratio of path-link pair m (normalised over l).  The
+    OD-level pattern (row_ptr, col_idx) is the union of the path incidences, and
+    pair_nz[m] is the pattern entry that pair m feeds.
+    """
+    P: int
+    L: int
+    T: int
+    H: int
+    K: int
+    n_paths: int
+    path_od: np.ndarray          # int32 [n_paths]
+    pair_ptr: np.ndarray         # int32 [n_paths+1]
+    pair_link: np.ndarray        # int32 [n_pairs]
+    pair_nz: np.ndarray          # int32 [n_pairs]
+    row_ptr: np.ndarray          # int32 [L+1]
+    col_idx: np.ndarray          # int32 [nnz]
+    R: list                      # per cluster float64 [K][T][n_pairs]
+    pi_true: list                # per cluster float64 [n_paths] true route proportions
+    z0: list                     # per cluster float64 [n_paths] starting logits
+    qstar: np.ndarray
+    x: np.ndarray
+    day_cluster: np.ndarray
+    sizes: tuple
+    seed: int
+
+    @property
+    def n_pairs(self) -> int:
+        return int(self.pair_link.shape[0])
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col_idx.shape[0])
+
+    @property
+    def D(self) -> int:
+        return int(self.day_cluster.shape[0])
+
+
+def chunk_h_blocks(L: int, H: int, batch_rows: int) -> int:
+    """Whole interval blocks per minibatch: floor(b / L), at least 1, at most H."""
+    return int(min(H, max(1, batch_rows // L)))
+
+
+def _pattern_csr(S: np.ndarray):
+    L = S.shape[0]
+    row_ptr = np.zeros(L + 1, dtype=np.int32)
+    row_ptr[1:] = np.cumsum(S.sum(axis=1))
+    _, cols = np.nonzero(S)
+    return row_ptr, cols.astype(np.int32)
+
+
+def _incidence(rng, L, P, inc, pattern):
+    if pattern == "bernoulli":
+        S = rng.random((L, P)) < inc
+        while True:
+            empty = np.nonzero(~S.any(axis=0))[0]
+            if empty.size == 0:
+                break
+            S[:, empty] = rng.random((L, empty.size)) < inc
+        return S
+    if pattern == "corridor":
+        # Four corridor-directions of L/4 consecutive links; each OD takes a
+        # contiguous route of round(inc*L) links in one of them.  ODs sorted by
+        # (corridor, origin).
+        ncor = 4 if L >= 4 else 1
+        seg = L // ncor
+        m = max(1, int(round(inc * L)))
+        if m > seg:
+            raise ValueError("route longer than a corridor")
+        cor = rng.integers(0, ncor, size=P)
+        org = rng.integers(0, seg - m + 1, size=P)
+        order = np.lexsort((org, cor))
+        cor, org = cor[order], org[order]
+        S = np.zeros((L, P), dtype=bool)
+        for p in range(P):
+            s0 = cor[p] * seg + org[p]
+            S[s0:s0 + m, p] = True
+        return S
+    raise ValueError(pattern)
+
+
+def _lag_ratios(rng, K, T, H, n):
+    """[K][T][n] ratios: U(0,1) per lag, normalised over the K lags, then lags
+    that land past the last interval are dropped (their mass leaves the day)."""
+    w = rng.random((T, n, K))
+    w /= w.sum(axis=2, keepdims=True)
+    W = np.ascontiguousarray(w.transpose(2, 0, 1))
+    for l in range(K):
+        if H - l < T:
+            W[l, max(H - l, 0):, :] = 0.0
+    return W
+
+
+def _profile(T):
+    tau = np.arange(T) * (24.0 / T)
+    prof = 0.2 + np.exp(-(tau - 8.0) ** 2 / 2.0) + 0.9 * np.exp(-(tau - 17.5) ** 2 / (2 * 1.25 ** 2))
+    return prof / prof.mean()
+
+
+class _BandCSR:
+    """Row-compressed layout of the full (H*L) x (T*P) band matrix of one pattern.
+    Built once per pattern; `src` maps each CSR slot to its flat [K][T][nnz] value."""
+
+    def __init__(self, P, L, T, H, K, row_ptr, col_idx):
+        import scipy.sparse as sp
+        rows = np.repeat(np.arange(L, dtype=np.int64), np.diff(row_ptr))
+        nnz = col_idx.shape[0]
+        R, C, V = [], [], []
+        for l in range(K):
+            tmax = min(T, H - l)
+            if tmax <= 0:
+                continue
+            tt = np.arange(tmax, dtype=np.int64)
+            R.append(((tt[:, None] + l) * L + rows[None, :]).ravel())
+            C.append((tt[:, None] * P + col_idx[None, :].astype(np.int64)).ravel())
+            V.append((l * T * nnz + tt[:, None] * nnz + np.arange(nnz)[None, :]).ravel())
+        src = np.concatenate(V).astype(np.float64) + 1.0
+        M = sp.csr_matrix((src, (np.concatenate(R), np.concatenate(C))), shape=(H * L, T * P))
+        self.indptr, self.indices = M.indptr, M.indices
+        self.src = (M.data - 1.0).astype(np.int64)
+        self.shape = (H * L, T * P)
+
+    def product(self, Wc, Q):
+        """[n][H][L] link counts of the days in Q ([n][T][P])."""
+        import scipy.sparse as sp
+        M = sp.csr_matrix((Wc.ravel()[self.src], self.indices, self.indptr), shape=self.shape)
+        n = Q.shape[0]
+        Y = M @ np.ascontiguousarray(Q.reshape(n, -1).T)
+        return np.ascontiguousarray(Y.T)
+
+
+def _observe(P, L, T, H, K, row_ptr, col_idx, Wc, Q, band=None):
+    """Noiseless link counts of the days in Q ([n][T][P]) under one cluster's blocks."""
+    n = Q.shape[0]
+    if K * T * L * P > 2_000_000:
+        band = band or _BandCSR(P, L, T, H, K, row_ptr, col_idx)
+        return band.product(Wc, Q).reshape(n, H, L)
+    X0 = np.zeros((n, H, L))
+    rows = np.repeat(np.arange(L), np.diff(row_ptr))
+    for l in range(K):
+        for t in range(min(T, H - l)):
+            # fixed-order element loop over the pattern entries
+            contrib = Wc[l, t][None, :] * Q[:, t, col_idx]                # [n][nnz]
+            for j in range(rows.shape[0]):
+                X0[:, t + l, rows[j]] += contrib[:, j]
+    return X0
+
+
+def make_instance(P, L, T, K, sizes, inc, pattern="corridor", demand="gamma", noise="mult5",
+                  x_dtype="f32", seed=BASE_SEED, H=None, planted_zero_frac=0.0, keep_x0=False,
+                  **_ignored):
+    H = T if H is None else H
+    rng = np.random.Generator(np.random.PCG64(seed))
+    S = _incidence(rng, L, P, inc, pattern)
+    row_ptr, col_idx = _pattern_csr(S)
+    nnz = col_idx.shape[0]
+    C = len(sizes)
+    W = [_lag_ratios(rng, K, T, H, nnz) for _ in range(C)]
+    D = int(sum(sizes))
+    day_cluster = np.repeat(np.arange(C, dtype=np.int32), sizes)
+    if demand == "uniform50":
+        qstar = rng.uniform(0.0, 50.0, size=(D, T, P))
+    elif demand == "gamma":
+        qstar = rng.standard_gamma(2.0, size=(D, T, P), dtype=np.float32).astype(np.float64)
+        qstar *= 10.0 * _profile(T)[None, :, None]
+    else:
+        raise ValueError(demand)
+    if planted_zero_frac > 0:
+        qstar[rng.random(qstar.shape) < planted_zero_frac] = 0.0
+    big = K * T * L * P > 2_000_000
+    band = _BandCSR(P, L, T, H, K, row_ptr, col_idx) if big else None
+    keep = keep_x0 or not big
+    x0 = np.empty((D, H, L)) if keep else None
+    x = np.empty((D, H, L), dtype=np.float32 if x_dtype == "f32" else np.float64)
+    for c in range(C):
+        d = np.nonzero(day_cluster == c)[0]
+        x0c = _observe(P, L, T, H, K, row_ptr, col_idx, W[c], qstar[d], band)
+        if keep:
+            x0[d] = x0c
+        # observation noise, drawn cluster by cluster
+        if noise == "add1":
+            x0c += rng.standard_normal(x0c.shape)
+        elif noise == "mult5":
+            x0c *= 1.0 + 0.05 * rng.standard_normal(x0c.shape, dtype=np.float32)
+        elif noise != "none":
+            raise ValueError(noise)
+        np.maximum(x0c, 0.0, out=x0c)
+        x[d] = x0c
+        del x0c
+    return Instance(P=P, L=L, T=T, H=H, K=K, sizes=tuple(int(s) for s in sizes),
+                    day_cluster=day_cluster, row_ptr=row_ptr, col_idx=col_idx, W=W,
+                    qstar=qstar, x0=x0, x=x, seed=seed,
+                    meta=dict(inc=inc, pattern=pattern, demand=demand, noise=noise))
+
+
+def make_config(cid: int, sizes=None, pattern=None, seed=None) -> Instance:
+    """Instance for one benchmark configuration (optionally with fewer days or
+    the Bernoulli stress pattern).  Seed = 190109266 + 100 * config id."""
+    cfg = dict(CONFIGS[cid])
+    if sizes is not None:
+        cfg["sizes"] = tuple(sizes)
+    if pattern is not None:
+        cfg["pattern"] = pattern
+    s = BASE_SEED + 100 * cid if seed is None else seed
+    inst = make_instance(seed=s, **cfg)
+    inst.meta.update(config=cid, epochs=cfg["epochs"], batch_rows=cfg["batch_rows"],
+                     optimizer=cfg["optimizer"], eta=cfg["eta"])
+    return inst
+
+
+def make_perms(seed: int, E: int, C: int, H: int) -> np.ndarray:
+    """int32 [E][C][H]: one Fisher-Yates shuffle of the H interval blocks per (epoch, cluster)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = np.empty((E, C, H), dtype=np.int32)
+    for e in range(E):
+        for c in range(C):
+            out[e, c] = rng.permutation(H)
+    return out
+
+
+def make_row_perms(seed: int, E: int, n_rows: int) -> np.ndarray:
+    """int32 [E][n_rows]: row-level shuffles for the paper-literal row minibatches."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.stack([rng.permutation(n_rows) for _ in range(E)]).astype(np.int32)
+
+
+def make_route_instance(P=4, L=6, T=12, K=3, n_paths=150, sizes=(7,), link_prob=0.5,
+                        seed=BASE_SEED + 400, noise="add1") -> RouteInstance:
+    """Route-choice workload: n_paths candidate paths spread over the P ODs, each
+    with a Bernoulli(link_prob) non-empty link set and its own lag ratios.  True
+    route proportions are Dirichlet(1) per OD; starting logits are N(0,1)."""
+    H = T
+    rng = np.random.Generator(np.random.PCG64(seed))
+    path_od = np.repeat(np.arange(P, dtype=np.int32), [len(a) for a in np.array_split(np.arange(n_paths), P)])
+    links = []
+    for k in range(n_paths):
+        while True:
+            m = rng.random(L) < link_prob
+            if m.any():
+                break
+        links.append(np.nonzero(m)[0].astype(np.int32))
+    pair_ptr = np.zeros(n_paths + 1, dtype=np.int32)
+    pair_ptr[1:] = np.cumsum([len(a) for a in links])
+    pair_link = np.concatenate(links).astype(np.int32)
+    pair_path = np.repeat(np.arange(n_paths), np.diff(pair_ptr))
+    S = np.zeros((L, P), dtype=bool)
+    S[pair_link, path_od[pair_path]] = True
+    row_ptr, col_idx = _pattern_csr(S)
+    nzmap = -np.ones((L, P), dtype=np.int64)
+    rows = np.repeat(np.arange(L), np.diff(row_ptr))
+    nzmap[rows, col_idx] = np.arange(col_idx.shape[0])
+    pair_nz = nzmap[pair_link, path_od[pair_path]].astype(np.int32)
+    C = len(sizes)
+    R = [_lag_ratios(rng, K, T, H, pair_link.shape[0]) for _ in range(C)]
+    pi_true, z0 = [], []
+    for c in range(C):
+        pi = np.empty(n_paths)
+        for p in range(P):
+            ks = np.nonzero(path_od == p)[0]
+            pi[ks] = rng.dirichlet(np.ones(ks.size))
+        pi_true.append(pi)
+        z0.append(rng.standard_normal(n_paths))
+    D = int(sum(sizes))
+    day_cluster = np.repeat(np.arange(C, dtype=np.int32), sizes)
+    qstar = rng.uniform(0.0, 50.0, size=(D, T, P))
+    x = np.empty((D, H, L))
+    for c in range(C):
+        # true assignment of cluster c: path ratios weighted by true proportions
+        Wc = np.zeros((K, T, col_idx.shape[0]))
+        np.add.at(Wc, (slice(None), slice(None), pair_nz), R[c] * pi_true[c][pair_path][None, None, :])
+        d = np.nonzero(day_cluster == c)[0]
+        x[d] = _observe(P, L, T, H, K, row_ptr, col_idx, Wc, qstar[d])
+    if noise == "add1":
+        x = np.maximum(0.0, x + rng.standard_normal(x.shape))
+    return RouteInstance(P=P, L=L, T=T, H=H, K=K, n_paths=n_paths, path_od=path_od,
+                         pair_ptr=pair_ptr, pair_link=pair_link, pair_nz=pair_nz,
+                         row_ptr=row_ptr, col_idx=col_idx, R=R, pi_true=pi_true, z0=z0,
+                         qstar=qstar, x=x, day_cluster=day_cluster, sizes=tuple(sizes), seed=seed)
