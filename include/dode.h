@@ -1,0 +1,178 @@
+/*
+ * dode.h -- C ABI of the MI355X library for the per-day dynamic OD estimation
+ * problem of Ma & Qian, "Estimating multi-year 24/7 origin-destination demand
+ * using high-granular multi-source traffic data" (arXiv 1901.09266).
+ *
+ * The library solves, for every day d of traffic-pattern cluster c,
+ *     min_{q_d >= 0} || rho_c q_d - x_d ||_2^2          (eq. "nnls")
+ * with the stochastic projected gradient descent of Algorithm 1 ("SPGD"),
+ * batched over days (days are independent subproblems, section "Estimate the
+ * dynamic OD demand").
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Dimensions: P OD pairs, L observed links, T departure intervals, H
+ *    observation intervals, K lag band (rho_c has a nonzero block for
+ *    departure interval t and observation interval h only if 0 <= h-t < K).
+ *  - Per-day vectors are interval-major (Table "DODE framework variable
+ *    vectorization"): demand q[t][p] (T*P values), counts x[h][a] (H*L values).
+ *    A batch of n days is day-major: Q[n][T][P], X[n][H][L].
+ *  - rho_c is given by a static incidence pattern shared by all clusters (CSR
+ *    over links: row_ptr[L+1], col_idx[nnz] = the ODs whose route crosses link
+ *    a, strictly increasing within a row) and per-cluster values W_c[K][T][nnz]:
+ *        rho_c[(t+l)*L + a, t*P + p] = W_c[l][t][nz(a,p)]     (eq. "assign")
+ *    Values of blocks with t+l >= H are ignored (spill-over past the last
+ *    interval is dropped).
+ *  - State type: a handle created with storage DODE_F64 works on double
+ *    Q, X, A, G, Xhat buffers; every other storage works on float buffers.
+ *  - Device buffers (Q, X, A, G, Xhat, loss outputs marked "dev") are owned by
+ *    the caller and are never freed by the library.  Host buffers are read or
+ *    written before the call returns unless stated otherwise.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue work
+ *    on it and return; calls that return host results synchronise it.
+ *  - Argument and shape errors are detected before any launch and returned as
+ *    a status; HIP failures return DODE_ERR_HIP.  dode_last_error() gives the
+ *    message of the last failing call of the calling thread.  No C++
+ *    exception crosses this interface.
+ *  - A handle is immutable after creation except through dar_set_values;
+ *    concurrent calls that only read one handle are safe.
+ */
+#ifndef DODE_H
+#define DODE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DODE_OK = 0,
+  DODE_ERR_ARG = 1,         /* NULL pointer, bad enum or parameter value */
+  DODE_ERR_SHAPE = 2,       /* inconsistent dimensions or pattern */
+  DODE_ERR_DTYPE = 3,       /* storage type not usable for this call */
+  DODE_ERR_NONFINITE = 4,   /* NaN or Inf in the observations or values */
+  DODE_ERR_OOM = 5,         /* device allocation failed */
+  DODE_ERR_HIP = 6,         /* a HIP runtime call failed */
+  DODE_ERR_UNSUPPORTED = 7  /* valid request this build does not implement */
+} dode_status;
+
+typedef enum {
+  DODE_F64 = 0,       /* values and state in double */
+  DODE_F32 = 1,       /* values and state in float */
+  DODE_BF16 = 2,      /* values bfloat16 (round to nearest even), state float */
+  DODE_FP8_E4M3 = 3   /* values OCP E4M3FN with one float scale per (cluster, l, t,
+                         64-OD column tile); state float */
+} dode_dtype;
+
+typedef struct {
+  int32_t P, L, T, H, K;
+} dode_dims;
+
+typedef struct dode_dar dode_dar;   /* opaque, library-owned */
+
+typedef struct {
+  int32_t epochs;      /* E, number of passes over the rows (paper: 300) */
+  int32_t batch_rows;  /* b, rows per minibatch (paper: 8192); rounded down to
+                          whole observation intervals: b_h = max(1, b / L) */
+  double eta;          /* learning rate (paper: 5) */
+  double eps;          /* Adagrad denominator offset, added after the square root */
+  int32_t optimizer;   /* 0 = Adagrad (Algorithm 1), 1 = fixed step q -= eta g */
+  int32_t check_finite;/* nonzero: scan X for NaN/Inf before solving */
+} dode_spgd_params;
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* dode_last_error(void);
+
+/* Fill p with the defaults: epochs 300, batch_rows 8192, eta 5, eps 1e-10,
+ * Adagrad, check_finite 1 (section "Goodness of fit" gives E, b and eta). */
+void dode_spgd_defaults(dode_spgd_params* p);
+
+/*
+ * Build a device copy of the assignment matrices rho_c of n_clusters clusters
+ * (eq. "assign"; the COO sparse layout of section "Tensor representation" is
+ * replaced by the band form described above).
+ *   dims            P, L, T, H, K (all >= 1)
+ *   row_ptr, col_idx  host CSR incidence pattern (see conventions)
+ *   values          host array of n_clusters pointers, each to FP64 [K][T][nnz]
+ *   storage         value type kept on the device
+ *   out             receives the handle; release it with dar_destroy
+ * Errors: DODE_ERR_SHAPE for a malformed pattern, DODE_ERR_NONFINITE for
+ * non-finite values, DODE_ERR_OOM, DODE_ERR_HIP.  Synchronises `stream`.
+ */
+dode_status dar_create(const dode_dims* dims, int32_t n_clusters, const int32_t* row_ptr,
+                       const int32_t* col_idx, const double* const* values, dode_dtype storage,
+                       void* stream, dode_dar** out);
+
+/* Free a handle (NULL is a no-op).  The caller must have finished every call
+ * that uses it. */
+dode_status dar_destroy(dode_dar* dar);
+
+/* Shape, cluster count, pattern size, storage type and device bytes of a handle.
+ * Any output pointer may be NULL. */
+dode_status dar_info(const dode_dar* dar, dode_dims* dims, int32_t* n_clusters, int64_t* nnz,
+                     dode_dtype* storage, int64_t* device_bytes);
+
+/* Replace cluster c's values with the device array W_dev (state type,
+ * [K][T][nnz]) -- used when rho_c is a learned function of route logits.
+ * For reduced storage the values are rounded (and FP8 scales recomputed) on
+ * the device.  Asynchronous on `stream`. */
+dode_status dar_set_values(dode_dar* dar, int32_t cluster, const void* W_dev, void* stream);
+
+/* Xhat = rho_c Q for n_days days of cluster c (eq. "finalobj").
+ *   Q dev [n][T][P], Xhat dev [n][H][L], state type. */
+dode_status dode_apply(const dode_dar* dar, int32_t cluster, const void* Q, int32_t n_days,
+                       void* Xhat, void* stream);
+
+/* loss[d] = || rho_c q_d - x_d ||^2 per day (eq. "nnls"), accumulated in FP64
+ * in a fixed order (bitwise reproducible).  loss dev double [n]. */
+dode_status dode_loss(const dode_dar* dar, int32_t cluster, const void* Q, const void* X,
+                      int32_t n_days, double* loss, void* stream);
+
+/* G = rho_c^T (rho_c Q - X), Algorithm 1's gradient (half the gradient of the
+ * loss).  G dev [n][T][P], state type. */
+dode_status dode_grad(const dode_dar* dar, int32_t cluster, const void* Q, const void* X,
+                      int32_t n_days, void* G, void* stream);
+
+/* End-of-solve figures per day (Step 6 "Quality check"), all FP64 dev [n],
+ * each may be NULL:  loss as dode_loss;  kkt = max_i |min(q_i, g_i)| with the
+ * full gradient g;  r2 = 1 - sum (x - xhat)^2 / sum (x - mean x)^2. */
+dode_status dode_metrics(const dode_dar* dar, int32_t cluster, const void* Q, const void* X,
+                         int32_t n_days, double* loss, double* kkt, double* r2, void* stream);
+
+/*
+ * One minibatch of Algorithm 1 for n_days days of cluster c, on the rows of
+ * the n_h observation intervals chunk_h (host, distinct, each in [0, H)):
+ *   g = rho_o^T (rho_o q - x_o)  with rho_o the chunk's rows,
+ *   Adagrad (A += g*g; q -= eta g / (sqrt(A) + eps)) or fixed step, q = max(q, 0).
+ * Only the coordinates (t, p) that the chunk reaches (h - K < t <= h) are
+ * written; the others have g = 0 and keep their value (the same as the
+ * algorithm when Q >= 0 on entry).  X dev, Q and A dev (in/out), state type.
+ */
+dode_status spgd_step(const dode_dar* dar, int32_t cluster, const int32_t* chunk_h, int32_t n_h,
+                      const void* X, void* Q, void* A, int32_t n_days,
+                      const dode_spgd_params* params, void* stream);
+
+/*
+ * Algorithm 1 for D days of any clusters in one call (all clusters advance
+ * together, one minibatch at a time).
+ *   day_cluster  host [D], cluster of each day
+ *   X dev [D][H][L]; Q, A dev [D][T][P] (in/out; pass A = 0 and the starting
+ *                Q, e.g. 0, to start fresh; Q is projected onto Q >= 0 first)
+ *   perm         host [E][C][H]: the permutation of the H observation
+ *                intervals of each (epoch, cluster); NULL = drawn by the library
+ *                from `seed` (SplitMix64 + Fisher-Yates)
+ *   loss_hist    host [D][E] or NULL: full loss of each day after each epoch
+ *                (costs one extra forward pass per epoch; synchronises stream)
+ * The minibatches of epoch e and cluster c are consecutive slices of b_h
+ * intervals of perm[e][c]; the last may be shorter.
+ */
+dode_status spgd_solve(const dode_dar* dar, const int32_t* day_cluster, int32_t D, const void* X,
+                       void* Q, void* A, const dode_spgd_params* params, const int32_t* perm,
+                       uint64_t seed, double* loss_hist, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DODE_H */

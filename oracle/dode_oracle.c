@@ -167,6 +167,27 @@ static void spgd_minibatch(const orc_dims* dm, const int32_t* row_ptr, const int
   }
 }
 
+/* One minibatch of Algorithm 1 on the rows of the n_h observation intervals
+ * hblocks[] (all L rows of each, in the order given). */
+int orc_spgd_step(const orc_dims* dm, const int32_t* row_ptr, const int32_t* col, const double* W,
+                  const double* x, double* q, double* A, const int32_t* hblocks, int32_t n_h,
+                  int32_t optimizer, double eta, double eps) {
+  const int64_t nrows = (int64_t)n_h * dm->L;
+  int64_t* rows = (int64_t*)malloc(sizeof(int64_t) * (size_t)nrows);
+  double* r = (double*)malloc(sizeof(double) * (size_t)nrows);
+  double* g = (double*)malloc(sizeof(double) * (size_t)dm->T * dm->P);
+  if (!rows || !r || !g) {
+    free(rows); free(r); free(g);
+    return 2;
+  }
+  int64_t k = 0;
+  for (int32_t i = 0; i < n_h; ++i)
+    for (int a = 0; a < dm->L; ++a) rows[k++] = (int64_t)hblocks[i] * dm->L + a;
+  spgd_minibatch(dm, row_ptr, col, W, x, q, A, rows, nrows, optimizer, eta, eps, r, g);
+  free(rows); free(r); free(g);
+  return 0;
+}
+
 /*
  * O4: Algorithm 1 for one day.
  *   granularity 0: the permuted units are interval blocks (all L rows of an

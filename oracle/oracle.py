@@ -33,8 +33,8 @@ _SRC = os.path.join(_HERE, "dode_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 __all__ = ["build_oracle", "Dims", "apply", "adjoint", "loss", "grad", "kkt", "r2", "spgd_day",
-           "spgd", "metrics", "route_softmax", "rho_from_logits", "loss_backward",
-           "logits_backward", "lib"]
+           "spgd_step", "spgd", "metrics", "route_softmax", "rho_from_logits", "loss_backward",
+           "logits_backward", "fixed_step_eta", "lib"]
 
 
 def build_oracle(force: bool = True) -> str:
@@ -71,6 +71,8 @@ def lib():
         L.orc_spgd_day.argtypes = [dims, iptr, iptr, dptr, dptr, dptr, dptr, iptr, ctypes.c_int64,
                                    ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                    ctypes.c_double, ctypes.c_double, dptr]
+        L.orc_spgd_step.argtypes = [dims, iptr, iptr, dptr, dptr, dptr, dptr, iptr, ctypes.c_int32,
+                                    ctypes.c_int32, ctypes.c_double, ctypes.c_double]
         L.orc_spgd.argtypes = [dims, ctypes.c_int32, iptr, iptr, iptr, P(dptr), dptr, dptr, dptr,
                                iptr, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                                ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
@@ -214,6 +216,21 @@ def spgd_day(inst, W, x, perm, E, chunk, q0=None, A0=None, granularity=0, optimi
     return q, A, hist
 
 
+def spgd_step(inst, W, x, q, A, hblocks, optimizer=0, eta=5.0, eps=1e-10):
+    """One minibatch on the rows of the listed observation intervals; returns (q, A)."""
+    pt = _pat(inst)
+    W, Wp = _d(W)
+    x, xp = _d(x)
+    q = np.array(q, dtype=np.float64, copy=True)
+    A = np.array(A, dtype=np.float64, copy=True)
+    hb, hbp = _i(hblocks)
+    rc = lib().orc_spgd_step(pt.dims, pt.rp_p, pt.ci_p, Wp, xp, _d(q)[1], _d(A)[1], hbp, hb.size,
+                             optimizer, eta, eps)
+    if rc != 0:
+        raise RuntimeError("orc_spgd_step failed")
+    return q, A
+
+
 def spgd(inst, x, perm, E, chunk, days=None, q0=None, A0=None, granularity=0, optimizer=0,
          eta=5.0, eps=1e-10, record_loss=True, nthreads=None, W=None):
     """Algorithm 1 on many days of `inst` (all, or the index list `days`), OpenMP over days.
@@ -316,3 +333,17 @@ def logits_backward(ri, c, z, dW):
     if rc != 0:
         raise RuntimeError("pair not in pattern")
     return dz
+
+
+def fixed_step_eta(inst, c=0, iters=200):
+    """Fixed step 1/lambda_max(rho^T rho) for cluster c: lambda_max from `iters`
+    FP64 power-iteration steps on g = rho^T rho v starting at all ones."""
+    W = inst.W[c]
+    v = np.ones((inst.T, inst.P))
+    lam = 0.0
+    zero = np.zeros((inst.H, inst.L))
+    for _ in range(iters):
+        w = grad(inst, W, v, zero)          # rho^T (rho v - 0)
+        lam = float(np.sqrt(np.sum(w * w)) / np.sqrt(np.sum(v * v)))
+        v = w / np.sqrt(np.sum(w * w))
+    return 1.0 / lam

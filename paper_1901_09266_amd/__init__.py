@@ -1,0 +1,12 @@
+"""MI355X library for the SPGD solve of the per-day DODE NNLS (arXiv 1901.09266).
+
+The computation lives in libdode.so (HIP kernels for gfx950 behind the C ABI of
+include/dode.h); this package is its Python binding.
+"""
+from ._lib import (DodeError, Dar, SpgdParams, STORAGE, EXPORTS, lib, dar_create, dar_info,
+                   dar_set_values, dode_apply, dode_loss, dode_grad, dode_metrics, spgd_step,
+                   spgd_solve, spgd_defaults, make_params)
+
+__all__ = ["DodeError", "Dar", "SpgdParams", "STORAGE", "EXPORTS", "lib", "dar_create", "dar_info",
+           "dar_set_values", "dode_apply", "dode_loss", "dode_grad", "dode_metrics", "spgd_step",
+           "spgd_solve", "spgd_defaults", "make_params"]

@@ -1,0 +1,249 @@
+"""ctypes binding of libdode.so: the C ABI of include/dode.h with the same names.
+
+Only argument marshalling happens here (shape/dtype/device checks, pointers,
+the current HIP stream); every step of the computation runs in the library's
+kernels.  Tensors are torch tensors on the GPU; the library reads and writes
+their memory in place.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libdode.so")
+
+DODE_OK, DODE_ERR_ARG, DODE_ERR_SHAPE, DODE_ERR_DTYPE, DODE_ERR_NONFINITE, DODE_ERR_OOM, \
+    DODE_ERR_HIP, DODE_ERR_UNSUPPORTED = range(8)
+STATUS_NAMES = ["DODE_OK", "DODE_ERR_ARG", "DODE_ERR_SHAPE", "DODE_ERR_DTYPE",
+                "DODE_ERR_NONFINITE", "DODE_ERR_OOM", "DODE_ERR_HIP", "DODE_ERR_UNSUPPORTED"]
+DODE_F64, DODE_F32, DODE_BF16, DODE_FP8_E4M3 = range(4)
+STORAGE = {"f64": DODE_F64, "f32": DODE_F32, "bf16": DODE_BF16, "fp8": DODE_FP8_E4M3}
+
+# Every symbol include/dode.h declares (checked by the CPU test suite).
+EXPORTS = ["dode_last_error", "dode_spgd_defaults", "dar_create", "dar_destroy", "dar_info",
+           "dar_set_values", "dode_apply", "dode_loss", "dode_grad", "dode_metrics", "spgd_step",
+           "spgd_solve"]
+
+
+class DodeError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        self.status = status
+        name = STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else str(status)
+        super().__init__(f"{name}: {msg}")
+
+
+class Dims(ctypes.Structure):
+    _fields_ = [("P", ctypes.c_int32), ("L", ctypes.c_int32), ("T", ctypes.c_int32),
+                ("H", ctypes.c_int32), ("K", ctypes.c_int32)]
+
+
+class SpgdParams(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int32), ("batch_rows", ctypes.c_int32), ("eta", ctypes.c_double),
+                ("eps", ctypes.c_double), ("optimizer", ctypes.c_int32),
+                ("check_finite", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libdode.so; raise if it has not been built (no fallback path exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_1901_09266_amd.build` (hipcc, gfx950)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        P = ctypes.POINTER
+        L.dode_last_error.restype = ctypes.c_char_p
+        L.dode_spgd_defaults.argtypes = [P(SpgdParams)]
+        L.dode_spgd_defaults.restype = None
+        L.dar_create.argtypes = [P(Dims), i32, P(i32), P(i32), P(P(dbl)), i32, vp, P(vp)]
+        L.dar_destroy.argtypes = [vp]
+        L.dar_info.argtypes = [vp, P(Dims), P(i32), P(i64), P(i32), P(i64)]
+        L.dar_set_values.argtypes = [vp, i32, vp, vp]
+        L.dode_apply.argtypes = [vp, i32, vp, i32, vp, vp]
+        L.dode_loss.argtypes = [vp, i32, vp, vp, i32, vp, vp]
+        L.dode_grad.argtypes = [vp, i32, vp, vp, i32, vp, vp]
+        L.dode_metrics.argtypes = [vp, i32, vp, vp, i32, vp, vp, vp, vp]
+        L.spgd_step.argtypes = [vp, i32, P(i32), i32, vp, vp, vp, i32, P(SpgdParams), vp]
+        L.spgd_solve.argtypes = [vp, P(i32), i32, vp, vp, vp, P(SpgdParams), P(i32), ctypes.c_uint64,
+                                 P(dbl), vp]
+        for name in EXPORTS:
+            if name not in ("dode_last_error", "dode_spgd_defaults"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != DODE_OK:
+        raise DodeError(status, lib().dode_last_error().decode())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t, name, dtype=None, shape=None):
+    import torch
+    if t is None:
+        return ctypes.c_void_p(0)
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def spgd_defaults() -> SpgdParams:
+    p = SpgdParams()
+    lib().dode_spgd_defaults(ctypes.byref(p))
+    return p
+
+
+def make_params(epochs=300, batch_rows=8192, eta=5.0, eps=1e-10, optimizer=0, check_finite=1):
+    return SpgdParams(int(epochs), int(batch_rows), float(eta), float(eps), int(optimizer),
+                      int(check_finite))
+
+
+class Dar:
+    """Owner of a dode_dar handle (freed by dar_destroy on close / garbage collection)."""
+
+    def __init__(self, handle, dims, C, storage):
+        self.handle = handle
+        self.dims = dims
+        self.C = C
+        self.storage = storage
+
+    @property
+    def state_dtype(self):
+        import torch
+        return torch.float64 if self.storage == DODE_F64 else torch.float32
+
+    def close(self):
+        if self.handle:
+            lib().dar_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def dar_create(P, L, T, H, K, row_ptr, col_idx, values, storage="f32", stream=None) -> Dar:
+    """values: list of C float64 arrays [K][T][nnz] (host)."""
+    st = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    vals = [np.ascontiguousarray(v, dtype=np.float64) for v in values]
+    nnz = int(rp[-1]) if rp.size else 0
+    for v in vals:
+        if v.size != K * T * nnz:
+            raise ValueError(f"values must be [K][T][nnz] = {K * T * nnz} entries, got {v.size}")
+    ptrs = (ctypes.POINTER(ctypes.c_double) * len(vals))(
+        *[v.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for v in vals])
+    dims = Dims(P, L, T, H, K)
+    out = ctypes.c_void_p()
+    _check(lib().dar_create(ctypes.byref(dims), len(vals),
+                            rp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                            ci.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ptrs, st,
+                            _stream(stream), ctypes.byref(out)))
+    return Dar(out, (P, L, T, H, K), len(vals), st)
+
+
+def dar_info(dar: Dar):
+    dims, C, nnz, st, nb = Dims(), ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()
+    _check(lib().dar_info(dar.handle, ctypes.byref(dims), ctypes.byref(C), ctypes.byref(nnz),
+                          ctypes.byref(st), ctypes.byref(nb)))
+    return dict(P=dims.P, L=dims.L, T=dims.T, H=dims.H, K=dims.K, C=C.value, nnz=nnz.value,
+                storage=st.value, device_bytes=nb.value)
+
+
+def dar_set_values(dar: Dar, cluster: int, W, stream=None):
+    P, L, T, H, K = dar.dims
+    _check(lib().dar_set_values(dar.handle, cluster, _ptr(W, "W", dar.state_dtype), _stream(stream)))
+
+
+def dode_apply(dar: Dar, cluster: int, Q, Xhat, stream=None):
+    P, L, T, H, K = dar.dims
+    n = Q.shape[0]
+    _check(lib().dode_apply(dar.handle, cluster, _ptr(Q, "Q", dar.state_dtype, (n, T, P)), n,
+                            _ptr(Xhat, "Xhat", dar.state_dtype, (n, H, L)), _stream(stream)))
+
+
+def dode_loss(dar: Dar, cluster: int, Q, X, loss, stream=None):
+    import torch
+    P, L, T, H, K = dar.dims
+    n = Q.shape[0]
+    _check(lib().dode_loss(dar.handle, cluster, _ptr(Q, "Q", dar.state_dtype, (n, T, P)),
+                           _ptr(X, "X", dar.state_dtype, (n, H, L)), n,
+                           _ptr(loss, "loss", torch.float64, (n,)), _stream(stream)))
+
+
+def dode_grad(dar: Dar, cluster: int, Q, X, G, stream=None):
+    P, L, T, H, K = dar.dims
+    n = Q.shape[0]
+    _check(lib().dode_grad(dar.handle, cluster, _ptr(Q, "Q", dar.state_dtype, (n, T, P)),
+                           _ptr(X, "X", dar.state_dtype, (n, H, L)), n,
+                           _ptr(G, "G", dar.state_dtype, (n, T, P)), _stream(stream)))
+
+
+def dode_metrics(dar: Dar, cluster: int, Q, X, loss=None, kkt=None, r2=None, stream=None):
+    import torch
+    P, L, T, H, K = dar.dims
+    n = Q.shape[0]
+    _check(lib().dode_metrics(dar.handle, cluster, _ptr(Q, "Q", dar.state_dtype, (n, T, P)),
+                              _ptr(X, "X", dar.state_dtype, (n, H, L)), n,
+                              _ptr(loss, "loss", torch.float64, (n,)),
+                              _ptr(kkt, "kkt", torch.float64, (n,)),
+                              _ptr(r2, "r2", torch.float64, (n,)), _stream(stream)))
+
+
+def spgd_step(dar: Dar, cluster: int, chunk_h, X, Q, A, params: SpgdParams, stream=None):
+    P, L, T, H, K = dar.dims
+    n = Q.shape[0]
+    ch = np.ascontiguousarray(chunk_h, dtype=np.int32)
+    _check(lib().spgd_step(dar.handle, cluster, ch.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                           ch.size, _ptr(X, "X", dar.state_dtype, (n, H, L)),
+                           _ptr(Q, "Q", dar.state_dtype, (n, T, P)),
+                           _ptr(A, "A", dar.state_dtype, (n, T, P)), n, ctypes.byref(params),
+                           _stream(stream)))
+
+
+def spgd_solve(dar: Dar, day_cluster, X, Q, A, params: SpgdParams, perm=None, seed=0,
+               loss_hist=False, stream=None):
+    """Runs Algorithm 1 on all days; returns loss history [D][E] (numpy) if asked."""
+    P, L, T, H, K = dar.dims
+    dc = np.ascontiguousarray(day_cluster, dtype=np.int32)
+    D = dc.size
+    pp = ctypes.POINTER(ctypes.c_int32)()
+    if perm is not None:
+        perm = np.ascontiguousarray(perm, dtype=np.int32)
+        if perm.shape != (params.epochs, dar.C, H):
+            raise ValueError(f"perm must be [E][C][H] = {(params.epochs, dar.C, H)}")
+        pp = perm.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    hist = np.zeros((D, params.epochs)) if loss_hist else None
+    hp = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if loss_hist else \
+        ctypes.POINTER(ctypes.c_double)()
+    _check(lib().spgd_solve(dar.handle, dc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), D,
+                            _ptr(X, "X", dar.state_dtype, (D, H, L)),
+                            _ptr(Q, "Q", dar.state_dtype, (D, T, P)),
+                            _ptr(A, "A", dar.state_dtype, (D, T, P)), ctypes.byref(params), pp,
+                            ctypes.c_uint64(seed), hp, _stream(stream)))
+    return hist

@@ -1,0 +1,606 @@
+// Host side of the C ABI declared in include/dode.h: argument checks, device
+// copies of the assignment matrices, minibatch schedules and kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "dode_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+dode_status fail(dode_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(e_ == hipErrorOutOfMemory ? DODE_ERR_OOM : DODE_ERR_HIP, "%s: %s (%s:%d)", \
+                  #expr, hipGetErrorString(e_), __FILE__, __LINE__);                       \
+  } while (0)
+
+inline hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+// Stream-ordered scratch allocation released at scope exit on the same stream.
+struct DevBuf {
+  void* p = nullptr;
+  hipStream_t s = nullptr;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() {
+    if (p) (void)hipFreeAsync(p, s);
+  }
+  hipError_t alloc(size_t bytes, hipStream_t st) {
+    s = st;
+    return hipMallocAsync(&p, bytes ? bytes : 16, st);
+  }
+  template <typename T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+size_t state_size(const dode_dar* d) { return d->storage == DODE_F64 ? 8 : 4; }
+
+dode_status check_dims(const dode_dims* dm) {
+  if (!dm) return fail(DODE_ERR_ARG, "dims is NULL");
+  if (dm->P < 1 || dm->L < 1 || dm->T < 1 || dm->H < 1 || dm->K < 1)
+    return fail(DODE_ERR_SHAPE, "dims must be >= 1 (P=%d L=%d T=%d H=%d K=%d)", dm->P, dm->L,
+                dm->T, dm->H, dm->K);
+  if (dm->K > 64) return fail(DODE_ERR_SHAPE, "K=%d exceeds 64", dm->K);
+  if ((int64_t)dm->T * dm->P > (1LL << 31) || (int64_t)dm->H * dm->L > (1LL << 31))
+    return fail(DODE_ERR_SHAPE, "per-day vectors exceed 2^31 entries");
+  return DODE_OK;
+}
+
+dode_status check_dar(const dode_dar* dar, int32_t cluster) {
+  if (!dar) return fail(DODE_ERR_ARG, "dar handle is NULL");
+  if (cluster < 0 || cluster >= dar->C)
+    return fail(DODE_ERR_ARG, "cluster %d out of range [0, %d)", cluster, dar->C);
+  return DODE_OK;
+}
+
+dode_status check_days(int32_t n_days) {
+  if (n_days < 0) return fail(DODE_ERR_ARG, "n_days=%d is negative", n_days);
+  if (n_days > 65535) return fail(DODE_ERR_SHAPE, "n_days=%d exceeds 65535 per call", n_days);
+  return DODE_OK;
+}
+
+// ------------------------------------------------ permutations / schedule --
+uint64_t splitmix64(uint64_t& s) {
+  uint64_t z = (s += 0x9E3779B97F4A7C15ULL);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+struct HostSched {
+  int32_t bh = 0, nch = 0, mt = 0;
+  std::vector<int32_t> perm, pos, touched;   // [E][C][H], [E][C][H], [E][nch][C][mt]
+};
+
+// Minibatch layout for epochs of C clusters from permutations perm [E][C][H].
+dode_status build_sched(const dode_dims& dm, int32_t C, int32_t E, int32_t bh,
+                        const int32_t* perm, uint64_t seed, HostSched& hs) {
+  const int32_t H = dm.H, T = dm.T, K = dm.K;
+  hs.bh = bh;
+  hs.nch = (H + bh - 1) / bh;
+  hs.mt = std::min<int32_t>(T, bh * K);
+  const size_t ech = (size_t)E * C * H;
+  hs.perm.resize(ech);
+  hs.pos.assign(ech, -1);
+  if (perm) {
+    std::memcpy(hs.perm.data(), perm, ech * sizeof(int32_t));
+  } else {
+    uint64_t s = seed;
+    for (size_t ec = 0; ec < (size_t)E * C; ++ec) {
+      int32_t* p = hs.perm.data() + ec * H;
+      for (int32_t i = 0; i < H; ++i) p[i] = i;
+      for (int32_t i = H - 1; i > 0; --i) std::swap(p[i], p[splitmix64(s) % (uint64_t)(i + 1)]);
+    }
+  }
+  for (size_t ec = 0; ec < (size_t)E * C; ++ec) {
+    const int32_t* p = hs.perm.data() + ec * H;
+    int32_t* q = hs.pos.data() + ec * H;
+    for (int32_t i = 0; i < H; ++i) {
+      if (p[i] < 0 || p[i] >= H || q[p[i]] >= 0)
+        return fail(DODE_ERR_ARG, "perm[%zu][%zu] is not a permutation of 0..H-1", ec / C, ec % C);
+      q[p[i]] = i;
+    }
+  }
+  hs.touched.assign((size_t)E * hs.nch * C * hs.mt, -1);
+  std::vector<char> mark(T);
+  for (int32_t e = 0; e < E; ++e)
+    for (int32_t c = 0; c < C; ++c) {
+      const int32_t* p = hs.perm.data() + ((size_t)e * C + c) * H;
+      for (int32_t j = 0; j < hs.nch; ++j) {
+        std::fill(mark.begin(), mark.end(), 0);
+        for (int32_t s = j * bh; s < std::min(H, (j + 1) * bh); ++s)
+          for (int32_t l = 0; l < K; ++l) {
+            const int32_t t = p[s] - l;
+            if (t >= 0 && t < T) mark[t] = 1;
+          }
+        int32_t* out = hs.touched.data() + (((size_t)e * hs.nch + j) * C + c) * hs.mt;
+        int32_t n = 0;
+        for (int32_t t = 0; t < T; ++t)
+          if (mark[t]) out[n++] = t;
+      }
+    }
+  return DODE_OK;
+}
+
+struct DevSched {
+  DevBuf perm, pos, touched;
+  int32_t bh = 0, nch = 0, mt = 0, C = 0, H = 0;
+  ChunkSched chunk(int32_t e, int32_t j) const {
+    return ChunkSched{perm.as<int32_t>() + (size_t)e * C * H, pos.as<int32_t>() + (size_t)e * C * H,
+                      touched.as<int32_t>() + ((size_t)e * nch + j) * C * mt, j * bh, bh, mt};
+  }
+};
+
+dode_status upload_sched(const HostSched& hs, int32_t C, int32_t H, hipStream_t s, DevSched& ds) {
+  ds.bh = hs.bh;
+  ds.nch = hs.nch;
+  ds.mt = hs.mt;
+  ds.C = C;
+  ds.H = H;
+  HIP_TRY(ds.perm.alloc(hs.perm.size() * 4, s));
+  HIP_TRY(ds.pos.alloc(hs.pos.size() * 4, s));
+  HIP_TRY(ds.touched.alloc(hs.touched.size() * 4, s));
+  HIP_TRY(hipMemcpyAsync(ds.perm.p, hs.perm.data(), hs.perm.size() * 4, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(ds.pos.p, hs.pos.data(), hs.pos.size() * 4, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(ds.touched.p, hs.touched.data(), hs.touched.size() * 4,
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return DODE_OK;
+}
+
+dode_status check_params(const dode_spgd_params* p) {
+  if (!p) return fail(DODE_ERR_ARG, "params is NULL");
+  if (p->epochs < 0) return fail(DODE_ERR_ARG, "epochs=%d is negative", p->epochs);
+  if (p->batch_rows < 1) return fail(DODE_ERR_ARG, "batch_rows=%d must be >= 1", p->batch_rows);
+  if (!(p->eta > 0) || !std::isfinite(p->eta)) return fail(DODE_ERR_ARG, "eta must be > 0");
+  if (!(p->eps >= 0) || !std::isfinite(p->eps)) return fail(DODE_ERR_ARG, "eps must be >= 0");
+  if (p->optimizer != 0 && p->optimizer != 1)
+    return fail(DODE_ERR_ARG, "optimizer=%d (0 Adagrad, 1 fixed step)", p->optimizer);
+  return DODE_OK;
+}
+
+dode_status scan_finite(const dode_dar* dar, const void* X, int64_t n, hipStream_t s) {
+  DevBuf flag;
+  HIP_TRY(flag.alloc(4, s));
+  HIP_TRY(hipMemsetAsync(flag.p, 0, 4, s));
+  HIP_TRY(check_finite(dar->storage == DODE_F64, X, n, flag.as<int32_t>(), s));
+  int32_t h = 0;
+  HIP_TRY(hipMemcpyAsync(&h, flag.p, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (h) return fail(DODE_ERR_NONFINITE, "X holds NaN or Inf");
+  return DODE_OK;
+}
+
+}  // namespace
+
+bool is_f64(const dode_dar* d) { return d->storage == DODE_F64; }
+
+// ------------------------------------------------------ number formats --
+uint16_t host_f64_to_bf16(double v) {
+  if (std::isnan(v)) return 0x7FC0;
+  const uint16_t sign = std::signbit(v) ? 0x8000 : 0;
+  const double a = std::fabs(v);
+  if (a == 0.0) return sign;
+  if (a < 0x1p-126) {   // bfloat16 subnormals: multiples of 2^-133
+    const double m = std::nearbyint(a * 0x1p133);
+    return sign | static_cast<uint16_t>(m);
+  }
+  int e = 0;
+  std::frexp(a, &e);                                   // a = f 2^e, f in [0.5, 1)
+  double M = std::nearbyint(std::ldexp(a, 8 - e));    // 8 significant bits, ties to even
+  if (M >= 256.0) { M = 128.0; ++e; }
+  if (e - 1 > 127) return sign | 0x7F80;               // overflow to infinity
+  const float f = static_cast<float>(std::ldexp(M, e - 8));
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  return sign | static_cast<uint16_t>(u >> 16);
+}
+
+double host_bf16_to_f64(uint16_t b) {
+  const uint32_t u = static_cast<uint32_t>(b) << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+uint8_t host_f64_to_e4m3(double v) {
+  const uint8_t sign = std::signbit(v) ? 0x80 : 0;
+  const double a = std::fabs(v);
+  if (!(a < 448.0)) return sign | 0x7E;   // saturate at the largest finite value
+  if (a < 0x1p-6) return sign | static_cast<uint8_t>(std::nearbyint(a * 512.0));
+  int e = 0;
+  const double f = std::frexp(a, &e);
+  int E = e - 1;
+  int m = static_cast<int>(std::nearbyint((2.0 * f - 1.0) * 8.0));
+  if (m == 8) { m = 0; ++E; }
+  int code = ((E + 7) << 3) | m;
+  if (code > 0x7E) code = 0x7E;
+  return sign | static_cast<uint8_t>(code);
+}
+
+double host_e4m3_to_f64(uint8_t b) {
+  const int e = (b >> 3) & 0xF, m = b & 7;
+  const double v = e == 0 ? m * 0x1p-9 : std::ldexp(1.0 + m / 8.0, e - 7);
+  return (b & 0x80) ? -v : v;
+}
+
+// ================================================================== ABI ==
+extern "C" {
+
+const char* dode_last_error(void) { return g_err.c_str(); }
+
+void dode_spgd_defaults(dode_spgd_params* p) {
+  if (!p) return;
+  p->epochs = 300;
+  p->batch_rows = 8192;
+  p->eta = 5.0;
+  p->eps = 1e-10;
+  p->optimizer = 0;
+  p->check_finite = 1;
+}
+
+dode_status dar_destroy(dode_dar* dar) {
+  if (!dar) return DODE_OK;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(dar->device);
+  for (void* p : {(void*)dar->d_row_ptr, (void*)dar->d_col, (void*)dar->d_col_ptr,
+                  (void*)dar->d_row, (void*)dar->d_csc2csr, dar->d_W, dar->d_WT,
+                  (void*)dar->d_scale})
+    if (p) (void)hipFree(p);
+  (void)hipSetDevice(cur);
+  delete dar;
+  return DODE_OK;
+}
+
+dode_status dar_create(const dode_dims* dims, int32_t n_clusters, const int32_t* row_ptr,
+                       const int32_t* col_idx, const double* const* values, dode_dtype storage,
+                       void* stream, dode_dar** out) {
+  if (!out) return fail(DODE_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (dode_status st = check_dims(dims)) return st;
+  if (n_clusters < 1) return fail(DODE_ERR_ARG, "n_clusters=%d must be >= 1", n_clusters);
+  if (!row_ptr || !col_idx || !values) return fail(DODE_ERR_ARG, "pattern or values is NULL");
+  if (storage < DODE_F64 || storage > DODE_FP8_E4M3)
+    return fail(DODE_ERR_DTYPE, "unknown storage type %d", (int)storage);
+  const dode_dims dm = *dims;
+  if (row_ptr[0] != 0) return fail(DODE_ERR_SHAPE, "row_ptr[0] must be 0");
+  for (int32_t a = 0; a < dm.L; ++a) {
+    if (row_ptr[a + 1] < row_ptr[a]) return fail(DODE_ERR_SHAPE, "row_ptr decreases at %d", a);
+    for (int32_t j = row_ptr[a]; j < row_ptr[a + 1]; ++j) {
+      if (col_idx[j] < 0 || col_idx[j] >= dm.P)
+        return fail(DODE_ERR_SHAPE, "col_idx[%d]=%d outside [0, P)", j, col_idx[j]);
+      if (j > row_ptr[a] && col_idx[j] <= col_idx[j - 1])
+        return fail(DODE_ERR_SHAPE, "col_idx not strictly increasing in row %d", a);
+    }
+  }
+  const int64_t nnz = row_ptr[dm.L];
+  for (int32_t c = 0; c < n_clusters; ++c)
+    if (!values[c]) return fail(DODE_ERR_ARG, "values[%d] is NULL", c);
+  const int64_t cstride = (int64_t)dm.K * dm.T * nnz;
+  for (int32_t c = 0; c < n_clusters; ++c)
+    for (int32_t l = 0; l < dm.K; ++l)
+      for (int32_t t = 0; t < std::min(dm.T, dm.H - l); ++t)
+        for (int64_t j = 0; j < nnz; ++j)
+          if (!std::isfinite(values[c][((int64_t)l * dm.T + t) * nnz + j]))
+            return fail(DODE_ERR_NONFINITE, "values[%d] holds NaN or Inf", c);
+
+  std::unique_ptr<dode_dar> d(new dode_dar());
+  d->dims = dm;
+  d->C = n_clusters;
+  d->nnz = nnz;
+  d->storage = storage;
+  HIP_TRY(hipGetDevice(&d->device));
+  d->h_row_ptr.assign(row_ptr, row_ptr + dm.L + 1);
+  d->h_col.assign(col_idx, col_idx + nnz);
+  // CSC by OD, with the map back to CSR slots
+  d->h_col_ptr.assign(dm.P + 1, 0);
+  for (int64_t j = 0; j < nnz; ++j) d->h_col_ptr[col_idx[j] + 1]++;
+  for (int32_t p = 0; p < dm.P; ++p) d->h_col_ptr[p + 1] += d->h_col_ptr[p];
+  d->h_row.resize(nnz);
+  d->h_csc2csr.resize(nnz);
+  {
+    std::vector<int32_t> fillp(d->h_col_ptr.begin(), d->h_col_ptr.end() - 1);
+    for (int32_t a = 0; a < dm.L; ++a)
+      for (int32_t j = row_ptr[a]; j < row_ptr[a + 1]; ++j) {
+        const int32_t jj = fillp[col_idx[j]]++;
+        d->h_row[jj] = a;
+        d->h_csc2csr[jj] = j;
+      }
+  }
+  hipStream_t s = as_stream(stream);
+  auto dev_copy = [&](int32_t** dst, const std::vector<int32_t>& src) -> hipError_t {
+    hipError_t e = hipMalloc(dst, std::max<size_t>(16, src.size() * 4));
+    if (e != hipSuccess) return e;
+    d->device_bytes += src.size() * 4;
+    return hipMemcpy(*dst, src.data(), src.size() * 4, hipMemcpyHostToDevice);
+  };
+  HIP_TRY(dev_copy(&d->d_row_ptr, d->h_row_ptr));
+  HIP_TRY(dev_copy(&d->d_col, d->h_col));
+  HIP_TRY(dev_copy(&d->d_col_ptr, d->h_col_ptr));
+  HIP_TRY(dev_copy(&d->d_row, d->h_row));
+  HIP_TRY(dev_copy(&d->d_csc2csr, d->h_csc2csr));
+
+  const size_t esz = storage == DODE_F64 ? 8 : storage == DODE_F32 ? 4 : storage == DODE_BF16 ? 2 : 1;
+  const size_t vbytes = (size_t)n_clusters * cstride * esz;
+  HIP_TRY(hipMalloc(&d->d_W, std::max<size_t>(16, vbytes)));
+  HIP_TRY(hipMalloc(&d->d_WT, std::max<size_t>(16, vbytes)));
+  d->device_bytes += 2 * vbytes;
+  const int32_t n_ptile = (dm.P + 63) / 64;
+  const size_t sbytes = (size_t)n_clusters * dm.K * dm.T * n_ptile * 4;
+  if (storage == DODE_FP8_E4M3) {
+    HIP_TRY(hipMalloc(&d->d_scale, sbytes));
+    d->device_bytes += sbytes;
+  }
+  // host conversion, one cluster at a time
+  std::vector<uint8_t> hw(cstride * esz), hwt(cstride * esz);
+  std::vector<float> hs(storage == DODE_FP8_E4M3 ? (size_t)dm.K * dm.T * n_ptile : 0);
+  std::vector<double> tmax(n_ptile);
+  for (int32_t c = 0; c < n_clusters; ++c) {
+    const double* src = values[c];
+    if (storage == DODE_FP8_E4M3) {
+      for (int64_t lt = 0; lt < (int64_t)dm.K * dm.T; ++lt) {
+        std::fill(tmax.begin(), tmax.end(), 0.0);
+        for (int64_t j = 0; j < nnz; ++j)
+          tmax[col_idx[j] >> 6] = std::max(tmax[col_idx[j] >> 6], std::fabs(src[lt * nnz + j]));
+        for (int32_t i = 0; i < n_ptile; ++i)
+          hs[lt * n_ptile + i] = tmax[i] > 0 ? static_cast<float>(tmax[i] / 448.0) : 1.0f;
+      }
+    }
+    for (int64_t lt = 0; lt < (int64_t)dm.K * dm.T; ++lt)
+      for (int64_t jj = 0; jj < nnz; ++jj) {
+        const int64_t j = d->h_csc2csr[jj];
+        const double v = src[lt * nnz + j];
+        const int64_t ij = lt * nnz + j, ijj = lt * nnz + jj;
+        switch (storage) {
+          case DODE_F64:
+            reinterpret_cast<double*>(hw.data())[ij] = v;
+            reinterpret_cast<double*>(hwt.data())[ijj] = v;
+            break;
+          case DODE_F32:
+            reinterpret_cast<float*>(hw.data())[ij] = static_cast<float>(v);
+            reinterpret_cast<float*>(hwt.data())[ijj] = static_cast<float>(v);
+            break;
+          case DODE_BF16: {
+            const uint16_t b = host_f64_to_bf16(v);
+            reinterpret_cast<uint16_t*>(hw.data())[ij] = b;
+            reinterpret_cast<uint16_t*>(hwt.data())[ijj] = b;
+            break;
+          }
+          case DODE_FP8_E4M3: {
+            const double sc = hs[lt * n_ptile + (col_idx[j] >> 6)];
+            const uint8_t b = host_f64_to_e4m3(v / sc);
+            hw[ij] = b;
+            hwt[ijj] = b;
+            break;
+          }
+        }
+      }
+    HIP_TRY(hipMemcpy(static_cast<uint8_t*>(d->d_W) + c * cstride * esz, hw.data(), cstride * esz,
+                      hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(static_cast<uint8_t*>(d->d_WT) + c * cstride * esz, hwt.data(),
+                      cstride * esz, hipMemcpyHostToDevice));
+    if (storage == DODE_FP8_E4M3)
+      HIP_TRY(hipMemcpy(d->d_scale + (size_t)c * dm.K * dm.T * n_ptile, hs.data(), hs.size() * 4,
+                        hipMemcpyHostToDevice));
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  *out = d.release();
+  return DODE_OK;
+}
+
+dode_status dar_info(const dode_dar* dar, dode_dims* dims, int32_t* n_clusters, int64_t* nnz,
+                     dode_dtype* storage, int64_t* device_bytes) {
+  if (!dar) return fail(DODE_ERR_ARG, "dar handle is NULL");
+  if (dims) *dims = dar->dims;
+  if (n_clusters) *n_clusters = dar->C;
+  if (nnz) *nnz = dar->nnz;
+  if (storage) *storage = dar->storage;
+  if (device_bytes) *device_bytes = dar->device_bytes;
+  return DODE_OK;
+}
+
+dode_status dar_set_values(dode_dar* dar, int32_t cluster, const void* W_dev, void* stream) {
+  if (dode_status st = check_dar(dar, cluster)) return st;
+  if (!W_dev) return fail(DODE_ERR_ARG, "W_dev is NULL");
+  if (dar->storage == DODE_FP8_E4M3 && dar->dims.P > 64 * 64)
+    return fail(DODE_ERR_UNSUPPORTED, "device FP8 requantisation supports P <= 4096");
+  HIP_TRY(quantize_values(dar, cluster, W_dev, as_stream(stream)));
+  return DODE_OK;
+}
+
+dode_status dode_apply(const dode_dar* dar, int32_t cluster, const void* Q, int32_t n_days,
+                       void* Xhat, void* stream) {
+  if (dode_status st = check_dar(dar, cluster)) return st;
+  if (dode_status st = check_days(n_days)) return st;
+  if (n_days == 0) return DODE_OK;
+  if (!Q || !Xhat) return fail(DODE_ERR_ARG, "Q or Xhat is NULL");
+  HIP_TRY(plain_apply_rows(dar, nullptr, cluster, Q, nullptr, Xhat, nullptr, n_days,
+                           as_stream(stream)));
+  return DODE_OK;
+}
+
+dode_status dode_loss(const dode_dar* dar, int32_t cluster, const void* Q, const void* X,
+                      int32_t n_days, double* loss, void* stream) {
+  if (dode_status st = check_dar(dar, cluster)) return st;
+  if (dode_status st = check_days(n_days)) return st;
+  if (n_days == 0) return DODE_OK;
+  if (!Q || !X || !loss) return fail(DODE_ERR_ARG, "Q, X or loss is NULL");
+  hipStream_t s = as_stream(stream);
+  DevBuf part;
+  HIP_TRY(part.alloc((size_t)n_days * dar->dims.H * 8, s));
+  HIP_TRY(plain_apply_rows(dar, nullptr, cluster, Q, X, nullptr, part.as<double>(), n_days, s));
+  HIP_TRY(sum_partials(part.as<double>(), dar->dims.H, n_days, loss, s));
+  return DODE_OK;
+}
+
+dode_status dode_grad(const dode_dar* dar, int32_t cluster, const void* Q, const void* X,
+                      int32_t n_days, void* G, void* stream) {
+  if (dode_status st = check_dar(dar, cluster)) return st;
+  if (dode_status st = check_days(n_days)) return st;
+  if (n_days == 0) return DODE_OK;
+  if (!Q || !X || !G) return fail(DODE_ERR_ARG, "Q, X or G is NULL");
+  hipStream_t s = as_stream(stream);
+  DevBuf R;
+  HIP_TRY(R.alloc((size_t)n_days * dar->dims.H * dar->dims.L * state_size(dar), s));
+  HIP_TRY(plain_apply_rows(dar, nullptr, cluster, Q, X, R.p, nullptr, n_days, s));
+  HIP_TRY(plain_adjoint_rows(dar, nullptr, cluster, R.p, G, n_days, s));
+  return DODE_OK;
+}
+
+dode_status dode_metrics(const dode_dar* dar, int32_t cluster, const void* Q, const void* X,
+                         int32_t n_days, double* loss, double* kkt, double* r2, void* stream) {
+  if (dode_status st = check_dar(dar, cluster)) return st;
+  if (dode_status st = check_days(n_days)) return st;
+  if (n_days == 0) return DODE_OK;
+  if (!Q || !X) return fail(DODE_ERR_ARG, "Q or X is NULL");
+  hipStream_t s = as_stream(stream);
+  const dode_dims& dm = dar->dims;
+  const int32_t n = n_days;
+  DevBuf part, lbuf, sumx, sst, R, G;
+  HIP_TRY(part.alloc((size_t)n * std::max(dm.H, dm.T) * 8, s));
+  HIP_TRY(lbuf.alloc((size_t)n * 8, s));
+  if (kkt) {
+    HIP_TRY(R.alloc((size_t)n * dm.H * dm.L * state_size(dar), s));
+    HIP_TRY(G.alloc((size_t)n * dm.T * dm.P * state_size(dar), s));
+  }
+  HIP_TRY(plain_apply_rows(dar, nullptr, cluster, Q, X, kkt ? R.p : nullptr, part.as<double>(), n, s));
+  HIP_TRY(sum_partials(part.as<double>(), dm.H, n, lbuf.as<double>(), s));
+  if (loss) HIP_TRY(hipMemcpyAsync(loss, lbuf.p, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
+  if (kkt) {
+    HIP_TRY(plain_adjoint_rows(dar, nullptr, cluster, R.p, G.p, n, s));
+    HIP_TRY(kkt_partials(is_f64(dar), Q, G.p, dm.T, dm.P, n, part.as<double>(), s));
+    HIP_TRY(max_partials(part.as<double>(), dm.T, n, kkt, s));
+  }
+  if (r2) {
+    HIP_TRY(sumx.alloc((size_t)n * 8, s));
+    HIP_TRY(sst.alloc((size_t)n * 8, s));
+    HIP_TRY(x_moment_partials(is_f64(dar), X, dm.H, dm.L, n, nullptr, part.as<double>(), s));
+    HIP_TRY(sum_partials(part.as<double>(), dm.H, n, sumx.as<double>(), s));
+    HIP_TRY(x_moment_partials(is_f64(dar), X, dm.H, dm.L, n, sumx.as<double>(), part.as<double>(), s));
+    HIP_TRY(sum_partials(part.as<double>(), dm.H, n, sst.as<double>(), s));
+    HIP_TRY(r2_finish(lbuf.as<double>(), sst.as<double>(), n, r2, s));
+  }
+  return DODE_OK;
+}
+
+dode_status spgd_step(const dode_dar* dar, int32_t cluster, const int32_t* chunk_h, int32_t n_h,
+                      const void* X, void* Q, void* A, int32_t n_days,
+                      const dode_spgd_params* params, void* stream) {
+  if (dode_status st = check_dar(dar, cluster)) return st;
+  if (dode_status st = check_days(n_days)) return st;
+  if (dode_status st = check_params(params)) return st;
+  const dode_dims& dm = dar->dims;
+  if (!chunk_h || n_h < 1 || n_h > dm.H) return fail(DODE_ERR_ARG, "chunk_h must list 1..H intervals");
+  if (n_days == 0) return DODE_OK;
+  if (!X || !Q || (!A && params->optimizer == 0)) return fail(DODE_ERR_ARG, "X, Q or A is NULL");
+  // one permutation per cluster whose first n_h positions are the chunk
+  std::vector<int32_t> perm((size_t)dar->C * dm.H);
+  std::vector<char> seen(dm.H, 0);
+  for (int32_t i = 0; i < n_h; ++i) {
+    if (chunk_h[i] < 0 || chunk_h[i] >= dm.H || seen[chunk_h[i]])
+      return fail(DODE_ERR_ARG, "chunk_h[%d]=%d is out of range or repeated", i, chunk_h[i]);
+    seen[chunk_h[i]] = 1;
+  }
+  for (int32_t c = 0; c < dar->C; ++c) {
+    int32_t* p = perm.data() + (size_t)c * dm.H;
+    int32_t k = 0;
+    for (int32_t i = 0; i < n_h; ++i) p[k++] = chunk_h[i];
+    for (int32_t h = 0; h < dm.H; ++h)
+      if (!seen[h]) p[k++] = h;
+  }
+  HostSched hs;
+  if (dode_status st = build_sched(dm, dar->C, 1, n_h, perm.data(), 0, hs)) return st;
+  hipStream_t s = as_stream(stream);
+  DevSched ds;
+  if (dode_status st = upload_sched(hs, dar->C, dm.H, s, ds)) return st;
+  DevBuf R, Adummy;
+  HIP_TRY(R.alloc((size_t)n_days * n_h * dm.L * state_size(dar), s));
+  if (!A) {
+    HIP_TRY(Adummy.alloc((size_t)n_days * dm.T * dm.P * state_size(dar), s));
+    A = Adummy.p;
+  }
+  const StepArgs sa{params->eta, params->eps, params->optimizer};
+  const ChunkSched cs = ds.chunk(0, 0);
+  HIP_TRY(plain_chunk_resid(dar, nullptr, cluster, cs, Q, X, R.p, n_days, s));
+  HIP_TRY(plain_chunk_adj_step(dar, nullptr, cluster, cs, R.p, Q, A, n_days, sa, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return DODE_OK;
+}
+
+dode_status spgd_solve(const dode_dar* dar, const int32_t* day_cluster, int32_t D, const void* X,
+                       void* Q, void* A, const dode_spgd_params* params, const int32_t* perm,
+                       uint64_t seed, double* loss_hist, void* stream) {
+  if (!dar) return fail(DODE_ERR_ARG, "dar handle is NULL");
+  if (dode_status st = check_days(D)) return st;
+  if (dode_status st = check_params(params)) return st;
+  if (D == 0 || params->epochs == 0) return DODE_OK;
+  if (!day_cluster || !X || !Q || !A) return fail(DODE_ERR_ARG, "day_cluster, X, Q or A is NULL");
+  for (int32_t d = 0; d < D; ++d)
+    if (day_cluster[d] < 0 || day_cluster[d] >= dar->C)
+      return fail(DODE_ERR_ARG, "day_cluster[%d]=%d out of range", d, day_cluster[d]);
+  const dode_dims& dm = dar->dims;
+  const int32_t E = params->epochs, C = dar->C;
+  const int32_t bh = std::max<int32_t>(1, std::min<int32_t>(dm.H, params->batch_rows / dm.L));
+  hipStream_t s = as_stream(stream);
+  if (params->check_finite)
+    if (dode_status st = scan_finite(dar, X, (int64_t)D * dm.H * dm.L, s)) return st;
+  HostSched hs;
+  if (dode_status st = build_sched(dm, C, E, bh, perm, seed, hs)) return st;
+  DevSched ds;
+  if (dode_status st = upload_sched(hs, C, dm.H, s, ds)) return st;
+  DevBuf dcl, R, part, hist;
+  HIP_TRY(dcl.alloc((size_t)D * 4, s));
+  HIP_TRY(hipMemcpyAsync(dcl.p, day_cluster, (size_t)D * 4, hipMemcpyHostToDevice, s));
+  HIP_TRY(R.alloc((size_t)D * bh * dm.L * state_size(dar), s));
+  if (loss_hist) {
+    HIP_TRY(part.alloc((size_t)D * dm.H * 8, s));
+    HIP_TRY(hist.alloc((size_t)E * D * 8, s));
+  }
+  HIP_TRY(clamp_nonneg(is_f64(dar), Q, (int64_t)D * dm.T * dm.P, s));
+  const StepArgs sa{params->eta, params->eps, params->optimizer};
+  const int32_t* dc = dcl.as<int32_t>();
+  for (int32_t e = 0; e < E; ++e) {
+    for (int32_t j = 0; j < ds.nch; ++j) {
+      const ChunkSched cs = ds.chunk(e, j);
+      HIP_TRY(plain_chunk_resid(dar, dc, 0, cs, Q, X, R.p, D, s));
+      HIP_TRY(plain_chunk_adj_step(dar, dc, 0, cs, R.p, Q, A, D, sa, s));
+    }
+    if (loss_hist) {
+      HIP_TRY(plain_apply_rows(dar, dc, 0, Q, X, nullptr, part.as<double>(), D, s));
+      HIP_TRY(sum_partials(part.as<double>(), dm.H, D, hist.as<double>() + (size_t)e * D, s));
+    }
+  }
+  if (loss_hist) {
+    std::vector<double> h((size_t)E * D);
+    HIP_TRY(hipMemcpyAsync(h.data(), hist.p, h.size() * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int32_t d = 0; d < D; ++d)
+      for (int32_t e = 0; e < E; ++e) loss_hist[(size_t)d * E + e] = h[(size_t)e * D + d];
+  }
+  return DODE_OK;
+}
+
+}  // extern "C"

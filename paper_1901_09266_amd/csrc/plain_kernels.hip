@@ -1,0 +1,503 @@
+// Sparse (pattern-compact) kernels of libdode: the general path for every
+// storage type.  Each thread owns one output entry and walks the pattern, so
+// results are deterministic (fixed summation order, no atomics).
+//
+// Algorithm 1 (section "Non-negative least square on GPU") per minibatch:
+//   chunk_resid   : r = rho_o q - x_o on the minibatch rows (eq. "finalobj")
+//   chunk_adj_step: g = rho_o^T r, then Adagrad / fixed step and max(q, 0),
+//                   fused, for every departure interval the minibatch reaches.
+#include "dode_internal.h"
+
+#include <cmath>
+
+namespace {
+
+constexpr int kRowsBlock = 256;
+constexpr int kColsBlock = 64;
+constexpr int kRedBlock = 256;
+
+// ---------------------------------------------------------------- values --
+__device__ __forceinline__ float bf16_bits_to_f32(uint16_t b) {
+  return __uint_as_float(static_cast<uint32_t>(b) << 16);
+}
+
+// OCP E4M3FN: 1 sign, 4 exponent bits (bias 7), 3 mantissa bits; exponent
+// field 0 is subnormal (m * 2^-9); the all-ones code is NaN (never stored).
+__device__ __forceinline__ float e4m3_bits_to_f32(uint8_t b) {
+  const uint32_t e = (b >> 3) & 0xF, m = b & 7;
+  float v = e == 0 ? static_cast<float>(m) * 0x1p-9f : __uint_as_float(((e + 120u) << 23) | (m << 20));
+  return (b & 0x80) ? -v : v;
+}
+
+template <int ST>
+struct Load;
+template <>
+struct Load<DODE_F64> {
+  __device__ static double get(const void* W, int64_t i, const float*, int64_t) {
+    return static_cast<const double*>(W)[i];
+  }
+};
+template <>
+struct Load<DODE_F32> {
+  __device__ static float get(const void* W, int64_t i, const float*, int64_t) {
+    return static_cast<const float*>(W)[i];
+  }
+};
+template <>
+struct Load<DODE_BF16> {
+  __device__ static float get(const void* W, int64_t i, const float*, int64_t) {
+    return bf16_bits_to_f32(static_cast<const uint16_t*>(W)[i]);
+  }
+};
+template <>
+struct Load<DODE_FP8_E4M3> {
+  __device__ static float get(const void* W, int64_t i, const float* scale, int64_t si) {
+    return e4m3_bits_to_f32(static_cast<const uint8_t*>(W)[i]) * scale[si];
+  }
+};
+
+__device__ __forceinline__ int day_cl(const int32_t* day_cluster, int32_t cluster, int d) {
+  return day_cluster ? day_cluster[d] : cluster;
+}
+
+// Fixed-order block sum of one double per thread (blockDim.x == kRedBlock).
+__device__ double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = kRedBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+__device__ double block_max(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = kRedBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+// Row (h, a) of rho_c applied to q_d:  sum_l sum_{p in row a} W[l][h-l][a,p] q[h-l][p].
+template <int ST, typename S>
+__device__ __forceinline__ S row_dot(const DevPat& pt, const DevVals& v, int c, int h, int a,
+                                     const S* q) {
+  S acc = 0;
+  const int32_t j0 = pt.row_ptr[a], j1 = pt.row_ptr[a + 1];
+  for (int l = 0; l < pt.K; ++l) {
+    const int t = h - l;
+    if (t < 0) break;
+    if (t >= pt.T) continue;
+    const int64_t base = c * v.cstride + ((int64_t)l * pt.T + t) * pt.nnz;
+    const int64_t sbase = (c * (int64_t)pt.K * pt.T + (int64_t)l * pt.T + t) * v.n_ptile;
+    const S* qt = q + (int64_t)t * pt.P;
+    for (int32_t j = j0; j < j1; ++j) {
+      const int p = pt.col[j];
+      acc += static_cast<S>(Load<ST>::get(v.W, base + j, v.scale, sbase + (p >> 6))) * qt[p];
+    }
+  }
+  return acc;
+}
+
+// Column (t, p) of rho_c^T applied to residual rows: sum over lags l whose row
+// block h = t+l is in the minibatch (slot pos[h]-first in [0, bh)) of sum_{a on p} W[l][t][a,p] r[slot][a].
+template <int ST, typename S>
+__device__ __forceinline__ S col_dot_chunk(const DevPat& pt, const DevVals& v, int c, int t, int p,
+                                           const int32_t* pos_c, int32_t first, int32_t bh,
+                                           const S* Rd, int32_t L) {
+  S acc = 0;
+  const int32_t k0 = pt.col_ptr[p], k1 = pt.col_ptr[p + 1];
+  for (int l = 0; l < pt.K; ++l) {
+    const int h = t + l;
+    if (h >= pt.H) break;
+    const int s = pos_c ? pos_c[h] - first : h;
+    if (s < 0 || s >= bh) continue;
+    const int64_t base = c * v.cstride + ((int64_t)l * pt.T + t) * pt.nnz;
+    const int64_t si = (c * (int64_t)pt.K * pt.T + (int64_t)l * pt.T + t) * v.n_ptile + (p >> 6);
+    const S* r = Rd + (int64_t)s * L;
+    for (int32_t jj = k0; jj < k1; ++jj)
+      acc += static_cast<S>(Load<ST>::get(v.WT, base + jj, v.scale, si)) * r[pt.row[jj]];
+  }
+  return acc;
+}
+
+// ------------------------------------------------------------- kernels --
+template <int ST, typename S>
+__global__ void __launch_bounds__(kRowsBlock)
+k_chunk_resid(DevPat pt, DevVals v, const int32_t* day_cluster, int32_t cluster, ChunkSched cs,
+              const S* __restrict__ Q, const S* __restrict__ X, S* __restrict__ R) {
+  const int a = blockIdx.x * kRowsBlock + threadIdx.x;
+  const int s = blockIdx.y, d = blockIdx.z;
+  if (a >= pt.L) return;
+  const int c = day_cl(day_cluster, cluster, d);
+  if (cs.j0 + s >= pt.H) return;
+  const int h = cs.perm[c * pt.H + cs.j0 + s];
+  const S* q = Q + (int64_t)d * pt.T * pt.P;
+  const S xhat = row_dot<ST, S>(pt, v, c, h, a, q);
+  R[((int64_t)d * cs.bh + s) * pt.L + a] = xhat - X[((int64_t)d * pt.H + h) * pt.L + a];
+}
+
+template <int ST, typename S>
+__global__ void __launch_bounds__(kColsBlock)
+k_chunk_adj_step(DevPat pt, DevVals v, const int32_t* day_cluster, int32_t cluster, ChunkSched cs,
+                 const S* __restrict__ R, S* __restrict__ Q, S* __restrict__ A, StepArgs st) {
+  const int p = blockIdx.x * kColsBlock + threadIdx.x;
+  const int i = blockIdx.y, d = blockIdx.z;
+  if (p >= pt.P) return;
+  const int c = day_cl(day_cluster, cluster, d);
+  const int t = cs.touched[c * cs.max_touched + i];
+  if (t < 0) return;
+  const S g = col_dot_chunk<ST, S>(pt, v, c, t, p, cs.pos + (int64_t)c * pt.H, cs.j0, cs.bh,
+                                   R + (int64_t)d * cs.bh * pt.L, pt.L);
+  const int64_t idx = ((int64_t)d * pt.T + t) * pt.P + p;
+  S q = Q[idx];
+  if (st.optimizer == 0) {
+    const S acc = A[idx] + g * g;
+    A[idx] = acc;
+    q -= static_cast<S>(st.eta) * g / (sqrt(acc) + static_cast<S>(st.eps));
+  } else {
+    q -= static_cast<S>(st.eta) * g;
+  }
+  Q[idx] = q > S(0) ? q : S(0);
+}
+
+template <int ST, typename S>
+__global__ void __launch_bounds__(kRedBlock)
+k_apply_rows(DevPat pt, DevVals v, const int32_t* day_cluster, int32_t cluster,
+             const S* __restrict__ Q, const S* __restrict__ X, S* __restrict__ out,
+             double* __restrict__ part) {
+  __shared__ double sh[kRedBlock];
+  const int h = blockIdx.x, d = blockIdx.y;
+  const int c = day_cl(day_cluster, cluster, d);
+  const S* q = Q + (int64_t)d * pt.T * pt.P;
+  double ss = 0.0;
+  for (int a = threadIdx.x; a < pt.L; a += kRedBlock) {
+    S val = row_dot<ST, S>(pt, v, c, h, a, q);
+    const int64_t o = ((int64_t)d * pt.H + h) * pt.L + a;
+    if (X) val -= X[o];
+    if (out) out[o] = val;
+    ss += static_cast<double>(val) * static_cast<double>(val);
+  }
+  if (part) {
+    const double tot = block_sum(ss, sh);
+    if (threadIdx.x == 0) part[(int64_t)d * pt.H + h] = tot;
+  }
+}
+
+template <int ST, typename S>
+__global__ void __launch_bounds__(kColsBlock)
+k_adjoint_rows(DevPat pt, DevVals v, const int32_t* day_cluster, int32_t cluster,
+               const S* __restrict__ R, S* __restrict__ G) {
+  const int t = blockIdx.x, d = blockIdx.y;
+  const int c = day_cl(day_cluster, cluster, d);
+  const S* Rd = R + (int64_t)d * pt.H * pt.L;
+  for (int p = threadIdx.x; p < pt.P; p += kColsBlock)
+    G[((int64_t)d * pt.T + t) * pt.P + p] = col_dot_chunk<ST, S>(pt, v, c, t, p, nullptr, 0, pt.H, Rd, pt.L);
+}
+
+__global__ void k_sum_partials(const double* __restrict__ part, int32_t n_per, int32_t n_days,
+                               double* __restrict__ out) {
+  const int d = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= n_days) return;
+  double s = 0.0;
+  for (int i = 0; i < n_per; ++i) s += part[(int64_t)d * n_per + i];
+  out[d] = s;
+}
+
+__global__ void k_max_partials(const double* __restrict__ part, int32_t n_per, int32_t n_days,
+                               double* __restrict__ out) {
+  const int d = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= n_days) return;
+  double m = 0.0;
+  for (int i = 0; i < n_per; ++i) m = fmax(m, part[(int64_t)d * n_per + i]);
+  out[d] = m;
+}
+
+template <typename S>
+__global__ void __launch_bounds__(kRedBlock)
+k_kkt_partials(const S* __restrict__ Q, const S* __restrict__ G, int32_t T, int32_t P,
+               double* __restrict__ part) {
+  __shared__ double sh[kRedBlock];
+  const int t = blockIdx.x, d = blockIdx.y;
+  double m = 0.0;
+  for (int p = threadIdx.x; p < P; p += kRedBlock) {
+    const int64_t i = ((int64_t)d * T + t) * P + p;
+    const double q = Q[i], g = G[i];
+    m = fmax(m, fabs(q < g ? q : g));
+  }
+  const double r = block_max(m, sh);
+  if (threadIdx.x == 0) part[(int64_t)d * T + t] = r;
+}
+
+// First pass (sum_x == nullptr): per (d, h) sum of x.  Second pass: sum of (x - mean)^2.
+template <typename S>
+__global__ void __launch_bounds__(kRedBlock)
+k_x_moment(const S* __restrict__ X, int32_t H, int32_t L, const double* __restrict__ sum_x,
+           double* __restrict__ part) {
+  __shared__ double sh[kRedBlock];
+  const int h = blockIdx.x, d = blockIdx.y;
+  const double mean = sum_x ? sum_x[d] / (static_cast<double>(H) * L) : 0.0;
+  double s = 0.0;
+  for (int a = threadIdx.x; a < L; a += kRedBlock) {
+    const double x = X[((int64_t)d * H + h) * L + a];
+    s += sum_x ? (x - mean) * (x - mean) : x;
+  }
+  const double r = block_sum(s, sh);
+  if (threadIdx.x == 0) part[(int64_t)d * H + h] = r;
+}
+
+__global__ void k_r2(const double* loss, const double* sst, int32_t n, double* r2) {
+  const int d = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d < n) r2[d] = 1.0 - loss[d] / sst[d];
+}
+
+template <typename S>
+__global__ void k_check_finite(const S* __restrict__ X, int64_t n, int32_t* flag) {
+  int bad = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    bad |= !isfinite(X[i]);
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+
+template <typename S>
+__global__ void k_clamp(S* __restrict__ Q, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    Q[i] = Q[i] > S(0) ? Q[i] : S(0);
+}
+
+// ------------------------------------------------- device quantisation --
+__device__ uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return static_cast<uint16_t>((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+
+// Round |v| <= 448 (already scaled) to the nearest E4M3FN code, ties to even.
+__device__ uint8_t f32_to_e4m3_rne(float v) {
+  const uint8_t sgn = v < 0.f ? 0x80 : 0;
+  float a = fabsf(v);
+  if (!(a < 448.f)) return sgn | 0x7E;
+  if (a < 0x1p-6f) {
+    const int m = static_cast<int>(rintf(a * 512.f));   // multiples of 2^-9
+    return sgn | static_cast<uint8_t>(m);                // m == 8 is the code of 2^-6
+  }
+  int e = 0;
+  const float f = frexpf(a, &e);   // a = f * 2^e, f in [0.5, 1)
+  int E = e - 1;                   // a = (2f) * 2^E, 2f in [1, 2)
+  int m = static_cast<int>(rintf((2.f * f - 1.f) * 8.f));
+  if (m == 8) { m = 0; ++E; }
+  int code = ((E + 7) << 3) | m;
+  if (code > 0x7E) code = 0x7E;
+  return sgn | static_cast<uint8_t>(code);
+}
+
+template <typename S>
+__global__ void __launch_bounds__(kRedBlock)
+k_quantize(DevPat pt, int32_t storage, int32_t c, const S* __restrict__ Wsrc, void* W, void* WT,
+           float* scale, const int32_t* __restrict__ csc2csr, int64_t cstride, int32_t n_ptile) {
+  // one block per (l, t) block of cluster c
+  const int lt = blockIdx.x;
+  const int64_t base = (int64_t)lt * pt.nnz;
+  const S* src = Wsrc + base;
+  const int64_t dst = c * cstride + base;
+  __shared__ float smax[64];
+  if (storage == DODE_FP8_E4M3) {
+    for (int i = threadIdx.x; i < n_ptile; i += blockDim.x) smax[i] = 0.f;
+    __syncthreads();
+    for (int64_t j = threadIdx.x; j < pt.nnz; j += blockDim.x) {
+      const float a = fabsf(static_cast<float>(src[j]));
+      atomicMax(reinterpret_cast<unsigned int*>(&smax[pt.col[j] >> 6]), __float_as_uint(a));
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n_ptile; i += blockDim.x)
+      scale[((int64_t)c * pt.K * pt.T + lt) * n_ptile + i] = smax[i] > 0.f ? smax[i] / 448.f : 1.f;
+    __syncthreads();
+  }
+  for (int64_t jj = threadIdx.x; jj < pt.nnz; jj += blockDim.x) {
+    const int64_t j = csc2csr[jj];
+    const float w = static_cast<float>(src[j]);
+    if (storage == DODE_F32) {
+      static_cast<float*>(W)[dst + j] = w;
+      static_cast<float*>(WT)[dst + jj] = w;
+    } else if (storage == DODE_BF16) {
+      const uint16_t b = f32_to_bf16_rne(w);
+      static_cast<uint16_t*>(W)[dst + j] = b;
+      static_cast<uint16_t*>(WT)[dst + jj] = b;
+    } else if (storage == DODE_FP8_E4M3) {
+      const float sc = smax[pt.col[j] >> 6] > 0.f ? smax[pt.col[j] >> 6] / 448.f : 1.f;
+      const uint8_t b = f32_to_e4m3_rne(w / sc);
+      static_cast<uint8_t*>(W)[dst + j] = b;
+      static_cast<uint8_t*>(WT)[dst + jj] = b;
+    } else {
+      static_cast<double*>(W)[dst + j] = static_cast<double>(src[j]);
+      static_cast<double*>(WT)[dst + jj] = static_cast<double>(src[j]);
+    }
+  }
+}
+
+template <template <int, typename> class F, typename... Args>
+hipError_t dispatch(const dode_dar* dar, Args&&... args) {
+  switch (dar->storage) {
+    case DODE_F64: return F<DODE_F64, double>::run(args...);
+    case DODE_F32: return F<DODE_F32, float>::run(args...);
+    case DODE_BF16: return F<DODE_BF16, float>::run(args...);
+    case DODE_FP8_E4M3: return F<DODE_FP8_E4M3, float>::run(args...);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int ST, typename S>
+struct RunResid {
+  static hipError_t run(const dode_dar* dar, const int32_t* dc, int32_t cl, const ChunkSched& cs,
+                        const void* Q, const void* X, void* R, int32_t n, hipStream_t s) {
+    dim3 grid((dar->dims.L + kRowsBlock - 1) / kRowsBlock, cs.bh, n);
+    hipLaunchKernelGGL((k_chunk_resid<ST, S>), grid, dim3(kRowsBlock), 0, s, dar->pat(), dar->vals(),
+                       dc, cl, cs, static_cast<const S*>(Q), static_cast<const S*>(X),
+                       static_cast<S*>(R));
+    return hipGetLastError();
+  }
+};
+
+template <int ST, typename S>
+struct RunAdjStep {
+  static hipError_t run(const dode_dar* dar, const int32_t* dc, int32_t cl, const ChunkSched& cs,
+                        const void* R, void* Q, void* A, int32_t n, const StepArgs& st,
+                        hipStream_t s) {
+    dim3 grid((dar->dims.P + kColsBlock - 1) / kColsBlock, cs.max_touched, n);
+    hipLaunchKernelGGL((k_chunk_adj_step<ST, S>), grid, dim3(kColsBlock), 0, s, dar->pat(),
+                       dar->vals(), dc, cl, cs, static_cast<const S*>(R), static_cast<S*>(Q),
+                       static_cast<S*>(A), st);
+    return hipGetLastError();
+  }
+};
+
+template <int ST, typename S>
+struct RunApplyRows {
+  static hipError_t run(const dode_dar* dar, const int32_t* dc, int32_t cl, const void* Q,
+                        const void* X, void* out, double* part, int32_t n, hipStream_t s) {
+    dim3 grid(dar->dims.H, n);
+    hipLaunchKernelGGL((k_apply_rows<ST, S>), grid, dim3(kRedBlock), 0, s, dar->pat(), dar->vals(),
+                       dc, cl, static_cast<const S*>(Q), static_cast<const S*>(X),
+                       static_cast<S*>(out), part);
+    return hipGetLastError();
+  }
+};
+
+template <int ST, typename S>
+struct RunAdjRows {
+  static hipError_t run(const dode_dar* dar, const int32_t* dc, int32_t cl, const void* R, void* G,
+                        int32_t n, hipStream_t s) {
+    dim3 grid(dar->dims.T, n);
+    hipLaunchKernelGGL((k_adjoint_rows<ST, S>), grid, dim3(kColsBlock), 0, s, dar->pat(),
+                       dar->vals(), dc, cl, static_cast<const S*>(R), static_cast<S*>(G));
+    return hipGetLastError();
+  }
+};
+
+}  // namespace
+
+hipError_t plain_chunk_resid(const dode_dar* dar, const int32_t* day_cluster, int32_t cluster,
+                             const ChunkSched& cs, const void* Q, const void* X, void* R,
+                             int32_t n_days, hipStream_t s) {
+  return dispatch<RunResid>(dar, dar, day_cluster, cluster, cs, Q, X, R, n_days, s);
+}
+
+hipError_t plain_chunk_adj_step(const dode_dar* dar, const int32_t* day_cluster, int32_t cluster,
+                                const ChunkSched& cs, const void* R, void* Q, void* A,
+                                int32_t n_days, const StepArgs& st, hipStream_t s) {
+  return dispatch<RunAdjStep>(dar, dar, day_cluster, cluster, cs, R, Q, A, n_days, st, s);
+}
+
+hipError_t plain_apply_rows(const dode_dar* dar, const int32_t* day_cluster, int32_t cluster,
+                            const void* Q, const void* X, void* out, double* part, int32_t n_days,
+                            hipStream_t s) {
+  return dispatch<RunApplyRows>(dar, dar, day_cluster, cluster, Q, X, out, part, n_days, s);
+}
+
+hipError_t plain_adjoint_rows(const dode_dar* dar, const int32_t* day_cluster, int32_t cluster,
+                              const void* R, void* G, int32_t n_days, hipStream_t s) {
+  return dispatch<RunAdjRows>(dar, dar, day_cluster, cluster, R, G, n_days, s);
+}
+
+hipError_t sum_partials(const double* part, int32_t n_per, int32_t n_days, double* out,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_partials, dim3((n_days + 127) / 128), dim3(128), 0, s, part, n_per,
+                     n_days, out);
+  return hipGetLastError();
+}
+
+hipError_t max_partials(const double* part, int32_t n_per, int32_t n_days, double* out,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_max_partials, dim3((n_days + 127) / 128), dim3(128), 0, s, part, n_per,
+                     n_days, out);
+  return hipGetLastError();
+}
+
+hipError_t kkt_partials(bool f64, const void* Q, const void* G, int32_t T, int32_t P,
+                        int32_t n_days, double* part, hipStream_t s) {
+  if (f64)
+    hipLaunchKernelGGL(k_kkt_partials<double>, dim3(T, n_days), dim3(kRedBlock), 0, s,
+                       static_cast<const double*>(Q), static_cast<const double*>(G), T, P, part);
+  else
+    hipLaunchKernelGGL(k_kkt_partials<float>, dim3(T, n_days), dim3(kRedBlock), 0, s,
+                       static_cast<const float*>(Q), static_cast<const float*>(G), T, P, part);
+  return hipGetLastError();
+}
+
+hipError_t x_moment_partials(bool f64, const void* X, int32_t H, int32_t L, int32_t n_days,
+                             const double* sum_x, double* part, hipStream_t s) {
+  if (f64)
+    hipLaunchKernelGGL(k_x_moment<double>, dim3(H, n_days), dim3(kRedBlock), 0, s,
+                       static_cast<const double*>(X), H, L, sum_x, part);
+  else
+    hipLaunchKernelGGL(k_x_moment<float>, dim3(H, n_days), dim3(kRedBlock), 0, s,
+                       static_cast<const float*>(X), H, L, sum_x, part);
+  return hipGetLastError();
+}
+
+hipError_t r2_finish(const double* loss, const double* sst, int32_t n_days, double* r2,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_r2, dim3((n_days + 127) / 128), dim3(128), 0, s, loss, sst, n_days, r2);
+  return hipGetLastError();
+}
+
+hipError_t check_finite(bool f64, const void* X, int64_t n, int32_t* flag, hipStream_t s) {
+  const int64_t blocks = std::min<int64_t>(4096, (n + 255) / 256 > 0 ? (n + 255) / 256 : 1);
+  if (f64)
+    hipLaunchKernelGGL(k_check_finite<double>, dim3(blocks), dim3(256), 0, s,
+                       static_cast<const double*>(X), n, flag);
+  else
+    hipLaunchKernelGGL(k_check_finite<float>, dim3(blocks), dim3(256), 0, s,
+                       static_cast<const float*>(X), n, flag);
+  return hipGetLastError();
+}
+
+hipError_t clamp_nonneg(bool f64, void* Q, int64_t n, hipStream_t s) {
+  const int64_t blocks = std::min<int64_t>(4096, (n + 255) / 256 > 0 ? (n + 255) / 256 : 1);
+  if (f64)
+    hipLaunchKernelGGL(k_clamp<double>, dim3(blocks), dim3(256), 0, s, static_cast<double*>(Q), n);
+  else
+    hipLaunchKernelGGL(k_clamp<float>, dim3(blocks), dim3(256), 0, s, static_cast<float*>(Q), n);
+  return hipGetLastError();
+}
+
+hipError_t quantize_values(const dode_dar* dar, int32_t cluster, const void* W_state,
+                           hipStream_t s) {
+  const dim3 grid(dar->dims.K * dar->dims.T);
+  const int32_t n_ptile = (dar->dims.P + 63) / 64;
+  if (dar->storage == DODE_F64)
+    hipLaunchKernelGGL(k_quantize<double>, grid, dim3(kRedBlock), 0, s, dar->pat(),
+                       (int32_t)dar->storage, cluster, static_cast<const double*>(W_state), dar->d_W,
+                       dar->d_WT, dar->d_scale, dar->d_csc2csr, dar->vals().cstride, n_ptile);
+  else
+    hipLaunchKernelGGL(k_quantize<float>, grid, dim3(kRedBlock), 0, s, dar->pat(),
+                       (int32_t)dar->storage, cluster, static_cast<const float*>(W_state), dar->d_W,
+                       dar->d_WT, dar->d_scale, dar->d_csc2csr, dar->vals().cstride, n_ptile);
+  return hipGetLastError();
+}

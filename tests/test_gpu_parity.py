@@ -1,0 +1,198 @@
+"""GPU parity: the HIP library through its C ABI against the FP64 oracle.
+
+Bars (element by element unless stated):
+  FP64 storage  kernels 1e-12 relative to the largest entry; solve loss <= 1e-6
+                relative (final and history), demand 1e-8
+  FP32 storage  kernels 2e-6 (ratios rounded to float on both sides); solve
+                final loss <= 1e-3 relative per day
+  BF16 / FP8    the library's kernels against the oracle run on the same
+                rounded ratios (values computed independently in the test);
+                solve final loss <= 1e-3 relative per day
+"""
+import numpy as np
+import pytest
+
+import oracle as orc
+import paper_1901_09266_amd as dode
+from synth import make_config, make_instance, make_perms, chunk_h_blocks
+from gpu_helpers import say, make_dar, dev, rel, dequantized_values
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+SHAPES = {
+    "config1": dict(P=4, L=6, T=12, K=3, sizes=(7,), inc=0.5, pattern="bernoulli"),
+    "ragged": dict(P=37, L=300, T=20, H=17, K=4, sizes=(3,), inc=0.1, pattern="bernoulli"),
+    "wideP": dict(P=70, L=5, T=9, H=12, K=3, sizes=(2,), inc=0.5, pattern="bernoulli"),
+    "corridor": dict(P=50, L=200, T=40, K=6, sizes=(4,), inc=0.1, pattern="corridor"),
+    "Tlt K": dict(P=3, L=4, T=2, H=5, K=4, sizes=(2,), inc=0.6, pattern="bernoulli"),
+}
+
+
+def inst_of(name, seed=1234, noise="add1"):
+    kw = dict(SHAPES[name])
+    return make_instance(demand="uniform50", noise=noise, x_dtype="f64", seed=seed, **kw)
+
+
+def oracle_rows(inst, Wl, Q):
+    xh = np.stack([orc.apply(inst, Wl[inst.day_cluster[d]], Q[d]) for d in range(Q.shape[0])])
+    g = np.stack([orc.grad(inst, Wl[inst.day_cluster[d]], Q[d], inst.x[d]) for d in range(Q.shape[0])])
+    ls = np.array([orc.loss(inst, Wl[inst.day_cluster[d]], Q[d], inst.x[d]) for d in range(Q.shape[0])])
+    return xh, g, ls
+
+
+@pytest.mark.parametrize("name", list(SHAPES))
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16", "fp8"])
+def test_kernels_match_oracle(name, storage):
+    inst = inst_of(name)
+    say("kernels", name, storage)
+    Wq = dequantized_values(inst, storage)
+    dt = torch.float64 if storage == "f64" else torch.float32
+    rng = np.random.default_rng(5)
+    Q = rng.uniform(0, 20, (inst.D, inst.T, inst.P))
+    if storage != "f64":
+        Q = Q.astype(np.float32).astype(np.float64)
+    X = inst.x if storage == "f64" else inst.x.astype(np.float32).astype(np.float64)
+    xh_o, g_o, l_o = oracle_rows(inst, Wq, Q) if storage == "f64" else (None, None, None)
+    if storage != "f64":
+        xh_o = np.stack([orc.apply(inst, Wq[0], Q[d]) for d in range(inst.D)])
+        g_o = np.stack([orc.grad(inst, Wq[0], Q[d], X[d]) for d in range(inst.D)])
+        l_o = np.array([orc.loss(inst, Wq[0], Q[d], X[d]) for d in range(inst.D)])
+    dar = make_dar(inst, storage)
+    Qd, Xd = dev(Q, dt), dev(X, dt)
+    Xh = torch.empty((inst.D, inst.H, inst.L), dtype=dt, device="cuda")
+    G = torch.empty((inst.D, inst.T, inst.P), dtype=dt, device="cuda")
+    loss = torch.empty(inst.D, dtype=torch.float64, device="cuda")
+    dode.dode_apply(dar, 0, Qd, Xh)
+    dode.dode_grad(dar, 0, Qd, Xd, G)
+    dode.dode_loss(dar, 0, Qd, Xd, loss)
+    torch.cuda.synchronize()
+    tol = 1e-12 if storage == "f64" else 2e-6
+    assert rel(Xh.cpu().numpy(), xh_o) <= tol
+    assert rel(G.cpu().numpy(), g_o) <= (tol if storage == "f64" else 1e-4)
+    np.testing.assert_allclose(loss.cpu().numpy(), l_o, rtol=1e-12 if storage == "f64" else 1e-4)
+
+
+@pytest.mark.parametrize("name", ["config1", "ragged", "corridor"])
+def test_metrics_match_oracle(name):
+    inst = inst_of(name)
+    say("metrics", name)
+    rng = np.random.default_rng(6)
+    Q = rng.uniform(0, 20, (inst.D, inst.T, inst.P))
+    lo, ko, ro = orc.metrics(inst, inst.x, Q)
+    dar = make_dar(inst, "f64")
+    out = [torch.empty(inst.D, dtype=torch.float64, device="cuda") for _ in range(3)]
+    dode.dode_metrics(dar, 0, dev(Q, torch.float64), dev(inst.x, torch.float64), *out)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(out[0].cpu().numpy(), lo, rtol=1e-12)
+    np.testing.assert_allclose(out[1].cpu().numpy(), ko, rtol=1e-10)
+    np.testing.assert_allclose(out[2].cpu().numpy(), ro, rtol=1e-12)
+
+
+def test_spgd_step_matches_oracle():
+    inst = inst_of("ragged")
+    say("spgd_step ragged")
+    rng = np.random.default_rng(7)
+    Q0 = rng.uniform(0, 5, (inst.D, inst.T, inst.P))
+    A0 = rng.uniform(0, 2, (inst.D, inst.T, inst.P))
+    chunk = np.array([16, 3, 9, 0, 4], dtype=np.int32)
+    for opt in (0, 1):
+        dar = make_dar(inst, "f64")
+        Qd, Ad = dev(Q0, torch.float64), dev(A0, torch.float64)
+        p = dode.make_params(eta=0.3 if opt == 0 else 1e-3, optimizer=opt)
+        dode.spgd_step(dar, 0, chunk, dev(inst.x, torch.float64), Qd, Ad, p)
+        torch.cuda.synchronize()
+        for d in range(inst.D):
+            q, A = orc.spgd_step(inst, inst.W[0], inst.x[d], Q0[d], A0[d], chunk, optimizer=opt,
+                                 eta=p.eta)
+            assert rel(Qd[d].cpu().numpy(), q) <= 1e-12
+            if opt == 0:
+                assert rel(Ad[d].cpu().numpy(), A) <= 1e-12
+
+
+def run_solve(inst, storage, E, batch_rows, eta, optimizer, perms, loss_hist=True, days=None):
+    dt = torch.float64 if storage == "f64" else torch.float32
+    dar = make_dar(inst, storage)
+    D = inst.D
+    Xd = dev(inst.x, dt)
+    Qd = torch.zeros((D, inst.T, inst.P), dtype=dt, device="cuda")
+    Ad = torch.zeros_like(Qd)
+    p = dode.make_params(epochs=E, batch_rows=batch_rows, eta=eta, optimizer=optimizer)
+    hist = dode.spgd_solve(dar, inst.day_cluster, Xd, Qd, Ad, p, perm=perms, loss_hist=loss_hist)
+    torch.cuda.synchronize()
+    return Qd.cpu().numpy().astype(np.float64), Ad.cpu().numpy().astype(np.float64), hist
+
+
+def test_solve_config1_fixed_step_f64():
+    """Config 1: FP64, fixed step 1/lambda_max, 200 epochs, full batch."""
+    inst = make_config(1)
+    say("solve config1 f64")
+    E = 200
+    eta = orc.fixed_step_eta(inst)
+    perms = make_perms(inst.seed + 1, E, inst.C, inst.H)
+    bh = chunk_h_blocks(inst.L, inst.H, 8192)
+    Qo, Ao, ho = orc.spgd(inst, inst.x, perms, E, bh, optimizer=1, eta=eta)
+    Qg, Ag, hg = run_solve(inst, "f64", E, 8192, eta, 1, perms)
+    assert np.max(np.abs(hg - ho) / ho) <= 1e-6
+    assert np.max(np.abs(hg[:, -1] - ho[:, -1]) / ho[:, -1]) <= 1e-10
+    assert rel(Qg, Qo) <= 1e-8
+
+
+@pytest.mark.parametrize("batch_rows", [35, 8192])
+def test_solve_adagrad_multicluster_f64(batch_rows):
+    """Several clusters of uneven size, several minibatches with a short tail."""
+    inst = make_instance(P=6, L=10, T=16, K=3, sizes=(3, 2, 1), inc=0.4, pattern="bernoulli",
+                         demand="uniform50", noise="add1", x_dtype="f64", seed=44)
+    say("solve multicluster f64", batch_rows)
+    E, eta = 25, 2.0
+    perms = make_perms(45, E, inst.C, inst.H)
+    bh = chunk_h_blocks(inst.L, inst.H, batch_rows)
+    Qo, Ao, ho = orc.spgd(inst, inst.x, perms, E, bh, optimizer=0, eta=eta)
+    Qg, Ag, hg = run_solve(inst, "f64", E, batch_rows, eta, 0, perms)
+    assert np.max(np.abs(hg - ho) / ho) <= 1e-6
+    assert rel(Qg, Qo) <= 1e-8
+    assert rel(Ag, Ao) <= 1e-8
+
+
+def test_solve_is_deterministic():
+    inst = make_instance(P=20, L=40, T=24, K=4, sizes=(5, 3), inc=0.2, pattern="corridor",
+                         demand="gamma", noise="mult5", seed=46)
+    say("determinism")
+    perms = make_perms(47, 10, inst.C, inst.H)
+    a = run_solve(inst, "f32", 10, 200, 5.0, 0, perms)
+    b = run_solve(inst, "f32", 10, 200, 5.0, 0, perms)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[2], b[2])
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16", "fp8"])
+def test_solve_config2_shape_reduced_precision(storage):
+    """Config-2 shapes (50 OD, 200 links, 288 intervals, K=6), 12 days, Adagrad
+    eta 5, b 8192 (40 intervals per minibatch), 300 epochs."""
+    inst = make_config(2, sizes=(12,))
+    say("solve config2-shape", storage)
+    E = 300
+    perms = make_perms(inst.seed + 1, E, inst.C, inst.H)
+    bh = chunk_h_blocks(inst.L, inst.H, 8192)
+    Wq = dequantized_values(inst, storage)
+    x64 = inst.x.astype(np.float64)
+    Qo, _, ho = orc.spgd(inst, x64, perms, E, bh, optimizer=0, eta=5.0, W=Wq)
+    Qg, _, hg = run_solve(inst, storage, E, 8192, 5.0, 0, perms)
+    # final loss of the GPU demand, evaluated in FP64 with the library's ratios
+    lg, _, _ = orc.metrics(inst, x64, Qg, W=Wq)
+    lo = ho[:, -1]
+    assert np.max(np.abs(lg - lo) / lo) <= 1e-3
+    # and the history the library reports
+    assert np.max(np.abs(hg[:, -1] - lo) / lo) <= 1e-3
+
+
+def test_nonfinite_observations_rejected():
+    inst = inst_of("config1")
+    say("nonfinite")
+    x = inst.x.copy()
+    x[2, 3, 1] = np.nan
+    dar = make_dar(inst, "f64")
+    Q = torch.zeros((inst.D, inst.T, inst.P), dtype=torch.float64, device="cuda")
+    A = torch.zeros_like(Q)
+    with pytest.raises(dode.DodeError, match="NONFINITE"):
+        dode.spgd_solve(dar, inst.day_cluster, dev(x, torch.float64), Q, A, dode.make_params(epochs=2))
