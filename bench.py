@@ -1,0 +1,284 @@
+"""Benchmark: SPGD day-gradients per second on one MI355X.
+
+A step is one SPGD epoch (Algorithm 1: every minibatch of every day, all
+clusters together) over the whole synthetic workload, with X, Q, A and the
+assignment matrices resident in HBM.  One day-gradient = one epoch of one day.
+
+Default workload: 150 OD pairs, 500 links, T = H = 288 five-minute intervals,
+K = 6 lags, 1095 days in 8 clusters of uneven size, corridor incidence 8 %,
+Adagrad eta 5, b 8192 rows.  The headline form runs with bfloat16 assignment
+values; the plain FP32 form runs on the same days for comparison, and both are
+checked to reach the same final loss (within 1e-3 relative) as each other and
+as the FP64 oracle on a day sample.
+
+Prints ONE JSON line (stdout).  Progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+WORKLOADS = {
+    2: "50 OD, 200 links, T=H=288, K=6, 365 days in 1 cluster, corridor incidence 10%",
+    3: "150 OD, 500 links, T=H=288, K=6, 1095 days in 8 clusters (400..15), corridor incidence 8%",
+    5: "400 OD, 1500 links, T=H=288, K=6, 1095 days in 12 clusters (300..10), corridor incidence 8%",
+}
+
+ESIZE = {"f64": 8, "f32": 4, "bf16": 2, "fp8": 1}
+FORMS = {
+    "bf16": "grouped matrix-core form: bf16 assignment tiles x FP32 demand/residual split into bf16 "
+            "hi+lo, v_mfma_f32_16x16x32_bf16, FP32 accumulation, fused FP32 Adagrad step",
+    "f32": "plain form: FP32 values, sparse pattern kernels (one thread per output entry)",
+    "fp8": "FP8 e4m3 assignment values, sparse pattern kernels",
+    "f64": "FP64 values, sparse pattern kernels",
+}
+
+
+def launch_bytes(inst, perms, bh, esz, epochs, s_state=4):
+    """Algorithmic HBM bytes of every forward-residual and adjoint-step launch
+    of the given epochs: the minibatch's X rows, residual rows, the demand /
+    accumulator rows of the departure intervals it reaches, and the assignment
+    values of its blocks read once per cluster."""
+    P, L, T, H, K, nnz = inst.P, inst.L, inst.T, inst.H, inst.K, inst.nnz
+    n_c = np.bincount(inst.day_cluster, minlength=inst.C)
+    fwd, adj = [], []
+    for e in epochs:
+        for j in range(0, H, bh):
+            bf = ba = 0
+            for c in range(inst.C):
+                S = perms[e, c, j:j + bh]
+                win = np.unique(np.concatenate([S - l for l in range(K)]))
+                win = win[(win >= 0) & (win < T)]
+                nblk_fwd = sum(1 for h in S for l in range(K) if 0 <= h - l < T)
+                Sset = set(S.tolist())
+                nblk_adj = sum(1 for t in win for l in range(K) if (t + l) in Sset)
+                bf += n_c[c] * (len(S) * L * (4 + s_state) + len(win) * P * s_state) + nblk_fwd * nnz * esz
+                ba += n_c[c] * (len(S) * L * s_state + len(win) * P * 4 * s_state) + nblk_adj * nnz * esz
+            fwd.append(bf)
+            adj.append(ba)
+    return np.array(fwd, dtype=np.float64), np.array(adj, dtype=np.float64)
+
+
+def run_form(dode, torch, inst, form, perms, E_total, warmup, steps, bh):
+    dt = torch.float64 if form == "f64" else torch.float32
+    t0 = time.time()
+    dar = dode.dar_create(inst.P, inst.L, inst.T, inst.H, inst.K, inst.row_ptr, inst.col_idx, inst.W,
+                          storage=form, stream=0)
+    X = torch.as_tensor(inst.x).to(device="cuda", dtype=dt).contiguous()
+    D = inst.D
+    Q = torch.zeros((D, inst.T, inst.P), dtype=dt, device="cuda")
+    A = torch.zeros_like(Q)
+    params = dode.make_params(epochs=E_total, batch_rows=8192, eta=5.0, optimizer=0)
+    plan = dode.spgd_plan_create(dar, inst.day_cluster, params, perm=perms, stream=0)
+    torch.cuda.synchronize()
+    log(f"{form}: dar + plan ready in {time.time() - t0:.1f}s")
+    stream = torch.cuda.current_stream()
+    dode.spgd_run(plan, X, Q, A, 0, warmup, stream=stream)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev0.record(stream)
+    dode.spgd_run(plan, X, Q, A, warmup, steps, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms = ev0.elapsed_time(ev1)
+    log(f"{form}: {steps} epochs in {ms:.2f} ms (wall {wall * 1e3:.2f} ms)")
+    # per-kernel durations: events around every launch, same epochs again
+    dode.spgd_plan_timing(plan, True)
+    e2 = warmup + steps
+    dode.spgd_run(plan, X, Q, A, e2, steps, stream=stream)
+    kms, kn = dode.spgd_plan_timing(plan, False)
+    torch.cuda.synchronize()
+    return dict(dar=dar, plan=plan, X=X, Q=Q, A=A, ms=ms, wall=wall, kernel_ms=kms, kernel_n=kn,
+                timing_epochs=list(range(e2, e2 + steps)))
+
+
+def solve_full(dode, torch, inst, form, perms_full, E, E_snap, sample):
+    """E-epoch solve of all days from zero; also returns the sample days' demand
+    after E_snap epochs (for the comparison with the oracle run of that length)."""
+    dt = torch.float64 if form == "f64" else torch.float32
+    dar = dode.dar_create(inst.P, inst.L, inst.T, inst.H, inst.K, inst.row_ptr, inst.col_idx, inst.W,
+                          storage=form, stream=0)
+    X = torch.as_tensor(inst.x).to(device="cuda", dtype=dt).contiguous()
+    Q = torch.zeros((inst.D, inst.T, inst.P), dtype=dt, device="cuda")
+    A = torch.zeros_like(Q)
+    p = dode.make_params(epochs=E, batch_rows=8192, eta=5.0, optimizer=0)
+    plan = dode.spgd_plan_create(dar, inst.day_cluster, p, perm=perms_full, stream=0)
+    t0 = time.time()
+    dode.spgd_run(plan, X, Q, A, 0, E_snap)
+    snap = Q[torch.as_tensor(sample, device="cuda")].double().cpu().numpy()
+    dode.spgd_run(plan, X, Q, A, E_snap, E - E_snap)
+    torch.cuda.synchronize()
+    log(f"{form}: full {E}-epoch solve in {time.time() - t0:.2f}s")
+    plan.close()
+    del X, A, dar
+    return Q, snap
+
+
+def fp64_losses(dode, torch, inst, Qs):
+    """Per-day loss of each demand in Qs, in FP64 against the exact FP64 ratios."""
+    dar = dode.dar_create(inst.P, inst.L, inst.T, inst.H, inst.K, inst.row_ptr, inst.col_idx, inst.W,
+                          storage="f64", stream=0)
+    out = {k: np.zeros(inst.D) for k in Qs}
+    for c in range(inst.C):
+        days = np.nonzero(inst.day_cluster == c)[0]
+        sl = slice(days[0], days[-1] + 1)
+        X = torch.as_tensor(inst.x[sl]).to(device="cuda", dtype=torch.float64).contiguous()
+        for k, Q in Qs.items():
+            loss = torch.empty(len(days), dtype=torch.float64, device="cuda")
+            dode.dode_loss(dar, c, Q[sl].double().contiguous(), X, loss)
+            out[k][sl] = loss.cpu().numpy()
+    torch.cuda.synchronize()
+    return out
+
+
+def cpu_baseline(inst, perms_full, sample, target_s=20.0, max_epochs=300):
+    """Time the FP64 oracle on the sample days (all in parallel) for as many
+    epochs as fit in about target_s seconds (calibrated on two epochs)."""
+    import oracle as orc
+    from synth import chunk_h_blocks
+    nthreads = min(len(sample), os.cpu_count() or 1)
+    x64 = inst.x[sample].astype(np.float64)
+
+    class _Days:
+        pass
+    sub = _Days()
+    for k in ("P", "L", "T", "H", "K", "row_ptr", "col_idx", "W", "C"):
+        setattr(sub, k, getattr(inst, k))
+    sub.day_cluster = inst.day_cluster[sample]
+    sub.D = len(sample)
+    bh = chunk_h_blocks(inst.L, inst.H, 8192)
+    t0 = time.perf_counter()
+    orc.spgd(sub, x64, perms_full, 2, bh, eta=5.0, record_loss=False, nthreads=nthreads)
+    per_epoch = (time.perf_counter() - t0) / 2
+    E = int(max(2, min(max_epochs, target_s / per_epoch)))
+    t0 = time.perf_counter()
+    Q, _, _ = orc.spgd(sub, x64, perms_full, E, bh, eta=5.0, record_loss=False, nthreads=nthreads)
+    dt = time.perf_counter() - t0
+    return dict(value=len(sample) * E / dt, seconds=dt, threads=nthreads, epochs=E, sub=sub, x64=x64,
+                Q=Q)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=3, choices=[2, 3, 5])
+    ap.add_argument("--form", default="bf16", choices=["f32", "bf16", "fp8", "f64"])
+    ap.add_argument("--compare", default="f32", help="plain form timed beside the headline ('' = none)")
+    ap.add_argument("--epochs", type=int, default=300, help="epochs of the equal-loss solves")
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--skip-check", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the days are independent, "
+              "so a multi-GPU run would only repeat the one-GPU kernel on each GPU's share of days.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1901_09266_amd as dode
+    from synth import make_config, make_perms, chunk_h_blocks
+
+    t0 = time.time()
+    inst = make_config(args.config)
+    log(f"config {args.config}: D={inst.D} C={inst.C} nnz={inst.nnz} generated in {time.time() - t0:.1f}s")
+    bh = chunk_h_blocks(inst.L, inst.H, 8192)
+    E_total = args.warmup + 2 * args.steps
+    perms = make_perms(inst.seed + 1, max(E_total, args.epochs), inst.C, inst.H)
+    forms = [args.form] + ([args.compare] if args.compare and args.compare != args.form else [])
+    res = {}
+    for f in forms:
+        r = run_form(dode, torch, inst, f, perms[:E_total], E_total, args.warmup, args.steps, bh)
+        fb, ab = launch_bytes(inst, perms, bh, ESIZE[f], r["timing_epochs"])
+        r["fwd_bytes"], r["adj_bytes"] = fb.sum(), ab.sum()
+        res[f] = r
+        for k in ("plan", "dar", "X", "Q", "A"):
+            r.pop(k)
+        torch.cuda.empty_cache()
+
+    head = res[args.form]
+    ms_step = head["ms"] / args.steps
+    value = inst.D * args.steps / (head["ms"] / 1e3)
+    # roofline of the dominant kernel (largest summed duration in the timed pass)
+    kms, kn = head["kernel_ms"], head["kernel_n"]
+    names = ["chunk_resid (forward + residual)", "chunk_adj_step (adjoint + Adagrad + projection)"]
+    k = int(np.argmax(kms[:2]))
+    byts = head["fwd_bytes"] if k == 0 else head["adj_bytes"]
+    achieved = byts / (kms[k] / 1e3) / 1e9
+    roof = {"bound": "hbm", "kernel": names[k], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "avg_launch_us": round(kms[k] / kn[k] * 1e3, 2), "launches": kn[k],
+            "bytes_per_launch": round(byts / kn[k]), "kernel_ms_per_step":
+            [round(kms[i] / args.steps, 4) for i in range(2)]}
+
+    out = {"metric": "SPGD day-gradients/sec", "value": round(value, 1), "unit": "day-gradients/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": {"bf16": "bf16", "f32": "f32", "fp8": "f32", "f64": "f64"}[args.form],
+           "data": "synthetic",
+           "config": {"workload": f"config {args.config}: " + WORKLOADS[args.config],
+                      "form": FORMS[args.form],
+                      "global_batch": inst.D, "seq_len": inst.H, "parallelism": "none (1 GPU)",
+                      "epochs_per_step": 1, "batch_rows": 8192, "minibatch_intervals": bh},
+           "roofline": roof}
+    out["forms"] = {f: {"day_gradients_per_s": round(inst.D * args.steps / (r["ms"] / 1e3), 1),
+                        "ms_per_step": round(r["ms"] / args.steps, 4),
+                        "kernel_ms_per_step": [round(x / args.steps, 4) for x in r["kernel_ms"][:2]]}
+                    for f, r in res.items()}
+
+    if not args.skip_check:
+        import oracle as orc
+        E = args.epochs
+        sample = np.array([np.nonzero(inst.day_cluster == c)[0][0] for c in range(inst.C)])
+        cb = None
+        if not args.skip_cpu:
+            cb = cpu_baseline(inst, perms[:E], sample)
+            log(f"oracle: {len(sample)} days x {cb['epochs']} epochs in {cb['seconds']:.1f}s")
+        E_snap = cb["epochs"] if cb else E
+        sols = {f: solve_full(dode, torch, inst, f, perms[:E], E, E_snap, sample) for f in forms}
+        L64 = fp64_losses(dode, torch, inst, {f: q for f, (q, _) in sols.items()})
+        chk = {}
+        ref = forms[-1]
+        for f in forms:
+            chk[f] = {"epochs": E, "total_loss_fp64": float(L64[f].sum())}
+            if f != ref:
+                chk[f]["rel_vs_" + ref] = float(abs(L64[f].sum() - L64[ref].sum()) / L64[ref].sum())
+        if cb:
+            # oracle demand after E_snap epochs on the sample days
+            lo, _, _ = orc.metrics(cb["sub"], cb["x64"], cb["Q"])
+            for f, (_, snap) in sols.items():
+                lg, _, _ = orc.metrics(cb["sub"], cb["x64"], snap)
+                chk[f]["sample_epochs"] = E_snap
+                chk[f]["max_rel_vs_oracle_sample"] = float(np.max(np.abs(lg - lo) / lo))
+            out["cpu_baseline"] = {"value": round(cb["value"], 3), "unit": "day-gradients/s",
+                                   "cores": cb["threads"], "kind": "oracle",
+                                   "sample": f"{len(sample)} days (first of each cluster) x "
+                                             f"{cb['epochs']} epochs of Algorithm 1 in FP64, "
+                                             f"{cb['seconds']:.1f}s"}
+        out["equal_loss"] = chk
+        del sols
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

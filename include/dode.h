@@ -79,13 +79,16 @@ typedef struct {
   double eps;          /* Adagrad denominator offset, added after the square root */
   int32_t optimizer;   /* 0 = Adagrad (Algorithm 1), 1 = fixed step q -= eta g */
   int32_t check_finite;/* nonzero: scan X for NaN/Inf before solving */
+  int32_t kernel_path; /* 0 = fastest available for the storage type (matrix-core
+                          tiles for BF16 / FP8), 1 = sparse pattern kernels */
 } dode_spgd_params;
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* dode_last_error(void);
 
 /* Fill p with the defaults: epochs 300, batch_rows 8192, eta 5, eps 1e-10,
- * Adagrad, check_finite 1 (section "Goodness of fit" gives E, b and eta). */
+ * Adagrad, check_finite 1, kernel_path 0 (section "Goodness of fit" gives E,
+ * b and eta). */
 void dode_spgd_defaults(dode_spgd_params* p);
 
 /*
@@ -170,6 +173,42 @@ dode_status spgd_step(const dode_dar* dar, int32_t cluster, const int32_t* chunk
 dode_status spgd_solve(const dode_dar* dar, const int32_t* day_cluster, int32_t D, const void* X,
                        void* Q, void* A, const dode_spgd_params* params, const int32_t* perm,
                        uint64_t seed, double* loss_hist, void* stream);
+
+/*
+ * Reusable form of spgd_solve for repeated or timed runs: the plan holds the
+ * minibatch schedule of every epoch (permutations, their inverses, the
+ * departure intervals each minibatch reaches) and the residual scratch, on
+ * the device of `dar`.  Arguments as for spgd_solve; `params->epochs` is the
+ * number of epochs the schedule covers.  The plan keeps a pointer to `dar`,
+ * which must outlive it.  Synchronises `stream`.
+ */
+typedef struct dode_plan dode_plan;
+
+dode_status spgd_plan_create(const dode_dar* dar, const int32_t* day_cluster, int32_t D,
+                             const dode_spgd_params* params, const int32_t* perm, uint64_t seed,
+                             void* stream, dode_plan** out);
+
+dode_status spgd_plan_destroy(dode_plan* plan);
+
+/*
+ * Epochs epoch_begin .. epoch_begin+n_epochs-1 of the plan's schedule on the
+ * caller's X (dev [D][H][L]), Q and A (dev [D][T][P], in/out, state type).
+ * Q must already be >= 0 (spgd_solve projects it first).  loss_dev (dev
+ * double [n_epochs][D]) receives the full loss of each day after each epoch,
+ * or pass NULL to skip that extra forward pass.  Asynchronous on `stream`;
+ * calls on one plan must not overlap (they share its scratch).
+ */
+dode_status spgd_run(dode_plan* plan, const void* X, void* Q, void* A, int32_t epoch_begin,
+                     int32_t n_epochs, double* loss_dev, void* stream);
+
+/*
+ * Kernel timing of a plan.  enable != 0 makes later spgd_run calls record a
+ * HIP event pair around every kernel launch on the run's stream; the summed
+ * durations in milliseconds (host [3]: forward-residual kernel, adjoint-step
+ * kernel, loss kernels) and the launch counts (host [3]) are returned and
+ * reset by the next call (which synchronises the last run's stream).
+ */
+dode_status spgd_plan_timing(dode_plan* plan, int32_t enable, double* ms, int64_t* launches);
 
 #ifdef __cplusplus
 }

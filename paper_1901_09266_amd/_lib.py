@@ -25,7 +25,7 @@ STORAGE = {"f64": DODE_F64, "f32": DODE_F32, "bf16": DODE_BF16, "fp8": DODE_FP8_
 # Every symbol include/dode.h declares (checked by the CPU test suite).
 EXPORTS = ["dode_last_error", "dode_spgd_defaults", "dar_create", "dar_destroy", "dar_info",
            "dar_set_values", "dode_apply", "dode_loss", "dode_grad", "dode_metrics", "spgd_step",
-           "spgd_solve"]
+           "spgd_solve", "spgd_plan_create", "spgd_plan_destroy", "spgd_run", "spgd_plan_timing"]
 
 
 class DodeError(RuntimeError):
@@ -43,7 +43,7 @@ class Dims(ctypes.Structure):
 class SpgdParams(ctypes.Structure):
     _fields_ = [("epochs", ctypes.c_int32), ("batch_rows", ctypes.c_int32), ("eta", ctypes.c_double),
                 ("eps", ctypes.c_double), ("optimizer", ctypes.c_int32),
-                ("check_finite", ctypes.c_int32)]
+                ("check_finite", ctypes.c_int32), ("kernel_path", ctypes.c_int32)]
 
 
 _lib = None
@@ -73,6 +73,11 @@ def lib():
         L.spgd_step.argtypes = [vp, i32, P(i32), i32, vp, vp, vp, i32, P(SpgdParams), vp]
         L.spgd_solve.argtypes = [vp, P(i32), i32, vp, vp, vp, P(SpgdParams), P(i32), ctypes.c_uint64,
                                  P(dbl), vp]
+        L.spgd_plan_create.argtypes = [vp, P(i32), i32, P(SpgdParams), P(i32), ctypes.c_uint64, vp,
+                                       P(vp)]
+        L.spgd_plan_destroy.argtypes = [vp]
+        L.spgd_run.argtypes = [vp, vp, vp, vp, i32, i32, vp, vp]
+        L.spgd_plan_timing.argtypes = [vp, i32, P(dbl), P(i64)]
         for name in EXPORTS:
             if name not in ("dode_last_error", "dode_spgd_defaults"):
                 getattr(L, name).restype = ctypes.c_int
@@ -115,9 +120,11 @@ def spgd_defaults() -> SpgdParams:
     return p
 
 
-def make_params(epochs=300, batch_rows=8192, eta=5.0, eps=1e-10, optimizer=0, check_finite=1):
+def make_params(epochs=300, batch_rows=8192, eta=5.0, eps=1e-10, optimizer=0, check_finite=1,
+                kernel_path=0):
+    """kernel_path 0 = fastest for the storage type, 1 = sparse pattern kernels."""
     return SpgdParams(int(epochs), int(batch_rows), float(eta), float(eps), int(optimizer),
-                      int(check_finite))
+                      int(check_finite), int(kernel_path))
 
 
 class Dar:
@@ -247,3 +254,59 @@ def spgd_solve(dar: Dar, day_cluster, X, Q, A, params: SpgdParams, perm=None, se
                             _ptr(A, "A", dar.state_dtype, (D, T, P)), ctypes.byref(params), pp,
                             ctypes.c_uint64(seed), hp, _stream(stream)))
     return hist
+
+
+class Plan:
+    """Owner of a dode_plan handle; keeps its Dar alive."""
+
+    def __init__(self, handle, dar, D, E):
+        self.handle = handle
+        self.dar = dar
+        self.D = D
+        self.E = E
+
+    def close(self):
+        if self.handle:
+            lib().spgd_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def spgd_plan_create(dar: Dar, day_cluster, params: SpgdParams, perm=None, seed=0, stream=None) -> Plan:
+    P, L, T, H, K = dar.dims
+    dc = np.ascontiguousarray(day_cluster, dtype=np.int32)
+    pp = ctypes.POINTER(ctypes.c_int32)()
+    if perm is not None:
+        perm = np.ascontiguousarray(perm, dtype=np.int32)
+        if perm.shape != (params.epochs, dar.C, H):
+            raise ValueError(f"perm must be [E][C][H] = {(params.epochs, dar.C, H)}")
+        pp = perm.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    out = ctypes.c_void_p()
+    _check(lib().spgd_plan_create(dar.handle, dc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                  dc.size, ctypes.byref(params), pp, ctypes.c_uint64(seed),
+                                  _stream(stream), ctypes.byref(out)))
+    return Plan(out, dar, dc.size, params.epochs)
+
+
+def spgd_run(plan: Plan, X, Q, A, epoch_begin, n_epochs, loss=None, stream=None):
+    import torch
+    P, L, T, H, K = plan.dar.dims
+    D = plan.D
+    dt = plan.dar.state_dtype
+    _check(lib().spgd_run(plan.handle, _ptr(X, "X", dt, (D, H, L)), _ptr(Q, "Q", dt, (D, T, P)),
+                          _ptr(A, "A", dt, (D, T, P)), int(epoch_begin), int(n_epochs),
+                          _ptr(loss, "loss", torch.float64, (n_epochs, D)) if loss is not None
+                          else ctypes.c_void_p(0), _stream(stream)))
+
+
+def spgd_plan_timing(plan: Plan, enable: bool):
+    """Returns (ms[3], launches[3]) accumulated since the last call and switches timing."""
+    ms = (ctypes.c_double * 3)()
+    n = (ctypes.c_int64 * 3)()
+    _check(lib().spgd_plan_timing(plan.handle, int(bool(enable)), ms, n))
+    return list(ms), list(n)

@@ -144,32 +144,6 @@ dode_status build_sched(const dode_dims& dm, int32_t C, int32_t E, int32_t bh,
   return DODE_OK;
 }
 
-struct DevSched {
-  DevBuf perm, pos, touched;
-  int32_t bh = 0, nch = 0, mt = 0, C = 0, H = 0;
-  ChunkSched chunk(int32_t e, int32_t j) const {
-    return ChunkSched{perm.as<int32_t>() + (size_t)e * C * H, pos.as<int32_t>() + (size_t)e * C * H,
-                      touched.as<int32_t>() + ((size_t)e * nch + j) * C * mt, j * bh, bh, mt};
-  }
-};
-
-dode_status upload_sched(const HostSched& hs, int32_t C, int32_t H, hipStream_t s, DevSched& ds) {
-  ds.bh = hs.bh;
-  ds.nch = hs.nch;
-  ds.mt = hs.mt;
-  ds.C = C;
-  ds.H = H;
-  HIP_TRY(ds.perm.alloc(hs.perm.size() * 4, s));
-  HIP_TRY(ds.pos.alloc(hs.pos.size() * 4, s));
-  HIP_TRY(ds.touched.alloc(hs.touched.size() * 4, s));
-  HIP_TRY(hipMemcpyAsync(ds.perm.p, hs.perm.data(), hs.perm.size() * 4, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(ds.pos.p, hs.pos.data(), hs.pos.size() * 4, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(ds.touched.p, hs.touched.data(), hs.touched.size() * 4,
-                         hipMemcpyHostToDevice, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  return DODE_OK;
-}
-
 dode_status check_params(const dode_spgd_params* p) {
   if (!p) return fail(DODE_ERR_ARG, "params is NULL");
   if (p->epochs < 0) return fail(DODE_ERR_ARG, "epochs=%d is negative", p->epochs);
@@ -178,6 +152,8 @@ dode_status check_params(const dode_spgd_params* p) {
   if (!(p->eps >= 0) || !std::isfinite(p->eps)) return fail(DODE_ERR_ARG, "eps must be >= 0");
   if (p->optimizer != 0 && p->optimizer != 1)
     return fail(DODE_ERR_ARG, "optimizer=%d (0 Adagrad, 1 fixed step)", p->optimizer);
+  if (p->kernel_path != 0 && p->kernel_path != 1)
+    return fail(DODE_ERR_ARG, "kernel_path=%d (0 best, 1 sparse)", p->kernel_path);
   return DODE_OK;
 }
 
@@ -246,6 +222,66 @@ double host_e4m3_to_f64(uint8_t b) {
   return (b & 0x80) ? -v : v;
 }
 
+namespace {
+
+hipEvent_t plan_event(dode_plan* p) {
+  if (p->event_next < p->event_pool.size()) return p->event_pool[p->event_next++];
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  p->event_pool.push_back(e);
+  p->event_next = p->event_pool.size();
+  return e;
+}
+
+// Launch `f` and, when timing is on, bracket it with an event pair of kind k.
+template <typename F>
+hipError_t timed(dode_plan* p, int k, hipStream_t s, F&& f) {
+  if (!p->timing) return f();
+  hipEvent_t a = plan_event(p), b = plan_event(p);
+  if (!a || !b) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(a, s);
+  if (e != hipSuccess) return e;
+  e = f();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(b, s);
+  p->pending[k].push_back({a, b});
+  return e;
+}
+
+}  // namespace
+
+namespace {
+
+// Minibatch j of epoch e: forward + residual, then adjoint + step + projection.
+dode_status run_minibatch(dode_plan* plan, const void* X, void* Q, void* A, int32_t e, int32_t j,
+                          hipStream_t s) {
+  const dode_dar* dar = plan->dar;
+  const ChunkSched cs = plan->chunk(e, j);
+  if (plan->use_mfma) {
+    const DayGroups dg = plan->groups();
+    float* R = static_cast<float*>(plan->d_R);
+    HIP_TRY(timed(plan, 0, s, [&] {
+      return mfma_chunk_resid(dar, cs, dg, static_cast<const float*>(Q),
+                              static_cast<const float*>(X), R, s);
+    }));
+    HIP_TRY(timed(plan, 1, s, [&] {
+      return mfma_chunk_adj_step(dar, cs, dg, R, static_cast<float*>(Q), static_cast<float*>(A),
+                                 plan->sa, s);
+    }));
+    return DODE_OK;
+  }
+  const int32_t* dc = plan->d_dc;
+  HIP_TRY(timed(plan, 0, s, [&] {
+    return plain_chunk_resid(dar, dc, 0, cs, Q, X, plan->d_R, plan->D, s);
+  }));
+  HIP_TRY(timed(plan, 1, s, [&] {
+    return plain_chunk_adj_step(dar, dc, 0, cs, plan->d_R, Q, A, plan->D, plan->sa, s);
+  }));
+  return DODE_OK;
+}
+
+}  // namespace
+
 // ================================================================== ABI ==
 extern "C" {
 
@@ -259,6 +295,7 @@ void dode_spgd_defaults(dode_spgd_params* p) {
   p->eps = 1e-10;
   p->optimizer = 0;
   p->check_finite = 1;
+  p->kernel_path = 0;
 }
 
 dode_status dar_destroy(dode_dar* dar) {
@@ -268,7 +305,8 @@ dode_status dar_destroy(dode_dar* dar) {
   (void)hipSetDevice(dar->device);
   for (void* p : {(void*)dar->d_row_ptr, (void*)dar->d_col, (void*)dar->d_col_ptr,
                   (void*)dar->d_row, (void*)dar->d_csc2csr, dar->d_W, dar->d_WT,
-                  (void*)dar->d_scale})
+                  (void*)dar->d_scale, (void*)dar->d_tile_meta, dar->d_Fv, dar->d_Gv,
+                  (void*)dar->d_Fsc, (void*)dar->d_Gsc})
     if (p) (void)hipFree(p);
   (void)hipSetDevice(cur);
   delete dar;
@@ -406,6 +444,13 @@ dode_status dar_create(const dode_dims* dims, int32_t n_clusters, const int32_t*
       HIP_TRY(hipMemcpy(d->d_scale + (size_t)c * dm.K * dm.T * n_ptile, hs.data(), hs.size() * 4,
                         hipMemcpyHostToDevice));
   }
+  if (storage == DODE_BF16 || storage == DODE_FP8_E4M3) {
+    std::string err;
+    if (dode_status st = build_tiles(d.get(), values, err)) {
+      dar_destroy(d.release());
+      return fail(st, "tile build failed: %s", err.c_str());
+    }
+  }
   HIP_TRY(hipStreamSynchronize(s));
   *out = d.release();
   return DODE_OK;
@@ -515,8 +560,9 @@ dode_status spgd_step(const dode_dar* dar, int32_t cluster, const int32_t* chunk
   const dode_dims& dm = dar->dims;
   if (!chunk_h || n_h < 1 || n_h > dm.H) return fail(DODE_ERR_ARG, "chunk_h must list 1..H intervals");
   if (n_days == 0) return DODE_OK;
-  if (!X || !Q || (!A && params->optimizer == 0)) return fail(DODE_ERR_ARG, "X, Q or A is NULL");
-  // one permutation per cluster whose first n_h positions are the chunk
+  if (!X || !Q || !A) return fail(DODE_ERR_ARG, "X, Q or A is NULL");
+  if ((int64_t)n_h * dm.L > INT32_MAX) return fail(DODE_ERR_SHAPE, "minibatch too large");
+  // one permutation per cluster whose first n_h positions are the minibatch
   std::vector<int32_t> perm((size_t)dar->C * dm.H);
   std::vector<char> seen(dm.H, 0);
   for (int32_t i = 0; i < n_h; ++i) {
@@ -531,22 +577,147 @@ dode_status spgd_step(const dode_dar* dar, int32_t cluster, const int32_t* chunk
     for (int32_t h = 0; h < dm.H; ++h)
       if (!seen[h]) p[k++] = h;
   }
+  dode_spgd_params p1 = *params;
+  p1.epochs = 1;
+  p1.batch_rows = n_h * dm.L;
+  std::vector<int32_t> dc(n_days, cluster);
+  dode_plan* raw = nullptr;
+  if (dode_status st = spgd_plan_create(dar, dc.data(), n_days, &p1, perm.data(), 0, stream, &raw))
+    return st;
+  std::unique_ptr<dode_plan, dode_status (*)(dode_plan*)> plan(raw, spgd_plan_destroy);
+  if (dode_status st = run_minibatch(plan.get(), X, Q, A, 0, 0, as_stream(stream))) return st;
+  HIP_TRY(hipStreamSynchronize(as_stream(stream)));
+  return DODE_OK;
+}
+
+dode_status spgd_plan_destroy(dode_plan* plan) {
+  if (!plan) return DODE_OK;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(plan->device);
+  if (plan->last_stream) (void)hipStreamSynchronize(plan->last_stream);
+  for (void* p : {(void*)plan->d_perm, (void*)plan->d_pos, (void*)plan->d_touched,
+                  (void*)plan->d_dc, plan->d_R, (void*)plan->d_part, (void*)plan->d_groups})
+    if (p) (void)hipFree(p);
+  for (hipEvent_t e : plan->event_pool) (void)hipEventDestroy(e);
+  (void)hipSetDevice(cur);
+  delete plan;
+  return DODE_OK;
+}
+
+dode_status spgd_plan_create(const dode_dar* dar, const int32_t* day_cluster, int32_t D,
+                             const dode_spgd_params* params, const int32_t* perm, uint64_t seed,
+                             void* stream, dode_plan** out) {
+  if (!out) return fail(DODE_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!dar) return fail(DODE_ERR_ARG, "dar handle is NULL");
+  if (dode_status st = check_days(D)) return st;
+  if (dode_status st = check_params(params)) return st;
+  if (D < 1) return fail(DODE_ERR_ARG, "a plan needs D >= 1 days");
+  if (params->epochs < 1) return fail(DODE_ERR_ARG, "a plan needs epochs >= 1");
+  if (!day_cluster) return fail(DODE_ERR_ARG, "day_cluster is NULL");
+  for (int32_t d = 0; d < D; ++d)
+    if (day_cluster[d] < 0 || day_cluster[d] >= dar->C)
+      return fail(DODE_ERR_ARG, "day_cluster[%d]=%d out of range", d, day_cluster[d]);
+  const dode_dims& dm = dar->dims;
+  const int32_t E = params->epochs, C = dar->C;
+  const int32_t bh = std::max<int32_t>(1, std::min<int32_t>(dm.H, params->batch_rows / dm.L));
   HostSched hs;
-  if (dode_status st = build_sched(dm, dar->C, 1, n_h, perm.data(), 0, hs)) return st;
-  hipStream_t s = as_stream(stream);
-  DevSched ds;
-  if (dode_status st = upload_sched(hs, dar->C, dm.H, s, ds)) return st;
-  DevBuf R, Adummy;
-  HIP_TRY(R.alloc((size_t)n_days * n_h * dm.L * state_size(dar), s));
-  if (!A) {
-    HIP_TRY(Adummy.alloc((size_t)n_days * dm.T * dm.P * state_size(dar), s));
-    A = Adummy.p;
+  if (dode_status st = build_sched(dm, C, E, bh, perm, seed, hs)) return st;
+  std::unique_ptr<dode_plan, dode_status (*)(dode_plan*)> pl(new dode_plan(), spgd_plan_destroy);
+  dode_plan* p = pl.get();
+  p->dar = dar;
+  p->D = D;
+  p->E = E;
+  p->C = C;
+  p->bh = hs.bh;
+  p->nch = hs.nch;
+  p->mt = hs.mt;
+  p->sa = StepArgs{params->eta, params->eps, params->optimizer};
+  HIP_TRY(hipGetDevice(&p->device));
+  auto up = [&](int32_t** dst, const void* src, size_t bytes) -> hipError_t {
+    hipError_t e = hipMalloc(dst, std::max<size_t>(bytes, 16));
+    if (e != hipSuccess) return e;
+    return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+  };
+  HIP_TRY(up(&p->d_perm, hs.perm.data(), hs.perm.size() * 4));
+  HIP_TRY(up(&p->d_pos, hs.pos.data(), hs.pos.size() * 4));
+  HIP_TRY(up(&p->d_touched, hs.touched.data(), hs.touched.size() * 4));
+  HIP_TRY(up(&p->d_dc, day_cluster, (size_t)D * 4));
+  HIP_TRY(hipMalloc(&p->d_R, (size_t)D * bh * dm.L * state_size(dar)));
+  HIP_TRY(hipMalloc(&p->d_part, (size_t)D * dm.H * 8));
+  {
+    // groups of up to 32 days of one cluster, clusters in order
+    std::vector<int32_t> gc, gf, gn, days;
+    for (int32_t c = 0; c < C; ++c) {
+      const int32_t start = (int32_t)days.size();
+      for (int32_t d = 0; d < D; ++d)
+        if (day_cluster[d] == c) days.push_back(d);
+      for (int32_t f = start; f < (int32_t)days.size(); f += 32) {
+        gc.push_back(c);
+        gf.push_back(f);
+        gn.push_back(std::min<int32_t>(32, (int32_t)days.size() - f));
+      }
+    }
+    p->n_groups = (int32_t)gc.size();
+    if (p->n_groups > 65535) return fail(DODE_ERR_SHAPE, "too many day groups (%d)", p->n_groups);
+    std::vector<int32_t> buf;
+    buf.insert(buf.end(), gc.begin(), gc.end());
+    buf.insert(buf.end(), gf.begin(), gf.end());
+    buf.insert(buf.end(), gn.begin(), gn.end());
+    buf.insert(buf.end(), days.begin(), days.end());
+    HIP_TRY(up(&p->d_groups, buf.data(), buf.size() * 4));
   }
-  const StepArgs sa{params->eta, params->eps, params->optimizer};
-  const ChunkSched cs = ds.chunk(0, 0);
-  HIP_TRY(plain_chunk_resid(dar, nullptr, cluster, cs, Q, X, R.p, n_days, s));
-  HIP_TRY(plain_chunk_adj_step(dar, nullptr, cluster, cs, R.p, Q, A, n_days, sa, s));
-  HIP_TRY(hipStreamSynchronize(s));
+  p->use_mfma = dar->has_tiles && dar->storage == DODE_BF16 && params->kernel_path == 0;
+  (void)stream;
+  *out = pl.release();
+  return DODE_OK;
+}
+
+
+dode_status spgd_run(dode_plan* plan, const void* X, void* Q, void* A, int32_t epoch_begin,
+                     int32_t n_epochs, double* loss_dev, void* stream) {
+  if (!plan) return fail(DODE_ERR_ARG, "plan is NULL");
+  if (!X || !Q || !A) return fail(DODE_ERR_ARG, "X, Q or A is NULL");
+  if (epoch_begin < 0 || n_epochs < 0 || epoch_begin + n_epochs > plan->E)
+    return fail(DODE_ERR_ARG, "epochs [%d, %d) outside the plan's %d", epoch_begin,
+                epoch_begin + n_epochs, plan->E);
+  const dode_dar* dar = plan->dar;
+  const dode_dims& dm = dar->dims;
+  hipStream_t s = as_stream(stream);
+  plan->last_stream = s;
+  const int32_t D = plan->D;
+  const int32_t* dc = plan->d_dc;
+  for (int32_t e = epoch_begin; e < epoch_begin + n_epochs; ++e) {
+    for (int32_t j = 0; j < plan->nch; ++j)
+      if (dode_status st = run_minibatch(plan, X, Q, A, e, j, s)) return st;
+    if (loss_dev) {
+      double* out = loss_dev + (size_t)(e - epoch_begin) * D;
+      HIP_TRY(timed(plan, 2, s, [&] {
+        hipError_t r = plain_apply_rows(dar, dc, 0, Q, X, nullptr, plan->d_part, D, s);
+        return r != hipSuccess ? r : sum_partials(plan->d_part, dm.H, D, out, s);
+      }));
+    }
+  }
+  return DODE_OK;
+}
+
+dode_status spgd_plan_timing(dode_plan* plan, int32_t enable, double* ms, int64_t* launches) {
+  if (!plan) return fail(DODE_ERR_ARG, "plan is NULL");
+  if (plan->last_stream || plan->timing) HIP_TRY(hipStreamSynchronize(plan->last_stream));
+  for (int k = 0; k < 3; ++k) {
+    double tot = 0.0;
+    for (auto& pr : plan->pending[k]) {
+      float t = 0.f;
+      HIP_TRY(hipEventElapsedTime(&t, pr.first, pr.second));
+      tot += t;
+    }
+    if (ms) ms[k] = tot;
+    if (launches) launches[k] = (int64_t)plan->pending[k].size();
+    plan->pending[k].clear();
+  }
+  plan->event_next = 0;
+  plan->timing = enable != 0;
   return DODE_OK;
 }
 
@@ -558,41 +729,21 @@ dode_status spgd_solve(const dode_dar* dar, const int32_t* day_cluster, int32_t 
   if (dode_status st = check_params(params)) return st;
   if (D == 0 || params->epochs == 0) return DODE_OK;
   if (!day_cluster || !X || !Q || !A) return fail(DODE_ERR_ARG, "day_cluster, X, Q or A is NULL");
-  for (int32_t d = 0; d < D; ++d)
-    if (day_cluster[d] < 0 || day_cluster[d] >= dar->C)
-      return fail(DODE_ERR_ARG, "day_cluster[%d]=%d out of range", d, day_cluster[d]);
   const dode_dims& dm = dar->dims;
-  const int32_t E = params->epochs, C = dar->C;
-  const int32_t bh = std::max<int32_t>(1, std::min<int32_t>(dm.H, params->batch_rows / dm.L));
+  const int32_t E = params->epochs;
   hipStream_t s = as_stream(stream);
+  dode_plan* raw = nullptr;
+  if (dode_status st = spgd_plan_create(dar, day_cluster, D, params, perm, seed, stream, &raw))
+    return st;
+  std::unique_ptr<dode_plan, dode_status (*)(dode_plan*)> plan(raw, spgd_plan_destroy);
   if (params->check_finite)
     if (dode_status st = scan_finite(dar, X, (int64_t)D * dm.H * dm.L, s)) return st;
-  HostSched hs;
-  if (dode_status st = build_sched(dm, C, E, bh, perm, seed, hs)) return st;
-  DevSched ds;
-  if (dode_status st = upload_sched(hs, C, dm.H, s, ds)) return st;
-  DevBuf dcl, R, part, hist;
-  HIP_TRY(dcl.alloc((size_t)D * 4, s));
-  HIP_TRY(hipMemcpyAsync(dcl.p, day_cluster, (size_t)D * 4, hipMemcpyHostToDevice, s));
-  HIP_TRY(R.alloc((size_t)D * bh * dm.L * state_size(dar), s));
-  if (loss_hist) {
-    HIP_TRY(part.alloc((size_t)D * dm.H * 8, s));
-    HIP_TRY(hist.alloc((size_t)E * D * 8, s));
-  }
+  DevBuf hist;
+  if (loss_hist) HIP_TRY(hist.alloc((size_t)E * D * 8, s));
   HIP_TRY(clamp_nonneg(is_f64(dar), Q, (int64_t)D * dm.T * dm.P, s));
-  const StepArgs sa{params->eta, params->eps, params->optimizer};
-  const int32_t* dc = dcl.as<int32_t>();
-  for (int32_t e = 0; e < E; ++e) {
-    for (int32_t j = 0; j < ds.nch; ++j) {
-      const ChunkSched cs = ds.chunk(e, j);
-      HIP_TRY(plain_chunk_resid(dar, dc, 0, cs, Q, X, R.p, D, s));
-      HIP_TRY(plain_chunk_adj_step(dar, dc, 0, cs, R.p, Q, A, D, sa, s));
-    }
-    if (loss_hist) {
-      HIP_TRY(plain_apply_rows(dar, dc, 0, Q, X, nullptr, part.as<double>(), D, s));
-      HIP_TRY(sum_partials(part.as<double>(), dm.H, D, hist.as<double>() + (size_t)e * D, s));
-    }
-  }
+  if (dode_status st = spgd_run(plan.get(), X, Q, A, 0, E, loss_hist ? hist.as<double>() : nullptr,
+                                stream))
+    return st;
   if (loss_hist) {
     std::vector<double> h((size_t)E * D);
     HIP_TRY(hipMemcpyAsync(h.data(), hist.p, h.size() * 8, hipMemcpyDeviceToHost, s));

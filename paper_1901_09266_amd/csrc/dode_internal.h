@@ -31,6 +31,27 @@ struct DevVals {
   int32_t n_ptile;       // ceil(P/64)
 };
 
+// Dense MFMA tiles of the assignment blocks (BF16 / FP8 storage).
+//   forward:  link tile i (16 links) x OD hull [f_plo[i], f_plo[i] + 32*f_ks[i])
+//   adjoint:  OD tile j (16 ODs) x link hull [g_alo[j], g_alo[j] + 32*g_ks[j])
+// Values of block (c, l, t) are stored per 16x32 k-step in MFMA operand order
+// (lane-major, 8 consecutive k per lane): Fv[c][l][t][kf_total][64 lanes][8].
+// FP8 storage keeps one float scale per 16-row tile and k-step range:
+//   Fsc[c][l][t][kf_total], Gsc[c][l][t][kg_total].
+struct DevTiles {
+  int32_t nLT = 0, nPT = 0, kf_total = 0, kg_total = 0;
+  const int32_t* f_plo = nullptr;
+  const int32_t* f_ks = nullptr;
+  const int32_t* f_koff = nullptr;
+  const int32_t* g_alo = nullptr;
+  const int32_t* g_ks = nullptr;
+  const int32_t* g_koff = nullptr;
+  const void* Fv = nullptr;
+  const void* Gv = nullptr;
+  const float* Fsc = nullptr;
+  const float* Gsc = nullptr;
+};
+
 struct dode_dar {
   dode_dims dims{};
   int32_t C = 0;
@@ -47,6 +68,14 @@ struct dode_dar {
   float* d_scale = nullptr;
   int64_t device_bytes = 0;
   std::vector<int32_t> h_row_ptr, h_col, h_col_ptr, h_row, h_csc2csr;
+  // MFMA tile layout (BF16 / FP8 storage only)
+  bool has_tiles = false;
+  DevTiles tiles;
+  int32_t* d_tile_meta = nullptr;   // f_plo | f_ks | f_koff | g_alo | g_ks | g_koff
+  void* d_Fv = nullptr;
+  void* d_Gv = nullptr;
+  float* d_Fsc = nullptr;
+  float* d_Gsc = nullptr;
 
   DevPat pat() const {
     return DevPat{dims.P, dims.L, dims.T, dims.H, dims.K, nnz, d_row_ptr, d_col, d_col_ptr, d_row};
@@ -78,6 +107,47 @@ struct ChunkSched {
   int32_t max_touched;
 };
 
+// Groups of up to 32 days of one cluster (two 16-day MFMA column tiles).
+struct DayGroups {
+  const int32_t* cluster;   // [n]
+  const int32_t* first;     // [n] offset into days
+  const int32_t* count;     // [n] 1..32
+  const int32_t* days;      // [D] day indices grouped by cluster
+  int32_t n;
+};
+
+// Minibatch schedule and scratch of spgd_run (see spgd_plan_create).
+struct dode_plan {
+  const dode_dar* dar = nullptr;
+  int device = 0;
+  int32_t D = 0, E = 0, C = 0, bh = 0, nch = 0, mt = 0;
+  StepArgs sa{};
+  int32_t* d_perm = nullptr;      // [E][C][H]
+  int32_t* d_pos = nullptr;       // [E][C][H]
+  int32_t* d_touched = nullptr;   // [E][nch][C][mt]
+  int32_t* d_dc = nullptr;        // [D]
+  void* d_R = nullptr;            // [D][bh][L] residual rows of the current minibatch
+  double* d_part = nullptr;       // [D][H] loss partials
+  int32_t* d_groups = nullptr;    // cluster | first | count (n_groups each) | days [D]
+  int32_t n_groups = 0;
+  bool use_mfma = false;
+  hipStream_t last_stream = nullptr;
+  bool timing = false;
+  std::vector<hipEvent_t> event_pool;
+  size_t event_next = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[3];
+
+  DayGroups groups() const {
+    return DayGroups{d_groups, d_groups + n_groups, d_groups + 2 * n_groups, d_groups + 3 * n_groups,
+                     n_groups};
+  }
+  ChunkSched chunk(int32_t e, int32_t j) const {
+    const int32_t H = dar->dims.H;
+    return ChunkSched{d_perm + (size_t)e * C * H, d_pos + (size_t)e * C * H,
+                      d_touched + ((size_t)e * nch + j) * C * mt, j * bh, bh, mt};
+  }
+};
+
 bool is_f64(const dode_dar* d);
 
 // ---- plain kernels (plain_kernels.hip) ---------------------------------
@@ -96,6 +166,15 @@ hipError_t plain_apply_rows(const dode_dar* dar, const int32_t* day_cluster, int
 // G = rho^T R for full residual rows R [n][H][L]
 hipError_t plain_adjoint_rows(const dode_dar* dar, const int32_t* day_cluster, int32_t cluster,
                               const void* R, void* G, int32_t n_days, hipStream_t s);
+
+// ---- MFMA tile kernels (mfma_kernels.hip) -------------------------------
+hipError_t mfma_chunk_resid(const dode_dar* dar, const ChunkSched& cs, const DayGroups& dg,
+                            const float* Q, const float* X, float* R, hipStream_t s);
+hipError_t mfma_chunk_adj_step(const dode_dar* dar, const ChunkSched& cs, const DayGroups& dg,
+                               const float* R, float* Q, float* A, const StepArgs& st,
+                               hipStream_t s);
+// host: build the tile layout of all clusters from FP64 values (tiles.hip)
+dode_status build_tiles(dode_dar* d, const double* const* values, std::string& err);
 
 // ---- small generic kernels (plain_kernels.hip) -------------------------
 hipError_t sum_partials(const double* part, int32_t n_per, int32_t n_days, double* out,

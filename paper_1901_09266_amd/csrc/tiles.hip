@@ -1,0 +1,184 @@
+// Host construction of the dense MFMA tiles of the assignment blocks.
+//
+// Every lag block rho_c[l][t] (L links x P ODs, eq. "assign") shares one
+// incidence pattern.  For the forward product a tile row is 16 consecutive
+// links and its columns are the contiguous OD range that covers the ODs of
+// those links (padded to whole 32-wide k-steps); for the adjoint a tile row is
+// 16 consecutive ODs and its columns the covering link range.  Entries of the
+// range that are not in the pattern hold zero.  With ODs sorted along their
+// corridor the ranges are short, so most of the empty area of a block is
+// never stored or multiplied.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "dode_internal.h"
+
+namespace {
+
+int32_t round_up(int32_t x, int32_t m) { return (x + m - 1) / m * m; }
+
+struct Hull {
+  int32_t lo = 0, ks = 0;
+};
+
+// Covering ranges of `n_rows` rows grouped by 16, given per-row sorted column lists.
+std::vector<Hull> hulls(int32_t n_rows, int32_t n_cols, const std::vector<int32_t>& ptr,
+                        const std::vector<int32_t>& idx) {
+  const int32_t nt = (n_rows + 15) / 16;
+  std::vector<Hull> out(nt);
+  for (int32_t i = 0; i < nt; ++i) {
+    int32_t lo = n_cols, hi = 0;
+    for (int32_t r = 16 * i; r < std::min(n_rows, 16 * i + 16); ++r)
+      if (ptr[r + 1] > ptr[r]) {
+        lo = std::min(lo, idx[ptr[r]]);
+        hi = std::max(hi, idx[ptr[r + 1] - 1] + 1);
+      }
+    if (hi <= lo) continue;
+    const int32_t len = round_up(hi - lo, 32);
+    if (len <= n_cols) lo = std::min(lo, n_cols - len);   // keep the range inside [0, n_cols)
+    out[i].lo = lo;
+    out[i].ks = len / 32;
+  }
+  return out;
+}
+
+// Position of a (row, col) entry inside the packed k-steps of its row tile.
+int64_t packed_pos(int32_t row, int32_t col, const std::vector<Hull>& hs,
+                   const std::vector<int32_t>& koff) {
+  const int32_t i = row / 16, m = row % 16;
+  const int32_t k = col - hs[i].lo;
+  const int32_t ks = k / 32, kk = k % 32;
+  const int32_t lane = m + 16 * (kk / 8), e = kk % 8;
+  return ((int64_t)(koff[i] + ks) * 64 + lane) * 8 + e;
+}
+
+}  // namespace
+
+dode_status build_tiles(dode_dar* d, const double* const* values, std::string& err) {
+  const dode_dims& dm = d->dims;
+  const int64_t nnz = d->nnz;
+  const std::vector<Hull> fh = hulls(dm.L, dm.P, d->h_row_ptr, d->h_col);
+  const std::vector<Hull> gh = hulls(dm.P, dm.L, d->h_col_ptr, d->h_row);
+  const int32_t nLT = (int32_t)fh.size(), nPT = (int32_t)gh.size();
+  std::vector<int32_t> meta;
+  std::vector<int32_t> fko(nLT + 1, 0), gko(nPT + 1, 0);
+  for (int32_t i = 0; i < nLT; ++i) fko[i + 1] = fko[i] + fh[i].ks;
+  for (int32_t j = 0; j < nPT; ++j) gko[j + 1] = gko[j] + gh[j].ks;
+  for (auto& h : fh) meta.push_back(h.lo);
+  for (auto& h : fh) meta.push_back(h.ks);
+  for (int32_t i = 0; i < nLT; ++i) meta.push_back(fko[i]);
+  for (auto& h : gh) meta.push_back(h.lo);
+  for (auto& h : gh) meta.push_back(h.ks);
+  for (int32_t j = 0; j < nPT; ++j) meta.push_back(gko[j]);
+  const int32_t kf = fko[nLT], kg = gko[nPT];
+
+  // packed position of every pattern entry, forward (CSR slot j) and adjoint (CSC slot jj)
+  std::vector<int64_t> posf(nnz), posg(nnz);
+  for (int32_t a = 0; a < dm.L; ++a)
+    for (int32_t j = d->h_row_ptr[a]; j < d->h_row_ptr[a + 1]; ++j)
+      posf[j] = packed_pos(a, d->h_col[j], fh, fko);
+  for (int32_t p = 0; p < dm.P; ++p)
+    for (int32_t jj = d->h_col_ptr[p]; jj < d->h_col_ptr[p + 1]; ++jj)
+      posg[jj] = packed_pos(p, d->h_row[jj], gh, gko);
+
+  const bool fp8 = d->storage == DODE_FP8_E4M3;
+  const size_t esz = fp8 ? 1 : 2;
+  const int64_t blocks = (int64_t)dm.K * dm.T;
+  const size_t fblk = (size_t)kf * 512, gblk = (size_t)kg * 512;   // elements per block
+  const size_t fbytes = (size_t)d->C * blocks * fblk * esz, gbytes = (size_t)d->C * blocks * gblk * esz;
+
+  auto hip_ok = [&](hipError_t e) {
+    if (e != hipSuccess) err = hipGetErrorString(e);
+    return e == hipSuccess;
+  };
+  if (!hip_ok(hipMalloc(&d->d_tile_meta, std::max<size_t>(16, meta.size() * 4)))) return DODE_ERR_OOM;
+  if (!hip_ok(hipMemcpy(d->d_tile_meta, meta.data(), meta.size() * 4, hipMemcpyHostToDevice)))
+    return DODE_ERR_HIP;
+  if (!hip_ok(hipMalloc(&d->d_Fv, std::max<size_t>(16, fbytes)))) return DODE_ERR_OOM;
+  if (!hip_ok(hipMalloc(&d->d_Gv, std::max<size_t>(16, gbytes)))) return DODE_ERR_OOM;
+  d->device_bytes += fbytes + gbytes + meta.size() * 4;
+  size_t fsc_n = 0, gsc_n = 0;
+  if (fp8) {
+    fsc_n = (size_t)d->C * blocks * kf;
+    gsc_n = (size_t)d->C * blocks * kg;
+    if (!hip_ok(hipMalloc(&d->d_Fsc, std::max<size_t>(16, fsc_n * 4)))) return DODE_ERR_OOM;
+    if (!hip_ok(hipMalloc(&d->d_Gsc, std::max<size_t>(16, gsc_n * 4)))) return DODE_ERR_OOM;
+    d->device_bytes += (fsc_n + gsc_n) * 4;
+  }
+
+  std::vector<uint8_t> fbuf(blocks * fblk * esz), gbuf(blocks * gblk * esz);
+  std::vector<float> fsc(fp8 ? blocks * kf : 0), gsc(fp8 ? blocks * kg : 0);
+  std::vector<double> tmp;
+  for (int32_t c = 0; c < d->C; ++c) {
+    std::fill(fbuf.begin(), fbuf.end(), 0);
+    std::fill(gbuf.begin(), gbuf.end(), 0);
+    const double* W = values[c];
+    for (int64_t lt = 0; lt < blocks; ++lt) {
+      const int32_t l = (int32_t)(lt / dm.T), t = (int32_t)(lt % dm.T);
+      if (t + l >= dm.H) continue;   // block past the last interval: never read
+      const double* w = W + lt * nnz;
+      if (!fp8) {
+        uint16_t* fb = reinterpret_cast<uint16_t*>(fbuf.data()) + lt * fblk;
+        uint16_t* gb = reinterpret_cast<uint16_t*>(gbuf.data()) + lt * gblk;
+        for (int64_t j = 0; j < nnz; ++j) fb[posf[j]] = host_f64_to_bf16(w[j]);
+        for (int64_t jj = 0; jj < nnz; ++jj) gb[posg[jj]] = host_f64_to_bf16(w[d->h_csc2csr[jj]]);
+      } else {
+        // one scale per packed 16x32 tile: max |value| / 448
+        tmp.assign(fblk, 0.0);
+        for (int64_t j = 0; j < nnz; ++j) tmp[posf[j]] = w[j];
+        for (int32_t k = 0; k < kf; ++k) {
+          double mx = 0;
+          for (int e = 0; e < 512; ++e) mx = std::max(mx, std::fabs(tmp[(size_t)k * 512 + e]));
+          const float sc = mx > 0 ? static_cast<float>(mx / 448.0) : 1.0f;
+          fsc[lt * kf + k] = sc;
+          for (int e = 0; e < 512; ++e)
+            fbuf[lt * fblk + (size_t)k * 512 + e] = host_f64_to_e4m3(tmp[(size_t)k * 512 + e] / sc);
+        }
+        tmp.assign(gblk, 0.0);
+        for (int64_t jj = 0; jj < nnz; ++jj) tmp[posg[jj]] = w[d->h_csc2csr[jj]];
+        for (int32_t k = 0; k < kg; ++k) {
+          double mx = 0;
+          for (int e = 0; e < 512; ++e) mx = std::max(mx, std::fabs(tmp[(size_t)k * 512 + e]));
+          const float sc = mx > 0 ? static_cast<float>(mx / 448.0) : 1.0f;
+          gsc[lt * kg + k] = sc;
+          for (int e = 0; e < 512; ++e)
+            gbuf[lt * gblk + (size_t)k * 512 + e] = host_f64_to_e4m3(tmp[(size_t)k * 512 + e] / sc);
+        }
+      }
+    }
+    if (!hip_ok(hipMemcpy(static_cast<uint8_t*>(d->d_Fv) + (size_t)c * blocks * fblk * esz, fbuf.data(),
+                          fbuf.size(), hipMemcpyHostToDevice)))
+      return DODE_ERR_HIP;
+    if (!hip_ok(hipMemcpy(static_cast<uint8_t*>(d->d_Gv) + (size_t)c * blocks * gblk * esz, gbuf.data(),
+                          gbuf.size(), hipMemcpyHostToDevice)))
+      return DODE_ERR_HIP;
+    if (fp8) {
+      if (!hip_ok(hipMemcpy(d->d_Fsc + (size_t)c * blocks * kf, fsc.data(), fsc.size() * 4,
+                            hipMemcpyHostToDevice)))
+        return DODE_ERR_HIP;
+      if (!hip_ok(hipMemcpy(d->d_Gsc + (size_t)c * blocks * kg, gsc.data(), gsc.size() * 4,
+                            hipMemcpyHostToDevice)))
+        return DODE_ERR_HIP;
+    }
+  }
+  DevTiles& T = d->tiles;
+  T.nLT = nLT;
+  T.nPT = nPT;
+  T.kf_total = kf;
+  T.kg_total = kg;
+  const int32_t* m = d->d_tile_meta;
+  T.f_plo = m;
+  T.f_ks = m + nLT;
+  T.f_koff = m + 2 * nLT;
+  T.g_alo = m + 3 * nLT;
+  T.g_ks = m + 3 * nLT + nPT;
+  T.g_koff = m + 3 * nLT + 2 * nPT;
+  T.Fv = d->d_Fv;
+  T.Gv = d->d_Gv;
+  T.Fsc = d->d_Fsc;
+  T.Gsc = d->d_Gsc;
+  d->has_tiles = true;
+  return DODE_OK;
+}

@@ -154,13 +154,14 @@ def test_solve_adagrad_multicluster_f64(batch_rows):
     assert rel(Ag, Ao) <= 1e-8
 
 
-def test_solve_is_deterministic():
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_solve_is_deterministic(storage):
     inst = make_instance(P=20, L=40, T=24, K=4, sizes=(5, 3), inc=0.2, pattern="corridor",
                          demand="gamma", noise="mult5", seed=46)
-    say("determinism")
+    say("determinism", storage)
     perms = make_perms(47, 10, inst.C, inst.H)
-    a = run_solve(inst, "f32", 10, 200, 5.0, 0, perms)
-    b = run_solve(inst, "f32", 10, 200, 5.0, 0, perms)
+    a = run_solve(inst, storage, 10, 200, 5.0, 0, perms)
+    b = run_solve(inst, storage, 10, 200, 5.0, 0, perms)
     np.testing.assert_array_equal(a[0], b[0])
     np.testing.assert_array_equal(a[2], b[2])
 
@@ -196,3 +197,59 @@ def test_nonfinite_observations_rejected():
     A = torch.zeros_like(Q)
     with pytest.raises(dode.DodeError, match="NONFINITE"):
         dode.spgd_solve(dar, inst.day_cluster, dev(x, torch.float64), Q, A, dode.make_params(epochs=2))
+
+
+MFMA_SHAPES = {
+    # 16-row tiles with ragged ends on both sides, a 1-day and a 33-day cluster
+    "ragged": dict(P=37, L=50, T=20, H=23, K=4, sizes=(1, 33, 17), inc=0.2, pattern="bernoulli"),
+    "corridor": dict(P=150, L=500, T=24, K=6, sizes=(40, 5), inc=0.08, pattern="corridor"),
+    "wide": dict(P=70, L=9, T=10, K=3, sizes=(20,), inc=0.5, pattern="bernoulli"),
+}
+
+
+@pytest.mark.parametrize("name", list(MFMA_SHAPES))
+@pytest.mark.parametrize("opt", [0, 1])
+def test_mfma_step_matches_oracle(name, opt):
+    """One minibatch through the matrix-core kernels (bf16 values, split FP32
+    operands) against the oracle on the same rounded values."""
+    kw = dict(MFMA_SHAPES[name])
+    inst = make_instance(demand="uniform50", noise="add1", x_dtype="f32", seed=77, **kw)
+    say("mfma step", name, opt)
+    Wq = dequantized_values(inst, "bf16")
+    rng = np.random.default_rng(8)
+    Q0 = rng.uniform(0, 5, (inst.D, inst.T, inst.P)).astype(np.float32).astype(np.float64)
+    A0 = rng.uniform(0, 2, (inst.D, inst.T, inst.P)).astype(np.float32).astype(np.float64)
+    X = inst.x.astype(np.float64)
+    chunk = rng.choice(inst.H, size=min(inst.H, 7), replace=False).astype(np.int32)
+    eta = 0.3 if opt == 0 else 1e-4
+    dar = make_dar(inst, "bf16")
+    for c in range(inst.C):
+        days = inst.days_of(c)
+        Qd, Ad = dev(Q0[days], torch.float32), dev(A0[days], torch.float32)
+        p = dode.make_params(eta=eta, optimizer=opt)
+        dode.spgd_step(dar, c, chunk, dev(X[days], torch.float32), Qd, Ad, p)
+        torch.cuda.synchronize()
+        Qg, Ag = Qd.cpu().numpy(), Ad.cpu().numpy()
+        for k, d in enumerate(days):
+            q, A = orc.spgd_step(inst, Wq[c], X[d], Q0[d], A0[d], chunk, optimizer=opt, eta=eta)
+            assert rel(Qg[k], q) <= 1e-4, (c, d)
+            if opt == 0:
+                assert rel(Ag[k], A) <= 1e-4, (c, d)
+
+
+@pytest.mark.parametrize("name", list(MFMA_SHAPES))
+def test_mfma_solve_matches_oracle(name):
+    kw = dict(MFMA_SHAPES[name])
+    inst = make_instance(demand="gamma", noise="mult5", x_dtype="f32", seed=78, **kw)
+    say("mfma solve", name)
+    E = 40
+    perms = make_perms(79, E, inst.C, inst.H)
+    batch_rows = 5 * inst.L
+    bh = chunk_h_blocks(inst.L, inst.H, batch_rows)
+    Wq = dequantized_values(inst, "bf16")
+    x64 = inst.x.astype(np.float64)
+    Qo, _, ho = orc.spgd(inst, x64, perms, E, bh, optimizer=0, eta=5.0, W=Wq)
+    Qg, _, hg = run_solve(inst, "bf16", E, batch_rows, 5.0, 0, perms)
+    lg, _, _ = orc.metrics(inst, x64, Qg, W=Wq)
+    assert np.max(np.abs(lg - ho[:, -1]) / ho[:, -1]) <= 1e-3
+    assert np.max(np.abs(hg - ho) / ho) <= 1e-3
