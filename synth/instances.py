@@ -25,9 +25,9 @@ import numpy as np
 
 BASE_SEED = 190109266
 
-# Synthetic workloads.  Sizes, densities and hyper-parameters follow the five
-# benchmark configurations; constants that the paper leaves open are listed in
-# DESIGN.md ("Input recipe").
+# Synthetic workloads: sizes, densities and SPGD hyper-parameters of the five
+# benchmark configurations.  The Sacramento network and its PeMS / NPMRDS data
+# are not available; these seeded corridors stand in for them.
 CONFIGS = {
     1: dict(P=4, L=6, T=12, K=3, sizes=(7,), inc=0.5, pattern="bernoulli",
             demand="uniform50", noise="add1", x_dtype="f64",
