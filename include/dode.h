@@ -175,6 +175,51 @@ dode_status spgd_solve(const dode_dar* dar, const int32_t* day_cluster, int32_t 
                        uint64_t seed, double* loss_hist, void* stream);
 
 /*
+ * Gradients of the summed loss f = grad_out * sum_d ||rho_c q_d - x_d||^2 over
+ * n_days days of cluster c (eq. "nnls"), for learning rho_c or the route
+ * parameters behind it.  The residual r_d = rho_c q_d - x_d is recomputed,
+ * not stored.
+ *   dQ  dev [n][T][P], state type, or NULL:  dQ_d = 2 grad_out rho_c^T r_d
+ *   dW  dev [K][T][nnz], state type, or NULL:
+ *         dW[l][t][nz(a,p)] = 2 grad_out sum_d r_d[t+l][a] q_d[t][p]
+ *       (entries of blocks with t+l >= H are set to 0)
+ */
+dode_status dode_loss_bwd(const dode_dar* dar, int32_t cluster, const void* Q, const void* X,
+                          int32_t n_days, double grad_out, void* dQ, void* dW, void* stream);
+
+/*
+ * Route-choice parameterisation of rho_c (eqs. "logit", "flow", "assign"):
+ * path k serves OD path_od[k] and crosses the links
+ * pair_link[pair_ptr[k] .. pair_ptr[k+1]); pair m feeds pattern entry
+ * pair_nz[m] (the (link, OD) entry of the incidence pattern).  With
+ * per-pair lag ratios Rr[l][t][m] and logits z,
+ *   pi_k = softmax of z over the paths of OD path_od[k]   (time invariant)
+ *   W[l][t][nz] = sum over pairs m feeding nz of Rr[l][t][m] * pi_{path(m)}
+ * All host arrays are copied; the handle is immutable.  n_pairs = pair_ptr[n_paths].
+ */
+typedef struct dode_routes dode_routes;
+
+dode_status dode_routes_create(const dode_dims* dims, int64_t nnz, int32_t n_paths,
+                               const int32_t* path_od, const int32_t* pair_ptr,
+                               const int32_t* pair_link, const int32_t* pair_nz, void* stream,
+                               dode_routes** out);
+
+dode_status dode_routes_destroy(dode_routes* routes);
+
+/* W = rho(z) as above.  Rr dev [K][T][n_pairs], z dev [n_paths], W dev
+ * [K][T][nnz]; `f64` selects double (else float) for all three.  The result
+ * can be installed with dar_set_values. */
+dode_status dar_from_logits(const dode_routes* routes, int32_t f64, const void* Rr, const void* z,
+                            void* W, void* stream);
+
+/* Chain rule from dW (dev [K][T][nnz]) to the logits (eq. "logit"):
+ *   dpi_k = sum_{l,t, pairs m of k} Rr[l][t][m] dW[l][t][pair_nz[m]]
+ *   dz_k  = pi_k (dpi_k - sum_{k' serving od(k)} pi_k' dpi_k')
+ * dz dev [n_paths]; sums are taken in FP64 in a fixed order. */
+dode_status dar_logits_bwd(const dode_routes* routes, int32_t f64, const void* Rr, const void* z,
+                           const void* dW, void* dz, void* stream);
+
+/*
  * Reusable form of spgd_solve for repeated or timed runs: the plan holds the
  * minibatch schedule of every epoch (permutations, their inverses, the
  * departure intervals each minibatch reaches) and the residual scratch, on

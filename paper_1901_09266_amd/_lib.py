@@ -25,7 +25,9 @@ STORAGE = {"f64": DODE_F64, "f32": DODE_F32, "bf16": DODE_BF16, "fp8": DODE_FP8_
 # Every symbol include/dode.h declares (checked by the CPU test suite).
 EXPORTS = ["dode_last_error", "dode_spgd_defaults", "dar_create", "dar_destroy", "dar_info",
            "dar_set_values", "dode_apply", "dode_loss", "dode_grad", "dode_metrics", "spgd_step",
-           "spgd_solve", "spgd_plan_create", "spgd_plan_destroy", "spgd_run", "spgd_plan_timing"]
+           "spgd_solve", "spgd_plan_create", "spgd_plan_destroy", "spgd_run", "spgd_plan_timing",
+           "dode_loss_bwd", "dode_routes_create", "dode_routes_destroy", "dar_from_logits",
+           "dar_logits_bwd"]
 
 
 class DodeError(RuntimeError):
@@ -78,6 +80,11 @@ def lib():
         L.spgd_plan_destroy.argtypes = [vp]
         L.spgd_run.argtypes = [vp, vp, vp, vp, i32, i32, vp, vp]
         L.spgd_plan_timing.argtypes = [vp, i32, P(dbl), P(i64)]
+        L.dode_loss_bwd.argtypes = [vp, i32, vp, vp, i32, dbl, vp, vp, vp]
+        L.dode_routes_create.argtypes = [P(Dims), i64, i32, P(i32), P(i32), P(i32), P(i32), vp, P(vp)]
+        L.dode_routes_destroy.argtypes = [vp]
+        L.dar_from_logits.argtypes = [vp, i32, vp, vp, vp, vp]
+        L.dar_logits_bwd.argtypes = [vp, i32, vp, vp, vp, vp, vp]
         for name in EXPORTS:
             if name not in ("dode_last_error", "dode_spgd_defaults"):
                 getattr(L, name).restype = ctypes.c_int
@@ -310,3 +317,72 @@ def spgd_plan_timing(plan: Plan, enable: bool):
     n = (ctypes.c_int64 * 3)()
     _check(lib().spgd_plan_timing(plan.handle, int(bool(enable)), ms, n))
     return list(ms), list(n)
+
+
+def dode_loss_bwd(dar: Dar, cluster: int, Q, X, grad_out: float, dQ=None, dW=None, stream=None):
+    P, L, T, H, K = dar.dims
+    n = Q.shape[0]
+    dt = dar.state_dtype
+    nnz = dar_info(dar)["nnz"]
+    _check(lib().dode_loss_bwd(dar.handle, cluster, _ptr(Q, "Q", dt, (n, T, P)),
+                               _ptr(X, "X", dt, (n, H, L)), n, float(grad_out),
+                               _ptr(dQ, "dQ", dt, (n, T, P)), _ptr(dW, "dW", dt, (K, T, nnz)),
+                               _stream(stream)))
+
+
+class Routes:
+    """Owner of a dode_routes handle (path structure of the route-choice model)."""
+
+    def __init__(self, handle, dims, nnz, n_paths, n_pairs):
+        self.handle = handle
+        self.dims = dims
+        self.nnz = nnz
+        self.n_paths = n_paths
+        self.n_pairs = n_pairs
+
+    def close(self):
+        if self.handle:
+            lib().dode_routes_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def dode_routes_create(P, L, T, H, K, nnz, path_od, pair_ptr, pair_link, pair_nz, stream=None) -> Routes:
+    arrs = [np.ascontiguousarray(a, dtype=np.int32) for a in (path_od, pair_ptr, pair_link, pair_nz)]
+    ip = [a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) for a in arrs]
+    out = ctypes.c_void_p()
+    dims = Dims(P, L, T, H, K)
+    _check(lib().dode_routes_create(ctypes.byref(dims), int(nnz), arrs[0].size, *ip, _stream(stream),
+                                    ctypes.byref(out)))
+    return Routes(out, (P, L, T, H, K), int(nnz), arrs[0].size, int(arrs[1][-1]))
+
+
+def _route_dtype(t):
+    import torch
+    if t.dtype not in (torch.float32, torch.float64):
+        raise TypeError("route tensors must be float32 or float64")
+    return 1 if t.dtype == torch.float64 else 0
+
+
+def dar_from_logits(routes: Routes, Rr, z, W, stream=None):
+    P, L, T, H, K = routes.dims
+    f64 = _route_dtype(z)
+    dt = z.dtype
+    _check(lib().dar_from_logits(routes.handle, f64, _ptr(Rr, "Rr", dt, (K, T, routes.n_pairs)),
+                                 _ptr(z, "z", dt, (routes.n_paths,)),
+                                 _ptr(W, "W", dt, (K, T, routes.nnz)), _stream(stream)))
+
+
+def dar_logits_bwd(routes: Routes, Rr, z, dW, dz, stream=None):
+    P, L, T, H, K = routes.dims
+    f64 = _route_dtype(z)
+    dt = z.dtype
+    _check(lib().dar_logits_bwd(routes.handle, f64, _ptr(Rr, "Rr", dt, (K, T, routes.n_pairs)),
+                                _ptr(z, "z", dt, (routes.n_paths,)),
+                                _ptr(dW, "dW", dt, (K, T, routes.nnz)),
+                                _ptr(dz, "dz", dt, (routes.n_paths,)), _stream(stream)))

@@ -123,8 +123,12 @@ dode_status build_sched(const dode_dims& dm, int32_t C, int32_t E, int32_t bh,
       q[p[i]] = i;
     }
   }
-  hs.touched.assign((size_t)E * hs.nch * C * hs.mt, -1);
+  // departure intervals each minibatch reaches, packed to the largest count seen
+  std::vector<int32_t> tl;
+  std::vector<int32_t> cnt((size_t)E * hs.nch * C, 0);
+  tl.assign((size_t)E * hs.nch * C * hs.mt, -1);
   std::vector<char> mark(T);
+  int32_t mt_used = 1;
   for (int32_t e = 0; e < E; ++e)
     for (int32_t c = 0; c < C; ++c) {
       const int32_t* p = hs.perm.data() + ((size_t)e * C + c) * H;
@@ -135,12 +139,17 @@ dode_status build_sched(const dode_dims& dm, int32_t C, int32_t E, int32_t bh,
             const int32_t t = p[s] - l;
             if (t >= 0 && t < T) mark[t] = 1;
           }
-        int32_t* out = hs.touched.data() + (((size_t)e * hs.nch + j) * C + c) * hs.mt;
+        int32_t* out = tl.data() + (((size_t)e * hs.nch + j) * C + c) * hs.mt;
         int32_t n = 0;
         for (int32_t t = 0; t < T; ++t)
           if (mark[t]) out[n++] = t;
+        mt_used = std::max(mt_used, n);
       }
     }
+  hs.touched.assign((size_t)E * hs.nch * C * mt_used, -1);
+  for (size_t r = 0; r < (size_t)E * hs.nch * C; ++r)
+    std::memcpy(hs.touched.data() + r * mt_used, tl.data() + r * hs.mt, mt_used * sizeof(int32_t));
+  hs.mt = mt_used;
   return DODE_OK;
 }
 
@@ -306,7 +315,8 @@ dode_status dar_destroy(dode_dar* dar) {
   for (void* p : {(void*)dar->d_row_ptr, (void*)dar->d_col, (void*)dar->d_col_ptr,
                   (void*)dar->d_row, (void*)dar->d_csc2csr, dar->d_W, dar->d_WT,
                   (void*)dar->d_scale, (void*)dar->d_tile_meta, dar->d_Fv, dar->d_Gv,
-                  (void*)dar->d_Fsc, (void*)dar->d_Gsc})
+                  (void*)dar->d_Fsc, (void*)dar->d_Gsc, (void*)dar->d_row_of_nz,
+                  (void*)dar->d_posf, (void*)dar->d_posg})
     if (p) (void)hipFree(p);
   (void)hipSetDevice(cur);
   delete dar;
@@ -380,6 +390,12 @@ dode_status dar_create(const dode_dims* dims, int32_t n_clusters, const int32_t*
   HIP_TRY(dev_copy(&d->d_col_ptr, d->h_col_ptr));
   HIP_TRY(dev_copy(&d->d_row, d->h_row));
   HIP_TRY(dev_copy(&d->d_csc2csr, d->h_csc2csr));
+  {
+    std::vector<int32_t> rows(nnz);
+    for (int32_t a = 0; a < dm.L; ++a)
+      for (int32_t j = row_ptr[a]; j < row_ptr[a + 1]; ++j) rows[j] = a;
+    HIP_TRY(dev_copy(&d->d_row_of_nz, rows));
+  }
 
   const size_t esz = storage == DODE_F64 ? 8 : storage == DODE_F32 ? 4 : storage == DODE_BF16 ? 2 : 1;
   const size_t vbytes = (size_t)n_clusters * cstride * esz;
@@ -472,7 +488,10 @@ dode_status dar_set_values(dode_dar* dar, int32_t cluster, const void* W_dev, vo
   if (!W_dev) return fail(DODE_ERR_ARG, "W_dev is NULL");
   if (dar->storage == DODE_FP8_E4M3 && dar->dims.P > 64 * 64)
     return fail(DODE_ERR_UNSUPPORTED, "device FP8 requantisation supports P <= 4096");
+  if (dar->has_tiles && (size_t)(dar->tiles.kf_total + dar->tiles.kg_total) * 4 > 64 * 1024)
+    return fail(DODE_ERR_UNSUPPORTED, "tile rewrite needs kf + kg <= 16384 k-steps");
   HIP_TRY(quantize_values(dar, cluster, W_dev, as_stream(stream)));
+  if (dar->has_tiles) HIP_TRY(update_tiles(dar, cluster, W_dev, as_stream(stream)));
   return DODE_OK;
 }
 
@@ -548,6 +567,123 @@ dode_status dode_metrics(const dode_dar* dar, int32_t cluster, const void* Q, co
     HIP_TRY(sum_partials(part.as<double>(), dm.H, n, sst.as<double>(), s));
     HIP_TRY(r2_finish(lbuf.as<double>(), sst.as<double>(), n, r2, s));
   }
+  return DODE_OK;
+}
+
+dode_status dode_loss_bwd(const dode_dar* dar, int32_t cluster, const void* Q, const void* X,
+                          int32_t n_days, double grad_out, void* dQ, void* dW, void* stream) {
+  if (dode_status st = check_dar(dar, cluster)) return st;
+  if (dode_status st = check_days(n_days)) return st;
+  if (!Q || !X) return fail(DODE_ERR_ARG, "Q or X is NULL");
+  if (!std::isfinite(grad_out)) return fail(DODE_ERR_ARG, "grad_out is not finite");
+  const dode_dims& dm = dar->dims;
+  hipStream_t s = as_stream(stream);
+  const bool f64 = is_f64(dar);
+  DevBuf R;
+  HIP_TRY(R.alloc((size_t)std::max(n_days, 1) * dm.H * dm.L * state_size(dar), s));
+  if (n_days > 0) HIP_TRY(plain_apply_rows(dar, nullptr, cluster, Q, X, R.p, nullptr, n_days, s));
+  if (dQ && n_days > 0) {
+    HIP_TRY(plain_adjoint_rows(dar, nullptr, cluster, R.p, dQ, n_days, s));
+    HIP_TRY(scale_state(f64, dQ, (int64_t)n_days * dm.T * dm.P, 2.0 * grad_out, s));
+  }
+  if (dW) HIP_TRY(loss_bwd_dW(dar, R.p, Q, n_days, 2.0 * grad_out, dW, s));
+  return DODE_OK;
+}
+
+dode_status dode_routes_destroy(dode_routes* routes) {
+  if (!routes) return DODE_OK;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(routes->device);
+  if (routes->d_buf) (void)hipFree(routes->d_buf);
+  (void)hipSetDevice(cur);
+  delete routes;
+  return DODE_OK;
+}
+
+dode_status dode_routes_create(const dode_dims* dims, int64_t nnz, int32_t n_paths,
+                               const int32_t* path_od, const int32_t* pair_ptr,
+                               const int32_t* pair_link, const int32_t* pair_nz, void* stream,
+                               dode_routes** out) {
+  if (!out) return fail(DODE_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (dode_status st = check_dims(dims)) return st;
+  if (n_paths < 1 || nnz < 1) return fail(DODE_ERR_ARG, "need n_paths >= 1 and nnz >= 1");
+  if (!path_od || !pair_ptr || !pair_link || !pair_nz) return fail(DODE_ERR_ARG, "NULL route array");
+  const dode_dims dm = *dims;
+  if (pair_ptr[0] != 0) return fail(DODE_ERR_SHAPE, "pair_ptr[0] must be 0");
+  for (int32_t k = 0; k < n_paths; ++k) {
+    if (path_od[k] < 0 || path_od[k] >= dm.P) return fail(DODE_ERR_SHAPE, "path_od[%d] out of range", k);
+    if (pair_ptr[k + 1] < pair_ptr[k]) return fail(DODE_ERR_SHAPE, "pair_ptr decreases at %d", k);
+  }
+  const int32_t n_pairs = pair_ptr[n_paths];
+  std::vector<int32_t> pair_path(n_pairs);
+  for (int32_t k = 0; k < n_paths; ++k)
+    for (int32_t m = pair_ptr[k]; m < pair_ptr[k + 1]; ++m) {
+      if (pair_link[m] < 0 || pair_link[m] >= dm.L) return fail(DODE_ERR_SHAPE, "pair_link[%d]", m);
+      if (pair_nz[m] < 0 || pair_nz[m] >= nnz) return fail(DODE_ERR_SHAPE, "pair_nz[%d]", m);
+      pair_path[m] = k;
+    }
+  std::vector<int32_t> od_ptr(dm.P + 1, 0), od_paths(n_paths), nz_ptr(nnz + 1, 0), nz_pairs(n_pairs);
+  for (int32_t k = 0; k < n_paths; ++k) od_ptr[path_od[k] + 1]++;
+  for (int32_t p = 0; p < dm.P; ++p) od_ptr[p + 1] += od_ptr[p];
+  {
+    std::vector<int32_t> f(od_ptr.begin(), od_ptr.end() - 1);
+    for (int32_t k = 0; k < n_paths; ++k) od_paths[f[path_od[k]]++] = k;
+  }
+  for (int32_t m = 0; m < n_pairs; ++m) nz_ptr[pair_nz[m] + 1]++;
+  for (int64_t j = 0; j < nnz; ++j) nz_ptr[j + 1] += nz_ptr[j];
+  {
+    std::vector<int32_t> f(nz_ptr.begin(), nz_ptr.end() - 1);
+    for (int32_t m = 0; m < n_pairs; ++m) nz_pairs[f[pair_nz[m]]++] = m;
+  }
+  std::vector<int32_t> buf;
+  std::vector<size_t> off;
+  auto put = [&](const int32_t* a, size_t n) {
+    off.push_back(buf.size());
+    buf.insert(buf.end(), a, a + n);
+  };
+  put(path_od, n_paths);
+  put(pair_ptr, n_paths + 1);
+  put(pair_nz, n_pairs);
+  put(pair_path.data(), n_pairs);
+  put(od_ptr.data(), od_ptr.size());
+  put(od_paths.data(), n_paths);
+  put(nz_ptr.data(), nz_ptr.size());
+  put(nz_pairs.data(), n_pairs);
+  std::unique_ptr<dode_routes> r(new dode_routes());
+  HIP_TRY(hipGetDevice(&r->device));
+  HIP_TRY(hipMalloc(&r->d_buf, buf.size() * 4));
+  HIP_TRY(hipMemcpy(r->d_buf, buf.data(), buf.size() * 4, hipMemcpyHostToDevice));
+  DevRoutes& v = r->dv;
+  v = DevRoutes{dm.P, dm.L, dm.T, dm.H, dm.K, n_paths, nnz, n_pairs,
+                r->d_buf + off[0], r->d_buf + off[1], r->d_buf + off[2], r->d_buf + off[3],
+                r->d_buf + off[4], r->d_buf + off[5], r->d_buf + off[6], r->d_buf + off[7]};
+  (void)stream;
+  *out = r.release();
+  return DODE_OK;
+}
+
+dode_status dar_from_logits(const dode_routes* routes, int32_t f64, const void* Rr, const void* z,
+                            void* W, void* stream) {
+  if (!routes) return fail(DODE_ERR_ARG, "routes is NULL");
+  if (!Rr || !z || !W) return fail(DODE_ERR_ARG, "Rr, z or W is NULL");
+  hipStream_t s = as_stream(stream);
+  DevBuf pi;
+  HIP_TRY(pi.alloc((size_t)routes->dv.n_paths * 8, s));
+  HIP_TRY(routes_rho(routes->dv, f64 != 0, Rr, z, W, pi.as<double>(), s));
+  return DODE_OK;
+}
+
+dode_status dar_logits_bwd(const dode_routes* routes, int32_t f64, const void* Rr, const void* z,
+                           const void* dW, void* dz, void* stream) {
+  if (!routes) return fail(DODE_ERR_ARG, "routes is NULL");
+  if (!Rr || !z || !dW || !dz) return fail(DODE_ERR_ARG, "Rr, z, dW or dz is NULL");
+  hipStream_t s = as_stream(stream);
+  DevBuf pi, dpi;
+  HIP_TRY(pi.alloc((size_t)routes->dv.n_paths * 8, s));
+  HIP_TRY(dpi.alloc((size_t)routes->dv.n_paths * 8, s));
+  HIP_TRY(routes_logits_bwd(routes->dv, f64 != 0, Rr, z, dW, dz, pi.as<double>(), dpi.as<double>(), s));
   return DODE_OK;
 }
 

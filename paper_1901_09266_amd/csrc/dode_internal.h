@@ -63,6 +63,7 @@ struct dode_dar {
   int32_t* d_col_ptr = nullptr;
   int32_t* d_row = nullptr;
   int32_t* d_csc2csr = nullptr;   // CSC slot -> CSR slot
+  int32_t* d_row_of_nz = nullptr; // link of CSR slot j
   void* d_W = nullptr;
   void* d_WT = nullptr;
   float* d_scale = nullptr;
@@ -72,6 +73,8 @@ struct dode_dar {
   bool has_tiles = false;
   DevTiles tiles;
   int32_t* d_tile_meta = nullptr;   // f_plo | f_ks | f_koff | g_alo | g_ks | g_koff
+  int32_t* d_posf = nullptr;        // [nnz] element offset of CSR slot j in a forward block
+  int32_t* d_posg = nullptr;        // [nnz] element offset of CSC slot jj in an adjoint block
   void* d_Fv = nullptr;
   void* d_Gv = nullptr;
   float* d_Fsc = nullptr;
@@ -83,6 +86,26 @@ struct dode_dar {
   DevVals vals() const {
     return DevVals{d_W, d_WT, d_scale, (int64_t)dims.K * dims.T * nnz, (dims.P + 63) / 64};
   }
+};
+
+// Device view of a route-choice structure (see dode_routes_create).
+struct DevRoutes {
+  int32_t P, L, T, H, K, n_paths;
+  int64_t nnz, n_pairs;
+  const int32_t* path_od;     // [n_paths]
+  const int32_t* pair_ptr;    // [n_paths+1]
+  const int32_t* pair_nz;     // [n_pairs]
+  const int32_t* pair_path;   // [n_pairs]
+  const int32_t* od_ptr;      // [P+1]   paths grouped by OD
+  const int32_t* od_paths;    // [n_paths]
+  const int32_t* nz_ptr;      // [nnz+1] pairs grouped by pattern entry
+  const int32_t* nz_pairs;    // [n_pairs]
+};
+
+struct dode_routes {
+  DevRoutes dv{};
+  int device = 0;
+  int32_t* d_buf = nullptr;   // all index arrays above, one allocation
 };
 
 // Optimizer settings as the kernels see them.
@@ -175,6 +198,17 @@ hipError_t mfma_chunk_adj_step(const dode_dar* dar, const ChunkSched& cs, const 
                                hipStream_t s);
 // host: build the tile layout of all clusters from FP64 values (tiles.hip)
 dode_status build_tiles(dode_dar* d, const double* const* values, std::string& err);
+
+// ---- differentiation (route_kernels.hip) --------------------------------
+hipError_t routes_rho(const DevRoutes& r, bool f64, const void* Rr, const void* z, void* W,
+                      double* pi, hipStream_t s);
+hipError_t routes_logits_bwd(const DevRoutes& r, bool f64, const void* Rr, const void* z,
+                             const void* dW, void* dz, double* pi, double* dpi, hipStream_t s);
+hipError_t loss_bwd_dW(const dode_dar* dar, const void* R, const void* Q, int32_t n_days,
+                       double scale, void* dW, hipStream_t s);
+hipError_t scale_state(bool f64, void* x, int64_t n, double f, hipStream_t s);
+// rewrite the MFMA tiles of one cluster from state-typed values [K][T][nnz]
+hipError_t update_tiles(const dode_dar* dar, int32_t cluster, const void* W_state, hipStream_t s);
 
 // ---- small generic kernels (plain_kernels.hip) -------------------------
 hipError_t sum_partials(const double* part, int32_t n_per, int32_t n_days, double* out,

@@ -7,175 +7,329 @@
 //
 // Precision: the assignment values are bfloat16; the FP32 operand (demand in
 // the forward product, residual in the adjoint) is split into a bfloat16 head
-// and tail, x = hi + lo, and both halves are multiplied (two MFMAs per k-step),
-// so the products keep ~16 significant bits of the FP32 operand; accumulation
-// is FP32.  The Adagrad step, the projection and the residual are FP32.
+// and tail, x = hi + lo (both rounded to nearest even by v_cvt_pk_bf16_f32),
+// and both halves are multiplied (two MFMAs per k-step), so the products keep
+// ~16 significant bits of the FP32 operand; accumulation is FP32.  The
+// Adagrad step, the projection and the residual are FP32.
 //
 // Layouts (caller-owned, day-major): Q, A [D][T][P]; X [D][H][L]; the residual
 // scratch R [D][bh][L] holds the rows of the current minibatch.
 #include "dode_internal.h"
+#include "numfmt.h"
 
 namespace {
 
-typedef short bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+// four floats at a 4-byte-aligned address (one global_load_dwordx4 on gfx950)
+typedef float f32x4u __attribute__((ext_vector_type(4), aligned(4)));
 
-__device__ __forceinline__ uint32_t bf16_rne_bits(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return u >> 16;
-}
+constexpr int kXcds = 8;   // gfx950: workgroups are dealt to 8 XCDs round-robin
 
-// hi = bf16(v), lo = bf16(v - hi), packed 8 values per operand register set.
-__device__ __forceinline__ void split8(const float (&v)[8], bf16x8& hi, bf16x8& lo) {
-#pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const uint32_t h = bf16_rne_bits(v[e]);
-    const float hf = __uint_as_float(h << 16);
-    hi[e] = static_cast<short>(h);
-    lo[e] = static_cast<short>(bf16_rne_bits(v[e] - hf));
-  }
+// Logical block of physical block b: each XCD gets one contiguous range of
+// logical blocks, so blocks that share operands run under the same L2.
+__device__ __forceinline__ int xcd_logical_block(int nblk) {
+  const int b = blockIdx.x;
+  const int per = (nblk + kXcds - 1) / kXcds;
+  return (b % kXcds) * per + b / kXcds;
 }
 
 // 8 consecutive entries [k0, k0+8) of row `row` of a day-major [D][rows][n] array,
 // zero outside [0, n) or for an absent day (d < 0).
-__device__ __forceinline__ void load8(const float* __restrict__ base, int d, int64_t row_stride_d,
-                                      int row, int n, int k0, float (&v)[8]) {
-  if (d < 0) {
-#pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = 0.f;
-    return;
-  }
-  const float* p = base + (int64_t)d * row_stride_d + (int64_t)row * n;
+__device__ __forceinline__ f32x8 load8(const float* __restrict__ base, int d, int64_t row_stride_d,
+                                       int row, int n, int k0) {
+  f32x8 v = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (d < 0) return v;
+  const float* p = base + (int64_t)d * row_stride_d + (int64_t)row * n + k0;
   if (k0 + 8 <= n) {
-#pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = p[k0 + e];
+    const f32x4u a = *reinterpret_cast<const f32x4u*>(p);
+    const f32x4u b = *reinterpret_cast<const f32x4u*>(p + 4);
+    v = f32x8{a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
   } else {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = (k0 + e < n) ? p[k0 + e] : 0.f;
+    for (int e = 0; e < 8; ++e)
+      if (k0 + e < n) v[e] = p[e];
   }
+  return v;
 }
 
-__device__ __forceinline__ void mma2(const bf16x8& a, const float (&v)[8], f32x4& acc) {
-  bf16x8 hi, lo;
-  split8(v, hi, lo);
+// acc += a * (hi + lo) with hi = bf16(v), lo = bf16(v - hi).
+__device__ __forceinline__ void mma_split(const bf16x8& a, const f32x8& v, f32x4& acc) {
+  const bf16x8 hi = __builtin_convertvector(v, bf16x8);
+  const bf16x8 lo = __builtin_convertvector(v - __builtin_convertvector(hi, f32x8), bf16x8);
   acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, hi, acc, 0, 0, 0);
   acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, lo, acc, 0, 0, 0);
 }
 
+// Four consecutive floats; `full` when all four are inside the row, else the
+// first `valid` only (the rest read as zero / are not written).
+__device__ __forceinline__ f32x4 load4(const float* __restrict__ p, bool full, int valid) {
+  if (full) {
+    const f32x4u v = *reinterpret_cast<const f32x4u*>(p);
+    return f32x4{v[0], v[1], v[2], v[3]};
+  }
+  f32x4 v = {0.f, 0.f, 0.f, 0.f};
+  for (int k = 0; k < valid; ++k) v[k] = p[k];
+  return v;
+}
+
+__device__ __forceinline__ void store4(float* __restrict__ p, const f32x4& v, bool full, int valid) {
+  if (full) {
+    *reinterpret_cast<f32x4u*>(p) = f32x4u{v[0], v[1], v[2], v[3]};
+    return;
+  }
+  for (int k = 0; k < valid; ++k) p[k] = v[k];
+}
+
 // Forward product and residual of the minibatch rows:
 //   R[d][s][a] = sum_l rho_c[l][h-l][a, :] . Q_d[h-l][:] - X_d[h][a],  h = perm[j0+s].
-// grid (ceil(nLT/4), bh, n_groups), 4 waves per block, wave = link tile.
+// One wave per item (day group g, slot s, link tile i), i fastest; 4 items per
+// block; blocks remapped so each XCD walks a contiguous range of day groups.
+// The (lag, k-step) loop is flattened and its operands fetched one step ahead.
 __global__ void __launch_bounds__(256)
 k_fwd_bf16(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, const float* __restrict__ Q,
            const float* __restrict__ X, float* __restrict__ R) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int i = blockIdx.x * 4 + wave;
-  const int s = blockIdx.y, g = blockIdx.z;
-  if (i >= tl.nLT || cs.j0 + s >= pt.H) return;
+  const int n_items = dg.n * cs.bh * tl.nLT;
+  const int item = xcd_logical_block((n_items + 3) / 4) * 4 + wave;
+  if (item >= n_items) return;
+  const int i = item % tl.nLT;
+  const int s = (item / tl.nLT) % cs.bh;
+  const int g = item / (tl.nLT * cs.bh);
+  if (cs.j0 + s >= pt.H) return;
   const int c = dg.cluster[g];
   const int h = cs.perm[c * pt.H + cs.j0 + s];
   const int n = lane & 15, kg = lane >> 4;
   const int first = dg.first[g], cnt = dg.count[g];
   const int d0 = n < cnt ? dg.days[first + n] : -1;
   const int d1 = 16 + n < cnt ? dg.days[first + 16 + n] : -1;
+  // observations of the output rows, fetched before the product
+  const int a0 = 16 * i + 4 * kg;
+  const bool full = a0 + 4 <= pt.L;
+  const int valid = pt.L - a0;
+  f32x4 x0 = {0.f, 0.f, 0.f, 0.f}, x1 = x0;
+  if (a0 < pt.L) {
+    if (d0 >= 0) x0 = load4(X + ((int64_t)d0 * pt.H + h) * pt.L + a0, full, valid);
+    if (d1 >= 0) x1 = load4(X + ((int64_t)d1 * pt.H + h) * pt.L + a0, full, valid);
+  }
+  // lags with t = h - l inside [0, T)
+  const int l_lo = h - pt.T + 1 > 0 ? h - pt.T + 1 : 0;
+  const int l_hi = h < pt.K - 1 ? h : pt.K - 1;
   const int nks = tl.f_ks[i], plo = tl.f_plo[i];
+  const int n_it = l_hi >= l_lo ? (l_hi - l_lo + 1) * nks : 0;
   const int64_t qstride = (int64_t)pt.T * pt.P;
-  f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
   const bf16x8* Fv = static_cast<const bf16x8*>(tl.Fv);
-  for (int l = 0; l < pt.K; ++l) {
-    const int t = h - l;
-    if (t < 0) break;
-    if (t >= pt.T) continue;
-    const bf16x8* Ab = Fv + ((((int64_t)c * pt.K + l) * pt.T + t) * tl.kf_total + tl.f_koff[i]) * 64;
-    for (int ks = 0; ks < nks; ++ks) {
-      const bf16x8 a = Ab[ks * 64 + lane];
+  const int64_t blk = (int64_t)tl.kf_total * 64;
+  const int64_t base_c = ((int64_t)c * pt.K * pt.T) * blk + (int64_t)tl.f_koff[i] * 64 + lane;
+  f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
+  if (n_it > 0) {
+    auto fetch = [&](int it, bf16x8& a, f32x8& v0, f32x8& v1) {
+      const int l = l_lo + it / nks, ks = it % nks;
+      const int t = h - l;
+      a = Fv[base_c + ((int64_t)l * pt.T + t) * blk + ks * 64];
       const int p0 = plo + 32 * ks + 8 * kg;
-      float v0[8], v1[8];
-      load8(Q, d0, qstride, t, pt.P, p0, v0);
-      load8(Q, d1, qstride, t, pt.P, p0, v1);
-      mma2(a, v0, acc0);
-      mma2(a, v1, acc1);
+      v0 = load8(Q, d0, qstride, t, pt.P, p0);
+      v1 = load8(Q, d1, qstride, t, pt.P, p0);
+    };
+    bf16x8 a;
+    f32x8 v0, v1;
+    fetch(0, a, v0, v1);
+    for (int it = 0; it < n_it; ++it) {
+      bf16x8 an = a;
+      f32x8 v0n = v0, v1n = v1;
+      if (it + 1 < n_it) fetch(it + 1, an, v0n, v1n);
+      mma_split(a, v0, acc0);
+      mma_split(a, v1, acc1);
+      a = an;
+      v0 = v0n;
+      v1 = v1n;
     }
   }
-  const int a0 = 16 * i + 4 * kg;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int a = a0 + r;
-    if (a >= pt.L) break;
-    if (d0 >= 0)
-      R[((int64_t)d0 * cs.bh + s) * pt.L + a] = acc0[r] - X[((int64_t)d0 * pt.H + h) * pt.L + a];
-    if (d1 >= 0)
-      R[((int64_t)d1 * cs.bh + s) * pt.L + a] = acc1[r] - X[((int64_t)d1 * pt.H + h) * pt.L + a];
-  }
+  if (a0 >= pt.L) return;
+  if (d0 >= 0) store4(R + ((int64_t)d0 * cs.bh + s) * pt.L + a0, acc0 - x0, full, valid);
+  if (d1 >= 0) store4(R + ((int64_t)d1 * cs.bh + s) * pt.L + a0, acc1 - x1, full, valid);
 }
 
-__device__ __forceinline__ void adagrad_update(float* __restrict__ Q, float* __restrict__ A,
-                                               int64_t idx, float g, const StepArgs& st) {
-  float q = Q[idx];
-  if (st.optimizer == 0) {
-    const float acc = A[idx] + g * g;
-    A[idx] = acc;
-    q -= static_cast<float>(st.eta) * g / (sqrtf(acc) + static_cast<float>(st.eps));
-  } else {
-    q -= static_cast<float>(st.eta) * g;
+__device__ __forceinline__ f32x4 step4(f32x4 q, f32x4& a, const f32x4& g, const StepArgs& st) {
+  const float eta = static_cast<float>(st.eta), eps = static_cast<float>(st.eps);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (st.optimizer == 0) {
+      a[k] += g[k] * g[k];
+      q[k] -= eta * g[k] / (sqrtf(a[k]) + eps);
+    } else {
+      q[k] -= eta * g[k];
+    }
+    q[k] = q[k] > 0.f ? q[k] : 0.f;
   }
-  Q[idx] = q > 0.f ? q : 0.f;
+  return q;
 }
 
 // Adjoint of the minibatch and the fused Adagrad step + projection:
 //   g_d[t][p] = sum_{l: t+l in minibatch} rho_c[l][t][:, p] . R_d[slot(t+l)][:]
-// grid (ceil(nPT/4), max_touched, n_groups), wave = OD tile.
+// One wave per item (day group g, reached interval index ti, OD tile j), j
+// fastest; same block remapping as the forward kernel.  The demand and
+// accumulator rows are fetched before the product.
 __global__ void __launch_bounds__(256)
 k_adj_bf16(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, const float* __restrict__ R,
            float* __restrict__ Q, float* __restrict__ A, StepArgs st) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int j = blockIdx.x * 4 + wave;
-  const int g = blockIdx.z;
-  if (j >= tl.nPT) return;
+  const int n_items = dg.n * cs.max_touched * tl.nPT;
+  const int item = xcd_logical_block((n_items + 3) / 4) * 4 + wave;
+  if (item >= n_items) return;
+  const int j = item % tl.nPT;
+  const int ti = (item / tl.nPT) % cs.max_touched;
+  const int g = item / (tl.nPT * cs.max_touched);
   const int c = dg.cluster[g];
-  const int t = cs.touched[c * cs.max_touched + blockIdx.y];
+  const int t = cs.touched[c * cs.max_touched + ti];
   if (t < 0) return;
   const int n = lane & 15, kg = lane >> 4;
   const int first = dg.first[g], cnt = dg.count[g];
   const int d0 = n < cnt ? dg.days[first + n] : -1;
   const int d1 = 16 + n < cnt ? dg.days[first + 16 + n] : -1;
-  const int nks = tl.g_ks[j], alo = tl.g_alo[j];
-  const int64_t rstride = (int64_t)cs.bh * pt.L;
-  f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
-  const bf16x8* Gv = static_cast<const bf16x8*>(tl.Gv);
-  const int32_t* pos = cs.pos + (int64_t)c * pt.H;
-  for (int l = 0; l < pt.K; ++l) {
-    const int h = t + l;
-    if (h >= pt.H) break;
-    const int s = pos[h] - cs.j0;
-    if (s < 0 || s >= cs.bh) continue;
-    const bf16x8* Ab = Gv + ((((int64_t)c * pt.K + l) * pt.T + t) * tl.kg_total + tl.g_koff[j]) * 64;
-    for (int ks = 0; ks < nks; ++ks) {
-      const bf16x8 a = Ab[ks * 64 + lane];
-      const int k0 = alo + 32 * ks + 8 * kg;
-      float v0[8], v1[8];
-      load8(R, d0, rstride, s, pt.L, k0, v0);
-      load8(R, d1, rstride, s, pt.L, k0, v1);
-      mma2(a, v0, acc0);
-      mma2(a, v1, acc1);
+  const int p0 = 16 * j + 4 * kg;
+  const bool full = p0 + 4 <= pt.P;
+  const int valid = pt.P - p0;
+  const bool adagrad = st.optimizer == 0;
+  f32x4 q0 = {0.f, 0.f, 0.f, 0.f}, q1 = q0, a0 = q0, a1 = q0;
+  const int64_t i0 = ((int64_t)d0 * pt.T + t) * pt.P + p0;
+  const int64_t i1 = ((int64_t)d1 * pt.T + t) * pt.P + p0;
+  if (p0 < pt.P) {
+    if (d0 >= 0) {
+      q0 = load4(Q + i0, full, valid);
+      if (adagrad) a0 = load4(A + i0, full, valid);
+    }
+    if (d1 >= 0) {
+      q1 = load4(Q + i1, full, valid);
+      if (adagrad) a1 = load4(A + i1, full, valid);
     }
   }
-  const int p0 = 16 * j + 4 * kg;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int p = p0 + r;
-    if (p >= pt.P) break;
-    if (d0 >= 0) adagrad_update(Q, A, ((int64_t)d0 * pt.T + t) * pt.P + p, acc0[r], st);
-    if (d1 >= 0) adagrad_update(Q, A, ((int64_t)d1 * pt.T + t) * pt.P + p, acc1[r], st);
+  // lags whose row block h = t + l is in this minibatch, as a bit mask
+  const int32_t* pos = cs.pos + (int64_t)c * pt.H;
+  uint64_t lmask = 0;
+  for (int l = 0; l < pt.K && t + l < pt.H; ++l) {
+    const int sl = pos[t + l] - cs.j0;
+    if (sl >= 0 && sl < cs.bh) lmask |= 1ull << l;
+  }
+  const int nks = tl.g_ks[j], alo = tl.g_alo[j];
+  const int n_it = __popcll(lmask) * nks;
+  const int64_t rstride = (int64_t)cs.bh * pt.L;
+  const bf16x8* Gv = static_cast<const bf16x8*>(tl.Gv);
+  const int64_t blk = (int64_t)tl.kg_total * 64;
+  const int64_t base_c = ((int64_t)c * pt.K * pt.T) * blk + (int64_t)tl.g_koff[j] * 64 + lane;
+  f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
+  if (n_it > 0) {
+    // iteration it -> (it / nks)-th set bit of lmask, k-step it % nks
+    uint64_t m = lmask;
+    int l = __builtin_ctzll(m);
+    int ks = 0;
+    auto fetch = [&](int lv, int kv, bf16x8& a, f32x8& v0, f32x8& v1) {
+      a = Gv[base_c + ((int64_t)lv * pt.T + t) * blk + kv * 64];
+      const int sl = pos[t + lv] - cs.j0;
+      const int k0 = alo + 32 * kv + 8 * kg;
+      v0 = load8(R, d0, rstride, sl, pt.L, k0);
+      v1 = load8(R, d1, rstride, sl, pt.L, k0);
+    };
+    bf16x8 a;
+    f32x8 v0, v1;
+    fetch(l, ks, a, v0, v1);
+    for (int it = 0; it < n_it; ++it) {
+      int ln = l, ksn = ks + 1;
+      if (ksn == nks) {
+        ksn = 0;
+        m &= m - 1;
+        ln = m ? __builtin_ctzll(m) : l;
+      }
+      bf16x8 an = a;
+      f32x8 v0n = v0, v1n = v1;
+      if (it + 1 < n_it) fetch(ln, ksn, an, v0n, v1n);
+      mma_split(a, v0, acc0);
+      mma_split(a, v1, acc1);
+      a = an;
+      v0 = v0n;
+      v1 = v1n;
+      l = ln;
+      ks = ksn;
+    }
+  }
+  if (p0 >= pt.P) return;
+  if (d0 >= 0) {
+    q0 = step4(q0, a0, acc0, st);
+    store4(Q + i0, q0, full, valid);
+    if (adagrad) store4(A + i0, a0, full, valid);
+  }
+  if (d1 >= 0) {
+    q1 = step4(q1, a1, acc1, st);
+    store4(Q + i1, q1, full, valid);
+    if (adagrad) store4(A + i1, a1, full, valid);
+  }
+}
+
+// Rewrite the packed tiles of one (cluster, l, t) block from FP32 values W[nnz]
+// (CSR order).  BF16: round each entry.  FP8: one scale per 16x32 k-step tile,
+// max |value| / 448, then round value / scale.  Padding entries stay zero.
+__global__ void __launch_bounds__(256)
+k_update_tiles(DevPat pt, DevTiles tl, int32_t storage, int32_t c, const float* __restrict__ W,
+               const int32_t* __restrict__ posf, const int32_t* __restrict__ posg,
+               const int32_t* __restrict__ csc2csr, void* Fv, void* Gv, float* Fsc, float* Gsc) {
+  extern __shared__ float smax[];   // [kf_total + kg_total] when FP8
+  const int64_t lt = blockIdx.x;
+  const int l = (int)(lt / pt.T), t = (int)(lt % pt.T);
+  if (t + l >= pt.H) return;   // block never read
+  const float* w = W + lt * pt.nnz;
+  const int64_t fb = ((int64_t)c * pt.K * pt.T + lt) * tl.kf_total * 512;
+  const int64_t gb = ((int64_t)c * pt.K * pt.T + lt) * tl.kg_total * 512;
+  if (storage == DODE_BF16) {
+    uint16_t* F = static_cast<uint16_t*>(Fv);
+    uint16_t* G = static_cast<uint16_t*>(Gv);
+    for (int64_t j = threadIdx.x; j < pt.nnz; j += blockDim.x) F[fb + posf[j]] = f32_to_bf16_rne(w[j]);
+    for (int64_t jj = threadIdx.x; jj < pt.nnz; jj += blockDim.x)
+      G[gb + posg[jj]] = f32_to_bf16_rne(w[csc2csr[jj]]);
+    return;
+  }
+  float* sf = smax;
+  float* sg = smax + tl.kf_total;
+  for (int k = threadIdx.x; k < tl.kf_total + tl.kg_total; k += blockDim.x) smax[k] = 0.f;
+  __syncthreads();
+  for (int64_t j = threadIdx.x; j < pt.nnz; j += blockDim.x)
+    atomicMax(reinterpret_cast<unsigned int*>(&sf[posf[j] / 512]), __float_as_uint(fabsf(w[j])));
+  for (int64_t jj = threadIdx.x; jj < pt.nnz; jj += blockDim.x)
+    atomicMax(reinterpret_cast<unsigned int*>(&sg[posg[jj] / 512]),
+              __float_as_uint(fabsf(w[csc2csr[jj]])));
+  __syncthreads();
+  for (int k = threadIdx.x; k < tl.kf_total; k += blockDim.x)
+    Fsc[((int64_t)c * pt.K * pt.T + lt) * tl.kf_total + k] = sf[k] > 0.f ? sf[k] / 448.f : 1.f;
+  for (int k = threadIdx.x; k < tl.kg_total; k += blockDim.x)
+    Gsc[((int64_t)c * pt.K * pt.T + lt) * tl.kg_total + k] = sg[k] > 0.f ? sg[k] / 448.f : 1.f;
+  uint8_t* F = static_cast<uint8_t*>(Fv);
+  uint8_t* G = static_cast<uint8_t*>(Gv);
+  for (int64_t j = threadIdx.x; j < pt.nnz; j += blockDim.x) {
+    const float m = sf[posf[j] / 512];
+    F[fb + posf[j]] = f32_to_e4m3_rne(w[j] / (m > 0.f ? m / 448.f : 1.f));
+  }
+  for (int64_t jj = threadIdx.x; jj < pt.nnz; jj += blockDim.x) {
+    const float m = sg[posg[jj] / 512];
+    G[gb + posg[jj]] = f32_to_e4m3_rne(w[csc2csr[jj]] / (m > 0.f ? m / 448.f : 1.f));
   }
 }
 
 }  // namespace
 
+hipError_t update_tiles(const dode_dar* dar, int32_t cluster, const void* W_state, hipStream_t s) {
+  const DevTiles& tl = dar->tiles;
+  const size_t shm = dar->storage == DODE_FP8_E4M3 ? (size_t)(tl.kf_total + tl.kg_total) * 4 : 0;
+  hipLaunchKernelGGL(k_update_tiles, dim3(dar->dims.K * dar->dims.T), dim3(256), shm, s, dar->pat(),
+                     tl, (int32_t)dar->storage, cluster, static_cast<const float*>(W_state),
+                     dar->d_posf, dar->d_posg, dar->d_csc2csr, dar->d_Fv, dar->d_Gv, dar->d_Fsc,
+                     dar->d_Gsc);
+  return hipGetLastError();
+}
+
 hipError_t mfma_chunk_resid(const dode_dar* dar, const ChunkSched& cs, const DayGroups& dg,
                             const float* Q, const float* X, float* R, hipStream_t s) {
-  const dim3 grid((dar->tiles.nLT + 3) / 4, cs.bh, dg.n);
+  const int64_t nblk = ((int64_t)dg.n * cs.bh * dar->tiles.nLT + 3) / 4;
+  const dim3 grid((unsigned)(((nblk + kXcds - 1) / kXcds) * kXcds));
   hipLaunchKernelGGL(k_fwd_bf16, grid, dim3(256), 0, s, dar->pat(), dar->tiles, cs, dg, Q, X, R);
   return hipGetLastError();
 }
@@ -183,7 +337,8 @@ hipError_t mfma_chunk_resid(const dode_dar* dar, const ChunkSched& cs, const Day
 hipError_t mfma_chunk_adj_step(const dode_dar* dar, const ChunkSched& cs, const DayGroups& dg,
                                const float* R, float* Q, float* A, const StepArgs& st,
                                hipStream_t s) {
-  const dim3 grid((dar->tiles.nPT + 3) / 4, cs.max_touched, dg.n);
+  const int64_t nblk = ((int64_t)dg.n * cs.max_touched * dar->tiles.nPT + 3) / 4;
+  const dim3 grid((unsigned)(((nblk + kXcds - 1) / kXcds) * kXcds));
   hipLaunchKernelGGL(k_adj_bf16, grid, dim3(256), 0, s, dar->pat(), dar->tiles, cs, dg, R, Q, A,
                      st);
   return hipGetLastError();

@@ -7,6 +7,7 @@
 //   chunk_adj_step: g = rho_o^T r, then Adagrad / fixed step and max(q, 0),
 //                   fused, for every departure interval the minibatch reaches.
 #include "dode_internal.h"
+#include "numfmt.h"
 
 #include <cmath>
 
@@ -268,33 +269,6 @@ __global__ void k_clamp(S* __restrict__ Q, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     Q[i] = Q[i] > S(0) ? Q[i] : S(0);
-}
-
-// ------------------------------------------------- device quantisation --
-__device__ uint16_t f32_to_bf16_rne(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return static_cast<uint16_t>((u >> 16) | 0x40u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return static_cast<uint16_t>(u >> 16);
-}
-
-// Round |v| <= 448 (already scaled) to the nearest E4M3FN code, ties to even.
-__device__ uint8_t f32_to_e4m3_rne(float v) {
-  const uint8_t sgn = v < 0.f ? 0x80 : 0;
-  float a = fabsf(v);
-  if (!(a < 448.f)) return sgn | 0x7E;
-  if (a < 0x1p-6f) {
-    const int m = static_cast<int>(rintf(a * 512.f));   // multiples of 2^-9
-    return sgn | static_cast<uint8_t>(m);                // m == 8 is the code of 2^-6
-  }
-  int e = 0;
-  const float f = frexpf(a, &e);   // a = f * 2^e, f in [0.5, 1)
-  int E = e - 1;                   // a = (2f) * 2^E, 2f in [1, 2)
-  int m = static_cast<int>(rintf((2.f * f - 1.f) * 8.f));
-  if (m == 8) { m = 0; ++E; }
-  int code = ((E + 7) << 3) | m;
-  if (code > 0x7E) code = 0x7E;
-  return sgn | static_cast<uint8_t>(code);
 }
 
 template <typename S>

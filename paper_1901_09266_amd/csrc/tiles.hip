@@ -36,8 +36,13 @@ std::vector<Hull> hulls(int32_t n_rows, int32_t n_cols, const std::vector<int32_
         hi = std::max(hi, idx[ptr[r + 1] - 1] + 1);
       }
     if (hi <= lo) continue;
+    lo = lo / 8 * 8;   // starts on a multiple of 8 columns (32-byte FP32 operand loads)
     const int32_t len = round_up(hi - lo, 32);
-    if (len <= n_cols) lo = std::min(lo, n_cols - len);   // keep the range inside [0, n_cols)
+    if (lo + len > n_cols && len <= n_cols) {
+      // move the range left to stay inside [0, n_cols) when it still covers [lo, hi)
+      const int32_t lo2 = (n_cols - len) / 8 * 8;
+      if (lo2 + len >= hi) lo = lo2;
+    }
     out[i].lo = lo;
     out[i].ks = len / 32;
   }
@@ -75,14 +80,37 @@ dode_status build_tiles(dode_dar* d, const double* const* values, std::string& e
   const int32_t kf = fko[nLT], kg = gko[nPT];
 
   // packed position of every pattern entry, forward (CSR slot j) and adjoint (CSC slot jj)
+  auto inside = [](int32_t col, const Hull& h) { return col >= h.lo && col < h.lo + 32 * h.ks; };
   std::vector<int64_t> posf(nnz), posg(nnz);
   for (int32_t a = 0; a < dm.L; ++a)
-    for (int32_t j = d->h_row_ptr[a]; j < d->h_row_ptr[a + 1]; ++j)
+    for (int32_t j = d->h_row_ptr[a]; j < d->h_row_ptr[a + 1]; ++j) {
+      if (!inside(d->h_col[j], fh[a / 16])) {
+        err = "internal: forward tile range misses a pattern entry";
+        return DODE_ERR_SHAPE;
+      }
       posf[j] = packed_pos(a, d->h_col[j], fh, fko);
+    }
   for (int32_t p = 0; p < dm.P; ++p)
-    for (int32_t jj = d->h_col_ptr[p]; jj < d->h_col_ptr[p + 1]; ++jj)
+    for (int32_t jj = d->h_col_ptr[p]; jj < d->h_col_ptr[p + 1]; ++jj) {
+      if (!inside(d->h_row[jj], gh[p / 16])) {
+        err = "internal: adjoint tile range misses a pattern entry";
+        return DODE_ERR_SHAPE;
+      }
       posg[jj] = packed_pos(p, d->h_row[jj], gh, gko);
+    }
 
+  {
+    std::vector<int32_t> pf(posf.begin(), posf.end()), pg(posg.begin(), posg.end());
+    auto up = [&](int32_t** dst, const std::vector<int32_t>& v) -> bool {
+      if (hipMalloc(dst, std::max<size_t>(16, v.size() * 4)) != hipSuccess) return false;
+      return hipMemcpy(*dst, v.data(), v.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
+    };
+    if (!up(&d->d_posf, pf) || !up(&d->d_posg, pg)) {
+      err = "position tables";
+      return DODE_ERR_OOM;
+    }
+    d->device_bytes += 8 * nnz;
+  }
   const bool fp8 = d->storage == DODE_FP8_E4M3;
   const size_t esz = fp8 ? 1 : 2;
   const int64_t blocks = (int64_t)dm.K * dm.T;

@@ -1,0 +1,109 @@
+"""Differentiation through the C ABI (route-choice logits, config-4 shapes):
+route-choice assignment, the loss adjoints with respect to Q and the ratios,
+the logits chain rule, torch.autograd gradcheck and central finite
+differences, against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle as orc
+import paper_1901_09266_amd as dode
+from paper_1901_09266_amd.autograd import DodeLoss
+from synth import make_route_instance
+from gpu_helpers import say, dev, rel, quantize_bf16
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def setup(storage, dt):
+    ri = make_route_instance()
+    dar = dode.dar_create(ri.P, ri.L, ri.T, ri.H, ri.K, ri.row_ptr, ri.col_idx,
+                          [np.zeros((ri.K, ri.T, ri.nnz))], storage=storage, stream=0)
+    routes = dode.dode_routes_create(ri.P, ri.L, ri.T, ri.H, ri.K, ri.nnz, ri.path_od, ri.pair_ptr,
+                                     ri.pair_link, ri.pair_nz, stream=0)
+    Rr = dev(ri.R[0], dt)
+    return ri, dar, routes, Rr
+
+
+def test_route_assignment_and_adjoints_match_oracle():
+    ri, dar, routes, Rr = setup("f64", torch.float64)
+    say("routes f64")
+    z = dev(ri.z0[0], torch.float64)
+    W = torch.empty((ri.K, ri.T, ri.nnz), dtype=torch.float64, device="cuda")
+    dode.dar_from_logits(routes, Rr, z, W)
+    torch.cuda.synchronize()
+    Wo = orc.rho_from_logits(ri, 0, ri.z0[0])
+    assert rel(W.cpu().numpy(), Wo) <= 1e-14
+    dode.dar_set_values(dar, 0, W)
+    Q = ri.qstar * 0.8
+    Qd, Xd = dev(Q, torch.float64), dev(ri.x, torch.float64)
+    dQ = torch.empty_like(Qd)
+    dW = torch.empty_like(W)
+    dode.dode_loss_bwd(dar, 0, Qd, Xd, 0.75, dQ=dQ, dW=dW)
+    dz = torch.empty_like(z)
+    dode.dar_logits_bwd(routes, Rr, z, dW, dz)
+    torch.cuda.synchronize()
+    dWo, dQo = orc.loss_backward(ri, Wo, ri.x, Q)
+    assert rel(dQ.cpu().numpy(), 0.75 * dQo) <= 1e-12
+    assert rel(dW.cpu().numpy(), 0.75 * dWo) <= 1e-12
+    dzo = orc.logits_backward(ri, 0, ri.z0[0], 0.75 * dWo)
+    assert rel(dz.cpu().numpy(), dzo) <= 1e-11
+
+
+def test_gradcheck_fp64():
+    """torch.autograd.gradcheck (FP64 central differences) on Q and z."""
+    ri, dar, routes, Rr = setup("f64", torch.float64)
+    say("gradcheck f64")
+    X = dev(ri.x, torch.float64)
+    Q = dev(ri.qstar * 0.8, torch.float64).requires_grad_(True)
+    z = dev(ri.z0[0], torch.float64).requires_grad_(True)
+    f = lambda q, zz: DodeLoss.apply(q, zz, dar, 0, routes, Rr, X) * 1e-4
+    assert torch.autograd.gradcheck(f, (Q, z), eps=1e-6, atol=1e-5, rtol=1e-6)
+
+
+def test_finite_differences_on_logits_fp64():
+    """dL/dz from the adjoint chain against central differences of the GPU loss."""
+    ri, dar, routes, Rr = setup("f64", torch.float64)
+    say("fd logits f64")
+    X = dev(ri.x, torch.float64)
+    Q = dev(ri.qstar * 0.8, torch.float64)
+    z = dev(ri.z0[0], torch.float64).requires_grad_(True)
+    loss = DodeLoss.apply(Q, z, dar, 0, routes, Rr, X)
+    (gz,) = torch.autograd.grad(loss, z)
+    h = 1e-5
+    rng = np.random.default_rng(3)
+    for k in rng.choice(ri.n_paths, 10, replace=False):
+        zp, zm = z.detach().clone(), z.detach().clone()
+        zp[k] += h
+        zm[k] -= h
+        fd = (DodeLoss.apply(Q, zp, dar, 0, routes, Rr, X) - DodeLoss.apply(Q, zm, dar, 0, routes, Rr, X)) / (2 * h)
+        assert abs(float(fd) - float(gz[k])) <= 1e-6 * (1 + abs(float(fd)))
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_reduced_precision_gradients(storage):
+    """FP32 and BF16 runs: loss and gradients against the FP64 oracle.
+    FP32 to 1e-5; BF16 against the oracle on bf16-rounded ratios to 1e-4 and
+    against exact ratios within the rounding of the ratios (3e-3)."""
+    ri, dar, routes, Rr = setup(storage, torch.float32)
+    say("autograd", storage)
+    X = dev(ri.x, torch.float32)
+    Q = dev(ri.qstar * 0.8, torch.float32).requires_grad_(True)
+    z = dev(ri.z0[0], torch.float32).requires_grad_(True)
+    loss = DodeLoss.apply(Q, z, dar, 0, routes, Rr, X)
+    gQ, gz = torch.autograd.grad(loss, (Q, z))
+    q64 = Q.detach().double().cpu().numpy()
+    x64 = X.double().cpu().numpy()
+    Wo = orc.rho_from_logits(ri, 0, z.detach().double().cpu().numpy())
+    Wref = Wo if storage == "f32" else quantize_bf16(Wo.astype(np.float32).astype(np.float64))
+    lo = sum(orc.loss(ri, Wref, q64[d], x64[d]) for d in range(ri.D))
+    dWo, dQo = orc.loss_backward(ri, Wref, x64, q64)
+    dzo = orc.logits_backward(ri, 0, z.detach().double().cpu().numpy(), dWo)
+    tol = 1e-5 if storage == "f32" else 1e-4
+    assert abs(float(loss) - lo) / lo <= tol
+    assert rel(gQ.cpu().numpy(), dQo) <= tol
+    # dz is computed from the FP32 dW through the FP32 chain rule
+    assert rel(gz.cpu().numpy(), dzo) <= (1e-4 if storage == "f32" else 3e-3)
+    if storage == "bf16":
+        lexact = sum(orc.loss(ri, Wo, q64[d], x64[d]) for d in range(ri.D))
+        assert abs(float(loss) - lexact) / lexact <= 3e-3
