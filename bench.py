@@ -86,16 +86,17 @@ def run_form(dode, torch, inst, form, perms, E_total, warmup, steps, bh):
     A = torch.zeros_like(Q)
     params = dode.make_params(epochs=E_total, batch_rows=8192, eta=5.0, optimizer=0)
     plan = dode.spgd_plan_create(dar, inst.day_cluster, params, perm=perms, stream=0)
+    dode.spgd_plan_load(plan, X, Q, A, stream=0)
     torch.cuda.synchronize()
     log(f"{form}: dar + plan ready in {time.time() - t0:.1f}s")
     stream = torch.cuda.current_stream()
-    dode.spgd_run(plan, X, Q, A, 0, warmup, stream=stream)
+    dode.spgd_run(plan, 0, warmup, stream=stream)
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     w0 = time.perf_counter()
     ev0.record(stream)
-    dode.spgd_run(plan, X, Q, A, warmup, steps, stream=stream)
+    dode.spgd_run(plan, warmup, steps, stream=stream)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
@@ -104,7 +105,7 @@ def run_form(dode, torch, inst, form, perms, E_total, warmup, steps, bh):
     # per-kernel durations: events around every launch, same epochs again
     dode.spgd_plan_timing(plan, True)
     e2 = warmup + steps
-    dode.spgd_run(plan, X, Q, A, e2, steps, stream=stream)
+    dode.spgd_run(plan, e2, steps, stream=stream)
     kms, kn = dode.spgd_plan_timing(plan, False)
     torch.cuda.synchronize()
     return dict(dar=dar, plan=plan, X=X, Q=Q, A=A, ms=ms, wall=wall, kernel_ms=kms, kernel_n=kn,
@@ -122,10 +123,13 @@ def solve_full(dode, torch, inst, form, perms_full, E, E_snap, sample):
     A = torch.zeros_like(Q)
     p = dode.make_params(epochs=E, batch_rows=8192, eta=5.0, optimizer=0)
     plan = dode.spgd_plan_create(dar, inst.day_cluster, p, perm=perms_full, stream=0)
+    dode.spgd_plan_load(plan, X, Q, A)
     t0 = time.time()
-    dode.spgd_run(plan, X, Q, A, 0, E_snap)
+    dode.spgd_run(plan, 0, E_snap)
+    dode.spgd_plan_store(plan, Q)
     snap = Q[torch.as_tensor(sample, device="cuda")].double().cpu().numpy()
-    dode.spgd_run(plan, X, Q, A, E_snap, E - E_snap)
+    dode.spgd_run(plan, E_snap, E - E_snap)
+    dode.spgd_plan_store(plan, Q)
     torch.cuda.synchronize()
     log(f"{form}: full {E}-epoch solve in {time.time() - t0:.2f}s")
     plan.close()
@@ -188,6 +192,8 @@ def main():
     ap.add_argument("--epochs", type=int, default=300, help="epochs of the equal-loss solves")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-check", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one 512 MiB device copy first (reference for traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the days are independent, "
@@ -199,6 +205,13 @@ def main():
     import paper_1901_09266_amd as dode
     from synth import make_config, make_perms, chunk_h_blocks
 
+    if args.calibrate_copy:
+        a = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     t0 = time.time()
     inst = make_config(args.config)
     log(f"config {args.config}: D={inst.D} C={inst.C} nnz={inst.nnz} generated in {time.time() - t0:.1f}s")

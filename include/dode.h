@@ -81,14 +81,16 @@ typedef struct {
   int32_t check_finite;/* nonzero: scan X for NaN/Inf before solving */
   int32_t kernel_path; /* 0 = fastest available for the storage type (matrix-core
                           tiles for BF16 / FP8), 1 = sparse pattern kernels */
+  int32_t use_graph;   /* nonzero: spgd_run replays one captured hipGraph per epoch
+                          (the epoch index lives in a device counter) */
 } dode_spgd_params;
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* dode_last_error(void);
 
 /* Fill p with the defaults: epochs 300, batch_rows 8192, eta 5, eps 1e-10,
- * Adagrad, check_finite 1, kernel_path 0 (section "Goodness of fit" gives E,
- * b and eta). */
+ * Adagrad, check_finite 1, kernel_path 0, use_graph 1 (section "Goodness of
+ * fit" gives E, b and eta). */
 void dode_spgd_defaults(dode_spgd_params* p);
 
 /*
@@ -220,12 +222,17 @@ dode_status dar_logits_bwd(const dode_routes* routes, int32_t f64, const void* R
                            const void* dW, void* dz, void* stream);
 
 /*
- * Reusable form of spgd_solve for repeated or timed runs: the plan holds the
- * minibatch schedule of every epoch (permutations, their inverses, the
- * departure intervals each minibatch reaches) and the residual scratch, on
- * the device of `dar`.  Arguments as for spgd_solve; `params->epochs` is the
- * number of epochs the schedule covers.  The plan keeps a pointer to `dar`,
- * which must outlive it.  Synchronises `stream`.
+ * Reusable form of spgd_solve for repeated or timed runs.  A plan holds
+ *  - the minibatch schedule of every epoch (permutations, their inverses and
+ *    the departure intervals each minibatch reaches),
+ *  - its own copy of the solver state of the D days -- X, Q and A -- in an
+ *    interval-major layout ([rows][days][cols], days grouped by cluster) so
+ *    that the rows one minibatch touches are contiguous across days,
+ *  - the residual scratch of one minibatch,
+ * all on the device of `dar`.  Arguments as for spgd_solve; `params->epochs`
+ * is the number of epochs the schedule covers.  The plan keeps a pointer to
+ * `dar`, which must outlive it.  The state starts at X = 0, Q = 0, A = 0;
+ * fill it with spgd_plan_load.  Synchronises `stream`.
  */
 typedef struct dode_plan dode_plan;
 
@@ -235,16 +242,25 @@ dode_status spgd_plan_create(const dode_dar* dar, const int32_t* day_cluster, in
 
 dode_status spgd_plan_destroy(dode_plan* plan);
 
+/* Copy the caller's X (dev [D][H][L]), Q and A (dev [D][T][P], state type; A
+ * may be NULL for zeros) into the plan, projecting Q onto Q >= 0 (day d is
+ * day d of the plan's day_cluster).  With params->check_finite, X is scanned
+ * for NaN/Inf first (DODE_ERR_NONFINITE; synchronises `stream`). */
+dode_status spgd_plan_load(dode_plan* plan, const void* X, const void* Q, const void* A,
+                           void* stream);
+
+/* Copy the plan's Q (and A unless NULL) back to the caller (dev [D][T][P]). */
+dode_status spgd_plan_store(const dode_plan* plan, void* Q, void* A, void* stream);
+
 /*
  * Epochs epoch_begin .. epoch_begin+n_epochs-1 of the plan's schedule on the
- * caller's X (dev [D][H][L]), Q and A (dev [D][T][P], in/out, state type).
- * Q must already be >= 0 (spgd_solve projects it first).  loss_dev (dev
- * double [n_epochs][D]) receives the full loss of each day after each epoch,
- * or pass NULL to skip that extra forward pass.  Asynchronous on `stream`;
- * calls on one plan must not overlap (they share its scratch).
+ * plan's state.  loss_dev (dev double [n_epochs][D], caller's day order)
+ * receives the full loss of each day after each epoch, or pass NULL to skip
+ * that extra forward pass.  Asynchronous on `stream`; calls on one plan must
+ * not overlap (they share its state and scratch).
  */
-dode_status spgd_run(dode_plan* plan, const void* X, void* Q, void* A, int32_t epoch_begin,
-                     int32_t n_epochs, double* loss_dev, void* stream);
+dode_status spgd_run(dode_plan* plan, int32_t epoch_begin, int32_t n_epochs, double* loss_dev,
+                     void* stream);
 
 /*
  * Kernel timing of a plan.  enable != 0 makes later spgd_run calls record a

@@ -25,7 +25,8 @@ STORAGE = {"f64": DODE_F64, "f32": DODE_F32, "bf16": DODE_BF16, "fp8": DODE_FP8_
 # Every symbol include/dode.h declares (checked by the CPU test suite).
 EXPORTS = ["dode_last_error", "dode_spgd_defaults", "dar_create", "dar_destroy", "dar_info",
            "dar_set_values", "dode_apply", "dode_loss", "dode_grad", "dode_metrics", "spgd_step",
-           "spgd_solve", "spgd_plan_create", "spgd_plan_destroy", "spgd_run", "spgd_plan_timing",
+           "spgd_solve", "spgd_plan_create", "spgd_plan_destroy", "spgd_plan_load",
+           "spgd_plan_store", "spgd_run", "spgd_plan_timing",
            "dode_loss_bwd", "dode_routes_create", "dode_routes_destroy", "dar_from_logits",
            "dar_logits_bwd"]
 
@@ -45,7 +46,8 @@ class Dims(ctypes.Structure):
 class SpgdParams(ctypes.Structure):
     _fields_ = [("epochs", ctypes.c_int32), ("batch_rows", ctypes.c_int32), ("eta", ctypes.c_double),
                 ("eps", ctypes.c_double), ("optimizer", ctypes.c_int32),
-                ("check_finite", ctypes.c_int32), ("kernel_path", ctypes.c_int32)]
+                ("check_finite", ctypes.c_int32), ("kernel_path", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32)]
 
 
 _lib = None
@@ -78,7 +80,9 @@ def lib():
         L.spgd_plan_create.argtypes = [vp, P(i32), i32, P(SpgdParams), P(i32), ctypes.c_uint64, vp,
                                        P(vp)]
         L.spgd_plan_destroy.argtypes = [vp]
-        L.spgd_run.argtypes = [vp, vp, vp, vp, i32, i32, vp, vp]
+        L.spgd_run.argtypes = [vp, i32, i32, vp, vp]
+        L.spgd_plan_load.argtypes = [vp, vp, vp, vp, vp]
+        L.spgd_plan_store.argtypes = [vp, vp, vp, vp]
         L.spgd_plan_timing.argtypes = [vp, i32, P(dbl), P(i64)]
         L.dode_loss_bwd.argtypes = [vp, i32, vp, vp, i32, dbl, vp, vp, vp]
         L.dode_routes_create.argtypes = [P(Dims), i64, i32, P(i32), P(i32), P(i32), P(i32), vp, P(vp)]
@@ -128,10 +132,11 @@ def spgd_defaults() -> SpgdParams:
 
 
 def make_params(epochs=300, batch_rows=8192, eta=5.0, eps=1e-10, optimizer=0, check_finite=1,
-                kernel_path=0):
-    """kernel_path 0 = fastest for the storage type, 1 = sparse pattern kernels."""
+                kernel_path=0, use_graph=1):
+    """kernel_path 0 = fastest for the storage type, 1 = sparse pattern kernels;
+    use_graph 1 = replay one captured hipGraph per epoch."""
     return SpgdParams(int(epochs), int(batch_rows), float(eta), float(eps), int(optimizer),
-                      int(check_finite), int(kernel_path))
+                      int(check_finite), int(kernel_path), int(use_graph))
 
 
 class Dar:
@@ -300,14 +305,28 @@ def spgd_plan_create(dar: Dar, day_cluster, params: SpgdParams, perm=None, seed=
     return Plan(out, dar, dc.size, params.epochs)
 
 
-def spgd_run(plan: Plan, X, Q, A, epoch_begin, n_epochs, loss=None, stream=None):
-    import torch
+def spgd_plan_load(plan: Plan, X, Q, A=None, stream=None):
+    """Copy X [D][H][L], Q and A [D][T][P] (A None = zeros) into the plan's state."""
     P, L, T, H, K = plan.dar.dims
     D = plan.D
     dt = plan.dar.state_dtype
-    _check(lib().spgd_run(plan.handle, _ptr(X, "X", dt, (D, H, L)), _ptr(Q, "Q", dt, (D, T, P)),
-                          _ptr(A, "A", dt, (D, T, P)), int(epoch_begin), int(n_epochs),
-                          _ptr(loss, "loss", torch.float64, (n_epochs, D)) if loss is not None
+    _check(lib().spgd_plan_load(plan.handle, _ptr(X, "X", dt, (D, H, L)), _ptr(Q, "Q", dt, (D, T, P)),
+                                _ptr(A, "A", dt, (D, T, P)), _stream(stream)))
+
+
+def spgd_plan_store(plan: Plan, Q, A=None, stream=None):
+    P, L, T, H, K = plan.dar.dims
+    D = plan.D
+    dt = plan.dar.state_dtype
+    _check(lib().spgd_plan_store(plan.handle, _ptr(Q, "Q", dt, (D, T, P)), _ptr(A, "A", dt, (D, T, P)),
+                                 _stream(stream)))
+
+
+def spgd_run(plan: Plan, epoch_begin, n_epochs, loss=None, stream=None):
+    """Epochs of the plan's schedule on its state; loss (optional) is dev float64 [n_epochs][D]."""
+    import torch
+    _check(lib().spgd_run(plan.handle, int(epoch_begin), int(n_epochs),
+                          _ptr(loss, "loss", torch.float64, (n_epochs, plan.D)) if loss is not None
                           else ctypes.c_void_p(0), _stream(stream)))
 
 

@@ -261,31 +261,57 @@ hipError_t timed(dode_plan* p, int k, hipStream_t s, F&& f) {
 
 namespace {
 
-// Minibatch j of epoch e: forward + residual, then adjoint + step + projection.
-dode_status run_minibatch(dode_plan* plan, const void* X, void* Q, void* A, int32_t e, int32_t j,
-                          hipStream_t s) {
+// Minibatch j of epoch e on the plan's state: forward + residual, then
+// adjoint + step + projection.
+dode_status run_chunk(dode_plan* plan, const ChunkSched& cs, hipStream_t s) {
   const dode_dar* dar = plan->dar;
-  const ChunkSched cs = plan->chunk(e, j);
+  const Layout& ly = plan->ly;
   if (plan->use_mfma) {
     const DayGroups dg = plan->groups();
     float* R = static_cast<float*>(plan->d_R);
-    HIP_TRY(timed(plan, 0, s, [&] {
-      return mfma_chunk_resid(dar, cs, dg, static_cast<const float*>(Q),
-                              static_cast<const float*>(X), R, s);
-    }));
-    HIP_TRY(timed(plan, 1, s, [&] {
-      return mfma_chunk_adj_step(dar, cs, dg, R, static_cast<float*>(Q), static_cast<float*>(A),
-                                 plan->sa, s);
-    }));
+    float* Q = static_cast<float*>(plan->d_Q);
+    float* A = static_cast<float*>(plan->d_A);
+    const float* X = static_cast<const float*>(plan->d_X);
+    HIP_TRY(timed(plan, 0, s, [&] { return mfma_chunk_resid(dar, cs, dg, ly, Q, X, R, s); }));
+    HIP_TRY(timed(plan, 1, s, [&] { return mfma_chunk_adj_step(dar, cs, dg, ly, R, Q, A, plan->sa, s); }));
     return DODE_OK;
   }
   const int32_t* dc = plan->d_dc;
   HIP_TRY(timed(plan, 0, s, [&] {
-    return plain_chunk_resid(dar, dc, 0, cs, Q, X, plan->d_R, plan->D, s);
+    return plain_chunk_resid(dar, dc, 0, cs, ly, plan->d_Q, plan->d_X, plan->d_R, plan->D, s);
   }));
   HIP_TRY(timed(plan, 1, s, [&] {
-    return plain_chunk_adj_step(dar, dc, 0, cs, plan->d_R, Q, A, plan->D, plan->sa, s);
+    return plain_chunk_adj_step(dar, dc, 0, cs, ly, plan->d_R, plan->d_Q, plan->d_A, plan->D,
+                                plan->sa, s);
   }));
+  return DODE_OK;
+}
+
+dode_status run_minibatch(dode_plan* plan, int32_t e, int32_t j, hipStream_t s) {
+  return run_chunk(plan, plan->chunk(e, j), s);
+}
+
+// Capture one epoch (every minibatch, then the epoch-counter increment) into a
+// graph on the plan's own stream; replays read the epoch from d_epoch.
+dode_status build_epoch_graph(dode_plan* plan) {
+  if (plan->graph_exec) return DODE_OK;
+  if (!plan->capture_stream)
+    HIP_TRY(hipStreamCreateWithFlags(&plan->capture_stream, hipStreamNonBlocking));
+  hipStream_t cs = plan->capture_stream;
+  HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  dode_status st = DODE_OK;
+  for (int32_t j = 0; j < plan->nch && st == DODE_OK; ++j) st = run_chunk(plan, plan->chunk_dev(j), cs);
+  hipError_t e = st == DODE_OK ? bump_counter(plan->d_epoch, cs) : hipSuccess;
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(cs, &g);
+  if (st != DODE_OK || e != hipSuccess || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    if (st != DODE_OK) return st;
+    return fail(DODE_ERR_HIP, "epoch graph capture: %s",
+                hipGetErrorString(e != hipSuccess ? e : e2));
+  }
+  plan->graph = g;
+  HIP_TRY(hipGraphInstantiate(&plan->graph_exec, g, nullptr, nullptr, 0));
   return DODE_OK;
 }
 
@@ -305,6 +331,7 @@ void dode_spgd_defaults(dode_spgd_params* p) {
   p->optimizer = 0;
   p->check_finite = 1;
   p->kernel_path = 0;
+  p->use_graph = 1;
 }
 
 dode_status dar_destroy(dode_dar* dar) {
@@ -315,7 +342,7 @@ dode_status dar_destroy(dode_dar* dar) {
   for (void* p : {(void*)dar->d_row_ptr, (void*)dar->d_col, (void*)dar->d_col_ptr,
                   (void*)dar->d_row, (void*)dar->d_csc2csr, dar->d_W, dar->d_WT,
                   (void*)dar->d_scale, (void*)dar->d_tile_meta, dar->d_Fv, dar->d_Gv,
-                  (void*)dar->d_Fsc, (void*)dar->d_Gsc, (void*)dar->d_row_of_nz,
+                  (void*)dar->d_row_of_nz,
                   (void*)dar->d_posf, (void*)dar->d_posg})
     if (p) (void)hipFree(p);
   (void)hipSetDevice(cur);
@@ -408,6 +435,14 @@ dode_status dar_create(const dode_dims* dims, int32_t n_clusters, const int32_t*
     HIP_TRY(hipMalloc(&d->d_scale, sbytes));
     d->device_bytes += sbytes;
   }
+  const bool tiled = storage == DODE_BF16 || storage == DODE_FP8_E4M3;
+  if (tiled) {
+    std::string err;
+    if (dode_status st = tiles_prepare(d.get(), err)) {
+      dar_destroy(d.release());
+      return fail(st, "tile layout: %s", err.c_str());
+    }
+  }
   // host conversion, one cluster at a time
   std::vector<uint8_t> hw(cstride * esz), hwt(cstride * esz);
   std::vector<float> hs(storage == DODE_FP8_E4M3 ? (size_t)dm.K * dm.T * n_ptile : 0);
@@ -459,12 +494,12 @@ dode_status dar_create(const dode_dims* dims, int32_t n_clusters, const int32_t*
     if (storage == DODE_FP8_E4M3)
       HIP_TRY(hipMemcpy(d->d_scale + (size_t)c * dm.K * dm.T * n_ptile, hs.data(), hs.size() * 4,
                         hipMemcpyHostToDevice));
-  }
-  if (storage == DODE_BF16 || storage == DODE_FP8_E4M3) {
-    std::string err;
-    if (dode_status st = build_tiles(d.get(), values, err)) {
-      dar_destroy(d.release());
-      return fail(st, "tile build failed: %s", err.c_str());
+    if (tiled) {
+      std::string err;
+      if (dode_status st = tiles_fill_cluster(d.get(), c, hw.data(), err)) {
+        dar_destroy(d.release());
+        return fail(st, "tile fill: %s", err.c_str());
+      }
     }
   }
   HIP_TRY(hipStreamSynchronize(s));
@@ -488,10 +523,8 @@ dode_status dar_set_values(dode_dar* dar, int32_t cluster, const void* W_dev, vo
   if (!W_dev) return fail(DODE_ERR_ARG, "W_dev is NULL");
   if (dar->storage == DODE_FP8_E4M3 && dar->dims.P > 64 * 64)
     return fail(DODE_ERR_UNSUPPORTED, "device FP8 requantisation supports P <= 4096");
-  if (dar->has_tiles && (size_t)(dar->tiles.kf_total + dar->tiles.kg_total) * 4 > 64 * 1024)
-    return fail(DODE_ERR_UNSUPPORTED, "tile rewrite needs kf + kg <= 16384 k-steps");
   HIP_TRY(quantize_values(dar, cluster, W_dev, as_stream(stream)));
-  if (dar->has_tiles) HIP_TRY(update_tiles(dar, cluster, W_dev, as_stream(stream)));
+  if (dar->has_tiles) HIP_TRY(update_tiles(dar, cluster, as_stream(stream)));
   return DODE_OK;
 }
 
@@ -501,7 +534,7 @@ dode_status dode_apply(const dode_dar* dar, int32_t cluster, const void* Q, int3
   if (dode_status st = check_days(n_days)) return st;
   if (n_days == 0) return DODE_OK;
   if (!Q || !Xhat) return fail(DODE_ERR_ARG, "Q or Xhat is NULL");
-  HIP_TRY(plain_apply_rows(dar, nullptr, cluster, Q, nullptr, Xhat, nullptr, n_days,
+  HIP_TRY(plain_apply_rows(dar, nullptr, cluster, day_major(dar->dims), Q, nullptr, Xhat, nullptr, n_days,
                            as_stream(stream)));
   return DODE_OK;
 }
@@ -515,7 +548,8 @@ dode_status dode_loss(const dode_dar* dar, int32_t cluster, const void* Q, const
   hipStream_t s = as_stream(stream);
   DevBuf part;
   HIP_TRY(part.alloc((size_t)n_days * dar->dims.H * 8, s));
-  HIP_TRY(plain_apply_rows(dar, nullptr, cluster, Q, X, nullptr, part.as<double>(), n_days, s));
+  HIP_TRY(plain_apply_rows(dar, nullptr, cluster, day_major(dar->dims), Q, X, nullptr,
+                           part.as<double>(), n_days, s));
   HIP_TRY(sum_partials(part.as<double>(), dar->dims.H, n_days, loss, s));
   return DODE_OK;
 }
@@ -529,8 +563,8 @@ dode_status dode_grad(const dode_dar* dar, int32_t cluster, const void* Q, const
   hipStream_t s = as_stream(stream);
   DevBuf R;
   HIP_TRY(R.alloc((size_t)n_days * dar->dims.H * dar->dims.L * state_size(dar), s));
-  HIP_TRY(plain_apply_rows(dar, nullptr, cluster, Q, X, R.p, nullptr, n_days, s));
-  HIP_TRY(plain_adjoint_rows(dar, nullptr, cluster, R.p, G, n_days, s));
+  HIP_TRY(plain_apply_rows(dar, nullptr, cluster, day_major(dar->dims), Q, X, R.p, nullptr, n_days, s));
+  HIP_TRY(plain_adjoint_rows(dar, nullptr, cluster, day_major(dar->dims), R.p, G, n_days, s));
   return DODE_OK;
 }
 
@@ -550,11 +584,12 @@ dode_status dode_metrics(const dode_dar* dar, int32_t cluster, const void* Q, co
     HIP_TRY(R.alloc((size_t)n * dm.H * dm.L * state_size(dar), s));
     HIP_TRY(G.alloc((size_t)n * dm.T * dm.P * state_size(dar), s));
   }
-  HIP_TRY(plain_apply_rows(dar, nullptr, cluster, Q, X, kkt ? R.p : nullptr, part.as<double>(), n, s));
+  HIP_TRY(plain_apply_rows(dar, nullptr, cluster, day_major(dm), Q, X, kkt ? R.p : nullptr,
+                           part.as<double>(), n, s));
   HIP_TRY(sum_partials(part.as<double>(), dm.H, n, lbuf.as<double>(), s));
   if (loss) HIP_TRY(hipMemcpyAsync(loss, lbuf.p, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
   if (kkt) {
-    HIP_TRY(plain_adjoint_rows(dar, nullptr, cluster, R.p, G.p, n, s));
+    HIP_TRY(plain_adjoint_rows(dar, nullptr, cluster, day_major(dm), R.p, G.p, n, s));
     HIP_TRY(kkt_partials(is_f64(dar), Q, G.p, dm.T, dm.P, n, part.as<double>(), s));
     HIP_TRY(max_partials(part.as<double>(), dm.T, n, kkt, s));
   }
@@ -581,9 +616,10 @@ dode_status dode_loss_bwd(const dode_dar* dar, int32_t cluster, const void* Q, c
   const bool f64 = is_f64(dar);
   DevBuf R;
   HIP_TRY(R.alloc((size_t)std::max(n_days, 1) * dm.H * dm.L * state_size(dar), s));
-  if (n_days > 0) HIP_TRY(plain_apply_rows(dar, nullptr, cluster, Q, X, R.p, nullptr, n_days, s));
+  if (n_days > 0)
+    HIP_TRY(plain_apply_rows(dar, nullptr, cluster, day_major(dm), Q, X, R.p, nullptr, n_days, s));
   if (dQ && n_days > 0) {
-    HIP_TRY(plain_adjoint_rows(dar, nullptr, cluster, R.p, dQ, n_days, s));
+    HIP_TRY(plain_adjoint_rows(dar, nullptr, cluster, day_major(dm), R.p, dQ, n_days, s));
     HIP_TRY(scale_state(f64, dQ, (int64_t)n_days * dm.T * dm.P, 2.0 * grad_out, s));
   }
   if (dW) HIP_TRY(loss_bwd_dW(dar, R.p, Q, n_days, 2.0 * grad_out, dW, s));
@@ -716,12 +752,15 @@ dode_status spgd_step(const dode_dar* dar, int32_t cluster, const int32_t* chunk
   dode_spgd_params p1 = *params;
   p1.epochs = 1;
   p1.batch_rows = n_h * dm.L;
+  p1.check_finite = 0;
   std::vector<int32_t> dc(n_days, cluster);
   dode_plan* raw = nullptr;
   if (dode_status st = spgd_plan_create(dar, dc.data(), n_days, &p1, perm.data(), 0, stream, &raw))
     return st;
   std::unique_ptr<dode_plan, dode_status (*)(dode_plan*)> plan(raw, spgd_plan_destroy);
-  if (dode_status st = run_minibatch(plan.get(), X, Q, A, 0, 0, as_stream(stream))) return st;
+  if (dode_status st = spgd_plan_load(plan.get(), X, Q, A, stream)) return st;
+  if (dode_status st = run_minibatch(plan.get(), 0, 0, as_stream(stream))) return st;
+  if (dode_status st = spgd_plan_store(plan.get(), Q, A, stream)) return st;
   HIP_TRY(hipStreamSynchronize(as_stream(stream)));
   return DODE_OK;
 }
@@ -733,9 +772,14 @@ dode_status spgd_plan_destroy(dode_plan* plan) {
   (void)hipSetDevice(plan->device);
   if (plan->last_stream) (void)hipStreamSynchronize(plan->last_stream);
   for (void* p : {(void*)plan->d_perm, (void*)plan->d_pos, (void*)plan->d_touched,
-                  (void*)plan->d_dc, plan->d_R, (void*)plan->d_part, (void*)plan->d_groups})
+                  (void*)plan->d_dc, plan->d_R, (void*)plan->d_part, (void*)plan->d_groups,
+                  plan->d_X, plan->d_Q, plan->d_A, (void*)plan->d_loss, (void*)plan->d_order})
     if (p) (void)hipFree(p);
   for (hipEvent_t e : plan->event_pool) (void)hipEventDestroy(e);
+  if (plan->graph_exec) (void)hipGraphExecDestroy(plan->graph_exec);
+  if (plan->graph) (void)hipGraphDestroy(plan->graph);
+  if (plan->capture_stream) (void)hipStreamDestroy(plan->capture_stream);
+  if (plan->d_epoch) (void)hipFree(plan->d_epoch);
   (void)hipSetDevice(cur);
   delete plan;
   return DODE_OK;
@@ -770,6 +814,7 @@ dode_status spgd_plan_create(const dode_dar* dar, const int32_t* day_cluster, in
   p->nch = hs.nch;
   p->mt = hs.mt;
   p->sa = StepArgs{params->eta, params->eps, params->optimizer};
+  p->check_finite = params->check_finite != 0;
   HIP_TRY(hipGetDevice(&p->device));
   auto up = [&](int32_t** dst, const void* src, size_t bytes) -> hipError_t {
     hipError_t e = hipMalloc(dst, std::max<size_t>(bytes, 16));
@@ -779,42 +824,89 @@ dode_status spgd_plan_create(const dode_dar* dar, const int32_t* day_cluster, in
   HIP_TRY(up(&p->d_perm, hs.perm.data(), hs.perm.size() * 4));
   HIP_TRY(up(&p->d_pos, hs.pos.data(), hs.pos.size() * 4));
   HIP_TRY(up(&p->d_touched, hs.touched.data(), hs.touched.size() * 4));
-  HIP_TRY(up(&p->d_dc, day_cluster, (size_t)D * 4));
-  HIP_TRY(hipMalloc(&p->d_R, (size_t)D * bh * dm.L * state_size(dar)));
-  HIP_TRY(hipMalloc(&p->d_part, (size_t)D * dm.H * 8));
-  {
-    // groups of up to 32 days of one cluster, clusters in order
-    std::vector<int32_t> gc, gf, gn, days;
-    for (int32_t c = 0; c < C; ++c) {
-      const int32_t start = (int32_t)days.size();
-      for (int32_t d = 0; d < D; ++d)
-        if (day_cluster[d] == c) days.push_back(d);
-      for (int32_t f = start; f < (int32_t)days.size(); f += 32) {
-        gc.push_back(c);
-        gf.push_back(f);
-        gn.push_back(std::min<int32_t>(32, (int32_t)days.size() - f));
+  // plan day i = caller day order[i], days grouped by cluster; groups of up to 32 days
+  std::vector<int32_t> order, dc_plan, gc, gf, gn;
+  for (int32_t c = 0; c < C; ++c) {
+    const int32_t start = (int32_t)order.size();
+    for (int32_t d = 0; d < D; ++d)
+      if (day_cluster[d] == c) {
+        order.push_back(d);
+        dc_plan.push_back(c);
       }
+    for (int32_t f = start; f < (int32_t)order.size(); f += 32) {
+      gc.push_back(c);
+      gf.push_back(f);
+      gn.push_back(std::min<int32_t>(32, (int32_t)order.size() - f));
     }
-    p->n_groups = (int32_t)gc.size();
-    if (p->n_groups > 65535) return fail(DODE_ERR_SHAPE, "too many day groups (%d)", p->n_groups);
+  }
+  p->n_groups = (int32_t)gc.size();
+  {
     std::vector<int32_t> buf;
     buf.insert(buf.end(), gc.begin(), gc.end());
     buf.insert(buf.end(), gf.begin(), gf.end());
     buf.insert(buf.end(), gn.begin(), gn.end());
-    buf.insert(buf.end(), days.begin(), days.end());
+    for (int32_t i = 0; i < D; ++i) buf.push_back(i);   // plan days are already grouped
     HIP_TRY(up(&p->d_groups, buf.data(), buf.size() * 4));
   }
-  p->use_mfma = dar->has_tiles && dar->storage == DODE_BF16 && params->kernel_path == 0;
-  (void)stream;
+  HIP_TRY(up(&p->d_order, order.data(), (size_t)D * 4));
+  HIP_TRY(up(&p->d_dc, dc_plan.data(), (size_t)D * 4));
+  const size_t ss = state_size(dar);
+  HIP_TRY(hipMalloc(&p->d_R, (size_t)D * bh * dm.L * ss));
+  HIP_TRY(hipMalloc(&p->d_part, (size_t)D * dm.H * 8));
+  HIP_TRY(hipMalloc(&p->d_loss, (size_t)D * 8));
+  HIP_TRY(hipMalloc(&p->d_X, (size_t)D * dm.H * dm.L * ss));
+  HIP_TRY(hipMalloc(&p->d_Q, (size_t)D * dm.T * dm.P * ss));
+  HIP_TRY(hipMalloc(&p->d_A, (size_t)D * dm.T * dm.P * ss));
+  p->ly = Layout{dm.P, (int64_t)D * dm.P, dm.L, (int64_t)D * dm.L, dm.L, (int64_t)D * dm.L};
+  hipStream_t s = as_stream(stream);
+  HIP_TRY(fill_zero(is_f64(dar), p->d_X, (int64_t)D * dm.H * dm.L, s));
+  HIP_TRY(fill_zero(is_f64(dar), p->d_Q, (int64_t)D * dm.T * dm.P, s));
+  HIP_TRY(fill_zero(is_f64(dar), p->d_A, (int64_t)D * dm.T * dm.P, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  p->use_mfma = dar->has_tiles && params->kernel_path == 0;
+  p->use_graph = params->use_graph != 0;
+  HIP_TRY(hipMalloc(&p->d_epoch, 16));
+  HIP_TRY(set_counter(p->d_epoch, 0, s));
+  HIP_TRY(hipStreamSynchronize(s));
   *out = pl.release();
   return DODE_OK;
 }
 
-
-dode_status spgd_run(dode_plan* plan, const void* X, void* Q, void* A, int32_t epoch_begin,
-                     int32_t n_epochs, double* loss_dev, void* stream) {
+dode_status spgd_plan_load(dode_plan* plan, const void* X, const void* Q, const void* A,
+                           void* stream) {
   if (!plan) return fail(DODE_ERR_ARG, "plan is NULL");
-  if (!X || !Q || !A) return fail(DODE_ERR_ARG, "X, Q or A is NULL");
+  if (!X || !Q) return fail(DODE_ERR_ARG, "X or Q is NULL");
+  const dode_dar* dar = plan->dar;
+  const dode_dims& dm = dar->dims;
+  hipStream_t s = as_stream(stream);
+  const bool f64 = is_f64(dar);
+  const int32_t D = plan->D;
+  if (plan->check_finite)
+    if (dode_status st = scan_finite(dar, X, (int64_t)D * dm.H * dm.L, s)) return st;
+  HIP_TRY(gather_rows(f64, X, plan->d_X, plan->d_order, D, dm.H, dm.L, false, s));
+  HIP_TRY(gather_rows(f64, Q, plan->d_Q, plan->d_order, D, dm.T, dm.P, true, s));
+  if (A)
+    HIP_TRY(gather_rows(f64, A, plan->d_A, plan->d_order, D, dm.T, dm.P, false, s));
+  else
+    HIP_TRY(fill_zero(f64, plan->d_A, (int64_t)D * dm.T * dm.P, s));
+  plan->last_stream = s;
+  return DODE_OK;
+}
+
+dode_status spgd_plan_store(const dode_plan* plan, void* Q, void* A, void* stream) {
+  if (!plan) return fail(DODE_ERR_ARG, "plan is NULL");
+  if (!Q) return fail(DODE_ERR_ARG, "Q is NULL");
+  const dode_dims& dm = plan->dar->dims;
+  hipStream_t s = as_stream(stream);
+  const bool f64 = is_f64(plan->dar);
+  HIP_TRY(scatter_rows(f64, plan->d_Q, Q, plan->d_order, plan->D, dm.T, dm.P, s));
+  if (A) HIP_TRY(scatter_rows(f64, plan->d_A, A, plan->d_order, plan->D, dm.T, dm.P, s));
+  return DODE_OK;
+}
+
+dode_status spgd_run(dode_plan* plan, int32_t epoch_begin, int32_t n_epochs, double* loss_dev,
+                     void* stream) {
+  if (!plan) return fail(DODE_ERR_ARG, "plan is NULL");
   if (epoch_begin < 0 || n_epochs < 0 || epoch_begin + n_epochs > plan->E)
     return fail(DODE_ERR_ARG, "epochs [%d, %d) outside the plan's %d", epoch_begin,
                 epoch_begin + n_epochs, plan->E);
@@ -823,15 +915,25 @@ dode_status spgd_run(dode_plan* plan, const void* X, void* Q, void* A, int32_t e
   hipStream_t s = as_stream(stream);
   plan->last_stream = s;
   const int32_t D = plan->D;
-  const int32_t* dc = plan->d_dc;
+  const bool graph = plan->use_graph && !plan->timing && n_epochs > 0;
+  if (graph) {
+    if (dode_status st = build_epoch_graph(plan)) return st;
+    HIP_TRY(set_counter(plan->d_epoch, epoch_begin, s));
+  }
   for (int32_t e = epoch_begin; e < epoch_begin + n_epochs; ++e) {
-    for (int32_t j = 0; j < plan->nch; ++j)
-      if (dode_status st = run_minibatch(plan, X, Q, A, e, j, s)) return st;
+    if (graph) {
+      HIP_TRY(hipGraphLaunch(plan->graph_exec, s));
+    } else {
+      for (int32_t j = 0; j < plan->nch; ++j)
+        if (dode_status st = run_minibatch(plan, e, j, s)) return st;
+    }
     if (loss_dev) {
       double* out = loss_dev + (size_t)(e - epoch_begin) * D;
       HIP_TRY(timed(plan, 2, s, [&] {
-        hipError_t r = plain_apply_rows(dar, dc, 0, Q, X, nullptr, plan->d_part, D, s);
-        return r != hipSuccess ? r : sum_partials(plan->d_part, dm.H, D, out, s);
+        hipError_t r = plain_apply_rows(dar, plan->d_dc, 0, plan->ly, plan->d_Q, plan->d_X, nullptr,
+                                        plan->d_part, D, s);
+        if (r == hipSuccess) r = sum_partials(plan->d_part, dm.H, D, plan->d_loss, s);
+        return r != hipSuccess ? r : permute_loss(plan->d_loss, plan->d_order, D, out, s);
       }));
     }
   }
@@ -865,21 +967,18 @@ dode_status spgd_solve(const dode_dar* dar, const int32_t* day_cluster, int32_t 
   if (dode_status st = check_params(params)) return st;
   if (D == 0 || params->epochs == 0) return DODE_OK;
   if (!day_cluster || !X || !Q || !A) return fail(DODE_ERR_ARG, "day_cluster, X, Q or A is NULL");
-  const dode_dims& dm = dar->dims;
   const int32_t E = params->epochs;
   hipStream_t s = as_stream(stream);
   dode_plan* raw = nullptr;
   if (dode_status st = spgd_plan_create(dar, day_cluster, D, params, perm, seed, stream, &raw))
     return st;
   std::unique_ptr<dode_plan, dode_status (*)(dode_plan*)> plan(raw, spgd_plan_destroy);
-  if (params->check_finite)
-    if (dode_status st = scan_finite(dar, X, (int64_t)D * dm.H * dm.L, s)) return st;
+  if (dode_status st = spgd_plan_load(plan.get(), X, Q, A, stream)) return st;
   DevBuf hist;
   if (loss_hist) HIP_TRY(hist.alloc((size_t)E * D * 8, s));
-  HIP_TRY(clamp_nonneg(is_f64(dar), Q, (int64_t)D * dm.T * dm.P, s));
-  if (dode_status st = spgd_run(plan.get(), X, Q, A, 0, E, loss_hist ? hist.as<double>() : nullptr,
-                                stream))
+  if (dode_status st = spgd_run(plan.get(), 0, E, loss_hist ? hist.as<double>() : nullptr, stream))
     return st;
+  if (dode_status st = spgd_plan_store(plan.get(), Q, A, stream)) return st;
   if (loss_hist) {
     std::vector<double> h((size_t)E * D);
     HIP_TRY(hipMemcpyAsync(h.data(), hist.p, h.size() * 8, hipMemcpyDeviceToHost, s));

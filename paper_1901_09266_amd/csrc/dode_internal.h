@@ -36,8 +36,8 @@ struct DevVals {
 //   adjoint:  OD tile j (16 ODs) x link hull [g_alo[j], g_alo[j] + 32*g_ks[j])
 // Values of block (c, l, t) are stored per 16x32 k-step in MFMA operand order
 // (lane-major, 8 consecutive k per lane): Fv[c][l][t][kf_total][64 lanes][8].
-// FP8 storage keeps one float scale per 16-row tile and k-step range:
-//   Fsc[c][l][t][kf_total], Gsc[c][l][t][kg_total].
+// The entries are the same codes as the pattern-form arrays (bf16, or E4M3
+// with the pattern form's scale per (c, l, t, 64-OD group): scale[...][n_ptile]).
 struct DevTiles {
   int32_t nLT = 0, nPT = 0, kf_total = 0, kg_total = 0;
   const int32_t* f_plo = nullptr;
@@ -48,8 +48,8 @@ struct DevTiles {
   const int32_t* g_koff = nullptr;
   const void* Fv = nullptr;
   const void* Gv = nullptr;
-  const float* Fsc = nullptr;
-  const float* Gsc = nullptr;
+  const float* scale = nullptr;   // FP8 only: [C][K][T][n_ptile]
+  int32_t n_ptile = 0;
 };
 
 struct dode_dar {
@@ -77,8 +77,7 @@ struct dode_dar {
   int32_t* d_posg = nullptr;        // [nnz] element offset of CSC slot jj in an adjoint block
   void* d_Fv = nullptr;
   void* d_Gv = nullptr;
-  float* d_Fsc = nullptr;
-  float* d_Gsc = nullptr;
+  std::vector<int32_t> h_posf, h_posg;
 
   DevPat pat() const {
     return DevPat{dims.P, dims.L, dims.T, dims.H, dims.K, nnz, d_row_ptr, d_col, d_col_ptr, d_row};
@@ -108,6 +107,20 @@ struct dode_routes {
   int32_t* d_buf = nullptr;   // all index arrays above, one allocation
 };
 
+// Element strides of the per-day state arrays.  Entry (day d, row r, col k):
+//   Q, A, G : d*q_d + t*q_t + p      X, Xhat : d*x_d + h*x_h + a
+//   R       : d*r_d + s*r_s + a      (s = minibatch slot, or h for full rows)
+// Caller arrays are day-major (q_d = T*P, q_t = P, ...); a plan keeps its copy
+// interval-major (q_d = P, q_t = D*P, ...) so a minibatch's rows are
+// contiguous across days.
+struct Layout {
+  int64_t q_d, q_t, x_d, x_h, r_d, r_s;
+};
+
+inline Layout day_major(const dode_dims& dm) {
+  return Layout{(int64_t)dm.T * dm.P, dm.P, (int64_t)dm.H * dm.L, dm.L, (int64_t)dm.H * dm.L, dm.L};
+}
+
 // Optimizer settings as the kernels see them.
 struct StepArgs {
   double eta;
@@ -121,6 +134,8 @@ struct StepArgs {
 //   perm[c][H]      the epoch's permutation of cluster c
 //   pos[c][H]       its inverse (position of interval h)
 //   touched[c][mt]  departure intervals the minibatch reaches (-1 padded)
+//   epoch           device epoch counter (graph replays) or nullptr; when set,
+//                   the kernels add (*epoch) * perm_e / touched_e to the pointers
 struct ChunkSched {
   const int32_t* perm;
   const int32_t* pos;
@@ -128,7 +143,21 @@ struct ChunkSched {
   int32_t j0;
   int32_t bh;
   int32_t max_touched;
+  const int32_t* epoch;
+  int64_t perm_e;
+  int64_t touched_e;
 };
+
+// Resolve the epoch of a chunk schedule read from device memory (kernel side).
+__device__ __forceinline__ ChunkSched resolve_epoch(ChunkSched cs) {
+  if (cs.epoch) {
+    const int64_t e = *cs.epoch;
+    cs.perm += e * cs.perm_e;
+    cs.pos += e * cs.perm_e;
+    cs.touched += e * cs.touched_e;
+  }
+  return cs;
+}
 
 // Groups of up to 32 days of one cluster (two 16-day MFMA column tiles).
 struct DayGroups {
@@ -149,11 +178,23 @@ struct dode_plan {
   int32_t* d_pos = nullptr;       // [E][C][H]
   int32_t* d_touched = nullptr;   // [E][nch][C][mt]
   int32_t* d_dc = nullptr;        // [D]
-  void* d_R = nullptr;            // [D][bh][L] residual rows of the current minibatch
+  void* d_R = nullptr;            // [bh][D][L] residual rows of the current minibatch
   double* d_part = nullptr;       // [D][H] loss partials
+  void* d_X = nullptr;            // [H][D][L] plan copy of the observations
+  void* d_Q = nullptr;            // [T][D][P] plan copy of the demand
+  void* d_A = nullptr;            // [T][D][P] plan copy of the Adagrad accumulator
+  double* d_loss = nullptr;       // [D] loss of the plan's days (plan order)
+  int32_t* d_order = nullptr;     // [D] caller day of plan day i (days grouped by cluster)
+  Layout ly{};                    // plan layout of X, Q, A, R
   int32_t* d_groups = nullptr;    // cluster | first | count (n_groups each) | days [D]
   int32_t n_groups = 0;
   bool use_mfma = false;
+  bool check_finite = true;
+  bool use_graph = true;
+  int32_t* d_epoch = nullptr;         // epoch counter read by graph replays
+  hipStream_t capture_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
   hipStream_t last_stream = nullptr;
   bool timing = false;
   std::vector<hipEvent_t> event_pool;
@@ -167,7 +208,13 @@ struct dode_plan {
   ChunkSched chunk(int32_t e, int32_t j) const {
     const int32_t H = dar->dims.H;
     return ChunkSched{d_perm + (size_t)e * C * H, d_pos + (size_t)e * C * H,
-                      d_touched + ((size_t)e * nch + j) * C * mt, j * bh, bh, mt};
+                      d_touched + ((size_t)e * nch + j) * C * mt, j * bh, bh, mt, nullptr, 0, 0};
+  }
+  // minibatch j of the epoch held in d_epoch (for graph replays)
+  ChunkSched chunk_dev(int32_t j) const {
+    const int32_t H = dar->dims.H;
+    return ChunkSched{d_perm, d_pos, d_touched + (size_t)j * C * mt, j * bh, bh, mt, d_epoch,
+                      (int64_t)C * H, (int64_t)nch * C * mt};
   }
 };
 
@@ -177,38 +224,54 @@ bool is_f64(const dode_dar* d);
 // All launchers return hipSuccess or the launch error.  `day_cluster` may be
 // nullptr, then every day belongs to `cluster`.
 hipError_t plain_chunk_resid(const dode_dar* dar, const int32_t* day_cluster, int32_t cluster,
-                             const ChunkSched& cs, const void* Q, const void* X, void* R,
-                             int32_t n_days, hipStream_t s);
+                             const ChunkSched& cs, const Layout& ly, const void* Q, const void* X,
+                             void* R, int32_t n_days, hipStream_t s);
 hipError_t plain_chunk_adj_step(const dode_dar* dar, const int32_t* day_cluster, int32_t cluster,
-                                const ChunkSched& cs, const void* R, void* Q, void* A,
-                                int32_t n_days, const StepArgs& st, hipStream_t s);
-// out (nullable) = rho Q (- X if X); part (nullable) = per (day, h) sum of squares of that
+                                const ChunkSched& cs, const Layout& ly, const void* R, void* Q,
+                                void* A, int32_t n_days, const StepArgs& st, hipStream_t s);
+// out (nullable, X layout) = rho Q (- X if X); part (nullable) = [n][H] row sums of squares
 hipError_t plain_apply_rows(const dode_dar* dar, const int32_t* day_cluster, int32_t cluster,
-                            const void* Q, const void* X, void* out, double* part, int32_t n_days,
-                            hipStream_t s);
-// G = rho^T R for full residual rows R [n][H][L]
+                            const Layout& ly, const void* Q, const void* X, void* out, double* part,
+                            int32_t n_days, hipStream_t s);
+// G (Q layout) = rho^T R for full residual rows R (R layout with r_s = row stride of h)
 hipError_t plain_adjoint_rows(const dode_dar* dar, const int32_t* day_cluster, int32_t cluster,
-                              const void* R, void* G, int32_t n_days, hipStream_t s);
+                              const Layout& ly, const void* R, void* G, int32_t n_days,
+                              hipStream_t s);
+// plan state copies: dst[r][i][k] = src[order[i]][r][k] (gather) and back (scatter);
+// clamp projects onto >= 0 on the way in
+hipError_t gather_rows(bool f64, const void* src, void* dst, const int32_t* order, int32_t D,
+                       int32_t rows, int32_t n, bool clamp, hipStream_t s);
+hipError_t scatter_rows(bool f64, const void* src, void* dst, const int32_t* order, int32_t D,
+                        int32_t rows, int32_t n, hipStream_t s);
+hipError_t fill_zero(bool f64, void* x, int64_t n, hipStream_t s);
+hipError_t permute_loss(const double* src, const int32_t* order, int32_t D, double* dst,
+                        hipStream_t s);
+hipError_t set_counter(int32_t* c, int32_t v, hipStream_t s);
+hipError_t bump_counter(int32_t* c, hipStream_t s);
 
 // ---- MFMA tile kernels (mfma_kernels.hip) -------------------------------
 hipError_t mfma_chunk_resid(const dode_dar* dar, const ChunkSched& cs, const DayGroups& dg,
-                            const float* Q, const float* X, float* R, hipStream_t s);
+                            const Layout& ly, const float* Q, const float* X, float* R,
+                            hipStream_t s);
 hipError_t mfma_chunk_adj_step(const dode_dar* dar, const ChunkSched& cs, const DayGroups& dg,
-                               const float* R, float* Q, float* A, const StepArgs& st,
-                               hipStream_t s);
-// host: build the tile layout of all clusters from FP64 values (tiles.hip)
-dode_status build_tiles(dode_dar* d, const double* const* values, std::string& err);
+                               const Layout& ly, const float* R, float* Q, float* A,
+                               const StepArgs& st, hipStream_t s);
+// host: tile layout (ranges, positions, device arrays), then each cluster's
+// entries from its pattern-form codes (CSR order, storage type) (tiles.hip)
+dode_status tiles_prepare(dode_dar* d, std::string& err);
+dode_status tiles_fill_cluster(dode_dar* d, int32_t c, const void* codes_csr, std::string& err);
 
 // ---- differentiation (route_kernels.hip) --------------------------------
 hipError_t routes_rho(const DevRoutes& r, bool f64, const void* Rr, const void* z, void* W,
                       double* pi, hipStream_t s);
 hipError_t routes_logits_bwd(const DevRoutes& r, bool f64, const void* Rr, const void* z,
                              const void* dW, void* dz, double* pi, double* dpi, hipStream_t s);
+// R full residual rows [n][H][L], Q [n][T][P] (day-major)
 hipError_t loss_bwd_dW(const dode_dar* dar, const void* R, const void* Q, int32_t n_days,
                        double scale, void* dW, hipStream_t s);
 hipError_t scale_state(bool f64, void* x, int64_t n, double f, hipStream_t s);
-// rewrite the MFMA tiles of one cluster from state-typed values [K][T][nnz]
-hipError_t update_tiles(const dode_dar* dar, int32_t cluster, const void* W_state, hipStream_t s);
+// copy the pattern-form codes of one cluster into its MFMA tiles (after quantize_values)
+hipError_t update_tiles(const dode_dar* dar, int32_t cluster, hipStream_t s);
 
 // ---- small generic kernels (plain_kernels.hip) -------------------------
 hipError_t sum_partials(const double* part, int32_t n_per, int32_t n_days, double* out,

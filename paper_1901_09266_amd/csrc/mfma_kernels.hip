@@ -1,21 +1,23 @@
-// Matrix-core kernels of one SPGD minibatch (Algorithm 1) for BF16 storage.
+// Matrix-core kernels of one SPGD minibatch (Algorithm 1) for BF16 and FP8
+// storage.
 //
 // The day batch is the MFMA N dimension: a wave owns 16 rows of the output
 // (16 links in the forward product, 16 ODs in the adjoint) for a group of up
 // to 32 days of one cluster (two 16-column tiles), and walks the packed 16x32
 // k-steps of the assignment blocks it needs with v_mfma_f32_16x16x32_bf16.
 //
-// Precision: the assignment values are bfloat16; the FP32 operand (demand in
+// Precision: the assignment values are bfloat16 (or OCP E4M3FN codes with one
+// FP32 scale per (lag block, 64-OD group), widened exactly to bfloat16 in
+// registers, the scale moved onto the other operand); the FP32 operand (demand in
 // the forward product, residual in the adjoint) is split into a bfloat16 head
 // and tail, x = hi + lo (both rounded to nearest even by v_cvt_pk_bf16_f32),
 // and both halves are multiplied (two MFMAs per k-step), so the products keep
 // ~16 significant bits of the FP32 operand; accumulation is FP32.  The
 // Adagrad step, the projection and the residual are FP32.
 //
-// Layouts (caller-owned, day-major): Q, A [D][T][P]; X [D][H][L]; the residual
-// scratch R [D][bh][L] holds the rows of the current minibatch.
+// Layouts: the plan's interval-major copies Q, A [T][D][P], X [H][D][L] and the
+// residual rows of the current minibatch R [bh][D][L] (strides in Layout).
 #include "dode_internal.h"
-#include "numfmt.h"
 
 namespace {
 
@@ -35,13 +37,13 @@ __device__ __forceinline__ int xcd_logical_block(int nblk) {
   return (b % kXcds) * per + b / kXcds;
 }
 
-// 8 consecutive entries [k0, k0+8) of row `row` of a day-major [D][rows][n] array,
-// zero outside [0, n) or for an absent day (d < 0).
-__device__ __forceinline__ f32x8 load8(const float* __restrict__ base, int d, int64_t row_stride_d,
-                                       int row, int n, int k0) {
+// 8 consecutive entries [k0, k0+8) of row `row` of day d (strides sd, sr), zero
+// outside [0, n) or for an absent day (d < 0).
+__device__ __forceinline__ f32x8 load8(const float* __restrict__ base, int d, int64_t sd, int row,
+                                       int64_t sr, int n, int k0) {
   f32x8 v = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   if (d < 0) return v;
-  const float* p = base + (int64_t)d * row_stride_d + (int64_t)row * n + k0;
+  const float* p = base + (int64_t)d * sd + (int64_t)row * sr + k0;
   if (k0 + 8 <= n) {
     const f32x4u a = *reinterpret_cast<const f32x4u*>(p);
     const f32x4u b = *reinterpret_cast<const f32x4u*>(p + 4);
@@ -52,6 +54,26 @@ __device__ __forceinline__ f32x8 load8(const float* __restrict__ base, int d, in
       if (k0 + e < n) v[e] = p[e];
   }
   return v;
+}
+
+// A operand of k-step `kidx` (element offset kidx*512 of the packed tiles):
+// BF16 storage loads 8 bf16 values per lane; FP8 storage loads 8 E4M3FN codes
+// per lane and widens them exactly to bf16 (4 significant bits fit).  The FP8
+// scale is applied by the caller to the other operand.
+template <bool FP8>
+__device__ __forceinline__ bf16x8 load_a(const void* tiles, int64_t kidx, int lane) {
+  if constexpr (!FP8) {
+    return static_cast<const bf16x8*>(tiles)[kidx * 64 + lane];
+  } else {
+    const uint2 w = static_cast<const uint2*>(tiles)[kidx * 64 + lane];
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    const f32x2 a = __builtin_amdgcn_cvt_pk_f32_fp8((int)w.x, false);
+    const f32x2 b = __builtin_amdgcn_cvt_pk_f32_fp8((int)w.x, true);
+    const f32x2 c = __builtin_amdgcn_cvt_pk_f32_fp8((int)w.y, false);
+    const f32x2 d = __builtin_amdgcn_cvt_pk_f32_fp8((int)w.y, true);
+    const f32x8 v = {a[0], a[1], b[0], b[1], c[0], c[1], d[0], d[1]};
+    return __builtin_convertvector(v, bf16x8);
+  }
 }
 
 // acc += a * (hi + lo) with hi = bf16(v), lo = bf16(v - hi).
@@ -87,9 +109,10 @@ __device__ __forceinline__ void store4(float* __restrict__ p, const f32x4& v, bo
 // One wave per item (day group g, slot s, link tile i), i fastest; 4 items per
 // block; blocks remapped so each XCD walks a contiguous range of day groups.
 // The (lag, k-step) loop is flattened and its operands fetched one step ahead.
+template <bool FP8>
 __global__ void __launch_bounds__(256)
-k_fwd_bf16(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, const float* __restrict__ Q,
-           const float* __restrict__ X, float* __restrict__ R) {
+k_fwd_mfma(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, Layout ly,
+           const float* __restrict__ Q, const float* __restrict__ X, float* __restrict__ R) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int n_items = dg.n * cs.bh * tl.nLT;
   const int item = xcd_logical_block((n_items + 3) / 4) * 4 + wave;
@@ -98,6 +121,7 @@ k_fwd_bf16(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, const float* __r
   const int s = (item / tl.nLT) % cs.bh;
   const int g = item / (tl.nLT * cs.bh);
   if (cs.j0 + s >= pt.H) return;
+  cs = resolve_epoch(cs);
   const int c = dg.cluster[g];
   const int h = cs.perm[c * pt.H + cs.j0 + s];
   const int n = lane & 15, kg = lane >> 4;
@@ -110,27 +134,32 @@ k_fwd_bf16(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, const float* __r
   const int valid = pt.L - a0;
   f32x4 x0 = {0.f, 0.f, 0.f, 0.f}, x1 = x0;
   if (a0 < pt.L) {
-    if (d0 >= 0) x0 = load4(X + ((int64_t)d0 * pt.H + h) * pt.L + a0, full, valid);
-    if (d1 >= 0) x1 = load4(X + ((int64_t)d1 * pt.H + h) * pt.L + a0, full, valid);
+    if (d0 >= 0) x0 = load4(X + d0 * ly.x_d + h * ly.x_h + a0, full, valid);
+    if (d1 >= 0) x1 = load4(X + d1 * ly.x_d + h * ly.x_h + a0, full, valid);
   }
   // lags with t = h - l inside [0, T)
   const int l_lo = h - pt.T + 1 > 0 ? h - pt.T + 1 : 0;
   const int l_hi = h < pt.K - 1 ? h : pt.K - 1;
   const int nks = tl.f_ks[i], plo = tl.f_plo[i];
   const int n_it = l_hi >= l_lo ? (l_hi - l_lo + 1) * nks : 0;
-  const int64_t qstride = (int64_t)pt.T * pt.P;
-  const bf16x8* Fv = static_cast<const bf16x8*>(tl.Fv);
-  const int64_t blk = (int64_t)tl.kf_total * 64;
-  const int64_t base_c = ((int64_t)c * pt.K * pt.T) * blk + (int64_t)tl.f_koff[i] * 64 + lane;
+  // k-step index of block (c, l, t): ((c*K + l)*T + t)*kf_total + f_koff[i] + ks
+  const int64_t kbase = (int64_t)c * pt.K * pt.T * tl.kf_total + tl.f_koff[i];
   f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
   if (n_it > 0) {
     auto fetch = [&](int it, bf16x8& a, f32x8& v0, f32x8& v1) {
       const int l = l_lo + it / nks, ks = it % nks;
       const int t = h - l;
-      a = Fv[base_c + ((int64_t)l * pt.T + t) * blk + ks * 64];
+      a = load_a<FP8>(tl.Fv, kbase + ((int64_t)l * pt.T + t) * tl.kf_total + ks, lane);
       const int p0 = plo + 32 * ks + 8 * kg;
-      v0 = load8(Q, d0, qstride, t, pt.P, p0);
-      v1 = load8(Q, d1, qstride, t, pt.P, p0);
+      v0 = load8(Q, d0, ly.q_d, t, ly.q_t, pt.P, p0);
+      v1 = load8(Q, d1, ly.q_d, t, ly.q_t, pt.P, p0);
+      if constexpr (FP8) {
+        // the lane's 8 ODs lie in one 64-OD scale group (p0 is a multiple of 8)
+        const int grp = min(p0 >> 6, tl.n_ptile - 1);
+        const float sc = tl.scale[(((int64_t)c * pt.K + l) * pt.T + t) * tl.n_ptile + grp];
+        v0 *= sc;
+        v1 *= sc;
+      }
     };
     bf16x8 a;
     f32x8 v0, v1;
@@ -147,8 +176,8 @@ k_fwd_bf16(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, const float* __r
     }
   }
   if (a0 >= pt.L) return;
-  if (d0 >= 0) store4(R + ((int64_t)d0 * cs.bh + s) * pt.L + a0, acc0 - x0, full, valid);
-  if (d1 >= 0) store4(R + ((int64_t)d1 * cs.bh + s) * pt.L + a0, acc1 - x1, full, valid);
+  if (d0 >= 0) store4(R + d0 * ly.r_d + s * ly.r_s + a0, acc0 - x0, full, valid);
+  if (d1 >= 0) store4(R + d1 * ly.r_d + s * ly.r_s + a0, acc1 - x1, full, valid);
 }
 
 __device__ __forceinline__ f32x4 step4(f32x4 q, f32x4& a, const f32x4& g, const StepArgs& st) {
@@ -171,9 +200,10 @@ __device__ __forceinline__ f32x4 step4(f32x4 q, f32x4& a, const f32x4& g, const 
 // One wave per item (day group g, reached interval index ti, OD tile j), j
 // fastest; same block remapping as the forward kernel.  The demand and
 // accumulator rows are fetched before the product.
+template <bool FP8>
 __global__ void __launch_bounds__(256)
-k_adj_bf16(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, const float* __restrict__ R,
-           float* __restrict__ Q, float* __restrict__ A, StepArgs st) {
+k_adj_mfma(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, Layout ly,
+           const float* __restrict__ R, float* __restrict__ Q, float* __restrict__ A, StepArgs st) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int n_items = dg.n * cs.max_touched * tl.nPT;
   const int item = xcd_logical_block((n_items + 3) / 4) * 4 + wave;
@@ -181,6 +211,7 @@ k_adj_bf16(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, const float* __r
   const int j = item % tl.nPT;
   const int ti = (item / tl.nPT) % cs.max_touched;
   const int g = item / (tl.nPT * cs.max_touched);
+  cs = resolve_epoch(cs);
   const int c = dg.cluster[g];
   const int t = cs.touched[c * cs.max_touched + ti];
   if (t < 0) return;
@@ -193,8 +224,8 @@ k_adj_bf16(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, const float* __r
   const int valid = pt.P - p0;
   const bool adagrad = st.optimizer == 0;
   f32x4 q0 = {0.f, 0.f, 0.f, 0.f}, q1 = q0, a0 = q0, a1 = q0;
-  const int64_t i0 = ((int64_t)d0 * pt.T + t) * pt.P + p0;
-  const int64_t i1 = ((int64_t)d1 * pt.T + t) * pt.P + p0;
+  const int64_t i0 = d0 * ly.q_d + t * ly.q_t + p0;
+  const int64_t i1 = d1 * ly.q_d + t * ly.q_t + p0;
   if (p0 < pt.P) {
     if (d0 >= 0) {
       q0 = load4(Q + i0, full, valid);
@@ -214,10 +245,7 @@ k_adj_bf16(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, const float* __r
   }
   const int nks = tl.g_ks[j], alo = tl.g_alo[j];
   const int n_it = __popcll(lmask) * nks;
-  const int64_t rstride = (int64_t)cs.bh * pt.L;
-  const bf16x8* Gv = static_cast<const bf16x8*>(tl.Gv);
-  const int64_t blk = (int64_t)tl.kg_total * 64;
-  const int64_t base_c = ((int64_t)c * pt.K * pt.T) * blk + (int64_t)tl.g_koff[j] * 64 + lane;
+  const int64_t kbase = (int64_t)c * pt.K * pt.T * tl.kg_total + tl.g_koff[j];
   f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
   if (n_it > 0) {
     // iteration it -> (it / nks)-th set bit of lmask, k-step it % nks
@@ -225,11 +253,17 @@ k_adj_bf16(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, const float* __r
     int l = __builtin_ctzll(m);
     int ks = 0;
     auto fetch = [&](int lv, int kv, bf16x8& a, f32x8& v0, f32x8& v1) {
-      a = Gv[base_c + ((int64_t)lv * pt.T + t) * blk + kv * 64];
+      a = load_a<FP8>(tl.Gv, kbase + ((int64_t)lv * pt.T + t) * tl.kg_total + kv, lane);
       const int sl = pos[t + lv] - cs.j0;
       const int k0 = alo + 32 * kv + 8 * kg;
-      v0 = load8(R, d0, rstride, sl, pt.L, k0);
-      v1 = load8(R, d1, rstride, sl, pt.L, k0);
+      v0 = load8(R, d0, ly.r_d, sl, ly.r_s, pt.L, k0);
+      v1 = load8(R, d1, ly.r_d, sl, ly.r_s, pt.L, k0);
+      if constexpr (FP8) {
+        // the tile's 16 ODs lie in one 64-OD scale group
+        const float sc = tl.scale[(((int64_t)c * pt.K + lv) * pt.T + t) * tl.n_ptile + ((16 * j) >> 6)];
+        v0 *= sc;
+        v1 *= sc;
+      }
     };
     bf16x8 a;
     f32x8 v0, v1;
@@ -266,80 +300,65 @@ k_adj_bf16(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, const float* __r
   }
 }
 
-// Rewrite the packed tiles of one (cluster, l, t) block from FP32 values W[nnz]
-// (CSR order).  BF16: round each entry.  FP8: one scale per 16x32 k-step tile,
-// max |value| / 448, then round value / scale.  Padding entries stay zero.
+// Copy the pattern-form codes of one (cluster, l, t) block (CSR order, just
+// rewritten by the quantisation kernel) into its packed tiles.
+template <typename E>
 __global__ void __launch_bounds__(256)
-k_update_tiles(DevPat pt, DevTiles tl, int32_t storage, int32_t c, const float* __restrict__ W,
+k_update_tiles(DevPat pt, DevTiles tl, int32_t c, const E* __restrict__ codes,
                const int32_t* __restrict__ posf, const int32_t* __restrict__ posg,
-               const int32_t* __restrict__ csc2csr, void* Fv, void* Gv, float* Fsc, float* Gsc) {
-  extern __shared__ float smax[];   // [kf_total + kg_total] when FP8
+               const int32_t* __restrict__ csc2csr, E* __restrict__ F, E* __restrict__ G) {
   const int64_t lt = blockIdx.x;
   const int l = (int)(lt / pt.T), t = (int)(lt % pt.T);
   if (t + l >= pt.H) return;   // block never read
-  const float* w = W + lt * pt.nnz;
-  const int64_t fb = ((int64_t)c * pt.K * pt.T + lt) * tl.kf_total * 512;
-  const int64_t gb = ((int64_t)c * pt.K * pt.T + lt) * tl.kg_total * 512;
-  if (storage == DODE_BF16) {
-    uint16_t* F = static_cast<uint16_t*>(Fv);
-    uint16_t* G = static_cast<uint16_t*>(Gv);
-    for (int64_t j = threadIdx.x; j < pt.nnz; j += blockDim.x) F[fb + posf[j]] = f32_to_bf16_rne(w[j]);
-    for (int64_t jj = threadIdx.x; jj < pt.nnz; jj += blockDim.x)
-      G[gb + posg[jj]] = f32_to_bf16_rne(w[csc2csr[jj]]);
-    return;
-  }
-  float* sf = smax;
-  float* sg = smax + tl.kf_total;
-  for (int k = threadIdx.x; k < tl.kf_total + tl.kg_total; k += blockDim.x) smax[k] = 0.f;
-  __syncthreads();
-  for (int64_t j = threadIdx.x; j < pt.nnz; j += blockDim.x)
-    atomicMax(reinterpret_cast<unsigned int*>(&sf[posf[j] / 512]), __float_as_uint(fabsf(w[j])));
-  for (int64_t jj = threadIdx.x; jj < pt.nnz; jj += blockDim.x)
-    atomicMax(reinterpret_cast<unsigned int*>(&sg[posg[jj] / 512]),
-              __float_as_uint(fabsf(w[csc2csr[jj]])));
-  __syncthreads();
-  for (int k = threadIdx.x; k < tl.kf_total; k += blockDim.x)
-    Fsc[((int64_t)c * pt.K * pt.T + lt) * tl.kf_total + k] = sf[k] > 0.f ? sf[k] / 448.f : 1.f;
-  for (int k = threadIdx.x; k < tl.kg_total; k += blockDim.x)
-    Gsc[((int64_t)c * pt.K * pt.T + lt) * tl.kg_total + k] = sg[k] > 0.f ? sg[k] / 448.f : 1.f;
-  uint8_t* F = static_cast<uint8_t*>(Fv);
-  uint8_t* G = static_cast<uint8_t*>(Gv);
-  for (int64_t j = threadIdx.x; j < pt.nnz; j += blockDim.x) {
-    const float m = sf[posf[j] / 512];
-    F[fb + posf[j]] = f32_to_e4m3_rne(w[j] / (m > 0.f ? m / 448.f : 1.f));
-  }
-  for (int64_t jj = threadIdx.x; jj < pt.nnz; jj += blockDim.x) {
-    const float m = sg[posg[jj] / 512];
-    G[gb + posg[jj]] = f32_to_e4m3_rne(w[csc2csr[jj]] / (m > 0.f ? m / 448.f : 1.f));
-  }
+  const int64_t blk = (int64_t)c * pt.K * pt.T + lt;
+  const E* w = codes + blk * pt.nnz;
+  E* f = F + blk * tl.kf_total * 512;
+  E* g = G + blk * tl.kg_total * 512;
+  for (int64_t j = threadIdx.x; j < pt.nnz; j += blockDim.x) f[posf[j]] = w[j];
+  for (int64_t jj = threadIdx.x; jj < pt.nnz; jj += blockDim.x) g[posg[jj]] = w[csc2csr[jj]];
 }
 
 }  // namespace
 
-hipError_t update_tiles(const dode_dar* dar, int32_t cluster, const void* W_state, hipStream_t s) {
-  const DevTiles& tl = dar->tiles;
-  const size_t shm = dar->storage == DODE_FP8_E4M3 ? (size_t)(tl.kf_total + tl.kg_total) * 4 : 0;
-  hipLaunchKernelGGL(k_update_tiles, dim3(dar->dims.K * dar->dims.T), dim3(256), shm, s, dar->pat(),
-                     tl, (int32_t)dar->storage, cluster, static_cast<const float*>(W_state),
-                     dar->d_posf, dar->d_posg, dar->d_csc2csr, dar->d_Fv, dar->d_Gv, dar->d_Fsc,
-                     dar->d_Gsc);
+hipError_t update_tiles(const dode_dar* dar, int32_t cluster, hipStream_t s) {
+  const dim3 grid(dar->dims.K * dar->dims.T);
+  if (dar->storage == DODE_FP8_E4M3)
+    hipLaunchKernelGGL(k_update_tiles<uint8_t>, grid, dim3(256), 0, s, dar->pat(), dar->tiles,
+                       cluster, static_cast<const uint8_t*>(dar->d_W), dar->d_posf, dar->d_posg,
+                       dar->d_csc2csr, static_cast<uint8_t*>(dar->d_Fv),
+                       static_cast<uint8_t*>(dar->d_Gv));
+  else
+    hipLaunchKernelGGL(k_update_tiles<uint16_t>, grid, dim3(256), 0, s, dar->pat(), dar->tiles,
+                       cluster, static_cast<const uint16_t*>(dar->d_W), dar->d_posf, dar->d_posg,
+                       dar->d_csc2csr, static_cast<uint16_t*>(dar->d_Fv),
+                       static_cast<uint16_t*>(dar->d_Gv));
   return hipGetLastError();
 }
 
 hipError_t mfma_chunk_resid(const dode_dar* dar, const ChunkSched& cs, const DayGroups& dg,
-                            const float* Q, const float* X, float* R, hipStream_t s) {
+                            const Layout& ly, const float* Q, const float* X, float* R,
+                            hipStream_t s) {
   const int64_t nblk = ((int64_t)dg.n * cs.bh * dar->tiles.nLT + 3) / 4;
   const dim3 grid((unsigned)(((nblk + kXcds - 1) / kXcds) * kXcds));
-  hipLaunchKernelGGL(k_fwd_bf16, grid, dim3(256), 0, s, dar->pat(), dar->tiles, cs, dg, Q, X, R);
+  if (dar->storage == DODE_FP8_E4M3)
+    hipLaunchKernelGGL(k_fwd_mfma<true>, grid, dim3(256), 0, s, dar->pat(), dar->tiles, cs, dg, ly,
+                       Q, X, R);
+  else
+    hipLaunchKernelGGL(k_fwd_mfma<false>, grid, dim3(256), 0, s, dar->pat(), dar->tiles, cs, dg, ly,
+                       Q, X, R);
   return hipGetLastError();
 }
 
 hipError_t mfma_chunk_adj_step(const dode_dar* dar, const ChunkSched& cs, const DayGroups& dg,
-                               const float* R, float* Q, float* A, const StepArgs& st,
-                               hipStream_t s) {
+                               const Layout& ly, const float* R, float* Q, float* A,
+                               const StepArgs& st, hipStream_t s) {
   const int64_t nblk = ((int64_t)dg.n * cs.max_touched * dar->tiles.nPT + 3) / 4;
   const dim3 grid((unsigned)(((nblk + kXcds - 1) / kXcds) * kXcds));
-  hipLaunchKernelGGL(k_adj_bf16, grid, dim3(256), 0, s, dar->pat(), dar->tiles, cs, dg, R, Q, A,
-                     st);
+  if (dar->storage == DODE_FP8_E4M3)
+    hipLaunchKernelGGL(k_adj_mfma<true>, grid, dim3(256), 0, s, dar->pat(), dar->tiles, cs, dg, ly,
+                       R, Q, A, st);
+  else
+    hipLaunchKernelGGL(k_adj_mfma<false>, grid, dim3(256), 0, s, dar->pat(), dar->tiles, cs, dg, ly,
+                       R, Q, A, st);
   return hipGetLastError();
 }

@@ -85,7 +85,7 @@ __device__ double block_max(double v, double* sh) {
 // Row (h, a) of rho_c applied to q_d:  sum_l sum_{p in row a} W[l][h-l][a,p] q[h-l][p].
 template <int ST, typename S>
 __device__ __forceinline__ S row_dot(const DevPat& pt, const DevVals& v, int c, int h, int a,
-                                     const S* q) {
+                                     const S* q, int64_t q_t) {
   S acc = 0;
   const int32_t j0 = pt.row_ptr[a], j1 = pt.row_ptr[a + 1];
   for (int l = 0; l < pt.K; ++l) {
@@ -94,7 +94,7 @@ __device__ __forceinline__ S row_dot(const DevPat& pt, const DevVals& v, int c, 
     if (t >= pt.T) continue;
     const int64_t base = c * v.cstride + ((int64_t)l * pt.T + t) * pt.nnz;
     const int64_t sbase = (c * (int64_t)pt.K * pt.T + (int64_t)l * pt.T + t) * v.n_ptile;
-    const S* qt = q + (int64_t)t * pt.P;
+    const S* qt = q + (int64_t)t * q_t;
     for (int32_t j = j0; j < j1; ++j) {
       const int p = pt.col[j];
       acc += static_cast<S>(Load<ST>::get(v.W, base + j, v.scale, sbase + (p >> 6))) * qt[p];
@@ -108,7 +108,7 @@ __device__ __forceinline__ S row_dot(const DevPat& pt, const DevVals& v, int c, 
 template <int ST, typename S>
 __device__ __forceinline__ S col_dot_chunk(const DevPat& pt, const DevVals& v, int c, int t, int p,
                                            const int32_t* pos_c, int32_t first, int32_t bh,
-                                           const S* Rd, int32_t L) {
+                                           const S* Rd, int64_t r_s) {
   S acc = 0;
   const int32_t k0 = pt.col_ptr[p], k1 = pt.col_ptr[p + 1];
   for (int l = 0; l < pt.K; ++l) {
@@ -118,7 +118,7 @@ __device__ __forceinline__ S col_dot_chunk(const DevPat& pt, const DevVals& v, i
     if (s < 0 || s >= bh) continue;
     const int64_t base = c * v.cstride + ((int64_t)l * pt.T + t) * pt.nnz;
     const int64_t si = (c * (int64_t)pt.K * pt.T + (int64_t)l * pt.T + t) * v.n_ptile + (p >> 6);
-    const S* r = Rd + (int64_t)s * L;
+    const S* r = Rd + (int64_t)s * r_s;
     for (int32_t jj = k0; jj < k1; ++jj)
       acc += static_cast<S>(Load<ST>::get(v.WT, base + jj, v.scale, si)) * r[pt.row[jj]];
   }
@@ -129,31 +129,33 @@ __device__ __forceinline__ S col_dot_chunk(const DevPat& pt, const DevVals& v, i
 template <int ST, typename S>
 __global__ void __launch_bounds__(kRowsBlock)
 k_chunk_resid(DevPat pt, DevVals v, const int32_t* day_cluster, int32_t cluster, ChunkSched cs,
-              const S* __restrict__ Q, const S* __restrict__ X, S* __restrict__ R) {
+              Layout ly, const S* __restrict__ Q, const S* __restrict__ X, S* __restrict__ R) {
   const int a = blockIdx.x * kRowsBlock + threadIdx.x;
   const int s = blockIdx.y, d = blockIdx.z;
   if (a >= pt.L) return;
+  cs = resolve_epoch(cs);
   const int c = day_cl(day_cluster, cluster, d);
   if (cs.j0 + s >= pt.H) return;
   const int h = cs.perm[c * pt.H + cs.j0 + s];
-  const S* q = Q + (int64_t)d * pt.T * pt.P;
-  const S xhat = row_dot<ST, S>(pt, v, c, h, a, q);
-  R[((int64_t)d * cs.bh + s) * pt.L + a] = xhat - X[((int64_t)d * pt.H + h) * pt.L + a];
+  const S xhat = row_dot<ST, S>(pt, v, c, h, a, Q + d * ly.q_d, ly.q_t);
+  R[d * ly.r_d + s * ly.r_s + a] = xhat - X[d * ly.x_d + h * ly.x_h + a];
 }
 
 template <int ST, typename S>
 __global__ void __launch_bounds__(kColsBlock)
 k_chunk_adj_step(DevPat pt, DevVals v, const int32_t* day_cluster, int32_t cluster, ChunkSched cs,
-                 const S* __restrict__ R, S* __restrict__ Q, S* __restrict__ A, StepArgs st) {
+                 Layout ly, const S* __restrict__ R, S* __restrict__ Q, S* __restrict__ A,
+                 StepArgs st) {
   const int p = blockIdx.x * kColsBlock + threadIdx.x;
   const int i = blockIdx.y, d = blockIdx.z;
   if (p >= pt.P) return;
+  cs = resolve_epoch(cs);
   const int c = day_cl(day_cluster, cluster, d);
   const int t = cs.touched[c * cs.max_touched + i];
   if (t < 0) return;
   const S g = col_dot_chunk<ST, S>(pt, v, c, t, p, cs.pos + (int64_t)c * pt.H, cs.j0, cs.bh,
-                                   R + (int64_t)d * cs.bh * pt.L, pt.L);
-  const int64_t idx = ((int64_t)d * pt.T + t) * pt.P + p;
+                                   R + d * ly.r_d, ly.r_s);
+  const int64_t idx = d * ly.q_d + t * ly.q_t + p;
   S q = Q[idx];
   if (st.optimizer == 0) {
     const S acc = A[idx] + g * g;
@@ -167,17 +169,17 @@ k_chunk_adj_step(DevPat pt, DevVals v, const int32_t* day_cluster, int32_t clust
 
 template <int ST, typename S>
 __global__ void __launch_bounds__(kRedBlock)
-k_apply_rows(DevPat pt, DevVals v, const int32_t* day_cluster, int32_t cluster,
+k_apply_rows(DevPat pt, DevVals v, const int32_t* day_cluster, int32_t cluster, Layout ly,
              const S* __restrict__ Q, const S* __restrict__ X, S* __restrict__ out,
              double* __restrict__ part) {
   __shared__ double sh[kRedBlock];
   const int h = blockIdx.x, d = blockIdx.y;
   const int c = day_cl(day_cluster, cluster, d);
-  const S* q = Q + (int64_t)d * pt.T * pt.P;
+  const S* q = Q + d * ly.q_d;
   double ss = 0.0;
   for (int a = threadIdx.x; a < pt.L; a += kRedBlock) {
-    S val = row_dot<ST, S>(pt, v, c, h, a, q);
-    const int64_t o = ((int64_t)d * pt.H + h) * pt.L + a;
+    S val = row_dot<ST, S>(pt, v, c, h, a, q, ly.q_t);
+    const int64_t o = d * ly.x_d + h * ly.x_h + a;
     if (X) val -= X[o];
     if (out) out[o] = val;
     ss += static_cast<double>(val) * static_cast<double>(val);
@@ -190,13 +192,13 @@ k_apply_rows(DevPat pt, DevVals v, const int32_t* day_cluster, int32_t cluster,
 
 template <int ST, typename S>
 __global__ void __launch_bounds__(kColsBlock)
-k_adjoint_rows(DevPat pt, DevVals v, const int32_t* day_cluster, int32_t cluster,
+k_adjoint_rows(DevPat pt, DevVals v, const int32_t* day_cluster, int32_t cluster, Layout ly,
                const S* __restrict__ R, S* __restrict__ G) {
   const int t = blockIdx.x, d = blockIdx.y;
   const int c = day_cl(day_cluster, cluster, d);
-  const S* Rd = R + (int64_t)d * pt.H * pt.L;
+  const S* Rd = R + d * ly.r_d;
   for (int p = threadIdx.x; p < pt.P; p += kColsBlock)
-    G[((int64_t)d * pt.T + t) * pt.P + p] = col_dot_chunk<ST, S>(pt, v, c, t, p, nullptr, 0, pt.H, Rd, pt.L);
+    G[d * ly.q_d + t * ly.q_t + p] = col_dot_chunk<ST, S>(pt, v, c, t, p, nullptr, 0, pt.H, Rd, ly.r_s);
 }
 
 __global__ void k_sum_partials(const double* __restrict__ part, int32_t n_per, int32_t n_days,
@@ -329,10 +331,11 @@ hipError_t dispatch(const dode_dar* dar, Args&&... args) {
 template <int ST, typename S>
 struct RunResid {
   static hipError_t run(const dode_dar* dar, const int32_t* dc, int32_t cl, const ChunkSched& cs,
-                        const void* Q, const void* X, void* R, int32_t n, hipStream_t s) {
+                        const Layout& ly, const void* Q, const void* X, void* R, int32_t n,
+                        hipStream_t s) {
     dim3 grid((dar->dims.L + kRowsBlock - 1) / kRowsBlock, cs.bh, n);
     hipLaunchKernelGGL((k_chunk_resid<ST, S>), grid, dim3(kRowsBlock), 0, s, dar->pat(), dar->vals(),
-                       dc, cl, cs, static_cast<const S*>(Q), static_cast<const S*>(X),
+                       dc, cl, cs, ly, static_cast<const S*>(Q), static_cast<const S*>(X),
                        static_cast<S*>(R));
     return hipGetLastError();
   }
@@ -341,11 +344,11 @@ struct RunResid {
 template <int ST, typename S>
 struct RunAdjStep {
   static hipError_t run(const dode_dar* dar, const int32_t* dc, int32_t cl, const ChunkSched& cs,
-                        const void* R, void* Q, void* A, int32_t n, const StepArgs& st,
-                        hipStream_t s) {
+                        const Layout& ly, const void* R, void* Q, void* A, int32_t n,
+                        const StepArgs& st, hipStream_t s) {
     dim3 grid((dar->dims.P + kColsBlock - 1) / kColsBlock, cs.max_touched, n);
     hipLaunchKernelGGL((k_chunk_adj_step<ST, S>), grid, dim3(kColsBlock), 0, s, dar->pat(),
-                       dar->vals(), dc, cl, cs, static_cast<const S*>(R), static_cast<S*>(Q),
+                       dar->vals(), dc, cl, cs, ly, static_cast<const S*>(R), static_cast<S*>(Q),
                        static_cast<S*>(A), st);
     return hipGetLastError();
   }
@@ -353,11 +356,12 @@ struct RunAdjStep {
 
 template <int ST, typename S>
 struct RunApplyRows {
-  static hipError_t run(const dode_dar* dar, const int32_t* dc, int32_t cl, const void* Q,
-                        const void* X, void* out, double* part, int32_t n, hipStream_t s) {
+  static hipError_t run(const dode_dar* dar, const int32_t* dc, int32_t cl, const Layout& ly,
+                        const void* Q, const void* X, void* out, double* part, int32_t n,
+                        hipStream_t s) {
     dim3 grid(dar->dims.H, n);
     hipLaunchKernelGGL((k_apply_rows<ST, S>), grid, dim3(kRedBlock), 0, s, dar->pat(), dar->vals(),
-                       dc, cl, static_cast<const S*>(Q), static_cast<const S*>(X),
+                       dc, cl, ly, static_cast<const S*>(Q), static_cast<const S*>(X),
                        static_cast<S*>(out), part);
     return hipGetLastError();
   }
@@ -365,11 +369,11 @@ struct RunApplyRows {
 
 template <int ST, typename S>
 struct RunAdjRows {
-  static hipError_t run(const dode_dar* dar, const int32_t* dc, int32_t cl, const void* R, void* G,
-                        int32_t n, hipStream_t s) {
+  static hipError_t run(const dode_dar* dar, const int32_t* dc, int32_t cl, const Layout& ly,
+                        const void* R, void* G, int32_t n, hipStream_t s) {
     dim3 grid(dar->dims.T, n);
     hipLaunchKernelGGL((k_adjoint_rows<ST, S>), grid, dim3(kColsBlock), 0, s, dar->pat(),
-                       dar->vals(), dc, cl, static_cast<const S*>(R), static_cast<S*>(G));
+                       dar->vals(), dc, cl, ly, static_cast<const S*>(R), static_cast<S*>(G));
     return hipGetLastError();
   }
 };
@@ -377,26 +381,118 @@ struct RunAdjRows {
 }  // namespace
 
 hipError_t plain_chunk_resid(const dode_dar* dar, const int32_t* day_cluster, int32_t cluster,
-                             const ChunkSched& cs, const void* Q, const void* X, void* R,
-                             int32_t n_days, hipStream_t s) {
-  return dispatch<RunResid>(dar, dar, day_cluster, cluster, cs, Q, X, R, n_days, s);
+                             const ChunkSched& cs, const Layout& ly, const void* Q, const void* X,
+                             void* R, int32_t n_days, hipStream_t s) {
+  return dispatch<RunResid>(dar, dar, day_cluster, cluster, cs, ly, Q, X, R, n_days, s);
 }
 
 hipError_t plain_chunk_adj_step(const dode_dar* dar, const int32_t* day_cluster, int32_t cluster,
-                                const ChunkSched& cs, const void* R, void* Q, void* A,
-                                int32_t n_days, const StepArgs& st, hipStream_t s) {
-  return dispatch<RunAdjStep>(dar, dar, day_cluster, cluster, cs, R, Q, A, n_days, st, s);
+                                const ChunkSched& cs, const Layout& ly, const void* R, void* Q,
+                                void* A, int32_t n_days, const StepArgs& st, hipStream_t s) {
+  return dispatch<RunAdjStep>(dar, dar, day_cluster, cluster, cs, ly, R, Q, A, n_days, st, s);
 }
 
 hipError_t plain_apply_rows(const dode_dar* dar, const int32_t* day_cluster, int32_t cluster,
-                            const void* Q, const void* X, void* out, double* part, int32_t n_days,
-                            hipStream_t s) {
-  return dispatch<RunApplyRows>(dar, dar, day_cluster, cluster, Q, X, out, part, n_days, s);
+                            const Layout& ly, const void* Q, const void* X, void* out, double* part,
+                            int32_t n_days, hipStream_t s) {
+  return dispatch<RunApplyRows>(dar, dar, day_cluster, cluster, ly, Q, X, out, part, n_days, s);
 }
 
 hipError_t plain_adjoint_rows(const dode_dar* dar, const int32_t* day_cluster, int32_t cluster,
-                              const void* R, void* G, int32_t n_days, hipStream_t s) {
-  return dispatch<RunAdjRows>(dar, dar, day_cluster, cluster, R, G, n_days, s);
+                              const Layout& ly, const void* R, void* G, int32_t n_days,
+                              hipStream_t s) {
+  return dispatch<RunAdjRows>(dar, dar, day_cluster, cluster, ly, R, G, n_days, s);
+}
+
+namespace {
+
+// dst[r][i][k] = src[order[i]][r][k]; block (i, r), threads over k.
+template <typename S>
+__global__ void k_gather(const S* __restrict__ src, S* __restrict__ dst, const int32_t* order,
+                         int32_t D, int32_t rows, int32_t n, int clamp) {
+  const int i = blockIdx.x, r = blockIdx.y;
+  const S* a = src + ((int64_t)order[i] * rows + r) * n;
+  S* b = dst + ((int64_t)r * D + i) * n;
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    const S v = a[k];
+    b[k] = clamp ? (v > S(0) ? v : S(0)) : v;
+  }
+}
+
+template <typename S>
+__global__ void k_scatter(const S* __restrict__ src, S* __restrict__ dst, const int32_t* order,
+                          int32_t D, int32_t rows, int32_t n) {
+  const int i = blockIdx.x, r = blockIdx.y;
+  const S* a = src + ((int64_t)r * D + i) * n;
+  S* b = dst + ((int64_t)order[i] * rows + r) * n;
+  for (int k = threadIdx.x; k < n; k += blockDim.x) b[k] = a[k];
+}
+
+template <typename S>
+__global__ void k_zero(S* __restrict__ x, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = S(0);
+}
+
+__global__ void k_set_counter(int32_t* c, int32_t v) { *c = v; }
+__global__ void k_bump_counter(int32_t* c) { *c += 1; }
+
+__global__ void k_permute_loss(const double* __restrict__ src, const int32_t* __restrict__ order,
+                               int32_t D, double* __restrict__ dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < D) dst[order[i]] = src[i];
+}
+
+}  // namespace
+
+hipError_t gather_rows(bool f64, const void* src, void* dst, const int32_t* order, int32_t D,
+                       int32_t rows, int32_t n, bool clamp, hipStream_t s) {
+  const dim3 grid(D, rows);
+  if (f64)
+    hipLaunchKernelGGL(k_gather<double>, grid, dim3(256), 0, s, static_cast<const double*>(src),
+                       static_cast<double*>(dst), order, D, rows, n, (int)clamp);
+  else
+    hipLaunchKernelGGL(k_gather<float>, grid, dim3(256), 0, s, static_cast<const float*>(src),
+                       static_cast<float*>(dst), order, D, rows, n, (int)clamp);
+  return hipGetLastError();
+}
+
+hipError_t scatter_rows(bool f64, const void* src, void* dst, const int32_t* order, int32_t D,
+                        int32_t rows, int32_t n, hipStream_t s) {
+  const dim3 grid(D, rows);
+  if (f64)
+    hipLaunchKernelGGL(k_scatter<double>, grid, dim3(256), 0, s, static_cast<const double*>(src),
+                       static_cast<double*>(dst), order, D, rows, n);
+  else
+    hipLaunchKernelGGL(k_scatter<float>, grid, dim3(256), 0, s, static_cast<const float*>(src),
+                       static_cast<float*>(dst), order, D, rows, n);
+  return hipGetLastError();
+}
+
+hipError_t fill_zero(bool f64, void* x, int64_t n, hipStream_t s) {
+  const int64_t blocks = std::min<int64_t>(4096, std::max<int64_t>(1, (n + 255) / 256));
+  if (f64)
+    hipLaunchKernelGGL(k_zero<double>, dim3(blocks), dim3(256), 0, s, static_cast<double*>(x), n);
+  else
+    hipLaunchKernelGGL(k_zero<float>, dim3(blocks), dim3(256), 0, s, static_cast<float*>(x), n);
+  return hipGetLastError();
+}
+
+hipError_t set_counter(int32_t* c, int32_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_counter, dim3(1), dim3(1), 0, s, c, v);
+  return hipGetLastError();
+}
+
+hipError_t bump_counter(int32_t* c, hipStream_t s) {
+  hipLaunchKernelGGL(k_bump_counter, dim3(1), dim3(1), 0, s, c);
+  return hipGetLastError();
+}
+
+hipError_t permute_loss(const double* src, const int32_t* order, int32_t D, double* dst,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_permute_loss, dim3((D + 255) / 256), dim3(256), 0, s, src, order, D, dst);
+  return hipGetLastError();
 }
 
 hipError_t sum_partials(const double* part, int32_t n_per, int32_t n_days, double* out,

@@ -61,7 +61,7 @@ int64_t packed_pos(int32_t row, int32_t col, const std::vector<Hull>& hs,
 
 }  // namespace
 
-dode_status build_tiles(dode_dar* d, const double* const* values, std::string& err) {
+dode_status tiles_prepare(dode_dar* d, std::string& err) {
   const dode_dims& dm = d->dims;
   const int64_t nnz = d->nnz;
   const std::vector<Hull> fh = hulls(dm.L, dm.P, d->h_row_ptr, d->h_col);
@@ -81,14 +81,15 @@ dode_status build_tiles(dode_dar* d, const double* const* values, std::string& e
 
   // packed position of every pattern entry, forward (CSR slot j) and adjoint (CSC slot jj)
   auto inside = [](int32_t col, const Hull& h) { return col >= h.lo && col < h.lo + 32 * h.ks; };
-  std::vector<int64_t> posf(nnz), posg(nnz);
+  d->h_posf.resize(nnz);
+  d->h_posg.resize(nnz);
   for (int32_t a = 0; a < dm.L; ++a)
     for (int32_t j = d->h_row_ptr[a]; j < d->h_row_ptr[a + 1]; ++j) {
       if (!inside(d->h_col[j], fh[a / 16])) {
         err = "internal: forward tile range misses a pattern entry";
         return DODE_ERR_SHAPE;
       }
-      posf[j] = packed_pos(a, d->h_col[j], fh, fko);
+      d->h_posf[j] = (int32_t)packed_pos(a, d->h_col[j], fh, fko);
     }
   for (int32_t p = 0; p < dm.P; ++p)
     for (int32_t jj = d->h_col_ptr[p]; jj < d->h_col_ptr[p + 1]; ++jj) {
@@ -96,101 +97,25 @@ dode_status build_tiles(dode_dar* d, const double* const* values, std::string& e
         err = "internal: adjoint tile range misses a pattern entry";
         return DODE_ERR_SHAPE;
       }
-      posg[jj] = packed_pos(p, d->h_row[jj], gh, gko);
+      d->h_posg[jj] = (int32_t)packed_pos(p, d->h_row[jj], gh, gko);
     }
-
-  {
-    std::vector<int32_t> pf(posf.begin(), posf.end()), pg(posg.begin(), posg.end());
-    auto up = [&](int32_t** dst, const std::vector<int32_t>& v) -> bool {
-      if (hipMalloc(dst, std::max<size_t>(16, v.size() * 4)) != hipSuccess) return false;
-      return hipMemcpy(*dst, v.data(), v.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
-    };
-    if (!up(&d->d_posf, pf) || !up(&d->d_posg, pg)) {
-      err = "position tables";
-      return DODE_ERR_OOM;
-    }
-    d->device_bytes += 8 * nnz;
-  }
-  const bool fp8 = d->storage == DODE_FP8_E4M3;
-  const size_t esz = fp8 ? 1 : 2;
-  const int64_t blocks = (int64_t)dm.K * dm.T;
-  const size_t fblk = (size_t)kf * 512, gblk = (size_t)kg * 512;   // elements per block
-  const size_t fbytes = (size_t)d->C * blocks * fblk * esz, gbytes = (size_t)d->C * blocks * gblk * esz;
-
   auto hip_ok = [&](hipError_t e) {
     if (e != hipSuccess) err = hipGetErrorString(e);
     return e == hipSuccess;
   };
-  if (!hip_ok(hipMalloc(&d->d_tile_meta, std::max<size_t>(16, meta.size() * 4)))) return DODE_ERR_OOM;
-  if (!hip_ok(hipMemcpy(d->d_tile_meta, meta.data(), meta.size() * 4, hipMemcpyHostToDevice)))
-    return DODE_ERR_HIP;
+  auto up = [&](int32_t** dst, const std::vector<int32_t>& v) -> bool {
+    if (!hip_ok(hipMalloc(dst, std::max<size_t>(16, v.size() * 4)))) return false;
+    return hip_ok(hipMemcpy(*dst, v.data(), v.size() * 4, hipMemcpyHostToDevice));
+  };
+  if (!up(&d->d_tile_meta, meta) || !up(&d->d_posf, d->h_posf) || !up(&d->d_posg, d->h_posg))
+    return DODE_ERR_OOM;
+  const size_t esz = d->storage == DODE_FP8_E4M3 ? 1 : 2;
+  const int64_t blocks = (int64_t)dm.K * dm.T;
+  const size_t fbytes = (size_t)d->C * blocks * kf * 512 * esz;
+  const size_t gbytes = (size_t)d->C * blocks * kg * 512 * esz;
   if (!hip_ok(hipMalloc(&d->d_Fv, std::max<size_t>(16, fbytes)))) return DODE_ERR_OOM;
   if (!hip_ok(hipMalloc(&d->d_Gv, std::max<size_t>(16, gbytes)))) return DODE_ERR_OOM;
-  d->device_bytes += fbytes + gbytes + meta.size() * 4;
-  size_t fsc_n = 0, gsc_n = 0;
-  if (fp8) {
-    fsc_n = (size_t)d->C * blocks * kf;
-    gsc_n = (size_t)d->C * blocks * kg;
-    if (!hip_ok(hipMalloc(&d->d_Fsc, std::max<size_t>(16, fsc_n * 4)))) return DODE_ERR_OOM;
-    if (!hip_ok(hipMalloc(&d->d_Gsc, std::max<size_t>(16, gsc_n * 4)))) return DODE_ERR_OOM;
-    d->device_bytes += (fsc_n + gsc_n) * 4;
-  }
-
-  std::vector<uint8_t> fbuf(blocks * fblk * esz), gbuf(blocks * gblk * esz);
-  std::vector<float> fsc(fp8 ? blocks * kf : 0), gsc(fp8 ? blocks * kg : 0);
-  std::vector<double> tmp;
-  for (int32_t c = 0; c < d->C; ++c) {
-    std::fill(fbuf.begin(), fbuf.end(), 0);
-    std::fill(gbuf.begin(), gbuf.end(), 0);
-    const double* W = values[c];
-    for (int64_t lt = 0; lt < blocks; ++lt) {
-      const int32_t l = (int32_t)(lt / dm.T), t = (int32_t)(lt % dm.T);
-      if (t + l >= dm.H) continue;   // block past the last interval: never read
-      const double* w = W + lt * nnz;
-      if (!fp8) {
-        uint16_t* fb = reinterpret_cast<uint16_t*>(fbuf.data()) + lt * fblk;
-        uint16_t* gb = reinterpret_cast<uint16_t*>(gbuf.data()) + lt * gblk;
-        for (int64_t j = 0; j < nnz; ++j) fb[posf[j]] = host_f64_to_bf16(w[j]);
-        for (int64_t jj = 0; jj < nnz; ++jj) gb[posg[jj]] = host_f64_to_bf16(w[d->h_csc2csr[jj]]);
-      } else {
-        // one scale per packed 16x32 tile: max |value| / 448
-        tmp.assign(fblk, 0.0);
-        for (int64_t j = 0; j < nnz; ++j) tmp[posf[j]] = w[j];
-        for (int32_t k = 0; k < kf; ++k) {
-          double mx = 0;
-          for (int e = 0; e < 512; ++e) mx = std::max(mx, std::fabs(tmp[(size_t)k * 512 + e]));
-          const float sc = mx > 0 ? static_cast<float>(mx / 448.0) : 1.0f;
-          fsc[lt * kf + k] = sc;
-          for (int e = 0; e < 512; ++e)
-            fbuf[lt * fblk + (size_t)k * 512 + e] = host_f64_to_e4m3(tmp[(size_t)k * 512 + e] / sc);
-        }
-        tmp.assign(gblk, 0.0);
-        for (int64_t jj = 0; jj < nnz; ++jj) tmp[posg[jj]] = w[d->h_csc2csr[jj]];
-        for (int32_t k = 0; k < kg; ++k) {
-          double mx = 0;
-          for (int e = 0; e < 512; ++e) mx = std::max(mx, std::fabs(tmp[(size_t)k * 512 + e]));
-          const float sc = mx > 0 ? static_cast<float>(mx / 448.0) : 1.0f;
-          gsc[lt * kg + k] = sc;
-          for (int e = 0; e < 512; ++e)
-            gbuf[lt * gblk + (size_t)k * 512 + e] = host_f64_to_e4m3(tmp[(size_t)k * 512 + e] / sc);
-        }
-      }
-    }
-    if (!hip_ok(hipMemcpy(static_cast<uint8_t*>(d->d_Fv) + (size_t)c * blocks * fblk * esz, fbuf.data(),
-                          fbuf.size(), hipMemcpyHostToDevice)))
-      return DODE_ERR_HIP;
-    if (!hip_ok(hipMemcpy(static_cast<uint8_t*>(d->d_Gv) + (size_t)c * blocks * gblk * esz, gbuf.data(),
-                          gbuf.size(), hipMemcpyHostToDevice)))
-      return DODE_ERR_HIP;
-    if (fp8) {
-      if (!hip_ok(hipMemcpy(d->d_Fsc + (size_t)c * blocks * kf, fsc.data(), fsc.size() * 4,
-                            hipMemcpyHostToDevice)))
-        return DODE_ERR_HIP;
-      if (!hip_ok(hipMemcpy(d->d_Gsc + (size_t)c * blocks * kg, gsc.data(), gsc.size() * 4,
-                            hipMemcpyHostToDevice)))
-        return DODE_ERR_HIP;
-    }
-  }
+  d->device_bytes += fbytes + gbytes + meta.size() * 4 + 8 * nnz;
   DevTiles& T = d->tiles;
   T.nLT = nLT;
   T.nPT = nPT;
@@ -205,8 +130,46 @@ dode_status build_tiles(dode_dar* d, const double* const* values, std::string& e
   T.g_koff = m + 3 * nLT + 2 * nPT;
   T.Fv = d->d_Fv;
   T.Gv = d->d_Gv;
-  T.Fsc = d->d_Fsc;
-  T.Gsc = d->d_Gsc;
+  T.scale = d->d_scale;
+  T.n_ptile = (dm.P + 63) / 64;
   d->has_tiles = true;
+  return DODE_OK;
+}
+
+dode_status tiles_fill_cluster(dode_dar* d, int32_t c, const void* codes_csr, std::string& err) {
+  const dode_dims& dm = d->dims;
+  const int64_t nnz = d->nnz;
+  const int32_t kf = d->tiles.kf_total, kg = d->tiles.kg_total;
+  const bool fp8 = d->storage == DODE_FP8_E4M3;
+  const size_t esz = fp8 ? 1 : 2;
+  const int64_t blocks = (int64_t)dm.K * dm.T;
+  const size_t fblk = (size_t)kf * 512, gblk = (size_t)kg * 512;   // elements per block
+  std::vector<uint8_t> fbuf(blocks * fblk * esz, 0), gbuf(blocks * gblk * esz, 0);
+  for (int64_t lt = 0; lt < blocks; ++lt) {
+    const int32_t l = (int32_t)(lt / dm.T), t = (int32_t)(lt % dm.T);
+    if (t + l >= dm.H) continue;   // block past the last interval: never read
+    if (fp8) {
+      const uint8_t* w = static_cast<const uint8_t*>(codes_csr) + lt * nnz;
+      uint8_t* fb = fbuf.data() + lt * fblk;
+      uint8_t* gb = gbuf.data() + lt * gblk;
+      for (int64_t j = 0; j < nnz; ++j) fb[d->h_posf[j]] = w[j];
+      for (int64_t jj = 0; jj < nnz; ++jj) gb[d->h_posg[jj]] = w[d->h_csc2csr[jj]];
+    } else {
+      const uint16_t* w = static_cast<const uint16_t*>(codes_csr) + lt * nnz;
+      uint16_t* fb = reinterpret_cast<uint16_t*>(fbuf.data()) + lt * fblk;
+      uint16_t* gb = reinterpret_cast<uint16_t*>(gbuf.data()) + lt * gblk;
+      for (int64_t j = 0; j < nnz; ++j) fb[d->h_posf[j]] = w[j];
+      for (int64_t jj = 0; jj < nnz; ++jj) gb[d->h_posg[jj]] = w[d->h_csc2csr[jj]];
+    }
+  }
+  hipError_t e = hipMemcpy(static_cast<uint8_t*>(d->d_Fv) + (size_t)c * blocks * fblk * esz,
+                           fbuf.data(), fbuf.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(static_cast<uint8_t*>(d->d_Gv) + (size_t)c * blocks * gblk * esz, gbuf.data(),
+                  gbuf.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    err = hipGetErrorString(e);
+    return DODE_ERR_HIP;
+  }
   return DODE_OK;
 }

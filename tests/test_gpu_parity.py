@@ -207,22 +207,23 @@ MFMA_SHAPES = {
 }
 
 
+@pytest.mark.parametrize("storage", ["bf16", "fp8"])
 @pytest.mark.parametrize("name", list(MFMA_SHAPES))
 @pytest.mark.parametrize("opt", [0, 1])
-def test_mfma_step_matches_oracle(name, opt):
-    """One minibatch through the matrix-core kernels (bf16 values, split FP32
-    operands) against the oracle on the same rounded values."""
+def test_mfma_step_matches_oracle(name, opt, storage):
+    """One minibatch through the matrix-core kernels (bf16 or E4M3 values, split
+    FP32 operands) against the oracle on the same rounded values."""
     kw = dict(MFMA_SHAPES[name])
     inst = make_instance(demand="uniform50", noise="add1", x_dtype="f32", seed=77, **kw)
-    say("mfma step", name, opt)
-    Wq = dequantized_values(inst, "bf16")
+    say("mfma step", name, opt, storage)
+    Wq = dequantized_values(inst, storage)
     rng = np.random.default_rng(8)
     Q0 = rng.uniform(0, 5, (inst.D, inst.T, inst.P)).astype(np.float32).astype(np.float64)
     A0 = rng.uniform(0, 2, (inst.D, inst.T, inst.P)).astype(np.float32).astype(np.float64)
     X = inst.x.astype(np.float64)
     chunk = rng.choice(inst.H, size=min(inst.H, 7), replace=False).astype(np.int32)
     eta = 0.3 if opt == 0 else 1e-4
-    dar = make_dar(inst, "bf16")
+    dar = make_dar(inst, storage)
     for c in range(inst.C):
         days = inst.days_of(c)
         Qd, Ad = dev(Q0[days], torch.float32), dev(A0[days], torch.float32)
@@ -237,19 +238,86 @@ def test_mfma_step_matches_oracle(name, opt):
                 assert rel(Ag[k], A) <= 1e-4, (c, d)
 
 
+@pytest.mark.parametrize("storage", ["bf16", "fp8"])
 @pytest.mark.parametrize("name", list(MFMA_SHAPES))
-def test_mfma_solve_matches_oracle(name):
+def test_mfma_solve_matches_oracle(name, storage):
     kw = dict(MFMA_SHAPES[name])
     inst = make_instance(demand="gamma", noise="mult5", x_dtype="f32", seed=78, **kw)
-    say("mfma solve", name)
+    say("mfma solve", name, storage)
     E = 40
     perms = make_perms(79, E, inst.C, inst.H)
     batch_rows = 5 * inst.L
     bh = chunk_h_blocks(inst.L, inst.H, batch_rows)
-    Wq = dequantized_values(inst, "bf16")
+    Wq = dequantized_values(inst, storage)
     x64 = inst.x.astype(np.float64)
     Qo, _, ho = orc.spgd(inst, x64, perms, E, bh, optimizer=0, eta=5.0, W=Wq)
-    Qg, _, hg = run_solve(inst, "bf16", E, batch_rows, 5.0, 0, perms)
+    Qg, _, hg = run_solve(inst, storage, E, batch_rows, 5.0, 0, perms)
     lg, _, _ = orc.metrics(inst, x64, Qg, W=Wq)
     assert np.max(np.abs(lg - ho[:, -1]) / ho[:, -1]) <= 1e-3
     assert np.max(np.abs(hg - ho) / ho) <= 1e-3
+
+
+@pytest.mark.parametrize("storage", ["f64", "bf16", "fp8"])
+def test_plan_with_interleaved_clusters(storage):
+    """Days of different clusters interleaved in the caller's order; the plan's
+    cluster-grouped copy, its loss history and the stored state must map back."""
+    inst = make_instance(P=20, L=40, T=24, K=4, sizes=(7, 5, 3), inc=0.2, pattern="corridor",
+                         demand="gamma", noise="mult5", x_dtype="f64", seed=48)
+    say("plan interleaved", storage)
+    rng = np.random.default_rng(11)
+    order = rng.permutation(inst.D)
+    inst.x = inst.x[order]
+    inst.day_cluster = inst.day_cluster[order].copy()
+    E = 12
+    perms = make_perms(49, E, inst.C, inst.H)
+    bh = chunk_h_blocks(inst.L, inst.H, 200)
+    W = inst.W if storage == "f64" else dequantized_values(inst, storage)
+    Qo, Ao, ho = orc.spgd(inst, inst.x, perms, E, bh, optimizer=0, eta=5.0, W=W)
+    dt = torch.float64 if storage == "f64" else torch.float32
+    dar = make_dar(inst, storage)
+    p = dode.make_params(epochs=E, batch_rows=200, eta=5.0)
+    plan = dode.spgd_plan_create(dar, inst.day_cluster, p, perm=perms, stream=0)
+    Q0 = torch.zeros((inst.D, inst.T, inst.P), dtype=dt, device="cuda")
+    dode.spgd_plan_load(plan, dev(inst.x, dt), Q0)
+    loss = torch.zeros((E, inst.D), dtype=torch.float64, device="cuda")
+    dode.spgd_run(plan, 0, 5, loss=loss[:5])
+    dode.spgd_run(plan, 5, E - 5, loss=loss[5:])
+    Q = torch.empty_like(Q0)
+    A = torch.empty_like(Q0)
+    dode.spgd_plan_store(plan, Q, A)
+    torch.cuda.synchronize()
+    tol = 1e-9 if storage == "f64" else 1e-3
+    assert np.max(np.abs(loss.cpu().numpy().T - ho) / ho) <= tol
+    assert rel(Q.cpu().numpy(), Qo) <= (1e-8 if storage == "f64" else 2e-2)
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_epoch_graph_replays_match_eager(storage):
+    """The captured per-epoch graph, replayed in several runs with eager work and
+    synchronisations in between, gives the eager result bit for bit after each run."""
+    inst = make_instance(P=30, L=60, T=48, K=5, sizes=(20, 13), inc=0.15, pattern="corridor",
+                         demand="gamma", noise="mult5", seed=52)
+    say("graph replay", storage)
+    E = 9
+    perms = make_perms(53, E, inst.C, inst.H)
+    dt = torch.float32
+    dar = make_dar(inst, storage)
+    X = dev(inst.x, dt)
+    Q0 = torch.zeros((inst.D, inst.T, inst.P), dtype=dt, device="cuda")
+    plans = []
+    for g in (1, 0):
+        p = dode.make_params(epochs=E, batch_rows=10 * inst.L, eta=5.0, use_graph=g)
+        plan = dode.spgd_plan_create(dar, inst.day_cluster, p, perm=perms, stream=0)
+        dode.spgd_plan_load(plan, X, Q0)
+        plans.append(plan)
+    for e0 in range(0, E, 3):
+        outs = []
+        for plan in plans:
+            dode.spgd_run(plan, e0, 3)
+            junk = torch.randn(1000, device="cuda").sum()   # eager work between replays
+            torch.cuda.synchronize()
+            Q = torch.empty_like(Q0)
+            dode.spgd_plan_store(plan, Q)
+            torch.cuda.synchronize()
+            outs.append(Q.cpu().numpy())
+        np.testing.assert_array_equal(outs[0], outs[1])
