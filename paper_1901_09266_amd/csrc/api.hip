@@ -123,9 +123,10 @@ dode_status build_sched(const dode_dims& dm, int32_t C, int32_t E, int32_t bh,
       q[p[i]] = i;
     }
   }
-  // departure intervals each minibatch reaches, packed to the largest count seen
+  // departure intervals each minibatch reaches, packed to the largest count seen;
+  // each entry is a descriptor [t, slot of t+0, ..., slot of t+K-1] (slot = position
+  // of interval t+l inside the minibatch, -1 if t+l is not in it)
   std::vector<int32_t> tl;
-  std::vector<int32_t> cnt((size_t)E * hs.nch * C, 0);
   tl.assign((size_t)E * hs.nch * C * hs.mt, -1);
   std::vector<char> mark(T);
   int32_t mt_used = 1;
@@ -146,9 +147,25 @@ dode_status build_sched(const dode_dims& dm, int32_t C, int32_t E, int32_t bh,
         mt_used = std::max(mt_used, n);
       }
     }
-  hs.touched.assign((size_t)E * hs.nch * C * mt_used, -1);
-  for (size_t r = 0; r < (size_t)E * hs.nch * C; ++r)
-    std::memcpy(hs.touched.data() + r * mt_used, tl.data() + r * hs.mt, mt_used * sizeof(int32_t));
+  const size_t dw = (size_t)K + 1;
+  hs.touched.assign((size_t)E * hs.nch * C * mt_used * dw, -1);
+  for (int32_t e = 0; e < E; ++e)
+    for (int32_t j = 0; j < hs.nch; ++j)
+      for (int32_t c = 0; c < C; ++c) {
+        const size_t r = ((size_t)e * hs.nch + j) * C + c;
+        const int32_t* pos = hs.pos.data() + ((size_t)e * C + c) * H;
+        for (int32_t i = 0; i < mt_used; ++i) {
+          const int32_t t = tl[r * hs.mt + i];
+          int32_t* dsc = hs.touched.data() + (r * mt_used + i) * dw;
+          if (t < 0) continue;
+          dsc[0] = t;
+          for (int32_t l = 0; l < K; ++l) {
+            const int32_t h = t + l;
+            const int32_t sl = h < H ? pos[h] - j * bh : -1;
+            dsc[1 + l] = (sl >= 0 && sl < bh) ? sl : -1;
+          }
+        }
+      }
   hs.mt = mt_used;
   return DODE_OK;
 }
@@ -845,7 +862,6 @@ dode_status spgd_plan_create(const dode_dar* dar, const int32_t* day_cluster, in
     buf.insert(buf.end(), gc.begin(), gc.end());
     buf.insert(buf.end(), gf.begin(), gf.end());
     buf.insert(buf.end(), gn.begin(), gn.end());
-    for (int32_t i = 0; i < D; ++i) buf.push_back(i);   // plan days are already grouped
     HIP_TRY(up(&p->d_groups, buf.data(), buf.size() * 4));
   }
   HIP_TRY(up(&p->d_order, order.data(), (size_t)D * 4));

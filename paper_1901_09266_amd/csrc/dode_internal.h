@@ -133,7 +133,9 @@ struct StepArgs {
 // permutation of the H observation intervals.
 //   perm[c][H]      the epoch's permutation of cluster c
 //   pos[c][H]       its inverse (position of interval h)
-//   touched[c][mt]  departure intervals the minibatch reaches (-1 padded)
+//   touched[c][mt][K+1]  descriptors of the departure intervals the minibatch
+//                   reaches: [t, slot of t+0, ..., slot of t+K-1] (slot -1 when
+//                   t+l is not in the minibatch; t = -1 pads the list)
 //   epoch           device epoch counter (graph replays) or nullptr; when set,
 //                   the kernels add (*epoch) * perm_e / touched_e to the pointers
 struct ChunkSched {
@@ -160,11 +162,11 @@ __device__ __forceinline__ ChunkSched resolve_epoch(ChunkSched cs) {
 }
 
 // Groups of up to 32 days of one cluster (two 16-day MFMA column tiles).
+// Plan days are grouped by cluster, so group g holds days first..first+count-1.
 struct DayGroups {
   const int32_t* cluster;   // [n]
-  const int32_t* first;     // [n] offset into days
+  const int32_t* first;     // [n] first plan day of the group
   const int32_t* count;     // [n] 1..32
-  const int32_t* days;      // [D] day indices grouped by cluster
   int32_t n;
 };
 
@@ -176,7 +178,7 @@ struct dode_plan {
   StepArgs sa{};
   int32_t* d_perm = nullptr;      // [E][C][H]
   int32_t* d_pos = nullptr;       // [E][C][H]
-  int32_t* d_touched = nullptr;   // [E][nch][C][mt]
+  int32_t* d_touched = nullptr;   // [E][nch][C][mt][K+1] reached-interval descriptors
   int32_t* d_dc = nullptr;        // [D]
   void* d_R = nullptr;            // [bh][D][L] residual rows of the current minibatch
   double* d_part = nullptr;       // [D][H] loss partials
@@ -186,7 +188,7 @@ struct dode_plan {
   double* d_loss = nullptr;       // [D] loss of the plan's days (plan order)
   int32_t* d_order = nullptr;     // [D] caller day of plan day i (days grouped by cluster)
   Layout ly{};                    // plan layout of X, Q, A, R
-  int32_t* d_groups = nullptr;    // cluster | first | count (n_groups each) | days [D]
+  int32_t* d_groups = nullptr;    // cluster | first | count (n_groups each)
   int32_t n_groups = 0;
   bool use_mfma = false;
   bool check_finite = true;
@@ -202,19 +204,20 @@ struct dode_plan {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[3];
 
   DayGroups groups() const {
-    return DayGroups{d_groups, d_groups + n_groups, d_groups + 2 * n_groups, d_groups + 3 * n_groups,
-                     n_groups};
+    return DayGroups{d_groups, d_groups + n_groups, d_groups + 2 * n_groups, n_groups};
   }
   ChunkSched chunk(int32_t e, int32_t j) const {
     const int32_t H = dar->dims.H;
+    const size_t dw = (size_t)dar->dims.K + 1;
     return ChunkSched{d_perm + (size_t)e * C * H, d_pos + (size_t)e * C * H,
-                      d_touched + ((size_t)e * nch + j) * C * mt, j * bh, bh, mt, nullptr, 0, 0};
+                      d_touched + ((size_t)e * nch + j) * C * mt * dw, j * bh, bh, mt, nullptr, 0, 0};
   }
   // minibatch j of the epoch held in d_epoch (for graph replays)
   ChunkSched chunk_dev(int32_t j) const {
     const int32_t H = dar->dims.H;
-    return ChunkSched{d_perm, d_pos, d_touched + (size_t)j * C * mt, j * bh, bh, mt, d_epoch,
-                      (int64_t)C * H, (int64_t)nch * C * mt};
+    const size_t dw = (size_t)dar->dims.K + 1;
+    return ChunkSched{d_perm, d_pos, d_touched + (size_t)j * C * mt * dw, j * bh, bh, mt, d_epoch,
+                      (int64_t)C * H, (int64_t)(nch * C * mt * dw)};
   }
 };
 

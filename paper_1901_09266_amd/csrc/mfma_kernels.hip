@@ -126,8 +126,8 @@ k_fwd_mfma(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, Layout ly,
   const int h = cs.perm[c * pt.H + cs.j0 + s];
   const int n = lane & 15, kg = lane >> 4;
   const int first = dg.first[g], cnt = dg.count[g];
-  const int d0 = n < cnt ? dg.days[first + n] : -1;
-  const int d1 = 16 + n < cnt ? dg.days[first + 16 + n] : -1;
+  const int d0 = n < cnt ? first + n : -1;
+  const int d1 = 16 + n < cnt ? first + 16 + n : -1;
   // observations of the output rows, fetched before the product
   const int a0 = 16 * i + 4 * kg;
   const bool full = a0 + 4 <= pt.L;
@@ -213,12 +213,13 @@ k_adj_mfma(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, Layout ly,
   const int g = item / (tl.nPT * cs.max_touched);
   cs = resolve_epoch(cs);
   const int c = dg.cluster[g];
-  const int t = cs.touched[c * cs.max_touched + ti];
+  const int32_t* dsc = cs.touched + ((int64_t)c * cs.max_touched + ti) * (pt.K + 1);
+  const int t = dsc[0];
   if (t < 0) return;
   const int n = lane & 15, kg = lane >> 4;
   const int first = dg.first[g], cnt = dg.count[g];
-  const int d0 = n < cnt ? dg.days[first + n] : -1;
-  const int d1 = 16 + n < cnt ? dg.days[first + 16 + n] : -1;
+  const int d0 = n < cnt ? first + n : -1;
+  const int d1 = 16 + n < cnt ? first + 16 + n : -1;
   const int p0 = 16 * j + 4 * kg;
   const bool full = p0 + 4 <= pt.P;
   const int valid = pt.P - p0;
@@ -237,12 +238,9 @@ k_adj_mfma(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, Layout ly,
     }
   }
   // lags whose row block h = t + l is in this minibatch, as a bit mask
-  const int32_t* pos = cs.pos + (int64_t)c * pt.H;
   uint64_t lmask = 0;
-  for (int l = 0; l < pt.K && t + l < pt.H; ++l) {
-    const int sl = pos[t + l] - cs.j0;
-    if (sl >= 0 && sl < cs.bh) lmask |= 1ull << l;
-  }
+  for (int l = 0; l < pt.K; ++l)
+    if (dsc[1 + l] >= 0) lmask |= 1ull << l;
   const int nks = tl.g_ks[j], alo = tl.g_alo[j];
   const int n_it = __popcll(lmask) * nks;
   const int64_t kbase = (int64_t)c * pt.K * pt.T * tl.kg_total + tl.g_koff[j];
@@ -254,7 +252,7 @@ k_adj_mfma(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, Layout ly,
     int ks = 0;
     auto fetch = [&](int lv, int kv, bf16x8& a, f32x8& v0, f32x8& v1) {
       a = load_a<FP8>(tl.Gv, kbase + ((int64_t)lv * pt.T + t) * tl.kg_total + kv, lane);
-      const int sl = pos[t + lv] - cs.j0;
+      const int sl = dsc[1 + lv];
       const int k0 = alo + 32 * kv + 8 * kg;
       v0 = load8(R, d0, ly.r_d, sl, ly.r_s, pt.L, k0);
       v1 = load8(R, d1, ly.r_d, sl, ly.r_s, pt.L, k0);
