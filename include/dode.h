@@ -83,14 +83,18 @@ typedef struct {
                           tiles for BF16 / FP8), 1 = sparse pattern kernels */
   int32_t use_graph;   /* nonzero: spgd_run replays one captured hipGraph per epoch
                           (the epoch index lives in a device counter) */
+  int32_t day_tile;    /* days of one cluster handled together by a matrix-core
+                          wave (the GEMM N dimension): 16, 32 or 64; 0 = let
+                          spgd_plan_load time the three and keep the fastest
+                          (results are the same bits for every choice) */
 } dode_spgd_params;
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* dode_last_error(void);
 
 /* Fill p with the defaults: epochs 300, batch_rows 8192, eta 5, eps 1e-10,
- * Adagrad, check_finite 1, kernel_path 0, use_graph 1 (section "Goodness of
- * fit" gives E, b and eta). */
+ * Adagrad, check_finite 1, kernel_path 0, use_graph 1, day_tile 32 (section
+ * "Goodness of fit" gives E, b and eta). */
 void dode_spgd_defaults(dode_spgd_params* p);
 
 /*
@@ -245,7 +249,10 @@ dode_status spgd_plan_destroy(dode_plan* plan);
 /* Copy the caller's X (dev [D][H][L]), Q and A (dev [D][T][P], state type; A
  * may be NULL for zeros) into the plan, projecting Q onto Q >= 0 (day d is
  * day d of the plan's day_cluster).  With params->check_finite, X is scanned
- * for NaN/Inf first (DODE_ERR_NONFINITE; synchronises `stream`). */
+ * for NaN/Inf first (DODE_ERR_NONFINITE; synchronises `stream`).  With
+ * params->day_tile == 0 the first load of a matrix-core plan also times a few
+ * minibatches at each day tile on this state, keeps the fastest, and loads Q
+ * and A again (synchronises `stream`). */
 dode_status spgd_plan_load(dode_plan* plan, const void* X, const void* Q, const void* A,
                            void* stream);
 
@@ -270,6 +277,12 @@ dode_status spgd_run(dode_plan* plan, int32_t epoch_begin, int32_t n_epochs, dou
  * reset by the next call (which synchronises the last run's stream).
  */
 dode_status spgd_plan_timing(dode_plan* plan, int32_t enable, double* ms, int64_t* launches);
+
+/* Shape of a plan's schedule (any pointer may be NULL): the day tile in use
+ * (0 for the sparse pattern kernels), minibatches per epoch, intervals per
+ * minibatch (b_h) and day groups. */
+dode_status spgd_plan_info(const dode_plan* plan, int32_t* day_tile, int32_t* n_minibatches,
+                           int32_t* minibatch_intervals, int32_t* n_day_groups);
 
 #ifdef __cplusplus
 }

@@ -7,12 +7,14 @@ from ._lib import (DodeError, Dar, SpgdParams, STORAGE, EXPORTS, lib, dar_create
                    dar_set_values, dode_apply, dode_loss, dode_grad, dode_metrics, spgd_step,
                    spgd_solve, spgd_defaults, make_params, Plan, spgd_plan_create, spgd_run,
                    spgd_plan_load, spgd_plan_store,
-                   spgd_plan_timing, dode_loss_bwd, Routes, dode_routes_create, dar_from_logits,
+                   spgd_plan_timing, spgd_plan_info, dode_loss_bwd, Routes, dode_routes_create,
+                   dar_from_logits,
                    dar_logits_bwd)
 
 __all__ = ["DodeError", "Dar", "SpgdParams", "STORAGE", "EXPORTS", "lib", "dar_create", "dar_info",
            "dar_set_values", "dode_apply", "dode_loss", "dode_grad", "dode_metrics", "spgd_step",
            "spgd_solve", "spgd_defaults", "make_params", "Plan", "spgd_plan_create", "spgd_run",
            "spgd_plan_load", "spgd_plan_store",
-           "spgd_plan_timing", "dode_loss_bwd", "Routes", "dode_routes_create", "dar_from_logits",
+           "spgd_plan_timing", "spgd_plan_info", "dode_loss_bwd", "Routes", "dode_routes_create",
+           "dar_from_logits",
            "dar_logits_bwd"]

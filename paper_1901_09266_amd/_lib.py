@@ -26,7 +26,7 @@ STORAGE = {"f64": DODE_F64, "f32": DODE_F32, "bf16": DODE_BF16, "fp8": DODE_FP8_
 EXPORTS = ["dode_last_error", "dode_spgd_defaults", "dar_create", "dar_destroy", "dar_info",
            "dar_set_values", "dode_apply", "dode_loss", "dode_grad", "dode_metrics", "spgd_step",
            "spgd_solve", "spgd_plan_create", "spgd_plan_destroy", "spgd_plan_load",
-           "spgd_plan_store", "spgd_run", "spgd_plan_timing",
+           "spgd_plan_store", "spgd_run", "spgd_plan_timing", "spgd_plan_info",
            "dode_loss_bwd", "dode_routes_create", "dode_routes_destroy", "dar_from_logits",
            "dar_logits_bwd"]
 
@@ -47,7 +47,7 @@ class SpgdParams(ctypes.Structure):
     _fields_ = [("epochs", ctypes.c_int32), ("batch_rows", ctypes.c_int32), ("eta", ctypes.c_double),
                 ("eps", ctypes.c_double), ("optimizer", ctypes.c_int32),
                 ("check_finite", ctypes.c_int32), ("kernel_path", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("day_tile", ctypes.c_int32)]
 
 
 _lib = None
@@ -84,6 +84,7 @@ def lib():
         L.spgd_plan_load.argtypes = [vp, vp, vp, vp, vp]
         L.spgd_plan_store.argtypes = [vp, vp, vp, vp]
         L.spgd_plan_timing.argtypes = [vp, i32, P(dbl), P(i64)]
+        L.spgd_plan_info.argtypes = [vp, P(i32), P(i32), P(i32), P(i32)]
         L.dode_loss_bwd.argtypes = [vp, i32, vp, vp, i32, dbl, vp, vp, vp]
         L.dode_routes_create.argtypes = [P(Dims), i64, i32, P(i32), P(i32), P(i32), P(i32), vp, P(vp)]
         L.dode_routes_destroy.argtypes = [vp]
@@ -132,11 +133,12 @@ def spgd_defaults() -> SpgdParams:
 
 
 def make_params(epochs=300, batch_rows=8192, eta=5.0, eps=1e-10, optimizer=0, check_finite=1,
-                kernel_path=0, use_graph=1):
+                kernel_path=0, use_graph=1, day_tile=32):
     """kernel_path 0 = fastest for the storage type, 1 = sparse pattern kernels;
-    use_graph 1 = replay one captured hipGraph per epoch."""
+    use_graph 1 = replay one captured hipGraph per epoch; day_tile = days per
+    matrix-core wave (16, 32 or 64, or 0 to time them at load and keep the fastest)."""
     return SpgdParams(int(epochs), int(batch_rows), float(eta), float(eps), int(optimizer),
-                      int(check_finite), int(kernel_path), int(use_graph))
+                      int(check_finite), int(kernel_path), int(use_graph), int(day_tile))
 
 
 class Dar:
@@ -328,6 +330,15 @@ def spgd_run(plan: Plan, epoch_begin, n_epochs, loss=None, stream=None):
     _check(lib().spgd_run(plan.handle, int(epoch_begin), int(n_epochs),
                           _ptr(loss, "loss", torch.float64, (n_epochs, plan.D)) if loss is not None
                           else ctypes.c_void_p(0), _stream(stream)))
+
+
+def spgd_plan_info(plan: Plan) -> dict:
+    """day_tile (0 on the sparse kernels), minibatches per epoch, intervals per
+    minibatch and day groups of a plan."""
+    v = [ctypes.c_int32() for _ in range(4)]
+    _check(lib().spgd_plan_info(plan.handle, *[ctypes.byref(x) for x in v]))
+    return dict(zip(("day_tile", "n_minibatches", "minibatch_intervals", "n_day_groups"),
+                    (x.value for x in v)))
 
 
 def spgd_plan_timing(plan: Plan, enable: bool):

@@ -180,6 +180,8 @@ dode_status check_params(const dode_spgd_params* p) {
     return fail(DODE_ERR_ARG, "optimizer=%d (0 Adagrad, 1 fixed step)", p->optimizer);
   if (p->kernel_path != 0 && p->kernel_path != 1)
     return fail(DODE_ERR_ARG, "kernel_path=%d (0 best, 1 sparse)", p->kernel_path);
+  if (p->day_tile != 0 && p->day_tile != 16 && p->day_tile != 32 && p->day_tile != 64)
+    return fail(DODE_ERR_ARG, "day_tile=%d (0 = tune, 16, 32 or 64)", p->day_tile);
   return DODE_OK;
 }
 
@@ -332,6 +334,84 @@ dode_status build_epoch_graph(dode_plan* plan) {
   return DODE_OK;
 }
 
+void drop_epoch_graph(dode_plan* plan) {
+  if (plan->graph_exec) (void)hipGraphExecDestroy(plan->graph_exec);
+  if (plan->graph) (void)hipGraphDestroy(plan->graph);
+  plan->graph_exec = nullptr;
+  plan->graph = nullptr;
+}
+
+// Day groups of `tile` days: each cluster's plan days, in order, cut into
+// groups of at most `tile`.  Replaces the device list and drops a captured
+// epoch graph (it holds the old list).
+dode_status set_day_groups(dode_plan* plan, int32_t tile) {
+  std::vector<int32_t> gc, gf, gn;
+  int32_t start = 0;
+  for (int32_t c = 0; c < plan->C; ++c) {
+    const int32_t n = plan->cluster_days[c];
+    for (int32_t f = 0; f < n; f += tile) {
+      gc.push_back(c);
+      gf.push_back(start + f);
+      gn.push_back(std::min<int32_t>(tile, n - f));
+    }
+    start += n;
+  }
+  std::vector<int32_t> buf;
+  buf.insert(buf.end(), gc.begin(), gc.end());
+  buf.insert(buf.end(), gf.begin(), gf.end());
+  buf.insert(buf.end(), gn.begin(), gn.end());
+  drop_epoch_graph(plan);
+  if (plan->d_groups) HIP_TRY(hipFree(plan->d_groups));
+  plan->d_groups = nullptr;
+  HIP_TRY(hipMalloc(&plan->d_groups, std::max<size_t>(buf.size() * 4, 16)));
+  HIP_TRY(hipMemcpy(plan->d_groups, buf.data(), buf.size() * 4, hipMemcpyHostToDevice));
+  plan->n_groups = (int32_t)gc.size();
+  plan->day_tile = tile;
+  return DODE_OK;
+}
+
+// Time the matrix-core minibatch kernels for each day tile on the loaded state
+// (the first minibatches of epoch 0, after one warm-up minibatch) and keep the
+// fastest.  The runs change the plan's Q and A: the caller reloads them.
+dode_status tune_day_tile(dode_plan* plan, hipStream_t s) {
+  static const int32_t kTiles[] = {16, 32, 64};
+  const int32_t n_mb = std::min<int32_t>(plan->nch, 4);
+  const bool timing = plan->timing;
+  plan->timing = false;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  dode_status st = DODE_OK;
+  float best_ms = 0.f;
+  int32_t best = 32;
+  for (int k = 0; k < 2 && st == DODE_OK; ++k)
+    if (hipEventCreate(&ev[k]) != hipSuccess) st = fail(DODE_ERR_HIP, "hipEventCreate failed");
+  for (int32_t tile : kTiles) {
+    if (st != DODE_OK) break;
+    if ((st = set_day_groups(plan, tile)) != DODE_OK) break;
+    if ((st = run_minibatch(plan, 0, 0, s)) != DODE_OK) break;
+    hipError_t e = hipEventRecord(ev[0], s);
+    for (int32_t j = 0; j < n_mb && st == DODE_OK && e == hipSuccess; ++j)
+      st = run_minibatch(plan, 0, j, s);
+    if (st != DODE_OK) break;
+    if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+    if (e != hipSuccess) {
+      st = fail(DODE_ERR_HIP, "day-tile tuning: %s", hipGetErrorString(e));
+      break;
+    }
+    if (tile == kTiles[0] || ms < best_ms) {
+      best_ms = ms;
+      best = tile;
+    }
+  }
+  for (hipEvent_t e : ev)
+    if (e) (void)hipEventDestroy(e);
+  plan->timing = timing;
+  if (st != DODE_OK) return st;
+  return set_day_groups(plan, best);
+}
+
 }  // namespace
 
 // ================================================================== ABI ==
@@ -349,6 +429,7 @@ void dode_spgd_defaults(dode_spgd_params* p) {
   p->check_finite = 1;
   p->kernel_path = 0;
   p->use_graph = 1;
+  p->day_tile = 32;
 }
 
 dode_status dar_destroy(dode_dar* dar) {
@@ -770,6 +851,7 @@ dode_status spgd_step(const dode_dar* dar, int32_t cluster, const int32_t* chunk
   p1.epochs = 1;
   p1.batch_rows = n_h * dm.L;
   p1.check_finite = 0;
+  if (p1.day_tile == 0) p1.day_tile = 32;   // one minibatch: nothing to tune for
   std::vector<int32_t> dc(n_days, cluster);
   dode_plan* raw = nullptr;
   if (dode_status st = spgd_plan_create(dar, dc.data(), n_days, &p1, perm.data(), 0, stream, &raw))
@@ -841,29 +923,17 @@ dode_status spgd_plan_create(const dode_dar* dar, const int32_t* day_cluster, in
   HIP_TRY(up(&p->d_perm, hs.perm.data(), hs.perm.size() * 4));
   HIP_TRY(up(&p->d_pos, hs.pos.data(), hs.pos.size() * 4));
   HIP_TRY(up(&p->d_touched, hs.touched.data(), hs.touched.size() * 4));
-  // plan day i = caller day order[i], days grouped by cluster; groups of up to 32 days
-  std::vector<int32_t> order, dc_plan, gc, gf, gn;
-  for (int32_t c = 0; c < C; ++c) {
-    const int32_t start = (int32_t)order.size();
+  // plan day i = caller day order[i], days grouped by cluster
+  std::vector<int32_t> order, dc_plan;
+  p->cluster_days.assign(C, 0);
+  for (int32_t c = 0; c < C; ++c)
     for (int32_t d = 0; d < D; ++d)
       if (day_cluster[d] == c) {
         order.push_back(d);
         dc_plan.push_back(c);
+        ++p->cluster_days[c];
       }
-    for (int32_t f = start; f < (int32_t)order.size(); f += 32) {
-      gc.push_back(c);
-      gf.push_back(f);
-      gn.push_back(std::min<int32_t>(32, (int32_t)order.size() - f));
-    }
-  }
-  p->n_groups = (int32_t)gc.size();
-  {
-    std::vector<int32_t> buf;
-    buf.insert(buf.end(), gc.begin(), gc.end());
-    buf.insert(buf.end(), gf.begin(), gf.end());
-    buf.insert(buf.end(), gn.begin(), gn.end());
-    HIP_TRY(up(&p->d_groups, buf.data(), buf.size() * 4));
-  }
+  if (dode_status st = set_day_groups(p, params->day_tile ? params->day_tile : 32)) return st;
   HIP_TRY(up(&p->d_order, order.data(), (size_t)D * 4));
   HIP_TRY(up(&p->d_dc, dc_plan.data(), (size_t)D * 4));
   const size_t ss = state_size(dar);
@@ -880,6 +950,7 @@ dode_status spgd_plan_create(const dode_dar* dar, const int32_t* day_cluster, in
   HIP_TRY(fill_zero(is_f64(dar), p->d_A, (int64_t)D * dm.T * dm.P, s));
   HIP_TRY(hipStreamSynchronize(s));
   p->use_mfma = dar->has_tiles && params->kernel_path == 0;
+  p->tune_day_tile = p->use_mfma && params->day_tile == 0;
   p->use_graph = params->use_graph != 0;
   HIP_TRY(hipMalloc(&p->d_epoch, 16));
   HIP_TRY(set_counter(p->d_epoch, 0, s));
@@ -900,11 +971,17 @@ dode_status spgd_plan_load(dode_plan* plan, const void* X, const void* Q, const 
   if (plan->check_finite)
     if (dode_status st = scan_finite(dar, X, (int64_t)D * dm.H * dm.L, s)) return st;
   HIP_TRY(gather_rows(f64, X, plan->d_X, plan->d_order, D, dm.H, dm.L, false, s));
-  HIP_TRY(gather_rows(f64, Q, plan->d_Q, plan->d_order, D, dm.T, dm.P, true, s));
-  if (A)
-    HIP_TRY(gather_rows(f64, A, plan->d_A, plan->d_order, D, dm.T, dm.P, false, s));
-  else
-    HIP_TRY(fill_zero(f64, plan->d_A, (int64_t)D * dm.T * dm.P, s));
+  for (int pass = 0; pass < 2; ++pass) {
+    HIP_TRY(gather_rows(f64, Q, plan->d_Q, plan->d_order, D, dm.T, dm.P, true, s));
+    if (A)
+      HIP_TRY(gather_rows(f64, A, plan->d_A, plan->d_order, D, dm.T, dm.P, false, s));
+    else
+      HIP_TRY(fill_zero(f64, plan->d_A, (int64_t)D * dm.T * dm.P, s));
+    if (pass == 1 || !plan->tune_day_tile) break;
+    // tuning runs minibatches on the loaded state; the second pass reloads it
+    if (dode_status st = tune_day_tile(plan, s)) return st;
+    plan->tune_day_tile = false;
+  }
   plan->last_stream = s;
   return DODE_OK;
 }
@@ -953,6 +1030,16 @@ dode_status spgd_run(dode_plan* plan, int32_t epoch_begin, int32_t n_epochs, dou
       }));
     }
   }
+  return DODE_OK;
+}
+
+dode_status spgd_plan_info(const dode_plan* plan, int32_t* day_tile, int32_t* n_minibatches,
+                           int32_t* minibatch_intervals, int32_t* n_day_groups) {
+  if (!plan) return fail(DODE_ERR_ARG, "plan is NULL");
+  if (day_tile) *day_tile = plan->use_mfma ? plan->day_tile : 0;
+  if (n_minibatches) *n_minibatches = plan->nch;
+  if (minibatch_intervals) *minibatch_intervals = plan->bh;
+  if (n_day_groups) *n_day_groups = plan->use_mfma ? plan->n_groups : 0;
   return DODE_OK;
 }
 

@@ -166,8 +166,9 @@ __device__ __forceinline__ ChunkSched resolve_epoch(ChunkSched cs) {
 struct DayGroups {
   const int32_t* cluster;   // [n]
   const int32_t* first;     // [n] first plan day of the group
-  const int32_t* count;     // [n] 1..32
+  const int32_t* count;     // [n] 1..tile
   int32_t n;
+  int32_t tile;             // days per group: 16, 32 or 64 (MFMA column tiles of a wave)
 };
 
 // Minibatch schedule and scratch of spgd_run (see spgd_plan_create).
@@ -190,6 +191,9 @@ struct dode_plan {
   Layout ly{};                    // plan layout of X, Q, A, R
   int32_t* d_groups = nullptr;    // cluster | first | count (n_groups each)
   int32_t n_groups = 0;
+  int32_t day_tile = 32;          // days per group
+  bool tune_day_tile = false;     // choose day_tile by timing at the next load
+  std::vector<int32_t> cluster_days;  // days of each cluster (plan days are grouped by cluster)
   bool use_mfma = false;
   bool check_finite = true;
   bool use_graph = true;
@@ -204,7 +208,7 @@ struct dode_plan {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[3];
 
   DayGroups groups() const {
-    return DayGroups{d_groups, d_groups + n_groups, d_groups + 2 * n_groups, n_groups};
+    return DayGroups{d_groups, d_groups + n_groups, d_groups + 2 * n_groups, n_groups, day_tile};
   }
   ChunkSched chunk(int32_t e, int32_t j) const {
     const int32_t H = dar->dims.H;

@@ -108,11 +108,13 @@ __device__ __forceinline__ void store4(float* __restrict__ p, const f32x4& v, bo
 //   R[d][s][a] = sum_l rho_c[l][h-l][a, :] . Q_d[h-l][:] - X_d[h][a],  h = perm[j0+s].
 // One wave per item (day group g, slot s, link tile i), i fastest; 4 items per
 // block; blocks remapped so each XCD walks a contiguous range of day groups.
-// The (lag, k-step) loop is flattened and its operands fetched one step ahead.
-template <bool FP8>
+// A wave covers NT 16-day column tiles; the (lag, k-step) loop is flattened and,
+// for NT <= 2, its operands are fetched one step ahead.
+template <bool FP8, int NT>
 __global__ void __launch_bounds__(256)
 k_fwd_mfma(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, Layout ly,
            const float* __restrict__ Q, const float* __restrict__ X, float* __restrict__ R) {
+  constexpr bool kAhead = NT <= 2;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int n_items = dg.n * cs.bh * tl.nLT;
   const int item = xcd_logical_block((n_items + 3) / 4) * 4 + wave;
@@ -126,16 +128,18 @@ k_fwd_mfma(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, Layout ly,
   const int h = cs.perm[c * pt.H + cs.j0 + s];
   const int n = lane & 15, kg = lane >> 4;
   const int first = dg.first[g], cnt = dg.count[g];
-  const int d0 = n < cnt ? first + n : -1;
-  const int d1 = 16 + n < cnt ? first + 16 + n : -1;
+  int d[NT];
+#pragma unroll
+  for (int u = 0; u < NT; ++u) d[u] = 16 * u + n < cnt ? first + 16 * u + n : -1;
   // observations of the output rows, fetched before the product
   const int a0 = 16 * i + 4 * kg;
   const bool full = a0 + 4 <= pt.L;
   const int valid = pt.L - a0;
-  f32x4 x0 = {0.f, 0.f, 0.f, 0.f}, x1 = x0;
-  if (a0 < pt.L) {
-    if (d0 >= 0) x0 = load4(X + d0 * ly.x_d + h * ly.x_h + a0, full, valid);
-    if (d1 >= 0) x1 = load4(X + d1 * ly.x_d + h * ly.x_h + a0, full, valid);
+  f32x4 x[NT];
+#pragma unroll
+  for (int u = 0; u < NT; ++u) {
+    x[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (a0 < pt.L && d[u] >= 0) x[u] = load4(X + d[u] * ly.x_d + h * ly.x_h + a0, full, valid);
   }
   // lags with t = h - l inside [0, T)
   const int l_lo = h - pt.T + 1 > 0 ? h - pt.T + 1 : 0;
@@ -144,40 +148,51 @@ k_fwd_mfma(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, Layout ly,
   const int n_it = l_hi >= l_lo ? (l_hi - l_lo + 1) * nks : 0;
   // k-step index of block (c, l, t): ((c*K + l)*T + t)*kf_total + f_koff[i] + ks
   const int64_t kbase = (int64_t)c * pt.K * pt.T * tl.kf_total + tl.f_koff[i];
-  f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
+  f32x4 acc[NT];
+#pragma unroll
+  for (int u = 0; u < NT; ++u) acc[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+  auto fetch = [&](int it, bf16x8& a, f32x8 (&v)[NT]) {
+    const int l = l_lo + it / nks, ks = it % nks;
+    const int t = h - l;
+    a = load_a<FP8>(tl.Fv, kbase + ((int64_t)l * pt.T + t) * tl.kf_total + ks, lane);
+    const int p0 = plo + 32 * ks + 8 * kg;
+#pragma unroll
+    for (int u = 0; u < NT; ++u) v[u] = load8(Q, d[u], ly.q_d, t, ly.q_t, pt.P, p0);
+    if constexpr (FP8) {
+      // the lane's 8 ODs lie in one 64-OD scale group (p0 is a multiple of 8)
+      const int grp = min(p0 >> 6, tl.n_ptile - 1);
+      const float sc = tl.scale[(((int64_t)c * pt.K + l) * pt.T + t) * tl.n_ptile + grp];
+#pragma unroll
+      for (int u = 0; u < NT; ++u) v[u] *= sc;
+    }
+  };
   if (n_it > 0) {
-    auto fetch = [&](int it, bf16x8& a, f32x8& v0, f32x8& v1) {
-      const int l = l_lo + it / nks, ks = it % nks;
-      const int t = h - l;
-      a = load_a<FP8>(tl.Fv, kbase + ((int64_t)l * pt.T + t) * tl.kf_total + ks, lane);
-      const int p0 = plo + 32 * ks + 8 * kg;
-      v0 = load8(Q, d0, ly.q_d, t, ly.q_t, pt.P, p0);
-      v1 = load8(Q, d1, ly.q_d, t, ly.q_t, pt.P, p0);
-      if constexpr (FP8) {
-        // the lane's 8 ODs lie in one 64-OD scale group (p0 is a multiple of 8)
-        const int grp = min(p0 >> 6, tl.n_ptile - 1);
-        const float sc = tl.scale[(((int64_t)c * pt.K + l) * pt.T + t) * tl.n_ptile + grp];
-        v0 *= sc;
-        v1 *= sc;
-      }
-    };
     bf16x8 a;
-    f32x8 v0, v1;
-    fetch(0, a, v0, v1);
+    f32x8 v[NT];
+    if constexpr (kAhead) fetch(0, a, v);
     for (int it = 0; it < n_it; ++it) {
-      bf16x8 an = a;
-      f32x8 v0n = v0, v1n = v1;
-      if (it + 1 < n_it) fetch(it + 1, an, v0n, v1n);
-      mma_split(a, v0, acc0);
-      mma_split(a, v1, acc1);
-      a = an;
-      v0 = v0n;
-      v1 = v1n;
+      if constexpr (kAhead) {
+        bf16x8 an = a;
+        f32x8 vn[NT];
+#pragma unroll
+        for (int u = 0; u < NT; ++u) vn[u] = v[u];
+        if (it + 1 < n_it) fetch(it + 1, an, vn);
+#pragma unroll
+        for (int u = 0; u < NT; ++u) mma_split(a, v[u], acc[u]);
+        a = an;
+#pragma unroll
+        for (int u = 0; u < NT; ++u) v[u] = vn[u];
+      } else {
+        fetch(it, a, v);
+#pragma unroll
+        for (int u = 0; u < NT; ++u) mma_split(a, v[u], acc[u]);
+      }
     }
   }
   if (a0 >= pt.L) return;
-  if (d0 >= 0) store4(R + d0 * ly.r_d + s * ly.r_s + a0, acc0 - x0, full, valid);
-  if (d1 >= 0) store4(R + d1 * ly.r_d + s * ly.r_s + a0, acc1 - x1, full, valid);
+#pragma unroll
+  for (int u = 0; u < NT; ++u)
+    if (d[u] >= 0) store4(R + d[u] * ly.r_d + s * ly.r_s + a0, acc[u] - x[u], full, valid);
 }
 
 __device__ __forceinline__ f32x4 step4(f32x4 q, f32x4& a, const f32x4& g, const StepArgs& st) {
@@ -200,10 +215,11 @@ __device__ __forceinline__ f32x4 step4(f32x4 q, f32x4& a, const f32x4& g, const 
 // One wave per item (day group g, reached interval index ti, OD tile j), j
 // fastest; same block remapping as the forward kernel.  The demand and
 // accumulator rows are fetched before the product.
-template <bool FP8>
+template <bool FP8, int NT>
 __global__ void __launch_bounds__(256)
 k_adj_mfma(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, Layout ly,
            const float* __restrict__ R, float* __restrict__ Q, float* __restrict__ A, StepArgs st) {
+  constexpr bool kAhead = NT <= 2;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int n_items = dg.n * cs.max_touched * tl.nPT;
   const int item = xcd_logical_block((n_items + 3) / 4) * 4 + wave;
@@ -218,23 +234,22 @@ k_adj_mfma(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, Layout ly,
   if (t < 0) return;
   const int n = lane & 15, kg = lane >> 4;
   const int first = dg.first[g], cnt = dg.count[g];
-  const int d0 = n < cnt ? first + n : -1;
-  const int d1 = 16 + n < cnt ? first + 16 + n : -1;
+  int d[NT];
+#pragma unroll
+  for (int u = 0; u < NT; ++u) d[u] = 16 * u + n < cnt ? first + 16 * u + n : -1;
   const int p0 = 16 * j + 4 * kg;
   const bool full = p0 + 4 <= pt.P;
   const int valid = pt.P - p0;
   const bool adagrad = st.optimizer == 0;
-  f32x4 q0 = {0.f, 0.f, 0.f, 0.f}, q1 = q0, a0 = q0, a1 = q0;
-  const int64_t i0 = d0 * ly.q_d + t * ly.q_t + p0;
-  const int64_t i1 = d1 * ly.q_d + t * ly.q_t + p0;
-  if (p0 < pt.P) {
-    if (d0 >= 0) {
-      q0 = load4(Q + i0, full, valid);
-      if (adagrad) a0 = load4(A + i0, full, valid);
-    }
-    if (d1 >= 0) {
-      q1 = load4(Q + i1, full, valid);
-      if (adagrad) a1 = load4(A + i1, full, valid);
+  f32x4 q[NT], a[NT];
+#pragma unroll
+  for (int u = 0; u < NT; ++u) {
+    q[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+    a[u] = q[u];
+    if (p0 < pt.P && d[u] >= 0) {
+      const int64_t idx = d[u] * ly.q_d + t * ly.q_t + p0;
+      q[u] = load4(Q + idx, full, valid);
+      if (adagrad) a[u] = load4(A + idx, full, valid);
     }
   }
   // lags whose row block h = t + l is in this minibatch, as a bit mask
@@ -244,28 +259,30 @@ k_adj_mfma(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, Layout ly,
   const int nks = tl.g_ks[j], alo = tl.g_alo[j];
   const int n_it = __popcll(lmask) * nks;
   const int64_t kbase = (int64_t)c * pt.K * pt.T * tl.kg_total + tl.g_koff[j];
-  f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
+  f32x4 acc[NT];
+#pragma unroll
+  for (int u = 0; u < NT; ++u) acc[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+  auto fetch = [&](int lv, int kv, bf16x8& av, f32x8 (&v)[NT]) {
+    av = load_a<FP8>(tl.Gv, kbase + ((int64_t)lv * pt.T + t) * tl.kg_total + kv, lane);
+    const int sl = dsc[1 + lv];
+    const int k0 = alo + 32 * kv + 8 * kg;
+#pragma unroll
+    for (int u = 0; u < NT; ++u) v[u] = load8(R, d[u], ly.r_d, sl, ly.r_s, pt.L, k0);
+    if constexpr (FP8) {
+      // the tile's 16 ODs lie in one 64-OD scale group
+      const float sc = tl.scale[(((int64_t)c * pt.K + lv) * pt.T + t) * tl.n_ptile + ((16 * j) >> 6)];
+#pragma unroll
+      for (int u = 0; u < NT; ++u) v[u] *= sc;
+    }
+  };
   if (n_it > 0) {
     // iteration it -> (it / nks)-th set bit of lmask, k-step it % nks
     uint64_t m = lmask;
     int l = __builtin_ctzll(m);
     int ks = 0;
-    auto fetch = [&](int lv, int kv, bf16x8& a, f32x8& v0, f32x8& v1) {
-      a = load_a<FP8>(tl.Gv, kbase + ((int64_t)lv * pt.T + t) * tl.kg_total + kv, lane);
-      const int sl = dsc[1 + lv];
-      const int k0 = alo + 32 * kv + 8 * kg;
-      v0 = load8(R, d0, ly.r_d, sl, ly.r_s, pt.L, k0);
-      v1 = load8(R, d1, ly.r_d, sl, ly.r_s, pt.L, k0);
-      if constexpr (FP8) {
-        // the tile's 16 ODs lie in one 64-OD scale group
-        const float sc = tl.scale[(((int64_t)c * pt.K + lv) * pt.T + t) * tl.n_ptile + ((16 * j) >> 6)];
-        v0 *= sc;
-        v1 *= sc;
-      }
-    };
-    bf16x8 a;
-    f32x8 v0, v1;
-    fetch(l, ks, a, v0, v1);
+    bf16x8 av;
+    f32x8 v[NT];
+    if constexpr (kAhead) fetch(l, ks, av, v);
     for (int it = 0; it < n_it; ++it) {
       int ln = l, ksn = ks + 1;
       if (ksn == nks) {
@@ -273,28 +290,34 @@ k_adj_mfma(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, Layout ly,
         m &= m - 1;
         ln = m ? __builtin_ctzll(m) : l;
       }
-      bf16x8 an = a;
-      f32x8 v0n = v0, v1n = v1;
-      if (it + 1 < n_it) fetch(ln, ksn, an, v0n, v1n);
-      mma_split(a, v0, acc0);
-      mma_split(a, v1, acc1);
-      a = an;
-      v0 = v0n;
-      v1 = v1n;
+      if constexpr (kAhead) {
+        bf16x8 an = av;
+        f32x8 vn[NT];
+#pragma unroll
+        for (int u = 0; u < NT; ++u) vn[u] = v[u];
+        if (it + 1 < n_it) fetch(ln, ksn, an, vn);
+#pragma unroll
+        for (int u = 0; u < NT; ++u) mma_split(av, v[u], acc[u]);
+        av = an;
+#pragma unroll
+        for (int u = 0; u < NT; ++u) v[u] = vn[u];
+      } else {
+        fetch(l, ks, av, v);
+#pragma unroll
+        for (int u = 0; u < NT; ++u) mma_split(av, v[u], acc[u]);
+      }
       l = ln;
       ks = ksn;
     }
   }
   if (p0 >= pt.P) return;
-  if (d0 >= 0) {
-    q0 = step4(q0, a0, acc0, st);
-    store4(Q + i0, q0, full, valid);
-    if (adagrad) store4(A + i0, a0, full, valid);
-  }
-  if (d1 >= 0) {
-    q1 = step4(q1, a1, acc1, st);
-    store4(Q + i1, q1, full, valid);
-    if (adagrad) store4(A + i1, a1, full, valid);
+#pragma unroll
+  for (int u = 0; u < NT; ++u) {
+    if (d[u] < 0) continue;
+    const int64_t idx = d[u] * ly.q_d + t * ly.q_t + p0;
+    q[u] = step4(q[u], a[u], acc[u], st);
+    store4(Q + idx, q[u], full, valid);
+    if (adagrad) store4(A + idx, a[u], full, valid);
   }
 }
 
@@ -333,30 +356,50 @@ hipError_t update_tiles(const dode_dar* dar, int32_t cluster, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t mfma_chunk_resid(const dode_dar* dar, const ChunkSched& cs, const DayGroups& dg,
-                            const Layout& ly, const float* Q, const float* X, float* R,
-                            hipStream_t s) {
+template <int NT>
+hipError_t launch_fwd(const dode_dar* dar, const ChunkSched& cs, const DayGroups& dg, const Layout& ly,
+                      const float* Q, const float* X, float* R, hipStream_t s) {
   const int64_t nblk = ((int64_t)dg.n * cs.bh * dar->tiles.nLT + 3) / 4;
   const dim3 grid((unsigned)(((nblk + kXcds - 1) / kXcds) * kXcds));
   if (dar->storage == DODE_FP8_E4M3)
-    hipLaunchKernelGGL(k_fwd_mfma<true>, grid, dim3(256), 0, s, dar->pat(), dar->tiles, cs, dg, ly,
-                       Q, X, R);
+    hipLaunchKernelGGL((k_fwd_mfma<true, NT>), grid, dim3(256), 0, s, dar->pat(), dar->tiles, cs, dg,
+                       ly, Q, X, R);
   else
-    hipLaunchKernelGGL(k_fwd_mfma<false>, grid, dim3(256), 0, s, dar->pat(), dar->tiles, cs, dg, ly,
-                       Q, X, R);
+    hipLaunchKernelGGL((k_fwd_mfma<false, NT>), grid, dim3(256), 0, s, dar->pat(), dar->tiles, cs, dg,
+                       ly, Q, X, R);
   return hipGetLastError();
+}
+
+template <int NT>
+hipError_t launch_adj(const dode_dar* dar, const ChunkSched& cs, const DayGroups& dg, const Layout& ly,
+                      const float* R, float* Q, float* A, const StepArgs& st, hipStream_t s) {
+  const int64_t nblk = ((int64_t)dg.n * cs.max_touched * dar->tiles.nPT + 3) / 4;
+  const dim3 grid((unsigned)(((nblk + kXcds - 1) / kXcds) * kXcds));
+  if (dar->storage == DODE_FP8_E4M3)
+    hipLaunchKernelGGL((k_adj_mfma<true, NT>), grid, dim3(256), 0, s, dar->pat(), dar->tiles, cs, dg,
+                       ly, R, Q, A, st);
+  else
+    hipLaunchKernelGGL((k_adj_mfma<false, NT>), grid, dim3(256), 0, s, dar->pat(), dar->tiles, cs, dg,
+                       ly, R, Q, A, st);
+  return hipGetLastError();
+}
+
+hipError_t mfma_chunk_resid(const dode_dar* dar, const ChunkSched& cs, const DayGroups& dg,
+                            const Layout& ly, const float* Q, const float* X, float* R,
+                            hipStream_t s) {
+  switch (dg.tile) {
+    case 16: return launch_fwd<1>(dar, cs, dg, ly, Q, X, R, s);
+    case 64: return launch_fwd<4>(dar, cs, dg, ly, Q, X, R, s);
+    default: return launch_fwd<2>(dar, cs, dg, ly, Q, X, R, s);
+  }
 }
 
 hipError_t mfma_chunk_adj_step(const dode_dar* dar, const ChunkSched& cs, const DayGroups& dg,
                                const Layout& ly, const float* R, float* Q, float* A,
                                const StepArgs& st, hipStream_t s) {
-  const int64_t nblk = ((int64_t)dg.n * cs.max_touched * dar->tiles.nPT + 3) / 4;
-  const dim3 grid((unsigned)(((nblk + kXcds - 1) / kXcds) * kXcds));
-  if (dar->storage == DODE_FP8_E4M3)
-    hipLaunchKernelGGL(k_adj_mfma<true>, grid, dim3(256), 0, s, dar->pat(), dar->tiles, cs, dg, ly,
-                       R, Q, A, st);
-  else
-    hipLaunchKernelGGL(k_adj_mfma<false>, grid, dim3(256), 0, s, dar->pat(), dar->tiles, cs, dg, ly,
-                       R, Q, A, st);
-  return hipGetLastError();
+  switch (dg.tile) {
+    case 16: return launch_adj<1>(dar, cs, dg, ly, R, Q, A, st, s);
+    case 64: return launch_adj<4>(dar, cs, dg, ly, R, Q, A, st, s);
+    default: return launch_adj<2>(dar, cs, dg, ly, R, Q, A, st, s);
+  }
 }

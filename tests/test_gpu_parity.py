@@ -321,3 +321,51 @@ def test_epoch_graph_replays_match_eager(storage):
             torch.cuda.synchronize()
             outs.append(Q.cpu().numpy())
         np.testing.assert_array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("storage", ["bf16", "fp8"])
+def test_day_tile_gives_identical_results(storage):
+    """Each day is its own matrix-core column with the same summation order, so
+    16-, 32- and 64-day waves give the same bits; clusters of 70, 33 and 1 days
+    leave ragged groups at every tile width.  A tuned plan (day_tile 0) runs
+    trial minibatches at load and must reload the state: same bits again.  The
+    64-day run is also checked against the oracle."""
+    inst = make_instance(P=45, L=70, T=24, K=5, sizes=(70, 33, 1), inc=0.15, pattern="corridor",
+                         demand="gamma", noise="mult5", x_dtype="f32", seed=61)
+    say("day tile", storage)
+    E = 8
+    perms = make_perms(62, E, inst.C, inst.H)
+    batch_rows = 6 * inst.L
+    dar = make_dar(inst, storage)
+    X = dev(inst.x, torch.float32)
+    Q0 = torch.zeros((inst.D, inst.T, inst.P), dtype=torch.float32, device="cuda")
+    outs = {}
+    for tile in (16, 32, 64, 0):
+        p = dode.make_params(epochs=E, batch_rows=batch_rows, eta=5.0, day_tile=tile)
+        plan = dode.spgd_plan_create(dar, inst.day_cluster, p, perm=perms, stream=0)
+        dode.spgd_plan_load(plan, X, Q0)
+        info = dode.spgd_plan_info(plan)
+        assert info["day_tile"] == tile if tile else info["day_tile"] in (16, 32, 64)
+        groups = sum(-(-n // info["day_tile"]) for n in (70, 33, 1))
+        assert info["n_day_groups"] == groups and info["minibatch_intervals"] == 6
+        loss = torch.zeros((E, inst.D), dtype=torch.float64, device="cuda")
+        dode.spgd_run(plan, 0, E, loss=loss)
+        Q = torch.empty_like(Q0)
+        A = torch.empty_like(Q0)
+        dode.spgd_plan_store(plan, Q, A)
+        torch.cuda.synchronize()
+        outs[tile] = (Q.cpu().numpy(), A.cpu().numpy(), loss.cpu().numpy())
+    for tile in (16, 64, 0):
+        for a, b in zip(outs[tile], outs[32]):
+            np.testing.assert_array_equal(a, b)
+    Wq = dequantized_values(inst, storage)
+    bh = chunk_h_blocks(inst.L, inst.H, batch_rows)
+    _, _, ho = orc.spgd(inst, inst.x.astype(np.float64), perms, E, bh, optimizer=0, eta=5.0, W=Wq)
+    assert np.max(np.abs(outs[64][2].T - ho) / ho) <= 1e-3
+
+
+def test_day_tile_rejected():
+    inst = make_instance(P=10, L=12, T=6, K=2, sizes=(3,), inc=0.3, seed=63)
+    dar = make_dar(inst, "bf16")
+    with pytest.raises(dode.DodeError, match="day_tile"):
+        dode.spgd_plan_create(dar, inst.day_cluster, dode.make_params(day_tile=48), stream=0)
