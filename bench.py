@@ -45,9 +45,45 @@ FORMS = {
     "bf16": "grouped matrix-core form: bf16 assignment tiles x FP32 demand/residual split into bf16 "
             "hi+lo, v_mfma_f32_16x16x32_bf16, FP32 accumulation, fused FP32 Adagrad step",
     "f32": "plain form: FP32 values, sparse pattern kernels (one thread per output entry)",
-    "fp8": "FP8 e4m3 assignment values, sparse pattern kernels",
+    "fp8": "grouped matrix-core form: FP8 e4m3 assignment tiles (one FP32 scale per 64-OD group, "
+           "widened exactly to bf16) x FP32 demand/residual split into bf16 hi+lo, "
+           "v_mfma_f32_16x16x32_bf16, FP32 accumulation, fused FP32 Adagrad step",
     "f64": "FP64 values, sparse pattern kernels",
 }
+
+
+KERNEL_SOURCES = ("paper_1901_09266_amd/csrc/mfma_kernels.hip",
+                  "paper_1901_09266_amd/csrc/plain_kernels.hip",
+                  "paper_1901_09266_amd/csrc/dode_internal.h")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def counted_traffic(config, form, kernel):
+    """HBM bytes per launch of `kernel` ("fwd" or "adj") from the committed
+    FETCH_SIZE / WRITE_SIZE counter summary of this workload and form, or None
+    when there is none or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_spgd_config{config}_{form}.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            line = line.strip().strip("`")
+            if ":" in line and line.split(":", 1)[0] in ("source_sha256", "fwd_bytes_per_launch",
+                                                         "adj_bytes_per_launch"):
+                k, v = line.split(":", 1)
+                vals[k] = v.strip()
+    if vals.get("source_sha256") != kernel_source_hash() or f"{kernel}_bytes_per_launch" not in vals:
+        return None
+    return float(vals[f"{kernel}_bytes_per_launch"])
 
 
 def launch_bytes(inst, perms, bh, esz, epochs, s_state=4):
@@ -238,8 +274,10 @@ def main():
     k = int(np.argmax(kms[:2]))
     byts = head["fwd_bytes"] if k == 0 else head["adj_bytes"]
     achieved = byts / (kms[k] / 1e3) / 1e9
+    traffic = counted_traffic(args.config, args.form, ("fwd", "adj")[k])
     roof = {"bound": "hbm", "kernel": names[k], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": round(traffic) if traffic is not None else None,
             "avg_launch_us": round(kms[k] / kn[k] * 1e3, 2), "launches": kn[k],
             "bytes_per_launch": round(byts / kn[k]), "kernel_ms_per_step":
             [round(kms[i] / args.steps, 4) for i in range(2)]}
@@ -247,7 +285,7 @@ def main():
     out = {"metric": "SPGD day-gradients/sec", "value": round(value, 1), "unit": "day-gradients/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": {"bf16": "bf16", "f32": "f32", "fp8": "f32", "f64": "f64"}[args.form],
+           "dtype": {"bf16": "bf16", "f32": "f32", "fp8": "bf16", "f64": "f64"}[args.form],
            "data": "synthetic",
            "config": {"workload": f"config {args.config}: " + WORKLOADS[args.config],
                       "form": FORMS[args.form],

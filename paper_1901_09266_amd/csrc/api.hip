@@ -124,8 +124,9 @@ dode_status build_sched(const dode_dims& dm, int32_t C, int32_t E, int32_t bh,
     }
   }
   // departure intervals each minibatch reaches, packed to the largest count seen;
-  // each entry is a descriptor [t, slot of t+0, ..., slot of t+K-1] (slot = position
-  // of interval t+l inside the minibatch, -1 if t+l is not in it)
+  // each entry is a descriptor [t, lag mask (2 words), slot of t+0, ..., slot of
+  // t+K-1] (slot = position of interval t+l inside the minibatch, -1 if t+l is
+  // not in it; mask bit l set when it is)
   std::vector<int32_t> tl;
   tl.assign((size_t)E * hs.nch * C * hs.mt, -1);
   std::vector<char> mark(T);
@@ -147,7 +148,7 @@ dode_status build_sched(const dode_dims& dm, int32_t C, int32_t E, int32_t bh,
         mt_used = std::max(mt_used, n);
       }
     }
-  const size_t dw = (size_t)K + 1;
+  const size_t dw = desc_width(K);
   hs.touched.assign((size_t)E * hs.nch * C * mt_used * dw, -1);
   for (int32_t e = 0; e < E; ++e)
     for (int32_t j = 0; j < hs.nch; ++j)
@@ -158,12 +159,17 @@ dode_status build_sched(const dode_dims& dm, int32_t C, int32_t E, int32_t bh,
           const int32_t t = tl[r * hs.mt + i];
           int32_t* dsc = hs.touched.data() + (r * mt_used + i) * dw;
           if (t < 0) continue;
-          dsc[0] = t;
+          dsc[kDescT] = t;
+          uint64_t mask = 0;
           for (int32_t l = 0; l < K; ++l) {
             const int32_t h = t + l;
             const int32_t sl = h < H ? pos[h] - j * bh : -1;
-            dsc[1 + l] = (sl >= 0 && sl < bh) ? sl : -1;
+            const bool in = sl >= 0 && sl < bh;
+            dsc[kDescSlot + l] = in ? sl : -1;
+            if (in) mask |= 1ull << l;
           }
+          dsc[kDescMask] = (int32_t)(uint32_t)mask;
+          dsc[kDescMask + 1] = (int32_t)(uint32_t)(mask >> 32);
         }
       }
   hs.mt = mt_used;
@@ -345,21 +351,22 @@ void drop_epoch_graph(dode_plan* plan) {
 // groups of at most `tile`.  Replaces the device list and drops a captured
 // epoch graph (it holds the old list).
 dode_status set_day_groups(dode_plan* plan, int32_t tile) {
-  std::vector<int32_t> gc, gf, gn;
+  std::vector<int32_t> gc, gf, gn, gb, gk;
   int32_t start = 0;
   for (int32_t c = 0; c < plan->C; ++c) {
     const int32_t n = plan->cluster_days[c];
+    const int32_t base = (int32_t)gc.size(), ng = (n + tile - 1) / tile;
     for (int32_t f = 0; f < n; f += tile) {
       gc.push_back(c);
       gf.push_back(start + f);
       gn.push_back(std::min<int32_t>(tile, n - f));
+      gb.push_back(base);
+      gk.push_back(ng);
     }
     start += n;
   }
   std::vector<int32_t> buf;
-  buf.insert(buf.end(), gc.begin(), gc.end());
-  buf.insert(buf.end(), gf.begin(), gf.end());
-  buf.insert(buf.end(), gn.begin(), gn.end());
+  for (const auto* v : {&gc, &gf, &gn, &gb, &gk}) buf.insert(buf.end(), v->begin(), v->end());
   drop_epoch_graph(plan);
   if (plan->d_groups) HIP_TRY(hipFree(plan->d_groups));
   plan->d_groups = nullptr;
@@ -936,18 +943,23 @@ dode_status spgd_plan_create(const dode_dar* dar, const int32_t* day_cluster, in
   if (dode_status st = set_day_groups(p, params->day_tile ? params->day_tile : 32)) return st;
   HIP_TRY(up(&p->d_order, order.data(), (size_t)D * 4));
   HIP_TRY(up(&p->d_dc, dc_plan.data(), (size_t)D * 4));
+  // State arrays carry kStatePad zeroed elements past their end: the
+  // matrix-core kernels load whole vectors that may run past a row's end.
   const size_t ss = state_size(dar);
-  HIP_TRY(hipMalloc(&p->d_R, (size_t)D * bh * dm.L * ss));
+  const int64_t nR = (int64_t)D * bh * dm.L + kStatePad, nX = (int64_t)D * dm.H * dm.L + kStatePad;
+  const int64_t nQ = (int64_t)D * dm.T * dm.P + kStatePad;
+  HIP_TRY(hipMalloc(&p->d_R, nR * ss));
   HIP_TRY(hipMalloc(&p->d_part, (size_t)D * dm.H * 8));
   HIP_TRY(hipMalloc(&p->d_loss, (size_t)D * 8));
-  HIP_TRY(hipMalloc(&p->d_X, (size_t)D * dm.H * dm.L * ss));
-  HIP_TRY(hipMalloc(&p->d_Q, (size_t)D * dm.T * dm.P * ss));
-  HIP_TRY(hipMalloc(&p->d_A, (size_t)D * dm.T * dm.P * ss));
+  HIP_TRY(hipMalloc(&p->d_X, nX * ss));
+  HIP_TRY(hipMalloc(&p->d_Q, nQ * ss));
+  HIP_TRY(hipMalloc(&p->d_A, nQ * ss));
   p->ly = Layout{dm.P, (int64_t)D * dm.P, dm.L, (int64_t)D * dm.L, dm.L, (int64_t)D * dm.L};
   hipStream_t s = as_stream(stream);
-  HIP_TRY(fill_zero(is_f64(dar), p->d_X, (int64_t)D * dm.H * dm.L, s));
-  HIP_TRY(fill_zero(is_f64(dar), p->d_Q, (int64_t)D * dm.T * dm.P, s));
-  HIP_TRY(fill_zero(is_f64(dar), p->d_A, (int64_t)D * dm.T * dm.P, s));
+  HIP_TRY(fill_zero(is_f64(dar), p->d_R, nR, s));
+  HIP_TRY(fill_zero(is_f64(dar), p->d_X, nX, s));
+  HIP_TRY(fill_zero(is_f64(dar), p->d_Q, nQ, s));
+  HIP_TRY(fill_zero(is_f64(dar), p->d_A, nQ, s));
   HIP_TRY(hipStreamSynchronize(s));
   p->use_mfma = dar->has_tiles && params->kernel_path == 0;
   p->tune_day_tile = p->use_mfma && params->day_tile == 0;

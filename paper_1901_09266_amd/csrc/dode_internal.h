@@ -133,11 +133,15 @@ struct StepArgs {
 // permutation of the H observation intervals.
 //   perm[c][H]      the epoch's permutation of cluster c
 //   pos[c][H]       its inverse (position of interval h)
-//   touched[c][mt][K+1]  descriptors of the departure intervals the minibatch
-//                   reaches: [t, slot of t+0, ..., slot of t+K-1] (slot -1 when
-//                   t+l is not in the minibatch; t = -1 pads the list)
+//   touched[c][mt][K+3]  descriptors of the departure intervals the minibatch
+//                   reaches: [t, lag mask (low, high word), slot of t+0, ...,
+//                   slot of t+K-1]; bit l of the mask is set when t+l is in the
+//                   minibatch, slot -1 when it is not; t = -1 pads the list
 //   epoch           device epoch counter (graph replays) or nullptr; when set,
 //                   the kernels add (*epoch) * perm_e / touched_e to the pointers
+constexpr int kDescT = 0, kDescMask = 1, kDescSlot = 3;
+__host__ __device__ inline int32_t desc_width(int32_t K) { return K + 3; }
+
 struct ChunkSched {
   const int32_t* perm;
   const int32_t* pos;
@@ -161,15 +165,44 @@ __device__ __forceinline__ ChunkSched resolve_epoch(ChunkSched cs) {
   return cs;
 }
 
-// Groups of up to 32 days of one cluster (two 16-day MFMA column tiles).
-// Plan days are grouped by cluster, so group g holds days first..first+count-1.
+// Groups of up to `tile` days of one cluster (tile/16 MFMA column tiles).
+// Plan days are grouped by cluster, so group g holds days first..first+count-1,
+// and the groups of one cluster are consecutive: cbase[g] is the first group of
+// g's cluster and cgroups[g] the number of groups of that cluster.
 struct DayGroups {
   const int32_t* cluster;   // [n]
   const int32_t* first;     // [n] first plan day of the group
   const int32_t* count;     // [n] 1..tile
+  const int32_t* cbase;     // [n]
+  const int32_t* cgroups;   // [n]
   int32_t n;
   int32_t tile;             // days per group: 16, 32 or 64 (MFMA column tiles of a wave)
 };
+
+// Work item order of the grouped kernels: (cluster, row u, group of the
+// cluster, tile k), k fastest.  All day groups of a cluster that need the same
+// assignment tiles (same cluster and row) run back to back, so the tiles are
+// fetched from HBM about once per XCD and then served by its L2; the rows of
+// consecutive groups are adjacent in the interval-major state.  `per_cluster`
+// is the row count (b_h or the reached-interval count), `n_tiles` the tiles per
+// row.  Returns the group and writes its cluster, u and k.
+__device__ __forceinline__ int decode_item(const DayGroups& dg, int item, int per_cluster,
+                                           int n_tiles, int& c, int& u, int& k) {
+  k = item % n_tiles;
+  const int q = item / n_tiles;            // = per_cluster*g0 + u*ng + (g - g0)
+  const int G = q / per_cluster;           // some group of the item's cluster
+  const int g0 = dg.cbase[G], ng = dg.cgroups[G];
+  c = dg.cluster[G];
+  const int r = q - per_cluster * g0;
+  u = r / ng;
+  return g0 + (r - u * ng);
+}
+
+// Zeroed elements past the end of each plan state array (X, Q, A, R).  The
+// matrix-core kernels read whole 8-float vectors, and the packed tile ranges
+// end at most 31 columns past a row, so a vector may run into the next row or,
+// for the last row, into this padding.
+constexpr int64_t kStatePad = 64;
 
 // Minibatch schedule and scratch of spgd_run (see spgd_plan_create).
 struct dode_plan {
@@ -179,7 +212,7 @@ struct dode_plan {
   StepArgs sa{};
   int32_t* d_perm = nullptr;      // [E][C][H]
   int32_t* d_pos = nullptr;       // [E][C][H]
-  int32_t* d_touched = nullptr;   // [E][nch][C][mt][K+1] reached-interval descriptors
+  int32_t* d_touched = nullptr;   // [E][nch][C][mt][K+3] reached-interval descriptors
   int32_t* d_dc = nullptr;        // [D]
   void* d_R = nullptr;            // [bh][D][L] residual rows of the current minibatch
   double* d_part = nullptr;       // [D][H] loss partials
@@ -189,7 +222,7 @@ struct dode_plan {
   double* d_loss = nullptr;       // [D] loss of the plan's days (plan order)
   int32_t* d_order = nullptr;     // [D] caller day of plan day i (days grouped by cluster)
   Layout ly{};                    // plan layout of X, Q, A, R
-  int32_t* d_groups = nullptr;    // cluster | first | count (n_groups each)
+  int32_t* d_groups = nullptr;    // cluster | first | count | cbase | cgroups (n_groups each)
   int32_t n_groups = 0;
   int32_t day_tile = 32;          // days per group
   bool tune_day_tile = false;     // choose day_tile by timing at the next load
@@ -208,18 +241,19 @@ struct dode_plan {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[3];
 
   DayGroups groups() const {
-    return DayGroups{d_groups, d_groups + n_groups, d_groups + 2 * n_groups, n_groups, day_tile};
+    return DayGroups{d_groups, d_groups + n_groups, d_groups + 2 * n_groups,
+                     d_groups + 3 * n_groups, d_groups + 4 * n_groups, n_groups, day_tile};
   }
   ChunkSched chunk(int32_t e, int32_t j) const {
     const int32_t H = dar->dims.H;
-    const size_t dw = (size_t)dar->dims.K + 1;
+    const size_t dw = desc_width(dar->dims.K);
     return ChunkSched{d_perm + (size_t)e * C * H, d_pos + (size_t)e * C * H,
                       d_touched + ((size_t)e * nch + j) * C * mt * dw, j * bh, bh, mt, nullptr, 0, 0};
   }
   // minibatch j of the epoch held in d_epoch (for graph replays)
   ChunkSched chunk_dev(int32_t j) const {
     const int32_t H = dar->dims.H;
-    const size_t dw = (size_t)dar->dims.K + 1;
+    const size_t dw = desc_width(dar->dims.K);
     return ChunkSched{d_perm, d_pos, d_touched + (size_t)j * C * mt * dw, j * bh, bh, mt, d_epoch,
                       (int64_t)C * H, (int64_t)(nch * C * mt * dw)};
   }

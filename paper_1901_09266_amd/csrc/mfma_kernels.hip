@@ -3,8 +3,10 @@
 //
 // The day batch is the MFMA N dimension: a wave owns 16 rows of the output
 // (16 links in the forward product, 16 ODs in the adjoint) for a group of up
-// to 32 days of one cluster (two 16-column tiles), and walks the packed 16x32
-// k-steps of the assignment blocks it needs with v_mfma_f32_16x16x32_bf16.
+// to 16*NT days of one cluster (NT 16-column tiles), and walks the packed
+// 16x32 k-steps of the assignment blocks it needs with v_mfma_f32_16x16x32_bf16.
+// Every day is its own MFMA column with the same summation order, so results
+// do not depend on NT.
 //
 // Precision: the assignment values are bfloat16 (or OCP E4M3FN codes with one
 // FP32 scale per (lag block, 64-OD group), widened exactly to bfloat16 in
@@ -18,6 +20,11 @@
 // Layouts: the plan's interval-major copies Q, A [T][D][P], X [H][D][L] and the
 // residual rows of the current minibatch R [bh][D][L] (strides in Layout).
 #include "dode_internal.h"
+
+// No fused multiply-add contraction in this file: the FP8 scale product feeds
+// the hi/lo split, and a contraction chosen differently per template
+// instantiation would make the result depend on the day tile.
+#pragma clang fp contract(off)
 
 namespace {
 
@@ -37,23 +44,22 @@ __device__ __forceinline__ int xcd_logical_block(int nblk) {
   return (b % kXcds) * per + b / kXcds;
 }
 
-// 8 consecutive entries [k0, k0+8) of row `row` of day d (strides sd, sr), zero
-// outside [0, n) or for an absent day (d < 0).
-__device__ __forceinline__ f32x8 load8(const float* __restrict__ base, int d, int64_t sd, int row,
-                                       int64_t sr, int n, int k0) {
-  f32x8 v = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  if (d < 0) return v;
-  const float* p = base + (int64_t)d * sd + (int64_t)row * sr + k0;
-  if (k0 + 8 <= n) {
-    const f32x4u a = *reinterpret_cast<const f32x4u*>(p);
-    const f32x4u b = *reinterpret_cast<const f32x4u*>(p + 4);
-    v = f32x8{a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
-  } else {
-#pragma unroll
-    for (int e = 0; e < 8; ++e)
-      if (k0 + e < n) v[e] = p[e];
-  }
-  return v;
+// Operand loads are always full vectors.  Where a row ends inside the vector
+// the load runs into the next row, or into the zeroed tail padding of the
+// array; the assignment entries those lanes meet are zero, so they add
+// nothing.  Only stores are cut at the row end.
+// B operand of one lane: k-step columns 4g..4g+3 and 16+4g..16+4g+3 of its
+// day's row (p points at column 4g), matching the packed tile order; the 16
+// lanes of a day then read two 64-byte runs.
+__device__ __forceinline__ f32x8 load8(const float* __restrict__ p) {
+  const f32x4u a = *reinterpret_cast<const f32x4u*>(p);
+  const f32x4u b = *reinterpret_cast<const f32x4u*>(p + 16);
+  return f32x8{a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
+}
+
+__device__ __forceinline__ f32x4 load4(const float* __restrict__ p) {
+  const f32x4u v = *reinterpret_cast<const f32x4u*>(p);
+  return f32x4{v[0], v[1], v[2], v[3]};
 }
 
 // A operand of k-step `kidx` (element offset kidx*512 of the packed tiles):
@@ -84,18 +90,7 @@ __device__ __forceinline__ void mma_split(const bf16x8& a, const f32x8& v, f32x4
   acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, lo, acc, 0, 0, 0);
 }
 
-// Four consecutive floats; `full` when all four are inside the row, else the
-// first `valid` only (the rest read as zero / are not written).
-__device__ __forceinline__ f32x4 load4(const float* __restrict__ p, bool full, int valid) {
-  if (full) {
-    const f32x4u v = *reinterpret_cast<const f32x4u*>(p);
-    return f32x4{v[0], v[1], v[2], v[3]};
-  }
-  f32x4 v = {0.f, 0.f, 0.f, 0.f};
-  for (int k = 0; k < valid; ++k) v[k] = p[k];
-  return v;
-}
-
+// Four consecutive floats, or the first `valid` when the row ends earlier.
 __device__ __forceinline__ void store4(float* __restrict__ p, const f32x4& v, bool full, int valid) {
   if (full) {
     *reinterpret_cast<f32x4u*>(p) = f32x4u{v[0], v[1], v[2], v[3]};
@@ -106,40 +101,40 @@ __device__ __forceinline__ void store4(float* __restrict__ p, const f32x4& v, bo
 
 // Forward product and residual of the minibatch rows:
 //   R[d][s][a] = sum_l rho_c[l][h-l][a, :] . Q_d[h-l][:] - X_d[h][a],  h = perm[j0+s].
-// One wave per item (day group g, slot s, link tile i), i fastest; 4 items per
-// block; blocks remapped so each XCD walks a contiguous range of day groups.
-// A wave covers NT 16-day column tiles; the (lag, k-step) loop is flattened and,
-// for NT <= 2, its operands are fetched one step ahead.
+// One wave per item (cluster, slot s, day group g, link tile i) in the order of
+// decode_item; 4 items per block; blocks remapped so each XCD walks a
+// contiguous range of items.  A wave covers NT 16-day column tiles; its
+// (lag, k-step) iterations run in batches of kBatch whose operand loads are
+// all issued before the first product, so a batch costs one memory round
+// trip.  Column n of tile u is day first+16u+n; past the group's end it reads
+// day `first` and its result is dropped.
 template <bool FP8, int NT>
 __global__ void __launch_bounds__(256)
 k_fwd_mfma(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, Layout ly,
            const float* __restrict__ Q, const float* __restrict__ X, float* __restrict__ R) {
-  constexpr bool kAhead = NT <= 2;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  constexpr int kBatch = 8 / NT;
+  // the wave index is uniform: everything derived from it lives in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int n_items = dg.n * cs.bh * tl.nLT;
   const int item = xcd_logical_block((n_items + 3) / 4) * 4 + wave;
   if (item >= n_items) return;
-  const int i = item % tl.nLT;
-  const int s = (item / tl.nLT) % cs.bh;
-  const int g = item / (tl.nLT * cs.bh);
+  int c, s, i;
+  const int g = decode_item(dg, item, cs.bh, tl.nLT, c, s, i);
   if (cs.j0 + s >= pt.H) return;
   cs = resolve_epoch(cs);
-  const int c = dg.cluster[g];
   const int h = cs.perm[c * pt.H + cs.j0 + s];
   const int n = lane & 15, kg = lane >> 4;
   const int first = dg.first[g], cnt = dg.count[g];
-  int d[NT];
-#pragma unroll
-  for (int u = 0; u < NT; ++u) d[u] = 16 * u + n < cnt ? first + 16 * u + n : -1;
-  // observations of the output rows, fetched before the product
   const int a0 = 16 * i + 4 * kg;
-  const bool full = a0 + 4 <= pt.L;
-  const int valid = pt.L - a0;
+  bool live[NT];
+  const float* qcol[NT];
   f32x4 x[NT];
 #pragma unroll
   for (int u = 0; u < NT; ++u) {
-    x[u] = f32x4{0.f, 0.f, 0.f, 0.f};
-    if (a0 < pt.L && d[u] >= 0) x[u] = load4(X + d[u] * ly.x_d + h * ly.x_h + a0, full, valid);
+    live[u] = 16 * u + n < cnt;
+    const int64_t du = live[u] ? first + 16 * u + n : first;
+    qcol[u] = Q + du * ly.q_d;
+    x[u] = load4(X + du * ly.x_d + h * ly.x_h + a0);   // observations, fetched first
   }
   // lags with t = h - l inside [0, T)
   const int l_lo = h - pt.T + 1 > 0 ? h - pt.T + 1 : 0;
@@ -151,48 +146,50 @@ k_fwd_mfma(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, Layout ly,
   f32x4 acc[NT];
 #pragma unroll
   for (int u = 0; u < NT; ++u) acc[u] = f32x4{0.f, 0.f, 0.f, 0.f};
-  auto fetch = [&](int it, bf16x8& a, f32x8 (&v)[NT]) {
-    const int l = l_lo + it / nks, ks = it % nks;
-    const int t = h - l;
-    a = load_a<FP8>(tl.Fv, kbase + ((int64_t)l * pt.T + t) * tl.kf_total + ks, lane);
-    const int p0 = plo + 32 * ks + 8 * kg;
+  const bf16x8 zero = __builtin_convertvector(f32x8{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, bf16x8);
+  int l = l_lo, ks = 0;
+  for (int it0 = 0; it0 < n_it; it0 += kBatch) {
+    bf16x8 a[kBatch];
+    f32x8 v[kBatch][NT];
 #pragma unroll
-    for (int u = 0; u < NT; ++u) v[u] = load8(Q, d[u], ly.q_d, t, ly.q_t, pt.P, p0);
-    if constexpr (FP8) {
-      // the lane's 8 ODs lie in one 64-OD scale group (p0 is a multiple of 8)
-      const int grp = min(p0 >> 6, tl.n_ptile - 1);
-      const float sc = tl.scale[(((int64_t)c * pt.K + l) * pt.T + t) * tl.n_ptile + grp];
+    for (int b = 0; b < kBatch; ++b) {
+      const int t = h - l;
+      a[b] = load_a<FP8>(tl.Fv, kbase + ((int64_t)l * pt.T + t) * tl.kf_total + ks, lane);
+      const int p0 = plo + 32 * ks + 4 * kg;
 #pragma unroll
-      for (int u = 0; u < NT; ++u) v[u] *= sc;
-    }
-  };
-  if (n_it > 0) {
-    bf16x8 a;
-    f32x8 v[NT];
-    if constexpr (kAhead) fetch(0, a, v);
-    for (int it = 0; it < n_it; ++it) {
-      if constexpr (kAhead) {
-        bf16x8 an = a;
-        f32x8 vn[NT];
+      for (int u = 0; u < NT; ++u) v[b][u] = load8(qcol[u] + t * ly.q_t + p0);
+      if constexpr (FP8) {
+        // each 4-OD half of the lane lies in one 64-OD scale group (p0 is a
+        // multiple of 4); the two halves may fall in neighbouring groups
+        const float* scl = tl.scale + (((int64_t)c * pt.K + l) * pt.T + t) * tl.n_ptile;
+        const float s0 = scl[min(p0 >> 6, tl.n_ptile - 1)];
+        const float s1 = scl[min((p0 + 16) >> 6, tl.n_ptile - 1)];
 #pragma unroll
-        for (int u = 0; u < NT; ++u) vn[u] = v[u];
-        if (it + 1 < n_it) fetch(it + 1, an, vn);
-#pragma unroll
-        for (int u = 0; u < NT; ++u) mma_split(a, v[u], acc[u]);
-        a = an;
-#pragma unroll
-        for (int u = 0; u < NT; ++u) v[u] = vn[u];
-      } else {
-        fetch(it, a, v);
-#pragma unroll
-        for (int u = 0; u < NT; ++u) mma_split(a, v[u], acc[u]);
+        for (int u = 0; u < NT; ++u) {
+          v[b][u][0] *= s0; v[b][u][1] *= s0; v[b][u][2] *= s0; v[b][u][3] *= s0;
+          v[b][u][4] *= s1; v[b][u][5] *= s1; v[b][u][6] *= s1; v[b][u][7] *= s1;
+        }
+      }
+      // past the last iteration: repeat its loads with a zero operand
+      if (it0 + b >= n_it) a[b] = zero;
+      else if (it0 + b + 1 < n_it && ++ks == nks) {
+        ks = 0;
+        ++l;
       }
     }
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b)
+#pragma unroll
+      for (int u = 0; u < NT; ++u) mma_split(a[b], v[b][u], acc[u]);
   }
   if (a0 >= pt.L) return;
+  const bool full = a0 + 4 <= pt.L;
+  const int valid = pt.L - a0;
 #pragma unroll
   for (int u = 0; u < NT; ++u)
-    if (d[u] >= 0) store4(R + d[u] * ly.r_d + s * ly.r_s + a0, acc[u] - x[u], full, valid);
+    if (live[u])
+      store4(R + (int64_t)(first + 16 * u + n) * ly.r_d + s * ly.r_s + a0, acc[u] - x[u], full,
+             valid);
 }
 
 __device__ __forceinline__ f32x4 step4(f32x4 q, f32x4& a, const f32x4& g, const StepArgs& st) {
@@ -212,109 +209,89 @@ __device__ __forceinline__ f32x4 step4(f32x4 q, f32x4& a, const f32x4& g, const 
 
 // Adjoint of the minibatch and the fused Adagrad step + projection:
 //   g_d[t][p] = sum_{l: t+l in minibatch} rho_c[l][t][:, p] . R_d[slot(t+l)][:]
-// One wave per item (day group g, reached interval index ti, OD tile j), j
-// fastest; same block remapping as the forward kernel.  The demand and
-// accumulator rows are fetched before the product.
+// One wave per item (cluster, reached interval index ti, day group g, OD tile
+// j) in the order of decode_item; same block remapping, batching and day
+// columns as the forward kernel.  The demand and accumulator rows are fetched
+// before the product.
 template <bool FP8, int NT>
 __global__ void __launch_bounds__(256)
 k_adj_mfma(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, Layout ly,
            const float* __restrict__ R, float* __restrict__ Q, float* __restrict__ A, StepArgs st) {
-  constexpr bool kAhead = NT <= 2;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  constexpr int kBatch = 8 / NT;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int n_items = dg.n * cs.max_touched * tl.nPT;
   const int item = xcd_logical_block((n_items + 3) / 4) * 4 + wave;
   if (item >= n_items) return;
-  const int j = item % tl.nPT;
-  const int ti = (item / tl.nPT) % cs.max_touched;
-  const int g = item / (tl.nPT * cs.max_touched);
+  int c, ti, j;
+  const int g = decode_item(dg, item, cs.max_touched, tl.nPT, c, ti, j);
   cs = resolve_epoch(cs);
-  const int c = dg.cluster[g];
-  const int32_t* dsc = cs.touched + ((int64_t)c * cs.max_touched + ti) * (pt.K + 1);
-  const int t = dsc[0];
+  const int32_t* dsc = cs.touched + ((int64_t)c * cs.max_touched + ti) * desc_width(pt.K);
+  const int t = dsc[kDescT];
   if (t < 0) return;
+  // lags whose row block h = t + l is in this minibatch
+  const uint64_t lmask = (uint64_t)(uint32_t)dsc[kDescMask] |
+                         (uint64_t)(uint32_t)dsc[kDescMask + 1] << 32;
   const int n = lane & 15, kg = lane >> 4;
   const int first = dg.first[g], cnt = dg.count[g];
-  int d[NT];
-#pragma unroll
-  for (int u = 0; u < NT; ++u) d[u] = 16 * u + n < cnt ? first + 16 * u + n : -1;
   const int p0 = 16 * j + 4 * kg;
-  const bool full = p0 + 4 <= pt.P;
-  const int valid = pt.P - p0;
   const bool adagrad = st.optimizer == 0;
+  bool live[NT];
+  const float* rcol[NT];
   f32x4 q[NT], a[NT];
 #pragma unroll
   for (int u = 0; u < NT; ++u) {
-    q[u] = f32x4{0.f, 0.f, 0.f, 0.f};
-    a[u] = q[u];
-    if (p0 < pt.P && d[u] >= 0) {
-      const int64_t idx = d[u] * ly.q_d + t * ly.q_t + p0;
-      q[u] = load4(Q + idx, full, valid);
-      if (adagrad) a[u] = load4(A + idx, full, valid);
-    }
+    live[u] = 16 * u + n < cnt;
+    const int64_t du = live[u] ? first + 16 * u + n : first;
+    rcol[u] = R + du * ly.r_d;
+    const int64_t idx = du * ly.q_d + t * ly.q_t + p0;
+    q[u] = load4(Q + idx);
+    a[u] = adagrad ? load4(A + idx) : f32x4{0.f, 0.f, 0.f, 0.f};
   }
-  // lags whose row block h = t + l is in this minibatch, as a bit mask
-  uint64_t lmask = 0;
-  for (int l = 0; l < pt.K; ++l)
-    if (dsc[1 + l] >= 0) lmask |= 1ull << l;
   const int nks = tl.g_ks[j], alo = tl.g_alo[j];
   const int n_it = __popcll(lmask) * nks;
   const int64_t kbase = (int64_t)c * pt.K * pt.T * tl.kg_total + tl.g_koff[j];
   f32x4 acc[NT];
 #pragma unroll
   for (int u = 0; u < NT; ++u) acc[u] = f32x4{0.f, 0.f, 0.f, 0.f};
-  auto fetch = [&](int lv, int kv, bf16x8& av, f32x8 (&v)[NT]) {
-    av = load_a<FP8>(tl.Gv, kbase + ((int64_t)lv * pt.T + t) * tl.kg_total + kv, lane);
-    const int sl = dsc[1 + lv];
-    const int k0 = alo + 32 * kv + 8 * kg;
+  const bf16x8 zero = __builtin_convertvector(f32x8{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, bf16x8);
+  // iteration -> (lag = next set bit of lmask, k-step)
+  uint64_t m = lmask;
+  int l = m ? __builtin_ctzll(m) : 0, ks = 0;
+  for (int it0 = 0; it0 < n_it; it0 += kBatch) {
+    bf16x8 w[kBatch];
+    f32x8 v[kBatch][NT];
 #pragma unroll
-    for (int u = 0; u < NT; ++u) v[u] = load8(R, d[u], ly.r_d, sl, ly.r_s, pt.L, k0);
-    if constexpr (FP8) {
-      // the tile's 16 ODs lie in one 64-OD scale group
-      const float sc = tl.scale[(((int64_t)c * pt.K + lv) * pt.T + t) * tl.n_ptile + ((16 * j) >> 6)];
+    for (int b = 0; b < kBatch; ++b) {
+      w[b] = load_a<FP8>(tl.Gv, kbase + ((int64_t)l * pt.T + t) * tl.kg_total + ks, lane);
+      const int sl = dsc[kDescSlot + l];
+      const int k0 = alo + 32 * ks + 4 * kg;
 #pragma unroll
-      for (int u = 0; u < NT; ++u) v[u] *= sc;
-    }
-  };
-  if (n_it > 0) {
-    // iteration it -> (it / nks)-th set bit of lmask, k-step it % nks
-    uint64_t m = lmask;
-    int l = __builtin_ctzll(m);
-    int ks = 0;
-    bf16x8 av;
-    f32x8 v[NT];
-    if constexpr (kAhead) fetch(l, ks, av, v);
-    for (int it = 0; it < n_it; ++it) {
-      int ln = l, ksn = ks + 1;
-      if (ksn == nks) {
-        ksn = 0;
+      for (int u = 0; u < NT; ++u) v[b][u] = load8(rcol[u] + sl * ly.r_s + k0);
+      if constexpr (FP8) {
+        // the tile's 16 ODs lie in one 64-OD scale group
+        const float sc = tl.scale[(((int64_t)c * pt.K + l) * pt.T + t) * tl.n_ptile + ((16 * j) >> 6)];
+#pragma unroll
+        for (int u = 0; u < NT; ++u) v[b][u] *= sc;
+      }
+      if (it0 + b >= n_it) w[b] = zero;
+      else if (it0 + b + 1 < n_it && ++ks == nks) {
+        ks = 0;
         m &= m - 1;
-        ln = m ? __builtin_ctzll(m) : l;
+        l = __builtin_ctzll(m);
       }
-      if constexpr (kAhead) {
-        bf16x8 an = av;
-        f32x8 vn[NT];
-#pragma unroll
-        for (int u = 0; u < NT; ++u) vn[u] = v[u];
-        if (it + 1 < n_it) fetch(ln, ksn, an, vn);
-#pragma unroll
-        for (int u = 0; u < NT; ++u) mma_split(av, v[u], acc[u]);
-        av = an;
-#pragma unroll
-        for (int u = 0; u < NT; ++u) v[u] = vn[u];
-      } else {
-        fetch(l, ks, av, v);
-#pragma unroll
-        for (int u = 0; u < NT; ++u) mma_split(av, v[u], acc[u]);
-      }
-      l = ln;
-      ks = ksn;
     }
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b)
+#pragma unroll
+      for (int u = 0; u < NT; ++u) mma_split(w[b], v[b][u], acc[u]);
   }
   if (p0 >= pt.P) return;
+  const bool full = p0 + 4 <= pt.P;
+  const int valid = pt.P - p0;
 #pragma unroll
   for (int u = 0; u < NT; ++u) {
-    if (d[u] < 0) continue;
-    const int64_t idx = d[u] * ly.q_d + t * ly.q_t + p0;
+    if (!live[u]) continue;
+    const int64_t idx = (int64_t)(first + 16 * u + n) * ly.q_d + t * ly.q_t + p0;
     q[u] = step4(q[u], a[u], acc[u], st);
     store4(Q + idx, q[u], full, valid);
     if (adagrad) store4(A + idx, a[u], full, valid);

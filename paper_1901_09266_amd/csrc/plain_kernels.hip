@@ -151,7 +151,7 @@ k_chunk_adj_step(DevPat pt, DevVals v, const int32_t* day_cluster, int32_t clust
   if (p >= pt.P) return;
   cs = resolve_epoch(cs);
   const int c = day_cl(day_cluster, cluster, d);
-  const int t = cs.touched[((int64_t)c * cs.max_touched + i) * (pt.K + 1)];
+  const int t = cs.touched[((int64_t)c * cs.max_touched + i) * desc_width(pt.K) + kDescT];
   if (t < 0) return;
   const S g = col_dot_chunk<ST, S>(pt, v, c, t, p, cs.pos + (int64_t)c * pt.H, cs.j0, cs.bh,
                                    R + d * ly.r_d, ly.r_s);

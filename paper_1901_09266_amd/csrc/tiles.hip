@@ -50,12 +50,16 @@ std::vector<Hull> hulls(int32_t n_rows, int32_t n_cols, const std::vector<int32_
 }
 
 // Position of a (row, col) entry inside the packed k-steps of its row tile.
+// Within a 32-wide k-step, lane group g (lanes 16g..16g+15) holds columns
+// 4g..4g+3 (elements 0-3) and 16+4g..16+4g+3 (elements 4-7): the FP32 operand
+// the kernels pair with it is then read as two 64-byte runs per row.
 int64_t packed_pos(int32_t row, int32_t col, const std::vector<Hull>& hs,
                    const std::vector<int32_t>& koff) {
   const int32_t i = row / 16, m = row % 16;
   const int32_t k = col - hs[i].lo;
   const int32_t ks = k / 32, kk = k % 32;
-  const int32_t lane = m + 16 * (kk / 8), e = kk % 8;
+  const int32_t half = kk / 16, g = (kk % 16) / 4;
+  const int32_t lane = m + 16 * g, e = 4 * half + kk % 4;
   return ((int64_t)(koff[i] + ks) * 64 + lane) * 8 + e;
 }
 

@@ -365,7 +365,7 @@ def test_day_tile_gives_identical_results(storage):
 
 
 def test_day_tile_rejected():
-    inst = make_instance(P=10, L=12, T=6, K=2, sizes=(3,), inc=0.3, seed=63)
+    inst = make_instance(P=10, L=12, T=6, K=2, sizes=(3,), inc=0.3, pattern="bernoulli", seed=63)
     dar = make_dar(inst, "bf16")
     with pytest.raises(dode.DodeError, match="day_tile"):
         dode.spgd_plan_create(dar, inst.day_cluster, dode.make_params(day_tile=48), stream=0)
