@@ -190,31 +190,47 @@ def fp64_losses(dode, torch, inst, Qs):
     return out
 
 
-def cpu_baseline(inst, perms_full, sample, target_s=20.0, max_epochs=300):
-    """Time the FP64 oracle on the sample days (all in parallel) for as many
-    epochs as fit in about target_s seconds (calibrated on two epochs)."""
+def cpu_baseline(inst, perms_full, target_s=20.0, epochs=300):
+    """Time the FP64 oracle over `epochs` epochs on a sample of days (the first
+    days of every cluster, all solved in parallel), sized from a two-epoch
+    calibration to take about target_s seconds.  Returns the rate, the sample
+    and the oracle's demand on it."""
     import oracle as orc
     from synth import chunk_h_blocks
-    nthreads = min(len(sample), os.cpu_count() or 1)
-    x64 = inst.x[sample].astype(np.float64)
+    threads = max(1, min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "16"))))
+    bh = chunk_h_blocks(inst.L, inst.H, 8192)
 
     class _Days:
         pass
-    sub = _Days()
-    for k in ("P", "L", "T", "H", "K", "row_ptr", "col_idx", "W", "C"):
-        setattr(sub, k, getattr(inst, k))
-    sub.day_cluster = inst.day_cluster[sample]
-    sub.D = len(sample)
-    bh = chunk_h_blocks(inst.L, inst.H, 8192)
+
+    def subset(days):
+        sub = _Days()
+        for k in ("P", "L", "T", "H", "K", "row_ptr", "col_idx", "W", "C"):
+            setattr(sub, k, getattr(inst, k))
+        sub.day_cluster = inst.day_cluster[days]
+        sub.D = len(days)
+        return sub, inst.x[days].astype(np.float64)
+
+    def first_days(per_cluster):
+        return np.concatenate([np.nonzero(inst.day_cluster == c)[0][:per_cluster]
+                               for c in range(inst.C)])
+
+    cal = first_days(max(1, -(-threads // inst.C)))
+    sub, x64 = subset(cal)
     t0 = time.perf_counter()
-    orc.spgd(sub, x64, perms_full, 2, bh, eta=5.0, record_loss=False, nthreads=nthreads)
-    per_epoch = (time.perf_counter() - t0) / 2
-    E = int(max(2, min(max_epochs, target_s / per_epoch)))
+    orc.spgd(sub, x64, perms_full, 2, bh, eta=5.0, record_loss=False, nthreads=threads)
+    per_day_epoch = (time.perf_counter() - t0) * min(threads, len(cal)) / (2 * len(cal))
+    n_days = target_s * threads / (per_day_epoch * epochs)
+    per_cluster = int(max(1, min(64, round(n_days / inst.C))))
+    E = epochs if per_cluster > 1 or n_days >= inst.C else int(max(2, epochs * n_days / inst.C))
+    sample = first_days(per_cluster)
+    sub, x64 = subset(sample)
+    used = min(threads, len(sample))
     t0 = time.perf_counter()
-    Q, _, _ = orc.spgd(sub, x64, perms_full, E, bh, eta=5.0, record_loss=False, nthreads=nthreads)
+    Q, _, _ = orc.spgd(sub, x64, perms_full, E, bh, eta=5.0, record_loss=False, nthreads=used)
     dt = time.perf_counter() - t0
-    return dict(value=len(sample) * E / dt, seconds=dt, threads=nthreads, epochs=E, sub=sub, x64=x64,
-                Q=Q)
+    return dict(value=len(sample) * E / dt, seconds=dt, threads=used, epochs=E, sub=sub, x64=x64,
+                Q=Q, sample=sample, per_cluster=per_cluster)
 
 
 def main():
@@ -303,8 +319,10 @@ def main():
         sample = np.array([np.nonzero(inst.day_cluster == c)[0][0] for c in range(inst.C)])
         cb = None
         if not args.skip_cpu:
-            cb = cpu_baseline(inst, perms[:E], sample)
-            log(f"oracle: {len(sample)} days x {cb['epochs']} epochs in {cb['seconds']:.1f}s")
+            cb = cpu_baseline(inst, perms[:E], epochs=E)
+            sample = cb["sample"]
+            log(f"oracle: {len(sample)} days x {cb['epochs']} epochs in {cb['seconds']:.1f}s "
+                f"on {cb['threads']} threads")
         E_snap = cb["epochs"] if cb else E
         sols = {f: solve_full(dode, torch, inst, f, perms[:E], E, E_snap, sample) for f in forms}
         L64 = fp64_losses(dode, torch, inst, {f: q for f, (q, _) in sols.items()})
@@ -323,7 +341,8 @@ def main():
                 chk[f]["max_rel_vs_oracle_sample"] = float(np.max(np.abs(lg - lo) / lo))
             out["cpu_baseline"] = {"value": round(cb["value"], 3), "unit": "day-gradients/s",
                                    "cores": cb["threads"], "kind": "oracle",
-                                   "sample": f"{len(sample)} days (first of each cluster) x "
+                                   "sample": f"{len(sample)} days (the first "
+                                             f"{cb['per_cluster']} of each cluster) x "
                                              f"{cb['epochs']} epochs of Algorithm 1 in FP64, "
                                              f"{cb['seconds']:.1f}s"}
         out["equal_loss"] = chk
