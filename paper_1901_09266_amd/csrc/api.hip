@@ -155,10 +155,15 @@ dode_status build_sched(const dode_dims& dm, int32_t C, int32_t E, int32_t bh,
       for (int32_t c = 0; c < C; ++c) {
         const size_t r = ((size_t)e * hs.nch + j) * C + c;
         const int32_t* pos = hs.pos.data() + ((size_t)e * C + c) * H;
-        for (int32_t i = 0; i < mt_used; ++i) {
-          const int32_t t = tl[r * hs.mt + i];
+        // the n reached intervals are spread evenly over the mt_used entries
+        // (padding in between), so any contiguous range of the grouped
+        // kernels' items holds its share of useful work
+        int32_t n = 0;
+        while (n < hs.mt && tl[r * hs.mt + n] >= 0) ++n;
+        for (int32_t k = 0; k < n; ++k) {
+          const int32_t t = tl[r * hs.mt + k];
+          const int32_t i = (int32_t)((int64_t)k * mt_used / n);
           int32_t* dsc = hs.touched.data() + (r * mt_used + i) * dw;
-          if (t < 0) continue;
           dsc[kDescT] = t;
           uint64_t mask = 0;
           for (int32_t l = 0; l < K; ++l) {

@@ -136,7 +136,8 @@ struct StepArgs {
 //   touched[c][mt][K+3]  descriptors of the departure intervals the minibatch
 //                   reaches: [t, lag mask (low, high word), slot of t+0, ...,
 //                   slot of t+K-1]; bit l of the mask is set when t+l is in the
-//                   minibatch, slot -1 when it is not; t = -1 pads the list
+//                   minibatch, slot -1 when it is not.  Entries with t = -1 pad
+//                   the list; they are spread evenly between the used ones.
 //   epoch           device epoch counter (graph replays) or nullptr; when set,
 //                   the kernels add (*epoch) * perm_e / touched_e to the pointers
 constexpr int kDescT = 0, kDescMask = 1, kDescSlot = 3;
