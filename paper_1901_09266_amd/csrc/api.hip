@@ -948,25 +948,32 @@ dode_status spgd_plan_create(const dode_dar* dar, const int32_t* day_cluster, in
   if (dode_status st = set_day_groups(p, params->day_tile ? params->day_tile : 32)) return st;
   HIP_TRY(up(&p->d_order, order.data(), (size_t)D * 4));
   HIP_TRY(up(&p->d_dc, dc_plan.data(), (size_t)D * 4));
-  // State arrays carry kStatePad zeroed elements past their end: the
-  // matrix-core kernels load whole vectors that may run past a row's end.
+  // Plan state layout (Layout): day-blocked rows for the matrix-core path,
+  // plain interval-major rows otherwise; every array carries kStatePad
+  // zeroed elements past its end, and the blocked rows their zero blocks.
+  p->use_mfma = dar->has_tiles && params->kernel_path == 0;
   const size_t ss = state_size(dar);
-  const int64_t nR = (int64_t)D * bh * dm.L + kStatePad, nX = (int64_t)D * dm.H * dm.L + kStatePad;
-  const int64_t nQ = (int64_t)D * dm.T * dm.P + kStatePad;
+  if (p->use_mfma) {
+    const int64_t pb = blocked_row_blocks(dm.P), lb = blocked_row_blocks(dm.L);
+    p->ly = Layout{4, pb * 4 * D, 4, lb * 4 * D, 4, lb * 4 * D, 4 * (int64_t)D, 4 * (int64_t)D,
+                   4 * (int64_t)D};
+  } else {
+    p->ly = Layout{dm.P, (int64_t)D * dm.P, dm.L, (int64_t)D * dm.L, dm.L, (int64_t)D * dm.L, 4, 4, 4};
+  }
+  const int64_t nR = bh * p->ly.r_s + kStatePad, nX = dm.H * p->ly.x_h + kStatePad;
+  const int64_t nQ = dm.T * p->ly.q_t + kStatePad;
   HIP_TRY(hipMalloc(&p->d_R, nR * ss));
   HIP_TRY(hipMalloc(&p->d_part, (size_t)D * dm.H * 8));
   HIP_TRY(hipMalloc(&p->d_loss, (size_t)D * 8));
   HIP_TRY(hipMalloc(&p->d_X, nX * ss));
   HIP_TRY(hipMalloc(&p->d_Q, nQ * ss));
   HIP_TRY(hipMalloc(&p->d_A, nQ * ss));
-  p->ly = Layout{dm.P, (int64_t)D * dm.P, dm.L, (int64_t)D * dm.L, dm.L, (int64_t)D * dm.L};
   hipStream_t s = as_stream(stream);
   HIP_TRY(fill_zero(is_f64(dar), p->d_R, nR, s));
   HIP_TRY(fill_zero(is_f64(dar), p->d_X, nX, s));
   HIP_TRY(fill_zero(is_f64(dar), p->d_Q, nQ, s));
   HIP_TRY(fill_zero(is_f64(dar), p->d_A, nQ, s));
   HIP_TRY(hipStreamSynchronize(s));
-  p->use_mfma = dar->has_tiles && params->kernel_path == 0;
   p->tune_day_tile = p->use_mfma && params->day_tile == 0;
   p->use_graph = params->use_graph != 0;
   HIP_TRY(hipMalloc(&p->d_epoch, 16));
@@ -987,13 +994,17 @@ dode_status spgd_plan_load(dode_plan* plan, const void* X, const void* Q, const 
   const int32_t D = plan->D;
   if (plan->check_finite)
     if (dode_status st = scan_finite(dar, X, (int64_t)D * dm.H * dm.L, s)) return st;
-  HIP_TRY(gather_rows(f64, X, plan->d_X, plan->d_order, D, dm.H, dm.L, false, s));
+  const Layout& ly = plan->ly;
+  HIP_TRY(gather_rows(f64, X, plan->d_X, plan->d_order, D, dm.H, dm.L, ly.x_d, ly.x_h, ly.x_b,
+                      false, s));
   for (int pass = 0; pass < 2; ++pass) {
-    HIP_TRY(gather_rows(f64, Q, plan->d_Q, plan->d_order, D, dm.T, dm.P, true, s));
+    HIP_TRY(gather_rows(f64, Q, plan->d_Q, plan->d_order, D, dm.T, dm.P, ly.q_d, ly.q_t, ly.q_b,
+                        true, s));
     if (A)
-      HIP_TRY(gather_rows(f64, A, plan->d_A, plan->d_order, D, dm.T, dm.P, false, s));
+      HIP_TRY(gather_rows(f64, A, plan->d_A, plan->d_order, D, dm.T, dm.P, ly.q_d, ly.q_t, ly.q_b,
+                          false, s));
     else
-      HIP_TRY(fill_zero(f64, plan->d_A, (int64_t)D * dm.T * dm.P, s));
+      HIP_TRY(fill_zero(f64, plan->d_A, dm.T * ly.q_t, s));
     if (pass == 1 || !plan->tune_day_tile) break;
     // tuning runs minibatches on the loaded state; the second pass reloads it
     if (dode_status st = tune_day_tile(plan, s)) return st;
@@ -1009,8 +1020,12 @@ dode_status spgd_plan_store(const dode_plan* plan, void* Q, void* A, void* strea
   const dode_dims& dm = plan->dar->dims;
   hipStream_t s = as_stream(stream);
   const bool f64 = is_f64(plan->dar);
-  HIP_TRY(scatter_rows(f64, plan->d_Q, Q, plan->d_order, plan->D, dm.T, dm.P, s));
-  if (A) HIP_TRY(scatter_rows(f64, plan->d_A, A, plan->d_order, plan->D, dm.T, dm.P, s));
+  const Layout& ly = plan->ly;
+  HIP_TRY(scatter_rows(f64, plan->d_Q, Q, plan->d_order, plan->D, dm.T, dm.P, ly.q_d, ly.q_t,
+                       ly.q_b, s));
+  if (A)
+    HIP_TRY(scatter_rows(f64, plan->d_A, A, plan->d_order, plan->D, dm.T, dm.P, ly.q_d, ly.q_t,
+                         ly.q_b, s));
   return DODE_OK;
 }
 

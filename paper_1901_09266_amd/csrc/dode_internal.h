@@ -107,19 +107,35 @@ struct dode_routes {
   int32_t* d_buf = nullptr;   // all index arrays above, one allocation
 };
 
-// Element strides of the per-day state arrays.  Entry (day d, row r, col k):
-//   Q, A, G : d*q_d + t*q_t + p      X, Xhat : d*x_d + h*x_h + a
-//   R       : d*r_d + s*r_s + a      (s = minibatch slot, or h for full rows)
-// Caller arrays are day-major (q_d = T*P, q_t = P, ...); a plan keeps its copy
-// interval-major (q_d = P, q_t = D*P, ...) so a minibatch's rows are
-// contiguous across days.
+// Element strides of the per-day state arrays.  Entry (day d, row r, col k)
+// of an array with day stride sd, row stride sr and block stride sb sits at
+//   d*sd + r*sr + (k/4)*sb + k%4
+// (col_at): columns come in blocks of 4.
+//   Q, A, G : (q_d, q_t, q_b), rows t, cols p     X, Xhat : (x_d, x_h, x_b)
+//   R       : (r_d, r_s, r_b), rows = minibatch slot s (or h for full rows)
+// Caller arrays are day-major and contiguous (q_d = T*P, q_t = P, q_b = 4).
+// A plan keeps interval-major copies so a minibatch's rows are contiguous
+// across days: the sparse pattern path uses q_d = P, q_t = D*P, q_b = 4; the
+// matrix-core path uses day-blocked rows, [row][col/4][day][4] with nb
+// blocks per row (q_d = 4, q_b = 4*D, q_t = nb*4*D), so the 16 days of an
+// MFMA column tile read 4 consecutive columns as one 256-byte run.
 struct Layout {
   int64_t q_d, q_t, x_d, x_h, r_d, r_s;
+  int64_t q_b = 4, x_b = 4, r_b = 4;
 };
 
-inline Layout day_major(const dode_dims& dm) {
-  return Layout{(int64_t)dm.T * dm.P, dm.P, (int64_t)dm.H * dm.L, dm.L, (int64_t)dm.H * dm.L, dm.L};
+__host__ __device__ __forceinline__ int64_t col_at(int64_t k, int64_t sb) {
+  return (k >> 2) * sb + (k & 3);
 }
+
+inline Layout day_major(const dode_dims& dm) {
+  return Layout{(int64_t)dm.T * dm.P, dm.P, (int64_t)dm.H * dm.L, dm.L, (int64_t)dm.H * dm.L, dm.L,
+                4, 4, 4};
+}
+
+// Blocks per row of the day-blocked plan layout for n columns: the packed tile
+// ranges reach at most 31 columns past the last one, so 8 zero blocks follow.
+__host__ __device__ inline int64_t blocked_row_blocks(int64_t n) { return (n + 3) / 4 + 8; }
 
 // Optimizer settings as the kernels see them.
 struct StepArgs {
@@ -199,10 +215,7 @@ __device__ __forceinline__ int decode_item(const DayGroups& dg, int item, int pe
   return g0 + (r - u * ng);
 }
 
-// Zeroed elements past the end of each plan state array (X, Q, A, R).  The
-// matrix-core kernels read whole 8-float vectors, and the packed tile ranges
-// end at most 31 columns past a row, so a vector may run into the next row or,
-// for the last row, into this padding.
+// Zeroed elements past the end of each plan state array (X, Q, A, R).
 constexpr int64_t kStatePad = 64;
 
 // Minibatch schedule and scratch of spgd_run (see spgd_plan_create).
@@ -279,12 +292,14 @@ hipError_t plain_apply_rows(const dode_dar* dar, const int32_t* day_cluster, int
 hipError_t plain_adjoint_rows(const dode_dar* dar, const int32_t* day_cluster, int32_t cluster,
                               const Layout& ly, const void* R, void* G, int32_t n_days,
                               hipStream_t s);
-// plan state copies: dst[r][i][k] = src[order[i]][r][k] (gather) and back (scatter);
-// clamp projects onto >= 0 on the way in
+// plan state copies: plan entry (day i, row r, col k) at i*sd + r*sr + col_at(k, sb)
+// = src[order[i]][r][k] (gather) and back (scatter); clamp projects onto >= 0
+// on the way in
 hipError_t gather_rows(bool f64, const void* src, void* dst, const int32_t* order, int32_t D,
-                       int32_t rows, int32_t n, bool clamp, hipStream_t s);
+                       int32_t rows, int32_t n, int64_t sd, int64_t sr, int64_t sb, bool clamp,
+                       hipStream_t s);
 hipError_t scatter_rows(bool f64, const void* src, void* dst, const int32_t* order, int32_t D,
-                        int32_t rows, int32_t n, hipStream_t s);
+                        int32_t rows, int32_t n, int64_t sd, int64_t sr, int64_t sb, hipStream_t s);
 hipError_t fill_zero(bool f64, void* x, int64_t n, hipStream_t s);
 hipError_t permute_loss(const double* src, const int32_t* order, int32_t D, double* dst,
                         hipStream_t s);

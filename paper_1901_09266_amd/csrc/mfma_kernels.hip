@@ -17,8 +17,9 @@
 // ~16 significant bits of the FP32 operand; accumulation is FP32.  The
 // Adagrad step, the projection and the residual are FP32.
 //
-// Layouts: the plan's interval-major copies Q, A [T][D][P], X [H][D][L] and the
-// residual rows of the current minibatch R [bh][D][L] (strides in Layout).
+// Layouts: the plan's day-blocked copies of Q, A (rows t), X (rows h) and the
+// residual rows of the current minibatch R (rows = slots): entry (day d, row
+// r, col k) at d*4 + r*row_stride + (k/4)*4D + k%4 (strides in Layout).
 #include "dode_internal.h"
 
 // No fused multiply-add contraction in this file: the FP8 scale product feeds
@@ -44,16 +45,18 @@ __device__ __forceinline__ int xcd_logical_block(int nblk) {
   return (b % kXcds) * per + b / kXcds;
 }
 
-// Operand loads are always full vectors.  Where a row ends inside the vector
-// the load runs into the next row, or into the zeroed tail padding of the
-// array; the assignment entries those lanes meet are zero, so they add
-// nothing.  Only stores are cut at the row end.
+// Operand loads are always full vectors over the day-blocked plan layout
+// ([row][col/4][day][4], Layout): 4 consecutive columns of one day are 16
+// contiguous bytes, and the 16 days of a column tile follow each other.  Where
+// a tile's columns run past the last one the loads meet the zero blocks that
+// end every row; the assignment entries there are zero as well.  Only stores
+// are cut at the row end.
 // B operand of one lane: k-step columns 4g..4g+3 and 16+4g..16+4g+3 of its
-// day's row (p points at column 4g), matching the packed tile order; the 16
-// lanes of a day then read two 64-byte runs.
-__device__ __forceinline__ f32x8 load8(const float* __restrict__ p) {
+// day (p points at column 4g; the second half is 4 blocks further), matching
+// the packed tile order.
+__device__ __forceinline__ f32x8 load8(const float* __restrict__ p, int64_t sb) {
   const f32x4u a = *reinterpret_cast<const f32x4u*>(p);
-  const f32x4u b = *reinterpret_cast<const f32x4u*>(p + 16);
+  const f32x4u b = *reinterpret_cast<const f32x4u*>(p + 4 * sb);
   return f32x8{a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
 }
 
@@ -134,7 +137,7 @@ k_fwd_mfma(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, Layout ly,
     live[u] = 16 * u + n < cnt;
     const int64_t du = live[u] ? first + 16 * u + n : first;
     qcol[u] = Q + du * ly.q_d;
-    x[u] = load4(X + du * ly.x_d + h * ly.x_h + a0);   // observations, fetched first
+    x[u] = load4(X + du * ly.x_d + h * ly.x_h + (a0 >> 2) * ly.x_b);   // observations first
   }
   // lags with t = h - l inside [0, T)
   const int l_lo = h - pt.T + 1 > 0 ? h - pt.T + 1 : 0;
@@ -157,7 +160,7 @@ k_fwd_mfma(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, Layout ly,
       a[b] = load_a<FP8>(tl.Fv, kbase + ((int64_t)l * pt.T + t) * tl.kf_total + ks, lane);
       const int p0 = plo + 32 * ks + 4 * kg;
 #pragma unroll
-      for (int u = 0; u < NT; ++u) v[b][u] = load8(qcol[u] + t * ly.q_t + p0);
+      for (int u = 0; u < NT; ++u) v[b][u] = load8(qcol[u] + t * ly.q_t + (p0 >> 2) * ly.q_b, ly.q_b);
       if constexpr (FP8) {
         // each 4-OD half of the lane lies in one 64-OD scale group (p0 is a
         // multiple of 4); the two halves may fall in neighbouring groups
@@ -188,8 +191,8 @@ k_fwd_mfma(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, Layout ly,
 #pragma unroll
   for (int u = 0; u < NT; ++u)
     if (live[u])
-      store4(R + (int64_t)(first + 16 * u + n) * ly.r_d + s * ly.r_s + a0, acc[u] - x[u], full,
-             valid);
+      store4(R + (int64_t)(first + 16 * u + n) * ly.r_d + s * ly.r_s + (a0 >> 2) * ly.r_b,
+             acc[u] - x[u], full, valid);
 }
 
 __device__ __forceinline__ f32x4 step4(f32x4 q, f32x4& a, const f32x4& g, const StepArgs& st) {
@@ -243,7 +246,7 @@ k_adj_mfma(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, Layout ly,
     live[u] = 16 * u + n < cnt;
     const int64_t du = live[u] ? first + 16 * u + n : first;
     rcol[u] = R + du * ly.r_d;
-    const int64_t idx = du * ly.q_d + t * ly.q_t + p0;
+    const int64_t idx = du * ly.q_d + t * ly.q_t + (p0 >> 2) * ly.q_b;
     q[u] = load4(Q + idx);
     a[u] = adagrad ? load4(A + idx) : f32x4{0.f, 0.f, 0.f, 0.f};
   }
@@ -266,7 +269,7 @@ k_adj_mfma(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, Layout ly,
       const int sl = dsc[kDescSlot + l];
       const int k0 = alo + 32 * ks + 4 * kg;
 #pragma unroll
-      for (int u = 0; u < NT; ++u) v[b][u] = load8(rcol[u] + sl * ly.r_s + k0);
+      for (int u = 0; u < NT; ++u) v[b][u] = load8(rcol[u] + sl * ly.r_s + (k0 >> 2) * ly.r_b, ly.r_b);
       if constexpr (FP8) {
         // the tile's 16 ODs lie in one 64-OD scale group
         const float sc = tl.scale[(((int64_t)c * pt.K + l) * pt.T + t) * tl.n_ptile + ((16 * j) >> 6)];
@@ -291,7 +294,7 @@ k_adj_mfma(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, Layout ly,
 #pragma unroll
   for (int u = 0; u < NT; ++u) {
     if (!live[u]) continue;
-    const int64_t idx = (int64_t)(first + 16 * u + n) * ly.q_d + t * ly.q_t + p0;
+    const int64_t idx = (int64_t)(first + 16 * u + n) * ly.q_d + t * ly.q_t + (p0 >> 2) * ly.q_b;
     q[u] = step4(q[u], a[u], acc[u], st);
     store4(Q + idx, q[u], full, valid);
     if (adagrad) store4(A + idx, a[u], full, valid);

@@ -85,7 +85,7 @@ __device__ double block_max(double v, double* sh) {
 // Row (h, a) of rho_c applied to q_d:  sum_l sum_{p in row a} W[l][h-l][a,p] q[h-l][p].
 template <int ST, typename S>
 __device__ __forceinline__ S row_dot(const DevPat& pt, const DevVals& v, int c, int h, int a,
-                                     const S* q, int64_t q_t) {
+                                     const S* q, int64_t q_t, int64_t q_b) {
   S acc = 0;
   const int32_t j0 = pt.row_ptr[a], j1 = pt.row_ptr[a + 1];
   for (int l = 0; l < pt.K; ++l) {
@@ -97,7 +97,8 @@ __device__ __forceinline__ S row_dot(const DevPat& pt, const DevVals& v, int c, 
     const S* qt = q + (int64_t)t * q_t;
     for (int32_t j = j0; j < j1; ++j) {
       const int p = pt.col[j];
-      acc += static_cast<S>(Load<ST>::get(v.W, base + j, v.scale, sbase + (p >> 6))) * qt[p];
+      acc += static_cast<S>(Load<ST>::get(v.W, base + j, v.scale, sbase + (p >> 6))) *
+             qt[col_at(p, q_b)];
     }
   }
   return acc;
@@ -108,7 +109,7 @@ __device__ __forceinline__ S row_dot(const DevPat& pt, const DevVals& v, int c, 
 template <int ST, typename S>
 __device__ __forceinline__ S col_dot_chunk(const DevPat& pt, const DevVals& v, int c, int t, int p,
                                            const int32_t* pos_c, int32_t first, int32_t bh,
-                                           const S* Rd, int64_t r_s) {
+                                           const S* Rd, int64_t r_s, int64_t r_b) {
   S acc = 0;
   const int32_t k0 = pt.col_ptr[p], k1 = pt.col_ptr[p + 1];
   for (int l = 0; l < pt.K; ++l) {
@@ -120,7 +121,7 @@ __device__ __forceinline__ S col_dot_chunk(const DevPat& pt, const DevVals& v, i
     const int64_t si = (c * (int64_t)pt.K * pt.T + (int64_t)l * pt.T + t) * v.n_ptile + (p >> 6);
     const S* r = Rd + (int64_t)s * r_s;
     for (int32_t jj = k0; jj < k1; ++jj)
-      acc += static_cast<S>(Load<ST>::get(v.WT, base + jj, v.scale, si)) * r[pt.row[jj]];
+      acc += static_cast<S>(Load<ST>::get(v.WT, base + jj, v.scale, si)) * r[col_at(pt.row[jj], r_b)];
   }
   return acc;
 }
@@ -137,8 +138,8 @@ k_chunk_resid(DevPat pt, DevVals v, const int32_t* day_cluster, int32_t cluster,
   const int c = day_cl(day_cluster, cluster, d);
   if (cs.j0 + s >= pt.H) return;
   const int h = cs.perm[c * pt.H + cs.j0 + s];
-  const S xhat = row_dot<ST, S>(pt, v, c, h, a, Q + d * ly.q_d, ly.q_t);
-  R[d * ly.r_d + s * ly.r_s + a] = xhat - X[d * ly.x_d + h * ly.x_h + a];
+  const S xhat = row_dot<ST, S>(pt, v, c, h, a, Q + d * ly.q_d, ly.q_t, ly.q_b);
+  R[d * ly.r_d + s * ly.r_s + col_at(a, ly.r_b)] = xhat - X[d * ly.x_d + h * ly.x_h + col_at(a, ly.x_b)];
 }
 
 template <int ST, typename S>
@@ -154,8 +155,8 @@ k_chunk_adj_step(DevPat pt, DevVals v, const int32_t* day_cluster, int32_t clust
   const int t = cs.touched[((int64_t)c * cs.max_touched + i) * desc_width(pt.K) + kDescT];
   if (t < 0) return;
   const S g = col_dot_chunk<ST, S>(pt, v, c, t, p, cs.pos + (int64_t)c * pt.H, cs.j0, cs.bh,
-                                   R + d * ly.r_d, ly.r_s);
-  const int64_t idx = d * ly.q_d + t * ly.q_t + p;
+                                   R + d * ly.r_d, ly.r_s, ly.r_b);
+  const int64_t idx = d * ly.q_d + t * ly.q_t + col_at(p, ly.q_b);
   S q = Q[idx];
   if (st.optimizer == 0) {
     const S acc = A[idx] + g * g;
@@ -178,8 +179,8 @@ k_apply_rows(DevPat pt, DevVals v, const int32_t* day_cluster, int32_t cluster, 
   const S* q = Q + d * ly.q_d;
   double ss = 0.0;
   for (int a = threadIdx.x; a < pt.L; a += kRedBlock) {
-    S val = row_dot<ST, S>(pt, v, c, h, a, q, ly.q_t);
-    const int64_t o = d * ly.x_d + h * ly.x_h + a;
+    S val = row_dot<ST, S>(pt, v, c, h, a, q, ly.q_t, ly.q_b);
+    const int64_t o = d * ly.x_d + h * ly.x_h + col_at(a, ly.x_b);
     if (X) val -= X[o];
     if (out) out[o] = val;
     ss += static_cast<double>(val) * static_cast<double>(val);
@@ -198,7 +199,8 @@ k_adjoint_rows(DevPat pt, DevVals v, const int32_t* day_cluster, int32_t cluster
   const int c = day_cl(day_cluster, cluster, d);
   const S* Rd = R + d * ly.r_d;
   for (int p = threadIdx.x; p < pt.P; p += kColsBlock)
-    G[d * ly.q_d + t * ly.q_t + p] = col_dot_chunk<ST, S>(pt, v, c, t, p, nullptr, 0, pt.H, Rd, ly.r_s);
+    G[d * ly.q_d + t * ly.q_t + col_at(p, ly.q_b)] =
+        col_dot_chunk<ST, S>(pt, v, c, t, p, nullptr, 0, pt.H, Rd, ly.r_s, ly.r_b);
 }
 
 __global__ void k_sum_partials(const double* __restrict__ part, int32_t n_per, int32_t n_days,
@@ -409,23 +411,23 @@ namespace {
 // dst[r][i][k] = src[order[i]][r][k]; block (i, r), threads over k.
 template <typename S>
 __global__ void k_gather(const S* __restrict__ src, S* __restrict__ dst, const int32_t* order,
-                         int32_t D, int32_t rows, int32_t n, int clamp) {
+                         int32_t rows, int32_t n, int64_t sd, int64_t sr, int64_t sb, int clamp) {
   const int i = blockIdx.x, r = blockIdx.y;
   const S* a = src + ((int64_t)order[i] * rows + r) * n;
-  S* b = dst + ((int64_t)r * D + i) * n;
+  S* b = dst + (int64_t)i * sd + (int64_t)r * sr;
   for (int k = threadIdx.x; k < n; k += blockDim.x) {
     const S v = a[k];
-    b[k] = clamp ? (v > S(0) ? v : S(0)) : v;
+    b[col_at(k, sb)] = clamp ? (v > S(0) ? v : S(0)) : v;
   }
 }
 
 template <typename S>
 __global__ void k_scatter(const S* __restrict__ src, S* __restrict__ dst, const int32_t* order,
-                          int32_t D, int32_t rows, int32_t n) {
+                          int32_t rows, int32_t n, int64_t sd, int64_t sr, int64_t sb) {
   const int i = blockIdx.x, r = blockIdx.y;
-  const S* a = src + ((int64_t)r * D + i) * n;
+  const S* a = src + (int64_t)i * sd + (int64_t)r * sr;
   S* b = dst + ((int64_t)order[i] * rows + r) * n;
-  for (int k = threadIdx.x; k < n; k += blockDim.x) b[k] = a[k];
+  for (int k = threadIdx.x; k < n; k += blockDim.x) b[k] = a[col_at(k, sb)];
 }
 
 template <typename S>
@@ -447,26 +449,27 @@ __global__ void k_permute_loss(const double* __restrict__ src, const int32_t* __
 }  // namespace
 
 hipError_t gather_rows(bool f64, const void* src, void* dst, const int32_t* order, int32_t D,
-                       int32_t rows, int32_t n, bool clamp, hipStream_t s) {
+                       int32_t rows, int32_t n, int64_t sd, int64_t sr, int64_t sb, bool clamp,
+                       hipStream_t s) {
   const dim3 grid(D, rows);
   if (f64)
     hipLaunchKernelGGL(k_gather<double>, grid, dim3(256), 0, s, static_cast<const double*>(src),
-                       static_cast<double*>(dst), order, D, rows, n, (int)clamp);
+                       static_cast<double*>(dst), order, rows, n, sd, sr, sb, (int)clamp);
   else
     hipLaunchKernelGGL(k_gather<float>, grid, dim3(256), 0, s, static_cast<const float*>(src),
-                       static_cast<float*>(dst), order, D, rows, n, (int)clamp);
+                       static_cast<float*>(dst), order, rows, n, sd, sr, sb, (int)clamp);
   return hipGetLastError();
 }
 
 hipError_t scatter_rows(bool f64, const void* src, void* dst, const int32_t* order, int32_t D,
-                        int32_t rows, int32_t n, hipStream_t s) {
+                        int32_t rows, int32_t n, int64_t sd, int64_t sr, int64_t sb, hipStream_t s) {
   const dim3 grid(D, rows);
   if (f64)
     hipLaunchKernelGGL(k_scatter<double>, grid, dim3(256), 0, s, static_cast<const double*>(src),
-                       static_cast<double*>(dst), order, D, rows, n);
+                       static_cast<double*>(dst), order, rows, n, sd, sr, sb);
   else
     hipLaunchKernelGGL(k_scatter<float>, grid, dim3(256), 0, s, static_cast<const float*>(src),
-                       static_cast<float*>(dst), order, D, rows, n);
+                       static_cast<float*>(dst), order, rows, n, sd, sr, sb);
   return hipGetLastError();
 }
 
