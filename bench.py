@@ -161,10 +161,20 @@ def solve_full(dode, torch, inst, form, perms_full, E, E_snap, sample):
     plan = dode.spgd_plan_create(dar, inst.day_cluster, p, perm=perms_full, stream=0)
     dode.spgd_plan_load(plan, X, Q, A)
     t0 = time.time()
-    dode.spgd_run(plan, 0, E_snap)
+
+    def run(e0, e1, step=25):
+        # in pieces, with a progress line per piece
+        for a in range(e0, e1, step):
+            b = min(e1, a + step)
+            dode.spgd_run(plan, a, b - a)
+            torch.cuda.synchronize()
+            if time.time() - t0 > 20:
+                log(f"{form}: {b}/{E} epochs, {time.time() - t0:.1f}s")
+
+    run(0, E_snap)
     dode.spgd_plan_store(plan, Q)
     snap = Q[torch.as_tensor(sample, device="cuda")].double().cpu().numpy()
-    dode.spgd_run(plan, E_snap, E - E_snap)
+    run(E_snap, E)
     dode.spgd_plan_store(plan, Q)
     torch.cuda.synchronize()
     log(f"{form}: full {E}-epoch solve in {time.time() - t0:.2f}s")
@@ -265,7 +275,7 @@ def main():
         torch.cuda.synchronize()
         del a, b
     t0 = time.time()
-    inst = make_config(args.config)
+    inst = make_config(args.config, progress=lambda m: log(f"generating: {m} ({time.time() - t0:.0f}s)"))
     log(f"config {args.config}: D={inst.D} C={inst.C} nnz={inst.nnz} generated in {time.time() - t0:.1f}s")
     bh = chunk_h_blocks(inst.L, inst.H, 8192)
     E_total = args.warmup + 2 * args.steps

@@ -107,15 +107,16 @@ __device__ __forceinline__ void store4(float* __restrict__ p, const f32x4& v, bo
 // One wave per item (cluster, slot s, day group g, link tile i) in the order of
 // decode_item; 4 items per block; blocks remapped so each XCD walks a
 // contiguous range of items.  A wave covers NT 16-day column tiles; its
-// (lag, k-step) iterations run in batches of kBatch whose operand loads are
-// all issued before the first product, so a batch costs one memory round
+// (lag, k-step) iterations run in batches of kBatch k-steps (3 for 32-day
+// waves, which keeps 4 waves per SIMD; 8/NT otherwise) whose operand loads
+// are all issued before the first product, so a batch costs one memory round
 // trip.  Column n of tile u is day first+16u+n; past the group's end it reads
 // day `first` and its result is dropped.
 template <bool FP8, int NT>
 __global__ void __launch_bounds__(256)
 k_fwd_mfma(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, Layout ly,
            const float* __restrict__ Q, const float* __restrict__ X, float* __restrict__ R) {
-  constexpr int kBatch = 8 / NT;
+  constexpr int kBatch = NT == 2 ? 3 : 8 / NT;
   // the wave index is uniform: everything derived from it lives in scalar registers
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int n_items = dg.n * cs.bh * tl.nLT;
@@ -220,7 +221,7 @@ template <bool FP8, int NT>
 __global__ void __launch_bounds__(256)
 k_adj_mfma(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, Layout ly,
            const float* __restrict__ R, float* __restrict__ Q, float* __restrict__ A, StepArgs st) {
-  constexpr int kBatch = 8 / NT;
+  constexpr int kBatch = NT == 2 ? 3 : 8 / NT;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int n_items = dg.n * cs.max_touched * tl.nPT;
   const int item = xcd_logical_block((n_items + 3) / 4) * 4 + wave;

@@ -244,7 +244,9 @@ def _observe(P, L, T, H, K, row_ptr, col_idx, Wc, Q, band=None):
 
 def make_instance(P, L, T, K, sizes, inc, pattern="corridor", demand="gamma", noise="mult5",
                   x_dtype="f32", seed=BASE_SEED, H=None, planted_zero_frac=0.0, keep_x0=False,
-                  **_ignored):
+                  progress=None, **_ignored):
+    """Seeded synthetic instance; `progress(msg)`, when given, is called after
+    each generation stage (large instances take minutes)."""
     H = T if H is None else H
     rng = np.random.Generator(np.random.PCG64(seed))
     S = _incidence(rng, L, P, inc, pattern)
@@ -252,6 +254,8 @@ def make_instance(P, L, T, K, sizes, inc, pattern="corridor", demand="gamma", no
     nnz = col_idx.shape[0]
     C = len(sizes)
     W = [_lag_ratios(rng, K, T, H, nnz) for _ in range(C)]
+    if progress:
+        progress(f"lag ratios of {C} clusters ({nnz} pattern entries)")
     D = int(sum(sizes))
     day_cluster = np.repeat(np.arange(C, dtype=np.int32), sizes)
     if demand == "uniform50":
@@ -265,6 +269,8 @@ def make_instance(P, L, T, K, sizes, inc, pattern="corridor", demand="gamma", no
         qstar[rng.random(qstar.shape) < planted_zero_frac] = 0.0
     big = K * T * L * P > 2_000_000
     band = _BandCSR(P, L, T, H, K, row_ptr, col_idx) if big else None
+    if progress and big:
+        progress("band matrix layout")
     keep = keep_x0 or not big
     x0 = np.empty((D, H, L)) if keep else None
     x = np.empty((D, H, L), dtype=np.float32 if x_dtype == "f32" else np.float64)
@@ -283,13 +289,15 @@ def make_instance(P, L, T, K, sizes, inc, pattern="corridor", demand="gamma", no
         np.maximum(x0c, 0.0, out=x0c)
         x[d] = x0c
         del x0c
+        if progress:
+            progress(f"observations of cluster {c + 1}/{C}")
     return Instance(P=P, L=L, T=T, H=H, K=K, sizes=tuple(int(s) for s in sizes),
                     day_cluster=day_cluster, row_ptr=row_ptr, col_idx=col_idx, W=W,
                     qstar=qstar, x0=x0, x=x, seed=seed,
                     meta=dict(inc=inc, pattern=pattern, demand=demand, noise=noise))
 
 
-def make_config(cid: int, sizes=None, pattern=None, seed=None) -> Instance:
+def make_config(cid: int, sizes=None, pattern=None, seed=None, progress=None) -> Instance:
     """Instance for one benchmark configuration (optionally with fewer days or
     the Bernoulli stress pattern).  Seed = 190109266 + 100 * config id."""
     cfg = dict(CONFIGS[cid])
@@ -298,7 +306,7 @@ def make_config(cid: int, sizes=None, pattern=None, seed=None) -> Instance:
     if pattern is not None:
         cfg["pattern"] = pattern
     s = BASE_SEED + 100 * cid if seed is None else seed
-    inst = make_instance(seed=s, **cfg)
+    inst = make_instance(seed=s, progress=progress, **cfg)
     inst.meta.update(config=cid, epochs=cfg["epochs"], batch_rows=cfg["batch_rows"],
                      optimizer=cfg["optimizer"], eta=cfg["eta"])
     return inst
