@@ -87,14 +87,19 @@ typedef struct {
                           wave (the GEMM N dimension): 16, 32 or 64; 0 = let
                           spgd_plan_load time the three and keep the fastest
                           (results are the same bits for every choice) */
+  int32_t refine_steps;/* full-batch refinement steps after the minibatches of
+                          every epoch: each is one step of Algorithm 1 with all
+                          H intervals as its minibatch, computed with the
+                          corrected values of an FP8 assignment (needs a dar
+                          built with DODE_DAR_CORRECTION); 0 = none */
 } dode_spgd_params;
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* dode_last_error(void);
 
 /* Fill p with the defaults: epochs 300, batch_rows 8192, eta 5, eps 1e-10,
- * Adagrad, check_finite 1, kernel_path 0, use_graph 1, day_tile 32 (section
- * "Goodness of fit" gives E, b and eta). */
+ * Adagrad, check_finite 1, kernel_path 0, use_graph 1, day_tile 32,
+ * refine_steps 0 (section "Goodness of fit" gives E, b and eta). */
 void dode_spgd_defaults(dode_spgd_params* p);
 
 /*
@@ -112,6 +117,20 @@ void dode_spgd_defaults(dode_spgd_params* p);
 dode_status dar_create(const dode_dims* dims, int32_t n_clusters, const int32_t* row_ptr,
                        const int32_t* col_idx, const double* const* values, dode_dtype storage,
                        void* stream, dode_dar** out);
+
+/*
+ * dar_create with options.  flags is 0 or DODE_DAR_CORRECTION: for FP8
+ * storage, also keep bfloat16 correction tiles c = bf16(w - h), where
+ * h = bf16(scale * e4m3(w / scale)) is the FP8 value as the kernels expand it,
+ * so that h + c matches w to about 2^-13 relative; refinement steps
+ * (dode_spgd_params.refine_steps) multiply with h + c.  dar_set_values is not
+ * supported on such a handle (DODE_ERR_UNSUPPORTED).  DODE_ERR_ARG for a flag
+ * that does not apply to the storage type.
+ */
+#define DODE_DAR_CORRECTION 1
+dode_status dar_create_ex(const dode_dims* dims, int32_t n_clusters, const int32_t* row_ptr,
+                          const int32_t* col_idx, const double* const* values,
+                          dode_dtype storage, int32_t flags, void* stream, dode_dar** out);
 
 /* Free a handle (NULL is a no-op).  The caller must have finished every call
  * that uses it. */

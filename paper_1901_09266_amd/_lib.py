@@ -23,7 +23,8 @@ DODE_F64, DODE_F32, DODE_BF16, DODE_FP8_E4M3 = range(4)
 STORAGE = {"f64": DODE_F64, "f32": DODE_F32, "bf16": DODE_BF16, "fp8": DODE_FP8_E4M3}
 
 # Every symbol include/dode.h declares (checked by the CPU test suite).
-EXPORTS = ["dode_last_error", "dode_spgd_defaults", "dar_create", "dar_destroy", "dar_info",
+EXPORTS = ["dode_last_error", "dode_spgd_defaults", "dar_create", "dar_create_ex", "dar_destroy",
+           "dar_info",
            "dar_set_values", "dode_apply", "dode_loss", "dode_grad", "dode_metrics", "spgd_step",
            "spgd_solve", "spgd_plan_create", "spgd_plan_destroy", "spgd_plan_load",
            "spgd_plan_store", "spgd_run", "spgd_plan_timing", "spgd_plan_info",
@@ -47,7 +48,8 @@ class SpgdParams(ctypes.Structure):
     _fields_ = [("epochs", ctypes.c_int32), ("batch_rows", ctypes.c_int32), ("eta", ctypes.c_double),
                 ("eps", ctypes.c_double), ("optimizer", ctypes.c_int32),
                 ("check_finite", ctypes.c_int32), ("kernel_path", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("day_tile", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("day_tile", ctypes.c_int32),
+                ("refine_steps", ctypes.c_int32)]
 
 
 _lib = None
@@ -67,6 +69,7 @@ def lib():
         L.dode_spgd_defaults.argtypes = [P(SpgdParams)]
         L.dode_spgd_defaults.restype = None
         L.dar_create.argtypes = [P(Dims), i32, P(i32), P(i32), P(P(dbl)), i32, vp, P(vp)]
+        L.dar_create_ex.argtypes = [P(Dims), i32, P(i32), P(i32), P(P(dbl)), i32, i32, vp, P(vp)]
         L.dar_destroy.argtypes = [vp]
         L.dar_info.argtypes = [vp, P(Dims), P(i32), P(i64), P(i32), P(i64)]
         L.dar_set_values.argtypes = [vp, i32, vp, vp]
@@ -133,12 +136,14 @@ def spgd_defaults() -> SpgdParams:
 
 
 def make_params(epochs=300, batch_rows=8192, eta=5.0, eps=1e-10, optimizer=0, check_finite=1,
-                kernel_path=0, use_graph=1, day_tile=32):
+                kernel_path=0, use_graph=1, day_tile=32, refine_steps=0):
     """kernel_path 0 = fastest for the storage type, 1 = sparse pattern kernels;
     use_graph 1 = replay one captured hipGraph per epoch; day_tile = days per
-    matrix-core wave (16, 32 or 64, or 0 to time them at load and keep the fastest)."""
+    matrix-core wave (16, 32 or 64, or 0 to time them at load and keep the fastest);
+    refine_steps = full-batch steps per epoch on corrected FP8 values."""
     return SpgdParams(int(epochs), int(batch_rows), float(eta), float(eps), int(optimizer),
-                      int(check_finite), int(kernel_path), int(use_graph), int(day_tile))
+                      int(check_finite), int(kernel_path), int(use_graph), int(day_tile),
+                      int(refine_steps))
 
 
 class Dar:
@@ -167,8 +172,13 @@ class Dar:
             pass
 
 
-def dar_create(P, L, T, H, K, row_ptr, col_idx, values, storage="f32", stream=None) -> Dar:
-    """values: list of C float64 arrays [K][T][nnz] (host)."""
+DAR_CORRECTION = 1
+
+
+def dar_create(P, L, T, H, K, row_ptr, col_idx, values, storage="f32", correction=False,
+               stream=None) -> Dar:
+    """values: list of C float64 arrays [K][T][nnz] (host).  correction (FP8
+    storage): also keep the bf16 correction tiles used by refinement steps."""
     st = STORAGE[storage] if isinstance(storage, str) else int(storage)
     rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
     ci = np.ascontiguousarray(col_idx, dtype=np.int32)
@@ -181,10 +191,11 @@ def dar_create(P, L, T, H, K, row_ptr, col_idx, values, storage="f32", stream=No
         *[v.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for v in vals])
     dims = Dims(P, L, T, H, K)
     out = ctypes.c_void_p()
-    _check(lib().dar_create(ctypes.byref(dims), len(vals),
-                            rp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                            ci.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ptrs, st,
-                            _stream(stream), ctypes.byref(out)))
+    _check(lib().dar_create_ex(ctypes.byref(dims), len(vals),
+                               rp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                               ci.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ptrs, st,
+                               DAR_CORRECTION if correction else 0, _stream(stream),
+                               ctypes.byref(out)))
     return Dar(out, (P, L, T, H, K), len(vals), st)
 
 

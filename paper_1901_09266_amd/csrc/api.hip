@@ -193,6 +193,8 @@ dode_status check_params(const dode_spgd_params* p) {
     return fail(DODE_ERR_ARG, "kernel_path=%d (0 best, 1 sparse)", p->kernel_path);
   if (p->day_tile != 0 && p->day_tile != 16 && p->day_tile != 32 && p->day_tile != 64)
     return fail(DODE_ERR_ARG, "day_tile=%d (0 = tune, 16, 32 or 64)", p->day_tile);
+  if (p->refine_steps < 0 || p->refine_steps > 16)
+    return fail(DODE_ERR_ARG, "refine_steps=%d outside [0, 16]", p->refine_steps);
   return DODE_OK;
 }
 
@@ -293,7 +295,7 @@ namespace {
 
 // Minibatch j of epoch e on the plan's state: forward + residual, then
 // adjoint + step + projection.
-dode_status run_chunk(dode_plan* plan, const ChunkSched& cs, hipStream_t s) {
+dode_status run_chunk(dode_plan* plan, const ChunkSched& cs, hipStream_t s, bool corr = false) {
   const dode_dar* dar = plan->dar;
   const Layout& ly = plan->ly;
   if (plan->use_mfma) {
@@ -302,8 +304,10 @@ dode_status run_chunk(dode_plan* plan, const ChunkSched& cs, hipStream_t s) {
     float* Q = static_cast<float*>(plan->d_Q);
     float* A = static_cast<float*>(plan->d_A);
     const float* X = static_cast<const float*>(plan->d_X);
-    HIP_TRY(timed(plan, 0, s, [&] { return mfma_chunk_resid(dar, cs, dg, ly, Q, X, R, s); }));
-    HIP_TRY(timed(plan, 1, s, [&] { return mfma_chunk_adj_step(dar, cs, dg, ly, R, Q, A, plan->sa, s); }));
+    HIP_TRY(timed(plan, 0, s, [&] { return mfma_chunk_resid(dar, cs, dg, ly, Q, X, R, corr, s); }));
+    HIP_TRY(timed(plan, 1, s, [&] {
+      return mfma_chunk_adj_step(dar, cs, dg, ly, R, Q, A, plan->sa, corr, s);
+    }));
     return DODE_OK;
   }
   const int32_t* dc = plan->d_dc;
@@ -321,6 +325,14 @@ dode_status run_minibatch(dode_plan* plan, int32_t e, int32_t j, hipStream_t s) 
   return run_chunk(plan, plan->chunk(e, j), s);
 }
 
+// The refinement steps that end every epoch: full-batch steps on the
+// corrected values (schedule independent of the epoch).
+dode_status run_refinement(dode_plan* plan, hipStream_t s) {
+  for (int32_t r = 0; r < plan->refine_steps; ++r)
+    if (dode_status st = run_chunk(plan, plan->chunk_full(), s, true)) return st;
+  return DODE_OK;
+}
+
 // Capture one epoch (every minibatch, then the epoch-counter increment) into a
 // graph on the plan's own stream; replays read the epoch from d_epoch.
 dode_status build_epoch_graph(dode_plan* plan) {
@@ -331,6 +343,7 @@ dode_status build_epoch_graph(dode_plan* plan) {
   HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
   dode_status st = DODE_OK;
   for (int32_t j = 0; j < plan->nch && st == DODE_OK; ++j) st = run_chunk(plan, plan->chunk_dev(j), cs);
+  if (st == DODE_OK) st = run_refinement(plan, cs);
   hipError_t e = st == DODE_OK ? bump_counter(plan->d_epoch, cs) : hipSuccess;
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(cs, &g);
@@ -442,6 +455,7 @@ void dode_spgd_defaults(dode_spgd_params* p) {
   p->kernel_path = 0;
   p->use_graph = 1;
   p->day_tile = 32;
+  p->refine_steps = 0;
 }
 
 dode_status dar_destroy(dode_dar* dar) {
@@ -452,6 +466,7 @@ dode_status dar_destroy(dode_dar* dar) {
   for (void* p : {(void*)dar->d_row_ptr, (void*)dar->d_col, (void*)dar->d_col_ptr,
                   (void*)dar->d_row, (void*)dar->d_csc2csr, dar->d_W, dar->d_WT,
                   (void*)dar->d_scale, (void*)dar->d_tile_meta, dar->d_Fv, dar->d_Gv,
+                  dar->d_Fc, dar->d_Gc,
                   (void*)dar->d_row_of_nz,
                   (void*)dar->d_posf, (void*)dar->d_posg})
     if (p) (void)hipFree(p);
@@ -463,8 +478,17 @@ dode_status dar_destroy(dode_dar* dar) {
 dode_status dar_create(const dode_dims* dims, int32_t n_clusters, const int32_t* row_ptr,
                        const int32_t* col_idx, const double* const* values, dode_dtype storage,
                        void* stream, dode_dar** out) {
+  return dar_create_ex(dims, n_clusters, row_ptr, col_idx, values, storage, 0, stream, out);
+}
+
+dode_status dar_create_ex(const dode_dims* dims, int32_t n_clusters, const int32_t* row_ptr,
+                          const int32_t* col_idx, const double* const* values,
+                          dode_dtype storage, int32_t flags, void* stream, dode_dar** out) {
   if (!out) return fail(DODE_ERR_ARG, "out is NULL");
   *out = nullptr;
+  if (flags & ~DODE_DAR_CORRECTION) return fail(DODE_ERR_ARG, "unknown flags 0x%x", flags);
+  if ((flags & DODE_DAR_CORRECTION) && storage != DODE_FP8_E4M3)
+    return fail(DODE_ERR_ARG, "DODE_DAR_CORRECTION applies to FP8 storage only");
   if (dode_status st = check_dims(dims)) return st;
   if (n_clusters < 1) return fail(DODE_ERR_ARG, "n_clusters=%d must be >= 1", n_clusters);
   if (!row_ptr || !col_idx || !values) return fail(DODE_ERR_ARG, "pattern or values is NULL");
@@ -497,6 +521,7 @@ dode_status dar_create(const dode_dims* dims, int32_t n_clusters, const int32_t*
   d->C = n_clusters;
   d->nnz = nnz;
   d->storage = storage;
+  d->has_corr = (flags & DODE_DAR_CORRECTION) != 0;
   HIP_TRY(hipGetDevice(&d->device));
   d->h_row_ptr.assign(row_ptr, row_ptr + dm.L + 1);
   d->h_col.assign(col_idx, col_idx + nnz);
@@ -555,6 +580,7 @@ dode_status dar_create(const dode_dims* dims, int32_t n_clusters, const int32_t*
   }
   // host conversion, one cluster at a time
   std::vector<uint8_t> hw(cstride * esz), hwt(cstride * esz);
+  std::vector<uint16_t> hcorr(d->has_corr ? cstride : 0);
   std::vector<float> hs(storage == DODE_FP8_E4M3 ? (size_t)dm.K * dm.T * n_ptile : 0);
   std::vector<double> tmax(n_ptile);
   for (int32_t c = 0; c < n_clusters; ++c) {
@@ -589,10 +615,17 @@ dode_status dar_create(const dode_dims* dims, int32_t n_clusters, const int32_t*
             break;
           }
           case DODE_FP8_E4M3: {
-            const double sc = hs[lt * n_ptile + (col_idx[j] >> 6)];
+            const float sc = hs[lt * n_ptile + (col_idx[j] >> 6)];
             const uint8_t b = host_f64_to_e4m3(v / sc);
             hw[ij] = b;
             hwt[ijj] = b;
+            if (d->has_corr) {
+              // the kernels expand a code to bf16(fp32(scale * e4m3)); the
+              // correction is what remains, rounded to bf16
+              const float prod = static_cast<float>(host_e4m3_to_f64(b)) * sc;
+              const double h = host_bf16_to_f64(host_f64_to_bf16(prod));
+              hcorr[ij] = host_f64_to_bf16(v - h);
+            }
             break;
           }
         }
@@ -610,6 +643,11 @@ dode_status dar_create(const dode_dims* dims, int32_t n_clusters, const int32_t*
         dar_destroy(d.release());
         return fail(st, "tile fill: %s", err.c_str());
       }
+      if (d->has_corr)
+        if (dode_status st = tiles_fill_correction(d.get(), c, hcorr.data(), err)) {
+          dar_destroy(d.release());
+          return fail(st, "correction tile fill: %s", err.c_str());
+        }
     }
   }
   HIP_TRY(hipStreamSynchronize(s));
@@ -631,6 +669,8 @@ dode_status dar_info(const dode_dar* dar, dode_dims* dims, int32_t* n_clusters, 
 dode_status dar_set_values(dode_dar* dar, int32_t cluster, const void* W_dev, void* stream) {
   if (dode_status st = check_dar(dar, cluster)) return st;
   if (!W_dev) return fail(DODE_ERR_ARG, "W_dev is NULL");
+  if (dar->has_corr)
+    return fail(DODE_ERR_UNSUPPORTED, "dar_set_values on a handle with correction tiles");
   if (dar->storage == DODE_FP8_E4M3 && dar->dims.P > 64 * 64)
     return fail(DODE_ERR_UNSUPPORTED, "device FP8 requantisation supports P <= 4096");
   HIP_TRY(quantize_values(dar, cluster, W_dev, as_stream(stream)));
@@ -864,6 +904,7 @@ dode_status spgd_step(const dode_dar* dar, int32_t cluster, const int32_t* chunk
   p1.batch_rows = n_h * dm.L;
   p1.check_finite = 0;
   if (p1.day_tile == 0) p1.day_tile = 32;   // one minibatch: nothing to tune for
+  p1.refine_steps = 0;
   std::vector<int32_t> dc(n_days, cluster);
   dode_plan* raw = nullptr;
   if (dode_status st = spgd_plan_create(dar, dc.data(), n_days, &p1, perm.data(), 0, stream, &raw))
@@ -884,6 +925,7 @@ dode_status spgd_plan_destroy(dode_plan* plan) {
   if (plan->last_stream) (void)hipStreamSynchronize(plan->last_stream);
   for (void* p : {(void*)plan->d_perm, (void*)plan->d_pos, (void*)plan->d_touched,
                   (void*)plan->d_dc, plan->d_R, (void*)plan->d_part, (void*)plan->d_groups,
+                  (void*)plan->d_full,
                   plan->d_X, plan->d_Q, plan->d_A, (void*)plan->d_loss, (void*)plan->d_order})
     if (p) (void)hipFree(p);
   for (hipEvent_t e : plan->event_pool) (void)hipEventDestroy(e);
@@ -960,7 +1002,36 @@ dode_status spgd_plan_create(const dode_dar* dar, const int32_t* day_cluster, in
   } else {
     p->ly = Layout{dm.P, (int64_t)D * dm.P, dm.L, (int64_t)D * dm.L, dm.L, (int64_t)D * dm.L, 4, 4, 4};
   }
-  const int64_t nR = bh * p->ly.r_s + kStatePad, nX = dm.H * p->ly.x_h + kStatePad;
+  p->refine_steps = params->refine_steps;
+  if (p->refine_steps > 0) {
+    if (!p->use_mfma || !dar->has_corr)
+      return fail(DODE_ERR_UNSUPPORTED,
+                  "refine_steps needs FP8 storage with correction tiles and kernel_path 0");
+    // the whole row set as one minibatch: identity order, every departure
+    // interval with every lag that stays inside the day
+    std::vector<int32_t> full((size_t)2 * C * dm.H + (size_t)C * dm.T * (dm.K + 3), -1);
+    for (int32_t c = 0; c < C; ++c)
+      for (int32_t h = 0; h < dm.H; ++h) {
+        full[(size_t)c * dm.H + h] = h;
+        full[(size_t)(C + c) * dm.H + h] = h;
+      }
+    for (int32_t c = 0; c < C; ++c)
+      for (int32_t t = 0; t < dm.T; ++t) {
+        int32_t* dsc = full.data() + 2 * (size_t)C * dm.H + ((size_t)c * dm.T + t) * (dm.K + 3);
+        uint64_t mask = 0;
+        for (int32_t l = 0; l < dm.K; ++l) {
+          const bool in = t + l < dm.H;
+          dsc[kDescSlot + l] = in ? t + l : -1;
+          if (in) mask |= 1ull << l;
+        }
+        dsc[kDescT] = t;
+        dsc[kDescMask] = (int32_t)(uint32_t)mask;
+        dsc[kDescMask + 1] = (int32_t)(uint32_t)(mask >> 32);
+      }
+    HIP_TRY(up(&p->d_full, full.data(), full.size() * 4));
+  }
+  const int64_t r_rows = p->refine_steps > 0 ? std::max(bh, dm.H) : bh;
+  const int64_t nR = r_rows * p->ly.r_s + kStatePad, nX = dm.H * p->ly.x_h + kStatePad;
   const int64_t nQ = dm.T * p->ly.q_t + kStatePad;
   HIP_TRY(hipMalloc(&p->d_R, nR * ss));
   HIP_TRY(hipMalloc(&p->d_part, (size_t)D * dm.H * 8));
@@ -1051,6 +1122,7 @@ dode_status spgd_run(dode_plan* plan, int32_t epoch_begin, int32_t n_epochs, dou
     } else {
       for (int32_t j = 0; j < plan->nch; ++j)
         if (dode_status st = run_minibatch(plan, e, j, s)) return st;
+      if (dode_status st = run_refinement(plan, s)) return st;
     }
     if (loss_dev) {
       double* out = loss_dev + (size_t)(e - epoch_begin) * D;

@@ -50,6 +50,8 @@ struct DevTiles {
   const void* Gv = nullptr;
   const float* scale = nullptr;   // FP8 only: [C][K][T][n_ptile]
   int32_t n_ptile = 0;
+  const void* Fc = nullptr;       // FP8 with correction: bf16 tiles, same packing
+  const void* Gc = nullptr;
 };
 
 struct dode_dar {
@@ -77,6 +79,9 @@ struct dode_dar {
   int32_t* d_posg = nullptr;        // [nnz] element offset of CSC slot jj in an adjoint block
   void* d_Fv = nullptr;
   void* d_Gv = nullptr;
+  void* d_Fc = nullptr;             // correction tiles (FP8 with DODE_DAR_CORRECTION)
+  void* d_Gc = nullptr;
+  bool has_corr = false;
   std::vector<int32_t> h_posf, h_posg;
 
   DevPat pat() const {
@@ -239,6 +244,8 @@ struct dode_plan {
   int32_t* d_groups = nullptr;    // cluster | first | count | cbase | cgroups (n_groups each)
   int32_t n_groups = 0;
   int32_t day_tile = 32;          // days per group
+  int32_t refine_steps = 0;       // full-batch steps per epoch on corrected values
+  int32_t* d_full = nullptr;      // full-batch schedule: perm | pos [C][H], descriptors [C][T][K+3]
   bool tune_day_tile = false;     // choose day_tile by timing at the next load
   std::vector<int32_t> cluster_days;  // days of each cluster (plan days are grouped by cluster)
   bool use_mfma = false;
@@ -263,6 +270,13 @@ struct dode_plan {
     const size_t dw = desc_width(dar->dims.K);
     return ChunkSched{d_perm + (size_t)e * C * H, d_pos + (size_t)e * C * H,
                       d_touched + ((size_t)e * nch + j) * C * mt * dw, j * bh, bh, mt, nullptr, 0, 0};
+  }
+  // the whole row set as one minibatch (identity order; refinement steps)
+  ChunkSched chunk_full() const {
+    const int32_t H = dar->dims.H;
+    const int32_t* perm = d_full;
+    const int32_t* pos = d_full + (size_t)C * H;
+    return ChunkSched{perm, pos, d_full + 2 * (size_t)C * H, 0, H, dar->dims.T, nullptr, 0, 0};
   }
   // minibatch j of the epoch held in d_epoch (for graph replays)
   ChunkSched chunk_dev(int32_t j) const {
@@ -307,16 +321,20 @@ hipError_t set_counter(int32_t* c, int32_t v, hipStream_t s);
 hipError_t bump_counter(int32_t* c, hipStream_t s);
 
 // ---- MFMA tile kernels (mfma_kernels.hip) -------------------------------
+// corr: multiply with the corrected FP8 values (refinement steps)
 hipError_t mfma_chunk_resid(const dode_dar* dar, const ChunkSched& cs, const DayGroups& dg,
-                            const Layout& ly, const float* Q, const float* X, float* R,
+                            const Layout& ly, const float* Q, const float* X, float* R, bool corr,
                             hipStream_t s);
 hipError_t mfma_chunk_adj_step(const dode_dar* dar, const ChunkSched& cs, const DayGroups& dg,
                                const Layout& ly, const float* R, float* Q, float* A,
-                               const StepArgs& st, hipStream_t s);
+                               const StepArgs& st, bool corr, hipStream_t s);
 // host: tile layout (ranges, positions, device arrays), then each cluster's
 // entries from its pattern-form codes (CSR order, storage type) (tiles.hip)
 dode_status tiles_prepare(dode_dar* d, std::string& err);
 dode_status tiles_fill_cluster(dode_dar* d, int32_t c, const void* codes_csr, std::string& err);
+// bf16 correction codes of one cluster (CSR order) into the correction tiles
+dode_status tiles_fill_correction(dode_dar* d, int32_t c, const uint16_t* corr_csr,
+                                  std::string& err);
 
 // ---- differentiation (route_kernels.hip) --------------------------------
 hipError_t routes_rho(const DevRoutes& r, bool f64, const void* Rr, const void* z, void* W,

@@ -65,24 +65,49 @@ __device__ __forceinline__ f32x4 load4(const float* __restrict__ p) {
   return f32x4{v[0], v[1], v[2], v[3]};
 }
 
+// Value modes of the assignment operand.
+//   kBF16     bfloat16 tiles.
+//   kFP8      E4M3FN codes widened exactly to bf16; the FP8 scale is applied by
+//             the caller to the other operand.
+//   kFP8Corr  the corrected FP8 values h + c of refinement steps: h =
+//             bf16(fp32(scale * e4m3)) is formed in registers, c comes from the
+//             bf16 correction tiles; the other operand is not scaled.
+enum { kBF16 = 0, kFP8 = 1, kFP8Corr = 2 };
+
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ f32x8 fp8_codes(const void* tiles, int64_t kidx, int lane) {
+  const uint2 w = static_cast<const uint2*>(tiles)[kidx * 64 + lane];
+  const f32x2 a = __builtin_amdgcn_cvt_pk_f32_fp8((int)w.x, false);
+  const f32x2 b = __builtin_amdgcn_cvt_pk_f32_fp8((int)w.x, true);
+  const f32x2 c = __builtin_amdgcn_cvt_pk_f32_fp8((int)w.y, false);
+  const f32x2 d = __builtin_amdgcn_cvt_pk_f32_fp8((int)w.y, true);
+  return f32x8{a[0], a[1], b[0], b[1], c[0], c[1], d[0], d[1]};
+}
+
 // A operand of k-step `kidx` (element offset kidx*512 of the packed tiles):
-// BF16 storage loads 8 bf16 values per lane; FP8 storage loads 8 E4M3FN codes
-// per lane and widens them exactly to bf16 (4 significant bits fit).  The FP8
-// scale is applied by the caller to the other operand.
-template <bool FP8>
+// 8 values per lane (kBF16, kFP8; see the modes above).
+template <int MODE>
 __device__ __forceinline__ bf16x8 load_a(const void* tiles, int64_t kidx, int lane) {
-  if constexpr (!FP8) {
+  if constexpr (MODE == kBF16) {
     return static_cast<const bf16x8*>(tiles)[kidx * 64 + lane];
   } else {
-    const uint2 w = static_cast<const uint2*>(tiles)[kidx * 64 + lane];
-    typedef float f32x2 __attribute__((ext_vector_type(2)));
-    const f32x2 a = __builtin_amdgcn_cvt_pk_f32_fp8((int)w.x, false);
-    const f32x2 b = __builtin_amdgcn_cvt_pk_f32_fp8((int)w.x, true);
-    const f32x2 c = __builtin_amdgcn_cvt_pk_f32_fp8((int)w.y, false);
-    const f32x2 d = __builtin_amdgcn_cvt_pk_f32_fp8((int)w.y, true);
-    const f32x8 v = {a[0], a[1], b[0], b[1], c[0], c[1], d[0], d[1]};
-    return __builtin_convertvector(v, bf16x8);
+    return __builtin_convertvector(fp8_codes(tiles, kidx, lane), bf16x8);
   }
+}
+
+// h = bf16(fp32(scale * e4m3)) of the lane's 8 codes, elements 0-3 with s0 and
+// 4-7 with s1 (kFP8Corr).
+__device__ __forceinline__ bf16x8 load_a_scaled(const void* tiles, int64_t kidx, int lane,
+                                                float s0, float s1) {
+  f32x8 v = fp8_codes(tiles, kidx, lane);
+  v[0] *= s0; v[1] *= s0; v[2] *= s0; v[3] *= s0;
+  v[4] *= s1; v[5] *= s1; v[6] *= s1; v[7] *= s1;
+  return __builtin_convertvector(v, bf16x8);
+}
+
+__device__ __forceinline__ bf16x8 load_corr(const void* tiles, int64_t kidx, int lane) {
+  return static_cast<const bf16x8*>(tiles)[kidx * 64 + lane];
 }
 
 // acc += a * (hi + lo) with hi = bf16(v), lo = bf16(v - hi).
@@ -112,7 +137,7 @@ __device__ __forceinline__ void store4(float* __restrict__ p, const f32x4& v, bo
 // are all issued before the first product, so a batch costs one memory round
 // trip.  Column n of tile u is day first+16u+n; past the group's end it reads
 // day `first` and its result is dropped.
-template <bool FP8, int NT>
+template <int MODE, int NT>
 __global__ void __launch_bounds__(256)
 k_fwd_mfma(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, Layout ly,
            const float* __restrict__ Q, const float* __restrict__ X, float* __restrict__ R) {
@@ -153,30 +178,40 @@ k_fwd_mfma(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, Layout ly,
   const bf16x8 zero = __builtin_convertvector(f32x8{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, bf16x8);
   int l = l_lo, ks = 0;
   for (int it0 = 0; it0 < n_it; it0 += kBatch) {
-    bf16x8 a[kBatch];
+    bf16x8 a[kBatch], ac[MODE == kFP8Corr ? kBatch : 1];
     f32x8 v[kBatch][NT];
 #pragma unroll
     for (int b = 0; b < kBatch; ++b) {
       const int t = h - l;
-      a[b] = load_a<FP8>(tl.Fv, kbase + ((int64_t)l * pt.T + t) * tl.kf_total + ks, lane);
+      const int64_t kidx = kbase + ((int64_t)l * pt.T + t) * tl.kf_total + ks;
       const int p0 = plo + 32 * ks + 4 * kg;
 #pragma unroll
       for (int u = 0; u < NT; ++u) v[b][u] = load8(qcol[u] + t * ly.q_t + (p0 >> 2) * ly.q_b, ly.q_b);
-      if constexpr (FP8) {
+      if constexpr (MODE == kBF16) {
+        a[b] = load_a<MODE>(tl.Fv, kidx, lane);
+      } else {
         // each 4-OD half of the lane lies in one 64-OD scale group (p0 is a
         // multiple of 4); the two halves may fall in neighbouring groups
         const float* scl = tl.scale + (((int64_t)c * pt.K + l) * pt.T + t) * tl.n_ptile;
         const float s0 = scl[min(p0 >> 6, tl.n_ptile - 1)];
         const float s1 = scl[min((p0 + 16) >> 6, tl.n_ptile - 1)];
+        if constexpr (MODE == kFP8) {
+          a[b] = load_a<MODE>(tl.Fv, kidx, lane);
 #pragma unroll
-        for (int u = 0; u < NT; ++u) {
-          v[b][u][0] *= s0; v[b][u][1] *= s0; v[b][u][2] *= s0; v[b][u][3] *= s0;
-          v[b][u][4] *= s1; v[b][u][5] *= s1; v[b][u][6] *= s1; v[b][u][7] *= s1;
+          for (int u = 0; u < NT; ++u) {
+            v[b][u][0] *= s0; v[b][u][1] *= s0; v[b][u][2] *= s0; v[b][u][3] *= s0;
+            v[b][u][4] *= s1; v[b][u][5] *= s1; v[b][u][6] *= s1; v[b][u][7] *= s1;
+          }
+        } else {
+          a[b] = load_a_scaled(tl.Fv, kidx, lane, s0, s1);
+          ac[b] = load_corr(tl.Fc, kidx, lane);
         }
       }
       // past the last iteration: repeat its loads with a zero operand
-      if (it0 + b >= n_it) a[b] = zero;
-      else if (it0 + b + 1 < n_it && ++ks == nks) {
+      if (it0 + b >= n_it) {
+        a[b] = zero;
+        if constexpr (MODE == kFP8Corr) ac[b] = zero;
+      } else if (it0 + b + 1 < n_it && ++ks == nks) {
         ks = 0;
         ++l;
       }
@@ -184,7 +219,10 @@ k_fwd_mfma(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, Layout ly,
 #pragma unroll
     for (int b = 0; b < kBatch; ++b)
 #pragma unroll
-      for (int u = 0; u < NT; ++u) mma_split(a[b], v[b][u], acc[u]);
+      for (int u = 0; u < NT; ++u) {
+        mma_split(a[b], v[b][u], acc[u]);
+        if constexpr (MODE == kFP8Corr) mma_split(ac[b], v[b][u], acc[u]);
+      }
   }
   if (a0 >= pt.L) return;
   const bool full = a0 + 4 <= pt.L;
@@ -217,7 +255,7 @@ __device__ __forceinline__ f32x4 step4(f32x4 q, f32x4& a, const f32x4& g, const 
 // j) in the order of decode_item; same block remapping, batching and day
 // columns as the forward kernel.  The demand and accumulator rows are fetched
 // before the product.
-template <bool FP8, int NT>
+template <int MODE, int NT>
 __global__ void __launch_bounds__(256)
 k_adj_mfma(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, Layout ly,
            const float* __restrict__ R, float* __restrict__ Q, float* __restrict__ A, StepArgs st) {
@@ -262,23 +300,33 @@ k_adj_mfma(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, Layout ly,
   uint64_t m = lmask;
   int l = m ? __builtin_ctzll(m) : 0, ks = 0;
   for (int it0 = 0; it0 < n_it; it0 += kBatch) {
-    bf16x8 w[kBatch];
+    bf16x8 w[kBatch], wc[MODE == kFP8Corr ? kBatch : 1];
     f32x8 v[kBatch][NT];
 #pragma unroll
     for (int b = 0; b < kBatch; ++b) {
-      w[b] = load_a<FP8>(tl.Gv, kbase + ((int64_t)l * pt.T + t) * tl.kg_total + ks, lane);
+      const int64_t kidx = kbase + ((int64_t)l * pt.T + t) * tl.kg_total + ks;
       const int sl = dsc[kDescSlot + l];
       const int k0 = alo + 32 * ks + 4 * kg;
 #pragma unroll
       for (int u = 0; u < NT; ++u) v[b][u] = load8(rcol[u] + sl * ly.r_s + (k0 >> 2) * ly.r_b, ly.r_b);
-      if constexpr (FP8) {
+      if constexpr (MODE == kBF16) {
+        w[b] = load_a<MODE>(tl.Gv, kidx, lane);
+      } else {
         // the tile's 16 ODs lie in one 64-OD scale group
         const float sc = tl.scale[(((int64_t)c * pt.K + l) * pt.T + t) * tl.n_ptile + ((16 * j) >> 6)];
+        if constexpr (MODE == kFP8) {
+          w[b] = load_a<MODE>(tl.Gv, kidx, lane);
 #pragma unroll
-        for (int u = 0; u < NT; ++u) v[b][u] *= sc;
+          for (int u = 0; u < NT; ++u) v[b][u] *= sc;
+        } else {
+          w[b] = load_a_scaled(tl.Gv, kidx, lane, sc, sc);
+          wc[b] = load_corr(tl.Gc, kidx, lane);
+        }
       }
-      if (it0 + b >= n_it) w[b] = zero;
-      else if (it0 + b + 1 < n_it && ++ks == nks) {
+      if (it0 + b >= n_it) {
+        w[b] = zero;
+        if constexpr (MODE == kFP8Corr) wc[b] = zero;
+      } else if (it0 + b + 1 < n_it && ++ks == nks) {
         ks = 0;
         m &= m - 1;
         l = __builtin_ctzll(m);
@@ -287,7 +335,10 @@ k_adj_mfma(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, Layout ly,
 #pragma unroll
     for (int b = 0; b < kBatch; ++b)
 #pragma unroll
-      for (int u = 0; u < NT; ++u) mma_split(w[b], v[b][u], acc[u]);
+      for (int u = 0; u < NT; ++u) {
+        mma_split(w[b], v[b][u], acc[u]);
+        if constexpr (MODE == kFP8Corr) mma_split(wc[b], v[b][u], acc[u]);
+      }
   }
   if (p0 >= pt.P) return;
   const bool full = p0 + 4 <= pt.P;
@@ -337,50 +388,61 @@ hipError_t update_tiles(const dode_dar* dar, int32_t cluster, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int NT>
+template <int MODE, int NT>
 hipError_t launch_fwd(const dode_dar* dar, const ChunkSched& cs, const DayGroups& dg, const Layout& ly,
                       const float* Q, const float* X, float* R, hipStream_t s) {
   const int64_t nblk = ((int64_t)dg.n * cs.bh * dar->tiles.nLT + 3) / 4;
   const dim3 grid((unsigned)(((nblk + kXcds - 1) / kXcds) * kXcds));
-  if (dar->storage == DODE_FP8_E4M3)
-    hipLaunchKernelGGL((k_fwd_mfma<true, NT>), grid, dim3(256), 0, s, dar->pat(), dar->tiles, cs, dg,
-                       ly, Q, X, R);
-  else
-    hipLaunchKernelGGL((k_fwd_mfma<false, NT>), grid, dim3(256), 0, s, dar->pat(), dar->tiles, cs, dg,
-                       ly, Q, X, R);
+  hipLaunchKernelGGL((k_fwd_mfma<MODE, NT>), grid, dim3(256), 0, s, dar->pat(), dar->tiles, cs, dg,
+                     ly, Q, X, R);
   return hipGetLastError();
 }
 
-template <int NT>
+template <int MODE, int NT>
 hipError_t launch_adj(const dode_dar* dar, const ChunkSched& cs, const DayGroups& dg, const Layout& ly,
                       const float* R, float* Q, float* A, const StepArgs& st, hipStream_t s) {
   const int64_t nblk = ((int64_t)dg.n * cs.max_touched * dar->tiles.nPT + 3) / 4;
   const dim3 grid((unsigned)(((nblk + kXcds - 1) / kXcds) * kXcds));
-  if (dar->storage == DODE_FP8_E4M3)
-    hipLaunchKernelGGL((k_adj_mfma<true, NT>), grid, dim3(256), 0, s, dar->pat(), dar->tiles, cs, dg,
-                       ly, R, Q, A, st);
-  else
-    hipLaunchKernelGGL((k_adj_mfma<false, NT>), grid, dim3(256), 0, s, dar->pat(), dar->tiles, cs, dg,
-                       ly, R, Q, A, st);
+  hipLaunchKernelGGL((k_adj_mfma<MODE, NT>), grid, dim3(256), 0, s, dar->pat(), dar->tiles, cs, dg,
+                     ly, R, Q, A, st);
   return hipGetLastError();
 }
 
+template <int NT>
+hipError_t fwd_mode(const dode_dar* dar, const ChunkSched& cs, const DayGroups& dg, const Layout& ly,
+                    const float* Q, const float* X, float* R, bool corr, hipStream_t s) {
+  if (dar->storage != DODE_FP8_E4M3) return launch_fwd<kBF16, NT>(dar, cs, dg, ly, Q, X, R, s);
+  if (corr) return launch_fwd<kFP8Corr, NT>(dar, cs, dg, ly, Q, X, R, s);
+  return launch_fwd<kFP8, NT>(dar, cs, dg, ly, Q, X, R, s);
+}
+
+template <int NT>
+hipError_t adj_mode(const dode_dar* dar, const ChunkSched& cs, const DayGroups& dg, const Layout& ly,
+                    const float* R, float* Q, float* A, const StepArgs& st, bool corr,
+                    hipStream_t s) {
+  if (dar->storage != DODE_FP8_E4M3) return launch_adj<kBF16, NT>(dar, cs, dg, ly, R, Q, A, st, s);
+  if (corr) return launch_adj<kFP8Corr, NT>(dar, cs, dg, ly, R, Q, A, st, s);
+  return launch_adj<kFP8, NT>(dar, cs, dg, ly, R, Q, A, st, s);
+}
+
 hipError_t mfma_chunk_resid(const dode_dar* dar, const ChunkSched& cs, const DayGroups& dg,
-                            const Layout& ly, const float* Q, const float* X, float* R,
+                            const Layout& ly, const float* Q, const float* X, float* R, bool corr,
                             hipStream_t s) {
+  if (corr && !dar->has_corr) return hipErrorInvalidValue;
   switch (dg.tile) {
-    case 16: return launch_fwd<1>(dar, cs, dg, ly, Q, X, R, s);
-    case 64: return launch_fwd<4>(dar, cs, dg, ly, Q, X, R, s);
-    default: return launch_fwd<2>(dar, cs, dg, ly, Q, X, R, s);
+    case 16: return fwd_mode<1>(dar, cs, dg, ly, Q, X, R, corr, s);
+    case 64: return fwd_mode<4>(dar, cs, dg, ly, Q, X, R, corr, s);
+    default: return fwd_mode<2>(dar, cs, dg, ly, Q, X, R, corr, s);
   }
 }
 
 hipError_t mfma_chunk_adj_step(const dode_dar* dar, const ChunkSched& cs, const DayGroups& dg,
                                const Layout& ly, const float* R, float* Q, float* A,
-                               const StepArgs& st, hipStream_t s) {
+                               const StepArgs& st, bool corr, hipStream_t s) {
+  if (corr && !dar->has_corr) return hipErrorInvalidValue;
   switch (dg.tile) {
-    case 16: return launch_adj<1>(dar, cs, dg, ly, R, Q, A, st, s);
-    case 64: return launch_adj<4>(dar, cs, dg, ly, R, Q, A, st, s);
-    default: return launch_adj<2>(dar, cs, dg, ly, R, Q, A, st, s);
+    case 16: return adj_mode<1>(dar, cs, dg, ly, R, Q, A, st, corr, s);
+    case 64: return adj_mode<4>(dar, cs, dg, ly, R, Q, A, st, corr, s);
+    default: return adj_mode<2>(dar, cs, dg, ly, R, Q, A, st, corr, s);
   }
 }

@@ -120,6 +120,13 @@ dode_status tiles_prepare(dode_dar* d, std::string& err) {
   if (!hip_ok(hipMalloc(&d->d_Fv, std::max<size_t>(16, fbytes)))) return DODE_ERR_OOM;
   if (!hip_ok(hipMalloc(&d->d_Gv, std::max<size_t>(16, gbytes)))) return DODE_ERR_OOM;
   d->device_bytes += fbytes + gbytes + meta.size() * 4 + 8 * nnz;
+  if (d->has_corr) {
+    // bf16 correction tiles, 2 bytes per entry whatever the storage type
+    const size_t cf = fbytes / esz * 2, cg = gbytes / esz * 2;
+    if (!hip_ok(hipMalloc(&d->d_Fc, std::max<size_t>(16, cf)))) return DODE_ERR_OOM;
+    if (!hip_ok(hipMalloc(&d->d_Gc, std::max<size_t>(16, cg)))) return DODE_ERR_OOM;
+    d->device_bytes += cf + cg;
+  }
   DevTiles& T = d->tiles;
   T.nLT = nLT;
   T.nPT = nPT;
@@ -136,44 +143,54 @@ dode_status tiles_prepare(dode_dar* d, std::string& err) {
   T.Gv = d->d_Gv;
   T.scale = d->d_scale;
   T.n_ptile = (dm.P + 63) / 64;
+  T.Fc = d->d_Fc;
+  T.Gc = d->d_Gc;
   d->has_tiles = true;
   return DODE_OK;
 }
 
-dode_status tiles_fill_cluster(dode_dar* d, int32_t c, const void* codes_csr, std::string& err) {
+namespace {
+
+// Scatter one cluster's codes (CSR order, esz bytes each) into packed forward
+// tiles F and adjoint tiles G.
+template <typename E>
+dode_status fill_tiles(dode_dar* d, int32_t c, const E* codes_csr, void* F, void* G,
+                       std::string& err) {
   const dode_dims& dm = d->dims;
   const int64_t nnz = d->nnz;
-  const int32_t kf = d->tiles.kf_total, kg = d->tiles.kg_total;
-  const bool fp8 = d->storage == DODE_FP8_E4M3;
-  const size_t esz = fp8 ? 1 : 2;
   const int64_t blocks = (int64_t)dm.K * dm.T;
-  const size_t fblk = (size_t)kf * 512, gblk = (size_t)kg * 512;   // elements per block
-  std::vector<uint8_t> fbuf(blocks * fblk * esz, 0), gbuf(blocks * gblk * esz, 0);
+  const size_t fblk = (size_t)d->tiles.kf_total * 512, gblk = (size_t)d->tiles.kg_total * 512;
+  std::vector<E> fbuf(blocks * fblk, E(0)), gbuf(blocks * gblk, E(0));
   for (int64_t lt = 0; lt < blocks; ++lt) {
     const int32_t l = (int32_t)(lt / dm.T), t = (int32_t)(lt % dm.T);
     if (t + l >= dm.H) continue;   // block past the last interval: never read
-    if (fp8) {
-      const uint8_t* w = static_cast<const uint8_t*>(codes_csr) + lt * nnz;
-      uint8_t* fb = fbuf.data() + lt * fblk;
-      uint8_t* gb = gbuf.data() + lt * gblk;
-      for (int64_t j = 0; j < nnz; ++j) fb[d->h_posf[j]] = w[j];
-      for (int64_t jj = 0; jj < nnz; ++jj) gb[d->h_posg[jj]] = w[d->h_csc2csr[jj]];
-    } else {
-      const uint16_t* w = static_cast<const uint16_t*>(codes_csr) + lt * nnz;
-      uint16_t* fb = reinterpret_cast<uint16_t*>(fbuf.data()) + lt * fblk;
-      uint16_t* gb = reinterpret_cast<uint16_t*>(gbuf.data()) + lt * gblk;
-      for (int64_t j = 0; j < nnz; ++j) fb[d->h_posf[j]] = w[j];
-      for (int64_t jj = 0; jj < nnz; ++jj) gb[d->h_posg[jj]] = w[d->h_csc2csr[jj]];
-    }
+    const E* w = codes_csr + lt * nnz;
+    E* fb = fbuf.data() + lt * fblk;
+    E* gb = gbuf.data() + lt * gblk;
+    for (int64_t j = 0; j < nnz; ++j) fb[d->h_posf[j]] = w[j];
+    for (int64_t jj = 0; jj < nnz; ++jj) gb[d->h_posg[jj]] = w[d->h_csc2csr[jj]];
   }
-  hipError_t e = hipMemcpy(static_cast<uint8_t*>(d->d_Fv) + (size_t)c * blocks * fblk * esz,
-                           fbuf.data(), fbuf.size(), hipMemcpyHostToDevice);
+  hipError_t e = hipMemcpy(static_cast<E*>(F) + (size_t)c * blocks * fblk, fbuf.data(),
+                           fbuf.size() * sizeof(E), hipMemcpyHostToDevice);
   if (e == hipSuccess)
-    e = hipMemcpy(static_cast<uint8_t*>(d->d_Gv) + (size_t)c * blocks * gblk * esz, gbuf.data(),
-                  gbuf.size(), hipMemcpyHostToDevice);
+    e = hipMemcpy(static_cast<E*>(G) + (size_t)c * blocks * gblk, gbuf.data(),
+                  gbuf.size() * sizeof(E), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     err = hipGetErrorString(e);
     return DODE_ERR_HIP;
   }
   return DODE_OK;
+}
+
+}  // namespace
+
+dode_status tiles_fill_cluster(dode_dar* d, int32_t c, const void* codes_csr, std::string& err) {
+  if (d->storage == DODE_FP8_E4M3)
+    return fill_tiles(d, c, static_cast<const uint8_t*>(codes_csr), d->d_Fv, d->d_Gv, err);
+  return fill_tiles(d, c, static_cast<const uint16_t*>(codes_csr), d->d_Fv, d->d_Gv, err);
+}
+
+dode_status tiles_fill_correction(dode_dar* d, int32_t c, const uint16_t* corr_csr,
+                                  std::string& err) {
+  return fill_tiles(d, c, corr_csr, d->d_Fc, d->d_Gc, err);
 }

@@ -12,9 +12,10 @@ def say(*a):
     sys.stdout.flush()
 
 
-def make_dar(inst, storage="f64", W=None):
+def make_dar(inst, storage="f64", W=None, correction=False):
     return dode.dar_create(inst.P, inst.L, inst.T, inst.H, inst.K, inst.row_ptr, inst.col_idx,
-                           inst.W if W is None else W, storage=storage, stream=0)
+                           inst.W if W is None else W, storage=storage, correction=correction,
+                           stream=0)
 
 
 def dev(a, dtype):
@@ -67,7 +68,10 @@ def dequantized_values(inst, storage):
             out.append(W.astype(np.float32).astype(np.float64))
         elif storage == "bf16":
             out.append(quantize_bf16(W))
-        elif storage == "fp8":
+        elif storage in ("fp8", "fp8corr"):
+            # one FP32 scale per (lag, interval, 64-OD group); "fp8corr" is the
+            # corrected value h + c of refinement steps: h = bf16(fp32(scale *
+            # code)), c = bf16(w - h)
             K, T, nnz = W.shape
             tiles = inst.col_idx // 64
             Wq = np.zeros_like(W)
@@ -75,6 +79,12 @@ def dequantized_values(inst, storage):
                 sel = tiles == tile
                 amax = np.abs(W[:, :, sel]).max(axis=2, keepdims=True)
                 sc = np.where(amax > 0, (amax / 448.0).astype(np.float32).astype(np.float64), 1.0)
-                Wq[:, :, sel] = quantize_e4m3(W[:, :, sel] / sc) * sc
+                code = quantize_e4m3(W[:, :, sel] / sc)
+                if storage == "fp8":
+                    Wq[:, :, sel] = code * sc
+                else:
+                    prod = (code.astype(np.float32) * sc.astype(np.float32)).astype(np.float64)
+                    h = quantize_bf16(prod)
+                    Wq[:, :, sel] = h + quantize_bf16(W[:, :, sel] - h)
             out.append(Wq)
     return out

@@ -369,3 +369,63 @@ def test_day_tile_rejected():
     dar = make_dar(inst, "bf16")
     with pytest.raises(dode.DodeError, match="day_tile"):
         dode.spgd_plan_create(dar, inst.day_cluster, dode.make_params(day_tile=48), stream=0)
+
+
+@pytest.mark.parametrize("name", ["ragged", "corridor"])
+def test_refinement_steps_match_oracle(name):
+    """FP8 plan with 2 refinement steps per epoch: each epoch is the minibatches
+    of Algorithm 1 on the FP8 values, then 2 full-batch steps (all H intervals
+    as one minibatch) on the corrected values h + c.  The oracle runs the same
+    composition in FP64; the plan's per-epoch losses (FP8 values) and final
+    demand must match, and the corrected values must beat plain FP8 on the
+    exact loss."""
+    kw = dict(MFMA_SHAPES[name])
+    inst = make_instance(demand="gamma", noise="mult5", x_dtype="f32", seed=91, **kw)
+    say("refinement", name)
+    E, R = 6, 2
+    perms = make_perms(92, E, inst.C, inst.H)
+    batch_rows = 4 * inst.L
+    bh = chunk_h_blocks(inst.L, inst.H, batch_rows)
+    Wq = dequantized_values(inst, "fp8")
+    Wr = dequantized_values(inst, "fp8corr")
+    # corrected values are far closer to the exact ones than the FP8 values
+    for c in range(inst.C):
+        assert np.max(np.abs(Wr[c] - inst.W[c])) <= 2.0 ** -12 * np.max(np.abs(inst.W[c]))
+        assert np.max(np.abs(Wr[c] - inst.W[c])) < 0.1 * np.max(np.abs(Wq[c] - inst.W[c]))
+    x64 = inst.x.astype(np.float64)
+    ident = np.tile(np.arange(inst.H, dtype=np.int32), (1, inst.C, 1))
+    Q = A = None
+    hist = []
+    for e in range(E):
+        Q, A, _ = orc.spgd(inst, x64, perms[e:e + 1], 1, bh, q0=Q, A0=A, W=Wq, record_loss=False)
+        for _ in range(R):
+            Q, A, _ = orc.spgd(inst, x64, ident, 1, inst.H, q0=Q, A0=A, W=Wr, record_loss=False)
+        hist.append(orc.metrics(inst, x64, Q, W=Wq)[0])
+    ho = np.stack(hist, axis=1)
+    dar = make_dar(inst, "fp8", correction=True)
+    p = dode.make_params(epochs=E, batch_rows=batch_rows, eta=5.0, refine_steps=R)
+    plan = dode.spgd_plan_create(dar, inst.day_cluster, p, perm=perms, stream=0)
+    Q0 = torch.zeros((inst.D, inst.T, inst.P), dtype=torch.float32, device="cuda")
+    dode.spgd_plan_load(plan, dev(inst.x, torch.float32), Q0)
+    loss = torch.zeros((E, inst.D), dtype=torch.float64, device="cuda")
+    dode.spgd_run(plan, 0, E, loss=loss)
+    Qg = torch.empty_like(Q0)
+    dode.spgd_plan_store(plan, Qg)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(loss.cpu().numpy().T - ho) / ho) <= 1e-3
+    lg, _, _ = orc.metrics(inst, x64, Qg.cpu().numpy().astype(np.float64))
+    lo, _, _ = orc.metrics(inst, x64, Q)
+    assert np.max(np.abs(lg - lo) / lo) <= 1e-3
+
+
+def test_refinement_needs_correction_tiles():
+    inst = make_instance(P=10, L=12, T=6, K=2, sizes=(3,), inc=0.3, pattern="bernoulli", seed=93)
+    for storage, corr in (("fp8", False), ("bf16", False)):
+        dar = make_dar(inst, storage, correction=corr)
+        with pytest.raises(dode.DodeError, match="refine_steps"):
+            dode.spgd_plan_create(dar, inst.day_cluster, dode.make_params(refine_steps=1), stream=0)
+    with pytest.raises(dode.DodeError, match="FP8"):
+        make_dar(inst, "bf16", correction=True)
+    dar = make_dar(inst, "fp8", correction=True)
+    with pytest.raises(dode.DodeError, match="correction"):
+        dode.dar_set_values(dar, 0, torch.zeros((inst.K, inst.T, len(inst.col_idx)), device="cuda"))
