@@ -380,3 +380,76 @@ int orc_logits_backward(const orc_dims* dm, int32_t n_paths, const int32_t* path
   free(pi); free(dpi);
   return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * Dynamic assignment ratios from link speeds (section "Dynamic assignment
+ * ratio", eqs. "dar2"/"dar", Example "DAR matrix computation"; section
+ * "Link/path travel time", eq. "cost").
+ *
+ * Time is in minutes, observation intervals are [h*dt, (h+1)*dt).  Link a
+ * entered at time t is crossed in c_a(t) = len[a] / speed[a][floor(t/dt)]
+ * minutes (speed per link and interval, length/speed in consistent units;
+ * the last interval's speed holds after the end of the day).  A vehicle of
+ * path k departing at t enters the i-th link of the path at tau_i(t), with
+ * tau_0(t) = t and tau_{i+1}(t) = tau_i(t) + c_{alpha(i)}(tau_i(t)) (eq.
+ * "cost").  Departure interval h maps onto the arrival window
+ * [tau_i(h*dt), tau_i((h+1)*dt)] at link alpha(i), and the ratio of
+ * observation interval h2 is the share of the window that lies in it (eq.
+ * "dar", as the worked example computes it from the two boundary
+ * trajectories).  A window of zero length puts all its mass in the interval
+ * of its start; reversed end points (a FIFO violation) are swapped.  Shares
+ * in intervals h2 >= H (after the day) or with h2 - h >= K are dropped.
+ *
+ * Paths: path_ptr[n_paths+1], path_link[] the links of each path in the order
+ * they are traversed; pair m = path_ptr[k] + i is the i-th link of path k.
+ * Output Rr[K][H][n_pairs] = the mean over the n_days days of each day's
+ * ratios (one averaged ratio set per traffic pattern).
+ * ---------------------------------------------------------------------- */
+static double link_time(const double* len, const double* speed_day, int32_t H_speed, double dt,
+                        int32_t a, double t) {
+  int64_t h = (int64_t)floor(t / dt);
+  if (h < 0) h = 0;
+  if (h >= H_speed) h = H_speed - 1;
+  return len[a] / speed_day[IDX2(a, h, H_speed)];
+}
+
+/* overlap length of [lo, hi] with [h2*dt, (h2+1)*dt) */
+static double overlap(double lo, double hi, int64_t h2, double dt) {
+  const double a = fmax(lo, (double)h2 * dt), b = fmin(hi, (double)(h2 + 1) * dt);
+  return b > a ? b - a : 0.0;
+}
+
+int orc_dar_from_speeds(int32_t n_paths, const int32_t* path_ptr, const int32_t* path_link,
+                        int32_t L, const double* len, const double* speed, int32_t n_days,
+                        int32_t H_speed, double dt, int32_t H, int32_t K, double* Rr) {
+  const int64_t n_pairs = path_ptr[n_paths];
+  memset(Rr, 0, sizeof(double) * (size_t)K * H * n_pairs);
+  if (n_days < 1) return 0;
+  for (int32_t d = 0; d < n_days; ++d) {
+    const double* sp = speed + (int64_t)d * L * H_speed;
+    for (int32_t k = 0; k < n_paths; ++k)
+      for (int32_t h = 0; h < H; ++h) {
+        /* the two boundary trajectories of departure interval h */
+        double s = h * dt, e = (h + 1) * dt;
+        for (int32_t m = path_ptr[k]; m < path_ptr[k + 1]; ++m) {
+          const int32_t a = path_link[m];
+          double lo = s, hi = e;
+          if (hi < lo) { const double tmp = lo; lo = hi; hi = tmp; }
+          const double w = hi - lo;
+          if (w <= 0.0) {
+            const int64_t h2 = (int64_t)floor(lo / dt);
+            if (h2 < H && h2 - h < K && h2 >= h) Rr[IDX2(IDX2(h2 - h, h, H), m, n_pairs)] += 1.0 / n_days;
+          } else {
+            const int64_t h2a = (int64_t)floor(lo / dt), h2b = (int64_t)floor(hi / dt);
+            for (int64_t h2 = h2a; h2 <= h2b; ++h2) {
+              if (h2 >= H || h2 - h >= K || h2 < h) continue;
+              Rr[IDX2(IDX2(h2 - h, h, H), m, n_pairs)] += overlap(lo, hi, h2, dt) / w / n_days;
+            }
+          }
+          s += link_time(len, sp, H_speed, dt, a, s);
+          e += link_time(len, sp, H_speed, dt, a, e);
+        }
+      }
+  }
+  return 0;
+}

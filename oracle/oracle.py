@@ -34,7 +34,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 __all__ = ["build_oracle", "Dims", "apply", "adjoint", "loss", "grad", "kkt", "r2", "spgd_day",
            "spgd_step", "spgd", "metrics", "route_softmax", "rho_from_logits", "loss_backward",
-           "logits_backward", "fixed_step_eta", "lib"]
+           "logits_backward", "fixed_step_eta", "dar_from_speeds", "lib"]
 
 
 def build_oracle(force: bool = True) -> str:
@@ -87,6 +87,9 @@ def lib():
         L.orc_loss_backward.restype = None
         L.orc_logits_backward.argtypes = [dims, ctypes.c_int32, iptr, iptr, iptr, dptr, dptr, iptr,
                                           iptr, dptr, dptr]
+        i32 = ctypes.c_int32
+        L.orc_dar_from_speeds.argtypes = [i32, iptr, iptr, i32, dptr, dptr, i32, i32,
+                                          ctypes.c_double, i32, i32, dptr]
         _lib = L
     return _lib
 
@@ -347,3 +350,27 @@ def fixed_step_eta(inst, c=0, iters=200):
         lam = float(np.sqrt(np.sum(w * w)) / np.sqrt(np.sum(v * v)))
         v = w / np.sqrt(np.sum(w * w))
     return 1.0 / lam
+
+
+def dar_from_speeds(path_ptr, path_link, link_len, speed, dt, H, K):
+    """Dynamic assignment ratios from link speeds (eqs. "dar", "cost"; see
+    orc_dar_from_speeds): speed is [n_days][L][H_speed] (or [L][H_speed] for
+    one day), link_len [L] in the same distance unit, dt in the time unit of
+    length/speed.  Returns Rr[K][H][n_pairs], the mean over the days."""
+    path_ptr, pp = _i(np.asarray(path_ptr))
+    path_link, plp = _i(np.asarray(path_link))
+    sp = np.asarray(speed, dtype=np.float64)
+    if sp.ndim == 2:
+        sp = sp[None]
+    n_days, L, H_speed = sp.shape
+    ln, lnp = _d(np.asarray(link_len, dtype=np.float64))
+    sp, spp = _d(sp)
+    n_paths = path_ptr.shape[0] - 1
+    n_pairs = int(path_ptr[-1])
+    out = np.zeros((K, H, n_pairs))
+    _, op = _d(out)
+    rc = lib().orc_dar_from_speeds(n_paths, pp, plp, L, lnp, spp, n_days, H_speed,
+                                   ctypes.c_double(dt), H, K, op)
+    if rc != 0:
+        raise RuntimeError(f"orc_dar_from_speeds failed ({rc})")
+    return out

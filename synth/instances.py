@@ -380,3 +380,63 @@ def make_route_instance(P=4, L=6, T=12, K=3, n_paths=150, sizes=(7,), link_prob=
                          pair_ptr=pair_ptr, pair_link=pair_link, pair_nz=pair_nz,
                          row_ptr=row_ptr, col_idx=col_idx, R=R, pi_true=pi_true, z0=z0,
                          qstar=qstar, x=x, day_cluster=day_cluster, sizes=tuple(sizes), seed=seed)
+
+
+@dataclass
+class SpeedInstance:
+    """Corridor network with ordered routes and per-day link speeds (for the
+    dynamic assignment ratios of paths)."""
+    L: int
+    H: int
+    dt: float                 # minutes per interval
+    path_ptr: np.ndarray      # [n_paths+1] int32
+    path_link: np.ndarray     # [n_pairs] int32, links of each path in traversal order
+    link_len: np.ndarray      # [L] miles
+    speed: np.ndarray         # [D][L][H] float32, miles per minute
+    day_cluster: np.ndarray   # [D] int32
+    sizes: tuple
+    seed: int
+
+
+def make_speed_instance(L=500, P=150, H=288, sizes=(400, 250, 150, 120, 80, 50, 30, 15),
+                        inc=0.08, dt=5.0, seed=BASE_SEED + 600, progress=None) -> SpeedInstance:
+    """Routes of the corridor pattern (each OD one path: round(inc*L) consecutive
+    links of one of 4 corridor-directions, in driving order), link lengths
+    U(0.15, 0.35) mi, free-flow speed 65 mph, and per-day speeds
+    v = vff * (1 - depth_c * congestion(t)) * (1 + 0.05 N(0,1)) clipped to
+    [5, 80] mph.  The congestion profile has AM and PM peaks; its depth depends
+    on the cluster (deep weekday-like patterns down to shallow weekend-like
+    ones) and on the corridor-direction (AM peak inbound, PM outbound)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ncor = 4
+    seg = L // ncor
+    m = max(1, int(round(inc * L)))
+    cor = rng.integers(0, ncor, size=P)
+    org = rng.integers(0, seg - m + 1, size=P)
+    order = np.lexsort((org, cor))
+    cor, org = cor[order], org[order]
+    path_link = np.concatenate([cor[p] * seg + org[p] + np.arange(m) for p in range(P)]).astype(np.int32)
+    path_ptr = (np.arange(P + 1) * m).astype(np.int32)
+    link_len = rng.uniform(0.15, 0.35, size=L)
+    C = len(sizes)
+    D = int(sum(sizes))
+    day_cluster = np.repeat(np.arange(C, dtype=np.int32), sizes)
+    tau = (np.arange(H) + 0.5) * dt / 60.0                          # hour of day
+    am = np.exp(-(tau - 8.0) ** 2 / 2.0)
+    pm = np.exp(-(tau - 17.5) ** 2 / (2 * 1.25 ** 2))
+    depth = np.linspace(0.6, 0.1, C)                                 # per cluster
+    link_cor = np.arange(L) // seg
+    inbound = (link_cor % 2 == 0)[:, None]                           # [L][1]
+    vff = 65.0 / 60.0                                                # miles per minute
+    speed = np.empty((D, L, H), dtype=np.float32)
+    for c in range(C):
+        prof = np.where(inbound, am[None, :] + 0.4 * pm[None, :], 0.4 * am[None, :] + pm[None, :])
+        base = vff * (1.0 - depth[c] * prof)                          # [L][H]
+        for d in np.nonzero(day_cluster == c)[0]:
+            v = base * (1.0 + 0.05 * rng.standard_normal((L, H)))
+            speed[d] = np.clip(v, 5.0 / 60.0, 80.0 / 60.0)
+        if progress:
+            progress(f"speeds of cluster {c + 1}/{C}")
+    return SpeedInstance(L=L, H=H, dt=dt, path_ptr=path_ptr, path_link=path_link,
+                         link_len=link_len, speed=speed, day_cluster=day_cluster,
+                         sizes=tuple(sizes), seed=seed)
