@@ -245,6 +245,37 @@ dode_status dar_logits_bwd(const dode_routes* routes, int32_t f64, const void* R
                            const void* dW, void* dz, void* stream);
 
 /*
+ * Dynamic assignment ratios of paths from link speeds (section "Dynamic
+ * assignment ratio", eqs. "dar2"/"dar" and Example "DAR matrix computation";
+ * section "Link/path travel time", eq. "cost").  All arrays are device memory.
+ *   path_ptr [n_paths+1], path_link [n_pairs]: the links of each path in the
+ *       order they are traversed; pair m = path_ptr[k] + i is the i-th link
+ *       of path k (the pair order of dode_routes_create)
+ *   link_len [L], speed [n_days][L][H_speed]: positive and finite, in
+ *       consistent units (e.g. miles and miles per minute); dt is the interval
+ *       length in the time unit of len/speed
+ *   Rr [K][H][n_pairs] (output): for departure interval t and lag l, the
+ *       share of the vehicles of path k departing in t that enter link i in
+ *       interval t+l, averaged over the n_days days (one ratio set per traffic
+ *       pattern).  Link a entered at time x is crossed in
+ *       len[a] / speed[a][floor(x/dt)] (the last interval's speed after the
+ *       day); an interval maps onto the window between the entry times of its
+ *       two boundary departures, and the ratios are the window's shares of the
+ *       observation intervals.  Shares past interval H-1 or at lags >= K are
+ *       dropped.
+ *   f64: nonzero for double arrays, else float.  K <= 16.
+ * Errors: DODE_ERR_SHAPE for malformed path tables, DODE_ERR_ARG for
+ * non-positive or non-finite lengths or speeds.  Synchronises `stream` (the
+ * path tables and the checks are read back); uses a scratch buffer of at
+ * most 256 MiB.
+ */
+dode_status dode_dar_from_speeds(int32_t n_paths, const int32_t* path_ptr,
+                                 const int32_t* path_link, int64_t n_pairs, int32_t L,
+                                 const void* link_len, const void* speed, int32_t n_days,
+                                 int32_t H_speed, double dt, int32_t H, int32_t K, int32_t f64,
+                                 void* Rr, void* stream);
+
+/*
  * Reusable form of spgd_solve for repeated or timed runs.  A plan holds
  *  - the minibatch schedule of every epoch (permutations, their inverses and
  *    the departure intervals each minibatch reaches),

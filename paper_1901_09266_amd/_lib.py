@@ -29,7 +29,7 @@ EXPORTS = ["dode_last_error", "dode_spgd_defaults", "dar_create", "dar_create_ex
            "spgd_solve", "spgd_plan_create", "spgd_plan_destroy", "spgd_plan_load",
            "spgd_plan_store", "spgd_run", "spgd_plan_timing", "spgd_plan_info",
            "dode_loss_bwd", "dode_routes_create", "dode_routes_destroy", "dar_from_logits",
-           "dar_logits_bwd"]
+           "dar_logits_bwd", "dode_dar_from_speeds"]
 
 
 class DodeError(RuntimeError):
@@ -70,6 +70,8 @@ def lib():
         L.dode_spgd_defaults.restype = None
         L.dar_create.argtypes = [P(Dims), i32, P(i32), P(i32), P(P(dbl)), i32, vp, P(vp)]
         L.dar_create_ex.argtypes = [P(Dims), i32, P(i32), P(i32), P(P(dbl)), i32, i32, vp, P(vp)]
+        L.dode_dar_from_speeds.argtypes = [i32, vp, vp, i64, i32, vp, vp, i32, i32, dbl, i32, i32,
+                                           i32, vp, vp]
         L.dar_destroy.argtypes = [vp]
         L.dar_info.argtypes = [vp, P(Dims), P(i32), P(i64), P(i32), P(i64)]
         L.dar_set_values.argtypes = [vp, i32, vp, vp]
@@ -427,3 +429,28 @@ def dar_logits_bwd(routes: Routes, Rr, z, dW, dz, stream=None):
                                 _ptr(z, "z", dt, (routes.n_paths,)),
                                 _ptr(dW, "dW", dt, (K, T, routes.nnz)),
                                 _ptr(dz, "dz", dt, (routes.n_paths,)), _stream(stream)))
+
+
+def dode_dar_from_speeds(path_ptr, path_link, link_len, speed, dt, H, K, Rr=None, stream=None):
+    """Dynamic assignment ratios from link speeds (device tensors): path_ptr
+    int32 [n_paths+1], path_link int32 [n_pairs] (links in traversal order),
+    link_len [L], speed [n_days][L][H_speed] (float32 or float64, one dtype).
+    Returns Rr [K][H][n_pairs], the day mean of the ratios."""
+    import torch
+    if speed.dim() == 2:
+        speed = speed.unsqueeze(0)
+    n_days, L, H_speed = speed.shape
+    f64 = speed.dtype == torch.float64
+    n_paths = path_ptr.numel() - 1
+    n_pairs = path_link.numel()
+    if Rr is None:
+        Rr = torch.empty((K, H, n_pairs), dtype=speed.dtype, device=speed.device)
+    for t in (path_ptr, path_link, link_len, speed, Rr):
+        if not t.is_contiguous():
+            raise ValueError("arrays must be contiguous")
+    if link_len.dtype != speed.dtype or Rr.dtype != speed.dtype:
+        raise ValueError("link_len, speed and Rr must share one dtype")
+    _check(lib().dode_dar_from_speeds(n_paths, path_ptr.data_ptr(), path_link.data_ptr(), n_pairs, L,
+                                      link_len.data_ptr(), speed.data_ptr(), n_days, H_speed,
+                                      float(dt), H, K, int(f64), Rr.data_ptr(), _stream(stream)))
+    return Rr

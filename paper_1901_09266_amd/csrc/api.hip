@@ -873,6 +873,55 @@ dode_status dar_logits_bwd(const dode_routes* routes, int32_t f64, const void* R
   return DODE_OK;
 }
 
+dode_status dode_dar_from_speeds(int32_t n_paths, const int32_t* path_ptr,
+                                 const int32_t* path_link, int64_t n_pairs, int32_t L,
+                                 const void* link_len, const void* speed, int32_t n_days,
+                                 int32_t H_speed, double dt, int32_t H, int32_t K, int32_t f64,
+                                 void* Rr, void* stream) {
+  if (n_paths < 1 || n_pairs < 0 || L < 1 || n_days < 1 || H_speed < 1 || H < 1)
+    return fail(DODE_ERR_SHAPE, "n_paths=%d n_pairs=%lld L=%d n_days=%d H_speed=%d H=%d", n_paths,
+                (long long)n_pairs, L, n_days, H_speed, H);
+  if (K < 1 || K > kMaxDarLags) return fail(DODE_ERR_SHAPE, "K=%d outside [1, %d]", K, kMaxDarLags);
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DODE_ERR_ARG, "dt=%g must be positive", dt);
+  if (!path_ptr || !path_link || !link_len || !speed || !Rr)
+    return fail(DODE_ERR_ARG, "path_ptr, path_link, link_len, speed or Rr is NULL");
+  hipStream_t s = as_stream(stream);
+  // the path tables are small: check them on the host (every index a kernel
+  // will use), then the lengths and speeds on the device
+  std::vector<int32_t> hp(n_paths + 1), hl((size_t)n_pairs);
+  HIP_TRY(hipMemcpyAsync(hp.data(), path_ptr, hp.size() * 4, hipMemcpyDeviceToHost, s));
+  if (n_pairs) HIP_TRY(hipMemcpyAsync(hl.data(), path_link, hl.size() * 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (hp[0] != 0 || hp[n_paths] != n_pairs)
+    return fail(DODE_ERR_SHAPE, "path_ptr must run from 0 to n_pairs=%lld", (long long)n_pairs);
+  for (int32_t k = 0; k < n_paths; ++k)
+    if (hp[k + 1] < hp[k]) return fail(DODE_ERR_SHAPE, "path_ptr decreases at path %d", k);
+  for (int64_t m = 0; m < n_pairs; ++m)
+    if (hl[m] < 0 || hl[m] >= L)
+      return fail(DODE_ERR_SHAPE, "path_link[%lld]=%d outside [0, L)", (long long)m, hl[m]);
+  {
+    DevBuf flag;
+    HIP_TRY(flag.alloc(4, s));
+    HIP_TRY(fill_zero(false, flag.p, 1, s));
+    HIP_TRY(dar_check_speeds(f64 != 0, link_len, L, flag.as<int32_t>(), s));
+    HIP_TRY(dar_check_speeds(f64 != 0, speed, (int64_t)n_days * L * H_speed, flag.as<int32_t>(), s));
+    int32_t h = 0;
+    HIP_TRY(hipMemcpyAsync(&h, flag.p, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (h) return fail(DODE_ERR_ARG, "link lengths and speeds must be positive and finite");
+  }
+  // trajectory scratch for a chunk of days, at most 256 MiB
+  const size_t ss = f64 ? 8 : 4;
+  const size_t per_day = (size_t)n_pairs * (H + 1) * ss;
+  const int32_t chunk =
+      (int32_t)std::max<size_t>(1, std::min<size_t>(n_days, (size_t(256) << 20) / std::max<size_t>(per_day, 1)));
+  DevBuf traj;
+  HIP_TRY(traj.alloc(std::max<size_t>(per_day * chunk, 16), s));
+  HIP_TRY(dar_from_speeds(f64 != 0, n_paths, path_ptr, path_link, n_pairs, L, link_len, speed, n_days,
+                          H_speed, dt, H, K, traj.p, chunk, Rr, s));
+  return DODE_OK;
+}
+
 dode_status spgd_step(const dode_dar* dar, int32_t cluster, const int32_t* chunk_h, int32_t n_h,
                       const void* X, void* Q, void* A, int32_t n_days,
                       const dode_spgd_params* params, void* stream) {

@@ -1,0 +1,158 @@
+// Dynamic assignment ratios from link speeds (section "Dynamic assignment
+// ratio", eqs. "dar2"/"dar" and Example "DAR matrix computation"; section
+// "Link/path travel time", eq. "cost").
+//
+// Time is in minutes and observation intervals are [h*dt, (h+1)*dt).  A link
+// entered at time t is crossed in len/speed(interval of t); the last
+// interval's speed holds after the end of the day.  A vehicle of path k
+// departing at t enters the path's i-th link at tau_i(t): tau_0(t) = t,
+// tau_{i+1}(t) = tau_i(t) + c(tau_i(t)).  Departure interval h maps onto the
+// arrival window [tau_i(h dt), tau_i((h+1) dt)] at that link, and the ratio of
+// observation interval h2 is the share of the window inside it.
+//
+// Two kernels per chunk of days:
+//   k_trajectories  one thread per (day, path, boundary b in 0..H): the travel
+//                   time from the b*dt departure to the entry of every link of
+//                   the path, traj[day][pair][b] (pairs = (path, i) in path
+//                   order);
+//   k_dar_windows   one thread per (pair, departure interval h): the shares
+//                   of the day windows, [r_h, dt + r_{h+1}] relative to h*dt,
+//                   summed over the chunk's days in order, added into the
+//                   running sums; the last chunk divides by the day count.
+// Keeping times relative to the departure keeps the window arithmetic at the
+// precision of travel times (tens of minutes), not of times of day.
+#include "dode_internal.h"
+
+#include <algorithm>
+
+namespace {
+
+constexpr int kBlock = 256;
+
+template <typename S>
+__device__ __forceinline__ S link_time(const S* __restrict__ len, const S* __restrict__ speed_day,
+                                       int32_t H_speed, S dt, int32_t a, S t) {
+  int64_t h = static_cast<int64_t>(floor(t / dt));
+  h = h < 0 ? 0 : (h >= H_speed ? H_speed - 1 : h);
+  return len[a] / speed_day[(int64_t)a * H_speed + h];
+}
+
+template <typename S>
+__global__ void __launch_bounds__(kBlock)
+k_trajectories(int32_t n_paths, const int32_t* __restrict__ path_ptr,
+               const int32_t* __restrict__ path_link, int32_t L, const S* __restrict__ len,
+               const S* __restrict__ speed, int32_t day0, int32_t n_days, int32_t H_speed, S dt,
+               int32_t H, int64_t n_pairs, S* __restrict__ traj) {
+  const int64_t per_day = (int64_t)n_paths * (H + 1);
+  const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= per_day * n_days) return;
+  const int32_t d = (int32_t)(idx / per_day);
+  const int32_t k = (int32_t)((idx % per_day) / (H + 1));
+  const int32_t b = (int32_t)(idx % (H + 1));
+  const S* sp = speed + (int64_t)(day0 + d) * L * H_speed;
+  S* out = traj + (int64_t)d * n_pairs * (H + 1);
+  const S t0 = static_cast<S>(b) * dt;
+  S r = 0;   // travel time so far
+  for (int32_t m = path_ptr[k]; m < path_ptr[k + 1]; ++m) {
+    out[(int64_t)m * (H + 1) + b] = r;
+    r += link_time(len, sp, H_speed, dt, path_link[m], t0 + r);
+  }
+}
+
+template <typename S, int KMAX>
+__global__ void __launch_bounds__(kBlock)
+k_dar_windows(int64_t n_pairs, int32_t n_days_chunk, int32_t H, int32_t K, S dt,
+              const S* __restrict__ traj, bool first_chunk, bool last_chunk, int32_t n_days_total,
+              S* __restrict__ Rr) {
+  const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= n_pairs * H) return;
+  const int64_t m = idx / H;
+  const int32_t h = (int32_t)(idx % H);
+  S acc[KMAX];
+#pragma unroll
+  for (int l = 0; l < KMAX; ++l) acc[l] = first_chunk || l >= K ? S(0) : Rr[((int64_t)l * H + h) * n_pairs + m];
+  for (int32_t d = 0; d < n_days_chunk; ++d) {
+    const S* tr = traj + ((int64_t)d * n_pairs + m) * (H + 1);
+    // window relative to h*dt; observation interval h+l is [l*dt, (l+1)*dt)
+    S lo = tr[h], hi = dt + tr[h + 1];
+    if (hi < lo) {   // FIFO violation: the window between the two end points
+      const S tmp = lo;
+      lo = hi;
+      hi = tmp;
+    }
+    const S w = hi - lo;
+    const int64_t la = static_cast<int64_t>(floor(lo / dt));
+    if (w <= S(0)) {   // all of the interval arrives at one instant
+      if (h + la < H && la >= 0 && la < K)
+#pragma unroll
+        for (int ll = 0; ll < KMAX; ++ll)
+          if (ll == la) acc[ll] += S(1);
+      continue;
+    }
+    const int64_t lb = static_cast<int64_t>(floor(hi / dt));
+#pragma unroll
+    for (int ll = 0; ll < KMAX; ++ll) {
+      if (ll >= K || h + ll >= H || ll < la || ll > lb) continue;
+      const S a = fmax(lo, static_cast<S>(ll) * dt), b = fmin(hi, static_cast<S>(ll + 1) * dt);
+      if (b > a) acc[ll] += (b - a) / w;
+    }
+  }
+#pragma unroll
+  for (int l = 0; l < KMAX; ++l) {
+    if (l >= K) break;
+    Rr[((int64_t)l * H + h) * n_pairs + m] = last_chunk ? acc[l] / static_cast<S>(n_days_total) : acc[l];
+  }
+}
+
+template <typename S>
+__global__ void k_check_speeds(const S* __restrict__ x, int64_t n, int32_t* __restrict__ flag) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    if (!(x[i] > S(0)) || !isfinite(x[i])) *flag = 1;
+}
+
+unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+template <typename S>
+hipError_t run(int32_t n_paths, const int32_t* path_ptr, const int32_t* path_link, int64_t n_pairs,
+               int32_t L, const S* len, const S* speed, int32_t n_days, int32_t H_speed, S dt,
+               int32_t H, int32_t K, S* traj, int32_t chunk, S* Rr, hipStream_t s) {
+  for (int32_t d0 = 0; d0 < n_days; d0 += chunk) {
+    const int32_t nd = std::min(chunk, n_days - d0);
+    const int64_t n1 = (int64_t)nd * n_paths * (H + 1);
+    hipLaunchKernelGGL(k_trajectories<S>, dim3(blocks_for(n1)), dim3(kBlock), 0, s, n_paths,
+                       path_ptr, path_link, L, len, speed, d0, nd, H_speed, dt, H, n_pairs, traj);
+    const bool first = d0 == 0, last = d0 + nd >= n_days;
+    hipLaunchKernelGGL((k_dar_windows<S, kMaxDarLags>), dim3(blocks_for(n_pairs * H)), dim3(kBlock),
+                       0, s, n_pairs, nd, H, K, dt, traj, first, last, n_days, Rr);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t dar_check_speeds(bool f64, const void* speed, int64_t n, int32_t* flag, hipStream_t s) {
+  const unsigned b = (unsigned)std::min<int64_t>(4096, std::max<int64_t>(1, blocks_for(n)));
+  if (f64)
+    hipLaunchKernelGGL(k_check_speeds<double>, dim3(b), dim3(kBlock), 0, s,
+                       static_cast<const double*>(speed), n, flag);
+  else
+    hipLaunchKernelGGL(k_check_speeds<float>, dim3(b), dim3(kBlock), 0, s,
+                       static_cast<const float*>(speed), n, flag);
+  return hipGetLastError();
+}
+
+hipError_t dar_from_speeds(bool f64, int32_t n_paths, const int32_t* path_ptr,
+                           const int32_t* path_link, int64_t n_pairs, int32_t L, const void* len,
+                           const void* speed, int32_t n_days, int32_t H_speed, double dt, int32_t H,
+                           int32_t K, void* traj, int32_t chunk, void* Rr, hipStream_t s) {
+  if (f64)
+    return run<double>(n_paths, path_ptr, path_link, n_pairs, L, static_cast<const double*>(len),
+                       static_cast<const double*>(speed), n_days, H_speed, dt, H, K,
+                       static_cast<double*>(traj), chunk, static_cast<double*>(Rr), s);
+  return run<float>(n_paths, path_ptr, path_link, n_pairs, L, static_cast<const float*>(len),
+                    static_cast<const float*>(speed), n_days, H_speed, static_cast<float>(dt), H, K,
+                    static_cast<float*>(traj), chunk, static_cast<float*>(Rr), s);
+}

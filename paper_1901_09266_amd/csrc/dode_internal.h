@@ -320,6 +320,16 @@ hipError_t permute_loss(const double* src, const int32_t* order, int32_t D, doub
 hipError_t set_counter(int32_t* c, int32_t v, hipStream_t s);
 hipError_t bump_counter(int32_t* c, hipStream_t s);
 
+// ---- dynamic assignment ratios from link speeds (dar_kernels.hip) -------
+constexpr int32_t kMaxDarLags = 16;
+// flag = 1 if any of the n values is not positive and finite
+hipError_t dar_check_speeds(bool f64, const void* speed, int64_t n, int32_t* flag, hipStream_t s);
+// Rr[K][H][n_pairs] = day mean of the ratios; traj = scratch for `chunk` days
+hipError_t dar_from_speeds(bool f64, int32_t n_paths, const int32_t* path_ptr,
+                           const int32_t* path_link, int64_t n_pairs, int32_t L, const void* len,
+                           const void* speed, int32_t n_days, int32_t H_speed, double dt, int32_t H,
+                           int32_t K, void* traj, int32_t chunk, void* Rr, hipStream_t s);
+
 // ---- MFMA tile kernels (mfma_kernels.hip) -------------------------------
 // corr: multiply with the corrected FP8 values (refinement steps)
 hipError_t mfma_chunk_resid(const dode_dar* dar, const ChunkSched& cs, const DayGroups& dg,
