@@ -253,6 +253,68 @@ def cpu_baseline(inst, perms_full, target_s=20.0, epochs=300):
                 Q=Q, sample=sample, per_cluster=per_cluster)
 
 
+def dar_bench(args):
+    """Dynamic assignment ratios from link speeds for every day, averaged per
+    traffic pattern: the corridor network of the config-3 workload (150 paths
+    of 40 links over 500 links), 288 five-minute intervals, K = 6 lags,
+    1095 days in 8 clusters.  A step is the whole job: one call per cluster."""
+    import torch
+    import paper_1901_09266_amd as dode
+    from synth import make_speed_instance
+    t0 = time.time()
+    si = make_speed_instance(progress=lambda m: log(f"generating: {m} ({time.time() - t0:.0f}s)"))
+    K, H = 6, si.H
+    dev = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dt)
+    pp, pl = dev(si.path_ptr, torch.int32), dev(si.path_link, torch.int32)
+    ln, sp = dev(si.link_len, torch.float32), dev(si.speed, torch.float32)
+    n_pairs = si.path_link.shape[0]
+    C = int(si.day_cluster.max()) + 1
+    days = [np.nonzero(si.day_cluster == c)[0] for c in range(C)]
+    outs = [torch.empty((K, H, n_pairs), dtype=torch.float32, device="cuda") for _ in range(C)]
+
+    def step():
+        for c in range(C):
+            dode.dode_dar_from_speeds(pp, pl, ln, sp[days[c][0]:days[c][-1] + 1], si.dt, H, K, Rr=outs[c])
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    D = int(si.day_cluster.shape[0])
+    # algorithmic bytes per step: every day's speeds read once, every pattern's
+    # ratios written once (the trajectory scratch is the implementation's)
+    byts = D * si.L * H * 4 + C * K * H * n_pairs * 4
+    achieved = byts / (ms / args.steps / 1e3) / 1e9
+    out = {"metric": "DAR construction days/sec", "value": round(D * args.steps / (ms / 1e3), 1),
+           "unit": "days/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(ms / args.steps, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{si.path_ptr.shape[0] - 1} paths of 40 links on 500 corridor links, "
+                                  f"H=288, K={K}, {D} days in {C} patterns (400..15)"},
+           "roofline": {"bound": "hbm", "kernel": "dode_dar_from_speeds (whole call, all patterns)",
+                        "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                        "bytes_per_step": byts}}
+    if not args.skip_cpu:
+        import oracle as orc
+        sample = days[0][:8]
+        t1 = time.perf_counter()
+        Ro = orc.dar_from_speeds(si.path_ptr, si.path_link, si.link_len,
+                                 si.speed[sample].astype(np.float64), si.dt, H, K)
+        dt_cpu = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": round(len(sample) / dt_cpu, 3), "unit": "days/s", "cores": 1,
+                               "kind": "oracle", "sample": f"{len(sample)} days of pattern 0, {dt_cpu:.1f}s"}
+        got = dode.dode_dar_from_speeds(pp, pl, ln, sp[sample[0]:sample[-1] + 1], si.dt, H, K)
+        out["check"] = {"max_abs_vs_oracle_sample": float(np.max(np.abs(got.cpu().numpy() - Ro)))}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -267,6 +329,8 @@ def main():
     ap.add_argument("--refine", type=int, default=None,
                     help="full-batch refinement steps per epoch on corrected FP8 values "
                          "(default: 2 for the FP8 form of config 5, else 0)")
+    ap.add_argument("--dar", action="store_true",
+                    help="measure dynamic assignment ratio construction from link speeds instead")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 512 MiB device copy first (reference for traffic counters)")
     args = ap.parse_args()
@@ -276,6 +340,9 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.dar:
+        dar_bench(args)
+        return
     import torch
     import paper_1901_09266_amd as dode
     from synth import make_config, make_perms, chunk_h_blocks

@@ -910,11 +910,11 @@ dode_status dode_dar_from_speeds(int32_t n_paths, const int32_t* path_ptr,
     HIP_TRY(hipStreamSynchronize(s));
     if (h) return fail(DODE_ERR_ARG, "link lengths and speeds must be positive and finite");
   }
-  // trajectory scratch for a chunk of days, at most 256 MiB
+  // trajectory scratch for a chunk of days, at most 1 GiB (at least one day)
   const size_t ss = f64 ? 8 : 4;
   const size_t per_day = (size_t)n_pairs * (H + 1) * ss;
-  const int32_t chunk =
-      (int32_t)std::max<size_t>(1, std::min<size_t>(n_days, (size_t(256) << 20) / std::max<size_t>(per_day, 1)));
+  const size_t cap = std::max<size_t>(1, (size_t(1) << 30) / std::max<size_t>(per_day, 1));
+  const int32_t chunk = (int32_t)std::min<size_t>((size_t)n_days, cap);
   DevBuf traj;
   HIP_TRY(traj.alloc(std::max<size_t>(per_day * chunk, 16), s));
   HIP_TRY(dar_from_speeds(f64 != 0, n_paths, path_ptr, path_link, n_pairs, L, link_len, speed, n_days,

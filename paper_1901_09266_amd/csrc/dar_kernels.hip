@@ -19,6 +19,9 @@
 //                   of the day windows, [r_h, dt + r_{h+1}] relative to h*dt,
 //                   summed over the chunk's days in order, added into the
 //                   running sums; the last chunk divides by the day count.
+//                   The share of interval h+l is F((l+1) dt) - F(l dt), with
+//                   F(x) = clamp((x - lo) / w, 0, 1) the fraction of the window
+//                   before x (the window's overlap with the interval over w).
 // Keeping times relative to the departure keeps the window arithmetic at the
 // precision of travel times (tens of minutes), not of times of day.
 #include "dode_internal.h"
@@ -68,33 +71,48 @@ k_dar_windows(int64_t n_pairs, int32_t n_days_chunk, int32_t H, int32_t K, S dt,
   if (idx >= n_pairs * H) return;
   const int64_t m = idx / H;
   const int32_t h = (int32_t)(idx % H);
+  const int kk = min(K, H - h);   // lags that stay inside the day
   S acc[KMAX];
 #pragma unroll
   for (int l = 0; l < KMAX; ++l) acc[l] = first_chunk || l >= K ? S(0) : Rr[((int64_t)l * H + h) * n_pairs + m];
-  for (int32_t d = 0; d < n_days_chunk; ++d) {
-    const S* tr = traj + ((int64_t)d * n_pairs + m) * (H + 1);
-    // window relative to h*dt; observation interval h+l is [l*dt, (l+1)*dt)
-    S lo = tr[h], hi = dt + tr[h + 1];
-    if (hi < lo) {   // FIFO violation: the window between the two end points
-      const S tmp = lo;
-      lo = hi;
-      hi = tmp;
+  const int64_t day_stride = n_pairs * (H + 1);
+  const S* tr = traj + m * (H + 1) + h;
+  constexpr int kDays = 4;   // loads of four days in flight together
+  for (int32_t d0 = 0; d0 < n_days_chunk; d0 += kDays) {
+    S lo[kDays], hi[kDays];
+#pragma unroll
+    for (int u = 0; u < kDays; ++u) {
+      const int64_t d = min(d0 + u, n_days_chunk - 1);
+      // window relative to h*dt; observation interval h+l is [l*dt, (l+1)*dt)
+      lo[u] = tr[d * day_stride];
+      hi[u] = dt + tr[d * day_stride + 1];
     }
-    const S w = hi - lo;
-    const int64_t la = static_cast<int64_t>(floor(lo / dt));
-    if (w <= S(0)) {   // all of the interval arrives at one instant
-      if (h + la < H && la >= 0 && la < K)
+#pragma unroll
+    for (int u = 0; u < kDays; ++u) {
+      if (d0 + u >= n_days_chunk) break;
+      S a0 = lo[u], b0 = hi[u];
+      if (b0 < a0) {   // FIFO violation: the window between the two end points
+        const S tmp = a0;
+        a0 = b0;
+        b0 = tmp;
+      }
+      const S w = b0 - a0;
+      if (w <= S(0)) {   // all of the interval arrives at one instant
+        const int64_t la = static_cast<int64_t>(floor(a0 / dt));
 #pragma unroll
         for (int ll = 0; ll < KMAX; ++ll)
-          if (ll == la) acc[ll] += S(1);
-      continue;
-    }
-    const int64_t lb = static_cast<int64_t>(floor(hi / dt));
+          if (ll == la && ll < kk) acc[ll] += S(1);
+        continue;
+      }
+      const S inv_w = S(1) / w;
+      S f_prev = S(0);   // F(0) = 0: windows start at or after their departure
 #pragma unroll
-    for (int ll = 0; ll < KMAX; ++ll) {
-      if (ll >= K || h + ll >= H || ll < la || ll > lb) continue;
-      const S a = fmax(lo, static_cast<S>(ll) * dt), b = fmin(hi, static_cast<S>(ll + 1) * dt);
-      if (b > a) acc[ll] += (b - a) / w;
+      for (int ll = 0; ll < KMAX; ++ll) {
+        const S x = (static_cast<S>(ll + 1) * dt - a0) * inv_w;
+        const S f = x < S(0) ? S(0) : (x > S(1) ? S(1) : x);
+        if (ll < kk) acc[ll] += f - f_prev;
+        f_prev = f;
+      }
     }
   }
 #pragma unroll
@@ -123,8 +141,12 @@ hipError_t run(int32_t n_paths, const int32_t* path_ptr, const int32_t* path_lin
     hipLaunchKernelGGL(k_trajectories<S>, dim3(blocks_for(n1)), dim3(kBlock), 0, s, n_paths,
                        path_ptr, path_link, L, len, speed, d0, nd, H_speed, dt, H, n_pairs, traj);
     const bool first = d0 == 0, last = d0 + nd >= n_days;
-    hipLaunchKernelGGL((k_dar_windows<S, kMaxDarLags>), dim3(blocks_for(n_pairs * H)), dim3(kBlock),
-                       0, s, n_pairs, nd, H, K, dt, traj, first, last, n_days, Rr);
+    if (K <= 8)
+      hipLaunchKernelGGL((k_dar_windows<S, 8>), dim3(blocks_for(n_pairs * H)), dim3(kBlock), 0, s,
+                         n_pairs, nd, H, K, dt, traj, first, last, n_days, Rr);
+    else
+      hipLaunchKernelGGL((k_dar_windows<S, kMaxDarLags>), dim3(blocks_for(n_pairs * H)),
+                         dim3(kBlock), 0, s, n_pairs, nd, H, K, dt, traj, first, last, n_days, Rr);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

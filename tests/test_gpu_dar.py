@@ -43,9 +43,9 @@ def test_matches_oracle_ragged_paths(f64):
 
 
 def test_several_day_chunks_fp32():
-    """80 days of a 500-link corridor need several trajectory chunks (256 MiB
-    each); the chunked day mean must equal the oracle's."""
-    si = make_speed_instance(L=500, P=150, H=288, sizes=(80,), seed=12)
+    """160 days of a 500-link corridor need two trajectory chunks (1 GiB, 154
+    days each); the chunked day mean must equal the oracle's."""
+    si = make_speed_instance(L=500, P=150, H=288, sizes=(160,), seed=12)
     say("dar chunks")
     R = run(si, 6, si.dt, si.speed, f64=False)
     torch.cuda.synchronize()
@@ -56,7 +56,7 @@ def test_several_day_chunks_fp32():
     # precision than the oracle's): one link's travel time then changes by up
     # to len*|1/v1 - 1/v2| ~ 0.03 min, 6e-3 of a 5-minute window, on that day
     # only.  Such flips are rare: bound the mean error by 1e-6 and the largest
-    # (a flip averaged over the 80 days, or a few) by 2e-3.
+    # (a flip averaged over the 160 days, or a few) by 2e-3.
     err = np.abs(R.cpu().numpy() - Ro)
     assert err.mean() <= 1e-6 and err.max() <= 2e-3
 
