@@ -453,3 +453,70 @@ int orc_dar_from_speeds(int32_t n_paths, const int32_t* path_ptr, const int32_t*
   }
   return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * Route choice portions from mean path travel times (section "Route choice
+ * portions", eqs. "logit" and "rt"; section "Link/path travel time",
+ * eq. "cost") and the assignment matrix they give (eq. "assign").
+ *
+ * Path cost: c_k(t1) is the time a vehicle departing at t1 needs to cross
+ * every link of path k in order, each link timed at the speed of the interval
+ * in which the vehicle enters it (the link time of orc_dar_from_speeds).  The
+ * portions of interval t use the departure at the interval's start, t1 = t*dt
+ * (eq. "rt" holds them constant over the interval), and c~ is the mean of the
+ * n_days days' costs.  Output cost[T][n_paths].
+ * ---------------------------------------------------------------------- */
+int orc_path_costs(int32_t n_paths, const int32_t* path_ptr, const int32_t* path_link, int32_t L,
+                   const double* len, const double* speed, int32_t n_days, int32_t H_speed,
+                   double dt, int32_t T, double* cost) {
+  memset(cost, 0, sizeof(double) * (size_t)T * n_paths);
+  if (n_days < 1) return 0;
+  for (int32_t t = 0; t < T; ++t)
+    for (int32_t k = 0; k < n_paths; ++k) {
+      double sum = 0.0;
+      for (int32_t d = 0; d < n_days; ++d) {
+        const double* sp = speed + (int64_t)d * L * H_speed;
+        const double t1 = t * dt;
+        double tau = t1; /* entry time of the current link */
+        for (int32_t m = path_ptr[k]; m < path_ptr[k + 1]; ++m)
+          tau += link_time(len, sp, H_speed, dt, path_link[m], tau);
+        sum += tau - t1;
+      }
+      cost[IDX2(t, k, n_paths)] = sum / n_days;
+    }
+  return 0;
+}
+
+/* p[t][k] = exp(-theta c[t][k]) / sum over the paths k' of od(k) of
+ * exp(-theta c[t][k']) (eq. "logit", interval-wise per eq. "rt"). */
+void orc_logit_portions(int32_t P, int32_t n_paths, const int32_t* path_od, int32_t T, double theta,
+                        const double* cost, double* p) {
+  double* z = (double*)malloc(sizeof(double) * (size_t)n_paths);
+  for (int32_t t = 0; t < T; ++t) {
+    for (int32_t k = 0; k < n_paths; ++k) z[k] = -theta * cost[IDX2(t, k, n_paths)];
+    orc_route_softmax(P, n_paths, path_od, z, p + (int64_t)t * n_paths);
+  }
+  free(z);
+}
+
+/* B of eq. "assign" with time-dependent portions: W[l][t][nz=(a,p)] = sum
+ * over the paths k of OD p that cross link a of Rr[l][t][pair (k,a)] *
+ * p[t][k]; the pair's delta is 1 by construction.  Rr [K][T][n_pairs],
+ * p [T][n_paths]. */
+int orc_rho_from_portions(const orc_dims* dm, int32_t n_paths, const int32_t* path_od,
+                          const int32_t* pair_ptr, const int32_t* pair_link, const double* Rr,
+                          const double* p, const int32_t* row_ptr, const int32_t* col,
+                          double* W_out) {
+  const int64_t nnz = row_ptr[dm->L], npairs = pair_ptr[n_paths];
+  memset(W_out, 0, sizeof(double) * (size_t)(dm->K * dm->T * nnz));
+  for (int32_t k = 0; k < n_paths; ++k)
+    for (int32_t m = pair_ptr[k]; m < pair_ptr[k + 1]; ++m) {
+      const int32_t j = find_nz(row_ptr, col, pair_link[m], path_od[k]);
+      if (j < 0) return 1;
+      for (int l = 0; l < dm->K; ++l)
+        for (int t = 0; t < dm->T; ++t)
+          W_out[((int64_t)l * dm->T + t) * nnz + j] +=
+              Rr[((int64_t)l * dm->T + t) * npairs + m] * p[IDX2(t, k, n_paths)];
+    }
+  return 0;
+}

@@ -11,6 +11,12 @@ What each entry point follows in the paper (arXiv 1901.09266):
   kkt, r2     end-of-solve checks (Step 6 "Quality check")
   rho_from_logits, loss_backward, logits_backward
               eqs. "logit", "flow", "assign" with free logits per path
+  dar_from_speeds
+              eqs. "dar2"/"dar", "cost": ratios from link speeds
+  path_costs, logit_portions, rho_from_portions
+              eqs. "cost", "logit", "rt", "assign": route portions from the
+              mean path travel time of a pattern's days, and the assignment
+              matrix they give
 
 Pins (tests/test_oracle_pins.py): brute-force active-set enumeration, scipy's
 Lawson-Hanson NNLS, planted noiseless recovery, KKT conditions, the adjoint
@@ -34,7 +40,8 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 __all__ = ["build_oracle", "Dims", "apply", "adjoint", "loss", "grad", "kkt", "r2", "spgd_day",
            "spgd_step", "spgd", "metrics", "route_softmax", "rho_from_logits", "loss_backward",
-           "logits_backward", "fixed_step_eta", "dar_from_speeds", "lib"]
+           "logits_backward", "fixed_step_eta", "dar_from_speeds", "path_costs", "logit_portions",
+           "rho_from_portions", "lib"]
 
 
 def build_oracle(force: bool = True) -> str:
@@ -90,6 +97,12 @@ def lib():
         i32 = ctypes.c_int32
         L.orc_dar_from_speeds.argtypes = [i32, iptr, iptr, i32, dptr, dptr, i32, i32,
                                           ctypes.c_double, i32, i32, dptr]
+        L.orc_path_costs.argtypes = [i32, iptr, iptr, i32, dptr, dptr, i32, i32, ctypes.c_double,
+                                     i32, dptr]
+        L.orc_logit_portions.argtypes = [i32, i32, iptr, i32, ctypes.c_double, dptr, dptr]
+        L.orc_logit_portions.restype = None
+        L.orc_rho_from_portions.argtypes = [dims, i32, iptr, iptr, iptr, dptr, dptr, iptr, iptr,
+                                            dptr]
         _lib = L
     return _lib
 
@@ -374,3 +387,54 @@ def dar_from_speeds(path_ptr, path_link, link_len, speed, dt, H, K):
     if rc != 0:
         raise RuntimeError(f"orc_dar_from_speeds failed ({rc})")
     return out
+
+
+def path_costs(path_ptr, path_link, link_len, speed, dt, T):
+    """Mean path travel time per departure interval (eqs. "cost", "logit",
+    "rt"; see orc_path_costs): speed [n_days][L][H_speed] (or [L][H_speed]),
+    departures at t*dt for t < T.  Returns cost[T][n_paths]."""
+    path_ptr, pp = _i(np.asarray(path_ptr))
+    path_link, plp = _i(np.asarray(path_link))
+    sp = np.asarray(speed, dtype=np.float64)
+    if sp.ndim == 2:
+        sp = sp[None]
+    n_days, L, H_speed = sp.shape
+    ln, lnp = _d(np.asarray(link_len, dtype=np.float64))
+    sp, spp = _d(sp)
+    n_paths = path_ptr.shape[0] - 1
+    out = np.zeros((T, n_paths))
+    _, op = _d(out)
+    rc = lib().orc_path_costs(n_paths, pp, plp, L, lnp, spp, n_days, H_speed, ctypes.c_double(dt),
+                              T, op)
+    if rc != 0:
+        raise RuntimeError(f"orc_path_costs failed ({rc})")
+    return out
+
+
+def logit_portions(P, path_od, theta, cost):
+    """Route portions p[T][n_paths] = per-OD softmax of -theta * cost[T][n_paths]
+    (eqs. "logit", "rt")."""
+    path_od, pop = _i(path_od)
+    cost, cp = _d(cost)
+    T, n_paths = cost.shape
+    out = np.zeros((T, n_paths))
+    lib().orc_logit_portions(P, n_paths, pop, T, ctypes.c_double(theta), cp, _d(out)[1])
+    return out
+
+
+def rho_from_portions(P, L, T, H, K, path_od, pair_ptr, pair_link, row_ptr, col_idx, Rr, p):
+    """W[K][T][nnz] of eq. "assign" from ratios Rr[K][T][n_pairs] and
+    time-dependent portions p[T][n_paths]."""
+    dims = _dims(P, L, T, H, K)
+    po, pop = _i(path_od)
+    pp_, ppp = _i(pair_ptr)
+    pl, plp = _i(pair_link)
+    R, Rp = _d(Rr)
+    pv, pvp = _d(p)
+    rp, rpp = _i(row_ptr)
+    ci, cip = _i(col_idx)
+    W = np.zeros((K, T, ci.shape[0]))
+    rc = lib().orc_rho_from_portions(dims, po.shape[0], pop, ppp, plp, Rp, pvp, rpp, cip, _d(W)[1])
+    if rc != 0:
+        raise RuntimeError("pair not in pattern")
+    return W

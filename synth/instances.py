@@ -440,3 +440,119 @@ def make_speed_instance(L=500, P=150, H=288, sizes=(400, 250, 150, 120, 80, 50, 
     return SpeedInstance(L=L, H=H, dt=dt, path_ptr=path_ptr, path_link=path_link,
                          link_len=link_len, speed=speed, day_cluster=day_cluster,
                          sizes=tuple(sizes), seed=seed)
+
+
+@dataclass
+class ChoiceInstance:
+    """Corridor network with alternative routes per OD and per-day link speeds
+    (for route portions from mean path costs and the assignment matrix they
+    give).  Path k serves OD path_od[k] and crosses links
+    path_link[path_ptr[k]:path_ptr[k+1]] in driving order; the OD-level pattern
+    (row_ptr, col_idx) is the union of the path incidences, and pair_nz[m] is
+    the pattern entry that pair m feeds."""
+    P: int
+    L: int
+    T: int
+    H: int
+    K: int
+    dt: float                 # minutes per interval
+    path_od: np.ndarray       # [n_paths] int32
+    path_ptr: np.ndarray      # [n_paths+1] int32
+    path_link: np.ndarray     # [n_pairs] int32
+    pair_nz: np.ndarray       # [n_pairs] int32
+    row_ptr: np.ndarray       # [L+1] int32
+    col_idx: np.ndarray       # [nnz] int32
+    link_len: np.ndarray      # [L] miles
+    speed: np.ndarray         # [D][L][H] float32, miles per minute
+    day_cluster: np.ndarray   # [D] int32
+    sizes: tuple
+    seed: int
+
+    @property
+    def n_paths(self) -> int:
+        return int(self.path_od.shape[0])
+
+    @property
+    def n_pairs(self) -> int:
+        return int(self.path_link.shape[0])
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col_idx.shape[0])
+
+
+def make_choice_instance(L=500, P=150, H=288, K=6, sizes=(400, 250, 150, 120, 80, 50, 30, 15),
+                         m=20, dt=5.0, ragged=False, seed=BASE_SEED + 700,
+                         progress=None) -> ChoiceInstance:
+    """Each of 4 corridor-directions has a freeway and a parallel arterial of
+    L//8 links each (link i of one beside link i of the other).  OD p spans m
+    consecutive link positions of one corridor-direction and has three routes:
+    all freeway, all arterial, and freeway for the first half then arterial
+    (with ragged=True each OD keeps a random non-empty subset of them, and m
+    varies per OD in [m/2, m]).  Link lengths U(0.15, 0.35) mi (arterial links
+    1.1x); free-flow speed 65 mph on freeways, 35 mph on arterials; per-day
+    speeds v = vff * (1 - depth * congestion(t)) * (1 + 0.05 N(0,1)) clipped
+    to [5, 80] mph, with AM/PM peaks by direction, the freeway depth per
+    cluster from 0.7 down to 0.1 and the arterial depth 0.3 of it."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ncor = 4
+    seg = L // (2 * ncor)
+    if seg < m:
+        raise ValueError("corridor shorter than a route")
+    fw = lambda c, i: c * seg + i                     # freeway link i of corridor c
+    art = lambda c, i: ncor * seg + c * seg + i       # arterial link i of corridor c
+    cor = rng.integers(0, ncor, size=P)
+    path_od, links = [], []
+    for p in range(P):
+        mp = int(rng.integers((m + 1) // 2, m + 1)) if ragged else m
+        o = int(rng.integers(0, seg - mp + 1))
+        idx = np.arange(o, o + mp)
+        h = mp // 2
+        alts = [fw(cor[p], idx), art(cor[p], idx),
+                np.concatenate([fw(cor[p], idx[:h]), art(cor[p], idx[h:])])]
+        keep = [0, 1, 2]
+        if ragged:
+            while True:
+                keep = [i for i in range(3) if rng.random() < 0.6]
+                if keep:
+                    break
+        for i in keep:
+            path_od.append(p)
+            links.append(np.asarray(alts[i], dtype=np.int32))
+    path_od = np.asarray(path_od, dtype=np.int32)
+    path_ptr = np.zeros(len(links) + 1, dtype=np.int32)
+    path_ptr[1:] = np.cumsum([len(a) for a in links])
+    path_link = np.concatenate(links).astype(np.int32)
+    pair_path = np.repeat(np.arange(len(links)), np.diff(path_ptr))
+    S = np.zeros((L, P), dtype=bool)
+    S[path_link, path_od[pair_path]] = True
+    row_ptr, col_idx = _pattern_csr(S)
+    nzmap = -np.ones((L, P), dtype=np.int64)
+    rows = np.repeat(np.arange(L), np.diff(row_ptr))
+    nzmap[rows, col_idx] = np.arange(col_idx.shape[0])
+    pair_nz = nzmap[path_link, path_od[pair_path]].astype(np.int32)
+    is_art = np.arange(L) >= ncor * seg
+    link_len = rng.uniform(0.15, 0.35, size=L) * np.where(is_art, 1.1, 1.0)
+    C = len(sizes)
+    D = int(sum(sizes))
+    day_cluster = np.repeat(np.arange(C, dtype=np.int32), sizes)
+    tau = (np.arange(H) + 0.5) * dt / 60.0                          # hour of day
+    am = np.exp(-(tau - 8.0) ** 2 / 2.0)
+    pm = np.exp(-(tau - 17.5) ** 2 / (2 * 1.25 ** 2))
+    depth = np.linspace(0.7, 0.1, C)
+    inbound = ((np.arange(L) % (ncor * seg)) // seg % 2 == 0)[:, None]
+    prof = np.where(inbound, am[None, :] + 0.4 * pm[None, :], 0.4 * am[None, :] + pm[None, :])
+    vff = np.where(is_art, 35.0, 65.0)[:, None] / 60.0               # miles per minute
+    dscale = np.where(is_art, 0.3, 1.0)[:, None]
+    speed = np.empty((D, L, H), dtype=np.float32)
+    for c in range(C):
+        base = vff * (1.0 - depth[c] * dscale * prof)
+        for d in np.nonzero(day_cluster == c)[0]:
+            v = base * (1.0 + 0.05 * rng.standard_normal((L, H)))
+            speed[d] = np.clip(v, 5.0 / 60.0, 80.0 / 60.0)
+        if progress:
+            progress(f"speeds of cluster {c + 1}/{C}")
+    return ChoiceInstance(P=P, L=L, T=H, H=H, K=K, dt=dt, path_od=path_od, path_ptr=path_ptr,
+                          path_link=path_link, pair_nz=pair_nz, row_ptr=row_ptr, col_idx=col_idx,
+                          link_len=link_len, speed=speed, day_cluster=day_cluster,
+                          sizes=tuple(sizes), seed=seed)
