@@ -276,6 +276,41 @@ dode_status dode_dar_from_speeds(int32_t n_paths, const int32_t* path_ptr,
                                  void* Rr, void* stream);
 
 /*
+ * Mean path travel times of a traffic pattern (section "Route choice
+ * portions", eqs. "logit" and "rt"; section "Link/path travel time",
+ * eq. "cost").  Path tables, lengths and speeds as for dode_dar_from_speeds
+ * (device memory, same checks and errors).
+ *   cost [T][n_paths] (output, device): for departure interval t, the mean
+ *       over the n_days days of the time a vehicle leaving at t*dt needs to
+ *       cross every link of path k, each link at the speed of the interval in
+ *       which it is entered (the last interval's speed after the day).  The
+ *       start of the interval stands for the whole interval (eq. "rt").
+ *   f64: nonzero for double arrays, else float; days are summed in FP64.
+ * Synchronises `stream` (the path tables and checks are read back); uses a
+ * scratch buffer of at most 256 MiB.
+ */
+dode_status dode_path_costs(int32_t n_paths, const int32_t* path_ptr, const int32_t* path_link,
+                            int64_t n_pairs, int32_t L, const void* link_len, const void* speed,
+                            int32_t n_days, int32_t H_speed, double dt, int32_t T, int32_t f64,
+                            void* cost, void* stream);
+
+/*
+ * Assignment matrix from path costs (eqs. "logit", "rt", "flow", "assign"):
+ *   p[t][k] = exp(-theta cost[t][k]) / sum over the paths k' of OD(k) of
+ *             exp(-theta cost[t][k'])                       (FP64 softmax)
+ *   W[l][t][nz] = sum over the pairs m feeding nz of Rr[l][t][m] p[t][path(m)]
+ * routes from dode_routes_create; Rr dev [K][T][n_pairs] (e.g. the output of
+ * dode_dar_from_speeds when T = H, or its first T intervals), cost dev
+ * [T][n_paths] (finite, in the time unit theta is the inverse of: 0.01 per
+ * second is 0.6 per minute), W dev [K][T][nnz] (output), portions dev
+ * [T][n_paths] (output, may be NULL).  `f64` selects double (else float) for
+ * every array.  Asynchronous on `stream`; W can be installed with
+ * dar_set_values.
+ */
+dode_status dar_from_costs(const dode_routes* routes, int32_t f64, const void* Rr, const void* cost,
+                           double theta, void* portions, void* W, void* stream);
+
+/*
  * Reusable form of spgd_solve for repeated or timed runs.  A plan holds
  *  - the minibatch schedule of every epoch (permutations, their inverses and
  *    the departure intervals each minibatch reaches),

@@ -29,7 +29,7 @@ EXPORTS = ["dode_last_error", "dode_spgd_defaults", "dar_create", "dar_create_ex
            "spgd_solve", "spgd_plan_create", "spgd_plan_destroy", "spgd_plan_load",
            "spgd_plan_store", "spgd_run", "spgd_plan_timing", "spgd_plan_info",
            "dode_loss_bwd", "dode_routes_create", "dode_routes_destroy", "dar_from_logits",
-           "dar_logits_bwd", "dode_dar_from_speeds"]
+           "dar_logits_bwd", "dode_dar_from_speeds", "dode_path_costs", "dar_from_costs"]
 
 
 class DodeError(RuntimeError):
@@ -72,6 +72,8 @@ def lib():
         L.dar_create_ex.argtypes = [P(Dims), i32, P(i32), P(i32), P(P(dbl)), i32, i32, vp, P(vp)]
         L.dode_dar_from_speeds.argtypes = [i32, vp, vp, i64, i32, vp, vp, i32, i32, dbl, i32, i32,
                                            i32, vp, vp]
+        L.dode_path_costs.argtypes = [i32, vp, vp, i64, i32, vp, vp, i32, i32, dbl, i32, i32, vp, vp]
+        L.dar_from_costs.argtypes = [vp, i32, vp, vp, dbl, vp, vp, vp]
         L.dar_destroy.argtypes = [vp]
         L.dar_info.argtypes = [vp, P(Dims), P(i32), P(i64), P(i32), P(i64)]
         L.dar_set_values.argtypes = [vp, i32, vp, vp]
@@ -454,3 +456,42 @@ def dode_dar_from_speeds(path_ptr, path_link, link_len, speed, dt, H, K, Rr=None
                                       link_len.data_ptr(), speed.data_ptr(), n_days, H_speed,
                                       float(dt), H, K, int(f64), Rr.data_ptr(), _stream(stream)))
     return Rr
+
+
+def dode_path_costs(path_ptr, path_link, link_len, speed, dt, T, cost=None, stream=None):
+    """Mean path travel times of a pattern's days (device tensors, as for
+    dode_dar_from_speeds).  Returns cost [T][n_paths]: for departures at t*dt,
+    the day mean of the time to cross the whole path."""
+    import torch
+    if speed.dim() == 2:
+        speed = speed.unsqueeze(0)
+    n_days, L, H_speed = speed.shape
+    f64 = speed.dtype == torch.float64
+    n_paths = path_ptr.numel() - 1
+    n_pairs = path_link.numel()
+    if cost is None:
+        cost = torch.empty((T, n_paths), dtype=speed.dtype, device=speed.device)
+    for t in (path_ptr, path_link, link_len, speed, cost):
+        if not t.is_contiguous():
+            raise ValueError("arrays must be contiguous")
+    if link_len.dtype != speed.dtype or cost.dtype != speed.dtype:
+        raise ValueError("link_len, speed and cost must share one dtype")
+    if tuple(cost.shape) != (T, n_paths):
+        raise ValueError(f"cost must be [{T}][{n_paths}]")
+    _check(lib().dode_path_costs(n_paths, path_ptr.data_ptr(), path_link.data_ptr(), n_pairs, L,
+                                 link_len.data_ptr(), speed.data_ptr(), n_days, H_speed, float(dt),
+                                 T, int(f64), cost.data_ptr(), _stream(stream)))
+    return cost
+
+
+def dar_from_costs(routes: Routes, Rr, cost, theta, W, portions=None, stream=None):
+    """W [K][T][nnz] of eq. "assign" from ratios Rr [K][T][n_pairs] and logit
+    portions of the path costs cost [T][n_paths] (eqs. "logit", "rt"); the
+    portions are also written to `portions` [T][n_paths] when given."""
+    P, L, T, H, K = routes.dims
+    f64 = _route_dtype(cost)
+    dt = cost.dtype
+    pp = None if portions is None else _ptr(portions, "portions", dt, (T, routes.n_paths))
+    _check(lib().dar_from_costs(routes.handle, f64, _ptr(Rr, "Rr", dt, (K, T, routes.n_pairs)),
+                                _ptr(cost, "cost", dt, (T, routes.n_paths)), float(theta), pp,
+                                _ptr(W, "W", dt, (K, T, routes.nnz)), _stream(stream)))

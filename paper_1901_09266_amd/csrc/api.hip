@@ -873,6 +873,38 @@ dode_status dar_logits_bwd(const dode_routes* routes, int32_t f64, const void* R
   return DODE_OK;
 }
 
+namespace {
+
+// The path tables are small: check them on the host (every index a kernel
+// will use), then the lengths and speeds on the device.
+dode_status check_paths_speeds(int32_t n_paths, const int32_t* path_ptr, const int32_t* path_link,
+                               int64_t n_pairs, int32_t L, const void* link_len, const void* speed,
+                               int32_t n_days, int32_t H_speed, bool f64, hipStream_t s) {
+  std::vector<int32_t> hp(n_paths + 1), hl((size_t)n_pairs);
+  HIP_TRY(hipMemcpyAsync(hp.data(), path_ptr, hp.size() * 4, hipMemcpyDeviceToHost, s));
+  if (n_pairs) HIP_TRY(hipMemcpyAsync(hl.data(), path_link, hl.size() * 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (hp[0] != 0 || hp[n_paths] != n_pairs)
+    return fail(DODE_ERR_SHAPE, "path_ptr must run from 0 to n_pairs=%lld", (long long)n_pairs);
+  for (int32_t k = 0; k < n_paths; ++k)
+    if (hp[k + 1] < hp[k]) return fail(DODE_ERR_SHAPE, "path_ptr decreases at path %d", k);
+  for (int64_t m = 0; m < n_pairs; ++m)
+    if (hl[m] < 0 || hl[m] >= L)
+      return fail(DODE_ERR_SHAPE, "path_link[%lld]=%d outside [0, L)", (long long)m, hl[m]);
+  DevBuf flag;
+  HIP_TRY(flag.alloc(4, s));
+  HIP_TRY(fill_zero(false, flag.p, 1, s));
+  HIP_TRY(dar_check_speeds(f64, link_len, L, flag.as<int32_t>(), s));
+  HIP_TRY(dar_check_speeds(f64, speed, (int64_t)n_days * L * H_speed, flag.as<int32_t>(), s));
+  int32_t h = 0;
+  HIP_TRY(hipMemcpyAsync(&h, flag.p, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (h) return fail(DODE_ERR_ARG, "link lengths and speeds must be positive and finite");
+  return DODE_OK;
+}
+
+}  // namespace
+
 dode_status dode_dar_from_speeds(int32_t n_paths, const int32_t* path_ptr,
                                  const int32_t* path_link, int64_t n_pairs, int32_t L,
                                  const void* link_len, const void* speed, int32_t n_days,
@@ -886,30 +918,9 @@ dode_status dode_dar_from_speeds(int32_t n_paths, const int32_t* path_ptr,
   if (!path_ptr || !path_link || !link_len || !speed || !Rr)
     return fail(DODE_ERR_ARG, "path_ptr, path_link, link_len, speed or Rr is NULL");
   hipStream_t s = as_stream(stream);
-  // the path tables are small: check them on the host (every index a kernel
-  // will use), then the lengths and speeds on the device
-  std::vector<int32_t> hp(n_paths + 1), hl((size_t)n_pairs);
-  HIP_TRY(hipMemcpyAsync(hp.data(), path_ptr, hp.size() * 4, hipMemcpyDeviceToHost, s));
-  if (n_pairs) HIP_TRY(hipMemcpyAsync(hl.data(), path_link, hl.size() * 4, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  if (hp[0] != 0 || hp[n_paths] != n_pairs)
-    return fail(DODE_ERR_SHAPE, "path_ptr must run from 0 to n_pairs=%lld", (long long)n_pairs);
-  for (int32_t k = 0; k < n_paths; ++k)
-    if (hp[k + 1] < hp[k]) return fail(DODE_ERR_SHAPE, "path_ptr decreases at path %d", k);
-  for (int64_t m = 0; m < n_pairs; ++m)
-    if (hl[m] < 0 || hl[m] >= L)
-      return fail(DODE_ERR_SHAPE, "path_link[%lld]=%d outside [0, L)", (long long)m, hl[m]);
-  {
-    DevBuf flag;
-    HIP_TRY(flag.alloc(4, s));
-    HIP_TRY(fill_zero(false, flag.p, 1, s));
-    HIP_TRY(dar_check_speeds(f64 != 0, link_len, L, flag.as<int32_t>(), s));
-    HIP_TRY(dar_check_speeds(f64 != 0, speed, (int64_t)n_days * L * H_speed, flag.as<int32_t>(), s));
-    int32_t h = 0;
-    HIP_TRY(hipMemcpyAsync(&h, flag.p, 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (h) return fail(DODE_ERR_ARG, "link lengths and speeds must be positive and finite");
-  }
+  if (dode_status st = check_paths_speeds(n_paths, path_ptr, path_link, n_pairs, L, link_len, speed,
+                                          n_days, H_speed, f64 != 0, s))
+    return st;
   // trajectory scratch for a chunk of days, at most 1 GiB (at least one day)
   const size_t ss = f64 ? 8 : 4;
   const size_t per_day = (size_t)n_pairs * (H + 1) * ss;
@@ -919,6 +930,47 @@ dode_status dode_dar_from_speeds(int32_t n_paths, const int32_t* path_ptr,
   HIP_TRY(traj.alloc(std::max<size_t>(per_day * chunk, 16), s));
   HIP_TRY(dar_from_speeds(f64 != 0, n_paths, path_ptr, path_link, n_pairs, L, link_len, speed, n_days,
                           H_speed, dt, H, K, traj.p, chunk, Rr, s));
+  return DODE_OK;
+}
+
+dode_status dode_path_costs(int32_t n_paths, const int32_t* path_ptr, const int32_t* path_link,
+                            int64_t n_pairs, int32_t L, const void* link_len, const void* speed,
+                            int32_t n_days, int32_t H_speed, double dt, int32_t T, int32_t f64,
+                            void* cost, void* stream) {
+  if (n_paths < 1 || n_pairs < 0 || L < 1 || n_days < 1 || H_speed < 1 || T < 1)
+    return fail(DODE_ERR_SHAPE, "n_paths=%d n_pairs=%lld L=%d n_days=%d H_speed=%d T=%d", n_paths,
+                (long long)n_pairs, L, n_days, H_speed, T);
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DODE_ERR_ARG, "dt=%g must be positive", dt);
+  if (!path_ptr || !path_link || !link_len || !speed || !cost)
+    return fail(DODE_ERR_ARG, "path_ptr, path_link, link_len, speed or cost is NULL");
+  if ((int64_t)n_paths * T > (int64_t(1) << 31))
+    return fail(DODE_ERR_SHAPE, "n_paths * T too large");
+  hipStream_t s = as_stream(stream);
+  if (dode_status st = check_paths_speeds(n_paths, path_ptr, path_link, n_pairs, L, link_len, speed,
+                                          n_days, H_speed, f64 != 0, s))
+    return st;
+  // FP64 slice sums: slices of 4 days (more when the scratch would pass 256 MiB)
+  const size_t per_slice_bytes = (size_t)n_paths * T * 8;
+  const size_t cap_slices = std::max<size_t>(1, (size_t(256) << 20) / per_slice_bytes);
+  const size_t groups = ((size_t)n_days + 3) / 4;
+  const int32_t per_slice = 4 * (int32_t)((groups + cap_slices - 1) / cap_slices);
+  const int32_t n_slices = (n_days + per_slice - 1) / per_slice;
+  DevBuf partial;
+  HIP_TRY(partial.alloc(per_slice_bytes * n_slices, s));
+  HIP_TRY(path_costs(f64 != 0, n_paths, path_ptr, path_link, L, link_len, speed, n_days, H_speed, dt,
+                     T, per_slice, partial.as<double>(), cost, s));
+  return DODE_OK;
+}
+
+dode_status dar_from_costs(const dode_routes* routes, int32_t f64, const void* Rr, const void* cost,
+                           double theta, void* portions, void* W, void* stream) {
+  if (!routes) return fail(DODE_ERR_ARG, "routes is NULL");
+  if (!Rr || !cost || !W) return fail(DODE_ERR_ARG, "Rr, cost or W is NULL");
+  if (!std::isfinite(theta)) return fail(DODE_ERR_ARG, "theta must be finite");
+  hipStream_t s = as_stream(stream);
+  DevBuf pi;
+  HIP_TRY(pi.alloc((size_t)routes->dv.T * routes->dv.n_paths * 8, s));
+  HIP_TRY(routes_rho_costs(routes->dv, f64 != 0, Rr, cost, theta, portions, W, pi.as<double>(), s));
   return DODE_OK;
 }
 

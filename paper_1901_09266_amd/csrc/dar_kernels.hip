@@ -24,6 +24,16 @@
 //                   before x (the window's overlap with the interval over w).
 // Keeping times relative to the departure keeps the window arithmetic at the
 // precision of travel times (tens of minutes), not of times of day.
+//
+// Mean path travel times (eqs. "cost", "logit", "rt"): the same walk from the
+// departure at t*dt to the exit of the path's last link, for every day of a
+// pattern, averaged over the days.  Two kernels:
+//   k_path_cost_slices  one thread per (slice of days, path, t), t fastest:
+//                       the FP64 sum of the slice's day costs; four days walk
+//                       the path together (the link index and length are
+//                       loaded once, four speed loads are in flight);
+//   k_cost_mean         one thread per (path, t): the slice sums in slice
+//                       order, divided by the day count.
 #include "dode_internal.h"
 
 #include <algorithm>
@@ -123,6 +133,57 @@ k_dar_windows(int64_t n_pairs, int32_t n_days_chunk, int32_t H, int32_t K, S dt,
 }
 
 template <typename S>
+__global__ void __launch_bounds__(kBlock)
+k_path_cost_slices(int32_t n_paths, const int32_t* __restrict__ path_ptr,
+                   const int32_t* __restrict__ path_link, int32_t L, const S* __restrict__ len,
+                   const S* __restrict__ speed, int32_t n_days, int32_t per_slice, int32_t n_slices,
+                   int32_t H_speed, S dt, int32_t T, double* __restrict__ partial) {
+  const int64_t per = (int64_t)n_paths * T;
+  const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= per * n_slices) return;
+  const int32_t g = (int32_t)(idx / per);
+  const int32_t k = (int32_t)((idx % per) / T);
+  const int32_t t = (int32_t)(idx % T);
+  const S t0 = static_cast<S>(t) * dt;
+  const int32_t m0 = path_ptr[k], m1 = path_ptr[k + 1];
+  const int32_t d_begin = g * per_slice, d_end = min(n_days, d_begin + per_slice);
+  constexpr int kDays = 4;
+  const int64_t day_stride = (int64_t)L * H_speed;
+  double sum = 0.0;
+  for (int32_t d0 = d_begin; d0 < d_end; d0 += kDays) {
+    const S* sp[kDays];
+    S r[kDays];
+#pragma unroll
+    for (int u = 0; u < kDays; ++u) {
+      sp[u] = speed + (int64_t)min(d0 + u, d_end - 1) * day_stride;
+      r[u] = S(0);
+    }
+    for (int32_t m = m0; m < m1; ++m) {
+      const int32_t a = path_link[m];
+#pragma unroll
+      for (int u = 0; u < kDays; ++u) r[u] += link_time(len, sp[u], H_speed, dt, a, t0 + r[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < kDays; ++u)
+      if (d0 + u < d_end) sum += static_cast<double>(r[u]);
+  }
+  partial[idx] = sum;
+}
+
+template <typename S>
+__global__ void __launch_bounds__(kBlock)
+k_cost_mean(int32_t n_paths, int32_t T, int32_t n_slices, int32_t n_days,
+            const double* __restrict__ partial, S* __restrict__ cost) {
+  const int64_t per = (int64_t)n_paths * T;
+  const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= per) return;
+  const int32_t k = (int32_t)(idx / T), t = (int32_t)(idx % T);
+  double s = 0.0;
+  for (int32_t g = 0; g < n_slices; ++g) s += partial[g * per + idx];
+  cost[(int64_t)t * n_paths + k] = static_cast<S>(s / n_days);
+}
+
+template <typename S>
 __global__ void k_check_speeds(const S* __restrict__ x, int64_t n, int32_t* __restrict__ flag) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -153,7 +214,34 @@ hipError_t run(int32_t n_paths, const int32_t* path_ptr, const int32_t* path_lin
   return hipSuccess;
 }
 
+template <typename S>
+hipError_t run_costs(int32_t n_paths, const int32_t* path_ptr, const int32_t* path_link, int32_t L,
+                     const S* len, const S* speed, int32_t n_days, int32_t H_speed, S dt, int32_t T,
+                     int32_t per_slice, double* partial, S* cost, hipStream_t s) {
+  const int32_t n_slices = (n_days + per_slice - 1) / per_slice;
+  const int64_t per = (int64_t)n_paths * T;
+  hipLaunchKernelGGL(k_path_cost_slices<S>, dim3(blocks_for(per * n_slices)), dim3(kBlock), 0, s,
+                     n_paths, path_ptr, path_link, L, len, speed, n_days, per_slice, n_slices,
+                     H_speed, dt, T, partial);
+  hipLaunchKernelGGL(k_cost_mean<S>, dim3(blocks_for(per)), dim3(kBlock), 0, s, n_paths, T,
+                     n_slices, n_days, partial, cost);
+  return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t path_costs(bool f64, int32_t n_paths, const int32_t* path_ptr, const int32_t* path_link,
+                      int32_t L, const void* len, const void* speed, int32_t n_days, int32_t H_speed,
+                      double dt, int32_t T, int32_t per_slice, double* partial, void* cost,
+                      hipStream_t s) {
+  if (f64)
+    return run_costs<double>(n_paths, path_ptr, path_link, L, static_cast<const double*>(len),
+                             static_cast<const double*>(speed), n_days, H_speed, dt, T, per_slice,
+                             partial, static_cast<double*>(cost), s);
+  return run_costs<float>(n_paths, path_ptr, path_link, L, static_cast<const float*>(len),
+                          static_cast<const float*>(speed), n_days, H_speed, static_cast<float>(dt),
+                          T, per_slice, partial, static_cast<float*>(cost), s);
+}
 
 hipError_t dar_check_speeds(bool f64, const void* speed, int64_t n, int32_t* flag, hipStream_t s) {
   const unsigned b = (unsigned)std::min<int64_t>(4096, std::max<int64_t>(1, blocks_for(n)));

@@ -329,6 +329,12 @@ hipError_t dar_from_speeds(bool f64, int32_t n_paths, const int32_t* path_ptr,
                            const int32_t* path_link, int64_t n_pairs, int32_t L, const void* len,
                            const void* speed, int32_t n_days, int32_t H_speed, double dt, int32_t H,
                            int32_t K, void* traj, int32_t chunk, void* Rr, hipStream_t s);
+// cost[T][n_paths] = day mean of the path travel times for departures at t*dt;
+// partial = FP64 scratch [ceil(n_days/per_slice)][n_paths][T], per_slice % 4 == 0
+hipError_t path_costs(bool f64, int32_t n_paths, const int32_t* path_ptr, const int32_t* path_link,
+                      int32_t L, const void* len, const void* speed, int32_t n_days, int32_t H_speed,
+                      double dt, int32_t T, int32_t per_slice, double* partial, void* cost,
+                      hipStream_t s);
 
 // ---- MFMA tile kernels (mfma_kernels.hip) -------------------------------
 // corr: multiply with the corrected FP8 values (refinement steps)
@@ -346,9 +352,12 @@ dode_status tiles_fill_cluster(dode_dar* d, int32_t c, const void* codes_csr, st
 dode_status tiles_fill_correction(dode_dar* d, int32_t c, const uint16_t* corr_csr,
                                   std::string& err);
 
-// ---- differentiation (route_kernels.hip) --------------------------------
+// ---- route choice and differentiation (route_kernels.hip) ---------------
+// pi = FP64 scratch [n_paths] (free logits) or [T][n_paths] (costs)
 hipError_t routes_rho(const DevRoutes& r, bool f64, const void* Rr, const void* z, void* W,
                       double* pi, hipStream_t s);
+hipError_t routes_rho_costs(const DevRoutes& r, bool f64, const void* Rr, const void* cost,
+                            double theta, void* portions, void* W, double* pi, hipStream_t s);
 hipError_t routes_logits_bwd(const DevRoutes& r, bool f64, const void* Rr, const void* z,
                              const void* dW, void* dz, double* pi, double* dpi, hipStream_t s);
 // R full residual rows [n][H][L], Q [n][T][P] (day-major)

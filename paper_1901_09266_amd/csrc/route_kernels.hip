@@ -1,7 +1,8 @@
-// Differentiation kernels: the loss gradient with respect to the assignment
-// values and the route-choice parameterisation of the assignment matrix
-// (eqs. "logit", "flow", "assign").  One thread or block per output entry,
-// fixed summation order, FP64 accumulation for the reductions.
+// Route-choice kernels: the assignment matrix from route portions (eqs.
+// "logit", "rt", "flow", "assign"), with portions from free logits per path or
+// from the mean path costs of a pattern, and the loss gradient with respect to
+// the assignment values and the free logits.  One thread or block per output
+// entry, fixed summation order, FP64 accumulation for the reductions.
 #include "dode_internal.h"
 
 #include <cmath>
@@ -22,34 +23,46 @@ __device__ double block_sum256(double v, double* sh) {
   return r;
 }
 
-// pi_k = exp(z_k - max) / sum over the paths of OD p; one thread per OD.
+// Per row t < n_rows and OD p: pi[t][k] = exp(a z[t][k] - max) / sum over the
+// paths of OD p (FP64); one thread per (t, p).  z rows are zs apart (zs = 0
+// repeats one row); a = 1 for free logits, -theta for costs.  When pi_out is
+// set the portions are also written there in the storage type.
 template <typename S>
-__global__ void k_softmax(DevRoutes r, const S* __restrict__ z, double* __restrict__ pi) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= r.P) return;
+__global__ void k_softmax(DevRoutes r, int32_t n_rows, const S* __restrict__ z, int64_t zs,
+                          double a, double* __restrict__ pi, S* __restrict__ pi_out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n_rows * r.P) return;
+  const int32_t t = (int32_t)(idx / r.P), p = (int32_t)(idx % r.P);
+  const S* zt = z + t * zs;
+  double* pt = pi + (int64_t)t * r.n_paths;
   const int k0 = r.od_ptr[p], k1 = r.od_ptr[p + 1];
   double zmax = -INFINITY;
-  for (int i = k0; i < k1; ++i) zmax = fmax(zmax, static_cast<double>(z[r.od_paths[i]]));
+  for (int i = k0; i < k1; ++i) zmax = fmax(zmax, a * static_cast<double>(zt[r.od_paths[i]]));
   double s = 0.0;
-  for (int i = k0; i < k1; ++i) s += exp(static_cast<double>(z[r.od_paths[i]]) - zmax);
+  for (int i = k0; i < k1; ++i) s += exp(a * static_cast<double>(zt[r.od_paths[i]]) - zmax);
   for (int i = k0; i < k1; ++i) {
     const int k = r.od_paths[i];
-    pi[k] = exp(static_cast<double>(z[k]) - zmax) / s;
+    const double v = exp(a * static_cast<double>(zt[k]) - zmax) / s;
+    pt[k] = v;
+    if (pi_out) pi_out[(int64_t)t * r.n_paths + k] = static_cast<S>(v);
   }
 }
 
-// W[lt][nz] = sum over pairs m feeding nz of Rr[lt][m] * pi[path(m)].
+// W[l][t][nz] = sum over pairs m feeding nz of Rr[l][t][m] * pi[t][path(m)]
+// (eq. "assign"); pi rows are ps apart (ps = 0: portions that do not depend
+// on the interval).  Pairs are summed in increasing order.
 template <typename S>
 __global__ void k_rho_from_pi(DevRoutes r, const S* __restrict__ Rr, const double* __restrict__ pi,
-                              S* __restrict__ W) {
+                              int64_t ps, S* __restrict__ W) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t total = (int64_t)r.K * r.T * r.nnz;
   if (idx >= total) return;
   const int64_t lt = idx / r.nnz, nz = idx % r.nnz;
+  const double* pt = pi + (lt % r.T) * ps;
   double s = 0.0;
   for (int i = r.nz_ptr[nz]; i < r.nz_ptr[nz + 1]; ++i) {
     const int m = r.nz_pairs[i];
-    s += static_cast<double>(Rr[lt * r.n_pairs + m]) * pi[r.pair_path[m]];
+    s += static_cast<double>(Rr[lt * r.n_pairs + m]) * pt[r.pair_path[m]];
   }
   W[idx] = static_cast<S>(s);
 }
@@ -116,37 +129,54 @@ __global__ void k_scale(S* __restrict__ x, int64_t n, double f) {
 
 unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
+template <typename S>
+void launch_rho(const DevRoutes& r, int32_t n_rows, const S* Rr, const S* z, int64_t zs, double a,
+                double* pi, S* pi_out, S* W, hipStream_t s) {
+  const int64_t total = (int64_t)r.K * r.T * r.nnz;
+  hipLaunchKernelGGL(k_softmax<S>, dim3(blocks_for((int64_t)n_rows * r.P)), dim3(kBlock), 0, s, r,
+                     n_rows, z, zs, a, pi, pi_out);
+  hipLaunchKernelGGL(k_rho_from_pi<S>, dim3(blocks_for(total)), dim3(kBlock), 0, s, r, Rr, pi,
+                     n_rows > 1 ? (int64_t)r.n_paths : 0, W);
+}
+
 }  // namespace
 
 hipError_t routes_rho(const DevRoutes& r, bool f64, const void* Rr, const void* z, void* W,
                       double* pi, hipStream_t s) {
-  const int64_t total = (int64_t)r.K * r.T * r.nnz;
-  if (f64) {
-    hipLaunchKernelGGL(k_softmax<double>, dim3(blocks_for(r.P)), dim3(kBlock), 0, s, r,
-                       static_cast<const double*>(z), pi);
-    hipLaunchKernelGGL(k_rho_from_pi<double>, dim3(blocks_for(total)), dim3(kBlock), 0, s, r,
-                       static_cast<const double*>(Rr), pi, static_cast<double*>(W));
-  } else {
-    hipLaunchKernelGGL(k_softmax<float>, dim3(blocks_for(r.P)), dim3(kBlock), 0, s, r,
-                       static_cast<const float*>(z), pi);
-    hipLaunchKernelGGL(k_rho_from_pi<float>, dim3(blocks_for(total)), dim3(kBlock), 0, s, r,
-                       static_cast<const float*>(Rr), pi, static_cast<float*>(W));
-  }
+  if (f64)
+    launch_rho<double>(r, 1, static_cast<const double*>(Rr), static_cast<const double*>(z), 0, 1.0,
+                       pi, nullptr, static_cast<double*>(W), s);
+  else
+    launch_rho<float>(r, 1, static_cast<const float*>(Rr), static_cast<const float*>(z), 0, 1.0, pi,
+                      nullptr, static_cast<float*>(W), s);
+  return hipGetLastError();
+}
+
+hipError_t routes_rho_costs(const DevRoutes& r, bool f64, const void* Rr, const void* cost,
+                            double theta, void* portions, void* W, double* pi, hipStream_t s) {
+  if (f64)
+    launch_rho<double>(r, r.T, static_cast<const double*>(Rr), static_cast<const double*>(cost),
+                       r.n_paths, -theta, pi, static_cast<double*>(portions),
+                       static_cast<double*>(W), s);
+  else
+    launch_rho<float>(r, r.T, static_cast<const float*>(Rr), static_cast<const float*>(cost),
+                      r.n_paths, -theta, pi, static_cast<float*>(portions), static_cast<float*>(W),
+                      s);
   return hipGetLastError();
 }
 
 hipError_t routes_logits_bwd(const DevRoutes& r, bool f64, const void* Rr, const void* z,
                              const void* dW, void* dz, double* pi, double* dpi, hipStream_t s) {
   if (f64) {
-    hipLaunchKernelGGL(k_softmax<double>, dim3(blocks_for(r.P)), dim3(kBlock), 0, s, r,
-                       static_cast<const double*>(z), pi);
+    hipLaunchKernelGGL(k_softmax<double>, dim3(blocks_for(r.P)), dim3(kBlock), 0, s, r, 1,
+                       static_cast<const double*>(z), (int64_t)0, 1.0, pi, (double*)nullptr);
     hipLaunchKernelGGL(k_dpi<double>, dim3(r.n_paths), dim3(kBlock), 0, s, r,
                        static_cast<const double*>(Rr), static_cast<const double*>(dW), dpi);
     hipLaunchKernelGGL(k_dz<double>, dim3(blocks_for(r.n_paths)), dim3(kBlock), 0, s, r, pi, dpi,
                        static_cast<double*>(dz));
   } else {
-    hipLaunchKernelGGL(k_softmax<float>, dim3(blocks_for(r.P)), dim3(kBlock), 0, s, r,
-                       static_cast<const float*>(z), pi);
+    hipLaunchKernelGGL(k_softmax<float>, dim3(blocks_for(r.P)), dim3(kBlock), 0, s, r, 1,
+                       static_cast<const float*>(z), (int64_t)0, 1.0, pi, (float*)nullptr);
     hipLaunchKernelGGL(k_dpi<float>, dim3(r.n_paths), dim3(kBlock), 0, s, r,
                        static_cast<const float*>(Rr), static_cast<const float*>(dW), dpi);
     hipLaunchKernelGGL(k_dz<float>, dim3(blocks_for(r.n_paths)), dim3(kBlock), 0, s, r, pi, dpi,

@@ -1,0 +1,161 @@
+"""Route portions from mean path costs and the assignment they give, on the
+GPU (dode_path_costs, dar_from_costs) against the FP64 oracle: FP64 and FP32,
+ragged routes, day counts that are not multiples of the 4-day groups, slices
+of more than 4 days, the whole speeds -> ratios -> costs -> assignment chain,
+and the argument checks."""
+import numpy as np
+import pytest
+
+import oracle as orc
+import paper_1901_09266_amd as dode
+from synth import make_choice_instance
+from gpu_helpers import say, dev, rel
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+THETA = 0.6   # 0.01 per second, costs in minutes
+
+
+def small(seed=0, days=(9,)):
+    return make_choice_instance(L=48, P=7, H=36, K=4, m=5, sizes=days, ragged=True,
+                                seed=2000 + seed)
+
+
+def costs(ci, speed, f64, T=None):
+    t = torch.float64 if f64 else torch.float32
+    return dode.dode_path_costs(dev(ci.path_ptr, torch.int32), dev(ci.path_link, torch.int32),
+                                dev(ci.link_len, t), dev(speed, t), ci.dt, ci.T if T is None else T)
+
+
+def routes(ci):
+    return dode.dode_routes_create(ci.P, ci.L, ci.T, ci.H, ci.K, ci.nnz, ci.path_od, ci.path_ptr,
+                                   ci.path_link, ci.pair_nz)
+
+
+@pytest.mark.parametrize("f64", [True, False])
+def test_path_costs_match_oracle(f64):
+    ci = small(seed=1)
+    say("path costs", f64, ci.n_paths, ci.speed.shape)
+    for days in (slice(0, 9), slice(2, 3), slice(0, 4), slice(1, 7)):
+        sp = ci.speed[days]
+        got = costs(ci, sp, f64).cpu().numpy()
+        ref = orc.path_costs(ci.path_ptr, ci.path_link, ci.link_len.astype(np.float32 if not f64
+                             else np.float64).astype(np.float64), sp.astype(np.float64), ci.dt, ci.T)
+        err = np.abs(got - ref) / ref
+        if f64:
+            assert err.max() <= 1e-13
+        else:
+            # FP32 link times summed over <= 5 links per day: a few ulps,
+            # unless a time lands within rounding distance of an interval
+            # boundary and takes the neighbouring interval's speed (rare)
+            assert np.median(err) <= 1e-6 and err.max() <= 2e-2
+
+
+def test_path_costs_partial_horizon():
+    """T below the speed horizon: only the first T departure intervals."""
+    ci = small(seed=2, days=(5,))
+    say("path costs T<H")
+    got = costs(ci, ci.speed, True, T=20).cpu().numpy()
+    ref = orc.path_costs(ci.path_ptr, ci.path_link, ci.link_len, ci.speed.astype(np.float64), ci.dt, 20)
+    assert got.shape == (20, ci.n_paths)
+    assert rel(got, ref) <= 1e-13
+
+
+def test_path_costs_slices_of_eight_days():
+    """1100 days of 450 routes over 288 intervals pass the 256 MiB slice
+    budget at 4 days per slice, so slices hold 8 days; checked on sampled
+    routes, which the oracle computes alone."""
+    ci = make_choice_instance(sizes=(1100,), seed=2100)
+    say("path costs 1100 days", ci.n_paths)
+    got = costs(ci, ci.speed, False).cpu().numpy()
+    rng = np.random.default_rng(0)
+    for k in rng.choice(ci.n_paths, 6, replace=False):
+        pp = np.array([0, ci.path_ptr[k + 1] - ci.path_ptr[k]])
+        pl = ci.path_link[ci.path_ptr[k]:ci.path_ptr[k + 1]]
+        ref = orc.path_costs(pp, pl, ci.link_len.astype(np.float32).astype(np.float64),
+                             ci.speed.astype(np.float64), ci.dt, ci.T)[:, 0]
+        err = np.abs(got[:, k] - ref) / ref
+        # interval flips (see above) on single days are divided by 1100
+        assert np.median(err) <= 1e-6 and err.max() <= 1e-4
+
+
+@pytest.mark.parametrize("f64", [True, False])
+def test_assignment_from_costs_matches_oracle(f64):
+    ci = small(seed=3)
+    t = torch.float64 if f64 else torch.float32
+    rng = np.random.default_rng(3)
+    Rr = rng.uniform(0, 1, size=(ci.K, ci.T, ci.n_pairs))
+    cost = rng.uniform(5, 25, size=(ci.T, ci.n_paths))
+    if not f64:
+        Rr = Rr.astype(np.float32).astype(np.float64)
+        cost = cost.astype(np.float32).astype(np.float64)
+    p_ref = orc.logit_portions(ci.P, ci.path_od, THETA, cost)
+    W_ref = orc.rho_from_portions(ci.P, ci.L, ci.T, ci.H, ci.K, ci.path_od, ci.path_ptr, ci.path_link,
+                                  ci.row_ptr, ci.col_idx, Rr, p_ref)
+    r = routes(ci)
+    say("assign from costs", f64)
+    W = torch.full((ci.K, ci.T, ci.nnz), -1.0, dtype=t, device="cuda")
+    p = torch.full((ci.T, ci.n_paths), -1.0, dtype=t, device="cuda")
+    dode.dar_from_costs(r, dev(Rr, t), dev(cost, t), THETA, W, portions=p)
+    torch.cuda.synchronize()
+    tol = 1e-14 if f64 else 1e-6     # FP64 sums; FP32: one rounding of the result
+    assert rel(p.cpu().numpy(), p_ref) <= tol
+    got = W.cpu().numpy()
+    assert np.all(np.abs(got - W_ref) <= tol * np.abs(W_ref) + 1e-300)
+    # without the portions output
+    W2 = torch.zeros_like(W)
+    dode.dar_from_costs(r, dev(Rr, t), dev(cost, t), THETA, W2)
+    torch.cuda.synchronize()
+    assert torch.equal(W, W2)
+
+
+def test_speeds_to_assignment_chain_fp64():
+    """speeds -> ratios (dode_dar_from_speeds) and mean costs (dode_path_costs)
+    -> portions and assignment (dar_from_costs), against the oracle's chain,
+    for each pattern of a two-pattern instance."""
+    ci = make_choice_instance(L=64, P=8, H=48, K=5, m=6, sizes=(6, 3), ragged=True, seed=2200)
+    r = routes(ci)
+    t = torch.float64
+    pp, pl, ln = dev(ci.path_ptr, torch.int32), dev(ci.path_link, torch.int32), dev(ci.link_len, t)
+    for c in range(2):
+        sp = ci.speed[ci.day_cluster == c].astype(np.float64)
+        say("chain pattern", c)
+        Rr = dode.dode_dar_from_speeds(pp, pl, ln, dev(sp, t), ci.dt, ci.H, ci.K)
+        cost = dode.dode_path_costs(pp, pl, ln, dev(sp, t), ci.dt, ci.T)
+        W = torch.empty((ci.K, ci.T, ci.nnz), dtype=t, device="cuda")
+        dode.dar_from_costs(r, Rr, cost, THETA, W)
+        torch.cuda.synchronize()
+        Rr_o = orc.dar_from_speeds(ci.path_ptr, ci.path_link, ci.link_len, sp, ci.dt, ci.H, ci.K)
+        c_o = orc.path_costs(ci.path_ptr, ci.path_link, ci.link_len, sp, ci.dt, ci.T)
+        W_o = orc.rho_from_portions(ci.P, ci.L, ci.T, ci.H, ci.K, ci.path_od, ci.path_ptr,
+                                    ci.path_link, ci.row_ptr, ci.col_idx, Rr_o,
+                                    orc.logit_portions(ci.P, ci.path_od, THETA, c_o))
+        assert rel(cost.cpu().numpy(), c_o) <= 1e-13
+        assert np.max(np.abs(W.cpu().numpy() - W_o)) <= 1e-12
+
+
+def test_argument_checks():
+    ci = small(seed=4, days=(2,))
+    say("choice checks")
+    t = torch.float64
+    bad = ci.path_link.copy()
+    bad[0] = ci.L
+    with pytest.raises(dode.DodeError, match="path_link"):
+        dode.dode_path_costs(dev(ci.path_ptr, torch.int32), dev(bad, torch.int32),
+                             dev(ci.link_len, t), dev(ci.speed, t), ci.dt, ci.T)
+    sp = ci.speed.astype(np.float64).copy()
+    sp[1, 2, 3] = np.nan
+    with pytest.raises(dode.DodeError, match="positive"):
+        costs(ci, sp, True)
+    with pytest.raises(dode.DodeError, match="dt"):
+        dode.dode_path_costs(dev(ci.path_ptr, torch.int32), dev(ci.path_link, torch.int32),
+                             dev(ci.link_len, t), dev(ci.speed, t), 0.0, ci.T)
+    r = routes(ci)
+    Rr = torch.zeros((ci.K, ci.T, ci.n_pairs), dtype=t, device="cuda")
+    cost = torch.ones((ci.T, ci.n_paths), dtype=t, device="cuda")
+    W = torch.empty((ci.K, ci.T, ci.nnz), dtype=t, device="cuda")
+    with pytest.raises(dode.DodeError, match="theta"):
+        dode.dar_from_costs(r, Rr, cost, float("inf"), W)
+    with pytest.raises(ValueError, match="cost"):
+        dode.dar_from_costs(r, Rr, cost[:, :-1].contiguous(), THETA, W)
