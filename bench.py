@@ -315,6 +315,115 @@ def dar_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def choice_bench(args):
+    """The assignment matrix of every traffic pattern from link speeds:
+    ratios (dode_dar_from_speeds), mean path costs (dode_path_costs), logit
+    portions and eq. "assign" (dar_from_costs).  Corridor network shaped like
+    the config-3 workload: 150 ODs with 3 routes each (freeway, arterial,
+    mixed) of 20 links over 500 links (8% incidence), 288 five-minute
+    intervals, K = 6 lags, theta = 0.01 per second, 1095 days in 8 clusters.
+    A step is the whole job: the three calls per cluster."""
+    import torch
+    import paper_1901_09266_amd as dode
+    from synth import make_choice_instance
+    t0 = time.time()
+    ci = make_choice_instance(progress=lambda m: log(f"generating: {m} ({time.time() - t0:.0f}s)"))
+    K, H, T = ci.K, ci.H, ci.T
+    theta = 0.6                        # per minute
+    dev = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dt)
+    pp, pl = dev(ci.path_ptr, torch.int32), dev(ci.path_link, torch.int32)
+    ln, sp = dev(ci.link_len, torch.float32), dev(ci.speed, torch.float32)
+    routes = dode.dode_routes_create(ci.P, ci.L, T, H, K, ci.nnz, ci.path_od, ci.path_ptr,
+                                     ci.path_link, ci.pair_nz)
+    C = len(ci.sizes)
+    days = [np.nonzero(ci.day_cluster == c)[0] for c in range(C)]
+    f32 = torch.float32
+    Rr = [torch.empty((K, H, ci.n_pairs), dtype=f32, device="cuda") for _ in range(C)]
+    cost = [torch.empty((T, ci.n_paths), dtype=f32, device="cuda") for _ in range(C)]
+    W = [torch.empty((K, T, ci.nnz), dtype=f32, device="cuda") for _ in range(C)]
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    stage_ms = {"dar": 0.0, "costs": 0.0, "assign": 0.0}
+
+    def step(timed):
+        for c in range(C):
+            s = sp[days[c][0]:days[c][-1] + 1]
+            e = [ev() for _ in range(4)] if timed else None
+            if timed:
+                e[0].record()
+            dode.dode_dar_from_speeds(pp, pl, ln, s, ci.dt, H, K, Rr=Rr[c])
+            if timed:
+                e[1].record()
+            dode.dode_path_costs(pp, pl, ln, s, ci.dt, T, cost=cost[c])
+            if timed:
+                e[2].record()
+            dode.dar_from_costs(routes, Rr[c], cost[c], theta, W[c])
+            if timed:
+                e[3].record()
+                marks.append(e)
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    marks = []
+    e0, e1 = ev(), ev()
+    e0.record()
+    for _ in range(args.steps):
+        step(True)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    for e in marks:
+        stage_ms["dar"] += e[0].elapsed_time(e[1])
+        stage_ms["costs"] += e[1].elapsed_time(e[2])
+        stage_ms["assign"] += e[2].elapsed_time(e[3])
+    per = {k: v / args.steps for k, v in stage_ms.items()}
+    D = int(ci.day_cluster.shape[0])
+    spd = D * ci.L * H * 4
+    byts = {"dar": spd + C * K * H * ci.n_pairs * 4,
+            "costs": spd + C * T * ci.n_paths * 4,
+            "assign": C * (K * T * ci.n_pairs + T * ci.n_paths + K * T * ci.nnz) * 4}
+    dom = max(per, key=per.get)
+    achieved = byts[dom] / (per[dom] / 1e3) / 1e9
+    names = {"dar": "dode_dar_from_speeds", "costs": "dode_path_costs", "assign": "dar_from_costs"}
+    out = {"metric": "Route-choice assignment from speeds days/sec",
+           "value": round(D * args.steps / (ms / 1e3), 1), "unit": "days/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms / args.steps, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": f"{ci.P} ODs x 3 routes of 20 links on {ci.L} corridor links "
+                                  f"(freeway/arterial), H=288, K={K}, theta=0.01/s, {D} days in "
+                                  f"{C} patterns (400..15)"},
+           "stages_ms_per_step": {names[k]: round(v, 4) for k, v in per.items()},
+           "roofline": {"bound": "hbm", "kernel": f"{names[dom]} (whole call, all patterns)",
+                        "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                        "bytes_per_step": byts[dom]}}
+    if not args.skip_cpu:
+        import oracle as orc
+        sample = days[0][:48]
+        sp64 = ci.speed[sample].astype(np.float64)
+        ln64 = ci.link_len.astype(np.float32).astype(np.float64)
+        t1 = time.perf_counter()
+        Ro = orc.dar_from_speeds(ci.path_ptr, ci.path_link, ln64, sp64, ci.dt, H, K)
+        co = orc.path_costs(ci.path_ptr, ci.path_link, ln64, sp64, ci.dt, T)
+        Wo = orc.rho_from_portions(ci.P, ci.L, T, H, K, ci.path_od, ci.path_ptr, ci.path_link,
+                                   ci.row_ptr, ci.col_idx, Ro,
+                                   orc.logit_portions(ci.P, ci.path_od, theta, co))
+        dt_cpu = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": round(len(sample) / dt_cpu, 3), "unit": "days/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"{len(sample)} days of pattern 0, {dt_cpu:.1f}s"}
+        s = sp[sample[0]:sample[-1] + 1]
+        r1 = dode.dode_dar_from_speeds(pp, pl, ln, s, ci.dt, H, K)
+        c1 = dode.dode_path_costs(pp, pl, ln, s, ci.dt, T)
+        w1 = torch.empty((K, T, ci.nnz), dtype=f32, device="cuda")
+        dode.dar_from_costs(routes, r1, c1, theta, w1)
+        out["check"] = {"max_abs_W_vs_oracle_sample": float(np.max(np.abs(w1.cpu().numpy() - Wo))),
+                        "max_rel_cost_vs_oracle_sample":
+                            float(np.max(np.abs(c1.cpu().numpy() - co) / co))}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -331,6 +440,8 @@ def main():
                          "(default: 2 for the FP8 form of config 5, else 0)")
     ap.add_argument("--dar", action="store_true",
                     help="measure dynamic assignment ratio construction from link speeds instead")
+    ap.add_argument("--routes", action="store_true",
+                    help="measure the route-choice assignment from link speeds instead")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 512 MiB device copy first (reference for traffic counters)")
     args = ap.parse_args()
@@ -342,6 +453,9 @@ def main():
 
     if args.dar:
         dar_bench(args)
+        return
+    if args.routes:
+        choice_bench(args)
         return
     import torch
     import paper_1901_09266_amd as dode
