@@ -520,3 +520,65 @@ int orc_rho_from_portions(const orc_dims* dm, int32_t n_paths, const int32_t* pa
     }
   return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * Dense NNLS by Algorithm 1 (section "Solution algorithm"), the workload of
+ * the efficiency experiment (section "Algorithm efficiency"): a random dense
+ * B [m][n] (row-major), y [m], min over q >= 0 of ||B q - y||^2.  Each epoch
+ * takes the rows in the order perm[e][0..m), in minibatches of `chunk` rows
+ * (the last one shorter); a minibatch computes r = B_o q - y_o, g = B_o^T r,
+ * the Adagrad (optimizer 0, PyTorch's form) or fixed step (optimizer 1), then
+ * q = max(q, 0).  q, A [n] are updated in place; loss_hist [E] (or NULL)
+ * receives ||B q - y||^2 after each epoch.
+ * ---------------------------------------------------------------------- */
+double orc_dense_loss(int32_t m, int32_t n, const double* B, const double* y, const double* q) {
+  double s = 0.0;
+  for (int32_t i = 0; i < m; ++i) {
+    double v = 0.0;
+    for (int32_t j = 0; j < n; ++j) v += B[IDX2(i, j, n)] * q[j];
+    v -= y[i];
+    s += v * v;
+  }
+  return s;
+}
+
+int orc_dense_spgd(int32_t m, int32_t n, const double* B, const double* y, double* q, double* A,
+                   const int32_t* perm, int32_t E, int32_t chunk, int32_t optimizer, double eta,
+                   double eps, double* loss_hist) {
+  if (chunk <= 0 || m < 0 || n < 0) return 1;
+  double* r = (double*)malloc(sizeof(double) * (size_t)(chunk > 0 ? chunk : 1));
+  double* g = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  if (!r || !g) {
+    free(r); free(g);
+    return 2;
+  }
+  for (int32_t e = 0; e < E; ++e) {
+    const int32_t* pe = perm + (int64_t)e * m;
+    for (int32_t s0 = 0; s0 < m; s0 += chunk) {
+      const int32_t nr = s0 + chunk < m ? chunk : m - s0;
+      for (int32_t i = 0; i < nr; ++i) {
+        const double* row = B + (int64_t)pe[s0 + i] * n;
+        double v = 0.0;
+        for (int32_t j = 0; j < n; ++j) v += row[j] * q[j];
+        r[i] = v - y[pe[s0 + i]];
+      }
+      for (int32_t j = 0; j < n; ++j) g[j] = 0.0;
+      for (int32_t i = 0; i < nr; ++i) {
+        const double* row = B + (int64_t)pe[s0 + i] * n;
+        for (int32_t j = 0; j < n; ++j) g[j] += row[j] * r[i];
+      }
+      for (int32_t j = 0; j < n; ++j) {
+        if (optimizer == 0) {
+          A[j] += g[j] * g[j];
+          q[j] -= eta * g[j] / (sqrt(A[j]) + eps);
+        } else {
+          q[j] -= eta * g[j];
+        }
+        if (!(q[j] > 0.0)) q[j] = 0.0;
+      }
+    }
+    if (loss_hist) loss_hist[e] = orc_dense_loss(m, n, B, y, q);
+  }
+  free(r); free(g);
+  return 0;
+}

@@ -17,6 +17,8 @@ What each entry point follows in the paper (arXiv 1901.09266):
               eqs. "cost", "logit", "rt", "assign": route portions from the
               mean path travel time of a pattern's days, and the assignment
               matrix they give
+  dense_spgd, dense_loss
+              Algorithm 1 on a dense B (section "Algorithm efficiency")
 
 Pins (tests/test_oracle_pins.py): brute-force active-set enumeration, scipy's
 Lawson-Hanson NNLS, planted noiseless recovery, KKT conditions, the adjoint
@@ -41,7 +43,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 __all__ = ["build_oracle", "Dims", "apply", "adjoint", "loss", "grad", "kkt", "r2", "spgd_day",
            "spgd_step", "spgd", "metrics", "route_softmax", "rho_from_logits", "loss_backward",
            "logits_backward", "fixed_step_eta", "dar_from_speeds", "path_costs", "logit_portions",
-           "rho_from_portions", "lib"]
+           "rho_from_portions", "dense_loss", "dense_spgd", "lib"]
 
 
 def build_oracle(force: bool = True) -> str:
@@ -101,6 +103,10 @@ def lib():
                                      i32, dptr]
         L.orc_logit_portions.argtypes = [i32, i32, iptr, i32, ctypes.c_double, dptr, dptr]
         L.orc_logit_portions.restype = None
+        L.orc_dense_loss.argtypes = [i32, i32, dptr, dptr, dptr]
+        L.orc_dense_loss.restype = ctypes.c_double
+        L.orc_dense_spgd.argtypes = [i32, i32, dptr, dptr, dptr, dptr, iptr, i32, i32, i32,
+                                     ctypes.c_double, ctypes.c_double, dptr]
         L.orc_rho_from_portions.argtypes = [dims, i32, iptr, iptr, iptr, dptr, dptr, iptr, iptr,
                                             dptr]
         _lib = L
@@ -438,3 +444,31 @@ def rho_from_portions(P, L, T, H, K, path_od, pair_ptr, pair_link, row_ptr, col_
     if rc != 0:
         raise RuntimeError("pair not in pattern")
     return W
+
+
+def dense_loss(B, y, q):
+    """||B q - y||^2 of a dense B [m][n]."""
+    B, Bp = _d(B)
+    y, yp = _d(y)
+    q, qp = _d(q)
+    return lib().orc_dense_loss(B.shape[0], B.shape[1], Bp, yp, qp)
+
+
+def dense_spgd(B, y, perms, chunk, eta, eps=1e-10, optimizer=0, q0=None, A0=None):
+    """Algorithm 1 on a dense B [m][n] (see orc_dense_spgd); perms [E][m] row
+    orders.  Returns (q, A, loss_hist [E])."""
+    B, Bp = _d(B)
+    y, yp = _d(y)
+    m, n = B.shape
+    perms, pp = _i(np.asarray(perms).reshape(-1, m) if m else np.zeros((0, 0)))
+    E = perms.shape[0]
+    q = np.zeros(n) if q0 is None else np.array(q0, dtype=np.float64)
+    A = np.zeros(n) if A0 is None else np.array(A0, dtype=np.float64)
+    q, qp = _d(q)
+    A, Ap = _d(A)
+    hist = np.zeros(E)
+    rc = lib().orc_dense_spgd(m, n, Bp, yp, qp, Ap, pp, E, chunk, optimizer, ctypes.c_double(eta),
+                              ctypes.c_double(eps), _d(hist)[1])
+    if rc != 0:
+        raise RuntimeError(f"orc_dense_spgd failed ({rc})")
+    return q, A, hist

@@ -556,3 +556,18 @@ def make_choice_instance(L=500, P=150, H=288, K=6, sizes=(400, 250, 150, 120, 80
                           path_link=path_link, pair_nz=pair_nz, row_ptr=row_ptr, col_idx=col_idx,
                           link_len=link_len, speed=speed, day_cluster=day_cluster,
                           sizes=tuple(sizes), seed=seed)
+
+
+def make_dense_instance(n, m=None, seed=BASE_SEED + 800, epochs=0, chunk=8192):
+    """The efficiency experiment's random NNLS: B [m][n] (m = n by default)
+    with U(0,1) entries, x* with U(0,1) entries, y = B x* (FP64), and `epochs`
+    row permutations [E][m].  Returns (B, y, xstar, perms)."""
+    m = n if m is None else m
+    rng = np.random.Generator(np.random.PCG64(seed + n))
+    B = rng.uniform(0.0, 1.0, size=(m, n))
+    xstar = rng.uniform(0.0, 1.0, size=n)
+    y = B @ xstar
+    prng = np.random.Generator(np.random.PCG64(seed + n + 1))
+    perms = np.stack([prng.permutation(m) for _ in range(epochs)]).astype(np.int32) if epochs else \
+        np.zeros((0, m), dtype=np.int32)
+    return B, y, xstar, perms
