@@ -311,6 +311,30 @@ dode_status dar_from_costs(const dode_routes* routes, int32_t f64, const void* R
                            double theta, void* portions, void* W, void* stream);
 
 /*
+ * Dense NNLS by Algorithm 1 (section "Solution algorithm"), the random dense
+ * workload of the efficiency experiment (section "Algorithm efficiency"):
+ * min over q >= 0 of ||B q - y||^2.
+ *   B dev [m][n] row-major, y dev [m]; q, A dev [n] (in/out: the iterate and
+ *       the Adagrad accumulator, usually zeros at the start)
+ *   perms dev [E][m]: epoch e takes the rows in the order perms[e], in
+ *       minibatches of `chunk` rows (the last one shorter); each minibatch
+ *       computes r = B_o q - y_o, g = B_o^T r, then Adagrad (optimizer 0:
+ *       A += g^2, q -= eta g / (sqrt(A) + eps)) or a fixed step (optimizer 1:
+ *       q -= eta g), then q = max(q, 0)
+ *   loss_hist host [E] or NULL: ||B q - y||^2 after each epoch (FP64 sum in
+ *       row order; costs one more pass over B per epoch)
+ *   f64: nonzero for double arrays, else float.
+ * Errors: DODE_ERR_ARG if a perms row is not a permutation of 0..m-1 (checked
+ * on the host), for a non-positive eta or chunk or a negative eps.
+ * Synchronises `stream` (the permutations are read back first, and the loss
+ * history after the run); scratch of m + ceil(min(chunk, m)/32)*n values.
+ */
+dode_status dense_spgd_run(int32_t m, int32_t n, int32_t f64, const void* B, const void* y, void* q,
+                           void* A, const int32_t* perms, int32_t E, int32_t chunk,
+                           int32_t optimizer, double eta, double eps, double* loss_hist,
+                           void* stream);
+
+/*
  * Reusable form of spgd_solve for repeated or timed runs.  A plan holds
  *  - the minibatch schedule of every epoch (permutations, their inverses and
  *    the departure intervals each minibatch reaches),

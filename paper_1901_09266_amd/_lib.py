@@ -29,7 +29,8 @@ EXPORTS = ["dode_last_error", "dode_spgd_defaults", "dar_create", "dar_create_ex
            "spgd_solve", "spgd_plan_create", "spgd_plan_destroy", "spgd_plan_load",
            "spgd_plan_store", "spgd_run", "spgd_plan_timing", "spgd_plan_info",
            "dode_loss_bwd", "dode_routes_create", "dode_routes_destroy", "dar_from_logits",
-           "dar_logits_bwd", "dode_dar_from_speeds", "dode_path_costs", "dar_from_costs"]
+           "dar_logits_bwd", "dode_dar_from_speeds", "dode_path_costs", "dar_from_costs",
+           "dense_spgd_run"]
 
 
 class DodeError(RuntimeError):
@@ -74,6 +75,8 @@ def lib():
                                            i32, vp, vp]
         L.dode_path_costs.argtypes = [i32, vp, vp, i64, i32, vp, vp, i32, i32, dbl, i32, i32, vp, vp]
         L.dar_from_costs.argtypes = [vp, i32, vp, vp, dbl, vp, vp, vp]
+        L.dense_spgd_run.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp, i32, i32, i32, dbl, dbl,
+                                     P(dbl), vp]
         L.dar_destroy.argtypes = [vp]
         L.dar_info.argtypes = [vp, P(Dims), P(i32), P(i64), P(i32), P(i64)]
         L.dar_set_values.argtypes = [vp, i32, vp, vp]
@@ -495,3 +498,26 @@ def dar_from_costs(routes: Routes, Rr, cost, theta, W, portions=None, stream=Non
     _check(lib().dar_from_costs(routes.handle, f64, _ptr(Rr, "Rr", dt, (K, T, routes.n_pairs)),
                                 _ptr(cost, "cost", dt, (T, routes.n_paths)), float(theta), pp,
                                 _ptr(W, "W", dt, (K, T, routes.nnz)), _stream(stream)))
+
+
+def dense_spgd_run(B, y, q, A, perms, chunk, eta, eps=1e-10, optimizer=0, loss_hist=False,
+                   stream=None):
+    """Algorithm 1 on a dense B [m][n] (device tensors, float32 or float64):
+    q, A [n] are updated in place; perms int32 [E][m] on the device.  Returns
+    the per-epoch losses (numpy, FP64) when loss_hist is set, else None."""
+    import torch
+    m, n = B.shape
+    dt = B.dtype
+    if dt not in (torch.float32, torch.float64):
+        raise TypeError("B must be float32 or float64")
+    E = perms.shape[0] if perms.numel() else 0
+    bp = _ptr(B, "B", dt, (m, n))
+    yp = _ptr(y, "y", dt, (m,))
+    qp = _ptr(q, "q", dt, (n,))
+    ap = _ptr(A, "A", dt, (n,))
+    pp = _ptr(perms, "perms", torch.int32, (E, m))
+    hist = np.zeros(max(E, 1)) if loss_hist else None
+    hp = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if loss_hist else None
+    _check(lib().dense_spgd_run(m, n, int(dt == torch.float64), bp, yp, qp, ap, pp, E, int(chunk),
+                                int(optimizer), float(eta), float(eps), hp, _stream(stream)))
+    return hist[:E] if loss_hist else None

@@ -974,6 +974,51 @@ dode_status dar_from_costs(const dode_routes* routes, int32_t f64, const void* R
   return DODE_OK;
 }
 
+dode_status dense_spgd_run(int32_t m, int32_t n, int32_t f64, const void* B, const void* y, void* q,
+                           void* A, const int32_t* perms, int32_t E, int32_t chunk,
+                           int32_t optimizer, double eta, double eps, double* loss_hist,
+                           void* stream) {
+  if (m < 1 || n < 1 || E < 0) return fail(DODE_ERR_SHAPE, "m=%d n=%d E=%d", m, n, E);
+  if (chunk < 1) return fail(DODE_ERR_ARG, "chunk=%d must be positive", chunk);
+  if (optimizer != 0 && optimizer != 1) return fail(DODE_ERR_ARG, "optimizer=%d", optimizer);
+  if (!(eta > 0.0) || !std::isfinite(eta) || !(eps >= 0.0) || !std::isfinite(eps))
+    return fail(DODE_ERR_ARG, "eta=%g eps=%g", eta, eps);
+  if (!B || !y || !q || !A || (E > 0 && !perms)) return fail(DODE_ERR_ARG, "NULL array");
+  if (E == 0) return DODE_OK;
+  hipStream_t s = as_stream(stream);
+  // every row index a kernel will use: each epoch must be a permutation of 0..m-1
+  {
+    std::vector<int32_t> hp((size_t)E * m);
+    HIP_TRY(hipMemcpyAsync(hp.data(), perms, hp.size() * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    std::vector<int32_t> seen(m, -1);
+    for (int32_t e = 0; e < E; ++e)
+      for (int32_t i = 0; i < m; ++i) {
+        const int32_t v = hp[(size_t)e * m + i];
+        if (v < 0 || v >= m || seen[v] == e)
+          return fail(DODE_ERR_ARG, "perms[%d] is not a permutation of 0..m-1", e);
+        seen[v] = e;
+      }
+  }
+  const size_t ss = f64 ? 8 : 4;
+  const int32_t rows = std::min(chunk, m);
+  const int32_t n_slices = (rows + dense_slice_rows() - 1) / dense_slice_rows();
+  if (n_slices > 65535) return fail(DODE_ERR_SHAPE, "chunk=%d too large", chunk);
+  DevBuf r, part, loss;
+  HIP_TRY(r.alloc((size_t)m * ss, s));
+  HIP_TRY(part.alloc((size_t)n_slices * n * ss, s));
+  if (loss_hist) HIP_TRY(loss.alloc((size_t)E * 8, s));
+  DenseArgs a{m, n, E, chunk, B, y, q, A, perms, r.p, part.p,
+              loss_hist ? loss.as<double>() : nullptr, StepArgs{eta, eps, optimizer}};
+  const bool vec = ((uintptr_t)B % 16 == 0) && ((uintptr_t)q % 16 == 0) && ((size_t)n * ss) % 16 == 0;
+  HIP_TRY(dense_spgd(a, f64 != 0, vec, s));
+  if (loss_hist) {
+    HIP_TRY(hipMemcpyAsync(loss_hist, loss.p, (size_t)E * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  return DODE_OK;
+}
+
 dode_status spgd_step(const dode_dar* dar, int32_t cluster, const int32_t* chunk_h, int32_t n_h,
                       const void* X, void* Q, void* A, int32_t n_days,
                       const dode_spgd_params* params, void* stream) {

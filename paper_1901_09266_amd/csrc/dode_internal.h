@@ -336,6 +336,23 @@ hipError_t path_costs(bool f64, int32_t n_paths, const int32_t* path_ptr, const 
                       double dt, int32_t T, int32_t per_slice, double* partial, void* cost,
                       hipStream_t s);
 
+// ---- dense NNLS by Algorithm 1 (dense_kernels.hip) ----------------------
+struct DenseArgs {
+  int32_t m, n, E, chunk;
+  const void* B;          // [m][n]
+  const void* y;          // [m]
+  void* q;                // [n]
+  void* A;                // [n]
+  const int32_t* perms;   // [E][m] (device)
+  void* r;                // scratch [m]
+  void* part;             // scratch [ceil(min(chunk, m) / dense_slice_rows())][n]
+  double* loss;           // [E] (device) or nullptr
+  StepArgs st;
+};
+int32_t dense_slice_rows();
+// vec: B and q are 16-byte aligned and a row of B is a multiple of 16 bytes
+hipError_t dense_spgd(const DenseArgs& a, bool f64, bool vec, hipStream_t s);
+
 // ---- MFMA tile kernels (mfma_kernels.hip) -------------------------------
 // corr: multiply with the corrected FP8 values (refinement steps)
 hipError_t mfma_chunk_resid(const dode_dar* dar, const ChunkSched& cs, const DayGroups& dg,
