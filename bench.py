@@ -120,7 +120,7 @@ def launch_bytes(inst, perms, bh, esz, epochs, s_state=4, refine=0):
     return np.array(fwd, dtype=np.float64), np.array(adj, dtype=np.float64)
 
 
-def run_form(dode, torch, inst, form, perms, E_total, warmup, steps, bh, refine=0):
+def run_form(dode, torch, inst, form, perms, E_total, warmup, steps, bh, refine=0, day_tile=32):
     dt = torch.float64 if form == "f64" else torch.float32
     t0 = time.time()
     dar = dode.dar_create(inst.P, inst.L, inst.T, inst.H, inst.K, inst.row_ptr, inst.col_idx, inst.W,
@@ -130,7 +130,7 @@ def run_form(dode, torch, inst, form, perms, E_total, warmup, steps, bh, refine=
     Q = torch.zeros((D, inst.T, inst.P), dtype=dt, device="cuda")
     A = torch.zeros_like(Q)
     params = dode.make_params(epochs=E_total, batch_rows=8192, eta=5.0, optimizer=0,
-                              refine_steps=refine)
+                              refine_steps=refine, day_tile=day_tile)
     plan = dode.spgd_plan_create(dar, inst.day_cluster, params, perm=perms, stream=0)
     dode.spgd_plan_load(plan, X, Q, A, stream=0)
     torch.cuda.synchronize()
@@ -424,6 +424,92 @@ def choice_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def dense_bench(args):
+    """The efficiency experiment (section "Algorithm efficiency"): random dense
+    NNLS B x = y with B [n][n] U(0,1), x* U(0,1), n = 100 ... 6000, solved by
+    Algorithm 1 with minibatches of 8192 rows (one per epoch at these sizes)
+    and Adagrad, in FP32.  Per n: seconds per epoch on the GPU (the slope
+    between E and 2E epochs in one call, so fixed costs drop out), the loss
+    after 2E epochs and the epochs to a relative loss of 1e-3, the FP64
+    oracle's seconds per epoch on one host core, and
+    scipy's Lawson-Hanson active-set solve for n <= 1000 (context)."""
+    import torch
+    import paper_1901_09266_amd as dode
+    from synth import make_dense_instance
+    sizes = [100, 500, 1000, 2000, 4000, 6000]
+    E = max(2, args.steps * 10)
+    rows = []
+    cpu = {}
+    for n in sizes:
+        B, y, _, perms = make_dense_instance(n, epochs=2 * E)
+        Bd = torch.as_tensor(B.astype(np.float32)).cuda()
+        yd = torch.as_tensor(y.astype(np.float32)).cuda()
+        pd = torch.as_tensor(perms).cuda()
+        eta = 0.2
+        times = []
+        for ne in (E, 2 * E):
+            q = torch.zeros(n, dtype=torch.float32, device="cuda")
+            A = torch.zeros(n, dtype=torch.float32, device="cuda")
+            dode.dense_spgd_run(Bd, yd, q, A, pd[:args.warmup].contiguous(), 8192, eta)
+            q.zero_()
+            A.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            dode.dense_spgd_run(Bd, yd, q, A, pd[:ne].contiguous(), 8192, eta)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        per_epoch = (times[1] - times[0]) / E
+        qn = q.double().cpu().numpy()
+        loss = float(np.sum((B @ qn - y) ** 2))
+        # epochs to a relative loss of 1e-3 (a second run with the loss history)
+        q.zero_()
+        A.zero_()
+        hist = dode.dense_spgd_run(Bd, yd, q, A, pd[:2 * E].contiguous(), 8192, eta, loss_hist=True)
+        hit = np.nonzero(hist / float(y @ y) <= 1e-3)[0]
+        to_1e3 = int(hit[0]) + 1 if hit.size else None
+        byts = 2 * n * n * 4          # B streamed twice per epoch (residual, column sums)
+        rows.append({"n": n, "s_per_epoch_gpu": per_epoch, "epochs": 2 * E,
+                     "gpu_s_total": times[1], "rel_loss": loss / float(y @ y),
+                     "epochs_to_rel_loss_1e-3": to_1e3,
+                     "gpu_s_to_rel_loss_1e-3": None if to_1e3 is None else to_1e3 * per_epoch,
+                     "achieved_GBps": byts / per_epoch / 1e9})
+        log(f"dense n={n}: {per_epoch * 1e6:.1f} us/epoch, {byts / per_epoch / 1e9:.0f} GB/s, "
+            f"rel loss {loss / float(y @ y):.3e} after {2 * E} epochs")
+        if not args.skip_cpu:
+            import oracle as orc
+            ne = max(1, min(50, int(2e9 // (3 * n * n))))
+            t1 = time.perf_counter()
+            orc.dense_spgd(B, y, perms[:ne], 8192, eta)
+            cpu[n] = {"oracle_s_per_epoch": (time.perf_counter() - t1) / ne, "oracle_epochs": ne}
+            if n <= 1000:
+                from scipy.optimize import nnls
+                t1 = time.perf_counter()
+                nnls(B, y, maxiter=50 * n)
+                cpu[n]["lawson_hanson_s"] = time.perf_counter() - t1
+            rows[-1].update(cpu[n])
+        del Bd
+    top = rows[-1]
+    out = {"metric": "Dense SPGD epochs/sec (n=6000)", "value": round(1.0 / top["s_per_epoch_gpu"], 1),
+           "unit": "epochs/s", "n_gpus": 1, "steps": 2 * E, "warmup": args.warmup,
+           "ms_per_step": round(top["s_per_epoch_gpu"] * 1e3, 5), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "random dense NNLS, B U(0,1) n x n, x* U(0,1), y = B x*, "
+                                  "minibatch 8192 rows, Adagrad eta=0.2, n = 100..6000"},
+           "sweep": [{k: (round(v, 9) if isinstance(v, float) else v) for k, v in r.items()}
+                     for r in rows],
+           "roofline": {"bound": "hbm", "kernel": "dense epoch (k_dense_resid + k_dense_colsum + "
+                        "k_dense_update), n=6000", "achieved": round(top["achieved_GBps"], 1),
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(top["achieved_GBps"] / HBM_PEAK_GBS, 4), "traffic": None,
+                        "bytes_per_step": 2 * 6000 * 6000 * 4}}
+    if not args.skip_cpu:
+        c = cpu[6000]
+        out["cpu_baseline"] = {"value": round(1.0 / c["oracle_s_per_epoch"], 3), "unit": "epochs/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"{c['oracle_epochs']} epochs at n=6000 (FP64)"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -442,6 +528,10 @@ def main():
                     help="measure dynamic assignment ratio construction from link speeds instead")
     ap.add_argument("--routes", action="store_true",
                     help="measure the route-choice assignment from link speeds instead")
+    ap.add_argument("--dense", action="store_true",
+                    help="measure Algorithm 1 on the dense random NNLS of the efficiency experiment")
+    ap.add_argument("--per-day", action="store_true",
+                    help="give every day its own ratio matrix (one cluster per day)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 512 MiB device copy first (reference for traffic counters)")
     args = ap.parse_args()
@@ -457,6 +547,9 @@ def main():
     if args.routes:
         choice_bench(args)
         return
+    if args.dense:
+        dense_bench(args)
+        return
     import torch
     import paper_1901_09266_amd as dode
     from synth import make_config, make_perms, chunk_h_blocks
@@ -469,7 +562,13 @@ def main():
         torch.cuda.synchronize()
         del a, b
     t0 = time.time()
-    inst = make_config(args.config, progress=lambda m: log(f"generating: {m} ({time.time() - t0:.0f}s)"))
+    per_day = None
+    if args.per_day:
+        # one ratio matrix per day: every day is its own cluster
+        from synth.instances import CONFIGS
+        per_day = (1,) * int(sum(CONFIGS[args.config]["sizes"]))
+    inst = make_config(args.config, sizes=per_day,
+                       progress=lambda m: log(f"generating: {m} ({time.time() - t0:.0f}s)"))
     log(f"config {args.config}: D={inst.D} C={inst.C} nnz={inst.nnz} generated in {time.time() - t0:.1f}s")
     bh = chunk_h_blocks(inst.L, inst.H, 8192)
     E_total = args.warmup + 2 * args.steps
@@ -481,7 +580,7 @@ def main():
     res = {}
     for f in forms:
         r = run_form(dode, torch, inst, f, perms[:E_total], E_total, args.warmup, args.steps, bh,
-                     refine[f])
+                     refine[f], day_tile=16 if args.per_day else 32)
         fb, ab = launch_bytes(inst, perms, bh, ESIZE[f], r["timing_epochs"], refine=refine[f])
         r["fwd_bytes"], r["adj_bytes"] = fb.sum(), ab.sum()
         res[f] = r
@@ -498,7 +597,7 @@ def main():
     k = int(np.argmax(kms[:2]))
     byts = head["fwd_bytes"] if k == 0 else head["adj_bytes"]
     achieved = byts / (kms[k] / 1e3) / 1e9
-    traffic = counted_traffic(args.config, args.form, ("fwd", "adj")[k])
+    traffic = None if args.per_day else counted_traffic(args.config, args.form, ("fwd", "adj")[k])
     roof = {"bound": "hbm", "kernel": names[k], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": round(traffic) if traffic is not None else None,
@@ -511,7 +610,8 @@ def main():
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": {"bf16": "bf16", "f32": "f32", "fp8": "bf16", "f64": "f64"}[args.form],
            "data": "synthetic",
-           "config": {"workload": f"config {args.config}: " + WORKLOADS[args.config],
+           "config": {"workload": f"config {args.config}: " + WORKLOADS[args.config] +
+                                  (", one ratio matrix per day (per-day DAR)" if args.per_day else ""),
                       "form": FORMS[args.form],
                       "global_batch": inst.D, "seq_len": inst.H, "parallelism": "none (1 GPU)",
                       "epochs_per_step": 1, "batch_rows": 8192, "minibatch_intervals": bh,
