@@ -8,13 +8,15 @@
 //                    sums them with a butterfly reduction;
 //   k_dense_colsum   split-K adjoint: block (column block, slice of kSliceRows
 //                    rows) writes part[slice][j] = sum over its rows of
-//                    B[o_s][j] r[s], four consecutive columns per thread, so a
-//                    wave reads 1 KiB of one row per step;
-//   k_dense_update   one thread per column: g = the slices' partial sums in
-//                    slice order (FP64), then Adagrad (or a fixed step) and
-//                    the projection q = max(q, 0).
+//                    B[o_s][j] r[s], four consecutive columns per lane, so a
+//                    wave reads 1 KiB of one row per step; the block's four
+//                    waves split the slice's rows and meet in LDS;
+//   k_dense_update   one block per 64 columns: g = the slices' partial sums
+//                    (FP64, four waves over the slices, added in a fixed
+//                    order), then Adagrad (or a fixed step) and the
+//                    projection q = max(q, 0).
 // The epoch loss ||B q - y||^2 (optional) uses the residual kernel over all
-// rows in natural order and an FP64 sum in row order.
+// rows in natural order and a one-block FP64 sum in a fixed order.
 #include "dode_internal.h"
 
 #include <algorithm>
@@ -23,7 +25,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
-constexpr int kSliceRows = 32;
+constexpr int kSliceRows = 128;
 
 template <typename S>
 struct Vec;
@@ -95,52 +97,77 @@ k_dense_resid(int32_t n, int32_t nr, const int32_t* __restrict__ rows, const S* 
   if (lane == 0) r[s] = acc - y[i];
 }
 
-// part[slice][j] = sum over the slice's rows s of B[rows[s]][j] r[s].
+// part[slice][j] = sum over the slice's rows s of B[rows[s]][j] r[s].  A block
+// covers 64*W columns (W per lane) and a slice of kSliceRows rows: wave w
+// takes rows w, w+4, ... of the slice (so the four waves stream neighbouring
+// rows), and the four wave sums are added in wave order through LDS.
 template <typename S, bool VEC>
 __global__ void __launch_bounds__(kBlock)
 k_dense_colsum(int32_t n, int32_t nr, const int32_t* __restrict__ rows, const S* __restrict__ B,
                const S* __restrict__ r, S* __restrict__ part) {
   constexpr int W = VEC ? Vec<S>::N : 1;
-  const int64_t j0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * W;
+  __shared__ S sh[kWaves][64 * W];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t c0 = (int64_t)blockIdx.x * 64 * W;
+  const int64_t j0 = c0 + (int64_t)lane * W;
   const int slice = blockIdx.y;
-  if (j0 >= n) return;
   const int s_begin = slice * kSliceRows, s_end = min(nr, s_begin + kSliceRows);
   S acc[W];
 #pragma unroll
   for (int w = 0; w < W; ++w) acc[w] = S(0);
-  if (VEC) {
-    using V = typename Vec<S>::T;
-#pragma unroll 8
-    for (int s = s_begin; s < s_end; ++s) {
-      const V b = *reinterpret_cast<const V*>(B + (int64_t)rows[s] * n + j0);
-      const S rs = r[s];
-      if constexpr (W == 4) {
-        acc[0] += b.x * rs;
-        acc[1] += b.y * rs;
-        acc[2] += b.z * rs;
-        acc[3] += b.w * rs;
-      } else if constexpr (W == 2) {
-        acc[0] += b.x * rs;
-        acc[1] += b.y * rs;
+  if (j0 < n) {
+    if (VEC) {
+      using V = typename Vec<S>::T;
+#pragma unroll 4
+      for (int s = s_begin + wave; s < s_end; s += kWaves) {
+        const V b = *reinterpret_cast<const V*>(B + (int64_t)rows[s] * n + j0);
+        const S rs = r[s];
+        if constexpr (W == 4) {
+          acc[0] += b.x * rs;
+          acc[1] += b.y * rs;
+          acc[2] += b.z * rs;
+          acc[3] += b.w * rs;
+        } else if constexpr (W == 2) {
+          acc[0] += b.x * rs;
+          acc[1] += b.y * rs;
+        }
       }
+    } else {
+      for (int s = s_begin + wave; s < s_end; s += kWaves) acc[0] += B[(int64_t)rows[s] * n + j0] * r[s];
     }
-  } else {
-    for (int s = s_begin; s < s_end; ++s) acc[0] += B[(int64_t)rows[s] * n + j0] * r[s];
   }
-  S* out = part + (int64_t)slice * n + j0;
 #pragma unroll
-  for (int w = 0; w < W; ++w)
-    if (j0 + w < n) out[w] = acc[w];
+  for (int w = 0; w < W; ++w) sh[wave][lane * W + w] = acc[w];
+  __syncthreads();
+  // thread t adds column t of the block (and t + 256 when the block is wider)
+  for (int c = threadIdx.x; c < 64 * W; c += kBlock) {
+    if (c0 + c >= n) break;
+    S v = sh[0][c];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) v += sh[w][c];
+    part[(int64_t)slice * n + c0 + c] = v;
+  }
 }
 
+// One block per 64 columns: wave w adds slices w, w+4, ... in FP64, the four
+// wave sums are added in wave order, then Adagrad (or the fixed step) and the
+// projection.
 template <typename S>
 __global__ void __launch_bounds__(kBlock)
 k_dense_update(int32_t n, int32_t n_slices, const S* __restrict__ part, S* __restrict__ q,
                S* __restrict__ A, StepArgs st) {
-  const int j = blockIdx.x * kBlock + threadIdx.x;
-  if (j >= n) return;
+  __shared__ double sh[kWaves][64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 64 + lane;
   double gd = 0.0;
-  for (int k = 0; k < n_slices; ++k) gd += static_cast<double>(part[(int64_t)k * n + j]);
+  if (j < n)
+    for (int k = wave; k < n_slices; k += kWaves) gd += static_cast<double>(part[(int64_t)k * n + j]);
+  sh[wave][lane] = gd;
+  __syncthreads();
+  if (wave != 0 || j >= n) return;
+  gd = sh[0][lane];
+#pragma unroll
+  for (int w = 1; w < kWaves; ++w) gd += sh[w][lane];
   const S g = static_cast<S>(gd);
   S v = q[j];
   if (st.optimizer == 0) {
@@ -153,7 +180,7 @@ k_dense_update(int32_t n, int32_t n_slices, const S* __restrict__ part, S* __res
   q[j] = v > S(0) ? v : S(0);
 }
 
-// loss[e] = sum over rows of r^2, in row order (FP64).
+// loss[e] = sum over rows of r^2 (FP64, fixed order: strided per thread, then a tree).
 template <typename S>
 __global__ void __launch_bounds__(kBlock)
 k_dense_sq_sum(int32_t m, const S* __restrict__ r, double* __restrict__ out) {
@@ -180,7 +207,7 @@ hipError_t run(const DenseArgs& a, hipStream_t s) {
   S* r = static_cast<S*>(a.r);
   S* part = static_cast<S*>(a.part);
   constexpr int W = VEC ? Vec<S>::N : 1;
-  const unsigned col_blocks = blocks_for(a.n, kBlock * W);
+  const unsigned col_blocks = blocks_for(a.n, 64 * W);
   for (int32_t e = 0; e < a.E; ++e) {
     for (int32_t s0 = 0; s0 < a.m; s0 += a.chunk) {
       const int32_t nr = std::min(a.chunk, a.m - s0);
@@ -190,7 +217,7 @@ hipError_t run(const DenseArgs& a, hipStream_t s) {
                          a.n, nr, rows, B, y, q, r);
       hipLaunchKernelGGL((k_dense_colsum<S, VEC>), dim3(col_blocks, n_slices), dim3(kBlock), 0, s,
                          a.n, nr, rows, B, r, part);
-      hipLaunchKernelGGL(k_dense_update<S>, dim3(blocks_for(a.n, kBlock)), dim3(kBlock), 0, s, a.n,
+      hipLaunchKernelGGL(k_dense_update<S>, dim3(blocks_for(a.n, 64)), dim3(kBlock), 0, s, a.n,
                          n_slices, part, q, A, a.st);
     }
     if (a.loss) {

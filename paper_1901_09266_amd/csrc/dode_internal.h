@@ -9,7 +9,13 @@
 
 #include "../../include/dode.h"
 
-// Device view of the incidence pattern (CSR by link and CSC by OD).
+// Device view of the incidence pattern (CSR by link and CSC by OD), and the
+// sliced layout of the adjoint's value copy WT: ODs come in slices of 64, and
+// entry k of OD p's column sits at sc_off[p/64] + 64*k + p%64 of a block, so
+// the 64 lanes that walk 64 neighbouring columns read 64 neighbouring values
+// at every step.  Slots past a column's degree are padding (zero, never read).
+// (Link degrees vary along a corridor, so the forward copy W stays in CSR
+// order: sliced, its padding would be fetched with the short rows' slices.)
 struct DevPat {
   int32_t P, L, T, H, K;
   int64_t nnz;
@@ -17,17 +23,22 @@ struct DevPat {
   const int32_t* col;       // [nnz]  OD of CSR entry j
   const int32_t* col_ptr;   // [P+1]
   const int32_t* row;       // [nnz]  link of CSC entry jj
+  int64_t sc_len;           // values per (l, t) block of WT
+  const int32_t* sc_off;    // [ceil(P/64)] first slot of each OD slice
+  const int32_t* sc_row;    // [sc_len]     link of each WT slot
+  const int32_t* sc_pos;    // [nnz]        WT slot of CSC entry jj
 };
 
 // Device view of the value arrays of all clusters.
-//   W : CSR order  [C][K][T][nnz]
-//   WT: CSC order  [C][K][T][nnz]
+//   W : CSR order      [C][K][T][nnz]
+//   WT: sliced by OD   [C][K][T][sc_len]
 //   scale (FP8 only): [C][K][T][n_ptile], one float per 64-OD column tile
 struct DevVals {
   const void* W;
   const void* WT;
   const float* scale;
-  int64_t cstride;       // K*T*nnz
+  int64_t cstride_r;     // K*T*nnz
+  int64_t cstride_c;     // K*T*sc_len
   int32_t n_ptile;       // ceil(P/64)
 };
 
@@ -66,6 +77,10 @@ struct dode_dar {
   int32_t* d_row = nullptr;
   int32_t* d_csc2csr = nullptr;   // CSC slot -> CSR slot
   int32_t* d_row_of_nz = nullptr; // link of CSR slot j
+  int64_t sc_len = 0;               // sliced layout of WT (see DevPat)
+  int32_t* d_sc_off = nullptr;
+  int32_t* d_sc_row = nullptr;
+  int32_t* d_sc_pos = nullptr;
   void* d_W = nullptr;
   void* d_WT = nullptr;
   float* d_scale = nullptr;
@@ -85,10 +100,12 @@ struct dode_dar {
   std::vector<int32_t> h_posf, h_posg;
 
   DevPat pat() const {
-    return DevPat{dims.P, dims.L, dims.T, dims.H, dims.K, nnz, d_row_ptr, d_col, d_col_ptr, d_row};
+    return DevPat{dims.P, dims.L, dims.T, dims.H, dims.K, nnz, d_row_ptr, d_col, d_col_ptr, d_row,
+                  sc_len, d_sc_off, d_sc_row, d_sc_pos};
   }
   DevVals vals() const {
-    return DevVals{d_W, d_WT, d_scale, (int64_t)dims.K * dims.T * nnz, (dims.P + 63) / 64};
+    return DevVals{d_W, d_WT, d_scale, (int64_t)dims.K * dims.T * nnz,
+                   (int64_t)dims.K * dims.T * sc_len, (dims.P + 63) / 64};
   }
 };
 

@@ -92,7 +92,7 @@ __device__ __forceinline__ S row_dot(const DevPat& pt, const DevVals& v, int c, 
     const int t = h - l;
     if (t < 0) break;
     if (t >= pt.T) continue;
-    const int64_t base = c * v.cstride + ((int64_t)l * pt.T + t) * pt.nnz;
+    const int64_t base = c * v.cstride_r + ((int64_t)l * pt.T + t) * pt.nnz;
     const int64_t sbase = (c * (int64_t)pt.K * pt.T + (int64_t)l * pt.T + t) * v.n_ptile;
     const S* qt = q + (int64_t)t * q_t;
     for (int32_t j = j0; j < j1; ++j) {
@@ -106,22 +106,26 @@ __device__ __forceinline__ S row_dot(const DevPat& pt, const DevVals& v, int c, 
 
 // Column (t, p) of rho_c^T applied to residual rows: sum over lags l whose row
 // block h = t+l is in the minibatch (slot pos[h]-first in [0, bh)) of sum_{a on p} W[l][t][a,p] r[slot][a].
+// The column's entries are taken in CSC order from the OD-sliced layout.
 template <int ST, typename S>
 __device__ __forceinline__ S col_dot_chunk(const DevPat& pt, const DevVals& v, int c, int t, int p,
                                            const int32_t* pos_c, int32_t first, int32_t bh,
                                            const S* Rd, int64_t r_s, int64_t r_b) {
   S acc = 0;
-  const int32_t k0 = pt.col_ptr[p], k1 = pt.col_ptr[p + 1];
+  const int32_t deg = pt.col_ptr[p + 1] - pt.col_ptr[p];
+  const int32_t s0 = pt.sc_off[p >> 6] + (p & 63);
   for (int l = 0; l < pt.K; ++l) {
     const int h = t + l;
     if (h >= pt.H) break;
     const int s = pos_c ? pos_c[h] - first : h;
     if (s < 0 || s >= bh) continue;
-    const int64_t base = c * v.cstride + ((int64_t)l * pt.T + t) * pt.nnz;
+    const int64_t base = c * v.cstride_c + ((int64_t)l * pt.T + t) * pt.sc_len;
     const int64_t si = (c * (int64_t)pt.K * pt.T + (int64_t)l * pt.T + t) * v.n_ptile + (p >> 6);
     const S* r = Rd + (int64_t)s * r_s;
-    for (int32_t jj = k0; jj < k1; ++jj)
-      acc += static_cast<S>(Load<ST>::get(v.WT, base + jj, v.scale, si)) * r[col_at(pt.row[jj], r_b)];
+    for (int32_t k = 0; k < deg; ++k) {
+      const int32_t slot = s0 + 64 * k;
+      acc += static_cast<S>(Load<ST>::get(v.WT, base + slot, v.scale, si)) * r[col_at(pt.sc_row[slot], r_b)];
+    }
   }
   return acc;
 }
@@ -278,12 +282,14 @@ __global__ void k_clamp(S* __restrict__ Q, int64_t n) {
 template <typename S>
 __global__ void __launch_bounds__(kRedBlock)
 k_quantize(DevPat pt, int32_t storage, int32_t c, const S* __restrict__ Wsrc, void* W, void* WT,
-           float* scale, const int32_t* __restrict__ csc2csr, int64_t cstride, int32_t n_ptile) {
-  // one block per (l, t) block of cluster c
+           float* scale, const int32_t* __restrict__ csc2csr, int64_t cstride_r, int64_t cstride_c,
+           int32_t n_ptile) {
+  // one block per (l, t) block of cluster c; the source is in CSR order, W is
+  // written in CSR order and WT in its OD-sliced layout
   const int lt = blockIdx.x;
-  const int64_t base = (int64_t)lt * pt.nnz;
-  const S* src = Wsrc + base;
-  const int64_t dst = c * cstride + base;
+  const S* src = Wsrc + (int64_t)lt * pt.nnz;
+  const int64_t dr = c * cstride_r + (int64_t)lt * pt.nnz;
+  const int64_t dc = c * cstride_c + (int64_t)lt * pt.sc_len;
   __shared__ float smax[64];
   if (storage == DODE_FP8_E4M3) {
     for (int i = threadIdx.x; i < n_ptile; i += blockDim.x) smax[i] = 0.f;
@@ -299,22 +305,23 @@ k_quantize(DevPat pt, int32_t storage, int32_t c, const S* __restrict__ Wsrc, vo
   }
   for (int64_t jj = threadIdx.x; jj < pt.nnz; jj += blockDim.x) {
     const int64_t j = csc2csr[jj];
+    const int64_t oj = dr + j, ojj = dc + pt.sc_pos[jj];
     const float w = static_cast<float>(src[j]);
     if (storage == DODE_F32) {
-      static_cast<float*>(W)[dst + j] = w;
-      static_cast<float*>(WT)[dst + jj] = w;
+      static_cast<float*>(W)[oj] = w;
+      static_cast<float*>(WT)[ojj] = w;
     } else if (storage == DODE_BF16) {
       const uint16_t b = f32_to_bf16_rne(w);
-      static_cast<uint16_t*>(W)[dst + j] = b;
-      static_cast<uint16_t*>(WT)[dst + jj] = b;
+      static_cast<uint16_t*>(W)[oj] = b;
+      static_cast<uint16_t*>(WT)[ojj] = b;
     } else if (storage == DODE_FP8_E4M3) {
       const float sc = smax[pt.col[j] >> 6] > 0.f ? smax[pt.col[j] >> 6] / 448.f : 1.f;
       const uint8_t b = f32_to_e4m3_rne(w / sc);
-      static_cast<uint8_t*>(W)[dst + j] = b;
-      static_cast<uint8_t*>(WT)[dst + jj] = b;
+      static_cast<uint8_t*>(W)[oj] = b;
+      static_cast<uint8_t*>(WT)[ojj] = b;
     } else {
-      static_cast<double*>(W)[dst + j] = static_cast<double>(src[j]);
-      static_cast<double*>(WT)[dst + jj] = static_cast<double>(src[j]);
+      static_cast<double*>(W)[oj] = static_cast<double>(src[j]);
+      static_cast<double*>(WT)[ojj] = static_cast<double>(src[j]);
     }
   }
 }
@@ -567,10 +574,12 @@ hipError_t quantize_values(const dode_dar* dar, int32_t cluster, const void* W_s
   if (dar->storage == DODE_F64)
     hipLaunchKernelGGL(k_quantize<double>, grid, dim3(kRedBlock), 0, s, dar->pat(),
                        (int32_t)dar->storage, cluster, static_cast<const double*>(W_state), dar->d_W,
-                       dar->d_WT, dar->d_scale, dar->d_csc2csr, dar->vals().cstride, n_ptile);
+                       dar->d_WT, dar->d_scale, dar->d_csc2csr, dar->vals().cstride_r,
+                       dar->vals().cstride_c, n_ptile);
   else
     hipLaunchKernelGGL(k_quantize<float>, grid, dim3(kRedBlock), 0, s, dar->pat(),
                        (int32_t)dar->storage, cluster, static_cast<const float*>(W_state), dar->d_W,
-                       dar->d_WT, dar->d_scale, dar->d_csc2csr, dar->vals().cstride, n_ptile);
+                       dar->d_WT, dar->d_scale, dar->d_csc2csr, dar->vals().cstride_r,
+                       dar->vals().cstride_c, n_ptile);
   return hipGetLastError();
 }
