@@ -461,22 +461,36 @@ void dode_spgd_defaults(dode_spgd_params* p) {
 namespace {
 
 // Sliced layout of n lines whose entries are ptr[i] .. ptr[i+1]-1: slice g
-// holds lines 64g .. 64g+63 and is 64 * (its largest degree) slots long; entry
-// k of line i goes to off[i/64] + 64k + i%64.  Returns the slots per block.
-int64_t build_slices(int32_t n, const std::vector<int32_t>& ptr, std::vector<int32_t>& off,
+// holds lines 64g .. 64g+63 and is 64 * (its largest degree) slots long.
+// With `ranked`, the lines of a slice take its lanes in order of decreasing
+// degree (ties by index), else line i takes lane i%64.  Entry k of line i goes
+// to first[i] + 64k.  Returns the slots per block.
+int64_t build_slices(int32_t n, const std::vector<int32_t>& ptr, bool ranked,
+                     std::vector<int32_t>& off, std::vector<int32_t>& first,
                      std::vector<int32_t>& pos) {
   const int32_t ng = (n + 63) / 64;
   off.assign(ng, 0);
+  first.assign(n, 0);
   pos.assign(ptr[n], 0);
   int64_t len = 0;
+  std::vector<int32_t> lines;
   for (int32_t g = 0; g < ng; ++g) {
+    lines.clear();
     int32_t width = 0;
-    for (int32_t i = 64 * g; i < std::min(n, 64 * g + 64); ++i) width = std::max(width, ptr[i + 1] - ptr[i]);
+    for (int32_t i = 64 * g; i < std::min(n, 64 * g + 64); ++i) {
+      lines.push_back(i);
+      width = std::max(width, ptr[i + 1] - ptr[i]);
+    }
+    if (ranked)
+      std::stable_sort(lines.begin(), lines.end(), [&](int32_t x, int32_t y) {
+        return ptr[x + 1] - ptr[x] > ptr[y + 1] - ptr[y];
+      });
     off[g] = (int32_t)len;
+    for (size_t lane = 0; lane < lines.size(); ++lane) first[lines[lane]] = (int32_t)(len + lane);
     len += 64 * (int64_t)width;
   }
   for (int32_t i = 0; i < n; ++i)
-    for (int32_t k = 0; k < ptr[i + 1] - ptr[i]; ++k) pos[ptr[i] + k] = off[i >> 6] + 64 * k + (i & 63);
+    for (int32_t k = 0; k < ptr[i + 1] - ptr[i]; ++k) pos[ptr[i] + k] = first[i] + 64 * k;
   return len;
 }
 
@@ -491,7 +505,8 @@ dode_status dar_destroy(dode_dar* dar) {
                   (void*)dar->d_row, (void*)dar->d_csc2csr, dar->d_W, dar->d_WT,
                   (void*)dar->d_scale, (void*)dar->d_tile_meta, dar->d_Fv, dar->d_Gv,
                   dar->d_Fc, dar->d_Gc,
-                  (void*)dar->d_row_of_nz, (void*)dar->d_sc_off, (void*)dar->d_sc_row,
+                  (void*)dar->d_row_of_nz, (void*)dar->d_sr_first, (void*)dar->d_sr_col,
+                  (void*)dar->d_sr_pos, (void*)dar->d_sc_off, (void*)dar->d_sc_row,
                   (void*)dar->d_sc_pos, (void*)dar->d_posf, (void*)dar->d_posg})
     if (p) (void)hipFree(p);
   (void)hipSetDevice(cur);
@@ -582,23 +597,29 @@ dode_status dar_create_ex(const dode_dims* dims, int32_t n_clusters, const int32
       for (int32_t j = row_ptr[a]; j < row_ptr[a + 1]; ++j) rows[j] = a;
     HIP_TRY(dev_copy(&d->d_row_of_nz, rows));
   }
-  // the OD-sliced layout of WT (CSC order inside a column)
-  std::vector<int32_t> sc_off, sc_pos;
-  d->sc_len = build_slices(dm.P, d->h_col_ptr, sc_off, sc_pos);
-  if (d->sc_len > INT32_MAX) {
+  // sliced value layouts: W by link (ranked by degree), WT by OD; each line's
+  // entries keep their CSR / CSC order
+  std::vector<int32_t> sr_off, sr_first, sr_pos, sc_off, sc_first, sc_pos;
+  d->sr_len = build_slices(dm.L, d->h_row_ptr, true, sr_off, sr_first, sr_pos);
+  d->sc_len = build_slices(dm.P, d->h_col_ptr, false, sc_off, sc_first, sc_pos);
+  if (d->sr_len > INT32_MAX || d->sc_len > INT32_MAX) {
     dar_destroy(d.release());
     return fail(DODE_ERR_SHAPE, "pattern too large for the sliced layout");
   }
   {
-    std::vector<int32_t> sc_row(d->sc_len, 0);
+    std::vector<int32_t> sr_col(d->sr_len, 0), sc_row(d->sc_len, 0);
+    for (int64_t j = 0; j < nnz; ++j) sr_col[sr_pos[j]] = col_idx[j];
     for (int64_t jj = 0; jj < nnz; ++jj) sc_row[sc_pos[jj]] = d->h_row[jj];
+    HIP_TRY(dev_copy(&d->d_sr_first, sr_first));
+    HIP_TRY(dev_copy(&d->d_sr_col, sr_col));
+    HIP_TRY(dev_copy(&d->d_sr_pos, sr_pos));
     HIP_TRY(dev_copy(&d->d_sc_off, sc_off));
     HIP_TRY(dev_copy(&d->d_sc_row, sc_row));
     HIP_TRY(dev_copy(&d->d_sc_pos, sc_pos));
   }
 
   const size_t esz = storage == DODE_F64 ? 8 : storage == DODE_F32 ? 4 : storage == DODE_BF16 ? 2 : 1;
-  const int64_t cstride_r = cstride, cstride_c = (int64_t)dm.K * dm.T * d->sc_len;
+  const int64_t cstride_r = (int64_t)dm.K * dm.T * d->sr_len, cstride_c = (int64_t)dm.K * dm.T * d->sc_len;
   const size_t vbytes_r = (size_t)n_clusters * cstride_r * esz, vbytes_c = (size_t)n_clusters * cstride_c * esz;
   HIP_TRY(hipMalloc(&d->d_W, std::max<size_t>(16, vbytes_r)));
   HIP_TRY(hipMalloc(&d->d_WT, std::max<size_t>(16, vbytes_c)));
@@ -617,9 +638,9 @@ dode_status dar_create_ex(const dode_dims* dims, int32_t n_clusters, const int32
       return fail(st, "tile layout: %s", err.c_str());
     }
   }
-  // host conversion, one cluster at a time: CSR-order codes (W and the tiles)
-  // and the OD-sliced copy WT (padding slots stay zero)
-  std::vector<uint8_t> hw(cstride * esz), hwt(cstride_c * esz, 0);
+  // host conversion, one cluster at a time: CSR-order codes (for the tiles)
+  // and the two sliced copies (padding slots stay zero)
+  std::vector<uint8_t> hw(cstride * esz), hws(cstride_r * esz, 0), hwt(cstride_c * esz, 0);
   std::vector<uint16_t> hcorr(d->has_corr ? cstride : 0);
   std::vector<float> hs(storage == DODE_FP8_E4M3 ? (size_t)dm.K * dm.T * n_ptile : 0);
   std::vector<double> tmax(n_ptile);
@@ -639,19 +660,22 @@ dode_status dar_create_ex(const dode_dims* dims, int32_t n_clusters, const int32
         const int64_t j = d->h_csc2csr[jj];
         const double v = src[lt * nnz + j];
         const int64_t ij = lt * nnz + j;
-        const int64_t sjj = lt * d->sc_len + sc_pos[jj];
+        const int64_t sj = lt * d->sr_len + sr_pos[j], sjj = lt * d->sc_len + sc_pos[jj];
         switch (storage) {
           case DODE_F64:
             reinterpret_cast<double*>(hw.data())[ij] = v;
+            reinterpret_cast<double*>(hws.data())[sj] = v;
             reinterpret_cast<double*>(hwt.data())[sjj] = v;
             break;
           case DODE_F32:
             reinterpret_cast<float*>(hw.data())[ij] = static_cast<float>(v);
+            reinterpret_cast<float*>(hws.data())[sj] = static_cast<float>(v);
             reinterpret_cast<float*>(hwt.data())[sjj] = static_cast<float>(v);
             break;
           case DODE_BF16: {
             const uint16_t b = host_f64_to_bf16(v);
             reinterpret_cast<uint16_t*>(hw.data())[ij] = b;
+            reinterpret_cast<uint16_t*>(hws.data())[sj] = b;
             reinterpret_cast<uint16_t*>(hwt.data())[sjj] = b;
             break;
           }
@@ -659,6 +683,7 @@ dode_status dar_create_ex(const dode_dims* dims, int32_t n_clusters, const int32
             const float sc = hs[lt * n_ptile + (col_idx[j] >> 6)];
             const uint8_t b = host_f64_to_e4m3(v / sc);
             hw[ij] = b;
+            hws[sj] = b;
             hwt[sjj] = b;
             if (d->has_corr) {
               // the kernels expand a code to bf16(fp32(scale * e4m3)); the
@@ -671,7 +696,7 @@ dode_status dar_create_ex(const dode_dims* dims, int32_t n_clusters, const int32
           }
         }
       }
-    HIP_TRY(hipMemcpy(static_cast<uint8_t*>(d->d_W) + c * cstride_r * esz, hw.data(),
+    HIP_TRY(hipMemcpy(static_cast<uint8_t*>(d->d_W) + c * cstride_r * esz, hws.data(),
                       cstride_r * esz, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(static_cast<uint8_t*>(d->d_WT) + c * cstride_c * esz, hwt.data(),
                       cstride_c * esz, hipMemcpyHostToDevice));

@@ -10,12 +10,13 @@
 #include "../../include/dode.h"
 
 // Device view of the incidence pattern (CSR by link and CSC by OD), and the
-// sliced layout of the adjoint's value copy WT: ODs come in slices of 64, and
-// entry k of OD p's column sits at sc_off[p/64] + 64*k + p%64 of a block, so
-// the 64 lanes that walk 64 neighbouring columns read 64 neighbouring values
-// at every step.  Slots past a column's degree are padding (zero, never read).
-// (Link degrees vary along a corridor, so the forward copy W stays in CSR
-// order: sliced, its padding would be fetched with the short rows' slices.)
+// sliced layouts of the two value copies.  Lines (links for W, ODs for WT)
+// come in slices of 64; entry k of a line sits 64*k after the line's first
+// slot, so the 64 lanes that walk 64 neighbouring lines read one run of
+// neighbouring values at every step.  In W a slice's links are ranked by
+// degree (longest first; link degrees vary along a corridor), so the lanes
+// still active at step k hold a prefix of the run and no padding is fetched.
+// Slots past a line's degree are padding (zero, never read).
 struct DevPat {
   int32_t P, L, T, H, K;
   int64_t nnz;
@@ -23,21 +24,24 @@ struct DevPat {
   const int32_t* col;       // [nnz]  OD of CSR entry j
   const int32_t* col_ptr;   // [P+1]
   const int32_t* row;       // [nnz]  link of CSC entry jj
-  int64_t sc_len;           // values per (l, t) block of WT
+  int64_t sr_len, sc_len;   // values per (l, t) block of W / WT
+  const int32_t* sr_first;  // [L]          first slot of each link
+  const int32_t* sr_col;    // [sr_len]     OD of each W slot
+  const int32_t* sr_pos;    // [nnz]        W slot of CSR entry j
   const int32_t* sc_off;    // [ceil(P/64)] first slot of each OD slice
   const int32_t* sc_row;    // [sc_len]     link of each WT slot
   const int32_t* sc_pos;    // [nnz]        WT slot of CSC entry jj
 };
 
 // Device view of the value arrays of all clusters.
-//   W : CSR order      [C][K][T][nnz]
+//   W : sliced by link [C][K][T][sr_len]
 //   WT: sliced by OD   [C][K][T][sc_len]
 //   scale (FP8 only): [C][K][T][n_ptile], one float per 64-OD column tile
 struct DevVals {
   const void* W;
   const void* WT;
   const float* scale;
-  int64_t cstride_r;     // K*T*nnz
+  int64_t cstride_r;     // K*T*sr_len
   int64_t cstride_c;     // K*T*sc_len
   int32_t n_ptile;       // ceil(P/64)
 };
@@ -77,7 +81,10 @@ struct dode_dar {
   int32_t* d_row = nullptr;
   int32_t* d_csc2csr = nullptr;   // CSC slot -> CSR slot
   int32_t* d_row_of_nz = nullptr; // link of CSR slot j
-  int64_t sc_len = 0;               // sliced layout of WT (see DevPat)
+  int64_t sr_len = 0, sc_len = 0;   // sliced value layouts (see DevPat)
+  int32_t* d_sr_first = nullptr;
+  int32_t* d_sr_col = nullptr;
+  int32_t* d_sr_pos = nullptr;
   int32_t* d_sc_off = nullptr;
   int32_t* d_sc_row = nullptr;
   int32_t* d_sc_pos = nullptr;
@@ -101,10 +108,10 @@ struct dode_dar {
 
   DevPat pat() const {
     return DevPat{dims.P, dims.L, dims.T, dims.H, dims.K, nnz, d_row_ptr, d_col, d_col_ptr, d_row,
-                  sc_len, d_sc_off, d_sc_row, d_sc_pos};
+                  sr_len, sc_len, d_sr_first, d_sr_col, d_sr_pos, d_sc_off, d_sc_row, d_sc_pos};
   }
   DevVals vals() const {
-    return DevVals{d_W, d_WT, d_scale, (int64_t)dims.K * dims.T * nnz,
+    return DevVals{d_W, d_WT, d_scale, (int64_t)dims.K * dims.T * sr_len,
                    (int64_t)dims.K * dims.T * sc_len, (dims.P + 63) / 64};
   }
 };

@@ -353,7 +353,7 @@ k_adj_mfma(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, Layout ly,
   }
 }
 
-// Copy the pattern-form codes of one (cluster, l, t) block (CSR order, just
+// Copy the pattern-form codes of one (cluster, l, t) block (link-sliced, just
 // rewritten by the quantisation kernel) into its packed tiles.
 template <typename E>
 __global__ void __launch_bounds__(256)
@@ -364,11 +364,12 @@ k_update_tiles(DevPat pt, DevTiles tl, int32_t c, const E* __restrict__ codes,
   const int l = (int)(lt / pt.T), t = (int)(lt % pt.T);
   if (t + l >= pt.H) return;   // block never read
   const int64_t blk = (int64_t)c * pt.K * pt.T + lt;
-  const E* w = codes + blk * pt.nnz;
+  const E* w = codes + blk * pt.sr_len;   // link-sliced codes
   E* f = F + blk * tl.kf_total * 512;
   E* g = G + blk * tl.kg_total * 512;
-  for (int64_t j = threadIdx.x; j < pt.nnz; j += blockDim.x) f[posf[j]] = w[j];
-  for (int64_t jj = threadIdx.x; jj < pt.nnz; jj += blockDim.x) g[posg[jj]] = w[csc2csr[jj]];
+  for (int64_t j = threadIdx.x; j < pt.nnz; j += blockDim.x) f[posf[j]] = w[pt.sr_pos[j]];
+  for (int64_t jj = threadIdx.x; jj < pt.nnz; jj += blockDim.x)
+    g[posg[jj]] = w[pt.sr_pos[csc2csr[jj]]];
 }
 
 }  // namespace

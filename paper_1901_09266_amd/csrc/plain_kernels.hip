@@ -83,21 +83,38 @@ __device__ double block_max(double v, double* sh) {
 }
 
 // Row (h, a) of rho_c applied to q_d:  sum_l sum_{p in row a} W[l][h-l][a,p] q[h-l][p].
+// The row's entries are taken in CSR order from the link-sliced layout, four
+// steps' loads issued together (the sums keep their order).
 template <int ST, typename S>
 __device__ __forceinline__ S row_dot(const DevPat& pt, const DevVals& v, int c, int h, int a,
                                      const S* q, int64_t q_t, int64_t q_b) {
   S acc = 0;
-  const int32_t j0 = pt.row_ptr[a], j1 = pt.row_ptr[a + 1];
+  const int32_t deg = pt.row_ptr[a + 1] - pt.row_ptr[a];
+  const int32_t s0 = pt.sr_first[a];
   for (int l = 0; l < pt.K; ++l) {
     const int t = h - l;
     if (t < 0) break;
     if (t >= pt.T) continue;
-    const int64_t base = c * v.cstride_r + ((int64_t)l * pt.T + t) * pt.nnz;
+    const int64_t base = c * v.cstride_r + ((int64_t)l * pt.T + t) * pt.sr_len;
     const int64_t sbase = (c * (int64_t)pt.K * pt.T + (int64_t)l * pt.T + t) * v.n_ptile;
     const S* qt = q + (int64_t)t * q_t;
-    for (int32_t j = j0; j < j1; ++j) {
-      const int p = pt.col[j];
-      acc += static_cast<S>(Load<ST>::get(v.W, base + j, v.scale, sbase + (p >> 6))) *
+    int32_t k = 0;
+    for (; k + 4 <= deg; k += 4) {
+      S w[4], x[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int32_t slot = s0 + 64 * (k + u);
+        const int p = pt.sr_col[slot];
+        w[u] = static_cast<S>(Load<ST>::get(v.W, base + slot, v.scale, sbase + (p >> 6)));
+        x[u] = qt[col_at(p, q_b)];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc += w[u] * x[u];
+    }
+    for (; k < deg; ++k) {
+      const int32_t slot = s0 + 64 * k;
+      const int p = pt.sr_col[slot];
+      acc += static_cast<S>(Load<ST>::get(v.W, base + slot, v.scale, sbase + (p >> 6))) *
              qt[col_at(p, q_b)];
     }
   }
@@ -106,7 +123,8 @@ __device__ __forceinline__ S row_dot(const DevPat& pt, const DevVals& v, int c, 
 
 // Column (t, p) of rho_c^T applied to residual rows: sum over lags l whose row
 // block h = t+l is in the minibatch (slot pos[h]-first in [0, bh)) of sum_{a on p} W[l][t][a,p] r[slot][a].
-// The column's entries are taken in CSC order from the OD-sliced layout.
+// The column's entries are taken in CSC order from the OD-sliced layout, four
+// steps' loads issued together.
 template <int ST, typename S>
 __device__ __forceinline__ S col_dot_chunk(const DevPat& pt, const DevVals& v, int c, int t, int p,
                                            const int32_t* pos_c, int32_t first, int32_t bh,
@@ -122,7 +140,19 @@ __device__ __forceinline__ S col_dot_chunk(const DevPat& pt, const DevVals& v, i
     const int64_t base = c * v.cstride_c + ((int64_t)l * pt.T + t) * pt.sc_len;
     const int64_t si = (c * (int64_t)pt.K * pt.T + (int64_t)l * pt.T + t) * v.n_ptile + (p >> 6);
     const S* r = Rd + (int64_t)s * r_s;
-    for (int32_t k = 0; k < deg; ++k) {
+    int32_t k = 0;
+    for (; k + 4 <= deg; k += 4) {
+      S w[4], x[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int32_t slot = s0 + 64 * (k + u);
+        w[u] = static_cast<S>(Load<ST>::get(v.WT, base + slot, v.scale, si));
+        x[u] = r[col_at(pt.sc_row[slot], r_b)];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc += w[u] * x[u];
+    }
+    for (; k < deg; ++k) {
       const int32_t slot = s0 + 64 * k;
       acc += static_cast<S>(Load<ST>::get(v.WT, base + slot, v.scale, si)) * r[col_at(pt.sc_row[slot], r_b)];
     }
@@ -284,11 +314,11 @@ __global__ void __launch_bounds__(kRedBlock)
 k_quantize(DevPat pt, int32_t storage, int32_t c, const S* __restrict__ Wsrc, void* W, void* WT,
            float* scale, const int32_t* __restrict__ csc2csr, int64_t cstride_r, int64_t cstride_c,
            int32_t n_ptile) {
-  // one block per (l, t) block of cluster c; the source is in CSR order, W is
-  // written in CSR order and WT in its OD-sliced layout
+  // one block per (l, t) block of cluster c; the source is in CSR order, the
+  // two copies are written in their sliced layouts
   const int lt = blockIdx.x;
   const S* src = Wsrc + (int64_t)lt * pt.nnz;
-  const int64_t dr = c * cstride_r + (int64_t)lt * pt.nnz;
+  const int64_t dr = c * cstride_r + (int64_t)lt * pt.sr_len;
   const int64_t dc = c * cstride_c + (int64_t)lt * pt.sc_len;
   __shared__ float smax[64];
   if (storage == DODE_FP8_E4M3) {
@@ -305,7 +335,7 @@ k_quantize(DevPat pt, int32_t storage, int32_t c, const S* __restrict__ Wsrc, vo
   }
   for (int64_t jj = threadIdx.x; jj < pt.nnz; jj += blockDim.x) {
     const int64_t j = csc2csr[jj];
-    const int64_t oj = dr + j, ojj = dc + pt.sc_pos[jj];
+    const int64_t oj = dr + pt.sr_pos[j], ojj = dc + pt.sc_pos[jj];
     const float w = static_cast<float>(src[j]);
     if (storage == DODE_F32) {
       static_cast<float*>(W)[oj] = w;
