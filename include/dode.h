@@ -322,12 +322,12 @@ dode_status dar_from_costs(const dode_routes* routes, int32_t f64, const void* R
  *       A += g^2, q -= eta g / (sqrt(A) + eps)) or a fixed step (optimizer 1:
  *       q -= eta g), then q = max(q, 0)
  *   loss_hist host [E] or NULL: ||B q - y||^2 after each epoch (FP64 sum in
- *       row order; costs one more pass over B per epoch)
+ *       a fixed order; costs one more pass over B per epoch)
  *   f64: nonzero for double arrays, else float.
  * Errors: DODE_ERR_ARG if a perms row is not a permutation of 0..m-1 (checked
  * on the host), for a non-positive eta or chunk or a negative eps.
  * Synchronises `stream` (the permutations are read back first, and the loss
- * history after the run); scratch of m + ceil(min(chunk, m)/32)*n values.
+ * history after the run); scratch of m + ceil(min(chunk, m)/128)*n values.
  */
 dode_status dense_spgd_run(int32_t m, int32_t n, int32_t f64, const void* B, const void* y, void* q,
                            void* A, const int32_t* perms, int32_t E, int32_t chunk,
