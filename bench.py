@@ -40,7 +40,9 @@ WORKLOADS = {
     5: "400 OD, 1500 links, T=H=288, K=6, 1095 days in 12 clusters (300..10), corridor incidence 8%",
 }
 
-ESIZE = {"f64": 8, "f32": 4, "bf16": 2, "fp8": 1}
+ESIZE = {"f64": 8, "f32": 4, "bf16": 2, "bf16-sparse": 2, "fp8": 1}
+STORAGE = {"f64": "f64", "f32": "f32", "bf16": "bf16", "bf16-sparse": "bf16", "fp8": "fp8"}
+KERNEL_PATH = {"bf16-sparse": 1}   # others: the fastest path for the storage type
 FORMS = {
     "bf16": "grouped matrix-core form: bf16 assignment tiles x FP32 demand/residual split into bf16 "
             "hi+lo, v_mfma_f32_16x16x32_bf16, FP32 accumulation, fused FP32 Adagrad step",
@@ -50,6 +52,8 @@ FORMS = {
            "v_mfma_f32_16x16x32_bf16, FP32 accumulation, fused FP32 Adagrad step; optional "
            "full-batch refinement steps on corrected values (FP8 + bf16 correction)",
     "f64": "FP64 values, sparse pattern kernels",
+    "bf16-sparse": "bf16 values, sparse pattern kernels (one thread per output entry), FP32 "
+                   "arithmetic",
 }
 
 
@@ -124,13 +128,14 @@ def run_form(dode, torch, inst, form, perms, E_total, warmup, steps, bh, refine=
     dt = torch.float64 if form == "f64" else torch.float32
     t0 = time.time()
     dar = dode.dar_create(inst.P, inst.L, inst.T, inst.H, inst.K, inst.row_ptr, inst.col_idx, inst.W,
-                          storage=form, correction=refine > 0, stream=0)
+                          storage=STORAGE[form], correction=refine > 0, stream=0)
     X = torch.as_tensor(inst.x).to(device="cuda", dtype=dt).contiguous()
     D = inst.D
     Q = torch.zeros((D, inst.T, inst.P), dtype=dt, device="cuda")
     A = torch.zeros_like(Q)
     params = dode.make_params(epochs=E_total, batch_rows=8192, eta=5.0, optimizer=0,
-                              refine_steps=refine, day_tile=day_tile)
+                              refine_steps=refine, day_tile=day_tile,
+                              kernel_path=KERNEL_PATH.get(form, 0))
     plan = dode.spgd_plan_create(dar, inst.day_cluster, params, perm=perms, stream=0)
     dode.spgd_plan_load(plan, X, Q, A, stream=0)
     torch.cuda.synchronize()
@@ -163,11 +168,12 @@ def solve_full(dode, torch, inst, form, perms_full, E, E_snap, sample, refine=0)
     after E_snap epochs (for the comparison with the oracle run of that length)."""
     dt = torch.float64 if form == "f64" else torch.float32
     dar = dode.dar_create(inst.P, inst.L, inst.T, inst.H, inst.K, inst.row_ptr, inst.col_idx, inst.W,
-                          storage=form, correction=refine > 0, stream=0)
+                          storage=STORAGE[form], correction=refine > 0, stream=0)
     X = torch.as_tensor(inst.x).to(device="cuda", dtype=dt).contiguous()
     Q = torch.zeros((inst.D, inst.T, inst.P), dtype=dt, device="cuda")
     A = torch.zeros_like(Q)
-    p = dode.make_params(epochs=E, batch_rows=8192, eta=5.0, optimizer=0, refine_steps=refine)
+    p = dode.make_params(epochs=E, batch_rows=8192, eta=5.0, optimizer=0, refine_steps=refine,
+                         kernel_path=KERNEL_PATH.get(form, 0))
     plan = dode.spgd_plan_create(dar, inst.day_cluster, p, perm=perms_full, stream=0)
     dode.spgd_plan_load(plan, X, Q, A)
     t0 = time.time()
@@ -516,7 +522,7 @@ def main():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=3, choices=[2, 3, 5])
-    ap.add_argument("--form", default="bf16", choices=["f32", "bf16", "fp8", "f64"])
+    ap.add_argument("--form", default="bf16", choices=["f32", "bf16", "fp8", "f64", "bf16-sparse"])
     ap.add_argument("--compare", default="f32", help="plain form timed beside the headline ('' = none)")
     ap.add_argument("--epochs", type=int, default=300, help="epochs of the equal-loss solves")
     ap.add_argument("--skip-cpu", action="store_true")
@@ -608,7 +614,8 @@ def main():
     out = {"metric": "SPGD day-gradients/sec", "value": round(value, 1), "unit": "day-gradients/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": {"bf16": "bf16", "f32": "f32", "fp8": "bf16", "f64": "f64"}[args.form],
+           "dtype": {"bf16": "bf16", "f32": "f32", "fp8": "bf16", "f64": "f64",
+                     "bf16-sparse": "f32"}[args.form],
            "data": "synthetic",
            "config": {"workload": f"config {args.config}: " + WORKLOADS[args.config] +
                                   (", one ratio matrix per day (per-day DAR)" if args.per_day else ""),
