@@ -323,12 +323,13 @@ def dar_bench(args):
 
 def choice_bench(args):
     """The assignment matrix of every traffic pattern from link speeds:
-    ratios (dode_dar_from_speeds), mean path costs (dode_path_costs), logit
-    portions and eq. "assign" (dar_from_costs).  Corridor network shaped like
+    ratios and mean path costs from the same trajectories
+    (dode_dar_costs_from_speeds), logit portions and eq. "assign"
+    (dar_from_costs).  Corridor network shaped like
     the config-3 workload: 150 ODs with 3 routes each (freeway, arterial,
     mixed) of 20 links over 500 links (8% incidence), 288 five-minute
     intervals, K = 6 lags, theta = 0.01 per second, 1095 days in 8 clusters.
-    A step is the whole job: the three calls per cluster."""
+    A step is the whole job: the two calls per cluster."""
     import torch
     import paper_1901_09266_amd as dode
     from synth import make_choice_instance
@@ -348,23 +349,20 @@ def choice_bench(args):
     cost = [torch.empty((T, ci.n_paths), dtype=f32, device="cuda") for _ in range(C)]
     W = [torch.empty((K, T, ci.nnz), dtype=f32, device="cuda") for _ in range(C)]
     ev = lambda: torch.cuda.Event(enable_timing=True)
-    stage_ms = {"dar": 0.0, "costs": 0.0, "assign": 0.0}
+    stage_ms = {"dar": 0.0, "assign": 0.0}
 
     def step(timed):
         for c in range(C):
             s = sp[days[c][0]:days[c][-1] + 1]
-            e = [ev() for _ in range(4)] if timed else None
+            e = [ev() for _ in range(3)] if timed else None
             if timed:
                 e[0].record()
-            dode.dode_dar_from_speeds(pp, pl, ln, s, ci.dt, H, K, Rr=Rr[c])
+            dode.dode_dar_costs_from_speeds(pp, pl, ln, s, ci.dt, H, K, Rr=Rr[c], cost=cost[c])
             if timed:
                 e[1].record()
-            dode.dode_path_costs(pp, pl, ln, s, ci.dt, T, cost=cost[c])
-            if timed:
-                e[2].record()
             dode.dar_from_costs(routes, Rr[c], cost[c], theta, W[c])
             if timed:
-                e[3].record()
+                e[2].record()
                 marks.append(e)
 
     for _ in range(args.warmup):
@@ -380,17 +378,15 @@ def choice_bench(args):
     ms = e0.elapsed_time(e1)
     for e in marks:
         stage_ms["dar"] += e[0].elapsed_time(e[1])
-        stage_ms["costs"] += e[1].elapsed_time(e[2])
-        stage_ms["assign"] += e[2].elapsed_time(e[3])
+        stage_ms["assign"] += e[1].elapsed_time(e[2])
     per = {k: v / args.steps for k, v in stage_ms.items()}
     D = int(ci.day_cluster.shape[0])
     spd = D * ci.L * H * 4
-    byts = {"dar": spd + C * K * H * ci.n_pairs * 4,
-            "costs": spd + C * T * ci.n_paths * 4,
+    byts = {"dar": spd + C * (K * H * ci.n_pairs + T * ci.n_paths) * 4,
             "assign": C * (K * T * ci.n_pairs + T * ci.n_paths + K * T * ci.nnz) * 4}
     dom = max(per, key=per.get)
     achieved = byts[dom] / (per[dom] / 1e3) / 1e9
-    names = {"dar": "dode_dar_from_speeds", "costs": "dode_path_costs", "assign": "dar_from_costs"}
+    names = {"dar": "dode_dar_costs_from_speeds", "assign": "dar_from_costs"}
     out = {"metric": "Route-choice assignment from speeds days/sec",
            "value": round(D * args.steps / (ms / 1e3), 1), "unit": "days/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms / args.steps, 4),
@@ -420,8 +416,7 @@ def choice_bench(args):
                                "kind": "oracle",
                                "sample": f"{len(sample)} days of pattern 0, {dt_cpu:.1f}s"}
         s = sp[sample[0]:sample[-1] + 1]
-        r1 = dode.dode_dar_from_speeds(pp, pl, ln, s, ci.dt, H, K)
-        c1 = dode.dode_path_costs(pp, pl, ln, s, ci.dt, T)
+        r1, c1 = dode.dode_dar_costs_from_speeds(pp, pl, ln, s, ci.dt, H, K)
         w1 = torch.empty((K, T, ci.nnz), dtype=f32, device="cuda")
         dode.dar_from_costs(routes, r1, c1, theta, w1)
         out["check"] = {"max_abs_W_vs_oracle_sample": float(np.max(np.abs(w1.cpu().numpy() - Wo))),

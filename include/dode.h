@@ -276,6 +276,23 @@ dode_status dode_dar_from_speeds(int32_t n_paths, const int32_t* path_ptr,
                                  void* Rr, void* stream);
 
 /*
+ * dode_dar_from_speeds and, from the same trajectories, the mean path costs
+ * of dode_path_costs for the H departure intervals (section "Route choice
+ * portions", eqs. "logit" and "rt"; eq. "cost").  Arguments, checks, errors
+ * and synchronisation as for dode_dar_from_speeds, plus
+ *   cost [H][n_paths] (output, device, may be NULL): for departure interval t,
+ *       the mean over the n_days days of the time to cross the whole path when
+ *       leaving at t*dt (days summed in FP64).
+ * The scratch grows by n_paths*(H+1) values per day of a chunk and an FP64
+ * array of n_paths*H.
+ */
+dode_status dode_dar_costs_from_speeds(int32_t n_paths, const int32_t* path_ptr,
+                                       const int32_t* path_link, int64_t n_pairs, int32_t L,
+                                       const void* link_len, const void* speed, int32_t n_days,
+                                       int32_t H_speed, double dt, int32_t H, int32_t K,
+                                       int32_t f64, void* Rr, void* cost, void* stream);
+
+/*
  * Mean path travel times of a traffic pattern (section "Route choice
  * portions", eqs. "logit" and "rt"; section "Link/path travel time",
  * eq. "cost").  Path tables, lengths and speeds as for dode_dar_from_speeds

@@ -30,7 +30,7 @@ EXPORTS = ["dode_last_error", "dode_spgd_defaults", "dar_create", "dar_create_ex
            "spgd_plan_store", "spgd_run", "spgd_plan_timing", "spgd_plan_info",
            "dode_loss_bwd", "dode_routes_create", "dode_routes_destroy", "dar_from_logits",
            "dar_logits_bwd", "dode_dar_from_speeds", "dode_path_costs", "dar_from_costs",
-           "dense_spgd_run"]
+           "dense_spgd_run", "dode_dar_costs_from_speeds"]
 
 
 class DodeError(RuntimeError):
@@ -73,6 +73,8 @@ def lib():
         L.dar_create_ex.argtypes = [P(Dims), i32, P(i32), P(i32), P(P(dbl)), i32, i32, vp, P(vp)]
         L.dode_dar_from_speeds.argtypes = [i32, vp, vp, i64, i32, vp, vp, i32, i32, dbl, i32, i32,
                                            i32, vp, vp]
+        L.dode_dar_costs_from_speeds.argtypes = [i32, vp, vp, i64, i32, vp, vp, i32, i32, dbl, i32,
+                                                 i32, i32, vp, vp, vp]
         L.dode_path_costs.argtypes = [i32, vp, vp, i64, i32, vp, vp, i32, i32, dbl, i32, i32, vp, vp]
         L.dar_from_costs.argtypes = [vp, i32, vp, vp, dbl, vp, vp, vp]
         L.dense_spgd_run.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp, i32, i32, i32, dbl, dbl,
@@ -441,6 +443,16 @@ def dode_dar_from_speeds(path_ptr, path_link, link_len, speed, dt, H, K, Rr=None
     int32 [n_paths+1], path_link int32 [n_pairs] (links in traversal order),
     link_len [L], speed [n_days][L][H_speed] (float32 or float64, one dtype).
     Returns Rr [K][H][n_pairs], the day mean of the ratios."""
+    Rr, _ = dode_dar_costs_from_speeds(path_ptr, path_link, link_len, speed, dt, H, K, Rr=Rr,
+                                       with_costs=False, stream=stream)
+    return Rr
+
+
+def dode_dar_costs_from_speeds(path_ptr, path_link, link_len, speed, dt, H, K, Rr=None, cost=None,
+                               with_costs=True, stream=None):
+    """As dode_dar_from_speeds, and (with_costs) the mean path costs of the H
+    departure intervals from the same trajectories.  Returns (Rr [K][H][n_pairs],
+    cost [H][n_paths] or None)."""
     import torch
     if speed.dim() == 2:
         speed = speed.unsqueeze(0)
@@ -450,15 +462,25 @@ def dode_dar_from_speeds(path_ptr, path_link, link_len, speed, dt, H, K, Rr=None
     n_pairs = path_link.numel()
     if Rr is None:
         Rr = torch.empty((K, H, n_pairs), dtype=speed.dtype, device=speed.device)
-    for t in (path_ptr, path_link, link_len, speed, Rr):
+    if with_costs and cost is None:
+        cost = torch.empty((H, n_paths), dtype=speed.dtype, device=speed.device)
+    if not with_costs:
+        cost = None
+    for t in (path_ptr, path_link, link_len, speed, Rr) + ((cost,) if cost is not None else ()):
         if not t.is_contiguous():
             raise ValueError("arrays must be contiguous")
-    if link_len.dtype != speed.dtype or Rr.dtype != speed.dtype:
-        raise ValueError("link_len, speed and Rr must share one dtype")
-    _check(lib().dode_dar_from_speeds(n_paths, path_ptr.data_ptr(), path_link.data_ptr(), n_pairs, L,
-                                      link_len.data_ptr(), speed.data_ptr(), n_days, H_speed,
-                                      float(dt), H, K, int(f64), Rr.data_ptr(), _stream(stream)))
-    return Rr
+    if link_len.dtype != speed.dtype or Rr.dtype != speed.dtype or (
+            cost is not None and cost.dtype != speed.dtype):
+        raise ValueError("link_len, speed, Rr and cost must share one dtype")
+    if tuple(Rr.shape) != (K, H, n_pairs):
+        raise ValueError(f"Rr must be [{K}][{H}][{n_pairs}]")
+    if cost is not None and tuple(cost.shape) != (H, n_paths):
+        raise ValueError(f"cost must be [{H}][{n_paths}]")
+    _check(lib().dode_dar_costs_from_speeds(
+        n_paths, path_ptr.data_ptr(), path_link.data_ptr(), n_pairs, L, link_len.data_ptr(),
+        speed.data_ptr(), n_days, H_speed, float(dt), H, K, int(f64), Rr.data_ptr(),
+        cost.data_ptr() if cost is not None else None, _stream(stream)))
+    return Rr, cost
 
 
 def dode_path_costs(path_ptr, path_link, link_len, speed, dt, T, cost=None, stream=None):

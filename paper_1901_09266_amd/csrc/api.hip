@@ -971,11 +971,11 @@ dode_status check_paths_speeds(int32_t n_paths, const int32_t* path_ptr, const i
 
 }  // namespace
 
-dode_status dode_dar_from_speeds(int32_t n_paths, const int32_t* path_ptr,
-                                 const int32_t* path_link, int64_t n_pairs, int32_t L,
-                                 const void* link_len, const void* speed, int32_t n_days,
-                                 int32_t H_speed, double dt, int32_t H, int32_t K, int32_t f64,
-                                 void* Rr, void* stream) {
+dode_status dode_dar_costs_from_speeds(int32_t n_paths, const int32_t* path_ptr,
+                                       const int32_t* path_link, int64_t n_pairs, int32_t L,
+                                       const void* link_len, const void* speed, int32_t n_days,
+                                       int32_t H_speed, double dt, int32_t H, int32_t K,
+                                       int32_t f64, void* Rr, void* cost, void* stream) {
   if (n_paths < 1 || n_pairs < 0 || L < 1 || n_days < 1 || H_speed < 1 || H < 1)
     return fail(DODE_ERR_SHAPE, "n_paths=%d n_pairs=%lld L=%d n_days=%d H_speed=%d H=%d", n_paths,
                 (long long)n_pairs, L, n_days, H_speed, H);
@@ -987,16 +987,29 @@ dode_status dode_dar_from_speeds(int32_t n_paths, const int32_t* path_ptr,
   if (dode_status st = check_paths_speeds(n_paths, path_ptr, path_link, n_pairs, L, link_len, speed,
                                           n_days, H_speed, f64 != 0, s))
     return st;
-  // trajectory scratch for a chunk of days, at most 1 GiB (at least one day)
+  // trajectory scratch (and path exit times) for a chunk of days, at most
+  // 1 GiB (at least one day)
   const size_t ss = f64 ? 8 : 4;
-  const size_t per_day = (size_t)n_pairs * (H + 1) * ss;
+  const size_t per_day = ((size_t)n_pairs + (cost ? (size_t)n_paths : 0)) * (H + 1) * ss;
   const size_t cap = std::max<size_t>(1, (size_t(1) << 30) / std::max<size_t>(per_day, 1));
   const int32_t chunk = (int32_t)std::min<size_t>((size_t)n_days, cap);
-  DevBuf traj;
+  DevBuf traj, sums;
   HIP_TRY(traj.alloc(std::max<size_t>(per_day * chunk, 16), s));
+  void* exit_time = static_cast<uint8_t*>(traj.p) + (size_t)n_pairs * (H + 1) * ss * chunk;
+  if (cost) HIP_TRY(sums.alloc((size_t)n_paths * H * 8, s));
   HIP_TRY(dar_from_speeds(f64 != 0, n_paths, path_ptr, path_link, n_pairs, L, link_len, speed, n_days,
-                          H_speed, dt, H, K, traj.p, chunk, Rr, s));
+                          H_speed, dt, H, K, traj.p, chunk, Rr, exit_time, sums.as<double>(), cost,
+                          s));
   return DODE_OK;
+}
+
+dode_status dode_dar_from_speeds(int32_t n_paths, const int32_t* path_ptr,
+                                 const int32_t* path_link, int64_t n_pairs, int32_t L,
+                                 const void* link_len, const void* speed, int32_t n_days,
+                                 int32_t H_speed, double dt, int32_t H, int32_t K, int32_t f64,
+                                 void* Rr, void* stream) {
+  return dode_dar_costs_from_speeds(n_paths, path_ptr, path_link, n_pairs, L, link_len, speed,
+                                    n_days, H_speed, dt, H, K, f64, Rr, nullptr, stream);
 }
 
 dode_status dode_path_costs(int32_t n_paths, const int32_t* path_ptr, const int32_t* path_link,

@@ -14,7 +14,9 @@
 //   k_trajectories  one thread per (day, path, boundary b in 0..H): the travel
 //                   time from the b*dt departure to the entry of every link of
 //                   the path, traj[day][pair][b] (pairs = (path, i) in path
-//                   order);
+//                   order), and optionally the whole path's travel time (the
+//                   path cost of eq. "cost" for a departure at b*dt), whose
+//                   day mean k_exit_sums forms;
 //   k_dar_windows   one thread per (pair, departure interval h): the shares
 //                   of the day windows, [r_h, dt + r_{h+1}] relative to h*dt,
 //                   summed over the chunk's days in order, added into the
@@ -55,7 +57,7 @@ __global__ void __launch_bounds__(kBlock)
 k_trajectories(int32_t n_paths, const int32_t* __restrict__ path_ptr,
                const int32_t* __restrict__ path_link, int32_t L, const S* __restrict__ len,
                const S* __restrict__ speed, int32_t day0, int32_t n_days, int32_t H_speed, S dt,
-               int32_t H, int64_t n_pairs, S* __restrict__ traj) {
+               int32_t H, int64_t n_pairs, S* __restrict__ traj, S* __restrict__ exit_time) {
   const int64_t per_day = (int64_t)n_paths * (H + 1);
   const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (idx >= per_day * n_days) return;
@@ -70,6 +72,28 @@ k_trajectories(int32_t n_paths, const int32_t* __restrict__ path_ptr,
     out[(int64_t)m * (H + 1) + b] = r;
     r += link_time(len, sp, H_speed, dt, path_link[m], t0 + r);
   }
+  if (exit_time) exit_time[idx] = r;   // [d][k][b]: the whole path's travel time
+}
+
+// Running FP64 sums of the chunk's path travel times, days in order, for the
+// departures at the interval starts (boundaries b < H); the last chunk writes
+// cost[t][k] = sum / n_days.
+template <typename S>
+__global__ void __launch_bounds__(kBlock)
+k_exit_sums(int32_t n_paths, int32_t H, int32_t n_days_chunk, const S* __restrict__ exit_time,
+            bool first_chunk, bool last_chunk, int32_t n_days_total, double* __restrict__ sums,
+            S* __restrict__ cost) {
+  const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= (int64_t)n_paths * H) return;
+  const int32_t k = (int32_t)(idx / H), t = (int32_t)(idx % H);
+  const int64_t per_day = (int64_t)n_paths * (H + 1);
+  const S* e = exit_time + (int64_t)k * (H + 1) + t;
+  double s = first_chunk ? 0.0 : sums[idx];
+  for (int32_t d = 0; d < n_days_chunk; ++d) s += static_cast<double>(e[d * per_day]);
+  if (last_chunk)
+    cost[(int64_t)t * n_paths + k] = static_cast<S>(s / n_days_total);
+  else
+    sums[idx] = s;
 }
 
 template <typename S, int KMAX>
@@ -195,13 +219,18 @@ unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 template <typename S>
 hipError_t run(int32_t n_paths, const int32_t* path_ptr, const int32_t* path_link, int64_t n_pairs,
                int32_t L, const S* len, const S* speed, int32_t n_days, int32_t H_speed, S dt,
-               int32_t H, int32_t K, S* traj, int32_t chunk, S* Rr, hipStream_t s) {
+               int32_t H, int32_t K, S* traj, int32_t chunk, S* Rr, S* exit_time, double* sums,
+               S* cost, hipStream_t s) {
   for (int32_t d0 = 0; d0 < n_days; d0 += chunk) {
     const int32_t nd = std::min(chunk, n_days - d0);
     const int64_t n1 = (int64_t)nd * n_paths * (H + 1);
     hipLaunchKernelGGL(k_trajectories<S>, dim3(blocks_for(n1)), dim3(kBlock), 0, s, n_paths,
-                       path_ptr, path_link, L, len, speed, d0, nd, H_speed, dt, H, n_pairs, traj);
+                       path_ptr, path_link, L, len, speed, d0, nd, H_speed, dt, H, n_pairs, traj,
+                       cost ? exit_time : nullptr);
     const bool first = d0 == 0, last = d0 + nd >= n_days;
+    if (cost)
+      hipLaunchKernelGGL(k_exit_sums<S>, dim3(blocks_for((int64_t)n_paths * H)), dim3(kBlock), 0, s,
+                         n_paths, H, nd, exit_time, first, last, n_days, sums, cost);
     if (K <= 8)
       hipLaunchKernelGGL((k_dar_windows<S, 8>), dim3(blocks_for(n_pairs * H)), dim3(kBlock), 0, s,
                          n_pairs, nd, H, K, dt, traj, first, last, n_days, Rr);
@@ -257,12 +286,15 @@ hipError_t dar_check_speeds(bool f64, const void* speed, int64_t n, int32_t* fla
 hipError_t dar_from_speeds(bool f64, int32_t n_paths, const int32_t* path_ptr,
                            const int32_t* path_link, int64_t n_pairs, int32_t L, const void* len,
                            const void* speed, int32_t n_days, int32_t H_speed, double dt, int32_t H,
-                           int32_t K, void* traj, int32_t chunk, void* Rr, hipStream_t s) {
+                           int32_t K, void* traj, int32_t chunk, void* Rr, void* exit_time,
+                           double* sums, void* cost, hipStream_t s) {
   if (f64)
     return run<double>(n_paths, path_ptr, path_link, n_pairs, L, static_cast<const double*>(len),
                        static_cast<const double*>(speed), n_days, H_speed, dt, H, K,
-                       static_cast<double*>(traj), chunk, static_cast<double*>(Rr), s);
+                       static_cast<double*>(traj), chunk, static_cast<double*>(Rr),
+                       static_cast<double*>(exit_time), sums, static_cast<double*>(cost), s);
   return run<float>(n_paths, path_ptr, path_link, n_pairs, L, static_cast<const float*>(len),
                     static_cast<const float*>(speed), n_days, H_speed, static_cast<float>(dt), H, K,
-                    static_cast<float*>(traj), chunk, static_cast<float*>(Rr), s);
+                    static_cast<float*>(traj), chunk, static_cast<float*>(Rr),
+                    static_cast<float*>(exit_time), sums, static_cast<float*>(cost), s);
 }

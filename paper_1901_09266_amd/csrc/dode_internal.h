@@ -348,11 +348,14 @@ hipError_t bump_counter(int32_t* c, hipStream_t s);
 constexpr int32_t kMaxDarLags = 16;
 // flag = 1 if any of the n values is not positive and finite
 hipError_t dar_check_speeds(bool f64, const void* speed, int64_t n, int32_t* flag, hipStream_t s);
-// Rr[K][H][n_pairs] = day mean of the ratios; traj = scratch for `chunk` days
+// Rr[K][H][n_pairs] = day mean of the ratios; traj = scratch for `chunk` days.
+// With cost non-null also cost[H][n_paths] = day mean of the path travel times
+// (exit_time = scratch [chunk][n_paths][H+1], sums = FP64 scratch [n_paths][H]).
 hipError_t dar_from_speeds(bool f64, int32_t n_paths, const int32_t* path_ptr,
                            const int32_t* path_link, int64_t n_pairs, int32_t L, const void* len,
                            const void* speed, int32_t n_days, int32_t H_speed, double dt, int32_t H,
-                           int32_t K, void* traj, int32_t chunk, void* Rr, hipStream_t s);
+                           int32_t K, void* traj, int32_t chunk, void* Rr, void* exit_time,
+                           double* sums, void* cost, hipStream_t s);
 // cost[T][n_paths] = day mean of the path travel times for departures at t*dt;
 // partial = FP64 scratch [ceil(n_days/per_slice)][n_paths][T], per_slice % 4 == 0
 hipError_t path_costs(bool f64, int32_t n_paths, const int32_t* path_ptr, const int32_t* path_link,

@@ -135,6 +135,42 @@ def test_speeds_to_assignment_chain_fp64():
         assert np.max(np.abs(W.cpu().numpy() - W_o)) <= 1e-12
 
 
+@pytest.mark.parametrize("f64", [True, False])
+def test_costs_from_ratio_trajectories(f64):
+    """The combined call returns the ratios of dode_dar_from_speeds bit for bit
+    and the path costs of dode_path_costs up to the order of the FP64 day sums."""
+    ci = small(seed=5)
+    t = torch.float64 if f64 else torch.float32
+    pp, pl, ln = dev(ci.path_ptr, torch.int32), dev(ci.path_link, torch.int32), dev(ci.link_len, t)
+    sp = dev(ci.speed, t)
+    say("ratios + costs", f64)
+    Rr2, c2 = dode.dode_dar_costs_from_speeds(pp, pl, ln, sp, ci.dt, ci.H, ci.K)
+    Rr1 = dode.dode_dar_from_speeds(pp, pl, ln, sp, ci.dt, ci.H, ci.K)
+    c1 = dode.dode_path_costs(pp, pl, ln, sp, ci.dt, ci.T)
+    torch.cuda.synchronize()
+    assert torch.equal(Rr1, Rr2)
+    assert rel(c2.cpu().numpy(), c1.cpu().numpy()) <= (1e-12 if f64 else 1e-6)
+    if f64:
+        ref = orc.path_costs(ci.path_ptr, ci.path_link, ci.link_len, ci.speed.astype(np.float64),
+                             ci.dt, ci.T)
+        assert rel(c2.cpu().numpy(), ref) <= 1e-13
+
+
+def test_costs_from_ratio_trajectories_chunks():
+    """160 days of 450 routes need two trajectory chunks (1 GiB): the running
+    FP64 sums across chunks give dode_path_costs' means."""
+    ci = make_choice_instance(sizes=(160,), seed=2300)
+    t = torch.float32
+    pp, pl, ln = dev(ci.path_ptr, torch.int32), dev(ci.path_link, torch.int32), dev(ci.link_len, t)
+    sp = dev(ci.speed, t)
+    say("ratios + costs, 160 days")
+    _, c2 = dode.dode_dar_costs_from_speeds(pp, pl, ln, sp, ci.dt, ci.H, ci.K)
+    c1 = dode.dode_path_costs(pp, pl, ln, sp, ci.dt, ci.T)
+    torch.cuda.synchronize()
+    # same FP32 day travel times on both sides; FP64 sums in another order
+    assert rel(c2.cpu().numpy(), c1.cpu().numpy()) <= 1e-6
+
+
 def test_argument_checks():
     ci = small(seed=4, days=(2,))
     say("choice checks")
