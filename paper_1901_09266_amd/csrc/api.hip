@@ -555,7 +555,8 @@ dode_status dar_create_ex(const dode_dims* dims, int32_t n_clusters, const int32
           if (!std::isfinite(values[c][((int64_t)l * dm.T + t) * nnz + j]))
             return fail(DODE_ERR_NONFINITE, "values[%d] holds NaN or Inf", c);
 
-  std::unique_ptr<dode_dar> d(new dode_dar());
+  // every early return frees what was allocated so far
+  std::unique_ptr<dode_dar, dode_status (*)(dode_dar*)> d(new dode_dar(), dar_destroy);
   d->dims = dm;
   d->C = n_clusters;
   d->nnz = nnz;
@@ -903,7 +904,8 @@ dode_status dode_routes_create(const dode_dims* dims, int64_t nnz, int32_t n_pat
   put(od_paths.data(), n_paths);
   put(nz_ptr.data(), nz_ptr.size());
   put(nz_pairs.data(), n_pairs);
-  std::unique_ptr<dode_routes> r(new dode_routes());
+  std::unique_ptr<dode_routes, dode_status (*)(dode_routes*)> r(new dode_routes(),
+                                                                 dode_routes_destroy);
   HIP_TRY(hipGetDevice(&r->device));
   HIP_TRY(hipMalloc(&r->d_buf, buf.size() * 4));
   HIP_TRY(hipMemcpy(r->d_buf, buf.data(), buf.size() * 4, hipMemcpyHostToDevice));
