@@ -231,7 +231,11 @@ hipError_t run(int32_t n_paths, const int32_t* path_ptr, const int32_t* path_lin
     if (cost)
       hipLaunchKernelGGL(k_exit_sums<S>, dim3(blocks_for((int64_t)n_paths * H)), dim3(kBlock), 0, s,
                          n_paths, H, nd, exit_time, first, last, n_days, sums, cost);
-    if (K <= 8)
+    // the window loop is unrolled to KMAX lags: the common K = 6 gets its own
+    if (K <= 6)
+      hipLaunchKernelGGL((k_dar_windows<S, 6>), dim3(blocks_for(n_pairs * H)), dim3(kBlock), 0, s,
+                         n_pairs, nd, H, K, dt, traj, first, last, n_days, Rr);
+    else if (K <= 8)
       hipLaunchKernelGGL((k_dar_windows<S, 8>), dim3(blocks_for(n_pairs * H)), dim3(kBlock), 0, s,
                          n_pairs, nd, H, K, dt, traj, first, last, n_days, Rr);
     else
