@@ -42,6 +42,18 @@ def test_matches_oracle_ragged_paths(f64):
             assert np.max(np.abs(got - Ro)) <= 1e-4
 
 
+@pytest.mark.parametrize("K", [3, 7, 8, 12, 16])
+def test_lag_counts_fp64(K):
+    """Every unrolled window instance (up to 6, 8 and 16 lags) against the oracle."""
+    si = make_speed_instance(L=80, P=12, H=40, sizes=(3,), inc=0.15, seed=15)
+    say("dar lags", K)
+    R = run(si, K, si.dt, si.speed, True)
+    torch.cuda.synchronize()
+    Ro = orc.dar_from_speeds(si.path_ptr, si.path_link, si.link_len, si.speed.astype(np.float64),
+                             si.dt, si.H, K)
+    assert np.max(np.abs(R.cpu().numpy() - Ro)) <= 1e-12
+
+
 def test_several_day_chunks_fp32():
     """160 days of a 500-link corridor need two trajectory chunks (1 GiB, 154
     days each); the chunked day mean must equal the oracle's."""
