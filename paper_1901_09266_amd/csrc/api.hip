@@ -461,11 +461,13 @@ void dode_spgd_defaults(dode_spgd_params* p) {
 namespace {
 
 // Sliced layout of n lines whose entries are ptr[i] .. ptr[i+1]-1: slice g
-// holds lines 64g .. 64g+63 and is 64 * (its largest degree) slots long.
-// With `ranked`, the lines of a slice take its lanes in order of decreasing
-// degree (ties by index), else line i takes lane i%64.  Entry k of line i goes
-// to first[i] + 64k.  Returns the slots per block.
-int64_t build_slices(int32_t n, const std::vector<int32_t>& ptr, bool ranked,
+// holds lines 64g .. 64g+63.  With `ranked`, the lines of a slice take its
+// lanes in order of decreasing degree (ties by index), else line i takes lane
+// i%64.  Unpaired, entry k of the line in lane r sits at off + 64k + r; paired,
+// entries come two by two, entry k at off + 128(k/2) + 2r + k%2, so a lane
+// reads two neighbouring entries with one load.  A slice is as long as its
+// longest line (rounded up to even when paired).  Returns the slots per block.
+int64_t build_slices(int32_t n, const std::vector<int32_t>& ptr, bool ranked, bool paired,
                      std::vector<int32_t>& off, std::vector<int32_t>& first,
                      std::vector<int32_t>& pos) {
   const int32_t ng = (n + 63) / 64;
@@ -486,11 +488,13 @@ int64_t build_slices(int32_t n, const std::vector<int32_t>& ptr, bool ranked,
         return ptr[x + 1] - ptr[x] > ptr[y + 1] - ptr[y];
       });
     off[g] = (int32_t)len;
-    for (size_t lane = 0; lane < lines.size(); ++lane) first[lines[lane]] = (int32_t)(len + lane);
-    len += 64 * (int64_t)width;
+    for (size_t lane = 0; lane < lines.size(); ++lane)
+      first[lines[lane]] = (int32_t)(len + (paired ? 2 : 1) * lane);
+    len += 64 * (int64_t)(paired ? (width + 1) / 2 * 2 : width);
   }
   for (int32_t i = 0; i < n; ++i)
-    for (int32_t k = 0; k < ptr[i + 1] - ptr[i]; ++k) pos[ptr[i] + k] = first[i] + 64 * k;
+    for (int32_t k = 0; k < ptr[i + 1] - ptr[i]; ++k)
+      pos[ptr[i] + k] = paired ? first[i] + 128 * (k >> 1) + (k & 1) : first[i] + 64 * k;
   return len;
 }
 
@@ -598,11 +602,11 @@ dode_status dar_create_ex(const dode_dims* dims, int32_t n_clusters, const int32
       for (int32_t j = row_ptr[a]; j < row_ptr[a + 1]; ++j) rows[j] = a;
     HIP_TRY(dev_copy(&d->d_row_of_nz, rows));
   }
-  // sliced value layouts: W by link (ranked by degree), WT by OD; each line's
-  // entries keep their CSR / CSC order
+  // sliced value layouts: W by link (ranked by degree, entries in pairs), WT
+  // by OD; each line's entries keep their CSR / CSC order
   std::vector<int32_t> sr_off, sr_first, sr_pos, sc_off, sc_first, sc_pos;
-  d->sr_len = build_slices(dm.L, d->h_row_ptr, true, sr_off, sr_first, sr_pos);
-  d->sc_len = build_slices(dm.P, d->h_col_ptr, false, sc_off, sc_first, sc_pos);
+  d->sr_len = build_slices(dm.L, d->h_row_ptr, true, true, sr_off, sr_first, sr_pos);
+  d->sc_len = build_slices(dm.P, d->h_col_ptr, false, false, sc_off, sc_first, sc_pos);
   if (d->sr_len > INT32_MAX || d->sc_len > INT32_MAX) {
     dar_destroy(d.release());
     return fail(DODE_ERR_SHAPE, "pattern too large for the sliced layout");

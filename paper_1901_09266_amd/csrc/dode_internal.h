@@ -11,12 +11,13 @@
 
 // Device view of the incidence pattern (CSR by link and CSC by OD), and the
 // sliced layouts of the two value copies.  Lines (links for W, ODs for WT)
-// come in slices of 64; entry k of a line sits 64*k after the line's first
+// come in slices of 64; in WT entry k of a column sits 64*k after its first
 // slot, so the 64 lanes that walk 64 neighbouring lines read one run of
-// neighbouring values at every step.  In W a slice's links are ranked by
-// degree (longest first; link degrees vary along a corridor), so the lanes
-// still active at step k hold a prefix of the run and no padding is fetched.
-// Slots past a line's degree are padding (zero, never read).
+// neighbouring values at every step.  In W entries come in pairs (entry k of a
+// link at first + 128*(k/2) + k%2, first even), so one load brings two, and a
+// slice's links are ranked by degree (longest first; link degrees vary along a
+// corridor): the lanes still active at a step hold a prefix of the run and no
+// padding is fetched.  Slots past a line's degree are padding (zero).
 struct DevPat {
   int32_t P, L, T, H, K;
   int64_t nnz;

@@ -57,6 +57,46 @@ struct Load<DODE_FP8_E4M3> {
   }
 };
 
+// Two neighbouring values i, i+1 (i even) with one load.
+template <int ST>
+struct Load2;
+template <>
+struct Load2<DODE_F64> {
+  __device__ static void get(const void* W, int64_t i, const float*, int64_t, int64_t, double& w0,
+                             double& w1) {
+    const double2 v = *reinterpret_cast<const double2*>(static_cast<const double*>(W) + i);
+    w0 = v.x;
+    w1 = v.y;
+  }
+};
+template <>
+struct Load2<DODE_F32> {
+  __device__ static void get(const void* W, int64_t i, const float*, int64_t, int64_t, float& w0,
+                             float& w1) {
+    const float2 v = *reinterpret_cast<const float2*>(static_cast<const float*>(W) + i);
+    w0 = v.x;
+    w1 = v.y;
+  }
+};
+template <>
+struct Load2<DODE_BF16> {
+  __device__ static void get(const void* W, int64_t i, const float*, int64_t, int64_t, float& w0,
+                             float& w1) {
+    const uint32_t b = *reinterpret_cast<const uint32_t*>(static_cast<const uint16_t*>(W) + i);
+    w0 = bf16_bits_to_f32(static_cast<uint16_t>(b & 0xFFFFu));
+    w1 = bf16_bits_to_f32(static_cast<uint16_t>(b >> 16));
+  }
+};
+template <>
+struct Load2<DODE_FP8_E4M3> {
+  __device__ static void get(const void* W, int64_t i, const float* scale, int64_t si0, int64_t si1,
+                             float& w0, float& w1) {
+    const uint16_t b = *reinterpret_cast<const uint16_t*>(static_cast<const uint8_t*>(W) + i);
+    w0 = e4m3_bits_to_f32(static_cast<uint8_t>(b & 0xFFu)) * scale[si0];
+    w1 = e4m3_bits_to_f32(static_cast<uint8_t>(b >> 8)) * scale[si1];
+  }
+};
+
 __device__ __forceinline__ int day_cl(const int32_t* day_cluster, int32_t cluster, int d) {
   return day_cluster ? day_cluster[d] : cluster;
 }
@@ -83,8 +123,9 @@ __device__ double block_max(double v, double* sh) {
 }
 
 // Row (h, a) of rho_c applied to q_d:  sum_l sum_{p in row a} W[l][h-l][a,p] q[h-l][p].
-// The row's entries are taken in CSR order from the link-sliced layout, four
-// steps' loads issued together (the sums keep their order).
+// The row's entries are taken in CSR order from the link-sliced layout, where
+// they come in pairs: one load brings two values (and one their two ODs), and
+// the loads of four entries are issued together (the sums keep their order).
 template <int ST, typename S>
 __device__ __forceinline__ S row_dot(const DevPat& pt, const DevVals& v, int c, int h, int a,
                                      const S* q, int64_t q_t, int64_t q_b) {
@@ -100,18 +141,31 @@ __device__ __forceinline__ S row_dot(const DevPat& pt, const DevVals& v, int c, 
     const S* qt = q + (int64_t)t * q_t;
     int32_t k = 0;
     for (; k + 4 <= deg; k += 4) {
-      S w[4], x[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int32_t slot = s0 + 64 * (k + u);
-        const int p = pt.sr_col[slot];
-        w[u] = static_cast<S>(Load<ST>::get(v.W, base + slot, v.scale, sbase + (p >> 6)));
-        x[u] = qt[col_at(p, q_b)];
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) acc += w[u] * x[u];
+      const int32_t slot = s0 + 64 * k;   // entries k, k+1; k+2, k+3 one pair further
+      const int2 p01 = *reinterpret_cast<const int2*>(pt.sr_col + slot);
+      const int2 p23 = *reinterpret_cast<const int2*>(pt.sr_col + slot + 128);
+      S w0, w1, w2, w3;
+      Load2<ST>::get(v.W, base + slot, v.scale, sbase + (p01.x >> 6), sbase + (p01.y >> 6), w0, w1);
+      Load2<ST>::get(v.W, base + slot + 128, v.scale, sbase + (p23.x >> 6), sbase + (p23.y >> 6), w2,
+                     w3);
+      const S x0 = qt[col_at(p01.x, q_b)], x1 = qt[col_at(p01.y, q_b)];
+      const S x2 = qt[col_at(p23.x, q_b)], x3 = qt[col_at(p23.y, q_b)];
+      acc += w0 * x0;
+      acc += w1 * x1;
+      acc += w2 * x2;
+      acc += w3 * x3;
     }
-    for (; k < deg; ++k) {
+    if (k + 2 <= deg) {
+      const int32_t slot = s0 + 64 * k;
+      const int2 p01 = *reinterpret_cast<const int2*>(pt.sr_col + slot);
+      S w0, w1;
+      Load2<ST>::get(v.W, base + slot, v.scale, sbase + (p01.x >> 6), sbase + (p01.y >> 6), w0, w1);
+      const S x0 = qt[col_at(p01.x, q_b)], x1 = qt[col_at(p01.y, q_b)];
+      acc += w0 * x0;
+      acc += w1 * x1;
+      k += 2;
+    }
+    if (k < deg) {
       const int32_t slot = s0 + 64 * k;
       const int p = pt.sr_col[slot];
       acc += static_cast<S>(Load<ST>::get(v.W, base + slot, v.scale, sbase + (p >> 6))) *
