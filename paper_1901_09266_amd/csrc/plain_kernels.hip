@@ -16,6 +16,7 @@ namespace {
 constexpr int kRowsBlock = 256;
 constexpr int kColsBlock = 64;
 constexpr int kRedBlock = 256;
+constexpr size_t kQStageBytes = 32768;   // demand rows staged in LDS by the forward
 
 // ---------------------------------------------------------------- values --
 __device__ __forceinline__ float bf16_bits_to_f32(uint16_t b) {
@@ -215,18 +216,36 @@ __device__ __forceinline__ S col_dot_chunk(const DevPat& pt, const DevVals& v, i
 }
 
 // ------------------------------------------------------------- kernels --
-template <int ST, typename S>
+// With STAGE the block first copies the K demand rows its links read,
+// Q_d[h-l] for l < K, into LDS (row l at l*P; rows outside the day are
+// zeros that no lane reads), so the walk's demand gathers are LDS reads.
+template <int ST, typename S, bool STAGE>
 __global__ void __launch_bounds__(kRowsBlock)
 k_chunk_resid(DevPat pt, DevVals v, const int32_t* day_cluster, int32_t cluster, ChunkSched cs,
               Layout ly, const S* __restrict__ Q, const S* __restrict__ X, S* __restrict__ R) {
+  extern __shared__ unsigned char q_stage[];
   const int a = blockIdx.x * kRowsBlock + threadIdx.x;
   const int s = blockIdx.y, d = blockIdx.z;
-  if (a >= pt.L) return;
   cs = resolve_epoch(cs);
   const int c = day_cl(day_cluster, cluster, d);
-  if (cs.j0 + s >= pt.H) return;
+  if (cs.j0 + s >= pt.H) return;   // the whole block
   const int h = cs.perm[c * pt.H + cs.j0 + s];
-  const S xhat = row_dot<ST, S>(pt, v, c, h, a, Q + d * ly.q_d, ly.q_t, ly.q_b);
+  S xhat;
+  if constexpr (STAGE) {
+    S* qs = reinterpret_cast<S*>(q_stage);
+    const S* qd = Q + d * ly.q_d;
+    for (int i = threadIdx.x; i < pt.K * pt.P; i += kRowsBlock) {
+      const int l = i / pt.P, p = i % pt.P, t = h - l;
+      qs[i] = (t >= 0 && t < pt.T) ? qd[(int64_t)t * ly.q_t + col_at(p, ly.q_b)] : S(0);
+    }
+    __syncthreads();
+    if (a >= pt.L) return;
+    // row t = h - l of the staged copy sits at (h - t) * P: base h*P, stride -P
+    xhat = row_dot<ST, S>(pt, v, c, h, a, qs + (int64_t)h * pt.P, -(int64_t)pt.P, 4);
+  } else {
+    if (a >= pt.L) return;
+    xhat = row_dot<ST, S>(pt, v, c, h, a, Q + d * ly.q_d, ly.q_t, ly.q_b);
+  }
   R[d * ly.r_d + s * ly.r_s + col_at(a, ly.r_b)] = xhat - X[d * ly.x_d + h * ly.x_h + col_at(a, ly.x_b)];
 }
 
@@ -427,9 +446,15 @@ struct RunResid {
                         const Layout& ly, const void* Q, const void* X, void* R, int32_t n,
                         hipStream_t s) {
     dim3 grid((dar->dims.L + kRowsBlock - 1) / kRowsBlock, cs.bh, n);
-    hipLaunchKernelGGL((k_chunk_resid<ST, S>), grid, dim3(kRowsBlock), 0, s, dar->pat(), dar->vals(),
-                       dc, cl, cs, ly, static_cast<const S*>(Q), static_cast<const S*>(X),
-                       static_cast<S*>(R));
+    const size_t stage = (size_t)dar->dims.K * dar->dims.P * sizeof(S);
+    if (stage <= kQStageBytes)
+      hipLaunchKernelGGL((k_chunk_resid<ST, S, true>), grid, dim3(kRowsBlock), stage, s, dar->pat(),
+                         dar->vals(), dc, cl, cs, ly, static_cast<const S*>(Q),
+                         static_cast<const S*>(X), static_cast<S*>(R));
+    else
+      hipLaunchKernelGGL((k_chunk_resid<ST, S, false>), grid, dim3(kRowsBlock), 0, s, dar->pat(),
+                         dar->vals(), dc, cl, cs, ly, static_cast<const S*>(Q),
+                         static_cast<const S*>(X), static_cast<S*>(R));
     return hipGetLastError();
   }
 };
