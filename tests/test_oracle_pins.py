@@ -411,3 +411,19 @@ def test_route_and_rho_gradients_by_finite_differences():
         zm[k] -= h
         fd = (total(orc.rho_from_logits(ri, 0, zp), Q) - total(orc.rho_from_logits(ri, 0, zm), Q)) / (2 * h)
         assert abs(fd - dz[k]) <= 1e-5 * (1 + abs(fd))
+
+
+def test_oracle_resume_is_bitwise():
+    """Stopping the oracle after E1 epochs and continuing from its (Q, A) with
+    the remaining epochs' permutations gives the uninterrupted run bit for bit."""
+    from synth import make_instance, make_perms, chunk_h_blocks
+    inst = make_instance(P=6, L=10, T=16, K=3, sizes=(3, 2), inc=0.4, pattern="bernoulli",
+                         demand="uniform50", noise="add1", x_dtype="f64", seed=71)
+    E, E1 = 9, 4
+    perms = make_perms(72, E, inst.C, inst.H)
+    bh = chunk_h_blocks(inst.L, inst.H, 25)
+    Qa, Aa, _ = orc.spgd(inst, inst.x, perms, E, bh, optimizer=0, eta=2.0)
+    Q1, A1, _ = orc.spgd(inst, inst.x, perms[:E1], E1, bh, optimizer=0, eta=2.0)
+    Qb, Ab, _ = orc.spgd(inst, inst.x, perms[E1:], E - E1, bh, optimizer=0, eta=2.0, q0=Q1, A0=A1)
+    np.testing.assert_array_equal(Qa, Qb)
+    np.testing.assert_array_equal(Aa, Ab)
