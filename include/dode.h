@@ -80,7 +80,9 @@ typedef struct {
   int32_t optimizer;   /* 0 = Adagrad (Algorithm 1), 1 = fixed step q -= eta g */
   int32_t check_finite;/* nonzero: scan X for NaN/Inf before solving */
   int32_t kernel_path; /* 0 = fastest available for the storage type (matrix-core
-                          tiles for BF16 / FP8), 1 = sparse pattern kernels */
+                          tiles for BF16 / FP8 when a cluster has more than 2
+                          days or refine_steps > 0, else the sparse kernels),
+                          1 = sparse pattern kernels */
   int32_t use_graph;   /* nonzero: spgd_run replays one captured hipGraph per epoch
                           (the epoch index lives in a device counter) */
   int32_t day_tile;    /* days of one cluster handled together by a matrix-core
