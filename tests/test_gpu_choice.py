@@ -171,6 +171,23 @@ def test_costs_from_ratio_trajectories_chunks():
     assert rel(c2.cpu().numpy(), c1.cpu().numpy()) <= 1e-6
 
 
+def test_theta_zero_gives_equal_portions():
+    """theta = 0: every route of an OD gets 1 / (its number of routes), whatever
+    the costs (eq. "logit"); single-route ODs get 1."""
+    ci = small(seed=6)
+    t = torch.float64
+    rng = np.random.default_rng(6)
+    cost = dev(rng.uniform(5, 25, size=(ci.T, ci.n_paths)), t)
+    Rr = dev(rng.uniform(0, 1, size=(ci.K, ci.T, ci.n_pairs)), t)
+    W = torch.empty((ci.K, ci.T, ci.nnz), dtype=t, device="cuda")
+    p = torch.empty((ci.T, ci.n_paths), dtype=t, device="cuda")
+    say("theta 0")
+    dode.dar_from_costs(routes(ci), Rr, cost, 0.0, W, portions=p)
+    torch.cuda.synchronize()
+    n_routes = np.bincount(ci.path_od, minlength=ci.P)[ci.path_od]
+    np.testing.assert_array_equal(p.cpu().numpy(), np.broadcast_to(1.0 / n_routes, (ci.T, ci.n_paths)))
+
+
 def test_argument_checks():
     ci = small(seed=4, days=(2,))
     say("choice checks")

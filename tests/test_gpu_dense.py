@@ -27,7 +27,8 @@ def run(B, y, perms, chunk, eta, f64, optimizer=0, loss=True, q0=None):
 
 
 @pytest.mark.parametrize("f64", [True, False])
-@pytest.mark.parametrize("m,n,chunk", [(100, 64, 100), (173, 61, 40), (300, 257, 77), (50, 7, 8)])
+@pytest.mark.parametrize("m,n,chunk", [(100, 64, 100), (173, 61, 40), (300, 257, 77), (50, 7, 8),
+                                        (1, 1, 1), (3, 1, 2), (1, 5, 4), (260, 12, 300)])
 def test_matches_oracle(f64, m, n, chunk):
     B, y, _, perms = make_dense_instance(n, m=m, epochs=4, seed=31)
     y = y - 0.3 * y.mean()          # active bounds

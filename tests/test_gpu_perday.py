@@ -67,3 +67,27 @@ def test_per_day_plan_matches_solve(storage):
     dode.spgd_plan_store(plan, Q2, A2, stream=0)
     torch.cuda.synchronize()
     assert torch.equal(Q1, Q2) and torch.equal(A1, A2)
+
+
+@pytest.mark.parametrize("storage", ["bf16", "fp8"])
+def test_fastest_path_for_one_day_clusters(storage):
+    """kernel_path 0 takes the sparse kernels when no cluster has more than 2
+    days: the plan reports no day tile and gives kernel_path 1's bits."""
+    inst = per_day_instance(seed=94)
+    say("path choice", storage)
+    E = 5
+    perms = make_perms(95, E, inst.C, inst.H)
+    dar = make_dar(inst, storage)
+    X = dev(inst.x, torch.float32)
+    outs = []
+    for path in (0, 1):
+        p = dode.make_params(epochs=E, batch_rows=7 * inst.L, eta=5.0, kernel_path=path)
+        plan = dode.spgd_plan_create(dar, inst.day_cluster, p, perm=perms, stream=0)
+        assert dode.spgd_plan_info(plan)["day_tile"] == 0
+        Q = torch.zeros((inst.D, inst.T, inst.P), dtype=torch.float32, device="cuda")
+        dode.spgd_plan_load(plan, X, Q)
+        dode.spgd_run(plan, 0, E)
+        dode.spgd_plan_store(plan, Q)
+        torch.cuda.synchronize()
+        outs.append(Q.cpu().numpy())
+    np.testing.assert_array_equal(outs[0], outs[1])
