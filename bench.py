@@ -531,6 +531,9 @@ def main():
                     help="measure the route-choice assignment from link speeds instead")
     ap.add_argument("--dense", action="store_true",
                     help="measure Algorithm 1 on the dense random NNLS of the efficiency experiment")
+    ap.add_argument("--pattern", default=None, choices=["corridor", "bernoulli"],
+                    help="incidence pattern (default: the configuration's own, corridor for 2/3/5); "
+                         "bernoulli = every (link, OD) pair independently, the stress case")
     ap.add_argument("--per-day", action="store_true",
                     help="give every day its own ratio matrix (one cluster per day)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -568,7 +571,7 @@ def main():
         # one ratio matrix per day: every day is its own cluster
         from synth.instances import CONFIGS
         per_day = (1,) * int(sum(CONFIGS[args.config]["sizes"]))
-    inst = make_config(args.config, sizes=per_day,
+    inst = make_config(args.config, sizes=per_day, pattern=args.pattern,
                        progress=lambda m: log(f"generating: {m} ({time.time() - t0:.0f}s)"))
     log(f"config {args.config}: D={inst.D} C={inst.C} nnz={inst.nnz} generated in {time.time() - t0:.1f}s")
     bh = chunk_h_blocks(inst.L, inst.H, 8192)
@@ -598,7 +601,8 @@ def main():
     k = int(np.argmax(kms[:2]))
     byts = head["fwd_bytes"] if k == 0 else head["adj_bytes"]
     achieved = byts / (kms[k] / 1e3) / 1e9
-    traffic = None if args.per_day else counted_traffic(args.config, args.form, ("fwd", "adj")[k])
+    traffic = None if (args.per_day or args.pattern == "bernoulli") else counted_traffic(
+        args.config, args.form, ("fwd", "adj")[k])
     roof = {"bound": "hbm", "kernel": names[k], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": round(traffic) if traffic is not None else None,
@@ -613,7 +617,9 @@ def main():
                      "bf16-sparse": "f32"}[args.form],
            "data": "synthetic",
            "config": {"workload": f"config {args.config}: " + WORKLOADS[args.config] +
-                                  (", one ratio matrix per day (per-day DAR)" if args.per_day else ""),
+                                  (", one ratio matrix per day (per-day DAR)" if args.per_day else "") +
+                                  (", Bernoulli incidence instead (stress case)"
+                                   if args.pattern == "bernoulli" else ""),
                       "form": FORMS[args.form],
                       "global_batch": inst.D, "seq_len": inst.H, "parallelism": "none (1 GPU)",
                       "epochs_per_step": 1, "batch_rows": 8192, "minibatch_intervals": bh,
