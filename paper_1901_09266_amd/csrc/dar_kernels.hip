@@ -11,7 +11,7 @@
 // observation interval h2 is the share of the window inside it.
 //
 // Two kernels per chunk of days:
-//   k_trajectories  one thread per (day, path, boundary b in 0..H): the travel
+//   k_trajectories  one thread per (four days, path, boundary b in 0..H): the travel
 //                   time from the b*dt departure to the entry of every link of
 //                   the path, traj[day][pair][b] (pairs = (path, i) in path
 //                   order), and optionally the whole path's travel time (the
@@ -52,27 +52,52 @@ __device__ __forceinline__ S link_time(const S* __restrict__ len, const S* __res
   return len[a] / speed_day[(int64_t)a * H_speed + h];
 }
 
+// One thread per (group of four days, path, boundary b), b fastest: the four
+// days' trajectories are walked together, so four independent chains of
+// speed gathers are in flight (days past the chunk repeat its last day and
+// are not stored).
 template <typename S>
 __global__ void __launch_bounds__(kBlock)
 k_trajectories(int32_t n_paths, const int32_t* __restrict__ path_ptr,
                const int32_t* __restrict__ path_link, int32_t L, const S* __restrict__ len,
                const S* __restrict__ speed, int32_t day0, int32_t n_days, int32_t H_speed, S dt,
                int32_t H, int64_t n_pairs, S* __restrict__ traj, S* __restrict__ exit_time) {
-  const int64_t per_day = (int64_t)n_paths * (H + 1);
+  constexpr int kDays = 4;
+  const int64_t per_group = (int64_t)n_paths * (H + 1);
   const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (idx >= per_day * n_days) return;
-  const int32_t d = (int32_t)(idx / per_day);
-  const int32_t k = (int32_t)((idx % per_day) / (H + 1));
-  const int32_t b = (int32_t)(idx % (H + 1));
-  const S* sp = speed + (int64_t)(day0 + d) * L * H_speed;
-  S* out = traj + (int64_t)d * n_pairs * (H + 1);
-  const S t0 = static_cast<S>(b) * dt;
-  S r = 0;   // travel time so far
-  for (int32_t m = path_ptr[k]; m < path_ptr[k + 1]; ++m) {
-    out[(int64_t)m * (H + 1) + b] = r;
-    r += link_time(len, sp, H_speed, dt, path_link[m], t0 + r);
+  const int32_t n_groups = (n_days + kDays - 1) / kDays;
+  if (idx >= per_group * n_groups) return;
+  const int32_t dg = (int32_t)(idx / per_group);
+  const int64_t kb = idx % per_group;   // k * (H+1) + b
+  const int32_t k = (int32_t)(kb / (H + 1));
+  const int32_t b = (int32_t)(kb % (H + 1));
+  const int64_t day_stride = (int64_t)L * H_speed, traj_stride = n_pairs * (H + 1);
+  const S* sp[kDays];
+  S* out[kDays];
+  bool on[kDays];
+#pragma unroll
+  for (int u = 0; u < kDays; ++u) {
+    const int32_t d = min(dg * kDays + u, n_days - 1);
+    on[u] = dg * kDays + u < n_days;
+    sp[u] = speed + (int64_t)(day0 + d) * day_stride;
+    out[u] = traj + (int64_t)d * traj_stride;
   }
-  if (exit_time) exit_time[idx] = r;   // [d][k][b]: the whole path's travel time
+  const S t0 = static_cast<S>(b) * dt;
+  S r[kDays];   // travel time so far
+#pragma unroll
+  for (int u = 0; u < kDays; ++u) r[u] = S(0);
+  for (int32_t m = path_ptr[k]; m < path_ptr[k + 1]; ++m) {
+    const int32_t a = path_link[m];
+#pragma unroll
+    for (int u = 0; u < kDays; ++u) {
+      if (on[u]) out[u][(int64_t)m * (H + 1) + b] = r[u];
+      r[u] += link_time(len, sp[u], H_speed, dt, a, t0 + r[u]);
+    }
+  }
+  if (exit_time)   // [d][k][b]: the whole path's travel time
+#pragma unroll
+    for (int u = 0; u < kDays; ++u)
+      if (on[u]) exit_time[(int64_t)(dg * kDays + u) * per_group + kb] = r[u];
 }
 
 // Running FP64 sums of the chunk's path travel times, days in order, for the
@@ -223,7 +248,7 @@ hipError_t run(int32_t n_paths, const int32_t* path_ptr, const int32_t* path_lin
                S* cost, hipStream_t s) {
   for (int32_t d0 = 0; d0 < n_days; d0 += chunk) {
     const int32_t nd = std::min(chunk, n_days - d0);
-    const int64_t n1 = (int64_t)nd * n_paths * (H + 1);
+    const int64_t n1 = (int64_t)((nd + 3) / 4) * n_paths * (H + 1);   // four days per thread
     hipLaunchKernelGGL(k_trajectories<S>, dim3(blocks_for(n1)), dim3(kBlock), 0, s, n_paths,
                        path_ptr, path_link, L, len, speed, d0, nd, H_speed, dt, H, n_pairs, traj,
                        cost ? exit_time : nullptr);
