@@ -429,7 +429,8 @@ def dense_bench(args):
     """The efficiency experiment (section "Algorithm efficiency"): random dense
     NNLS B x = y with B [n][n] U(0,1), x* U(0,1), n = 100 ... 6000, solved by
     Algorithm 1 with minibatches of 8192 rows (one per epoch at these sizes)
-    and Adagrad, in FP32.  Per n: seconds per epoch on the GPU (the slope
+    and Adagrad, in FP32 (and again with B stored as bfloat16, FP32
+    arithmetic: half the bytes per epoch).  Per n: seconds per epoch on the GPU (the slope
     between E and 2E epochs in one call, so fixed costs drop out), the loss
     after 2E epochs and the epochs to a relative loss of 1e-3, the FP64
     oracle's seconds per epoch on one host core, and
@@ -443,39 +444,50 @@ def dense_bench(args):
     cpu = {}
     for n in sizes:
         B, y, _, perms = make_dense_instance(n, epochs=2 * E)
-        Bd = torch.as_tensor(B.astype(np.float32)).cuda()
         yd = torch.as_tensor(y.astype(np.float32)).cuda()
         pd = torch.as_tensor(perms).cuda()
         eta = 0.2
-        times = []
-        for ne in (E, 2 * E):
-            q = torch.zeros(n, dtype=torch.float32, device="cuda")
-            A = torch.zeros(n, dtype=torch.float32, device="cuda")
-            dode.dense_spgd_run(Bd, yd, q, A, pd[:args.warmup].contiguous(), 8192, eta)
+
+        def timed(Bd):
+            times = []
+            for ne in (E, 2 * E):
+                q = torch.zeros(n, dtype=torch.float32, device="cuda")
+                A = torch.zeros(n, dtype=torch.float32, device="cuda")
+                dode.dense_spgd_run(Bd, yd, q, A, pd[:args.warmup].contiguous(), 8192, eta)
+                q.zero_()
+                A.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                dode.dense_spgd_run(Bd, yd, q, A, pd[:ne].contiguous(), 8192, eta)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+            per_epoch = (times[1] - times[0]) / E
+            loss = float(np.sum((B @ q.double().cpu().numpy() - y) ** 2))
+            # epochs to a relative loss of 1e-3 (a second run with the loss history)
             q.zero_()
             A.zero_()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            dode.dense_spgd_run(Bd, yd, q, A, pd[:ne].contiguous(), 8192, eta)
-            torch.cuda.synchronize()
-            times.append(time.perf_counter() - t0)
-        per_epoch = (times[1] - times[0]) / E
-        qn = q.double().cpu().numpy()
-        loss = float(np.sum((B @ qn - y) ** 2))
-        # epochs to a relative loss of 1e-3 (a second run with the loss history)
-        q.zero_()
-        A.zero_()
-        hist = dode.dense_spgd_run(Bd, yd, q, A, pd[:2 * E].contiguous(), 8192, eta, loss_hist=True)
-        hit = np.nonzero(hist / float(y @ y) <= 1e-3)[0]
-        to_1e3 = int(hit[0]) + 1 if hit.size else None
+            hist = dode.dense_spgd_run(Bd, yd, q, A, pd[:2 * E].contiguous(), 8192, eta,
+                                       loss_hist=True)
+            hit = np.nonzero(hist / float(y @ y) <= 1e-3)[0]
+            return per_epoch, times[1], loss, (int(hit[0]) + 1 if hit.size else None)
+
+        Bd = torch.as_tensor(B.astype(np.float32)).cuda()
+        per_epoch, total, loss, to_1e3 = timed(Bd)
         byts = 2 * n * n * 4          # B streamed twice per epoch (residual, column sums)
+        Bd = Bd.to(torch.bfloat16)
+        pe16, _, loss16, to16 = timed(Bd)
         rows.append({"n": n, "s_per_epoch_gpu": per_epoch, "epochs": 2 * E,
-                     "gpu_s_total": times[1], "rel_loss": loss / float(y @ y),
+                     "gpu_s_total": total, "rel_loss": loss / float(y @ y),
                      "epochs_to_rel_loss_1e-3": to_1e3,
                      "gpu_s_to_rel_loss_1e-3": None if to_1e3 is None else to_1e3 * per_epoch,
-                     "achieved_GBps": byts / per_epoch / 1e9})
+                     "achieved_GBps": byts / per_epoch / 1e9,
+                     "bf16_matrix": {"s_per_epoch_gpu": pe16, "rel_loss": loss16 / float(y @ y),
+                                     "epochs_to_rel_loss_1e-3": to16,
+                                     "achieved_GBps": byts / 2 / pe16 / 1e9}})
         log(f"dense n={n}: {per_epoch * 1e6:.1f} us/epoch, {byts / per_epoch / 1e9:.0f} GB/s, "
-            f"rel loss {loss / float(y @ y):.3e} after {2 * E} epochs")
+            f"rel loss {loss / float(y @ y):.3e} after {2 * E} epochs; bf16 B "
+            f"{pe16 * 1e6:.1f} us/epoch, {byts / 2 / pe16 / 1e9:.0f} GB/s, rel loss "
+            f"{loss16 / float(y @ y):.3e}")
         if not args.skip_cpu:
             import oracle as orc
             ne = max(1, min(50, int(2e9 // (3 * n * n))))

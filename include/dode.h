@@ -265,7 +265,9 @@ dode_status dar_logits_bwd(const dode_routes* routes, int32_t f64, const void* R
  *       two boundary departures, and the ratios are the window's shares of the
  *       observation intervals.  Shares past interval H-1 or at lags >= K are
  *       dropped.
- *   f64: nonzero for double arrays, else float.  K <= 16.
+ *   prec: 0 for float arrays, 1 for double arrays, 2 for B as bfloat16 bits
+ *       (uint16, the upper half of the float) with y, q, A and all
+ *       arithmetic in float.  K <= 16.
  * Errors: DODE_ERR_SHAPE for malformed path tables, DODE_ERR_ARG for
  * non-positive or non-finite lengths or speeds.  Synchronises `stream` (the
  * path tables and the checks are read back); uses a scratch buffer of at
@@ -342,13 +344,16 @@ dode_status dar_from_costs(const dode_routes* routes, int32_t f64, const void* R
  *       q -= eta g), then q = max(q, 0)
  *   loss_hist host [E] or NULL: ||B q - y||^2 after each epoch (FP64 sum in
  *       a fixed order; costs one more pass over B per epoch)
- *   f64: nonzero for double arrays, else float.
+ *   prec: 0 for float arrays, 1 for double arrays, 2 for B as bfloat16 bits
+ *       (uint16, the upper half of the float) with y, q, A and all
+ *       arithmetic in float.
  * Errors: DODE_ERR_ARG if a perms row is not a permutation of 0..m-1 (checked
- * on the host), for a non-positive eta or chunk or a negative eps.
+ * on the host), for a non-positive eta or chunk, a negative eps or another
+ * prec.
  * Synchronises `stream` (the permutations are read back first, and the loss
  * history after the run); scratch of m + ceil(min(chunk, m)/128)*n values.
  */
-dode_status dense_spgd_run(int32_t m, int32_t n, int32_t f64, const void* B, const void* y, void* q,
+dode_status dense_spgd_run(int32_t m, int32_t n, int32_t prec, const void* B, const void* y, void* q,
                            void* A, const int32_t* perms, int32_t E, int32_t chunk,
                            int32_t optimizer, double eta, double eps, double* loss_hist,
                            void* stream);

@@ -524,22 +524,24 @@ def dar_from_costs(routes: Routes, Rr, cost, theta, W, portions=None, stream=Non
 
 def dense_spgd_run(B, y, q, A, perms, chunk, eta, eps=1e-10, optimizer=0, loss_hist=False,
                    stream=None):
-    """Algorithm 1 on a dense B [m][n] (device tensors, float32 or float64):
-    q, A [n] are updated in place; perms int32 [E][m] on the device.  Returns
-    the per-epoch losses (numpy, FP64) when loss_hist is set, else None."""
+    """Algorithm 1 on a dense B [m][n] (device tensors, float32, float64, or
+    bfloat16 with float32 y, q, A): q, A [n] are updated in place; perms int32
+    [E][m] on the device.  Returns the per-epoch losses (numpy, FP64) when
+    loss_hist is set, else None."""
     import torch
     m, n = B.shape
-    dt = B.dtype
-    if dt not in (torch.float32, torch.float64):
-        raise TypeError("B must be float32 or float64")
+    if B.dtype not in (torch.float32, torch.float64, torch.bfloat16):
+        raise TypeError("B must be float32, float64 or bfloat16")
+    dt = torch.float32 if B.dtype == torch.bfloat16 else B.dtype
+    prec = 2 if B.dtype == torch.bfloat16 else int(dt == torch.float64)
     E = perms.shape[0] if perms.numel() else 0
-    bp = _ptr(B, "B", dt, (m, n))
+    bp = _ptr(B, "B", B.dtype, (m, n))
     yp = _ptr(y, "y", dt, (m,))
     qp = _ptr(q, "q", dt, (n,))
     ap = _ptr(A, "A", dt, (n,))
     pp = _ptr(perms, "perms", torch.int32, (E, m))
     hist = np.zeros(max(E, 1)) if loss_hist else None
     hp = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if loss_hist else None
-    _check(lib().dense_spgd_run(m, n, int(dt == torch.float64), bp, yp, qp, ap, pp, E, int(chunk),
+    _check(lib().dense_spgd_run(m, n, prec, bp, yp, qp, ap, pp, E, int(chunk),
                                 int(optimizer), float(eta), float(eps), hp, _stream(stream)))
     return hist[:E] if loss_hist else None

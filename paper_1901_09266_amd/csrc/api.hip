@@ -1066,11 +1066,12 @@ dode_status dar_from_costs(const dode_routes* routes, int32_t f64, const void* R
   return DODE_OK;
 }
 
-dode_status dense_spgd_run(int32_t m, int32_t n, int32_t f64, const void* B, const void* y, void* q,
+dode_status dense_spgd_run(int32_t m, int32_t n, int32_t prec, const void* B, const void* y, void* q,
                            void* A, const int32_t* perms, int32_t E, int32_t chunk,
                            int32_t optimizer, double eta, double eps, double* loss_hist,
                            void* stream) {
   if (m < 1 || n < 1 || E < 0) return fail(DODE_ERR_SHAPE, "m=%d n=%d E=%d", m, n, E);
+  if (prec < 0 || prec > 2) return fail(DODE_ERR_ARG, "prec=%d must be 0, 1 or 2", prec);
   if (chunk < 1) return fail(DODE_ERR_ARG, "chunk=%d must be positive", chunk);
   if (optimizer != 0 && optimizer != 1) return fail(DODE_ERR_ARG, "optimizer=%d", optimizer);
   if (!(eta > 0.0) || !std::isfinite(eta) || !(eps >= 0.0) || !std::isfinite(eps))
@@ -1092,7 +1093,8 @@ dode_status dense_spgd_run(int32_t m, int32_t n, int32_t f64, const void* B, con
         seen[v] = e;
       }
   }
-  const size_t ss = f64 ? 8 : 4;
+  const size_t ss = prec == 1 ? 8 : 4;                 // state and scratch
+  const size_t bs = prec == 2 ? 2 : ss;                // one value of B
   const int32_t rows = std::min(chunk, m);
   const int32_t n_slices = (rows + dense_slice_rows() - 1) / dense_slice_rows();
   if (n_slices > 65535) return fail(DODE_ERR_SHAPE, "chunk=%d too large", chunk);
@@ -1102,8 +1104,8 @@ dode_status dense_spgd_run(int32_t m, int32_t n, int32_t f64, const void* B, con
   if (loss_hist) HIP_TRY(loss.alloc((size_t)E * 8, s));
   DenseArgs a{m, n, E, chunk, B, y, q, A, perms, r.p, part.p,
               loss_hist ? loss.as<double>() : nullptr, StepArgs{eta, eps, optimizer}};
-  const bool vec = ((uintptr_t)B % 16 == 0) && ((uintptr_t)q % 16 == 0) && ((size_t)n * ss) % 16 == 0;
-  HIP_TRY(dense_spgd(a, f64 != 0, vec, s));
+  const bool vec = ((uintptr_t)B % 16 == 0) && ((uintptr_t)q % 16 == 0) && ((size_t)n * bs) % 16 == 0;
+  HIP_TRY(prec == 2 ? dense_spgd_bf16(a, vec, s) : dense_spgd(a, prec == 1, vec, s));
   if (loss_hist) {
     HIP_TRY(hipMemcpyAsync(loss_hist, loss.p, (size_t)E * 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));

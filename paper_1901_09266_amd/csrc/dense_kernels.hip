@@ -17,6 +17,8 @@
 //                    projection q = max(q, 0).
 // The epoch loss ||B q - y||^2 (optional) uses the residual kernel over all
 // rows in natural order and a one-block FP64 sum in a fixed order.
+// B may also be stored as bf16 (FP32 arithmetic and state): the *_bf16
+// kernels read 16 bytes = 8 values per lane and load.
 #include "dode_internal.h"
 
 #include <algorithm>
@@ -196,6 +198,96 @@ k_dense_sq_sum(int32_t m, const S* __restrict__ r, double* __restrict__ out) {
   if (threadIdx.x == 0) *out = sh[0];
 }
 
+// ---- B stored as bf16 (FP32 arithmetic and state) -------------------------
+__device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xFFFF0000u); }
+
+__device__ __forceinline__ float dot8(const uint4 b, const float4 q0, const float4 q1) {
+  return bf16_lo(b.x) * q0.x + bf16_hi(b.x) * q0.y + bf16_lo(b.y) * q0.z + bf16_hi(b.y) * q0.w +
+         bf16_lo(b.z) * q1.x + bf16_hi(b.z) * q1.y + bf16_lo(b.w) * q1.z + bf16_hi(b.w) * q1.w;
+}
+
+// r[s] = B[row] . q - y[row]; VEC: 16-byte rows (8 values per load)
+template <bool VEC>
+__global__ void __launch_bounds__(kBlock)
+k_dense_resid_bf16(int32_t n, int32_t nr, const int32_t* __restrict__ rows,
+                   const uint16_t* __restrict__ B, const float* __restrict__ y,
+                   const float* __restrict__ q, float* __restrict__ r) {
+  const int s = blockIdx.x * kWaves + (int)(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (s >= nr) return;
+  const int32_t i = rows ? rows[s] : s;
+  const uint16_t* row = B + (int64_t)i * n;
+  float acc = 0.f;
+  if (VEC) {
+    const uint4* rv = reinterpret_cast<const uint4*>(row);
+    const float4* qv = reinterpret_cast<const float4*>(q);
+    const int nv = n / 8;
+    float a2 = 0.f;
+    int j = lane;
+    for (; j + 64 < nv; j += 128) {   // two 16-byte loads in flight per lane
+      const uint4 b0 = rv[j], b1 = rv[j + 64];
+      acc += dot8(b0, qv[2 * j], qv[2 * j + 1]);
+      a2 += dot8(b1, qv[2 * (j + 64)], qv[2 * (j + 64) + 1]);
+    }
+    if (j < nv) acc += dot8(rv[j], qv[2 * j], qv[2 * j + 1]);
+    acc += a2;
+  } else {
+    for (int j = lane; j < n; j += 64) acc += __uint_as_float((uint32_t)row[j] << 16) * q[j];
+  }
+  acc = wave_sum(acc);
+  if (lane == 0) r[s] = acc - y[i];
+}
+
+// part[slice][j] = sum over the slice's rows of B[rows[s]][j] r[s]; a lane
+// covers 8 columns (one 16-byte load) in VEC mode, else 1.
+template <bool VEC>
+__global__ void __launch_bounds__(kBlock)
+k_dense_colsum_bf16(int32_t n, int32_t nr, const int32_t* __restrict__ rows,
+                    const uint16_t* __restrict__ B, const float* __restrict__ r,
+                    float* __restrict__ part) {
+  constexpr int W = VEC ? 8 : 1;
+  __shared__ float sh[kWaves][64 * W];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t c0 = (int64_t)blockIdx.x * 64 * W;
+  const int64_t j0 = c0 + (int64_t)lane * W;
+  const int slice = blockIdx.y;
+  const int s_begin = slice * kSliceRows, s_end = min(nr, s_begin + kSliceRows);
+  float acc[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) acc[w] = 0.f;
+  if (j0 < n) {
+    if (VEC) {
+#pragma unroll 4
+      for (int s = s_begin + wave; s < s_end; s += kWaves) {
+        const uint4 b = *reinterpret_cast<const uint4*>(B + (int64_t)rows[s] * n + j0);
+        const float rs = r[s];
+        acc[0] += bf16_lo(b.x) * rs;
+        acc[1] += bf16_hi(b.x) * rs;
+        acc[2] += bf16_lo(b.y) * rs;
+        acc[3] += bf16_hi(b.y) * rs;
+        acc[4] += bf16_lo(b.z) * rs;
+        acc[5] += bf16_hi(b.z) * rs;
+        acc[6] += bf16_lo(b.w) * rs;
+        acc[7] += bf16_hi(b.w) * rs;
+      }
+    } else {
+      for (int s = s_begin + wave; s < s_end; s += kWaves)
+        acc[0] += __uint_as_float((uint32_t)B[(int64_t)rows[s] * n + j0] << 16) * r[s];
+    }
+  }
+#pragma unroll
+  for (int w = 0; w < W; ++w) sh[wave][lane * W + w] = acc[w];
+  __syncthreads();
+  for (int c = threadIdx.x; c < 64 * W; c += kBlock) {
+    if (c0 + c >= n) break;
+    float v = sh[0][c];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) v += sh[w][c];
+    part[(int64_t)slice * n + c0 + c] = v;
+  }
+}
+
 unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 template <typename S, bool VEC>
@@ -231,9 +323,46 @@ hipError_t run(const DenseArgs& a, hipStream_t s) {
   return hipSuccess;
 }
 
+template <bool VEC>
+hipError_t run_bf16(const DenseArgs& a, hipStream_t s) {
+  const uint16_t* B = static_cast<const uint16_t*>(a.B);
+  const float* y = static_cast<const float*>(a.y);
+  float* q = static_cast<float*>(a.q);
+  float* A = static_cast<float*>(a.A);
+  float* r = static_cast<float*>(a.r);
+  float* part = static_cast<float*>(a.part);
+  constexpr int W = VEC ? 8 : 1;
+  const unsigned col_blocks = blocks_for(a.n, 64 * W);
+  for (int32_t e = 0; e < a.E; ++e) {
+    for (int32_t s0 = 0; s0 < a.m; s0 += a.chunk) {
+      const int32_t nr = std::min(a.chunk, a.m - s0);
+      const int32_t* rows = a.perms + (int64_t)e * a.m + s0;
+      const int32_t n_slices = (nr + kSliceRows - 1) / kSliceRows;
+      hipLaunchKernelGGL(k_dense_resid_bf16<VEC>, dim3(blocks_for(nr, kWaves)), dim3(kBlock), 0, s,
+                         a.n, nr, rows, B, y, q, r);
+      hipLaunchKernelGGL(k_dense_colsum_bf16<VEC>, dim3(col_blocks, n_slices), dim3(kBlock), 0, s,
+                         a.n, nr, rows, B, r, part);
+      hipLaunchKernelGGL(k_dense_update<float>, dim3(blocks_for(a.n, 64)), dim3(kBlock), 0, s, a.n,
+                         n_slices, part, q, A, a.st);
+    }
+    if (a.loss) {
+      hipLaunchKernelGGL(k_dense_resid_bf16<VEC>, dim3(blocks_for(a.m, kWaves)), dim3(kBlock), 0, s,
+                         a.n, a.m, (const int32_t*)nullptr, B, y, q, r);
+      hipLaunchKernelGGL(k_dense_sq_sum<float>, dim3(1), dim3(kBlock), 0, s, a.m, r, a.loss + e);
+    }
+    const hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+  }
+  return hipSuccess;
+}
+
 }  // namespace
 
 int32_t dense_slice_rows() { return kSliceRows; }
+
+hipError_t dense_spgd_bf16(const DenseArgs& a, bool vec, hipStream_t s) {
+  return vec ? run_bf16<true>(a, s) : run_bf16<false>(a, s);
+}
 
 hipError_t dense_spgd(const DenseArgs& a, bool f64, bool vec, hipStream_t s) {
   if (f64) return vec ? run<double, true>(a, s) : run<double, false>(a, s);

@@ -380,6 +380,8 @@ struct DenseArgs {
 int32_t dense_slice_rows();
 // vec: B and q are 16-byte aligned and a row of B is a multiple of 16 bytes
 hipError_t dense_spgd(const DenseArgs& a, bool f64, bool vec, hipStream_t s);
+// B as bf16 bits, FP32 y, q, A (vec: B and q 16-byte aligned, n % 8 == 0)
+hipError_t dense_spgd_bf16(const DenseArgs& a, bool vec, hipStream_t s);
 
 // ---- MFMA tile kernels (mfma_kernels.hip) -------------------------------
 // corr: multiply with the corrected FP8 values (refinement steps)

@@ -1,6 +1,7 @@
 """Algorithm 1 on the dense random NNLS of section "Algorithm efficiency" on
 the GPU (dense_spgd_run) against the FP64 oracle: FP64 and FP32, vector and
-scalar row paths (n a multiple of the vector width or not), minibatches with a
+scalar row paths (n a multiple of the vector width or not), B stored as
+bfloat16 with FP32 arithmetic, minibatches with a
 short tail and several slices, the fixed step, the per-epoch loss, the
 sizes of the efficiency experiment (sampled), and the argument checks."""
 import numpy as np
@@ -45,6 +46,46 @@ def test_matches_oracle(f64, m, n, chunk):
         # 1e-7 per step, through 4 epochs of Adagrad steps of size ~eta
         assert rel(q, qo) <= 2e-4 and rel(A, Ao) <= 2e-4
         np.testing.assert_allclose(hist, ho, rtol=2e-4)
+
+
+def run_bf16(B, y, perms, chunk, eta, loss=True):
+    """B rounded to bfloat16 on the host (the oracle gets the same values)."""
+    Bh = torch.as_tensor(np.ascontiguousarray(B), dtype=torch.float32).to(torch.bfloat16)
+    m, n = B.shape
+    q = torch.zeros(n, dtype=torch.float32, device="cuda")
+    A = torch.zeros(n, dtype=torch.float32, device="cuda")
+    hist = dode.dense_spgd_run(Bh.cuda(), dev(y, torch.float32), q, A, dev(perms, torch.int32),
+                               chunk, eta, loss_hist=loss)
+    torch.cuda.synchronize()
+    return q.cpu().numpy(), A.cpu().numpy(), hist, Bh.to(torch.float64).numpy()
+
+
+@pytest.mark.parametrize("m,n,chunk", [(100, 64, 100), (173, 61, 40), (300, 257, 77), (50, 7, 8),
+                                        (1, 1, 1), (260, 16, 300), (129, 24, 128)])
+def test_bf16_matrix_matches_oracle(m, n, chunk):
+    """B stored as bfloat16, FP32 arithmetic: equals the oracle run on the
+    bf16-rounded B to FP32 rounding (the 16-byte path for n % 8 == 0, the
+    scalar path otherwise)."""
+    B, y, _, perms = make_dense_instance(n, m=m, epochs=4, seed=35)
+    y = y - 0.3 * y.mean()
+    say("dense bf16", m, n, chunk)
+    q, A, hist, Bo = run_bf16(B, y, perms, chunk, 0.05)
+    qo, Ao, ho = orc.dense_spgd(Bo, y.astype(np.float32).astype(np.float64), perms, chunk, 0.05)
+    assert rel(q, qo) <= 2e-4 and rel(A, Ao) <= 2e-4
+    np.testing.assert_allclose(hist, ho, rtol=2e-4)
+
+
+def test_bf16_matrix_paper_size_sampled():
+    """n = 6000 square with B in bfloat16, 3 epochs of one 8192-row
+    minibatch: losses and a sample of q against the oracle on the same B."""
+    n = 6000
+    B, y, _, perms = make_dense_instance(n, epochs=3, seed=36)
+    say("dense bf16 6000")
+    q, _, hist, Bo = run_bf16(B, y, perms, 8192, 1e-3)
+    qo, _, ho = orc.dense_spgd(Bo, y.astype(np.float32).astype(np.float64), perms, 8192, 1e-3)
+    np.testing.assert_allclose(hist, ho, rtol=1e-4)
+    idx = np.random.default_rng(1).choice(n, 200, replace=False)
+    np.testing.assert_allclose(q[idx], qo[idx], rtol=1e-4, atol=1e-7)
 
 
 def test_fixed_step_fp64():
