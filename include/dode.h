@@ -265,9 +265,7 @@ dode_status dar_logits_bwd(const dode_routes* routes, int32_t f64, const void* R
  *       two boundary departures, and the ratios are the window's shares of the
  *       observation intervals.  Shares past interval H-1 or at lags >= K are
  *       dropped.
- *   prec: 0 for float arrays, 1 for double arrays, 2 for B as bfloat16 bits
- *       (uint16, the upper half of the float) with y, q, A and all
- *       arithmetic in float.  K <= 16.
+ *   f64: nonzero for double arrays, else float.  K <= 16.
  * Errors: DODE_ERR_SHAPE for malformed path tables, DODE_ERR_ARG for
  * non-positive or non-finite lengths or speeds.  Synchronises `stream` (the
  * path tables and the checks are read back); uses a scratch buffer of at
