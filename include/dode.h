@@ -269,7 +269,7 @@ dode_status dar_logits_bwd(const dode_routes* routes, int32_t f64, const void* R
  * Errors: DODE_ERR_SHAPE for malformed path tables, DODE_ERR_ARG for
  * non-positive or non-finite lengths or speeds.  Synchronises `stream` (the
  * path tables and the checks are read back); uses a scratch buffer of at
- * most 1 GiB.
+ * most 4 GiB (the trajectories of a chunk of days).
  */
 dode_status dode_dar_from_speeds(int32_t n_paths, const int32_t* path_ptr,
                                  const int32_t* path_link, int64_t n_pairs, int32_t L,
