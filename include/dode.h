@@ -269,7 +269,11 @@ dode_status dar_logits_bwd(const dode_routes* routes, int32_t f64, const void* R
  * Errors: DODE_ERR_SHAPE for malformed path tables, DODE_ERR_ARG for
  * non-positive or non-finite lengths or speeds.  Synchronises `stream` (the
  * path tables and the checks are read back); uses a scratch buffer of at
- * most 4 GiB (the trajectories of a chunk of days).
+ * most 4 GiB (the trajectories of a chunk of days), or of the byte count in
+ * the environment variable DODE_DAR_SCRATCH_BYTES (smaller values process
+ * fewer days at a time; a value that is not a positive integer is
+ * DODE_ERR_ARG).  The results do not depend on the chunking beyond the
+ * rounding of the running day sums.
  */
 dode_status dode_dar_from_speeds(int32_t n_paths, const int32_t* path_ptr,
                                  const int32_t* path_link, int64_t n_pairs, int32_t L,

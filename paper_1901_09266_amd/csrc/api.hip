@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -1001,10 +1002,18 @@ dode_status dode_dar_costs_from_speeds(int32_t n_paths, const int32_t* path_ptr,
                                           n_days, H_speed, f64 != 0, s))
     return st;
   // trajectory scratch (and path exit times) for a chunk of days, at most
-  // 4 GiB (at least one day)
+  // 4 GiB or DODE_DAR_SCRATCH_BYTES (at least one day)
   const size_t ss = f64 ? 8 : 4;
   const size_t per_day = ((size_t)n_pairs + (cost ? (size_t)n_paths : 0)) * (H + 1) * ss;
-  const size_t cap = std::max<size_t>(1, (size_t(1) << 32) / std::max<size_t>(per_day, 1));
+  size_t limit = size_t(1) << 32;
+  if (const char* e = std::getenv("DODE_DAR_SCRATCH_BYTES")) {
+    char* end = nullptr;
+    const unsigned long long v = std::strtoull(e, &end, 10);
+    if (e[0] < '0' || e[0] > '9' || *end != '\0' || v == 0)
+      return fail(DODE_ERR_ARG, "DODE_DAR_SCRATCH_BYTES='%s' is not a positive byte count", e);
+    limit = (size_t)v;
+  }
+  const size_t cap = std::max<size_t>(1, limit / std::max<size_t>(per_day, 1));
   const int32_t chunk = (int32_t)std::min<size_t>((size_t)n_days, cap);
   DevBuf traj, sums;
   HIP_TRY(traj.alloc(std::max<size_t>(per_day * chunk, 16), s));

@@ -100,7 +100,7 @@ def test_reduced_precision_gradients(storage):
     dWo, dQo = orc.loss_backward(ri, Wref, x64, q64)
     dzo = orc.logits_backward(ri, 0, z.detach().double().cpu().numpy(), dWo)
     tol = 1e-5 if storage == "f32" else 1e-4
-    assert abs(float(loss) - lo) / lo <= tol
+    assert abs(float(loss.detach()) - lo) / lo <= tol
     assert rel(gQ.cpu().numpy(), dQo) <= tol
     # dz is computed from the FP32 dW through the FP32 chain rule
     assert rel(gz.cpu().numpy(), dzo) <= (1e-4 if storage == "f32" else 3e-3)

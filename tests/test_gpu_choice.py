@@ -156,9 +156,11 @@ def test_costs_from_ratio_trajectories(f64):
         assert rel(c2.cpu().numpy(), ref) <= 1e-13
 
 
-def test_costs_from_ratio_trajectories_chunks():
-    """160 days of 450 routes need two trajectory chunks (1 GiB): the running
-    FP64 sums across chunks give dode_path_costs' means."""
+def test_costs_from_ratio_trajectories_chunks(monkeypatch):
+    """160 days of 450 routes with the trajectory scratch capped at 1 GiB need
+    two chunks: the running FP64 sums across chunks give dode_path_costs'
+    means."""
+    monkeypatch.setenv("DODE_DAR_SCRATCH_BYTES", str(1 << 30))
     ci = make_choice_instance(sizes=(160,), seed=2300)
     t = torch.float32
     pp, pl, ln = dev(ci.path_ptr, torch.int32), dev(ci.path_link, torch.int32), dev(ci.link_len, t)
@@ -169,6 +171,28 @@ def test_costs_from_ratio_trajectories_chunks():
     torch.cuda.synchronize()
     # same FP32 day travel times on both sides; FP64 sums in another order
     assert rel(c2.cpu().numpy(), c1.cpu().numpy()) <= 1e-6
+
+
+def test_chunking_does_not_change_bits(monkeypatch):
+    """40 days in one trajectory chunk, and in chunks of 2 days (the scratch
+    capped at 24 MiB, 10.9 MB per day): the days are summed in the same order
+    either way, so ratios and costs are equal bit for bit; a cap that is not a
+    positive byte count is an argument error."""
+    ci = make_choice_instance(sizes=(40,), seed=2400)
+    t = torch.float32
+    pp, pl, ln = dev(ci.path_ptr, torch.int32), dev(ci.path_link, torch.int32), dev(ci.link_len, t)
+    sp = dev(ci.speed, t)
+    say("chunking bits, 40 days")
+    monkeypatch.delenv("DODE_DAR_SCRATCH_BYTES", raising=False)
+    r1, c1 = dode.dode_dar_costs_from_speeds(pp, pl, ln, sp, ci.dt, ci.H, ci.K)
+    monkeypatch.setenv("DODE_DAR_SCRATCH_BYTES", str(24 << 20))
+    r2, c2 = dode.dode_dar_costs_from_speeds(pp, pl, ln, sp, ci.dt, ci.H, ci.K)
+    torch.cuda.synchronize()
+    assert torch.equal(r1, r2) and torch.equal(c1, c2)
+    for bad in ("0", "-5", "12x", ""):
+        monkeypatch.setenv("DODE_DAR_SCRATCH_BYTES", bad)
+        with pytest.raises(dode.DodeError, match="DODE_DAR_SCRATCH_BYTES"):
+            dode.dode_dar_costs_from_speeds(pp, pl, ln, sp, ci.dt, ci.H, ci.K)
 
 
 def test_theta_zero_gives_equal_portions():

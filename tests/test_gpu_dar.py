@@ -54,9 +54,11 @@ def test_lag_counts_fp64(K):
     assert np.max(np.abs(R.cpu().numpy() - Ro)) <= 1e-12
 
 
-def test_several_day_chunks_fp32():
-    """160 days of a 500-link corridor need two trajectory chunks (1 GiB, 154
-    days each); the chunked day mean must equal the oracle's."""
+def test_several_day_chunks_fp32(monkeypatch):
+    """160 days of a 500-link corridor with the trajectory scratch capped at
+    1 GiB need two chunks (154 days each); the chunked day mean must equal
+    the oracle's."""
+    monkeypatch.setenv("DODE_DAR_SCRATCH_BYTES", str(1 << 30))
     si = make_speed_instance(L=500, P=150, H=288, sizes=(160,), seed=12)
     say("dar chunks")
     R = run(si, 6, si.dt, si.speed, f64=False)
