@@ -11,8 +11,8 @@
 //                    B[o_s][j] r[s], four consecutive columns per lane, so a
 //                    wave reads 1 KiB of one row per step; the block's four
 //                    waves split the slice's rows and meet in LDS;
-//   k_dense_update   one block per 64 columns: g = the slices' partial sums
-//                    (FP64, four waves over the slices, added in a fixed
+//   k_dense_update   one block per 16 columns: g = the slices' partial sums
+//                    (FP64, 16 lane groups over the slices, added in a fixed
 //                    order), then Adagrad (or a fixed step) and the
 //                    projection q = max(q, 0).
 // The epoch loss ||B q - y||^2 (optional) uses the residual kernel over all
@@ -151,33 +151,36 @@ k_dense_colsum(int32_t n, int32_t nr, const int32_t* __restrict__ rows, const S*
   }
 }
 
-// One block per 64 columns: wave w adds slices w, w+4, ... in FP64, the four
-// wave sums are added in wave order, then Adagrad (or the fixed step) and the
+// One block per 16 columns: lane group g = threadIdx.x / 16 (four per wave)
+// adds slices g, g+16, ... of its column in FP64 (each group reads 64
+// neighbouring bytes of a slice row), the 16 partial sums of a column are
+// added in order of g through LDS, then Adagrad (or the fixed step) and the
 // projection.
 template <typename S>
 __global__ void __launch_bounds__(kBlock)
 k_dense_update(int32_t n, int32_t n_slices, const S* __restrict__ part, S* __restrict__ q,
                S* __restrict__ A, StepArgs st) {
-  __shared__ double sh[kWaves][64];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int j = blockIdx.x * 64 + lane;
+  constexpr int kCols = 16, kParts = kBlock / kCols;
+  __shared__ double sh[kParts][kCols];
+  const int c = threadIdx.x % kCols, g = threadIdx.x / kCols;
+  const int64_t j = (int64_t)blockIdx.x * kCols + c;
   double gd = 0.0;
   if (j < n)
-    for (int k = wave; k < n_slices; k += kWaves) gd += static_cast<double>(part[(int64_t)k * n + j]);
-  sh[wave][lane] = gd;
+    for (int k = g; k < n_slices; k += kParts) gd += static_cast<double>(part[(int64_t)k * n + j]);
+  sh[g][c] = gd;
   __syncthreads();
-  if (wave != 0 || j >= n) return;
-  gd = sh[0][lane];
+  if (threadIdx.x >= kCols || j >= n) return;
+  gd = sh[0][c];
 #pragma unroll
-  for (int w = 1; w < kWaves; ++w) gd += sh[w][lane];
-  const S g = static_cast<S>(gd);
+  for (int p = 1; p < kParts; ++p) gd += sh[p][c];
+  const S g_j = static_cast<S>(gd);
   S v = q[j];
   if (st.optimizer == 0) {
-    const S acc = A[j] + g * g;
+    const S acc = A[j] + g_j * g_j;
     A[j] = acc;
-    v -= static_cast<S>(st.eta) * g / (sqrt(acc) + static_cast<S>(st.eps));
+    v -= static_cast<S>(st.eta) * g_j / (sqrt(acc) + static_cast<S>(st.eps));
   } else {
-    v -= static_cast<S>(st.eta) * g;
+    v -= static_cast<S>(st.eta) * g_j;
   }
   q[j] = v > S(0) ? v : S(0);
 }
@@ -309,7 +312,7 @@ hipError_t run(const DenseArgs& a, hipStream_t s) {
                          a.n, nr, rows, B, y, q, r);
       hipLaunchKernelGGL((k_dense_colsum<S, VEC>), dim3(col_blocks, n_slices), dim3(kBlock), 0, s,
                          a.n, nr, rows, B, r, part);
-      hipLaunchKernelGGL(k_dense_update<S>, dim3(blocks_for(a.n, 64)), dim3(kBlock), 0, s, a.n,
+      hipLaunchKernelGGL(k_dense_update<S>, dim3(blocks_for(a.n, 16)), dim3(kBlock), 0, s, a.n,
                          n_slices, part, q, A, a.st);
     }
     if (a.loss) {
@@ -342,7 +345,7 @@ hipError_t run_bf16(const DenseArgs& a, hipStream_t s) {
                          a.n, nr, rows, B, y, q, r);
       hipLaunchKernelGGL(k_dense_colsum_bf16<VEC>, dim3(col_blocks, n_slices), dim3(kBlock), 0, s,
                          a.n, nr, rows, B, r, part);
-      hipLaunchKernelGGL(k_dense_update<float>, dim3(blocks_for(a.n, 64)), dim3(kBlock), 0, s, a.n,
+      hipLaunchKernelGGL(k_dense_update<float>, dim3(blocks_for(a.n, 16)), dim3(kBlock), 0, s, a.n,
                          n_slices, part, q, A, a.st);
     }
     if (a.loss) {
