@@ -106,4 +106,4 @@ def test_reduced_precision_gradients(storage):
     assert rel(gz.cpu().numpy(), dzo) <= (1e-4 if storage == "f32" else 3e-3)
     if storage == "bf16":
         lexact = sum(orc.loss(ri, Wo, q64[d], x64[d]) for d in range(ri.D))
-        assert abs(float(loss) - lexact) / lexact <= 3e-3
+        assert abs(float(loss.detach()) - lexact) / lexact <= 3e-3
