@@ -637,6 +637,22 @@ def main():
                       "epochs_per_step": 1, "batch_rows": 8192, "minibatch_intervals": bh,
                       "refine_steps": refine[args.form]},
            "roofline": roof}
+    # Whole-epoch roof.  Floor: every array moved once per epoch (each
+    # cluster's ratios, every day's X read, Q and A read and written).  The
+    # minibatch schedule of Algorithm 1 moves more: a minibatch of random
+    # departure intervals reaches up to K demand / accumulator rows per
+    # interval, and the residual rows go out and back between the launches.
+    nblk_all = sum(min(inst.K, inst.H - t) for t in range(inst.T) if t < inst.H)
+    floor_b = (inst.C * nblk_all * inst.nnz * ESIZE[args.form] +
+               inst.D * (inst.H * inst.L * 4 + 4 * inst.T * inst.P * 4))
+    sched_b = (head["fwd_bytes"] + head["adj_bytes"]) / args.steps
+    out["epoch_roofline"] = {
+        "bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s", "measured_us": round(ms_step * 1e3, 1),
+        "floor_bytes": int(floor_b), "floor_roof_us": round(floor_b / HBM_PEAK_GBS / 1e3, 1),
+        "floor_frac": round(floor_b / HBM_PEAK_GBS / 1e3 / (ms_step * 1e3), 4),
+        "schedule_bytes": int(sched_b), "schedule_roof_us": round(sched_b / HBM_PEAK_GBS / 1e3, 1),
+        "schedule_frac": round(sched_b / HBM_PEAK_GBS / 1e3 / (ms_step * 1e3), 4),
+        "schedule_over_floor": round(sched_b / floor_b, 2)}
     out["forms"] = {f: {"day_gradients_per_s": round(inst.D * args.steps / (r["ms"] / 1e3), 1),
                         "ms_per_step": round(r["ms"] / args.steps, 4),
                         "kernel_ms_per_step": [round(x / args.steps, 4) for x in r["kernel_ms"][:2]]}
