@@ -71,11 +71,11 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def counted_traffic(config, form, kernel):
+def counted_traffic(config, form, kernel, variant=""):
     """HBM bytes per launch of `kernel` ("fwd" or "adj") from the committed
     FETCH_SIZE / WRITE_SIZE counter summary of this workload and form, or None
     when there is none or the kernel sources changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", f"traffic_spgd_config{config}_{form}.md")
+    path = os.path.join(ROOT, "profiles", f"traffic_spgd_config{config}{variant}_{form}.md")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -626,8 +626,8 @@ def main():
     k = int(np.argmax(kms[:2]))
     byts = head["fwd_bytes"] if k == 0 else head["adj_bytes"]
     achieved = byts / (kms[k] / 1e3) / 1e9
-    traffic = None if (args.per_day or args.pattern == "bernoulli") else counted_traffic(
-        args.config, args.form, ("fwd", "adj")[k])
+    traffic = None if args.pattern == "bernoulli" else counted_traffic(
+        args.config, args.form, ("fwd", "adj")[k], "_perday" if args.per_day else "")
     roof = {"bound": "hbm", "kernel": names[k], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": round(traffic) if traffic is not None else None,
