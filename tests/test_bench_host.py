@@ -1,0 +1,97 @@
+"""Host logic of the measurement script (no GPU): the per-launch byte model
+behind the roofline figures, checked against closed forms and invariants
+that any correct count must meet, and the lookup of committed traffic
+counter summaries, which must refuse a summary taken on other kernel
+sources."""
+import os
+import sys
+from types import SimpleNamespace
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+from synth import make_perms  # noqa: E402
+
+
+def tiny(K, day_cluster, C=2, H=12, L=5, P=3, nnz=7):
+    return SimpleNamespace(P=P, L=L, T=H, H=H, K=K, nnz=nnz, C=C,
+                           day_cluster=np.asarray(day_cluster, dtype=np.int64))
+
+
+@pytest.mark.parametrize("bh", [1, 4, 5, 12])
+def test_single_lag_epoch_is_closed_form(bh):
+    """K = 1: a minibatch reaches exactly its own intervals, so one epoch
+    moves every X row once, every residual row out and back, every Q (and A)
+    row once and every ratio block once."""
+    inst = tiny(1, [0, 0, 1, 1, 1])
+    perms = make_perms(5, 2, inst.C, inst.H)
+    s, esz, D = 4, 2, 5
+    fwd, adj = bench.launch_bytes(inst, perms, bh, esz, [1], s_state=s)
+    assert len(fwd) == len(adj) == -(-inst.H // bh)
+    blocks = inst.C * inst.T * inst.nnz * esz
+    assert fwd.sum() == D * (inst.H * inst.L * (4 + s) + inst.T * inst.P * s) + blocks
+    assert adj.sum() == D * (inst.H * inst.L * s + inst.T * inst.P * 4 * s) + blocks
+
+
+@pytest.mark.parametrize("K", [2, 3, 6])
+def test_ratio_blocks_read_once_per_epoch(K):
+    """With no days only the ratio values remain: each block (l, t) with
+    t + l < H is read once per epoch by the forward and once by the adjoint,
+    whatever the permutation and the minibatch size."""
+    inst = tiny(K, [])
+    perms = make_perms(7, 3, inst.C, inst.H)
+    nblk = sum(min(K, inst.H - t) for t in range(inst.T))
+    for bh in (1, 3, 12):
+        fwd, adj = bench.launch_bytes(inst, perms, bh, 1, [0, 2])
+        assert fwd.sum() == adj.sum() == 2 * inst.C * nblk * inst.nnz
+
+
+def test_lags_only_add_reached_rows():
+    """K > 1 reaches more demand rows than K = 1 (never fewer), and the X and
+    residual rows, fixed by the minibatch alone, are unchanged."""
+    perms = make_perms(9, 1, 2, 12)
+    f1, a1 = bench.launch_bytes(tiny(1, [0, 1, 1], nnz=0), perms, 4, 2, [0])
+    f3, a3 = bench.launch_bytes(tiny(3, [0, 1, 1], nnz=0), perms, 4, 2, [0])
+    assert np.all(f3 >= f1) and np.all(a3 >= a1) and f3.sum() > f1.sum()
+    # with P = 0 only the X and residual rows are left: equal for any K
+    f1p, a1p = bench.launch_bytes(tiny(1, [0, 1, 1], P=0, nnz=0), perms, 4, 2, [0])
+    f3p, a3p = bench.launch_bytes(tiny(3, [0, 1, 1], P=0, nnz=0), perms, 4, 2, [0])
+    assert np.array_equal(f1p, f3p) and np.array_equal(a1p, a3p)
+
+
+def test_refinement_steps_move_everything():
+    """Each full-batch refinement step reads every row and every block, with
+    the 3-byte corrected values."""
+    inst = tiny(2, [0, 1])
+    perms = make_perms(11, 1, inst.C, inst.H)
+    f0, _ = bench.launch_bytes(inst, perms, 4, 1, [0], refine=0)
+    f2, a2 = bench.launch_bytes(inst, perms, 4, 1, [0], refine=2)
+    assert len(f2) == len(f0) + 2 and np.array_equal(f2[2:], f0)
+    nblk = sum(min(2, inst.H - t) for t in range(inst.T))
+    full_f = 2 * (inst.H * inst.L * 8 + inst.T * inst.P * 4) + inst.C * nblk * inst.nnz * 3
+    assert f2[0] == f2[1] == full_f
+
+
+def test_traffic_lookup_follows_the_source_hash(monkeypatch, tmp_path):
+    """A counter summary is used while the kernel sources hash to its
+    recorded value, and refused (None) once they do not; a missing summary or
+    kernel gives None."""
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "profiles" / "traffic_spgd_config3_bf16.md").write_text(
+        "# summary\n\nsource_sha256: " + "ab" * 32 + "\nfwd_bytes_per_launch: 123\n"
+        "adj_bytes_per_launch: 456\n")
+    (tmp_path / "profiles" / "traffic_spgd_config2_perday_f32.md").write_text(
+        "source_sha256: " + "ab" * 32 + "\nfwd_bytes_per_launch: 7\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "ab" * 32)
+    assert bench.counted_traffic(3, "bf16", "fwd") == 123
+    assert bench.counted_traffic(3, "bf16", "adj") == 456
+    assert bench.counted_traffic(2, "f32", "fwd", "_perday") == 7
+    assert bench.counted_traffic(2, "f32", "adj", "_perday") is None
+    assert bench.counted_traffic(3, "fp8", "adj") is None
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "cd" * 32)
+    assert bench.counted_traffic(3, "bf16", "adj") is None
