@@ -427,3 +427,104 @@ def test_oracle_resume_is_bitwise():
     Qb, Ab, _ = orc.spgd(inst, inst.x, perms[E1:], E - E1, bh, optimizer=0, eta=2.0, q0=Q1, A0=A1)
     np.testing.assert_array_equal(Qa, Qb)
     np.testing.assert_array_equal(Aa, Ab)
+
+
+# ------------------------------------------- helpers the GPU tests rely on --
+@pytest.mark.parametrize("shape", [dict(P=4, L=6, T=12, K=3, inc=0.5, bh=5),
+                                   dict(P=7, L=9, T=10, K=4, inc=0.3, bh=3, H=8)])
+def test_spgd_step_chain_equals_spgd_day(shape):
+    """orc_spgd_step against the pinned orc_spgd_day (Algorithm 1): running
+    spgd_step on the consecutive b_h-interval slices of each epoch's permutation
+    (the last one shorter) reproduces spgd_day bit for bit, for both optimizers."""
+    kw = dict(shape)
+    bh = kw.pop("bh")
+    H = kw.pop("H", None)
+    inst = make_instance(sizes=(1,), pattern="bernoulli", demand="uniform50", noise="add1",
+                         x_dtype="f64", seed=31, H=H, **kw)
+    E = 4
+    perm = make_perms(77, E, 1, inst.H)[:, 0]
+    x = inst.x[0]
+    for optimizer, eta in ((0, 2.0), (1, 0.02)):
+        q_day, A_day, _ = orc.spgd_day(inst, inst.W[0], x, perm, E, bh, optimizer=optimizer,
+                                       eta=eta, record_loss=False)
+        q = np.zeros((inst.T, inst.P))
+        A = np.zeros((inst.T, inst.P))
+        for e in range(E):
+            for s in range(0, inst.H, bh):
+                q, A = orc.spgd_step(inst, inst.W[0], x, q, A, perm[e, s:s + bh],
+                                     optimizer=optimizer, eta=eta)
+        assert np.array_equal(q, q_day) and np.array_equal(A, A_day)
+
+
+def test_spgd_step_against_dense_minibatch():
+    """orc_spgd_step on the rows of the listed intervals, against the minibatch
+    written with the paper's global matrix (Table "DODE framework variable
+    vectorization") and a library matmul: r = M_S q - x_S, g = M_S^T r, then
+    Adagrad (eps after the square root) and max(q, 0) (Algorithm 1)."""
+    inst = make_config(1)
+    M = dense_rho(inst, inst.W[0])
+    rng = np.random.default_rng(12)
+    q = rng.uniform(0, 20, (inst.T, inst.P))
+    A = rng.uniform(0, 5, (inst.T, inst.P))
+    x = inst.x[0]
+    hb = np.array([7, 2, 10], dtype=np.int32)
+    rows = (hb[:, None] * inst.L + np.arange(inst.L)[None, :]).ravel()
+    MS = M[rows]
+    g = MS.T @ (MS @ q.ravel() - x.ravel()[rows])
+    eta, eps = 3.0, 1e-10
+    A_ref = A.ravel() + g * g
+    q_ref = np.maximum(q.ravel() - eta * g / (np.sqrt(A_ref) + eps), 0.0)
+    q1, A1 = orc.spgd_step(inst, inst.W[0], x, q, A, hb, optimizer=0, eta=eta, eps=eps)
+    np.testing.assert_allclose(A1.ravel(), A_ref, rtol=1e-13, atol=1e-12)
+    np.testing.assert_allclose(q1.ravel(), q_ref, rtol=1e-12, atol=1e-11)
+    # untouched coordinates (g = 0) keep their value
+    untouched = np.abs(g) == 0
+    assert untouched.any()
+    assert np.array_equal(q1.ravel()[untouched], q.ravel()[untouched])
+    q2, _ = orc.spgd_step(inst, inst.W[0], x, q, A, hb, optimizer=1, eta=0.01)
+    np.testing.assert_allclose(q2.ravel(), np.maximum(q.ravel() - 0.01 * g, 0.0), rtol=1e-12,
+                               atol=1e-11)
+
+
+@pytest.mark.parametrize("cid_seed", [(1, None), (1, 5), (4, None)])
+def test_fixed_step_eta_is_inverse_lambda_max(cid_seed):
+    """The fixed step of the config-1 reading: 1/lambda_max(rho^T rho), against a
+    library symmetric eigensolver on the global matrix."""
+    cid, seed = cid_seed
+    if cid == 1:
+        inst = make_config(1, seed=seed) if seed else make_config(1)
+    else:
+        inst = make_instance(P=5, L=7, T=9, K=3, sizes=(1,), inc=0.5, pattern="bernoulli",
+                             demand="uniform50", noise="add1", x_dtype="f64", seed=44)
+    M = dense_rho(inst, inst.W[0])
+    lam = float(np.linalg.eigvalsh(M.T @ M)[-1])
+    assert abs(orc.fixed_step_eta(inst) * lam - 1.0) <= 1e-10
+
+
+def test_metrics_interleaved_clusters():
+    """orc_metrics with the days of three clusters interleaved: every day takes
+    its own cluster's matrix.  Loss, KKT residual and R^2 (Step 6 "Quality
+    check") against the global matrix of that cluster, written out with numpy,
+    and R^2 against a library routine."""
+    from sklearn.metrics import r2_score
+    inst = make_instance(P=4, L=6, T=12, K=3, sizes=(3, 2, 2), inc=0.5, pattern="bernoulli",
+                         demand="uniform50", noise="add1", x_dtype="f64", seed=52)
+    days = np.array([0, 3, 5, 1, 6, 2, 4])
+    assert len(set(inst.day_cluster[days][:3])) == 3
+    rng = np.random.default_rng(3)
+    Q = rng.uniform(0, 30, (days.size, inst.T, inst.P))
+    Q[:, :, 0] = 0.0
+    loss, kkt, r2 = orc.metrics(inst, inst.x, Q, days=days, nthreads=2)
+    for i, d in enumerate(days):
+        c = int(inst.day_cluster[d])
+        M = dense_rho(inst, inst.W[c])
+        y = inst.x[d].ravel()
+        r = M @ Q[i].ravel() - y
+        g = M.T @ r
+        assert abs(loss[i] - r @ r) <= 1e-12 * (r @ r)
+        assert abs(kkt[i] - np.max(np.abs(np.minimum(Q[i].ravel(), g)))) <= 1e-12 * np.abs(g).max()
+        assert abs(r2[i] - r2_score(y, M @ Q[i].ravel())) <= 1e-12
+        # a different cluster's matrix gives a different loss: the pick matters
+        other = dense_rho(inst, inst.W[(c + 1) % inst.C])
+        ro = other @ Q[i].ravel() - y
+        assert abs(ro @ ro - loss[i]) > 1e-6 * loss[i]
