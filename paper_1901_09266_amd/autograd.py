@@ -21,16 +21,24 @@ class DodeLoss(torch.autograd.Function):
     z   [n_paths] route logits (float32 or float64)
     Rr  [K][T][n_pairs] per-pair lag ratios (dtype of z)
     X   [n][H][L] observations
-    The values rho_c(z) are installed in `dar` (dar_set_values) on every forward.
+    The values rho_c(z) are installed in `dar` (dar_set_values) by the forward
+    and installed again from the saved z by the backward, so several forwards
+    with different logits on one `dar` (a sum of losses, a line search) each
+    get the gradient of their own rho_c(z).  After a backward, `dar` holds the
+    values of that call's z.
     """
 
     @staticmethod
-    def forward(ctx, Q, z, dar, cluster, routes, Rr, X):
+    def _install(dar, cluster, routes, Rr, z):
         P, L, T, H, K = dar.dims
         W = torch.empty((K, T, routes.nnz), dtype=z.dtype, device=z.device)
         _lib.dar_from_logits(routes, Rr, z, W)
         Wd = W if W.dtype == dar.state_dtype else W.to(dar.state_dtype)
         _lib.dar_set_values(dar, cluster, Wd.contiguous())
+
+    @staticmethod
+    def forward(ctx, Q, z, dar, cluster, routes, Rr, X):
+        DodeLoss._install(dar, cluster, routes, Rr, z)
         loss = torch.empty(Q.shape[0], dtype=torch.float64, device=Q.device)
         _lib.dode_loss(dar, cluster, Q, X, loss)
         ctx.dar, ctx.cluster, ctx.routes = dar, cluster, routes
@@ -43,6 +51,8 @@ class DodeLoss(torch.autograd.Function):
         dar, routes = ctx.dar, ctx.routes
         P, L, T, H, K = dar.dims
         go = float(g)
+        # the residual is recomputed with rho_c of this call's logits
+        DodeLoss._install(dar, ctx.cluster, routes, Rr, z)
         dQ = torch.empty_like(Q) if ctx.needs_input_grad[0] else None
         dz = None
         dW = None

@@ -177,10 +177,16 @@ def _incidence(rng, L, P, inc, pattern):
 
 def _lag_ratios(rng, K, T, H, n):
     """[K][T][n] ratios: U(0,1) per lag, normalised over the K lags, then lags
-    that land past the last interval are dropped (their mass leaves the day)."""
-    w = rng.random((T, n, K))
-    w /= w.sum(axis=2, keepdims=True)
-    W = np.ascontiguousarray(w.transpose(2, 0, 1))
+    that land past the last interval are dropped (their mass leaves the day).
+    The draws are taken in [T][n][K] order, a slab of intervals at a time (the
+    same stream as one draw of the whole array)."""
+    W = np.empty((K, T, n))
+    step = max(1, (1 << 22) // max(1, n * K))
+    for t0 in range(0, T, step):
+        t1 = min(T, t0 + step)
+        w = rng.random((t1 - t0, n, K))
+        w /= w.sum(axis=2, keepdims=True)
+        W[:, t0:t1, :] = w.transpose(2, 0, 1)
     for l in range(K):
         if H - l < T:
             W[l, max(H - l, 0):, :] = 0.0
@@ -194,35 +200,63 @@ def _profile(T):
 
 
 class _BandCSR:
-    """Row-compressed layout of the full (H*L) x (T*P) band matrix of one pattern.
-    Built once per pattern; `src` maps each CSR slot to its flat [K][T][nnz] value."""
+    """Row-compressed layout of the full (H*L) x (T*P) band matrix of one pattern,
+    columns sorted within each row.  Built once per pattern; `src` maps each
+    CSR slot to its flat [K][T][nnz] value."""
 
     def __init__(self, P, L, T, H, K, row_ptr, col_idx):
-        import scipy.sparse as sp
-        rows = np.repeat(np.arange(L, dtype=np.int64), np.diff(row_ptr))
+        row_ptr = np.asarray(row_ptr, dtype=np.int64)
+        col_idx = np.asarray(col_idx, dtype=np.int64)
         nnz = col_idx.shape[0]
-        R, C, V = [], [], []
-        for l in range(K):
-            tmax = min(T, H - l)
-            if tmax <= 0:
+        deg = np.diff(row_ptr)
+        # row (h, a) holds the departure intervals t = h-l inside [0, T) in
+        # increasing order, each with the pattern entries of link a
+        t_lo = np.maximum(np.arange(H) - (K - 1), 0)
+        t_hi = np.minimum(np.arange(H), T - 1)
+        nt = np.maximum(t_hi - t_lo + 1, 0)
+        lens = (nt[:, None] * deg[None, :]).ravel()
+        indptr = np.zeros(H * L + 1, dtype=np.int64)
+        np.cumsum(lens, out=indptr[1:])
+        indices = np.empty(indptr[-1], dtype=np.int32)
+        src = np.empty(indptr[-1], dtype=np.int64)
+        # inside row block h (all L links, nt intervals each), pattern entry j
+        # of link a at its t-th interval sits at nt*row_ptr[a] + t*deg[a] + (j - row_ptr[a])
+        J = np.arange(nnz, dtype=np.int64)
+        A = np.repeat(np.arange(L, dtype=np.int64), deg)
+        rel = {}
+        for h in range(H):
+            n_t = int(nt[h])
+            if n_t == 0:
                 continue
-            tt = np.arange(tmax, dtype=np.int64)
-            R.append(((tt[:, None] + l) * L + rows[None, :]).ravel())
-            C.append((tt[:, None] * P + col_idx[None, :].astype(np.int64)).ravel())
-            V.append((l * T * nnz + tt[:, None] * nnz + np.arange(nnz)[None, :]).ravel())
-        src = np.concatenate(V).astype(np.float64) + 1.0
-        M = sp.csr_matrix((src, (np.concatenate(R), np.concatenate(C))), shape=(H * L, T * P))
-        self.indptr, self.indices = M.indptr, M.indices
-        self.src = (M.data - 1.0).astype(np.int64)
+            if n_t not in rel:
+                ti = np.arange(n_t, dtype=np.int64)[:, None]
+                rel[n_t] = (n_t * row_ptr[A] + ti * deg[A] + (J - row_ptr[A])[None, :]).ravel()
+            tt = np.arange(t_lo[h], t_hi[h] + 1, dtype=np.int64)[:, None]
+            pos = indptr[h * L] + rel[n_t]
+            indices[pos] = (tt * P + col_idx[None, :]).ravel()
+            src[pos] = ((h - tt) * T * nnz + tt * nnz + J[None, :]).ravel()
+        self.indptr, self.indices, self.src = indptr, indices, src
         self.shape = (H * L, T * P)
 
     def product(self, Wc, Q):
-        """[n][H][L] link counts of the days in Q ([n][T][P])."""
+        """[n][H][L] link counts of the days in Q ([n][T][P]); days are split
+        over threads (each row's sum runs in the same order for any split)."""
         import scipy.sparse as sp
+        from concurrent.futures import ThreadPoolExecutor
         M = sp.csr_matrix((Wc.ravel()[self.src], self.indices, self.indptr), shape=self.shape)
         n = Q.shape[0]
-        Y = M @ np.ascontiguousarray(Q.reshape(n, -1).T)
-        return np.ascontiguousarray(Y.T)
+        Qt = np.ascontiguousarray(Q.reshape(n, -1).T)
+        Y = np.empty((n, self.shape[0]))
+        step = 16
+        chunks = [(d, min(n, d + step)) for d in range(0, n, step)]
+
+        def one(ab):
+            a, b = ab
+            Y[a:b] = (M @ np.ascontiguousarray(Qt[:, a:b])).T
+
+        with ThreadPoolExecutor(max_workers=min(16, len(chunks))) as ex:
+            list(ex.map(one, chunks))
+        return Y
 
 
 def _observe(P, L, T, H, K, row_ptr, col_idx, Wc, Q, band=None):

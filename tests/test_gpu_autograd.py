@@ -107,3 +107,27 @@ def test_reduced_precision_gradients(storage):
     if storage == "bf16":
         lexact = sum(orc.loss(ri, Wo, q64[d], x64[d]) for d in range(ri.D))
         assert abs(float(loss.detach()) - lexact) / lexact <= 3e-3
+
+
+def test_two_forwards_then_backward_of_each():
+    """Two losses with different logits on one dar, then the gradient of each
+    and of their sum: every backward recomputes rho_c from its own z, so the
+    first loss is not differentiated at the second forward's values."""
+    ri, dar, routes, Rr = setup("f64", torch.float64)
+    say("two forwards f64")
+    X = dev(ri.x, torch.float64)
+    Q = dev(ri.qstar * 0.8, torch.float64)
+    z1 = dev(ri.z0[0], torch.float64).requires_grad_(True)
+    z2 = dev(ri.z0[0] + np.random.default_rng(8).normal(0, 1.0, ri.n_paths),
+             torch.float64).requires_grad_(True)
+    l1 = DodeLoss.apply(Q, z1, dar, 0, routes, Rr, X)
+    l2 = DodeLoss.apply(Q, z2, dar, 0, routes, Rr, X)
+    (g1,) = torch.autograd.grad(l1, z1, retain_graph=True)
+    gs1, gs2 = torch.autograd.grad(l1 + l2, (z1, z2))
+    for z, g_list in ((z1, (g1, gs1)), (z2, (gs2,))):
+        zn = z.detach().cpu().numpy()
+        Wo = orc.rho_from_logits(ri, 0, zn)
+        dWo, _ = orc.loss_backward(ri, Wo, ri.x, ri.qstar * 0.8, want_Q=False)
+        dzo = orc.logits_backward(ri, 0, zn, dWo)
+        for g in g_list:
+            assert rel(g.cpu().numpy(), dzo) <= 1e-11
