@@ -81,8 +81,12 @@ typedef struct {
   int32_t check_finite;/* nonzero: scan X for NaN/Inf before solving */
   int32_t kernel_path; /* 0 = fastest available for the storage type (matrix-core
                           tiles for BF16 / FP8 when a cluster has more than 2
-                          days or refine_steps > 0, else the sparse kernels),
-                          1 = sparse pattern kernels */
+                          days or refine_steps > 0, a forward and an adjoint
+                          launch per minibatch, else the sparse kernels),
+                          1 = sparse pattern kernels, 2 = matrix-core tiles
+                          with one launch per minibatch, one workgroup per
+                          independent part of it (same bits as 0; slower on
+                          the benchmark workloads) */
   int32_t use_graph;   /* nonzero: spgd_run replays one captured hipGraph per epoch
                           (the epoch index lives in a device counter) */
   int32_t day_tile;    /* days of one cluster handled together by a matrix-core
@@ -191,7 +195,10 @@ dode_status spgd_step(const dode_dar* dar, int32_t cluster, const int32_t* chunk
  *                Q, e.g. 0, to start fresh; Q is projected onto Q >= 0 first)
  *   perm         host [E][C][H]: the permutation of the H observation
  *                intervals of each (epoch, cluster); NULL = drawn by the library
- *                from `seed` (SplitMix64 + Fisher-Yates)
+ *                from `seed`: one SplitMix64 stream (Steele, Lea and Flood
+ *                2014) started at `seed`, and for each (epoch, cluster) in
+ *                order a Fisher-Yates shuffle of 0..H-1 from the top, element
+ *                i swapping with element (next draw mod (i + 1)), i = H-1..1
  *   loss_hist    host [D][E] or NULL: full loss of each day after each epoch
  *                (costs one extra forward pass per epoch; synchronises stream)
  * The minibatches of epoch e and cluster c are consecutive slices of b_h
@@ -407,9 +414,10 @@ dode_status spgd_run(dode_plan* plan, int32_t epoch_begin, int32_t n_epochs, dou
 /*
  * Kernel timing of a plan.  enable != 0 makes later spgd_run calls record a
  * HIP event pair around every kernel launch on the run's stream; the summed
- * durations in milliseconds (host [3]: forward-residual kernel, adjoint-step
- * kernel, loss kernels) and the launch counts (host [3]) are returned and
- * reset by the next call (which synchronises the last run's stream).
+ * durations in milliseconds (host [3]: forward-residual launches, adjoint-step
+ * launches or whole-minibatch launches of the one-launch path, loss kernels)
+ * and the launch counts (host [3]) are returned and reset by the next call
+ * (which synchronises the last run's stream).
  */
 dode_status spgd_plan_timing(dode_plan* plan, int32_t enable, double* ms, int64_t* launches);
 

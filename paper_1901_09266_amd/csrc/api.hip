@@ -100,7 +100,28 @@ uint64_t splitmix64(uint64_t& s) {
 struct HostSched {
   int32_t bh = 0, nch = 0, mt = 0;
   std::vector<int32_t> perm, pos, touched;   // [E][C][H], [E][C][H], [E][nch][C][mt]
+  // component schedule (CompSched): [E][nch][C][bh], [E][nch][C][mt][K+3],
+  // [E][nch][C][max_comp][4]
+  int32_t max_comp = 1;
+  std::vector<int32_t> kslot, kdesc, kcomp;
 };
+
+// Descriptor of departure interval t for the minibatch at positions
+// j0..j0+bh-1 of a permutation with inverse `pos`: [t, lag mask, slot per lag].
+void fill_desc(int32_t* dsc, int32_t t, const int32_t* pos, int32_t j0, int32_t bh, int32_t H,
+               int32_t K) {
+  dsc[kDescT] = t;
+  uint64_t mask = 0;
+  for (int32_t l = 0; l < K; ++l) {
+    const int32_t h = t + l;
+    const int32_t sl = h < H ? pos[h] - j0 : -1;
+    const bool in = sl >= 0 && sl < bh;
+    dsc[kDescSlot + l] = in ? sl : -1;
+    if (in) mask |= 1ull << l;
+  }
+  dsc[kDescMask] = (int32_t)(uint32_t)mask;
+  dsc[kDescMask + 1] = (int32_t)(uint32_t)(mask >> 32);
+}
 
 // Minibatch layout for epochs of C clusters from permutations perm [E][C][H].
 dode_status build_sched(const dode_dims& dm, int32_t C, int32_t E, int32_t bh,
@@ -171,20 +192,54 @@ dode_status build_sched(const dode_dims& dm, int32_t C, int32_t E, int32_t bh,
         for (int32_t k = 0; k < n; ++k) {
           const int32_t t = tl[r * hs.mt + k];
           const int32_t i = (int32_t)((int64_t)k * mt_used / n);
-          int32_t* dsc = hs.touched.data() + (r * mt_used + i) * dw;
-          dsc[kDescT] = t;
-          uint64_t mask = 0;
-          for (int32_t l = 0; l < K; ++l) {
-            const int32_t h = t + l;
-            const int32_t sl = h < H ? pos[h] - j * bh : -1;
-            const bool in = sl >= 0 && sl < bh;
-            dsc[kDescSlot + l] = in ? sl : -1;
-            if (in) mask |= 1ull << l;
-          }
-          dsc[kDescMask] = (int32_t)(uint32_t)mask;
-          dsc[kDescMask + 1] = (int32_t)(uint32_t)(mask >> 32);
+          fill_desc(hs.touched.data() + (r * mt_used + i) * dw, t, pos, j * bh, bh, H, K);
         }
       }
+  // Components of each minibatch: its intervals sorted, cut where two
+  // neighbours are K or more apart.  Component [h_a .. h_b] reaches the
+  // departure intervals max(0, h_a-K+1) .. min(T-1, h_b), all of them, and no
+  // other component reaches any of these.
+  std::vector<int32_t> ncomp((size_t)E * hs.nch * C, 0);
+  std::vector<std::pair<int32_t, int32_t>> hsl;
+  for (int pass = 0; pass < 2; ++pass) {
+    if (pass == 1) {
+      hs.kslot.assign((size_t)E * hs.nch * C * bh, -1);
+      hs.kdesc.assign((size_t)E * hs.nch * C * mt_used * dw, -1);
+      hs.kcomp.assign((size_t)E * hs.nch * C * hs.max_comp * 4, 0);
+    }
+    for (int32_t e = 0; e < E; ++e)
+      for (int32_t j = 0; j < hs.nch; ++j)
+        for (int32_t c = 0; c < C; ++c) {
+          const size_t r = ((size_t)e * hs.nch + j) * C + c;
+          const int32_t* p = hs.perm.data() + ((size_t)e * C + c) * H;
+          const int32_t* pos = hs.pos.data() + ((size_t)e * C + c) * H;
+          hsl.clear();
+          for (int32_t sl = 0; sl < bh && j * bh + sl < H; ++sl) hsl.push_back({p[j * bh + sl], sl});
+          std::sort(hsl.begin(), hsl.end());
+          int32_t nc = 0, nd = 0;
+          for (size_t a = 0; a < hsl.size();) {
+            size_t b = a + 1;
+            while (b < hsl.size() && hsl[b].first - hsl[b - 1].first < K) ++b;
+            if (pass == 1) {
+              const int32_t tlo = std::max(0, hsl[a].first - K + 1);
+              const int32_t thi = std::min(T - 1, hsl[b - 1].first);
+              int32_t* cp = hs.kcomp.data() + (r * hs.max_comp + nc) * 4;
+              cp[0] = (int32_t)a;
+              cp[1] = (int32_t)(b - a);
+              cp[2] = nd;
+              cp[3] = std::max(0, thi - tlo + 1);
+              for (size_t q = a; q < b; ++q) hs.kslot[r * bh + q] = hsl[q].second;
+              for (int32_t t = tlo; t <= thi; ++t, ++nd)
+                fill_desc(hs.kdesc.data() + (r * mt_used + nd) * dw, t, pos, j * bh, bh, H, K);
+            }
+            ++nc;
+            a = b;
+          }
+          if (pass == 0) ncomp[r] = nc;
+        }
+    if (pass == 0)
+      hs.max_comp = std::max<int32_t>(1, *std::max_element(ncomp.begin(), ncomp.end()));
+  }
   hs.mt = mt_used;
   return DODE_OK;
 }
@@ -197,8 +252,9 @@ dode_status check_params(const dode_spgd_params* p) {
   if (!(p->eps >= 0) || !std::isfinite(p->eps)) return fail(DODE_ERR_ARG, "eps must be >= 0");
   if (p->optimizer != 0 && p->optimizer != 1)
     return fail(DODE_ERR_ARG, "optimizer=%d (0 Adagrad, 1 fixed step)", p->optimizer);
-  if (p->kernel_path != 0 && p->kernel_path != 1)
-    return fail(DODE_ERR_ARG, "kernel_path=%d (0 best, 1 sparse)", p->kernel_path);
+  if (p->kernel_path < 0 || p->kernel_path > 2)
+    return fail(DODE_ERR_ARG, "kernel_path=%d (0 best, 1 sparse, 2 tiles in one launch)",
+                p->kernel_path);
   if (p->day_tile != 0 && p->day_tile != 16 && p->day_tile != 32 && p->day_tile != 64)
     return fail(DODE_ERR_ARG, "day_tile=%d (0 = tune, 16, 32 or 64)", p->day_tile);
   if (p->refine_steps < 0 || p->refine_steps > 16)
@@ -303,7 +359,8 @@ namespace {
 
 // Minibatch j of epoch e on the plan's state: forward + residual, then
 // adjoint + step + projection.
-dode_status run_chunk(dode_plan* plan, const ChunkSched& cs, hipStream_t s, bool corr = false) {
+dode_status run_chunk(dode_plan* plan, const ChunkSched& cs, const CompSched* ks, hipStream_t s,
+                      bool corr = false) {
   const dode_dar* dar = plan->dar;
   const Layout& ly = plan->ly;
   if (plan->use_mfma) {
@@ -312,6 +369,10 @@ dode_status run_chunk(dode_plan* plan, const ChunkSched& cs, hipStream_t s, bool
     float* Q = static_cast<float*>(plan->d_Q);
     float* A = static_cast<float*>(plan->d_A);
     const float* X = static_cast<const float*>(plan->d_X);
+    if (plan->one_launch && ks && !corr) {
+      HIP_TRY(timed(plan, 1, s, [&] { return mfma_minibatch(dar, *ks, dg, ly, X, R, Q, A, plan->sa, s); }));
+      return DODE_OK;
+    }
     HIP_TRY(timed(plan, 0, s, [&] { return mfma_chunk_resid(dar, cs, dg, ly, Q, X, R, corr, s); }));
     HIP_TRY(timed(plan, 1, s, [&] {
       return mfma_chunk_adj_step(dar, cs, dg, ly, R, Q, A, plan->sa, corr, s);
@@ -330,14 +391,15 @@ dode_status run_chunk(dode_plan* plan, const ChunkSched& cs, hipStream_t s, bool
 }
 
 dode_status run_minibatch(dode_plan* plan, int32_t e, int32_t j, hipStream_t s) {
-  return run_chunk(plan, plan->chunk(e, j), s);
+  const CompSched ks = plan->comps(e, j);
+  return run_chunk(plan, plan->chunk(e, j), &ks, s);
 }
 
 // The refinement steps that end every epoch: full-batch steps on the
 // corrected values (schedule independent of the epoch).
 dode_status run_refinement(dode_plan* plan, hipStream_t s) {
   for (int32_t r = 0; r < plan->refine_steps; ++r)
-    if (dode_status st = run_chunk(plan, plan->chunk_full(), s, true)) return st;
+    if (dode_status st = run_chunk(plan, plan->chunk_full(), nullptr, s, true)) return st;
   return DODE_OK;
 }
 
@@ -350,7 +412,10 @@ dode_status build_epoch_graph(dode_plan* plan) {
   hipStream_t cs = plan->capture_stream;
   HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
   dode_status st = DODE_OK;
-  for (int32_t j = 0; j < plan->nch && st == DODE_OK; ++j) st = run_chunk(plan, plan->chunk_dev(j), cs);
+  for (int32_t j = 0; j < plan->nch && st == DODE_OK; ++j) {
+    const CompSched ks = plan->comps(-1, j);
+    st = run_chunk(plan, plan->chunk_dev(j), &ks, cs);
+  }
   if (st == DODE_OK) st = run_refinement(plan, cs);
   hipError_t e = st == DODE_OK ? bump_counter(plan->d_epoch, cs) : hipSuccess;
   hipGraph_t g = nullptr;
@@ -560,12 +625,17 @@ dode_status dar_create_ex(const dode_dims* dims, int32_t n_clusters, const int32
   for (int32_t c = 0; c < n_clusters; ++c)
     if (!values[c]) return fail(DODE_ERR_ARG, "values[%d] is NULL", c);
   const int64_t cstride = (int64_t)dm.K * dm.T * nnz;
-  for (int32_t c = 0; c < n_clusters; ++c)
-    for (int32_t l = 0; l < dm.K; ++l)
-      for (int32_t t = 0; t < std::min(dm.T, dm.H - l); ++t)
-        for (int64_t j = 0; j < nnz; ++j)
-          if (!std::isfinite(values[c][((int64_t)l * dm.T + t) * nnz + j]))
-            return fail(DODE_ERR_NONFINITE, "values[%d] holds NaN or Inf", c);
+  for (int32_t c = 0; c < n_clusters; ++c) {
+    std::vector<char> bad(dm.K, 0);
+    host_parallel_for(dm.K, [&](int64_t l0, int64_t l1) {
+      for (int64_t l = l0; l < l1; ++l)
+        for (int32_t t = 0; t < std::min<int32_t>(dm.T, dm.H - (int32_t)l); ++t)
+          for (int64_t j = 0; j < nnz; ++j)
+            if (!std::isfinite(values[c][((int64_t)l * dm.T + t) * nnz + j])) bad[l] = 1;
+    });
+    for (char b : bad)
+      if (b) return fail(DODE_ERR_NONFINITE, "values[%d] holds NaN or Inf", c);
+  }
 
   // every early return frees what was allocated so far
   std::unique_ptr<dode_dar, dode_status (*)(dode_dar*)> d(new dode_dar(), dar_destroy);
@@ -656,19 +726,22 @@ dode_status dar_create_ex(const dode_dims* dims, int32_t n_clusters, const int32
   std::vector<uint8_t> hw(cstride * esz), hws(cstride_r * esz, 0), hwt(cstride_c * esz, 0);
   std::vector<uint16_t> hcorr(d->has_corr ? cstride : 0);
   std::vector<float> hs(storage == DODE_FP8_E4M3 ? (size_t)dm.K * dm.T * n_ptile : 0);
-  std::vector<double> tmax(n_ptile);
   for (int32_t c = 0; c < n_clusters; ++c) {
     const double* src = values[c];
     if (storage == DODE_FP8_E4M3) {
-      for (int64_t lt = 0; lt < (int64_t)dm.K * dm.T; ++lt) {
-        std::fill(tmax.begin(), tmax.end(), 0.0);
-        for (int64_t j = 0; j < nnz; ++j)
-          tmax[col_idx[j] >> 6] = std::max(tmax[col_idx[j] >> 6], std::fabs(src[lt * nnz + j]));
-        for (int32_t i = 0; i < n_ptile; ++i)
-          hs[lt * n_ptile + i] = tmax[i] > 0 ? static_cast<float>(tmax[i] / 448.0) : 1.0f;
-      }
+      host_parallel_for((int64_t)dm.K * dm.T, [&](int64_t b0, int64_t b1) {
+        std::vector<double> tmax(n_ptile);
+        for (int64_t lt = b0; lt < b1; ++lt) {
+          std::fill(tmax.begin(), tmax.end(), 0.0);
+          for (int64_t j = 0; j < nnz; ++j)
+            tmax[col_idx[j] >> 6] = std::max(tmax[col_idx[j] >> 6], std::fabs(src[lt * nnz + j]));
+          for (int32_t i = 0; i < n_ptile; ++i)
+            hs[lt * n_ptile + i] = tmax[i] > 0 ? static_cast<float>(tmax[i] / 448.0) : 1.0f;
+        }
+      });
     }
-    for (int64_t lt = 0; lt < (int64_t)dm.K * dm.T; ++lt)
+    host_parallel_for((int64_t)dm.K * dm.T, [&](int64_t b0, int64_t b1) {
+    for (int64_t lt = b0; lt < b1; ++lt)
       for (int64_t jj = 0; jj < nnz; ++jj) {
         const int64_t j = d->h_csc2csr[jj];
         const double v = src[lt * nnz + j];
@@ -709,6 +782,7 @@ dode_status dar_create_ex(const dode_dims* dims, int32_t n_clusters, const int32
           }
         }
       }
+    });
     HIP_TRY(hipMemcpy(static_cast<uint8_t*>(d->d_W) + c * cstride_r * esz, hws.data(),
                       cstride_r * esz, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(static_cast<uint8_t*>(d->d_WT) + c * cstride_c * esz, hwt.data(),
@@ -1173,6 +1247,7 @@ dode_status spgd_plan_destroy(dode_plan* plan) {
   (void)hipSetDevice(plan->device);
   if (plan->last_stream) (void)hipStreamSynchronize(plan->last_stream);
   for (void* p : {(void*)plan->d_perm, (void*)plan->d_pos, (void*)plan->d_touched,
+                  (void*)plan->d_kslot, (void*)plan->d_kdesc, (void*)plan->d_kcomp,
                   (void*)plan->d_dc, plan->d_R, (void*)plan->d_part, (void*)plan->d_groups,
                   (void*)plan->d_full,
                   plan->d_X, plan->d_Q, plan->d_A, (void*)plan->d_loss, (void*)plan->d_order})
@@ -1226,6 +1301,11 @@ dode_status spgd_plan_create(const dode_dar* dar, const int32_t* day_cluster, in
   HIP_TRY(up(&p->d_perm, hs.perm.data(), hs.perm.size() * 4));
   HIP_TRY(up(&p->d_pos, hs.pos.data(), hs.pos.size() * 4));
   HIP_TRY(up(&p->d_touched, hs.touched.data(), hs.touched.size() * 4));
+  p->kmt = hs.mt;
+  p->max_comp = hs.max_comp;
+  HIP_TRY(up(&p->d_kslot, hs.kslot.data(), hs.kslot.size() * 4));
+  HIP_TRY(up(&p->d_kdesc, hs.kdesc.data(), hs.kdesc.size() * 4));
+  HIP_TRY(up(&p->d_kcomp, hs.kcomp.data(), hs.kcomp.size() * 4));
   // plan day i = caller day order[i], days grouped by cluster
   std::vector<int32_t> order, dc_plan;
   p->cluster_days.assign(C, 0);
@@ -1248,8 +1328,12 @@ dode_status spgd_plan_create(const dode_dar* dar, const int32_t* day_cluster, in
   // 4.83 ms per epoch with 365 one-day clusters of 50 ODs and 200 links.
   // Refinement steps need the tiles.
   const int32_t max_days = *std::max_element(p->cluster_days.begin(), p->cluster_days.end());
-  p->use_mfma = dar->has_tiles && params->kernel_path == 0 &&
-                (max_days > kSparseDays || params->refine_steps > 0);
+  if (params->kernel_path == 2 && !dar->has_tiles)
+    return fail(DODE_ERR_UNSUPPORTED, "kernel_path 2 needs BF16 or FP8 storage (matrix-core tiles)");
+  p->use_mfma = dar->has_tiles &&
+                ((params->kernel_path == 0 && (max_days > kSparseDays || params->refine_steps > 0)) ||
+                 params->kernel_path == 2);
+  p->one_launch = p->use_mfma && params->kernel_path == 2;
   const size_t ss = state_size(dar);
   if (p->use_mfma) {
     const int64_t pb = blocked_row_blocks(dm.P), lb = blocked_row_blocks(dm.L);
@@ -1262,7 +1346,7 @@ dode_status spgd_plan_create(const dode_dar* dar, const int32_t* day_cluster, in
   if (p->refine_steps > 0) {
     if (!p->use_mfma || !dar->has_corr)
       return fail(DODE_ERR_UNSUPPORTED,
-                  "refine_steps needs FP8 storage with correction tiles and kernel_path 0");
+                  "refine_steps needs FP8 storage with correction tiles and kernel_path 0 or 2");
     // the whole row set as one minibatch: identity order, every departure
     // interval with every lag that stays inside the day
     std::vector<int32_t> full((size_t)2 * C * dm.H + (size_t)C * dm.T * (dm.K + 3), -1);

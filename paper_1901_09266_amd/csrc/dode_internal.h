@@ -3,8 +3,10 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/dode.h"
@@ -201,6 +203,25 @@ struct ChunkSched {
   int64_t touched_e;
 };
 
+// Component schedule of one minibatch for the one-launch minibatch kernel.
+// The minibatch's intervals of cluster c, sorted, split where two neighbours
+// are K or more apart, form its components: the departure intervals one
+// component reaches are a contiguous range that no other component reaches.
+//   slot[c][bh]          minibatch slots sorted by interval (-1 past the end)
+//   desc[c][mt][K+3]     reached-interval descriptors sorted by t (ChunkSched
+//                        format, -1 past the end)
+//   comp[c][max_comp][4] per component: first entry in slot, slot count,
+//                        first entry in desc, descriptor count (count 0 pads)
+struct CompSched {
+  const int32_t* perm;   // [C][H] the epoch's permutations
+  const int32_t* slot;
+  const int32_t* desc;
+  const int32_t* comp;
+  int32_t j0, bh, mt, max_comp;
+  const int32_t* epoch;  // device epoch counter (graph replays) or nullptr
+  int64_t perm_e, slot_e, desc_e, comp_e;
+};
+
 // Resolve the epoch of a chunk schedule read from device memory (kernel side).
 __device__ __forceinline__ ChunkSched resolve_epoch(ChunkSched cs) {
   if (cs.epoch) {
@@ -210,6 +231,17 @@ __device__ __forceinline__ ChunkSched resolve_epoch(ChunkSched cs) {
     cs.touched += e * cs.touched_e;
   }
   return cs;
+}
+
+__device__ __forceinline__ CompSched resolve_epoch(CompSched ks) {
+  if (ks.epoch) {
+    const int64_t e = *ks.epoch;
+    ks.perm += e * ks.perm_e;
+    ks.slot += e * ks.slot_e;
+    ks.desc += e * ks.desc_e;
+    ks.comp += e * ks.comp_e;
+  }
+  return ks;
 }
 
 // Groups of up to `tile` days of one cluster (tile/16 MFMA column tiles).
@@ -257,6 +289,11 @@ struct dode_plan {
   int32_t* d_perm = nullptr;      // [E][C][H]
   int32_t* d_pos = nullptr;       // [E][C][H]
   int32_t* d_touched = nullptr;   // [E][nch][C][mt][K+3] reached-interval descriptors
+  int32_t* d_kslot = nullptr;     // [E][nch][C][bh]  component schedule (CompSched)
+  int32_t* d_kdesc = nullptr;     // [E][nch][C][kmt][K+3]
+  int32_t* d_kcomp = nullptr;     // [E][nch][C][max_comp][4]
+  int32_t kmt = 0, max_comp = 0;
+  bool one_launch = false;        // matrix-core minibatches as one launch each
   int32_t* d_dc = nullptr;        // [D]
   void* d_R = nullptr;            // [bh][D][L] residual rows of the current minibatch
   double* d_part = nullptr;       // [D][H] loss partials
@@ -303,6 +340,19 @@ struct dode_plan {
     const int32_t* pos = d_full + (size_t)C * H;
     return ChunkSched{perm, pos, d_full + 2 * (size_t)C * H, 0, H, dar->dims.T, nullptr, 0, 0};
   }
+  // component schedule of minibatch j of epoch e (e < 0: the epoch held in
+  // d_epoch, for graph replays)
+  CompSched comps(int32_t e, int32_t j) const {
+    const int32_t H = dar->dims.H;
+    const size_t dw = desc_width(dar->dims.K);
+    const int64_t ps = (int64_t)C * H, ss = (int64_t)nch * C * bh;
+    const int64_t ds = (int64_t)nch * C * kmt * dw, cs = (int64_t)nch * C * max_comp * 4;
+    const int64_t ee = e < 0 ? 0 : e;
+    return CompSched{d_perm + ee * ps, d_kslot + ee * ss + (int64_t)j * C * bh,
+                     d_kdesc + ee * ds + (int64_t)j * C * kmt * dw,
+                     d_kcomp + ee * cs + (int64_t)j * C * max_comp * 4, j * bh, bh, kmt, max_comp,
+                     e < 0 ? d_epoch : nullptr, ps, ss, ds, cs};
+  }
   // minibatch j of the epoch held in d_epoch (for graph replays)
   ChunkSched chunk_dev(int32_t j) const {
     const int32_t H = dar->dims.H;
@@ -313,6 +363,26 @@ struct dode_plan {
 };
 
 bool is_f64(const dode_dar* d);
+
+// Host loop over [0, n) split into contiguous ranges on up to 16 threads;
+// f(begin, end) must only touch what its range owns.  Used by the host-side
+// conversion of the assignment values, whose iterations are independent.
+template <typename F>
+void host_parallel_for(int64_t n, F&& f) {
+  const int64_t hw = std::max<int64_t>(1, (int64_t)std::thread::hardware_concurrency());
+  const int64_t nt = std::min<int64_t>({hw, int64_t(16), std::max<int64_t>(1, n)});
+  if (nt <= 1) {
+    f(int64_t(0), n);
+    return;
+  }
+  std::vector<std::thread> th;
+  const int64_t per = (n + nt - 1) / nt;
+  for (int64_t i = 0; i < nt; ++i) {
+    const int64_t b = i * per, e = std::min(n, b + per);
+    if (b < e) th.emplace_back([&f, b, e] { f(b, e); });
+  }
+  for (auto& t : th) t.join();
+}
 
 // ---- plain kernels (plain_kernels.hip) ---------------------------------
 // All launchers return hipSuccess or the launch error.  `day_cluster` may be
@@ -391,6 +461,10 @@ hipError_t mfma_chunk_resid(const dode_dar* dar, const ChunkSched& cs, const Day
 hipError_t mfma_chunk_adj_step(const dode_dar* dar, const ChunkSched& cs, const DayGroups& dg,
                                const Layout& ly, const float* R, float* Q, float* A,
                                const StepArgs& st, bool corr, hipStream_t s);
+// one whole minibatch (forward, residual, adjoint, step) in one launch
+hipError_t mfma_minibatch(const dode_dar* dar, const CompSched& ks, const DayGroups& dg,
+                          const Layout& ly, const float* X, float* R, float* Q, float* A,
+                          const StepArgs& st, hipStream_t s);
 // host: tile layout (ranges, positions, device arrays), then each cluster's
 // entries from its pattern-form codes (CSR order, storage type) (tiles.hip)
 dode_status tiles_prepare(dode_dar* d, std::string& err);

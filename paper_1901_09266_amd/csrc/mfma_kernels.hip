@@ -137,21 +137,15 @@ __device__ __forceinline__ void store4(float* __restrict__ p, const f32x4& v, bo
 // are all issued before the first product, so a batch costs one memory round
 // trip.  Column n of tile u is day first+16u+n; past the group's end it reads
 // day `first` and its result is dropped.
+// One forward item: link tile i of minibatch slot s (interval h) for day
+// group g of cluster c, written to the residual rows R[.][s].
 template <int MODE, int NT>
-__global__ void __launch_bounds__(256)
-k_fwd_mfma(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, Layout ly,
-           const float* __restrict__ Q, const float* __restrict__ X, float* __restrict__ R) {
+__device__ __forceinline__ void fwd_item(const DevPat& pt, const DevTiles& tl, const DayGroups& dg,
+                                         const Layout& ly, int c, int s, int h, int g, int i,
+                                         const float* __restrict__ Q, const float* __restrict__ X,
+                                         float* __restrict__ R) {
   constexpr int kBatch = NT == 2 ? 3 : 8 / NT;
-  // the wave index is uniform: everything derived from it lives in scalar registers
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int n_items = dg.n * cs.bh * tl.nLT;
-  const int item = xcd_logical_block((n_items + 3) / 4) * 4 + wave;
-  if (item >= n_items) return;
-  int c, s, i;
-  const int g = decode_item(dg, item, cs.bh, tl.nLT, c, s, i);
-  if (cs.j0 + s >= pt.H) return;
-  cs = resolve_epoch(cs);
-  const int h = cs.perm[c * pt.H + cs.j0 + s];
+  const int lane = threadIdx.x & 63;
   const int n = lane & 15, kg = lane >> 4;
   const int first = dg.first[g], cnt = dg.count[g];
   const int a0 = 16 * i + 4 * kg;
@@ -234,6 +228,26 @@ k_fwd_mfma(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, Layout ly,
              acc[u] - x[u], full, valid);
 }
 
+// Forward product and residual of the minibatch rows, one wave per item
+// (cluster, slot s, day group g, link tile i) in the order of decode_item;
+// 4 items per block, blocks remapped so each XCD walks a contiguous range.
+template <int MODE, int NT>
+__global__ void __launch_bounds__(256)
+k_fwd_mfma(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, Layout ly,
+           const float* __restrict__ Q, const float* __restrict__ X, float* __restrict__ R) {
+  // the wave index is uniform: everything derived from it lives in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int n_items = dg.n * cs.bh * tl.nLT;
+  const int item = xcd_logical_block((n_items + 3) / 4) * 4 + wave;
+  if (item >= n_items) return;
+  int c, s, i;
+  const int g = decode_item(dg, item, cs.bh, tl.nLT, c, s, i);
+  if (cs.j0 + s >= pt.H) return;
+  cs = resolve_epoch(cs);
+  const int h = cs.perm[c * pt.H + cs.j0 + s];
+  fwd_item<MODE, NT>(pt, tl, dg, ly, c, s, h, g, i, Q, X, R);
+}
+
 __device__ __forceinline__ f32x4 step4(f32x4 q, f32x4& a, const f32x4& g, const StepArgs& st) {
   const float eta = static_cast<float>(st.eta), eps = static_cast<float>(st.eps);
 #pragma unroll
@@ -255,21 +269,16 @@ __device__ __forceinline__ f32x4 step4(f32x4 q, f32x4& a, const f32x4& g, const 
 // j) in the order of decode_item; same block remapping, batching and day
 // columns as the forward kernel.  The demand and accumulator rows are fetched
 // before the product.
+// One adjoint item: OD tile j of the reached departure interval described by
+// dsc, for day group g of cluster c, with the step and projection fused.
 template <int MODE, int NT>
-__global__ void __launch_bounds__(256)
-k_adj_mfma(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, Layout ly,
-           const float* __restrict__ R, float* __restrict__ Q, float* __restrict__ A, StepArgs st) {
+__device__ __forceinline__ void adj_item(const DevPat& pt, const DevTiles& tl, const DayGroups& dg,
+                                         const Layout& ly, int c, const int32_t* dsc, int g, int j,
+                                         const float* __restrict__ R, float* __restrict__ Q,
+                                         float* __restrict__ A, const StepArgs& st) {
   constexpr int kBatch = NT == 2 ? 3 : 8 / NT;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int n_items = dg.n * cs.max_touched * tl.nPT;
-  const int item = xcd_logical_block((n_items + 3) / 4) * 4 + wave;
-  if (item >= n_items) return;
-  int c, ti, j;
-  const int g = decode_item(dg, item, cs.max_touched, tl.nPT, c, ti, j);
-  cs = resolve_epoch(cs);
-  const int32_t* dsc = cs.touched + ((int64_t)c * cs.max_touched + ti) * desc_width(pt.K);
+  const int lane = threadIdx.x & 63;
   const int t = dsc[kDescT];
-  if (t < 0) return;
   // lags whose row block h = t + l is in this minibatch
   const uint64_t lmask = (uint64_t)(uint32_t)dsc[kDescMask] |
                          (uint64_t)(uint32_t)dsc[kDescMask + 1] << 32;
@@ -353,6 +362,67 @@ k_adj_mfma(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, Layout ly,
   }
 }
 
+// Adjoint of the minibatch and the fused Adagrad step + projection, one wave
+// per item (cluster, reached interval index ti, day group g, OD tile j) in the
+// order of decode_item; same block remapping as the forward kernel.
+template <int MODE, int NT>
+__global__ void __launch_bounds__(256)
+k_adj_mfma(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, Layout ly,
+           const float* __restrict__ R, float* __restrict__ Q, float* __restrict__ A, StepArgs st) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int n_items = dg.n * cs.max_touched * tl.nPT;
+  const int item = xcd_logical_block((n_items + 3) / 4) * 4 + wave;
+  if (item >= n_items) return;
+  int c, ti, j;
+  const int g = decode_item(dg, item, cs.max_touched, tl.nPT, c, ti, j);
+  cs = resolve_epoch(cs);
+  const int32_t* dsc = cs.touched + ((int64_t)c * cs.max_touched + ti) * desc_width(pt.K);
+  if (dsc[kDescT] < 0) return;
+  adj_item<MODE, NT>(pt, tl, dg, ly, c, dsc, g, j, R, Q, A, st);
+}
+
+// One whole minibatch in one launch, one workgroup per (cluster, component,
+// day group).  A component is a maximal run of the minibatch's intervals whose
+// reached departure intervals overlap (sorted intervals less than K apart); the
+// reached intervals of different components are disjoint, so components are
+// independent within the minibatch.  The workgroup's four waves first compute
+// the residual rows of the component's intervals (every link tile), wait at a
+// barrier, then run the adjoint and the step for every reached interval of the
+// component (every OD tile).  The residual rows travel through the L2 of the
+// workgroup's XCD, and the demand rows the forward product read are the rows
+// the step rewrites.  Each item does exactly the arithmetic of the separate
+// forward and adjoint kernels, so results are the same bits.
+template <int MODE, int NT>
+__global__ void __launch_bounds__(256)
+k_minibatch_mfma(DevPat pt, DevTiles tl, CompSched ks, DayGroups dg, Layout ly,
+                 const float* __restrict__ X, float* __restrict__ R, float* __restrict__ Q,
+                 float* __restrict__ A, StepArgs st) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int n_items = dg.n * ks.max_comp;
+  const int item = xcd_logical_block(n_items);
+  if (item >= n_items) return;   // uniform over the workgroup
+  int c, k, unused;
+  const int g = decode_item(dg, item, ks.max_comp, 1, c, k, unused);
+  ks = resolve_epoch(ks);
+  const int32_t* cp = ks.comp + ((int64_t)c * ks.max_comp + k) * 4;
+  const int h0 = cp[0], n_h = cp[1], d0 = cp[2], n_t = cp[3];
+  if (n_h == 0) return;          // padding entry, uniform over the workgroup
+  const int32_t* slots = ks.slot + (int64_t)c * ks.bh;
+  for (int task = wave; task < n_h * tl.nLT; task += 4) {
+    const int a = task / tl.nLT, i = task - a * tl.nLT;
+    const int s = slots[h0 + a];
+    const int h = ks.perm[c * pt.H + ks.j0 + s];
+    fwd_item<MODE, NT>(pt, tl, dg, ly, c, s, h, g, i, Q, X, R);
+  }
+  __syncthreads();
+  const int dw = desc_width(pt.K);
+  for (int task = wave; task < n_t * tl.nPT; task += 4) {
+    const int b = task / tl.nPT, j = task - b * tl.nPT;
+    const int32_t* dsc = ks.desc + ((int64_t)c * ks.mt + d0 + b) * dw;
+    adj_item<MODE, NT>(pt, tl, dg, ly, c, dsc, g, j, R, Q, A, st);
+  }
+}
+
 // Copy the pattern-form codes of one (cluster, l, t) block (link-sliced, just
 // rewritten by the quantisation kernel) into its packed tiles.
 template <typename E>
@@ -409,6 +479,25 @@ hipError_t launch_adj(const dode_dar* dar, const ChunkSched& cs, const DayGroups
   return hipGetLastError();
 }
 
+template <int MODE, int NT>
+hipError_t launch_minibatch(const dode_dar* dar, const CompSched& ks, const DayGroups& dg,
+                            const Layout& ly, const float* X, float* R, float* Q, float* A,
+                            const StepArgs& st, hipStream_t s) {
+  const int64_t nblk = (int64_t)dg.n * ks.max_comp;
+  const dim3 grid((unsigned)(((nblk + kXcds - 1) / kXcds) * kXcds));
+  hipLaunchKernelGGL((k_minibatch_mfma<MODE, NT>), grid, dim3(256), 0, s, dar->pat(), dar->tiles,
+                     ks, dg, ly, X, R, Q, A, st);
+  return hipGetLastError();
+}
+
+template <int NT>
+hipError_t minibatch_mode(const dode_dar* dar, const CompSched& ks, const DayGroups& dg,
+                          const Layout& ly, const float* X, float* R, float* Q, float* A,
+                          const StepArgs& st, hipStream_t s) {
+  if (dar->storage != DODE_FP8_E4M3) return launch_minibatch<kBF16, NT>(dar, ks, dg, ly, X, R, Q, A, st, s);
+  return launch_minibatch<kFP8, NT>(dar, ks, dg, ly, X, R, Q, A, st, s);
+}
+
 template <int NT>
 hipError_t fwd_mode(const dode_dar* dar, const ChunkSched& cs, const DayGroups& dg, const Layout& ly,
                     const float* Q, const float* X, float* R, bool corr, hipStream_t s) {
@@ -445,5 +534,15 @@ hipError_t mfma_chunk_adj_step(const dode_dar* dar, const ChunkSched& cs, const 
     case 16: return adj_mode<1>(dar, cs, dg, ly, R, Q, A, st, corr, s);
     case 64: return adj_mode<4>(dar, cs, dg, ly, R, Q, A, st, corr, s);
     default: return adj_mode<2>(dar, cs, dg, ly, R, Q, A, st, corr, s);
+  }
+}
+
+hipError_t mfma_minibatch(const dode_dar* dar, const CompSched& ks, const DayGroups& dg,
+                          const Layout& ly, const float* X, float* R, float* Q, float* A,
+                          const StepArgs& st, hipStream_t s) {
+  switch (dg.tile) {
+    case 16: return minibatch_mode<1>(dar, ks, dg, ly, X, R, Q, A, st, s);
+    case 64: return minibatch_mode<4>(dar, ks, dg, ly, X, R, Q, A, st, s);
+    default: return minibatch_mode<2>(dar, ks, dg, ly, X, R, Q, A, st, s);
   }
 }

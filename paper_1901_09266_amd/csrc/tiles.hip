@@ -161,15 +161,17 @@ dode_status fill_tiles(dode_dar* d, int32_t c, const E* codes_csr, void* F, void
   const int64_t blocks = (int64_t)dm.K * dm.T;
   const size_t fblk = (size_t)d->tiles.kf_total * 512, gblk = (size_t)d->tiles.kg_total * 512;
   std::vector<E> fbuf(blocks * fblk, E(0)), gbuf(blocks * gblk, E(0));
-  for (int64_t lt = 0; lt < blocks; ++lt) {
-    const int32_t l = (int32_t)(lt / dm.T), t = (int32_t)(lt % dm.T);
-    if (t + l >= dm.H) continue;   // block past the last interval: never read
-    const E* w = codes_csr + lt * nnz;
-    E* fb = fbuf.data() + lt * fblk;
-    E* gb = gbuf.data() + lt * gblk;
-    for (int64_t j = 0; j < nnz; ++j) fb[d->h_posf[j]] = w[j];
-    for (int64_t jj = 0; jj < nnz; ++jj) gb[d->h_posg[jj]] = w[d->h_csc2csr[jj]];
-  }
+  host_parallel_for(blocks, [&](int64_t b0, int64_t b1) {
+    for (int64_t lt = b0; lt < b1; ++lt) {
+      const int32_t l = (int32_t)(lt / dm.T), t = (int32_t)(lt % dm.T);
+      if (t + l >= dm.H) continue;   // block past the last interval: never read
+      const E* w = codes_csr + lt * nnz;
+      E* fb = fbuf.data() + lt * fblk;
+      E* gb = gbuf.data() + lt * gblk;
+      for (int64_t j = 0; j < nnz; ++j) fb[d->h_posf[j]] = w[j];
+      for (int64_t jj = 0; jj < nnz; ++jj) gb[d->h_posg[jj]] = w[d->h_csc2csr[jj]];
+    }
+  });
   hipError_t e = hipMemcpy(static_cast<E*>(F) + (size_t)c * blocks * fblk, fbuf.data(),
                            fbuf.size() * sizeof(E), hipMemcpyHostToDevice);
   if (e == hipSuccess)

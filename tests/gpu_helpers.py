@@ -88,3 +88,12 @@ def dequantized_values(inst, storage):
                     Wq[:, :, sel] = h + quantize_bf16(W[:, :, sel] - h)
             out.append(Wq)
     return out
+
+
+def rel_elem(a, b, floor_frac=1e-3):
+    """Largest elementwise |a - b| / max(|b|, floor), floor = floor_frac * max|b|:
+    every entry is held to its own size, down to a floor for entries near zero."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    floor = max(floor_frac * float(np.max(np.abs(b))), 1e-300)
+    return float(np.max(np.abs(a - b) / np.maximum(np.abs(b), floor)))

@@ -95,3 +95,23 @@ def test_traffic_lookup_follows_the_source_hash(monkeypatch, tmp_path):
     assert bench.counted_traffic(3, "fp8", "adj") is None
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "cd" * 32)
     assert bench.counted_traffic(3, "bf16", "adj") is None
+
+
+def test_epoch_bytes_is_the_touch_once_floor():
+    """The headline roofline's bytes per epoch: each cluster's ratio nonzeros
+    once (the lag band has sum_t min(K, H - t) blocks) plus, per day, X read
+    once, Q read and written at 2 bytes (bf16 copy) and A read and written in
+    FP32.  At 150 OD, 500 links, T = H = 288, K = 6, 8 clusters of 6000
+    nonzeros per block and 1095 days this is 1.362816 GB."""
+    inst = SimpleNamespace(P=150, L=500, T=288, H=288, K=6, nnz=6000, C=8, D=1095)
+    nblk = 6 * 288 - (1 + 2 + 3 + 4 + 5)
+    assert nblk == 1713
+    want = 8 * nblk * 6000 * 2 + 1095 * (288 * 500 * 4 + 2 * 288 * 150 * 2 + 2 * 288 * 150 * 4)
+    assert want == 1_362_816_000
+    assert bench.epoch_bytes(inst, "bf16") == want
+    # FP32 demand and the plain FP32 form count 4 bytes per demand value
+    q32 = want + 1095 * 2 * 288 * 150 * 2
+    assert bench.epoch_bytes(inst, "bf16", s_q=4) == q32
+    assert bench.epoch_bytes(inst, "f32") == q32 + 8 * nblk * 6000 * 2
+    # FP8 values: one byte per nonzero
+    assert bench.epoch_bytes(inst, "fp8") == want - 8 * nblk * 6000

@@ -110,7 +110,8 @@ def test_spgd_step_matches_oracle():
                 assert rel(Ad[d].cpu().numpy(), A) <= 1e-12
 
 
-def run_solve(inst, storage, E, batch_rows, eta, optimizer, perms, loss_hist=True, days=None):
+def run_solve(inst, storage, E, batch_rows, eta, optimizer, perms, loss_hist=True, days=None,
+              seed=0):
     dt = torch.float64 if storage == "f64" else torch.float32
     dar = make_dar(inst, storage)
     D = inst.D
@@ -118,9 +119,63 @@ def run_solve(inst, storage, E, batch_rows, eta, optimizer, perms, loss_hist=Tru
     Qd = torch.zeros((D, inst.T, inst.P), dtype=dt, device="cuda")
     Ad = torch.zeros_like(Qd)
     p = dode.make_params(epochs=E, batch_rows=batch_rows, eta=eta, optimizer=optimizer)
-    hist = dode.spgd_solve(dar, inst.day_cluster, Xd, Qd, Ad, p, perm=perms, loss_hist=loss_hist)
+    hist = dode.spgd_solve(dar, inst.day_cluster, Xd, Qd, Ad, p, perm=perms, seed=seed,
+                           loss_hist=loss_hist)
     torch.cuda.synchronize()
     return Qd.cpu().numpy().astype(np.float64), Ad.cpu().numpy().astype(np.float64), hist
+
+
+def splitmix64_perms(seed, E, C, H):
+    """The permutations the library draws when none are passed: one SplitMix64
+    stream (Steele, Lea and Flood, "Fast splittable pseudorandom number
+    generators", 2014) started at `seed`; for each (epoch, cluster) in order,
+    a Fisher-Yates shuffle of 0..H-1 from the top, element i swapping with
+    element (next draw mod (i + 1)) for i = H-1 down to 1."""
+    M = (1 << 64) - 1
+    s = seed & M
+    out = np.empty((E, C, H), dtype=np.int32)
+    for e in range(E):
+        for c in range(C):
+            p = list(range(H))
+            for i in range(H - 1, 0, -1):
+                s = (s + 0x9E3779B97F4A7C15) & M
+                z = ((s ^ (s >> 30)) * 0xBF58476D1CE4E5B9) & M
+                z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M
+                z ^= z >> 31
+                j = z % (i + 1)
+                p[i], p[j] = p[j], p[i]
+            out[e, c] = p
+    return out
+
+
+@pytest.mark.parametrize("storage", ["f64", "bf16"])
+def test_library_drawn_permutations(storage):
+    """perm = NULL: the library draws its permutations from the seed.  They
+    are the SplitMix64 + Fisher-Yates draw above (so valid permutations): the
+    solve equals the one given those permutations bit for bit, the same seed
+    repeats, another seed differs, and the FP64 run matches the oracle."""
+    inst = make_instance(P=20, L=40, T=24, K=4, sizes=(5, 3), inc=0.2, pattern="corridor",
+                         demand="gamma", noise="mult5", x_dtype="f64", seed=56)
+    say("library permutations", storage)
+    E, seed, rows = 6, 0x5EED1901, 200
+    perms = splitmix64_perms(seed, E, inst.C, inst.H)
+    for e in range(E):
+        for c in range(inst.C):
+            assert sorted(perms[e, c]) == list(range(inst.H))
+    drawn = run_solve(inst, storage, E, rows, 5.0, 0, None, seed=seed)
+    given = run_solve(inst, storage, E, rows, 5.0, 0, perms)
+    again = run_solve(inst, storage, E, rows, 5.0, 0, None, seed=seed)
+    other = run_solve(inst, storage, E, rows, 5.0, 0, None, seed=seed + 1)
+    for a, b in zip(drawn, given):
+        np.testing.assert_array_equal(a, b)
+    for a, b in zip(drawn, again):
+        np.testing.assert_array_equal(a, b)
+    assert not np.array_equal(drawn[0], other[0])
+    if storage == "f64":
+        bh = chunk_h_blocks(inst.L, inst.H, rows)
+        Qo, _, ho = orc.spgd(inst, inst.x, perms, E, bh, optimizer=0, eta=5.0)
+        assert rel(drawn[0], Qo) <= 1e-8
+        assert np.max(np.abs(drawn[2] - ho) / ho) <= 1e-9
 
 
 def test_solve_config1_fixed_step_f64():
@@ -200,8 +255,10 @@ def test_nonfinite_observations_rejected():
 
 
 MFMA_SHAPES = {
-    # 16-row tiles with ragged ends on both sides, a 1-day and a 33-day cluster
-    "ragged": dict(P=37, L=50, T=20, H=23, K=4, sizes=(1, 33, 17), inc=0.2, pattern="bernoulli"),
+    # 16-row tiles with ragged ends on both sides, a 3-day, a 33-day and a
+    # 17-day cluster (every cluster has more than 2 days, so each one-cluster
+    # minibatch runs on the matrix-core tiles)
+    "ragged": dict(P=37, L=50, T=20, H=23, K=4, sizes=(3, 33, 17), inc=0.2, pattern="bernoulli"),
     "corridor": dict(P=150, L=500, T=24, K=6, sizes=(40, 5), inc=0.08, pattern="corridor"),
     "wide": dict(P=70, L=9, T=10, K=3, sizes=(20,), inc=0.5, pattern="bernoulli"),
 }
@@ -429,3 +486,54 @@ def test_refinement_needs_correction_tiles():
     dar = make_dar(inst, "fp8", correction=True)
     with pytest.raises(dode.DodeError, match="correction"):
         dode.dar_set_values(dar, 0, torch.zeros((inst.K, inst.T, len(inst.col_idx)), device="cuda"))
+
+
+ONE_LAUNCH_SHAPES = {
+    # 40 intervals per minibatch: long components of neighbouring intervals
+    "long components": dict(P=50, L=200, T=288, K=6, sizes=(20, 3), inc=0.1, pattern="corridor"),
+    # H > T + K: the last intervals reach no departure interval
+    "H past T": dict(P=37, L=50, T=20, H=30, K=4, sizes=(3, 33, 17), inc=0.2, pattern="bernoulli"),
+    # one lag: every interval is its own component
+    "K=1": dict(P=24, L=40, T=30, K=1, sizes=(17,), inc=0.3, pattern="bernoulli"),
+    "corridor": dict(P=150, L=500, T=48, K=6, sizes=(40, 5), inc=0.08, pattern="corridor"),
+}
+
+
+@pytest.mark.parametrize("storage", ["bf16", "fp8"])
+@pytest.mark.parametrize("name", list(ONE_LAUNCH_SHAPES))
+def test_one_launch_minibatch_equals_two_launches(name, storage):
+    """kernel_path 2 runs each minibatch as one launch (forward, residual,
+    adjoint and step per component of the minibatch); kernel_path 0 runs the
+    forward and the adjoint as separate launches.  Same arithmetic per item:
+    the demand, the accumulator and the loss history agree bit for bit, for
+    every day tile, and the one-launch run matches the oracle on the same
+    rounded values."""
+    kw = dict(ONE_LAUNCH_SHAPES[name])
+    inst = make_instance(demand="gamma", noise="mult5", x_dtype="f32", seed=95, **kw)
+    say("one launch vs two", name, storage)
+    E = 5
+    perms = make_perms(96, E, inst.C, inst.H)
+    batch_rows = 8192 if inst.L >= 200 else 7 * inst.L
+    dar = make_dar(inst, storage)
+    X = dev(inst.x, torch.float32)
+    Q0 = torch.zeros((inst.D, inst.T, inst.P), dtype=torch.float32, device="cuda")
+    outs = {}
+    for path, tile in ((0, 32), (2, 32), (2, 16), (2, 64)):
+        p = dode.make_params(epochs=E, batch_rows=batch_rows, eta=5.0, kernel_path=path,
+                             day_tile=tile)
+        plan = dode.spgd_plan_create(dar, inst.day_cluster, p, perm=perms, stream=0)
+        dode.spgd_plan_load(plan, X, Q0)
+        loss = torch.zeros((E, inst.D), dtype=torch.float64, device="cuda")
+        dode.spgd_run(plan, 0, E, loss=loss)
+        Q = torch.empty_like(Q0)
+        A = torch.empty_like(Q0)
+        dode.spgd_plan_store(plan, Q, A)
+        torch.cuda.synchronize()
+        outs[(path, tile)] = (Q.cpu().numpy(), A.cpu().numpy(), loss.cpu().numpy())
+    for key in ((2, 32), (2, 16), (2, 64)):
+        for a, b in zip(outs[key], outs[(0, 32)]):
+            np.testing.assert_array_equal(a, b)
+    Wq = dequantized_values(inst, storage)
+    bh = chunk_h_blocks(inst.L, inst.H, batch_rows)
+    _, _, ho = orc.spgd(inst, inst.x.astype(np.float64), perms, E, bh, optimizer=0, eta=5.0, W=Wq)
+    assert np.max(np.abs(outs[(2, 32)][2].T - ho) / ho) <= 1e-3
