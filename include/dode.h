@@ -163,6 +163,20 @@ dode_status dode_apply(const dode_dar* dar, int32_t cluster, const void* Q, int3
 dode_status dode_loss(const dode_dar* dar, int32_t cluster, const void* Q, const void* X,
                       int32_t n_days, double* loss, void* stream);
 
+/*
+ * dode_loss for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, kernels and results (the same bits) as dode_loss; it calls no
+ * allocator.  Its per-row partials live in one fixed 4 MiB device array per
+ * GPU, so n_days * H * 8 bytes must fit in 4 MiB (1820 days at H = 288):
+ * larger calls return DODE_ERR_ARG before any launch.  The current device
+ * must be the dar's (DODE_ERR_ARG otherwise).  All calls on one GPU share that
+ * array: calls that overlap in time on one GPU (concurrent streams, or threads)
+ * race and may return wrong losses; serialise them, as one stream does.
+ */
+dode_status dode_loss_noalloc(const dode_dar* dar, int32_t cluster, const void* Q, const void* X,
+                              int32_t n_days, double* loss, void* stream);
+
 /* G = rho_c^T (rho_c Q - X), Algorithm 1's gradient (half the gradient of the
  * loss).  G dev [n][T][P], state type. */
 dode_status dode_grad(const dode_dar* dar, int32_t cluster, const void* Q, const void* X,

@@ -4,8 +4,8 @@ The computation lives in libdode.so (HIP kernels for gfx950 behind the C ABI of
 include/dode.h); this package is its Python binding.
 """
 from ._lib import (DodeError, Dar, SpgdParams, STORAGE, EXPORTS, lib, dar_create, dar_info,
-                   dar_set_values, dode_apply, dode_loss, dode_grad, dode_metrics, spgd_step,
-                   spgd_solve, spgd_defaults, make_params, Plan, spgd_plan_create, spgd_run,
+                   dar_set_values, dode_apply, dode_loss, dode_loss_noalloc, dode_grad,
+                   dode_metrics, spgd_step, spgd_solve, spgd_defaults, make_params, Plan, spgd_plan_create, spgd_run,
                    spgd_plan_load, spgd_plan_store,
                    spgd_plan_timing, spgd_plan_info, dode_loss_bwd, Routes, dode_routes_create,
                    dar_from_logits,
@@ -13,8 +13,8 @@ from ._lib import (DodeError, Dar, SpgdParams, STORAGE, EXPORTS, lib, dar_create
                    dense_spgd_run, dode_dar_costs_from_speeds)
 
 __all__ = ["DodeError", "Dar", "SpgdParams", "STORAGE", "EXPORTS", "lib", "dar_create", "dar_info",
-           "dar_set_values", "dode_apply", "dode_loss", "dode_grad", "dode_metrics", "spgd_step",
-           "spgd_solve", "spgd_defaults", "make_params", "Plan", "spgd_plan_create", "spgd_run",
+           "dar_set_values", "dode_apply", "dode_loss", "dode_loss_noalloc", "dode_grad",
+           "dode_metrics", "spgd_step", "spgd_solve", "spgd_defaults", "make_params", "Plan", "spgd_plan_create", "spgd_run",
            "spgd_plan_load", "spgd_plan_store",
            "spgd_plan_timing", "spgd_plan_info", "dode_loss_bwd", "Routes", "dode_routes_create",
            "dar_from_logits",

@@ -25,7 +25,8 @@ STORAGE = {"f64": DODE_F64, "f32": DODE_F32, "bf16": DODE_BF16, "fp8": DODE_FP8_
 # Every symbol include/dode.h declares (checked by the CPU test suite).
 EXPORTS = ["dode_last_error", "dode_spgd_defaults", "dar_create", "dar_create_ex", "dar_destroy",
            "dar_info",
-           "dar_set_values", "dode_apply", "dode_loss", "dode_grad", "dode_metrics", "spgd_step",
+           "dar_set_values", "dode_apply", "dode_loss", "dode_loss_noalloc", "dode_grad",
+           "dode_metrics", "spgd_step",
            "spgd_solve", "spgd_plan_create", "spgd_plan_destroy", "spgd_plan_load",
            "spgd_plan_store", "spgd_run", "spgd_plan_timing", "spgd_plan_info",
            "dode_loss_bwd", "dode_routes_create", "dode_routes_destroy", "dar_from_logits",
@@ -84,6 +85,7 @@ def lib():
         L.dar_set_values.argtypes = [vp, i32, vp, vp]
         L.dode_apply.argtypes = [vp, i32, vp, i32, vp, vp]
         L.dode_loss.argtypes = [vp, i32, vp, vp, i32, vp, vp]
+        L.dode_loss_noalloc.argtypes = [vp, i32, vp, vp, i32, vp, vp]
         L.dode_grad.argtypes = [vp, i32, vp, vp, i32, vp, vp]
         L.dode_metrics.argtypes = [vp, i32, vp, vp, i32, vp, vp, vp, vp]
         L.spgd_step.argtypes = [vp, i32, P(i32), i32, vp, vp, vp, i32, P(SpgdParams), vp]
@@ -235,6 +237,16 @@ def dode_loss(dar: Dar, cluster: int, Q, X, loss, stream=None):
     _check(lib().dode_loss(dar.handle, cluster, _ptr(Q, "Q", dar.state_dtype, (n, T, P)),
                            _ptr(X, "X", dar.state_dtype, (n, H, L)), n,
                            _ptr(loss, "loss", torch.float64, (n,)), _stream(stream)))
+
+
+def dode_loss_noalloc(dar: Dar, cluster: int, Q, X, loss, stream=None):
+    """dode_loss without any allocation (library scratch of 4 MiB per GPU)."""
+    import torch
+    P, L, T, H, K = dar.dims
+    n = Q.shape[0]
+    _check(lib().dode_loss_noalloc(dar.handle, cluster, _ptr(Q, "Q", dar.state_dtype, (n, T, P)),
+                                   _ptr(X, "X", dar.state_dtype, (n, H, L)), n,
+                                   _ptr(loss, "loss", torch.float64, (n,)), _stream(stream)))
 
 
 def dode_grad(dar: Dar, cluster: int, Q, X, G, stream=None):

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -512,6 +513,38 @@ dode_status tune_day_tile(dode_plan* plan, hipStream_t s) {
 
 }  // namespace
 
+// ---------------------------------------- scratch of dode_loss_noalloc --
+// The per-row loss partials of dode_loss_noalloc live in this fixed device
+// array instead of a per-call allocation.  Each GPU that runs the call holds
+// its own copy until the process ends; host code reaches it only through the
+// per-device address taken once with hipGetSymbolAddress.
+constexpr size_t kLossScratchBytes = size_t(4) << 20;   // 4 MiB per device
+static __device__ __align__(256) double scratch[kLossScratchBytes / sizeof(double)];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::vector<double*> g_scratch_ptr;   // device address of `scratch`, per device
+
+// Address of the current device's `scratch`, looked up on the first call on
+// that device.
+dode_status loss_scratch(int dev, double** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(DODE_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                  hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return DODE_OK;
+}
+
+}  // namespace
+
 // ================================================================== ABI ==
 extern "C" {
 
@@ -854,6 +887,33 @@ dode_status dode_loss(const dode_dar* dar, int32_t cluster, const void* Q, const
   HIP_TRY(plain_apply_rows(dar, nullptr, cluster, day_major(dar->dims), Q, X, nullptr,
                            part.as<double>(), n_days, s));
   HIP_TRY(sum_partials(part.as<double>(), dar->dims.H, n_days, loss, s));
+  return DODE_OK;
+}
+
+dode_status dode_loss_noalloc(const dode_dar* dar, int32_t cluster, const void* Q, const void* X,
+                              int32_t n_days, double* loss, void* stream) {
+  if (dode_status st = check_dar(dar, cluster)) return st;
+  if (dode_status st = check_days(n_days)) return st;
+  if (n_days == 0) return DODE_OK;
+  if (!Q || !X || !loss) return fail(DODE_ERR_ARG, "Q, X or loss is NULL");
+  const size_t need = (size_t)n_days * dar->dims.H * sizeof(double);
+  if (need > kLossScratchBytes)
+    return fail(DODE_ERR_ARG,
+                "n_days=%d needs %zu bytes of loss scratch, more than the %zu bytes "
+                "dode_loss_noalloc holds (at most %zu days with H=%d)",
+                n_days, need, kLossScratchBytes,
+                kLossScratchBytes / (sizeof(double) * (size_t)dar->dims.H), dar->dims.H);
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != dar->device)
+    return fail(DODE_ERR_ARG, "the current device %d is not the dar's device %d", dev, dar->device);
+  double* part = nullptr;
+  if (dode_status st = loss_scratch(dev, &part)) return st;
+  hipStream_t s = as_stream(stream);
+  // every partial [d][h] is written before it is read: nothing to clear
+  HIP_TRY(plain_apply_rows(dar, nullptr, cluster, day_major(dar->dims), Q, X, nullptr, part,
+                           n_days, s));
+  HIP_TRY(sum_partials(part, dar->dims.H, n_days, loss, s));
   return DODE_OK;
 }
 
