@@ -140,7 +140,8 @@ def run_form(dode, torch, inst, form, perms, E_total, warmup, steps, bh, refine=
     plan = dode.spgd_plan_create(dar, inst.day_cluster, params, perm=perms, stream=0)
     dode.spgd_plan_load(plan, X, Q, A, stream=0)
     torch.cuda.synchronize()
-    log(f"{form}: dar + plan ready in {time.time() - t0:.1f}s")
+    sched = dode.spgd_plan_schedule(plan)
+    log(f"{form}: dar + plan ready in {time.time() - t0:.1f}s, schedule {sched}")
     stream = torch.cuda.current_stream()
     dode.spgd_run(plan, 0, warmup, stream=stream)
     torch.cuda.synchronize()
@@ -172,6 +173,7 @@ def run_form(dode, torch, inst, form, perms, E_total, warmup, steps, bh, refine=
     kms, kn = dode.spgd_plan_timing(plan, False)
     torch.cuda.synchronize()
     return dict(dar=dar, plan=plan, X=X, Q=Q, A=A, ms=ms, wall=wall, kernel_ms=kms, kernel_n=kn,
+                schedule=sched,
                 timing_epochs=list(range(e2, e2 + steps)), ms_runs=ms_runs)
 
 
@@ -188,7 +190,7 @@ def solve_curve(dode, torch, inst, form, dar, perms_full, E, every, snap_epochs,
     Q = torch.zeros((inst.D, inst.T, inst.P), dtype=dt, device="cuda")
     A = torch.zeros_like(Q)
     p = dode.make_params(epochs=E, batch_rows=8192, eta=5.0, optimizer=0, refine_steps=refine,
-                         kernel_path=KERNEL_PATH.get(form, 0))
+                         kernel_path=KERNEL_PATH.get(form, 0), day_tile=0)
     plan = dode.spgd_plan_create(dar, inst.day_cluster, p, perm=perms_full, stream=0)
     dode.spgd_plan_load(plan, X, Q, A)
     del A
@@ -589,8 +591,9 @@ def spgd_leg(args, dode, torch, config, form, compare, refine, pattern=None, per
     rf = {f: (refine if f == "fp8" else 0) for f in forms}
     res = {}
     for f in forms:
+        # day_tile 0: the library times its schedule candidates at load
         r = run_form(dode, torch, inst, f, perms[:E_total], E_total, args.warmup, args.steps, bh,
-                     rf[f], day_tile=16 if per_day else 32, repeats=5 if f == form else 1)
+                     rf[f], day_tile=16 if per_day else 0, repeats=5 if f == form else 1)
         fb, ab = launch_bytes(inst, perms, bh, ESIZE[f], r["timing_epochs"], refine=rf[f])
         r["fwd_bytes"], r["adj_bytes"] = fb.sum(), ab.sum()
         res[f] = r
@@ -658,7 +661,8 @@ def spgd_leg(args, dode, torch, config, form, compare, refine, pattern=None, per
                          "note": "value and ms_per_step are the median of the five timed runs"}
     out["forms"] = {f: {"day_gradients_per_s": round(inst.D * args.steps / (r["ms"] / 1e3), 1),
                         "ms_per_step": round(r["ms"] / args.steps, 4),
-                        "kernel_ms_per_step": [round(x / args.steps, 4) for x in r["kernel_ms"][:2]]}
+                        "kernel_ms_per_step": [round(x / args.steps, 4) for x in r["kernel_ms"][:2]],
+                        "schedule": r["schedule"]}
                     for f, r in res.items()}
     if not check:
         return out

@@ -7,7 +7,7 @@ from ._lib import (DodeError, Dar, SpgdParams, STORAGE, EXPORTS, lib, dar_create
                    dar_set_values, dode_apply, dode_loss, dode_loss_noalloc, dode_grad,
                    dode_metrics, spgd_step, spgd_solve, spgd_defaults, make_params, Plan, spgd_plan_create, spgd_run,
                    spgd_plan_load, spgd_plan_store,
-                   spgd_plan_timing, spgd_plan_info, dode_loss_bwd, Routes, dode_routes_create,
+                   spgd_plan_timing, spgd_plan_info, spgd_plan_schedule, dode_loss_bwd, Routes, dode_routes_create,
                    dar_from_logits,
                    dar_logits_bwd, dode_dar_from_speeds, dode_path_costs, dar_from_costs,
                    dense_spgd_run, dode_dar_costs_from_speeds)
@@ -16,7 +16,7 @@ __all__ = ["DodeError", "Dar", "SpgdParams", "STORAGE", "EXPORTS", "lib", "dar_c
            "dar_set_values", "dode_apply", "dode_loss", "dode_loss_noalloc", "dode_grad",
            "dode_metrics", "spgd_step", "spgd_solve", "spgd_defaults", "make_params", "Plan", "spgd_plan_create", "spgd_run",
            "spgd_plan_load", "spgd_plan_store",
-           "spgd_plan_timing", "spgd_plan_info", "dode_loss_bwd", "Routes", "dode_routes_create",
+           "spgd_plan_timing", "spgd_plan_info", "spgd_plan_schedule", "dode_loss_bwd", "Routes", "dode_routes_create",
            "dar_from_logits",
            "dar_logits_bwd", "dode_dar_from_speeds", "dode_path_costs", "dar_from_costs",
            "dense_spgd_run", "dode_dar_costs_from_speeds"]

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -260,6 +261,8 @@ dode_status check_params(const dode_spgd_params* p) {
     return fail(DODE_ERR_ARG, "day_tile=%d (0 = tune, 16, 32 or 64)", p->day_tile);
   if (p->refine_steps < 0 || p->refine_steps > 16)
     return fail(DODE_ERR_ARG, "refine_steps=%d outside [0, 16]", p->refine_steps);
+  if (p->adj_order != 0 && p->adj_order != 1)
+    return fail(DODE_ERR_ARG, "adj_order=%d (0 or 1)", p->adj_order);
   return DODE_OK;
 }
 
@@ -469,45 +472,85 @@ dode_status set_day_groups(dode_plan* plan, int32_t tile) {
   return DODE_OK;
 }
 
-// Time the matrix-core minibatch kernels for each day tile on the loaded state
-// (the first minibatches of epoch 0, after one warm-up minibatch) and keep the
-// fastest.  The runs change the plan's Q and A: the caller reloads them.
-dode_status tune_day_tile(dode_plan* plan, hipStream_t s) {
+// Matrix-core schedule choices made in this process, keyed by what decides
+// the fastest candidate: shapes, minibatch, storage, cluster sizes and GPU.
+std::mutex g_tune_mu;
+std::map<std::string, std::pair<int32_t, int32_t>> g_tuned;   // key -> (day tile, adj order)
+
+std::string tune_key(const dode_plan* plan) {
+  const dode_dims& dm = plan->dar->dims;
+  hipDeviceProp_t prop{};
+  std::string arch = hipGetDeviceProperties(&prop, plan->device) == hipSuccess ? prop.gcnArchName : "?";
+  std::string k = arch + "|" + std::to_string(dm.P) + "," + std::to_string(dm.L) + "," +
+                  std::to_string(dm.T) + "," + std::to_string(dm.H) + "," + std::to_string(dm.K) +
+                  "|" + std::to_string(plan->bh) + "|" + std::to_string((int)plan->dar->storage) +
+                  "|" + std::to_string(plan->refine_steps) + "|";
+  for (int32_t n : plan->cluster_days) k += std::to_string(n) + ",";
+  return k;
+}
+
+// Choose the matrix-core schedule on the loaded state: every day tile
+// (16, 32, 64) with both adjoint item orders, each timed over the first
+// minibatches of epoch 0 after one warm-up minibatch, fastest kept and
+// remembered for the same key.  The runs change the plan's Q and A: the
+// caller reloads them.
+dode_status tune_schedule(dode_plan* plan, hipStream_t s) {
   static const int32_t kTiles[] = {16, 32, 64};
+  const std::string key = tune_key(plan);
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) {
+      plan->adj_order = it->second.second;
+      plan->n_timed = 0;
+      plan->tune_ms = 0.0;
+      return set_day_groups(plan, it->second.first);
+    }
+  }
   const int32_t n_mb = std::min<int32_t>(plan->nch, 4);
   const bool timing = plan->timing;
   plan->timing = false;
   hipEvent_t ev[2] = {nullptr, nullptr};
   dode_status st = DODE_OK;
   float best_ms = 0.f;
-  int32_t best = 32;
+  int32_t best = 32, best_order = 1, n = 0;
   for (int k = 0; k < 2 && st == DODE_OK; ++k)
     if (hipEventCreate(&ev[k]) != hipSuccess) st = fail(DODE_ERR_HIP, "hipEventCreate failed");
-  for (int32_t tile : kTiles) {
-    if (st != DODE_OK) break;
-    if ((st = set_day_groups(plan, tile)) != DODE_OK) break;
-    if ((st = run_minibatch(plan, 0, 0, s)) != DODE_OK) break;
-    hipError_t e = hipEventRecord(ev[0], s);
-    for (int32_t j = 0; j < n_mb && st == DODE_OK && e == hipSuccess; ++j)
-      st = run_minibatch(plan, 0, j, s);
-    if (st != DODE_OK) break;
-    if (e == hipSuccess) e = hipEventRecord(ev[1], s);
-    if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
-    float ms = 0.f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
-    if (e != hipSuccess) {
-      st = fail(DODE_ERR_HIP, "day-tile tuning: %s", hipGetErrorString(e));
-      break;
+  for (int32_t tile : kTiles)
+    for (int32_t order = 0; order < 2; ++order) {
+      if (st != DODE_OK) break;
+      if ((st = set_day_groups(plan, tile)) != DODE_OK) break;
+      plan->adj_order = order;
+      if ((st = run_minibatch(plan, 0, 0, s)) != DODE_OK) break;
+      hipError_t e = hipEventRecord(ev[0], s);
+      for (int32_t j = 0; j < n_mb && st == DODE_OK && e == hipSuccess; ++j)
+        st = run_minibatch(plan, 0, j, s);
+      if (st != DODE_OK) break;
+      if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+      if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+      if (e != hipSuccess) {
+        st = fail(DODE_ERR_HIP, "schedule tuning: %s", hipGetErrorString(e));
+        break;
+      }
+      if (n++ == 0 || ms < best_ms) {
+        best_ms = ms;
+        best = tile;
+        best_order = order;
+      }
     }
-    if (tile == kTiles[0] || ms < best_ms) {
-      best_ms = ms;
-      best = tile;
-    }
-  }
   for (hipEvent_t e : ev)
     if (e) (void)hipEventDestroy(e);
   plan->timing = timing;
   if (st != DODE_OK) return st;
+  plan->adj_order = best_order;
+  plan->n_timed = n;
+  plan->tune_ms = best_ms;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tuned[key] = {best, best_order};
+  }
   return set_day_groups(plan, best);
 }
 
@@ -562,6 +605,7 @@ void dode_spgd_defaults(dode_spgd_params* p) {
   p->use_graph = 1;
   p->day_tile = 32;
   p->refine_steps = 0;
+  p->adj_order = 1;
 }
 
 namespace {
@@ -1446,6 +1490,7 @@ dode_status spgd_plan_create(const dode_dar* dar, const int32_t* day_cluster, in
   HIP_TRY(fill_zero(is_f64(dar), p->d_A, nQ, s));
   HIP_TRY(hipStreamSynchronize(s));
   p->tune_day_tile = p->use_mfma && params->day_tile == 0;
+  p->adj_order = params->adj_order;
   p->use_graph = params->use_graph != 0;
   HIP_TRY(hipMalloc(&p->d_epoch, 16));
   HIP_TRY(set_counter(p->d_epoch, 0, s));
@@ -1478,7 +1523,7 @@ dode_status spgd_plan_load(dode_plan* plan, const void* X, const void* Q, const 
       HIP_TRY(fill_zero(f64, plan->d_A, dm.T * ly.q_t, s));
     if (pass == 1 || !plan->tune_day_tile) break;
     // tuning runs minibatches on the loaded state; the second pass reloads it
-    if (dode_status st = tune_day_tile(plan, s)) return st;
+    if (dode_status st = tune_schedule(plan, s)) return st;
     plan->tune_day_tile = false;
   }
   plan->last_stream = s;
@@ -1544,6 +1589,16 @@ dode_status spgd_plan_info(const dode_plan* plan, int32_t* day_tile, int32_t* n_
   if (n_minibatches) *n_minibatches = plan->nch;
   if (minibatch_intervals) *minibatch_intervals = plan->bh;
   if (n_day_groups) *n_day_groups = plan->use_mfma ? plan->n_groups : 0;
+  return DODE_OK;
+}
+
+dode_status spgd_plan_schedule(const dode_plan* plan, int32_t* day_tile, int32_t* adj_order,
+                               int32_t* n_timed, double* best_ms) {
+  if (!plan) return fail(DODE_ERR_ARG, "plan is NULL");
+  if (day_tile) *day_tile = plan->use_mfma ? plan->day_tile : 0;
+  if (adj_order) *adj_order = plan->use_mfma ? plan->adj_order : 0;
+  if (n_timed) *n_timed = plan->n_timed;
+  if (best_ms) *best_ms = plan->tune_ms;
   return DODE_OK;
 }
 

@@ -373,8 +373,11 @@ k_adj_mfma(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, Layout ly,
   const int n_items = dg.n * cs.max_touched * tl.nPT;
   const int item = xcd_logical_block((n_items + 3) / 4) * 4 + wave;
   if (item >= n_items) return;
-  int c, ti, j;
-  const int g = decode_item(dg, item, cs.max_touched, tl.nPT, c, ti, j);
+  int c, ti, j, g;
+  if (cs.order == 1)
+    g = decode_item(dg, item, tl.nPT, cs.max_touched, c, j, ti);
+  else
+    g = decode_item(dg, item, cs.max_touched, tl.nPT, c, ti, j);
   cs = resolve_epoch(cs);
   const int32_t* dsc = cs.touched + ((int64_t)c * cs.max_touched + ti) * desc_width(pt.K);
   if (dsc[kDescT] < 0) return;

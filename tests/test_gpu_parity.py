@@ -397,12 +397,16 @@ def test_day_tile_gives_identical_results(storage):
     X = dev(inst.x, torch.float32)
     Q0 = torch.zeros((inst.D, inst.T, inst.P), dtype=torch.float32, device="cuda")
     outs = {}
-    for tile in (16, 32, 64, 0):
-        p = dode.make_params(epochs=E, batch_rows=batch_rows, eta=5.0, day_tile=tile)
+    for tile, order in ((16, 1), (32, 1), (64, 1), (16, 0), (32, 0), (64, 0), (0, 1)):
+        p = dode.make_params(epochs=E, batch_rows=batch_rows, eta=5.0, day_tile=tile,
+                             adj_order=order)
         plan = dode.spgd_plan_create(dar, inst.day_cluster, p, perm=perms, stream=0)
         dode.spgd_plan_load(plan, X, Q0)
         info = dode.spgd_plan_info(plan)
+        sch = dode.spgd_plan_schedule(plan)
         assert info["day_tile"] == tile if tile else info["day_tile"] in (16, 32, 64)
+        assert sch["day_tile"] == info["day_tile"]
+        assert sch["adj_order"] == order if tile else sch["adj_order"] in (0, 1)
         groups = sum(-(-n // info["day_tile"]) for n in (70, 33, 1))
         assert info["n_day_groups"] == groups and info["minibatch_intervals"] == 6
         loss = torch.zeros((E, inst.D), dtype=torch.float64, device="cuda")
@@ -411,14 +415,38 @@ def test_day_tile_gives_identical_results(storage):
         A = torch.empty_like(Q0)
         dode.spgd_plan_store(plan, Q, A)
         torch.cuda.synchronize()
-        outs[tile] = (Q.cpu().numpy(), A.cpu().numpy(), loss.cpu().numpy())
-    for tile in (16, 64, 0):
-        for a, b in zip(outs[tile], outs[32]):
+        outs[(tile, order)] = (Q.cpu().numpy(), A.cpu().numpy(), loss.cpu().numpy())
+    for key in outs:
+        for a, b in zip(outs[key], outs[(32, 1)]):
             np.testing.assert_array_equal(a, b)
     Wq = dequantized_values(inst, storage)
     bh = chunk_h_blocks(inst.L, inst.H, batch_rows)
     _, _, ho = orc.spgd(inst, inst.x.astype(np.float64), perms, E, bh, optimizer=0, eta=5.0, W=Wq)
-    assert np.max(np.abs(outs[64][2].T - ho) / ho) <= 1e-3
+    assert np.max(np.abs(outs[(64, 1)][2].T - ho) / ho) <= 1e-3
+
+
+def test_schedule_tuner_times_every_candidate_and_remembers():
+    """day_tile 0: the first plan of a shape times the 6 schedule candidates
+    (3 day tiles x 2 adjoint orders) and keeps the fastest; a second plan of the
+    same shapes, storage and cluster sizes reuses that choice without timing;
+    another storage type is a new key."""
+    inst = make_instance(P=41, L=66, T=30, K=4, sizes=(50, 20), inc=0.15, pattern="corridor",
+                         demand="gamma", noise="mult5", x_dtype="f32", seed=64)
+    say("schedule tuner")
+    perms = make_perms(65, 4, inst.C, inst.H)
+    X = dev(inst.x, torch.float32)
+    Q0 = torch.zeros((inst.D, inst.T, inst.P), dtype=torch.float32, device="cuda")
+    seen = []
+    for storage in ("bf16", "bf16", "fp8"):
+        dar = make_dar(inst, storage)
+        p = dode.make_params(epochs=4, batch_rows=5 * inst.L, eta=5.0, day_tile=0)
+        plan = dode.spgd_plan_create(dar, inst.day_cluster, p, perm=perms, stream=0)
+        dode.spgd_plan_load(plan, X, Q0)
+        seen.append(dode.spgd_plan_schedule(plan))
+    assert seen[0]["n_timed"] == 6 and seen[0]["best_ms"] > 0
+    assert seen[1]["n_timed"] == 0
+    assert (seen[1]["day_tile"], seen[1]["adj_order"]) == (seen[0]["day_tile"], seen[0]["adj_order"])
+    assert seen[2]["n_timed"] == 6
 
 
 def test_day_tile_rejected():
