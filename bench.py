@@ -553,6 +553,44 @@ def dense_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def schedule_sweep(args, dode, torch, config, form):
+    """Epoch time of every matrix-core schedule candidate (day tile x adjoint
+    item order x day slabs) on one workload, each from its own plan (the
+    record behind the load-time tuner's choice)."""
+    from synth import make_config, make_perms
+    inst = make_config(config)
+    E = args.warmup + args.steps
+    perms = make_perms(inst.seed + 1, E, inst.C, inst.H)
+    refine = 2 if (config == 5 and form == "fp8") else 0
+    dar = dode.dar_create(inst.P, inst.L, inst.T, inst.H, inst.K, inst.row_ptr, inst.col_idx, inst.W,
+                          storage=STORAGE[form], correction=refine > 0, stream=0)
+    X = torch.as_tensor(inst.x).to(device="cuda", dtype=torch.float32).contiguous()
+    Q = torch.zeros((inst.D, inst.T, inst.P), dtype=torch.float32, device="cuda")
+    rows = []
+    for tile in (16, 32, 64):
+        for order in (0, 1):
+            for slabs in (1, 2, 4):
+                p = dode.make_params(epochs=E, batch_rows=8192, eta=5.0, refine_steps=refine,
+                                     day_tile=tile, adj_order=order, slabs=slabs)
+                plan = dode.spgd_plan_create(dar, inst.day_cluster, p, perm=perms, stream=0)
+                dode.spgd_plan_load(plan, X, Q)
+                dode.spgd_run(plan, 0, args.warmup)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                torch.cuda.synchronize()
+                e0.record()
+                dode.spgd_run(plan, args.warmup, args.steps)
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / args.steps
+                rows.append({"day_tile": tile, "adj_order": order, "slabs": slabs,
+                             "ms_per_epoch": round(ms, 4)})
+                log(f"sweep: tile {tile} order {order} slabs {slabs}: {ms:.4f} ms")
+                plan.close()
+    best = min(rows, key=lambda r: r["ms_per_epoch"])
+    print(json.dumps({"metric": "schedule sweep (ms per epoch)", "config": config, "form": form,
+                      "refine_steps": refine, "rows": rows, "best": best}), flush=True)
+
+
 def epoch_bytes(inst, form, s_q=None):
     """Algorithmic bytes of one epoch over all days, touched once: each
     cluster's ratio nonzeros read once, every day's observations read once, its
@@ -756,6 +794,8 @@ def main():
                          "bernoulli = every (link, OD) pair independently, the stress case")
     ap.add_argument("--per-day", action="store_true",
                     help="give every day its own ratio matrix (one cluster per day)")
+    ap.add_argument("--sweep-schedules", action="store_true",
+                    help="time every matrix-core schedule candidate of the workload instead")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 512 MiB device copy first (reference for traffic counters)")
     args = ap.parse_args()
@@ -784,6 +824,9 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    if args.sweep_schedules:
+        schedule_sweep(args, dode, torch, args.config, args.form)
+        return
     if args.refine is None:
         args.refine = 2 if (args.config == 5 and args.form == "fp8") else 0
     leg = spgd_leg(args, dode, torch, args.config, args.form, args.compare, args.refine,

@@ -92,7 +92,8 @@ typedef struct {
   int32_t day_tile;    /* days of one cluster handled together by a matrix-core
                           wave (the GEMM N dimension): 16, 32 or 64; 0 = let
                           spgd_plan_load choose the matrix-core schedule (day
-                          tile and adjoint order) by timing every candidate,
+                          tile, adjoint order, day slabs) by timing an epoch of
+                          every candidate,
                           or reuse the choice made earlier in this process for
                           the same shapes, storage and GPU (results are the
                           same bits for every choice) */
@@ -105,6 +106,11 @@ typedef struct {
                           day_tile != 0: 0 = by reached interval, OD tiles
                           fastest; 1 = by OD tile, reached intervals fastest
                           (neighbouring waves share residual rows); same bits */
+  int32_t slabs;       /* day slabs of a matrix-core epoch when day_tile != 0:
+                          the epoch runs every minibatch on the first slab of
+                          about D/slabs days, then on the next, so a slab's
+                          demand and accumulator rows can stay in the last-level
+                          cache; 0 or 1 = all days together; same bits */
 } dode_spgd_params;
 
 /* Message of the last failing call on this thread ("" if none). */
@@ -112,7 +118,8 @@ const char* dode_last_error(void);
 
 /* Fill p with the defaults: epochs 300, batch_rows 8192, eta 5, eps 1e-10,
  * Adagrad, check_finite 1, kernel_path 0, use_graph 1, day_tile 32,
- * refine_steps 0, adj_order 1 (section "Goodness of fit" gives E, b and eta). */
+ * refine_steps 0, adj_order 1, slabs 1 (section "Goodness of fit" gives E, b
+ * and eta). */
 void dode_spgd_defaults(dode_spgd_params* p);
 
 /*
@@ -448,14 +455,15 @@ dode_status spgd_plan_timing(dode_plan* plan, int32_t enable, double* ms, int64_
 dode_status spgd_plan_info(const dode_plan* plan, int32_t* day_tile, int32_t* n_minibatches,
                            int32_t* minibatch_intervals, int32_t* n_day_groups);
 
-/* Matrix-core schedule of a plan (any pointer may be NULL): the day tile and
- * adjoint item order in use, the number of candidates timed at load (0 when
+/* Matrix-core schedule of a plan (any pointer may be NULL): the day tile,
+ * adjoint item order and day slabs in use, the number of candidates timed at
+ * load (0 when
  * given by the caller, or taken from this process's earlier choice for the
  * same P, L, T, H, K, b_h, storage, cluster sizes and GPU architecture), and
  * the time in milliseconds of the chosen candidate's trial minibatches (0 if
  * none ran).  A sparse-kernel plan reports day tile 0. */
 dode_status spgd_plan_schedule(const dode_plan* plan, int32_t* day_tile, int32_t* adj_order,
-                               int32_t* n_timed, double* best_ms);
+                               int32_t* n_slabs, int32_t* n_timed, double* best_ms);
 
 #ifdef __cplusplus
 }

@@ -52,7 +52,8 @@ class SpgdParams(ctypes.Structure):
                 ("eps", ctypes.c_double), ("optimizer", ctypes.c_int32),
                 ("check_finite", ctypes.c_int32), ("kernel_path", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("day_tile", ctypes.c_int32),
-                ("refine_steps", ctypes.c_int32), ("adj_order", ctypes.c_int32)]
+                ("refine_steps", ctypes.c_int32), ("adj_order", ctypes.c_int32),
+                ("slabs", ctypes.c_int32)]
 
 
 _lib = None
@@ -100,7 +101,7 @@ def lib():
         L.spgd_plan_store.argtypes = [vp, vp, vp, vp]
         L.spgd_plan_timing.argtypes = [vp, i32, P(dbl), P(i64)]
         L.spgd_plan_info.argtypes = [vp, P(i32), P(i32), P(i32), P(i32)]
-        L.spgd_plan_schedule.argtypes = [vp, P(i32), P(i32), P(i32), P(dbl)]
+        L.spgd_plan_schedule.argtypes = [vp, P(i32), P(i32), P(i32), P(i32), P(dbl)]
         L.dode_loss_bwd.argtypes = [vp, i32, vp, vp, i32, dbl, vp, vp, vp]
         L.dode_routes_create.argtypes = [P(Dims), i64, i32, P(i32), P(i32), P(i32), P(i32), vp, P(vp)]
         L.dode_routes_destroy.argtypes = [vp]
@@ -149,16 +150,17 @@ def spgd_defaults() -> SpgdParams:
 
 
 def make_params(epochs=300, batch_rows=8192, eta=5.0, eps=1e-10, optimizer=0, check_finite=1,
-                kernel_path=0, use_graph=1, day_tile=32, refine_steps=0, adj_order=1):
+                kernel_path=0, use_graph=1, day_tile=32, refine_steps=0, adj_order=1, slabs=1):
     """kernel_path 0 = fastest for the storage type, 1 = sparse pattern kernels,
     2 = matrix-core tiles with one launch per minibatch; use_graph 1 = replay
     one captured hipGraph per epoch; day_tile = days per matrix-core wave (16,
     32 or 64, or 0 to choose the schedule by timing at load); refine_steps =
     full-batch steps per epoch on corrected FP8 values; adj_order = item order
-    of the matrix-core adjoint (0 or 1) when day_tile is given."""
+    of the matrix-core adjoint (0 or 1) and slabs = day slabs per epoch when
+    day_tile is given."""
     return SpgdParams(int(epochs), int(batch_rows), float(eta), float(eps), int(optimizer),
                       int(check_finite), int(kernel_path), int(use_graph), int(day_tile),
-                      int(refine_steps), int(adj_order))
+                      int(refine_steps), int(adj_order), int(slabs))
 
 
 class Dar:
@@ -378,12 +380,13 @@ def spgd_plan_info(plan: Plan) -> dict:
 
 
 def spgd_plan_schedule(plan: Plan) -> dict:
-    """Matrix-core schedule in use: day tile, adjoint item order, candidates
-    timed at load and the chosen candidate's trial time (ms)."""
-    v = [ctypes.c_int32() for _ in range(3)]
+    """Matrix-core schedule in use: day tile, adjoint item order, day slabs,
+    candidates timed at load and the chosen candidate's epoch time (ms)."""
+    v = [ctypes.c_int32() for _ in range(4)]
     ms = ctypes.c_double()
     _check(lib().spgd_plan_schedule(plan.handle, *[ctypes.byref(x) for x in v], ctypes.byref(ms)))
-    return dict(day_tile=v[0].value, adj_order=v[1].value, n_timed=v[2].value, best_ms=ms.value)
+    return dict(day_tile=v[0].value, adj_order=v[1].value, slabs=v[2].value, n_timed=v[3].value,
+                best_ms=ms.value)
 
 
 def spgd_plan_timing(plan: Plan, enable: bool):

@@ -263,6 +263,8 @@ dode_status check_params(const dode_spgd_params* p) {
     return fail(DODE_ERR_ARG, "refine_steps=%d outside [0, 16]", p->refine_steps);
   if (p->adj_order != 0 && p->adj_order != 1)
     return fail(DODE_ERR_ARG, "adj_order=%d (0 or 1)", p->adj_order);
+  if (p->slabs < 0 || p->slabs > 64)
+    return fail(DODE_ERR_ARG, "slabs=%d outside [0, 64]", p->slabs);
   return DODE_OK;
 }
 
@@ -364,11 +366,11 @@ namespace {
 // Minibatch j of epoch e on the plan's state: forward + residual, then
 // adjoint + step + projection.
 dode_status run_chunk(dode_plan* plan, const ChunkSched& cs, const CompSched* ks, hipStream_t s,
-                      bool corr = false) {
+                      bool corr = false, int32_t slab = -1) {
   const dode_dar* dar = plan->dar;
   const Layout& ly = plan->ly;
   if (plan->use_mfma) {
-    const DayGroups dg = plan->groups();
+    const DayGroups dg = plan->slab_groups(slab);
     float* R = static_cast<float*>(plan->d_R);
     float* Q = static_cast<float*>(plan->d_Q);
     float* A = static_cast<float*>(plan->d_A);
@@ -394,9 +396,9 @@ dode_status run_chunk(dode_plan* plan, const ChunkSched& cs, const CompSched* ks
   return DODE_OK;
 }
 
-dode_status run_minibatch(dode_plan* plan, int32_t e, int32_t j, hipStream_t s) {
+dode_status run_minibatch(dode_plan* plan, int32_t e, int32_t j, hipStream_t s, int32_t slab = -1) {
   const CompSched ks = plan->comps(e, j);
-  return run_chunk(plan, plan->chunk(e, j), &ks, s);
+  return run_chunk(plan, plan->chunk(e, j), &ks, s, false, slab);
 }
 
 // The refinement steps that end every epoch: full-batch steps on the
@@ -407,6 +409,19 @@ dode_status run_refinement(dode_plan* plan, hipStream_t s) {
   return DODE_OK;
 }
 
+// Every minibatch of epoch e (e < 0: the epoch in the device counter, for
+// graph capture), slab by slab, then the refinement steps.
+dode_status run_epoch(dode_plan* plan, int32_t e, hipStream_t s) {
+  const int32_t ns = plan->use_mfma ? plan->n_slabs : 1;
+  for (int32_t k = 0; k < ns; ++k)
+    for (int32_t j = 0; j < plan->nch; ++j) {
+      const CompSched ks = plan->comps(e, j);
+      const ChunkSched cs = e < 0 ? plan->chunk_dev(j) : plan->chunk(e, j);
+      if (dode_status st = run_chunk(plan, cs, &ks, s, false, ns > 1 ? k : -1)) return st;
+    }
+  return run_refinement(plan, s);
+}
+
 // Capture one epoch (every minibatch, then the epoch-counter increment) into a
 // graph on the plan's own stream; replays read the epoch from d_epoch.
 dode_status build_epoch_graph(dode_plan* plan) {
@@ -415,12 +430,7 @@ dode_status build_epoch_graph(dode_plan* plan) {
     HIP_TRY(hipStreamCreateWithFlags(&plan->capture_stream, hipStreamNonBlocking));
   hipStream_t cs = plan->capture_stream;
   HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-  dode_status st = DODE_OK;
-  for (int32_t j = 0; j < plan->nch && st == DODE_OK; ++j) {
-    const CompSched ks = plan->comps(-1, j);
-    st = run_chunk(plan, plan->chunk_dev(j), &ks, cs);
-  }
-  if (st == DODE_OK) st = run_refinement(plan, cs);
+  dode_status st = run_epoch(plan, -1, cs);
   hipError_t e = st == DODE_OK ? bump_counter(plan->d_epoch, cs) : hipSuccess;
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(cs, &g);
@@ -440,6 +450,60 @@ void drop_epoch_graph(dode_plan* plan) {
   if (plan->graph) (void)hipGraphDestroy(plan->graph);
   plan->graph_exec = nullptr;
   plan->graph = nullptr;
+}
+
+// Split the day groups, in order, into n contiguous slabs of about D/n days
+// each (a cluster may be split), each slab with its own group list.  Drops a
+// captured epoch graph.
+dode_status set_slabs(dode_plan* plan, int32_t n) {
+  const int32_t G = (int32_t)plan->h_gc.size();
+  n = std::max<int32_t>(1, std::min<int32_t>(n, G));
+  drop_epoch_graph(plan);
+  if (plan->d_slabs) HIP_TRY(hipFree(plan->d_slabs));
+  plan->d_slabs = nullptr;
+  plan->slab_off.clear();
+  plan->slab_n.clear();
+  plan->n_slabs = n;
+  if (n == 1) return DODE_OK;
+  std::vector<int32_t> buf;
+  int64_t days = 0;
+  int32_t g = 0;
+  for (int32_t k = 0; k < n; ++k) {
+    // groups up to the (k+1)-th share of the days; every slab gets at least
+    // one group, the last slab all that remain
+    const int64_t target = (int64_t)plan->D * (k + 1) / n;
+    const int32_t a = g;
+    while (g < G) {
+      const bool take = k == n - 1 || g == a ||
+                        (days + plan->h_gn[g] <= target && G - (g + 1) >= n - k - 1);
+      if (!take) break;
+      days += plan->h_gn[g];
+      ++g;
+    }
+    const int32_t m = g - a;
+    std::vector<int32_t> cl(m), fi(m), co(m), cb(m), cg(m);
+    for (int32_t i = 0; i < m; ++i) {
+      cl[i] = plan->h_gc[a + i];
+      fi[i] = plan->h_gf[a + i];
+      co[i] = plan->h_gn[a + i];
+    }
+    // cluster runs inside the slab: first group and group count of each run
+    for (int32_t r0 = 0; r0 < m;) {
+      int32_t r1 = r0 + 1;
+      while (r1 < m && cl[r1] == cl[r0]) ++r1;
+      for (int32_t i = r0; i < r1; ++i) {
+        cb[i] = r0;
+        cg[i] = r1 - r0;
+      }
+      r0 = r1;
+    }
+    plan->slab_off.push_back((int64_t)buf.size());
+    plan->slab_n.push_back(m);
+    for (const auto* v : {&cl, &fi, &co, &cb, &cg}) buf.insert(buf.end(), v->begin(), v->end());
+  }
+  HIP_TRY(hipMalloc(&plan->d_slabs, std::max<size_t>(buf.size() * 4, 16)));
+  HIP_TRY(hipMemcpy(plan->d_slabs, buf.data(), buf.size() * 4, hipMemcpyHostToDevice));
+  return DODE_OK;
 }
 
 // Day groups of `tile` days: each cluster's plan days, in order, cut into
@@ -469,13 +533,19 @@ dode_status set_day_groups(dode_plan* plan, int32_t tile) {
   HIP_TRY(hipMemcpy(plan->d_groups, buf.data(), buf.size() * 4, hipMemcpyHostToDevice));
   plan->n_groups = (int32_t)gc.size();
   plan->day_tile = tile;
-  return DODE_OK;
+  plan->h_gc = gc;
+  plan->h_gf = gf;
+  plan->h_gn = gn;
+  return set_slabs(plan, plan->n_slabs);
 }
 
 // Matrix-core schedule choices made in this process, keyed by what decides
 // the fastest candidate: shapes, minibatch, storage, cluster sizes and GPU.
 std::mutex g_tune_mu;
-std::map<std::string, std::pair<int32_t, int32_t>> g_tuned;   // key -> (day tile, adj order)
+struct TunedSchedule {
+  int32_t day_tile, adj_order, n_slabs;
+};
+std::map<std::string, TunedSchedule> g_tuned;
 
 std::string tune_key(const dode_plan* plan) {
   const dode_dims& dm = plan->dar->dims;
@@ -490,68 +560,72 @@ std::string tune_key(const dode_plan* plan) {
 }
 
 // Choose the matrix-core schedule on the loaded state: every day tile
-// (16, 32, 64) with both adjoint item orders, each timed over the first
-// minibatches of epoch 0 after one warm-up minibatch, fastest kept and
-// remembered for the same key.  The runs change the plan's Q and A: the
-// caller reloads them.
+// (16, 32, 64) with both adjoint item orders and 1, 2 or 4 day slabs, each
+// timed over one whole epoch (epoch 0) after one warm-up minibatch, fastest
+// kept and remembered for the same key.  The runs change the plan's Q and A:
+// the caller reloads them.
 dode_status tune_schedule(dode_plan* plan, hipStream_t s) {
   static const int32_t kTiles[] = {16, 32, 64};
+  static const int32_t kSlabs[] = {1, 2, 4};
   const std::string key = tune_key(plan);
   {
     std::lock_guard<std::mutex> lock(g_tune_mu);
     auto it = g_tuned.find(key);
     if (it != g_tuned.end()) {
-      plan->adj_order = it->second.second;
+      plan->adj_order = it->second.adj_order;
+      plan->n_slabs = it->second.n_slabs;
       plan->n_timed = 0;
       plan->tune_ms = 0.0;
-      return set_day_groups(plan, it->second.first);
+      return set_day_groups(plan, it->second.day_tile);
     }
   }
-  const int32_t n_mb = std::min<int32_t>(plan->nch, 4);
   const bool timing = plan->timing;
   plan->timing = false;
   hipEvent_t ev[2] = {nullptr, nullptr};
   dode_status st = DODE_OK;
   float best_ms = 0.f;
-  int32_t best = 32, best_order = 1, n = 0;
+  TunedSchedule best{32, 1, 1};
+  int32_t n = 0;
   for (int k = 0; k < 2 && st == DODE_OK; ++k)
     if (hipEventCreate(&ev[k]) != hipSuccess) st = fail(DODE_ERR_HIP, "hipEventCreate failed");
   for (int32_t tile : kTiles)
-    for (int32_t order = 0; order < 2; ++order) {
-      if (st != DODE_OK) break;
-      if ((st = set_day_groups(plan, tile)) != DODE_OK) break;
-      plan->adj_order = order;
-      if ((st = run_minibatch(plan, 0, 0, s)) != DODE_OK) break;
-      hipError_t e = hipEventRecord(ev[0], s);
-      for (int32_t j = 0; j < n_mb && st == DODE_OK && e == hipSuccess; ++j)
-        st = run_minibatch(plan, 0, j, s);
-      if (st != DODE_OK) break;
-      if (e == hipSuccess) e = hipEventRecord(ev[1], s);
-      if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
-      float ms = 0.f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
-      if (e != hipSuccess) {
-        st = fail(DODE_ERR_HIP, "schedule tuning: %s", hipGetErrorString(e));
-        break;
+    for (int32_t order = 0; order < 2; ++order)
+      for (int32_t slabs : kSlabs) {
+        if (st != DODE_OK) break;
+        plan->n_slabs = slabs;
+        if ((st = set_day_groups(plan, tile)) != DODE_OK) break;
+        if (slabs > 1 && plan->n_slabs != slabs) continue;   // fewer groups than slabs
+        plan->adj_order = order;
+        if ((st = run_minibatch(plan, 0, 0, s)) != DODE_OK) break;
+        hipError_t e = hipEventRecord(ev[0], s);
+        if (e == hipSuccess) st = run_epoch(plan, 0, s);
+        if (st != DODE_OK) break;
+        if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+        if (e != hipSuccess) {
+          st = fail(DODE_ERR_HIP, "schedule tuning: %s", hipGetErrorString(e));
+          break;
+        }
+        if (n++ == 0 || ms < best_ms) {
+          best_ms = ms;
+          best = TunedSchedule{tile, order, slabs};
+        }
       }
-      if (n++ == 0 || ms < best_ms) {
-        best_ms = ms;
-        best = tile;
-        best_order = order;
-      }
-    }
   for (hipEvent_t e : ev)
     if (e) (void)hipEventDestroy(e);
   plan->timing = timing;
   if (st != DODE_OK) return st;
-  plan->adj_order = best_order;
+  plan->adj_order = best.adj_order;
+  plan->n_slabs = best.n_slabs;
   plan->n_timed = n;
   plan->tune_ms = best_ms;
   {
     std::lock_guard<std::mutex> lock(g_tune_mu);
-    g_tuned[key] = {best, best_order};
+    g_tuned[key] = best;
   }
-  return set_day_groups(plan, best);
+  return set_day_groups(plan, best.day_tile);
 }
 
 }  // namespace
@@ -606,6 +680,7 @@ void dode_spgd_defaults(dode_spgd_params* p) {
   p->day_tile = 32;
   p->refine_steps = 0;
   p->adj_order = 1;
+  p->slabs = 1;
 }
 
 namespace {
@@ -1352,6 +1427,7 @@ dode_status spgd_plan_destroy(dode_plan* plan) {
   if (plan->last_stream) (void)hipStreamSynchronize(plan->last_stream);
   for (void* p : {(void*)plan->d_perm, (void*)plan->d_pos, (void*)plan->d_touched,
                   (void*)plan->d_kslot, (void*)plan->d_kdesc, (void*)plan->d_kcomp,
+                  (void*)plan->d_slabs,
                   (void*)plan->d_dc, plan->d_R, (void*)plan->d_part, (void*)plan->d_groups,
                   (void*)plan->d_full,
                   plan->d_X, plan->d_Q, plan->d_A, (void*)plan->d_loss, (void*)plan->d_order})
@@ -1420,6 +1496,7 @@ dode_status spgd_plan_create(const dode_dar* dar, const int32_t* day_cluster, in
         dc_plan.push_back(c);
         ++p->cluster_days[c];
       }
+  p->n_slabs = std::max<int32_t>(1, params->slabs);
   if (dode_status st = set_day_groups(p, params->day_tile ? params->day_tile : 32)) return st;
   HIP_TRY(up(&p->d_order, order.data(), (size_t)D * 4));
   HIP_TRY(up(&p->d_dc, dc_plan.data(), (size_t)D * 4));
@@ -1565,9 +1642,7 @@ dode_status spgd_run(dode_plan* plan, int32_t epoch_begin, int32_t n_epochs, dou
     if (graph) {
       HIP_TRY(hipGraphLaunch(plan->graph_exec, s));
     } else {
-      for (int32_t j = 0; j < plan->nch; ++j)
-        if (dode_status st = run_minibatch(plan, e, j, s)) return st;
-      if (dode_status st = run_refinement(plan, s)) return st;
+      if (dode_status st = run_epoch(plan, e, s)) return st;
     }
     if (loss_dev) {
       double* out = loss_dev + (size_t)(e - epoch_begin) * D;
@@ -1593,10 +1668,11 @@ dode_status spgd_plan_info(const dode_plan* plan, int32_t* day_tile, int32_t* n_
 }
 
 dode_status spgd_plan_schedule(const dode_plan* plan, int32_t* day_tile, int32_t* adj_order,
-                               int32_t* n_timed, double* best_ms) {
+                               int32_t* n_slabs, int32_t* n_timed, double* best_ms) {
   if (!plan) return fail(DODE_ERR_ARG, "plan is NULL");
   if (day_tile) *day_tile = plan->use_mfma ? plan->day_tile : 0;
   if (adj_order) *adj_order = plan->use_mfma ? plan->adj_order : 0;
+  if (n_slabs) *n_slabs = plan->use_mfma ? plan->n_slabs : 1;
   if (n_timed) *n_timed = plan->n_timed;
   if (best_ms) *best_ms = plan->tune_ms;
   return DODE_OK;

@@ -301,6 +301,15 @@ struct dode_plan {
   int32_t kmt = 0, max_comp = 0;
   bool one_launch = false;        // matrix-core minibatches as one launch each
   int32_t adj_order = 0;          // ChunkSched::order of the matrix-core adjoint
+  // Day slabs: the matrix-core epoch runs every minibatch on the day groups of
+  // slab 0, then on those of slab 1, ...  (days are independent, so the
+  // results do not depend on the slabs); a slab's demand and accumulator rows
+  // can then stay in the last-level cache across its minibatches.
+  int32_t n_slabs = 1;
+  int32_t* d_slabs = nullptr;      // per slab: cluster | first | count | cbase | cgroups
+  std::vector<int64_t> slab_off;   // offset of slab k in d_slabs (elements)
+  std::vector<int32_t> slab_n;     // groups of slab k
+  std::vector<int32_t> h_gc, h_gf, h_gn;   // host copy of the day groups
   int32_t n_timed = 0;            // schedule candidates timed at load
   double tune_ms = 0.0;           // trial time of the chosen candidate
   int32_t* d_dc = nullptr;        // [D]
@@ -335,6 +344,13 @@ struct dode_plan {
   DayGroups groups() const {
     return DayGroups{d_groups, d_groups + n_groups, d_groups + 2 * n_groups,
                      d_groups + 3 * n_groups, d_groups + 4 * n_groups, n_groups, day_tile};
+  }
+  // day groups of slab k (k < 0: all)
+  DayGroups slab_groups(int32_t k) const {
+    if (k < 0 || n_slabs <= 1) return groups();
+    const int32_t* b = d_slabs + slab_off[k];
+    const int32_t n = slab_n[k];
+    return DayGroups{b, b + n, b + 2 * n, b + 3 * n, b + 4 * n, n, day_tile};
   }
   bool sorted_desc() const { return use_mfma && adj_order == 1; }
   ChunkSched chunk(int32_t e, int32_t j) const {

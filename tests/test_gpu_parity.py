@@ -397,9 +397,10 @@ def test_day_tile_gives_identical_results(storage):
     X = dev(inst.x, torch.float32)
     Q0 = torch.zeros((inst.D, inst.T, inst.P), dtype=torch.float32, device="cuda")
     outs = {}
-    for tile, order in ((16, 1), (32, 1), (64, 1), (16, 0), (32, 0), (64, 0), (0, 1)):
+    for tile, order, slabs in ((16, 1, 1), (32, 1, 1), (64, 1, 1), (16, 0, 1), (32, 0, 1),
+                               (64, 0, 1), (16, 1, 4), (32, 0, 2), (32, 1, 3), (0, 1, 1)):
         p = dode.make_params(epochs=E, batch_rows=batch_rows, eta=5.0, day_tile=tile,
-                             adj_order=order)
+                             adj_order=order, slabs=slabs)
         plan = dode.spgd_plan_create(dar, inst.day_cluster, p, perm=perms, stream=0)
         dode.spgd_plan_load(plan, X, Q0)
         info = dode.spgd_plan_info(plan)
@@ -407,6 +408,7 @@ def test_day_tile_gives_identical_results(storage):
         assert info["day_tile"] == tile if tile else info["day_tile"] in (16, 32, 64)
         assert sch["day_tile"] == info["day_tile"]
         assert sch["adj_order"] == order if tile else sch["adj_order"] in (0, 1)
+        assert sch["slabs"] == slabs if tile else sch["slabs"] in (1, 2, 4)
         groups = sum(-(-n // info["day_tile"]) for n in (70, 33, 1))
         assert info["n_day_groups"] == groups and info["minibatch_intervals"] == 6
         loss = torch.zeros((E, inst.D), dtype=torch.float64, device="cuda")
@@ -415,21 +417,22 @@ def test_day_tile_gives_identical_results(storage):
         A = torch.empty_like(Q0)
         dode.spgd_plan_store(plan, Q, A)
         torch.cuda.synchronize()
-        outs[(tile, order)] = (Q.cpu().numpy(), A.cpu().numpy(), loss.cpu().numpy())
+        outs[(tile, order, slabs)] = (Q.cpu().numpy(), A.cpu().numpy(), loss.cpu().numpy())
     for key in outs:
-        for a, b in zip(outs[key], outs[(32, 1)]):
+        for a, b in zip(outs[key], outs[(32, 1, 1)]):
             np.testing.assert_array_equal(a, b)
     Wq = dequantized_values(inst, storage)
     bh = chunk_h_blocks(inst.L, inst.H, batch_rows)
     _, _, ho = orc.spgd(inst, inst.x.astype(np.float64), perms, E, bh, optimizer=0, eta=5.0, W=Wq)
-    assert np.max(np.abs(outs[(64, 1)][2].T - ho) / ho) <= 1e-3
+    assert np.max(np.abs(outs[(64, 1, 1)][2].T - ho) / ho) <= 1e-3
 
 
 def test_schedule_tuner_times_every_candidate_and_remembers():
-    """day_tile 0: the first plan of a shape times the 6 schedule candidates
-    (3 day tiles x 2 adjoint orders) and keeps the fastest; a second plan of the
-    same shapes, storage and cluster sizes reuses that choice without timing;
-    another storage type is a new key."""
+    """day_tile 0: the first plan of a shape times an epoch of every schedule
+    candidate (3 day tiles x 2 adjoint orders x 1, 2 or 4 day slabs, slab
+    counts above the number of day groups skipped) and keeps the fastest; a
+    second plan of the same shapes, storage and cluster sizes reuses that
+    choice without timing; another storage type is a new key."""
     inst = make_instance(P=41, L=66, T=30, K=4, sizes=(50, 20), inc=0.15, pattern="corridor",
                          demand="gamma", noise="mult5", x_dtype="f32", seed=64)
     say("schedule tuner")
@@ -443,10 +446,14 @@ def test_schedule_tuner_times_every_candidate_and_remembers():
         plan = dode.spgd_plan_create(dar, inst.day_cluster, p, perm=perms, stream=0)
         dode.spgd_plan_load(plan, X, Q0)
         seen.append(dode.spgd_plan_schedule(plan))
-    assert seen[0]["n_timed"] == 6 and seen[0]["best_ms"] > 0
+    groups = {t: sum(-(-n // t) for n in (50, 20)) for t in (16, 32, 64)}
+    want = sum(2 * sum(1 for k in (1, 2, 4) if k <= groups[t]) for t in groups)
+    assert want == 14
+    assert seen[0]["n_timed"] == want and seen[0]["best_ms"] > 0
     assert seen[1]["n_timed"] == 0
-    assert (seen[1]["day_tile"], seen[1]["adj_order"]) == (seen[0]["day_tile"], seen[0]["adj_order"])
-    assert seen[2]["n_timed"] == 6
+    pick = ("day_tile", "adj_order", "slabs")
+    assert [seen[1][k] for k in pick] == [seen[0][k] for k in pick]
+    assert seen[2]["n_timed"] == want
 
 
 def test_day_tile_rejected():
