@@ -125,7 +125,7 @@ def launch_bytes(inst, perms, bh, esz, epochs, s_state=4, refine=0):
 
 
 def run_form(dode, torch, inst, form, perms, E_total, warmup, steps, bh, refine=0, day_tile=32,
-             repeats=1):
+             repeats=1, adj_order=1, slabs=1):
     dt = torch.float64 if form == "f64" else torch.float32
     t0 = time.time()
     dar = dode.dar_create(inst.P, inst.L, inst.T, inst.H, inst.K, inst.row_ptr, inst.col_idx, inst.W,
@@ -135,7 +135,8 @@ def run_form(dode, torch, inst, form, perms, E_total, warmup, steps, bh, refine=
     Q = torch.zeros((D, inst.T, inst.P), dtype=dt, device="cuda")
     A = torch.zeros_like(Q)
     params = dode.make_params(epochs=E_total, batch_rows=8192, eta=5.0, optimizer=0,
-                              refine_steps=refine, day_tile=day_tile,
+                              refine_steps=refine, day_tile=day_tile, adj_order=adj_order,
+                              slabs=slabs,
                               kernel_path=KERNEL_PATH.get(form, 0))
     plan = dode.spgd_plan_create(dar, inst.day_cluster, params, perm=perms, stream=0)
     dode.spgd_plan_load(plan, X, Q, A, stream=0)
@@ -630,8 +631,12 @@ def spgd_leg(args, dode, torch, config, form, compare, refine, pattern=None, per
     res = {}
     for f in forms:
         # day_tile 0: the library times its schedule candidates at load
+        tile, order, slabs = (16 if per_day else 0), 1, 1
+        if getattr(args, "schedule", None):
+            tile, order, slabs = (int(v) for v in args.schedule.split(","))
         r = run_form(dode, torch, inst, f, perms[:E_total], E_total, args.warmup, args.steps, bh,
-                     rf[f], day_tile=16 if per_day else 0, repeats=5 if f == form else 1)
+                     rf[f], day_tile=tile, repeats=5 if f == form else 1, adj_order=order,
+                     slabs=slabs)
         fb, ab = launch_bytes(inst, perms, bh, ESIZE[f], r["timing_epochs"], refine=rf[f])
         r["fwd_bytes"], r["adj_bytes"] = fb.sum(), ab.sum()
         res[f] = r
@@ -794,6 +799,8 @@ def main():
                          "bernoulli = every (link, OD) pair independently, the stress case")
     ap.add_argument("--per-day", action="store_true",
                     help="give every day its own ratio matrix (one cluster per day)")
+    ap.add_argument("--schedule", default=None,
+                    help="TILE,ORDER,SLABS: a fixed matrix-core schedule instead of the tuned one")
     ap.add_argument("--sweep-schedules", action="store_true",
                     help="time every matrix-core schedule candidate of the workload instead")
     ap.add_argument("--calibrate-copy", action="store_true",

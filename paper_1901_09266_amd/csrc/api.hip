@@ -379,9 +379,15 @@ dode_status run_chunk(dode_plan* plan, const ChunkSched& cs, const CompSched* ks
       HIP_TRY(timed(plan, 1, s, [&] { return mfma_minibatch(dar, *ks, dg, ly, X, R, Q, A, plan->sa, s); }));
       return DODE_OK;
     }
-    HIP_TRY(timed(plan, 0, s, [&] { return mfma_chunk_resid(dar, cs, dg, ly, Q, X, R, corr, s); }));
+    const dode_plan::WaveTables& wt =
+        corr ? plan->wt_full : plan->wt_mb[slab < 0 || plan->n_slabs <= 1 ? 0 : slab];
+    const int o = cs.order;
+    HIP_TRY(timed(plan, 0, s, [&] {
+      return mfma_chunk_resid(dar, cs, wt.fwd, wt.n_fwd, plan->day_tile, ly, Q, X, R, corr, s);
+    }));
     HIP_TRY(timed(plan, 1, s, [&] {
-      return mfma_chunk_adj_step(dar, cs, dg, ly, R, Q, A, plan->sa, corr, s);
+      return mfma_chunk_adj_step(dar, cs, wt.adj[o], wt.n_adj[o], plan->day_tile, ly, R, Q, A,
+                                 plan->sa, corr, s);
     }));
     return DODE_OK;
   }
@@ -452,6 +458,88 @@ void drop_epoch_graph(dode_plan* plan) {
   plan->graph = nullptr;
 }
 
+// Work table of a grouped matrix-core launch over a group list (cluster,
+// first day, day count per group; a cluster's groups are consecutive): items
+// (cluster, row u, group, tile k) with k fastest, u over per_cluster rows and
+// k over n_tiles, the order the launches have always used (all day groups of
+// a cluster that need the same assignment tiles run back to back).  fwd: rows
+// are minibatch slots, tiles link tiles; adjoint: rows are descriptor
+// indices, tiles OD tiles, swapped when `tile_major` (the OD-tile-major order).
+std::vector<WaveWork> work_table(const dode_dar* dar, const std::vector<int32_t>& gc,
+                                 const std::vector<int32_t>& gf, const std::vector<int32_t>& gn,
+                                 bool fwd, int32_t rows, bool tile_major) {
+  const int32_t nLT = dar->tiles.nLT, nPT = dar->tiles.nPT;
+  const std::vector<int32_t>& m = dar->h_tile_meta;
+  const int32_t* ks = fwd ? m.data() + nLT : m.data() + 3 * nLT + nPT;
+  const int32_t* lo = fwd ? m.data() : m.data() + 3 * nLT;
+  const int32_t* ko = fwd ? m.data() + 2 * nLT : m.data() + 3 * nLT + 2 * nPT;
+  const int32_t n_tiles = fwd ? nLT : nPT;
+  const int32_t per = tile_major ? n_tiles : rows, inner = tile_major ? rows : n_tiles;
+  std::vector<WaveWork> out;
+  out.reserve((size_t)gc.size() * rows * n_tiles);
+  for (size_t g0 = 0; g0 < gc.size();) {
+    size_t g1 = g0 + 1;
+    while (g1 < gc.size() && gc[g1] == gc[g0]) ++g1;
+    for (int32_t u = 0; u < per; ++u)
+      for (size_t g = g0; g < g1; ++g)
+        for (int32_t k = 0; k < inner; ++k) {
+          const int32_t row = tile_major ? k : u, tile = tile_major ? u : k;
+          out.push_back(WaveWork{gc[g0], gf[g], gn[g], row, tile, ks[tile], lo[tile], ko[tile]});
+        }
+    g0 = g1;
+  }
+  return out;
+}
+
+void free_tables(dode_plan::WaveTables& t) {
+  for (WaveWork* p : {t.fwd, t.adj[0], t.adj[1]})
+    if (p) (void)hipFree(p);
+  t = dode_plan::WaveTables{};
+}
+
+void free_wave_tables(dode_plan* plan) {
+  for (auto& t : plan->wt_mb) free_tables(t);
+  plan->wt_mb.clear();
+  free_tables(plan->wt_full);
+}
+
+hipError_t upload_table(const std::vector<WaveWork>& v, WaveWork** dst, int64_t* n) {
+  *n = (int64_t)v.size();
+  hipError_t e = hipMalloc(dst, std::max<size_t>(16, v.size() * sizeof(WaveWork)));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, v.data(), v.size() * sizeof(WaveWork), hipMemcpyHostToDevice);
+}
+
+// Work tables of every grouped matrix-core launch the plan makes: per slab
+// the minibatch forward and both adjoint orders, and on all groups the
+// refinement steps' forward and adjoint (every interval a row).
+dode_status build_wave_tables(dode_plan* plan, const std::vector<std::vector<int32_t>>& slab_gc,
+                              const std::vector<std::vector<int32_t>>& slab_gf,
+                              const std::vector<std::vector<int32_t>>& slab_gn) {
+  free_wave_tables(plan);
+  const dode_dar* dar = plan->dar;
+  if (!dar->has_tiles) return DODE_OK;
+  for (size_t k = 0; k < slab_gc.size(); ++k) {
+    dode_plan::WaveTables t;
+    const auto f = work_table(dar, slab_gc[k], slab_gf[k], slab_gn[k], true, plan->bh, false);
+    const auto a0 = work_table(dar, slab_gc[k], slab_gf[k], slab_gn[k], false, plan->mt, false);
+    const auto a1 = work_table(dar, slab_gc[k], slab_gf[k], slab_gn[k], false, plan->kmt, true);
+    hipError_t e = upload_table(f, &t.fwd, &t.n_fwd);
+    if (e == hipSuccess) e = upload_table(a0, &t.adj[0], &t.n_adj[0]);
+    if (e == hipSuccess) e = upload_table(a1, &t.adj[1], &t.n_adj[1]);
+    plan->wt_mb.push_back(t);
+    HIP_TRY(e);
+  }
+  if (plan->refine_steps > 0) {
+    const int32_t H = dar->dims.H, T = dar->dims.T;
+    const auto f = work_table(dar, plan->h_gc, plan->h_gf, plan->h_gn, true, H, false);
+    const auto a = work_table(dar, plan->h_gc, plan->h_gf, plan->h_gn, false, T, false);
+    HIP_TRY(upload_table(f, &plan->wt_full.fwd, &plan->wt_full.n_fwd));
+    HIP_TRY(upload_table(a, &plan->wt_full.adj[0], &plan->wt_full.n_adj[0]));
+  }
+  return DODE_OK;
+}
+
 // Split the day groups, in order, into n contiguous slabs of about D/n days
 // each (a cluster may be split), each slab with its own group list.  Drops a
 // captured epoch graph.
@@ -464,7 +552,8 @@ dode_status set_slabs(dode_plan* plan, int32_t n) {
   plan->slab_off.clear();
   plan->slab_n.clear();
   plan->n_slabs = n;
-  if (n == 1) return DODE_OK;
+  if (n == 1) return build_wave_tables(plan, {plan->h_gc}, {plan->h_gf}, {plan->h_gn});
+  std::vector<std::vector<int32_t>> sgc, sgf, sgn;
   std::vector<int32_t> buf;
   int64_t days = 0;
   int32_t g = 0;
@@ -500,10 +589,13 @@ dode_status set_slabs(dode_plan* plan, int32_t n) {
     plan->slab_off.push_back((int64_t)buf.size());
     plan->slab_n.push_back(m);
     for (const auto* v : {&cl, &fi, &co, &cb, &cg}) buf.insert(buf.end(), v->begin(), v->end());
+    sgc.push_back(cl);
+    sgf.push_back(fi);
+    sgn.push_back(co);
   }
   HIP_TRY(hipMalloc(&plan->d_slabs, std::max<size_t>(buf.size() * 4, 16)));
   HIP_TRY(hipMemcpy(plan->d_slabs, buf.data(), buf.size() * 4, hipMemcpyHostToDevice));
-  return DODE_OK;
+  return build_wave_tables(plan, sgc, sgf, sgn);
 }
 
 // Day groups of `tile` days: each cluster's plan days, in order, cut into
@@ -1432,6 +1524,7 @@ dode_status spgd_plan_destroy(dode_plan* plan) {
                   (void*)plan->d_full,
                   plan->d_X, plan->d_Q, plan->d_A, (void*)plan->d_loss, (void*)plan->d_order})
     if (p) (void)hipFree(p);
+  free_wave_tables(plan);
   for (hipEvent_t e : plan->event_pool) (void)hipEventDestroy(e);
   if (plan->graph_exec) (void)hipGraphExecDestroy(plan->graph_exec);
   if (plan->graph) (void)hipGraphDestroy(plan->graph);
@@ -1497,6 +1590,7 @@ dode_status spgd_plan_create(const dode_dar* dar, const int32_t* day_cluster, in
         ++p->cluster_days[c];
       }
   p->n_slabs = std::max<int32_t>(1, params->slabs);
+  p->refine_steps = params->refine_steps;   // the work tables cover refinement steps
   if (dode_status st = set_day_groups(p, params->day_tile ? params->day_tile : 32)) return st;
   HIP_TRY(up(&p->d_order, order.data(), (size_t)D * 4));
   HIP_TRY(up(&p->d_dc, dc_plan.data(), (size_t)D * 4));

@@ -100,6 +100,7 @@ struct dode_dar {
   bool has_tiles = false;
   DevTiles tiles;
   int32_t* d_tile_meta = nullptr;   // f_plo | f_ks | f_koff | g_alo | g_ks | g_koff
+  std::vector<int32_t> h_tile_meta; // host copy
   int32_t* d_posf = nullptr;        // [nnz] element offset of CSR slot j in a forward block
   int32_t* d_posg = nullptr;        // [nnz] element offset of CSC slot jj in an adjoint block
   void* d_Fv = nullptr;
@@ -283,6 +284,16 @@ __device__ __forceinline__ int decode_item(const DayGroups& dg, int item, int pe
   return g0 + (r - u * ng);
 }
 
+// One wave's work in a grouped matrix-core launch, decoded on the host: the
+// cluster, the day group's first plan day and day count, the row (minibatch
+// slot for the forward product, descriptor index for the adjoint), the tile
+// (link tile / OD tile) and that tile's packed k-step count, first column
+// (OD for the forward tiles, link for the adjoint tiles) and k-step offset.
+// A wave reads its entry with one scalar load instead of decoding its item.
+struct WaveWork {
+  int32_t c, first, count, row, tile, nks, lo, koff;
+};
+
 // Zeroed elements past the end of each plan state array (X, Q, A, R).
 constexpr int64_t kStatePad = 64;
 
@@ -310,6 +321,17 @@ struct dode_plan {
   std::vector<int64_t> slab_off;   // offset of slab k in d_slabs (elements)
   std::vector<int32_t> slab_n;     // groups of slab k
   std::vector<int32_t> h_gc, h_gf, h_gn;   // host copy of the day groups
+  // Work tables of the grouped matrix-core launches (WaveWork, one entry per
+  // wave): per slab (one entry when n_slabs == 1) the minibatch forward and
+  // the adjoint in either item order, and on all groups the refinement
+  // steps' forward and adjoint.
+  struct WaveTables {
+    WaveWork* fwd = nullptr;
+    WaveWork* adj[2] = {nullptr, nullptr};
+    int64_t n_fwd = 0, n_adj[2] = {0, 0};
+  };
+  std::vector<WaveTables> wt_mb;
+  WaveTables wt_full;
   int32_t n_timed = 0;            // schedule candidates timed at load
   double tune_ms = 0.0;           // trial time of the chosen candidate
   int32_t* d_dc = nullptr;        // [D]
@@ -492,12 +514,13 @@ hipError_t dense_spgd_bf16(const DenseArgs& a, bool vec, hipStream_t s);
 
 // ---- MFMA tile kernels (mfma_kernels.hip) -------------------------------
 // corr: multiply with the corrected FP8 values (refinement steps)
-hipError_t mfma_chunk_resid(const dode_dar* dar, const ChunkSched& cs, const DayGroups& dg,
-                            const Layout& ly, const float* Q, const float* X, float* R, bool corr,
-                            hipStream_t s);
-hipError_t mfma_chunk_adj_step(const dode_dar* dar, const ChunkSched& cs, const DayGroups& dg,
-                               const Layout& ly, const float* R, float* Q, float* A,
-                               const StepArgs& st, bool corr, hipStream_t s);
+// wt: the launch's work table (n_items entries, one per wave)
+hipError_t mfma_chunk_resid(const dode_dar* dar, const ChunkSched& cs, const WaveWork* wt,
+                            int64_t n_items, int32_t day_tile, const Layout& ly, const float* Q,
+                            const float* X, float* R, bool corr, hipStream_t s);
+hipError_t mfma_chunk_adj_step(const dode_dar* dar, const ChunkSched& cs, const WaveWork* wt,
+                               int64_t n_items, int32_t day_tile, const Layout& ly, const float* R,
+                               float* Q, float* A, const StepArgs& st, bool corr, hipStream_t s);
 // one whole minibatch (forward, residual, adjoint, step) in one launch
 hipError_t mfma_minibatch(const dode_dar* dar, const CompSched& ks, const DayGroups& dg,
                           const Layout& ly, const float* X, float* R, float* Q, float* A,

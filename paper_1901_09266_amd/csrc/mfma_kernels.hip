@@ -140,14 +140,14 @@ __device__ __forceinline__ void store4(float* __restrict__ p, const f32x4& v, bo
 // One forward item: link tile i of minibatch slot s (interval h) for day
 // group g of cluster c, written to the residual rows R[.][s].
 template <int MODE, int NT>
-__device__ __forceinline__ void fwd_item(const DevPat& pt, const DevTiles& tl, const DayGroups& dg,
-                                         const Layout& ly, int c, int s, int h, int g, int i,
-                                         const float* __restrict__ Q, const float* __restrict__ X,
-                                         float* __restrict__ R) {
+__device__ __forceinline__ void fwd_item(const DevPat& pt, const DevTiles& tl, const Layout& ly,
+                                         const WaveWork& w, int h, const float* __restrict__ Q,
+                                         const float* __restrict__ X, float* __restrict__ R) {
   constexpr int kBatch = NT == 2 ? 3 : 8 / NT;
   const int lane = threadIdx.x & 63;
   const int n = lane & 15, kg = lane >> 4;
-  const int first = dg.first[g], cnt = dg.count[g];
+  const int c = w.c, s = w.row, i = w.tile;
+  const int first = w.first, cnt = w.count;
   const int a0 = 16 * i + 4 * kg;
   bool live[NT];
   const float* qcol[NT];
@@ -162,10 +162,10 @@ __device__ __forceinline__ void fwd_item(const DevPat& pt, const DevTiles& tl, c
   // lags with t = h - l inside [0, T)
   const int l_lo = h - pt.T + 1 > 0 ? h - pt.T + 1 : 0;
   const int l_hi = h < pt.K - 1 ? h : pt.K - 1;
-  const int nks = tl.f_ks[i], plo = tl.f_plo[i];
+  const int nks = w.nks, plo = w.lo;
   const int n_it = l_hi >= l_lo ? (l_hi - l_lo + 1) * nks : 0;
   // k-step index of block (c, l, t): ((c*K + l)*T + t)*kf_total + f_koff[i] + ks
-  const int64_t kbase = (int64_t)c * pt.K * pt.T * tl.kf_total + tl.f_koff[i];
+  const int64_t kbase = (int64_t)c * pt.K * pt.T * tl.kf_total + w.koff;
   f32x4 acc[NT];
 #pragma unroll
   for (int u = 0; u < NT; ++u) acc[u] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -231,21 +231,27 @@ __device__ __forceinline__ void fwd_item(const DevPat& pt, const DevTiles& tl, c
 // Forward product and residual of the minibatch rows, one wave per item
 // (cluster, slot s, day group g, link tile i) in the order of decode_item;
 // 4 items per block, blocks remapped so each XCD walks a contiguous range.
+// Work item of a wave: its entry of the launch's work table (one scalar load).
+__device__ __forceinline__ WaveWork load_work(const WaveWork* __restrict__ wt, int item) {
+  const int4* p = reinterpret_cast<const int4*>(wt + item);
+  const int4 a = p[0], b = p[1];
+  return WaveWork{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+}
+
 template <int MODE, int NT>
 __global__ void __launch_bounds__(256)
-k_fwd_mfma(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, Layout ly,
-           const float* __restrict__ Q, const float* __restrict__ X, float* __restrict__ R) {
+k_fwd_mfma(DevPat pt, DevTiles tl, ChunkSched cs, const WaveWork* __restrict__ wt, int n_items,
+           Layout ly, const float* __restrict__ Q, const float* __restrict__ X,
+           float* __restrict__ R) {
   // the wave index is uniform: everything derived from it lives in scalar registers
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int n_items = dg.n * cs.bh * tl.nLT;
   const int item = xcd_logical_block((n_items + 3) / 4) * 4 + wave;
   if (item >= n_items) return;
-  int c, s, i;
-  const int g = decode_item(dg, item, cs.bh, tl.nLT, c, s, i);
-  if (cs.j0 + s >= pt.H) return;
+  const WaveWork w = load_work(wt, item);
+  if (cs.j0 + w.row >= pt.H) return;
   cs = resolve_epoch(cs);
-  const int h = cs.perm[c * pt.H + cs.j0 + s];
-  fwd_item<MODE, NT>(pt, tl, dg, ly, c, s, h, g, i, Q, X, R);
+  const int h = cs.perm[w.c * pt.H + cs.j0 + w.row];
+  fwd_item<MODE, NT>(pt, tl, ly, w, h, Q, X, R);
 }
 
 __device__ __forceinline__ f32x4 step4(f32x4 q, f32x4& a, const f32x4& g, const StepArgs& st) {
@@ -272,10 +278,11 @@ __device__ __forceinline__ f32x4 step4(f32x4 q, f32x4& a, const f32x4& g, const 
 // One adjoint item: OD tile j of the reached departure interval described by
 // dsc, for day group g of cluster c, with the step and projection fused.
 template <int MODE, int NT>
-__device__ __forceinline__ void adj_item(const DevPat& pt, const DevTiles& tl, const DayGroups& dg,
-                                         const Layout& ly, int c, const int32_t* dsc, int g, int j,
+__device__ __forceinline__ void adj_item(const DevPat& pt, const DevTiles& tl, const Layout& ly,
+                                         const WaveWork& w, const int32_t* dsc,
                                          const float* __restrict__ R, float* __restrict__ Q,
                                          float* __restrict__ A, const StepArgs& st) {
+  const int c = w.c, j = w.tile;
   constexpr int kBatch = NT == 2 ? 3 : 8 / NT;
   const int lane = threadIdx.x & 63;
   const int t = dsc[kDescT];
@@ -283,7 +290,7 @@ __device__ __forceinline__ void adj_item(const DevPat& pt, const DevTiles& tl, c
   const uint64_t lmask = (uint64_t)(uint32_t)dsc[kDescMask] |
                          (uint64_t)(uint32_t)dsc[kDescMask + 1] << 32;
   const int n = lane & 15, kg = lane >> 4;
-  const int first = dg.first[g], cnt = dg.count[g];
+  const int first = w.first, cnt = w.count;
   const int p0 = 16 * j + 4 * kg;
   const bool adagrad = st.optimizer == 0;
   bool live[NT];
@@ -298,9 +305,9 @@ __device__ __forceinline__ void adj_item(const DevPat& pt, const DevTiles& tl, c
     q[u] = load4(Q + idx);
     a[u] = adagrad ? load4(A + idx) : f32x4{0.f, 0.f, 0.f, 0.f};
   }
-  const int nks = tl.g_ks[j], alo = tl.g_alo[j];
+  const int nks = w.nks, alo = w.lo;
   const int n_it = __popcll(lmask) * nks;
-  const int64_t kbase = (int64_t)c * pt.K * pt.T * tl.kg_total + tl.g_koff[j];
+  const int64_t kbase = (int64_t)c * pt.K * pt.T * tl.kg_total + w.koff;
   f32x4 acc[NT];
 #pragma unroll
   for (int u = 0; u < NT; ++u) acc[u] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -367,21 +374,17 @@ __device__ __forceinline__ void adj_item(const DevPat& pt, const DevTiles& tl, c
 // order of decode_item; same block remapping as the forward kernel.
 template <int MODE, int NT>
 __global__ void __launch_bounds__(256)
-k_adj_mfma(DevPat pt, DevTiles tl, ChunkSched cs, DayGroups dg, Layout ly,
-           const float* __restrict__ R, float* __restrict__ Q, float* __restrict__ A, StepArgs st) {
+k_adj_mfma(DevPat pt, DevTiles tl, ChunkSched cs, const WaveWork* __restrict__ wt, int n_items,
+           Layout ly, const float* __restrict__ R, float* __restrict__ Q, float* __restrict__ A,
+           StepArgs st) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int n_items = dg.n * cs.max_touched * tl.nPT;
   const int item = xcd_logical_block((n_items + 3) / 4) * 4 + wave;
   if (item >= n_items) return;
-  int c, ti, j, g;
-  if (cs.order == 1)
-    g = decode_item(dg, item, tl.nPT, cs.max_touched, c, j, ti);
-  else
-    g = decode_item(dg, item, cs.max_touched, tl.nPT, c, ti, j);
+  const WaveWork w = load_work(wt, item);
   cs = resolve_epoch(cs);
-  const int32_t* dsc = cs.touched + ((int64_t)c * cs.max_touched + ti) * desc_width(pt.K);
+  const int32_t* dsc = cs.touched + ((int64_t)w.c * cs.max_touched + w.row) * desc_width(pt.K);
   if (dsc[kDescT] < 0) return;
-  adj_item<MODE, NT>(pt, tl, dg, ly, c, dsc, g, j, R, Q, A, st);
+  adj_item<MODE, NT>(pt, tl, ly, w, dsc, R, Q, A, st);
 }
 
 // One whole minibatch in one launch, one workgroup per (cluster, component,
@@ -411,18 +414,21 @@ k_minibatch_mfma(DevPat pt, DevTiles tl, CompSched ks, DayGroups dg, Layout ly,
   const int h0 = cp[0], n_h = cp[1], d0 = cp[2], n_t = cp[3];
   if (n_h == 0) return;          // padding entry, uniform over the workgroup
   const int32_t* slots = ks.slot + (int64_t)c * ks.bh;
+  const int first = dg.first[g], cnt = dg.count[g];
   for (int task = wave; task < n_h * tl.nLT; task += 4) {
     const int a = task / tl.nLT, i = task - a * tl.nLT;
     const int s = slots[h0 + a];
     const int h = ks.perm[c * pt.H + ks.j0 + s];
-    fwd_item<MODE, NT>(pt, tl, dg, ly, c, s, h, g, i, Q, X, R);
+    const WaveWork w{c, first, cnt, s, i, tl.f_ks[i], tl.f_plo[i], tl.f_koff[i]};
+    fwd_item<MODE, NT>(pt, tl, ly, w, h, Q, X, R);
   }
   __syncthreads();
   const int dw = desc_width(pt.K);
   for (int task = wave; task < n_t * tl.nPT; task += 4) {
     const int b = task / tl.nPT, j = task - b * tl.nPT;
     const int32_t* dsc = ks.desc + ((int64_t)c * ks.mt + d0 + b) * dw;
-    adj_item<MODE, NT>(pt, tl, dg, ly, c, dsc, g, j, R, Q, A, st);
+    const WaveWork w{c, first, cnt, d0 + b, j, tl.g_ks[j], tl.g_alo[j], tl.g_koff[j]};
+    adj_item<MODE, NT>(pt, tl, ly, w, dsc, R, Q, A, st);
   }
 }
 
@@ -463,22 +469,23 @@ hipError_t update_tiles(const dode_dar* dar, int32_t cluster, hipStream_t s) {
 }
 
 template <int MODE, int NT>
-hipError_t launch_fwd(const dode_dar* dar, const ChunkSched& cs, const DayGroups& dg, const Layout& ly,
-                      const float* Q, const float* X, float* R, hipStream_t s) {
-  const int64_t nblk = ((int64_t)dg.n * cs.bh * dar->tiles.nLT + 3) / 4;
+hipError_t launch_fwd(const dode_dar* dar, const ChunkSched& cs, const WaveWork* wt, int64_t n,
+                      const Layout& ly, const float* Q, const float* X, float* R, hipStream_t s) {
+  const int64_t nblk = (n + 3) / 4;
   const dim3 grid((unsigned)(((nblk + kXcds - 1) / kXcds) * kXcds));
-  hipLaunchKernelGGL((k_fwd_mfma<MODE, NT>), grid, dim3(256), 0, s, dar->pat(), dar->tiles, cs, dg,
-                     ly, Q, X, R);
+  hipLaunchKernelGGL((k_fwd_mfma<MODE, NT>), grid, dim3(256), 0, s, dar->pat(), dar->tiles, cs, wt,
+                     (int)n, ly, Q, X, R);
   return hipGetLastError();
 }
 
 template <int MODE, int NT>
-hipError_t launch_adj(const dode_dar* dar, const ChunkSched& cs, const DayGroups& dg, const Layout& ly,
-                      const float* R, float* Q, float* A, const StepArgs& st, hipStream_t s) {
-  const int64_t nblk = ((int64_t)dg.n * cs.max_touched * dar->tiles.nPT + 3) / 4;
+hipError_t launch_adj(const dode_dar* dar, const ChunkSched& cs, const WaveWork* wt, int64_t n,
+                      const Layout& ly, const float* R, float* Q, float* A, const StepArgs& st,
+                      hipStream_t s) {
+  const int64_t nblk = (n + 3) / 4;
   const dim3 grid((unsigned)(((nblk + kXcds - 1) / kXcds) * kXcds));
-  hipLaunchKernelGGL((k_adj_mfma<MODE, NT>), grid, dim3(256), 0, s, dar->pat(), dar->tiles, cs, dg,
-                     ly, R, Q, A, st);
+  hipLaunchKernelGGL((k_adj_mfma<MODE, NT>), grid, dim3(256), 0, s, dar->pat(), dar->tiles, cs, wt,
+                     (int)n, ly, R, Q, A, st);
   return hipGetLastError();
 }
 
@@ -502,41 +509,45 @@ hipError_t minibatch_mode(const dode_dar* dar, const CompSched& ks, const DayGro
 }
 
 template <int NT>
-hipError_t fwd_mode(const dode_dar* dar, const ChunkSched& cs, const DayGroups& dg, const Layout& ly,
-                    const float* Q, const float* X, float* R, bool corr, hipStream_t s) {
-  if (dar->storage != DODE_FP8_E4M3) return launch_fwd<kBF16, NT>(dar, cs, dg, ly, Q, X, R, s);
-  if (corr) return launch_fwd<kFP8Corr, NT>(dar, cs, dg, ly, Q, X, R, s);
-  return launch_fwd<kFP8, NT>(dar, cs, dg, ly, Q, X, R, s);
+hipError_t fwd_mode(const dode_dar* dar, const ChunkSched& cs, const WaveWork* wt, int64_t n,
+                    const Layout& ly, const float* Q, const float* X, float* R, bool corr,
+                    hipStream_t s) {
+  if (dar->storage != DODE_FP8_E4M3) return launch_fwd<kBF16, NT>(dar, cs, wt, n, ly, Q, X, R, s);
+  if (corr) return launch_fwd<kFP8Corr, NT>(dar, cs, wt, n, ly, Q, X, R, s);
+  return launch_fwd<kFP8, NT>(dar, cs, wt, n, ly, Q, X, R, s);
 }
 
 template <int NT>
-hipError_t adj_mode(const dode_dar* dar, const ChunkSched& cs, const DayGroups& dg, const Layout& ly,
-                    const float* R, float* Q, float* A, const StepArgs& st, bool corr,
-                    hipStream_t s) {
-  if (dar->storage != DODE_FP8_E4M3) return launch_adj<kBF16, NT>(dar, cs, dg, ly, R, Q, A, st, s);
-  if (corr) return launch_adj<kFP8Corr, NT>(dar, cs, dg, ly, R, Q, A, st, s);
-  return launch_adj<kFP8, NT>(dar, cs, dg, ly, R, Q, A, st, s);
+hipError_t adj_mode(const dode_dar* dar, const ChunkSched& cs, const WaveWork* wt, int64_t n,
+                    const Layout& ly, const float* R, float* Q, float* A, const StepArgs& st,
+                    bool corr, hipStream_t s) {
+  if (dar->storage != DODE_FP8_E4M3)
+    return launch_adj<kBF16, NT>(dar, cs, wt, n, ly, R, Q, A, st, s);
+  if (corr) return launch_adj<kFP8Corr, NT>(dar, cs, wt, n, ly, R, Q, A, st, s);
+  return launch_adj<kFP8, NT>(dar, cs, wt, n, ly, R, Q, A, st, s);
 }
 
-hipError_t mfma_chunk_resid(const dode_dar* dar, const ChunkSched& cs, const DayGroups& dg,
-                            const Layout& ly, const float* Q, const float* X, float* R, bool corr,
-                            hipStream_t s) {
+hipError_t mfma_chunk_resid(const dode_dar* dar, const ChunkSched& cs, const WaveWork* wt,
+                            int64_t n, int32_t day_tile, const Layout& ly, const float* Q,
+                            const float* X, float* R, bool corr, hipStream_t s) {
   if (corr && !dar->has_corr) return hipErrorInvalidValue;
-  switch (dg.tile) {
-    case 16: return fwd_mode<1>(dar, cs, dg, ly, Q, X, R, corr, s);
-    case 64: return fwd_mode<4>(dar, cs, dg, ly, Q, X, R, corr, s);
-    default: return fwd_mode<2>(dar, cs, dg, ly, Q, X, R, corr, s);
+  if (n > INT32_MAX) return hipErrorInvalidValue;
+  switch (day_tile) {
+    case 16: return fwd_mode<1>(dar, cs, wt, n, ly, Q, X, R, corr, s);
+    case 64: return fwd_mode<4>(dar, cs, wt, n, ly, Q, X, R, corr, s);
+    default: return fwd_mode<2>(dar, cs, wt, n, ly, Q, X, R, corr, s);
   }
 }
 
-hipError_t mfma_chunk_adj_step(const dode_dar* dar, const ChunkSched& cs, const DayGroups& dg,
-                               const Layout& ly, const float* R, float* Q, float* A,
-                               const StepArgs& st, bool corr, hipStream_t s) {
+hipError_t mfma_chunk_adj_step(const dode_dar* dar, const ChunkSched& cs, const WaveWork* wt,
+                               int64_t n, int32_t day_tile, const Layout& ly, const float* R,
+                               float* Q, float* A, const StepArgs& st, bool corr, hipStream_t s) {
   if (corr && !dar->has_corr) return hipErrorInvalidValue;
-  switch (dg.tile) {
-    case 16: return adj_mode<1>(dar, cs, dg, ly, R, Q, A, st, corr, s);
-    case 64: return adj_mode<4>(dar, cs, dg, ly, R, Q, A, st, corr, s);
-    default: return adj_mode<2>(dar, cs, dg, ly, R, Q, A, st, corr, s);
+  if (n > INT32_MAX) return hipErrorInvalidValue;
+  switch (day_tile) {
+    case 16: return adj_mode<1>(dar, cs, wt, n, ly, R, Q, A, st, corr, s);
+    case 64: return adj_mode<4>(dar, cs, wt, n, ly, R, Q, A, st, corr, s);
+    default: return adj_mode<2>(dar, cs, wt, n, ly, R, Q, A, st, corr, s);
   }
 }
 

@@ -111,6 +111,7 @@ dode_status tiles_prepare(dode_dar* d, std::string& err) {
     if (!hip_ok(hipMalloc(dst, std::max<size_t>(16, v.size() * 4)))) return false;
     return hip_ok(hipMemcpy(*dst, v.data(), v.size() * 4, hipMemcpyHostToDevice));
   };
+  d->h_tile_meta = meta;
   if (!up(&d->d_tile_meta, meta) || !up(&d->d_posf, d->h_posf) || !up(&d->d_posg, d->h_posg))
     return DODE_ERR_OOM;
   const size_t esz = d->storage == DODE_FP8_E4M3 ? 1 : 2;
