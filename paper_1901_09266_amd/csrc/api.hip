@@ -106,6 +106,9 @@ struct HostSched {
   // [E][nch][C][max_comp][4]
   int32_t max_comp = 1;
   std::vector<int32_t> kslot, kdesc, kcomp;
+  // reached-interval chunks (ChunkList): [E][nch][C][max_chunks][chunk_w]
+  int32_t max_chunks = 1, chunk_w = 0;
+  std::vector<int32_t> kchunk;
 };
 
 // Descriptor of departure interval t for the minibatch at positions
@@ -201,13 +204,18 @@ dode_status build_sched(const dode_dims& dm, int32_t C, int32_t E, int32_t bh,
   // neighbours are K or more apart.  Component [h_a .. h_b] reaches the
   // departure intervals max(0, h_a-K+1) .. min(T-1, h_b), all of them, and no
   // other component reaches any of these.
-  std::vector<int32_t> ncomp((size_t)E * hs.nch * C, 0);
+  // Each component's reached intervals are also cut into chunks of up to
+  // kChunkT consecutive ones, listed with the minibatch intervals (and their
+  // slots) that reach them: [t0, n_t, n_h, (h, slot) x n_h].
+  std::vector<int32_t> ncomp((size_t)E * hs.nch * C, 0), nchunk((size_t)E * hs.nch * C, 0);
   std::vector<std::pair<int32_t, int32_t>> hsl;
+  hs.chunk_w = 3 + 2 * (kChunkT + K - 1);
   for (int pass = 0; pass < 2; ++pass) {
     if (pass == 1) {
       hs.kslot.assign((size_t)E * hs.nch * C * bh, -1);
       hs.kdesc.assign((size_t)E * hs.nch * C * mt_used * dw, -1);
       hs.kcomp.assign((size_t)E * hs.nch * C * hs.max_comp * 4, 0);
+      hs.kchunk.assign((size_t)E * hs.nch * C * hs.max_chunks * hs.chunk_w, 0);
     }
     for (int32_t e = 0; e < E; ++e)
       for (int32_t j = 0; j < hs.nch; ++j)
@@ -218,10 +226,29 @@ dode_status build_sched(const dode_dims& dm, int32_t C, int32_t E, int32_t bh,
           hsl.clear();
           for (int32_t sl = 0; sl < bh && j * bh + sl < H; ++sl) hsl.push_back({p[j * bh + sl], sl});
           std::sort(hsl.begin(), hsl.end());
-          int32_t nc = 0, nd = 0;
+          int32_t nc = 0, nd = 0, nk = 0;
           for (size_t a = 0; a < hsl.size();) {
             size_t b = a + 1;
             while (b < hsl.size() && hsl[b].first - hsl[b - 1].first < K) ++b;
+            {
+              const int32_t tlo = std::max(0, hsl[a].first - K + 1);
+              const int32_t thi = std::min(T - 1, hsl[b - 1].first);
+              for (int32_t t0 = tlo; t0 <= thi; t0 += kChunkT, ++nk) {
+                if (pass == 0) continue;
+                const int32_t nt = std::min(kChunkT, thi - t0 + 1);
+                int32_t* ck = hs.kchunk.data() + (r * hs.max_chunks + nk) * hs.chunk_w;
+                ck[0] = t0;
+                ck[1] = nt;
+                int32_t nh = 0;
+                for (size_t q = a; q < b; ++q)
+                  if (hsl[q].first >= t0 && hsl[q].first <= t0 + nt - 1 + K - 1) {
+                    ck[3 + 2 * nh] = hsl[q].first;
+                    ck[4 + 2 * nh] = hsl[q].second;
+                    ++nh;
+                  }
+                ck[2] = nh;
+              }
+            }
             if (pass == 1) {
               const int32_t tlo = std::max(0, hsl[a].first - K + 1);
               const int32_t thi = std::min(T - 1, hsl[b - 1].first);
@@ -237,10 +264,15 @@ dode_status build_sched(const dode_dims& dm, int32_t C, int32_t E, int32_t bh,
             ++nc;
             a = b;
           }
-          if (pass == 0) ncomp[r] = nc;
+          if (pass == 0) {
+            ncomp[r] = nc;
+            nchunk[r] = nk;
+          }
         }
-    if (pass == 0)
+    if (pass == 0) {
       hs.max_comp = std::max<int32_t>(1, *std::max_element(ncomp.begin(), ncomp.end()));
+      hs.max_chunks = std::max<int32_t>(1, *std::max_element(nchunk.begin(), nchunk.end()));
+    }
   }
   hs.mt = mt_used;
   return DODE_OK;
@@ -261,8 +293,10 @@ dode_status check_params(const dode_spgd_params* p) {
     return fail(DODE_ERR_ARG, "day_tile=%d (0 = tune, 16, 32 or 64)", p->day_tile);
   if (p->refine_steps < 0 || p->refine_steps > 16)
     return fail(DODE_ERR_ARG, "refine_steps=%d outside [0, 16]", p->refine_steps);
-  if (p->adj_order != 0 && p->adj_order != 1)
-    return fail(DODE_ERR_ARG, "adj_order=%d (0 or 1)", p->adj_order);
+  if (p->adj_order < 0 || p->adj_order > 2)
+    return fail(DODE_ERR_ARG, "adj_order=%d (0, 1 or 2)", p->adj_order);
+  if (p->adj_order == 2 && p->day_tile == 64)
+    return fail(DODE_ERR_ARG, "adj_order 2 needs day_tile 16 or 32 (or 0 to tune)");
   if (p->slabs < 0 || p->slabs > 64)
     return fail(DODE_ERR_ARG, "slabs=%d outside [0, 64]", p->slabs);
   return DODE_OK;
@@ -365,8 +399,8 @@ namespace {
 
 // Minibatch j of epoch e on the plan's state: forward + residual, then
 // adjoint + step + projection.
-dode_status run_chunk(dode_plan* plan, const ChunkSched& cs, const CompSched* ks, hipStream_t s,
-                      bool corr = false, int32_t slab = -1) {
+dode_status run_chunk(dode_plan* plan, const ChunkSched& cs, const CompSched* ks,
+                      const ChunkList* ckl, hipStream_t s, bool corr = false, int32_t slab = -1) {
   const dode_dar* dar = plan->dar;
   const Layout& ly = plan->ly;
   if (plan->use_mfma) {
@@ -385,6 +419,13 @@ dode_status run_chunk(dode_plan* plan, const ChunkSched& cs, const CompSched* ks
     HIP_TRY(timed(plan, 0, s, [&] {
       return mfma_chunk_resid(dar, cs, wt.fwd, wt.n_fwd, plan->day_tile, ly, Q, X, R, corr, s);
     }));
+    if (o == 2 && ckl && !corr) {
+      HIP_TRY(timed(plan, 1, s, [&] {
+        return mfma_adj_chunks(dar, *ckl, wt.adj[2], wt.n_adj[2], plan->day_tile, ly, R, Q, A,
+                               plan->sa, s);
+      }));
+      return DODE_OK;
+    }
     HIP_TRY(timed(plan, 1, s, [&] {
       return mfma_chunk_adj_step(dar, cs, wt.adj[o], wt.n_adj[o], plan->day_tile, ly, R, Q, A,
                                  plan->sa, corr, s);
@@ -404,14 +445,15 @@ dode_status run_chunk(dode_plan* plan, const ChunkSched& cs, const CompSched* ks
 
 dode_status run_minibatch(dode_plan* plan, int32_t e, int32_t j, hipStream_t s, int32_t slab = -1) {
   const CompSched ks = plan->comps(e, j);
-  return run_chunk(plan, plan->chunk(e, j), &ks, s, false, slab);
+  const ChunkList ckl = plan->chunks(e, j);
+  return run_chunk(plan, plan->chunk(e, j), &ks, &ckl, s, false, slab);
 }
 
 // The refinement steps that end every epoch: full-batch steps on the
 // corrected values (schedule independent of the epoch).
 dode_status run_refinement(dode_plan* plan, hipStream_t s) {
   for (int32_t r = 0; r < plan->refine_steps; ++r)
-    if (dode_status st = run_chunk(plan, plan->chunk_full(), nullptr, s, true)) return st;
+    if (dode_status st = run_chunk(plan, plan->chunk_full(), nullptr, nullptr, s, true)) return st;
   return DODE_OK;
 }
 
@@ -422,8 +464,9 @@ dode_status run_epoch(dode_plan* plan, int32_t e, hipStream_t s) {
   for (int32_t k = 0; k < ns; ++k)
     for (int32_t j = 0; j < plan->nch; ++j) {
       const CompSched ks = plan->comps(e, j);
+      const ChunkList ckl = plan->chunks(e, j);
       const ChunkSched cs = e < 0 ? plan->chunk_dev(j) : plan->chunk(e, j);
-      if (dode_status st = run_chunk(plan, cs, &ks, s, false, ns > 1 ? k : -1)) return st;
+      if (dode_status st = run_chunk(plan, cs, &ks, &ckl, s, false, ns > 1 ? k : -1)) return st;
     }
   return run_refinement(plan, s);
 }
@@ -492,7 +535,7 @@ std::vector<WaveWork> work_table(const dode_dar* dar, const std::vector<int32_t>
 }
 
 void free_tables(dode_plan::WaveTables& t) {
-  for (WaveWork* p : {t.fwd, t.adj[0], t.adj[1]})
+  for (WaveWork* p : {t.fwd, t.adj[0], t.adj[1], t.adj[2]})
     if (p) (void)hipFree(p);
   t = dode_plan::WaveTables{};
 }
@@ -524,9 +567,12 @@ dode_status build_wave_tables(dode_plan* plan, const std::vector<std::vector<int
     const auto f = work_table(dar, slab_gc[k], slab_gf[k], slab_gn[k], true, plan->bh, false);
     const auto a0 = work_table(dar, slab_gc[k], slab_gf[k], slab_gn[k], false, plan->mt, false);
     const auto a1 = work_table(dar, slab_gc[k], slab_gf[k], slab_gn[k], false, plan->kmt, true);
+    const auto a2 =
+        work_table(dar, slab_gc[k], slab_gf[k], slab_gn[k], false, plan->max_chunks, true);
     hipError_t e = upload_table(f, &t.fwd, &t.n_fwd);
     if (e == hipSuccess) e = upload_table(a0, &t.adj[0], &t.n_adj[0]);
     if (e == hipSuccess) e = upload_table(a1, &t.adj[1], &t.n_adj[1]);
+    if (e == hipSuccess) e = upload_table(a2, &t.adj[2], &t.n_adj[2]);
     plan->wt_mb.push_back(t);
     HIP_TRY(e);
   }
@@ -681,9 +727,10 @@ dode_status tune_schedule(dode_plan* plan, hipStream_t s) {
   for (int k = 0; k < 2 && st == DODE_OK; ++k)
     if (hipEventCreate(&ev[k]) != hipSuccess) st = fail(DODE_ERR_HIP, "hipEventCreate failed");
   for (int32_t tile : kTiles)
-    for (int32_t order = 0; order < 2; ++order)
+    for (int32_t order = 0; order < 3; ++order)
       for (int32_t slabs : kSlabs) {
         if (st != DODE_OK) break;
+        if (order == 2 && tile == 64) continue;   // the chunked adjoint has no 64-day waves
         plan->n_slabs = slabs;
         if ((st = set_day_groups(plan, tile)) != DODE_OK) break;
         if (slabs > 1 && plan->n_slabs != slabs) continue;   // fewer groups than slabs
@@ -1519,6 +1566,7 @@ dode_status spgd_plan_destroy(dode_plan* plan) {
   if (plan->last_stream) (void)hipStreamSynchronize(plan->last_stream);
   for (void* p : {(void*)plan->d_perm, (void*)plan->d_pos, (void*)plan->d_touched,
                   (void*)plan->d_kslot, (void*)plan->d_kdesc, (void*)plan->d_kcomp,
+                  (void*)plan->d_kchunk,
                   (void*)plan->d_slabs,
                   (void*)plan->d_dc, plan->d_R, (void*)plan->d_part, (void*)plan->d_groups,
                   (void*)plan->d_full,
@@ -1579,6 +1627,9 @@ dode_status spgd_plan_create(const dode_dar* dar, const int32_t* day_cluster, in
   HIP_TRY(up(&p->d_kslot, hs.kslot.data(), hs.kslot.size() * 4));
   HIP_TRY(up(&p->d_kdesc, hs.kdesc.data(), hs.kdesc.size() * 4));
   HIP_TRY(up(&p->d_kcomp, hs.kcomp.data(), hs.kcomp.size() * 4));
+  p->max_chunks = hs.max_chunks;
+  p->chunk_w = hs.chunk_w;
+  HIP_TRY(up(&p->d_kchunk, hs.kchunk.data(), hs.kchunk.size() * 4));
   // plan day i = caller day order[i], days grouped by cluster
   std::vector<int32_t> order, dc_plan;
   p->cluster_days.assign(C, 0);

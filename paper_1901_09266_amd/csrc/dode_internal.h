@@ -206,7 +206,9 @@ struct ChunkSched {
   // day group, OD tile), OD tile fastest, over the evenly spread descriptor
   // list; 1 = (cluster, OD tile, day group, reached interval), interval
   // fastest, over the descriptors sorted by t (consecutive waves then read the
-  // same residual rows)
+  // same residual rows); 2 = as 1 with a chunk of up to kChunkT consecutive
+  // reached intervals per wave (k_adj_chunk; the chunk lists replace the
+  // descriptors)
   int32_t order = 0;
 };
 
@@ -228,6 +230,23 @@ struct CompSched {
   const int32_t* epoch;  // device epoch counter (graph replays) or nullptr
   int64_t perm_e, slot_e, desc_e, comp_e;
 };
+
+// Reached-interval chunks of one minibatch for the chunked adjoint: each
+// component's reached departure intervals cut into runs of up to kChunkT
+// consecutive ones, each listed with the minibatch intervals that reach it:
+//   chunk[c][max_chunks][w] = [t0, n_t, n_h, (h, slot) x n_h, ...] (n_t = 0 pads)
+constexpr int32_t kChunkT = 6;
+struct ChunkList {
+  const int32_t* chunk;
+  int32_t max_chunks, w;
+  const int32_t* epoch;   // device epoch counter (graph replays) or nullptr
+  int64_t chunk_e;
+};
+
+__device__ __forceinline__ ChunkList resolve_epoch(ChunkList ck) {
+  if (ck.epoch) ck.chunk += *ck.epoch * ck.chunk_e;
+  return ck;
+}
 
 // Resolve the epoch of a chunk schedule read from device memory (kernel side).
 __device__ __forceinline__ ChunkSched resolve_epoch(ChunkSched cs) {
@@ -310,6 +329,8 @@ struct dode_plan {
   int32_t* d_kdesc = nullptr;     // [E][nch][C][kmt][K+3]
   int32_t* d_kcomp = nullptr;     // [E][nch][C][max_comp][4]
   int32_t kmt = 0, max_comp = 0;
+  int32_t* d_kchunk = nullptr;    // [E][nch][C][max_chunks][chunk_w] (ChunkList)
+  int32_t max_chunks = 0, chunk_w = 0;
   bool one_launch = false;        // matrix-core minibatches as one launch each
   int32_t adj_order = 0;          // ChunkSched::order of the matrix-core adjoint
   // Day slabs: the matrix-core epoch runs every minibatch on the day groups of
@@ -327,8 +348,8 @@ struct dode_plan {
   // steps' forward and adjoint.
   struct WaveTables {
     WaveWork* fwd = nullptr;
-    WaveWork* adj[2] = {nullptr, nullptr};
-    int64_t n_fwd = 0, n_adj[2] = {0, 0};
+    WaveWork* adj[3] = {nullptr, nullptr, nullptr};   // per adjoint order
+    int64_t n_fwd = 0, n_adj[3] = {0, 0, 0};
   };
   std::vector<WaveTables> wt_mb;
   WaveTables wt_full;
@@ -374,14 +395,14 @@ struct dode_plan {
     const int32_t n = slab_n[k];
     return DayGroups{b, b + n, b + 2 * n, b + 3 * n, b + 4 * n, n, day_tile};
   }
-  bool sorted_desc() const { return use_mfma && adj_order == 1; }
+  bool sorted_desc() const { return use_mfma && adj_order >= 1; }
   ChunkSched chunk(int32_t e, int32_t j) const {
     const int32_t H = dar->dims.H;
     const size_t dw = desc_width(dar->dims.K);
     if (sorted_desc())
       return ChunkSched{d_perm + (size_t)e * C * H, d_pos + (size_t)e * C * H,
                         d_kdesc + ((size_t)e * nch + j) * C * kmt * dw, j * bh, bh, kmt, nullptr, 0,
-                        0, 1};
+                        0, adj_order};
     return ChunkSched{d_perm + (size_t)e * C * H, d_pos + (size_t)e * C * H,
                       d_touched + ((size_t)e * nch + j) * C * mt * dw, j * bh, bh, mt, nullptr, 0, 0};
   }
@@ -409,13 +430,20 @@ struct dode_plan {
                      d_kcomp + ee * cs + (int64_t)j * C * max_comp * 4, j * bh, bh, kmt, max_comp,
                      e < 0 ? d_epoch : nullptr, ps, ss, ds, cs};
   }
+  // reached-interval chunks of minibatch j of epoch e (e < 0: the epoch in d_epoch)
+  ChunkList chunks(int32_t e, int32_t j) const {
+    const int64_t per_e = (int64_t)nch * C * max_chunks * chunk_w;
+    const int64_t ee = e < 0 ? 0 : e;
+    return ChunkList{d_kchunk + ee * per_e + (int64_t)j * C * max_chunks * chunk_w, max_chunks,
+                     chunk_w, e < 0 ? d_epoch : nullptr, per_e};
+  }
   // minibatch j of the epoch held in d_epoch (for graph replays)
   ChunkSched chunk_dev(int32_t j) const {
     const int32_t H = dar->dims.H;
     const size_t dw = desc_width(dar->dims.K);
     if (sorted_desc())
       return ChunkSched{d_perm, d_pos, d_kdesc + (size_t)j * C * kmt * dw, j * bh, bh, kmt, d_epoch,
-                        (int64_t)C * H, (int64_t)(nch * C * kmt * dw), 1};
+                        (int64_t)C * H, (int64_t)(nch * C * kmt * dw), adj_order};
     return ChunkSched{d_perm, d_pos, d_touched + (size_t)j * C * mt * dw, j * bh, bh, mt, d_epoch,
                       (int64_t)C * H, (int64_t)(nch * C * mt * dw)};
   }
@@ -521,6 +549,11 @@ hipError_t mfma_chunk_resid(const dode_dar* dar, const ChunkSched& cs, const Wav
 hipError_t mfma_chunk_adj_step(const dode_dar* dar, const ChunkSched& cs, const WaveWork* wt,
                                int64_t n_items, int32_t day_tile, const Layout& ly, const float* R,
                                float* Q, float* A, const StepArgs& st, bool corr, hipStream_t s);
+// adjoint + step by reached-interval chunks (day tiles 16 and 32; not for the
+// refinement steps)
+hipError_t mfma_adj_chunks(const dode_dar* dar, const ChunkList& ck, const WaveWork* wt, int64_t n,
+                           int32_t day_tile, const Layout& ly, const float* R, float* Q, float* A,
+                           const StepArgs& st, hipStream_t s);
 // one whole minibatch (forward, residual, adjoint, step) in one launch
 hipError_t mfma_minibatch(const dode_dar* dar, const CompSched& ks, const DayGroups& dg,
                           const Layout& ly, const float* X, float* R, float* Q, float* A,

@@ -387,6 +387,130 @@ k_adj_mfma(DevPat pt, DevTiles tl, ChunkSched cs, const WaveWork* __restrict__ w
   adj_item<MODE, NT>(pt, tl, ly, w, dsc, R, Q, A, st);
 }
 
+// Adjoint + step for one chunk of reached departure intervals t0..t0+n_t-1
+// (consecutive, of one component) for OD tile j and one day group: every
+// residual row h that reaches the chunk is loaded once per k-step and
+// multiplied into each t with 0 <= h - t < K (the lag block (h - t, t)).  Each
+// t gets its products in increasing lag and k-step order, as in adj_item, so
+// the results are the same bits; the residual loads (and, in BF16 mode, their
+// head/tail split) are shared by up to kChunkT intervals.  Iterations (row,
+// k-step) run in batches of CB whose loads are all issued before the first
+// product.
+template <int MODE, int NT>
+__global__ void __launch_bounds__(256)
+k_adj_chunk(DevPat pt, DevTiles tl, ChunkList ck, const WaveWork* __restrict__ wt, int n_items,
+            Layout ly, const float* __restrict__ R, float* __restrict__ Q, float* __restrict__ A,
+            StepArgs st) {
+  constexpr int CB = NT == 1 ? 1 : 2;   // 4 and 3 waves per SIMD
+  constexpr int G = kChunkT;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int item = xcd_logical_block((n_items + 3) / 4) * 4 + wave;
+  if (item >= n_items) return;
+  const WaveWork w = load_work(wt, item);
+  ck = resolve_epoch(ck);
+  const int32_t* cr = ck.chunk + ((int64_t)w.c * ck.max_chunks + w.row) * ck.w;
+  const int t0 = cr[0], n_t = cr[1], n_h = cr[2];
+  if (n_t == 0) return;
+  const int c = w.c, j = w.tile;
+  const int n = lane & 15, kg = lane >> 4;
+  const int first = w.first, cnt = w.count;
+  const int p0 = 16 * j + 4 * kg;
+  bool live[NT];
+  const float* rcol[NT];
+#pragma unroll
+  for (int u = 0; u < NT; ++u) {
+    live[u] = 16 * u + n < cnt;
+    const int64_t du = live[u] ? first + 16 * u + n : first;
+    rcol[u] = R + du * ly.r_d;
+  }
+  const int nks = w.nks, alo = w.lo;
+  const int n_it = n_h * nks;
+  const int64_t kbase = (int64_t)c * pt.K * pt.T * tl.kg_total + w.koff;
+  f32x4 acc[G][NT];
+#pragma unroll
+  for (int k = 0; k < G; ++k)
+#pragma unroll
+    for (int u = 0; u < NT; ++u) acc[k][u] = f32x4{0.f, 0.f, 0.f, 0.f};
+  int ih = 0, ks = 0;
+  int h = cr[3], sl = cr[4];
+  for (int it0 = 0; it0 < n_it; it0 += CB) {
+    f32x8 v[CB][NT];
+    bf16x8 wa[CB][G];
+    float sc[CB][G];
+    bool use[CB][G];
+#pragma unroll
+    for (int b = 0; b < CB; ++b) {
+      const bool in = it0 + b < n_it;
+      const int k0 = alo + 32 * ks + 4 * kg;
+#pragma unroll
+      for (int u = 0; u < NT; ++u) v[b][u] = load8(rcol[u] + sl * ly.r_s + (k0 >> 2) * ly.r_b, ly.r_b);
+#pragma unroll
+      for (int k = 0; k < G; ++k) {
+        const int lag = h - (t0 + k);
+        use[b][k] = in && k < n_t && lag >= 0 && lag < pt.K;
+        if (use[b][k]) {
+          const int64_t kidx = kbase + ((int64_t)lag * pt.T + t0 + k) * tl.kg_total + ks;
+          wa[b][k] = load_a<MODE>(tl.Gv, kidx, lane);
+          if constexpr (MODE == kFP8)
+            sc[b][k] = tl.scale[(((int64_t)c * pt.K + lag) * pt.T + t0 + k) * tl.n_ptile +
+                                ((16 * j) >> 6)];
+        }
+      }
+      if (in && it0 + b + 1 < n_it && ++ks == nks) {
+        ks = 0;
+        ++ih;
+        h = cr[3 + 2 * ih];
+        sl = cr[4 + 2 * ih];
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < CB; ++b)
+#pragma unroll
+      for (int u = 0; u < NT; ++u) {
+        if constexpr (MODE == kBF16) {
+          const bf16x8 hi = __builtin_convertvector(v[b][u], bf16x8);
+          const bf16x8 lo =
+              __builtin_convertvector(v[b][u] - __builtin_convertvector(hi, f32x8), bf16x8);
+#pragma unroll
+          for (int k = 0; k < G; ++k)
+            if (use[b][k]) {
+              acc[k][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[b][k], hi, acc[k][u], 0, 0, 0);
+              acc[k][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[b][k], lo, acc[k][u], 0, 0, 0);
+            }
+        } else {
+#pragma unroll
+          for (int k = 0; k < G; ++k)
+            if (use[b][k]) mma_split(wa[b][k], v[b][u] * sc[b][k], acc[k][u]);
+        }
+      }
+  }
+  if (p0 >= pt.P) return;
+  const bool full = p0 + 4 <= pt.P;
+  const int valid = pt.P - p0;
+  const bool adagrad = st.optimizer == 0;
+#pragma unroll
+  for (int k = 0; k < G; ++k) {
+    if (k >= n_t) break;
+    const int t = t0 + k;
+    f32x4 q[NT], a[NT];
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
+      const int64_t du = live[u] ? first + 16 * u + n : first;
+      const int64_t idx = du * ly.q_d + t * ly.q_t + (p0 >> 2) * ly.q_b;
+      q[u] = load4(Q + idx);
+      a[u] = adagrad ? load4(A + idx) : f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
+      if (!live[u]) continue;
+      const int64_t idx = (int64_t)(first + 16 * u + n) * ly.q_d + t * ly.q_t + (p0 >> 2) * ly.q_b;
+      q[u] = step4(q[u], a[u], acc[k][u], st);
+      store4(Q + idx, q[u], full, valid);
+      if (adagrad) store4(A + idx, a[u], full, valid);
+    }
+  }
+}
+
 // One whole minibatch in one launch, one workgroup per (cluster, component,
 // day group).  A component is a maximal run of the minibatch's intervals whose
 // reached departure intervals overlap (sorted intervals less than K apart); the
@@ -508,6 +632,17 @@ hipError_t minibatch_mode(const dode_dar* dar, const CompSched& ks, const DayGro
   return launch_minibatch<kFP8, NT>(dar, ks, dg, ly, X, R, Q, A, st, s);
 }
 
+template <int MODE, int NT>
+hipError_t launch_adj_chunk(const dode_dar* dar, const ChunkList& ck, const WaveWork* wt, int64_t n,
+                            const Layout& ly, const float* R, float* Q, float* A,
+                            const StepArgs& st, hipStream_t s) {
+  const int64_t nblk = (n + 3) / 4;
+  const dim3 grid((unsigned)(((nblk + kXcds - 1) / kXcds) * kXcds));
+  hipLaunchKernelGGL((k_adj_chunk<MODE, NT>), grid, dim3(256), 0, s, dar->pat(), dar->tiles, ck,
+                     wt, (int)n, ly, R, Q, A, st);
+  return hipGetLastError();
+}
+
 template <int NT>
 hipError_t fwd_mode(const dode_dar* dar, const ChunkSched& cs, const WaveWork* wt, int64_t n,
                     const Layout& ly, const float* Q, const float* X, float* R, bool corr,
@@ -559,4 +694,16 @@ hipError_t mfma_minibatch(const dode_dar* dar, const CompSched& ks, const DayGro
     case 64: return minibatch_mode<4>(dar, ks, dg, ly, X, R, Q, A, st, s);
     default: return minibatch_mode<2>(dar, ks, dg, ly, X, R, Q, A, st, s);
   }
+}
+
+hipError_t mfma_adj_chunks(const dode_dar* dar, const ChunkList& ck, const WaveWork* wt, int64_t n,
+                           int32_t day_tile, const Layout& ly, const float* R, float* Q, float* A,
+                           const StepArgs& st, hipStream_t s) {
+  if (n > INT32_MAX || day_tile == 64) return hipErrorInvalidValue;
+  const bool fp8 = dar->storage == DODE_FP8_E4M3;
+  if (day_tile == 16)
+    return fp8 ? launch_adj_chunk<kFP8, 1>(dar, ck, wt, n, ly, R, Q, A, st, s)
+               : launch_adj_chunk<kBF16, 1>(dar, ck, wt, n, ly, R, Q, A, st, s);
+  return fp8 ? launch_adj_chunk<kFP8, 2>(dar, ck, wt, n, ly, R, Q, A, st, s)
+             : launch_adj_chunk<kBF16, 2>(dar, ck, wt, n, ly, R, Q, A, st, s);
 }

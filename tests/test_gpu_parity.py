@@ -398,7 +398,8 @@ def test_day_tile_gives_identical_results(storage):
     Q0 = torch.zeros((inst.D, inst.T, inst.P), dtype=torch.float32, device="cuda")
     outs = {}
     for tile, order, slabs in ((16, 1, 1), (32, 1, 1), (64, 1, 1), (16, 0, 1), (32, 0, 1),
-                               (64, 0, 1), (16, 1, 4), (32, 0, 2), (32, 1, 3), (0, 1, 1)):
+                               (64, 0, 1), (16, 2, 1), (32, 2, 1), (16, 1, 4), (32, 0, 2),
+                               (32, 1, 3), (32, 2, 2), (0, 1, 1)):
         p = dode.make_params(epochs=E, batch_rows=batch_rows, eta=5.0, day_tile=tile,
                              adj_order=order, slabs=slabs)
         plan = dode.spgd_plan_create(dar, inst.day_cluster, p, perm=perms, stream=0)
@@ -407,7 +408,7 @@ def test_day_tile_gives_identical_results(storage):
         sch = dode.spgd_plan_schedule(plan)
         assert info["day_tile"] == tile if tile else info["day_tile"] in (16, 32, 64)
         assert sch["day_tile"] == info["day_tile"]
-        assert sch["adj_order"] == order if tile else sch["adj_order"] in (0, 1)
+        assert sch["adj_order"] == order if tile else sch["adj_order"] in (0, 1, 2)
         assert sch["slabs"] == slabs if tile else sch["slabs"] in (1, 2, 4)
         groups = sum(-(-n // info["day_tile"]) for n in (70, 33, 1))
         assert info["n_day_groups"] == groups and info["minibatch_intervals"] == 6
@@ -429,10 +430,11 @@ def test_day_tile_gives_identical_results(storage):
 
 def test_schedule_tuner_times_every_candidate_and_remembers():
     """day_tile 0: the first plan of a shape times an epoch of every schedule
-    candidate (3 day tiles x 2 adjoint orders x 1, 2 or 4 day slabs, slab
-    counts above the number of day groups skipped) and keeps the fastest; a
-    second plan of the same shapes, storage and cluster sizes reuses that
-    choice without timing; another storage type is a new key."""
+    candidate (3 day tiles x 3 adjoint orders x 1, 2 or 4 day slabs; the
+    chunked order has no 64-day waves, and slab counts above the number of day
+    groups are skipped) and keeps the fastest; a second plan of the same
+    shapes, storage and cluster sizes reuses that choice without timing;
+    another storage type is a new key."""
     inst = make_instance(P=41, L=66, T=30, K=4, sizes=(50, 20), inc=0.15, pattern="corridor",
                          demand="gamma", noise="mult5", x_dtype="f32", seed=64)
     say("schedule tuner")
@@ -447,8 +449,8 @@ def test_schedule_tuner_times_every_candidate_and_remembers():
         dode.spgd_plan_load(plan, X, Q0)
         seen.append(dode.spgd_plan_schedule(plan))
     groups = {t: sum(-(-n // t) for n in (50, 20)) for t in (16, 32, 64)}
-    want = sum(2 * sum(1 for k in (1, 2, 4) if k <= groups[t]) for t in groups)
-    assert want == 14
+    want = sum((3 if t < 64 else 2) * sum(1 for k in (1, 2, 4) if k <= groups[t]) for t in groups)
+    assert want == 19
     assert seen[0]["n_timed"] == want and seen[0]["best_ms"] > 0
     assert seen[1]["n_timed"] == 0
     pick = ("day_tile", "adj_order", "slabs")
@@ -461,6 +463,9 @@ def test_day_tile_rejected():
     dar = make_dar(inst, "bf16")
     with pytest.raises(dode.DodeError, match="day_tile"):
         dode.spgd_plan_create(dar, inst.day_cluster, dode.make_params(day_tile=48), stream=0)
+    with pytest.raises(dode.DodeError, match="adj_order 2 needs day_tile"):
+        dode.spgd_plan_create(dar, inst.day_cluster, dode.make_params(day_tile=64, adj_order=2),
+                              stream=0)
 
 
 @pytest.mark.parametrize("name", ["ragged", "corridor"])

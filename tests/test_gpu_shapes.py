@@ -25,9 +25,10 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 
-def run_plan(inst, storage, E, perms, refine=0):
+def run_plan(inst, storage, E, perms, refine=0, adj_order=1):
     dar = make_dar(inst, storage, correction=refine > 0)
-    p = dode.make_params(epochs=E, batch_rows=8192, eta=5.0, refine_steps=refine)
+    p = dode.make_params(epochs=E, batch_rows=8192, eta=5.0, refine_steps=refine,
+                         adj_order=adj_order)
     plan = dode.spgd_plan_create(dar, inst.day_cluster, p, perm=perms, stream=0)
     Q0 = torch.zeros((inst.D, inst.T, inst.P), dtype=torch.float32, device="cuda")
     dode.spgd_plan_load(plan, dev(inst.x, torch.float32), Q0)
@@ -46,7 +47,7 @@ def test_config3_full_shape_bf16_plan():
     E = 3
     perms = make_perms(inst.seed + 1, E, inst.C, inst.H)
     bh = chunk_h_blocks(inst.L, inst.H, 8192)
-    Qg, hg, info = run_plan(inst, "bf16", E, perms)
+    Qg, hg, info = run_plan(inst, "bf16", E, perms, adj_order=2)
     assert info["day_tile"] in (16, 32, 64) and info["minibatch_intervals"] == bh == 16
     sample = np.concatenate([[d[0], d[-1]] for d in (inst.days_of(c) for c in range(inst.C))])
     Wq = dequantized_values(inst, "bf16")
@@ -64,7 +65,7 @@ def test_config5_shape_fp8_refinement_plan():
     E, R = 3, 2
     perms = make_perms(1902, E, inst.C, inst.H)
     bh = chunk_h_blocks(inst.L, inst.H, 8192)
-    Qg, hg, info = run_plan(inst, "fp8", E, perms, refine=R)
+    Qg, hg, info = run_plan(inst, "fp8", E, perms, refine=R, adj_order=2)
     assert info["minibatch_intervals"] == bh == 5 and info["day_tile"] > 0
     sample = np.array([0, 35, 36, 40, 42])
     Wq = dequantized_values(inst, "fp8")
