@@ -516,7 +516,9 @@ std::vector<WaveWork> work_table(const dode_dar* dar, const std::vector<int32_t>
   const int32_t* ks = fwd ? m.data() + nLT : m.data() + 3 * nLT + nPT;
   const int32_t* lo = fwd ? m.data() : m.data() + 3 * nLT;
   const int32_t* ko = fwd ? m.data() + 2 * nLT : m.data() + 3 * nLT + 2 * nPT;
-  const int32_t n_tiles = fwd ? nLT : nPT;
+  // forward waves take a group of kFwdTileGroup link tiles (tile = its first)
+  const int32_t step = fwd ? kFwdTileGroup : 1;
+  const int32_t n_tiles = fwd ? (nLT + step - 1) / step : nPT;
   const int32_t per = tile_major ? n_tiles : rows, inner = tile_major ? rows : n_tiles;
   std::vector<WaveWork> out;
   out.reserve((size_t)gc.size() * rows * n_tiles);
@@ -526,7 +528,7 @@ std::vector<WaveWork> work_table(const dode_dar* dar, const std::vector<int32_t>
     for (int32_t u = 0; u < per; ++u)
       for (size_t g = g0; g < g1; ++g)
         for (int32_t k = 0; k < inner; ++k) {
-          const int32_t row = tile_major ? k : u, tile = tile_major ? u : k;
+          const int32_t row = tile_major ? k : u, tile = (tile_major ? u : k) * step;
           out.push_back(WaveWork{gc[g0], gf[g], gn[g], row, tile, ks[tile], lo[tile], ko[tile]});
         }
     g0 = g1;

@@ -49,6 +49,11 @@ struct DevVals {
   int32_t n_ptile;       // ceil(P/64)
 };
 
+// Forward link tiles come in groups of kFwdTileGroup that share one OD range
+// (the range covering all of them): one wave multiplies the group's tiles
+// with the same demand operand.
+constexpr int32_t kFwdTileGroup = 2;
+
 // Dense MFMA tiles of the assignment blocks (BF16 / FP8 storage).
 //   forward:  link tile i (16 links) x OD hull [f_plo[i], f_plo[i] + 32*f_ks[i])
 //   adjoint:  OD tile j (16 ODs) x link hull [g_alo[j], g_alo[j] + 32*g_ks[j])

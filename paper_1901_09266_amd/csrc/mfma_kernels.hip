@@ -231,6 +231,119 @@ __device__ __forceinline__ void fwd_item(const DevPat& pt, const DevTiles& tl, c
 // Forward product and residual of the minibatch rows, one wave per item
 // (cluster, slot s, day group g, link tile i) in the order of decode_item;
 // 4 items per block, blocks remapped so each XCD walks a contiguous range.
+// Forward product and residual for a group of TP link tiles i0..i0+TP-1
+// (kFwdTileGroup) of one minibatch slot and day group: the tiles share their
+// OD range, so each demand operand (and its head/tail split) is loaded once
+// per k-step and multiplied with every tile of the group.  Per tile the
+// products come in increasing lag and k-step order, as in fwd_item.  Tile
+// i0+tt's k-steps follow tile i0's in the packed blocks (equal counts).
+template <int MODE, int NT, int TP>
+__device__ __forceinline__ void fwd_group(const DevPat& pt, const DevTiles& tl, const Layout& ly,
+                                          const WaveWork& w, int h, const float* __restrict__ Q,
+                                          const float* __restrict__ X, float* __restrict__ R) {
+  constexpr int kBatch = NT == 2 ? 2 : 4 / NT;
+  const int lane = threadIdx.x & 63;
+  const int n = lane & 15, kg = lane >> 4;
+  const int c = w.c, s = w.row, i0 = w.tile;
+  const int first = w.first, cnt = w.count;
+  const int n_tt = min(TP, tl.nLT - i0);   // tiles of this group (the last may be short)
+  bool live[NT];
+  const float* qcol[NT];
+  f32x4 x[TP][NT];
+#pragma unroll
+  for (int u = 0; u < NT; ++u) {
+    live[u] = 16 * u + n < cnt;
+    const int64_t du = live[u] ? first + 16 * u + n : first;
+    qcol[u] = Q + du * ly.q_d;
+#pragma unroll
+    for (int tt = 0; tt < TP; ++tt)
+      x[tt][u] = tt < n_tt ? load4(X + du * ly.x_d + h * ly.x_h + ((16 * (i0 + tt) + 4 * kg) >> 2) * ly.x_b)
+                           : f32x4{0.f, 0.f, 0.f, 0.f};
+  }
+  const int l_lo = h - pt.T + 1 > 0 ? h - pt.T + 1 : 0;
+  const int l_hi = h < pt.K - 1 ? h : pt.K - 1;
+  const int nks = w.nks, plo = w.lo;
+  const int n_it = l_hi >= l_lo ? (l_hi - l_lo + 1) * nks : 0;
+  const int64_t kbase = (int64_t)c * pt.K * pt.T * tl.kf_total + w.koff;
+  f32x4 acc[TP][NT];
+#pragma unroll
+  for (int tt = 0; tt < TP; ++tt)
+#pragma unroll
+    for (int u = 0; u < NT; ++u) acc[tt][u] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const bf16x8 zero = __builtin_convertvector(f32x8{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, bf16x8);
+  int l = l_lo, ks = 0;
+  for (int it0 = 0; it0 < n_it; it0 += kBatch) {
+    bf16x8 a[kBatch][TP], ac[MODE == kFP8Corr ? kBatch : 1][TP];
+    f32x8 v[kBatch][NT];
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      const int t = h - l;
+      const int64_t kidx = kbase + ((int64_t)l * pt.T + t) * tl.kf_total + ks;
+      const int p0 = plo + 32 * ks + 4 * kg;
+#pragma unroll
+      for (int u = 0; u < NT; ++u) v[b][u] = load8(qcol[u] + t * ly.q_t + (p0 >> 2) * ly.q_b, ly.q_b);
+      float s0 = 1.f, s1 = 1.f;
+      if constexpr (MODE != kBF16) {
+        const float* scl = tl.scale + (((int64_t)c * pt.K + l) * pt.T + t) * tl.n_ptile;
+        s0 = scl[min(p0 >> 6, tl.n_ptile - 1)];
+        s1 = scl[min((p0 + 16) >> 6, tl.n_ptile - 1)];
+      }
+#pragma unroll
+      for (int tt = 0; tt < TP; ++tt) {
+        const int64_t kt = kidx + tt * nks;
+        if (tt >= n_tt || it0 + b >= n_it) {
+          a[b][tt] = zero;
+          if constexpr (MODE == kFP8Corr) ac[b][tt] = zero;
+        } else if constexpr (MODE == kFP8Corr) {
+          a[b][tt] = load_a_scaled(tl.Fv, kt, lane, s0, s1);
+          ac[b][tt] = load_corr(tl.Fc, kt, lane);
+        } else {
+          a[b][tt] = load_a<MODE>(tl.Fv, kt, lane);
+        }
+      }
+      if constexpr (MODE == kFP8) {
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+          v[b][u][0] *= s0; v[b][u][1] *= s0; v[b][u][2] *= s0; v[b][u][3] *= s0;
+          v[b][u][4] *= s1; v[b][u][5] *= s1; v[b][u][6] *= s1; v[b][u][7] *= s1;
+        }
+      }
+      if (it0 + b < n_it && it0 + b + 1 < n_it && ++ks == nks) {
+        ks = 0;
+        ++l;
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b)
+#pragma unroll
+      for (int u = 0; u < NT; ++u) {
+        const bf16x8 hi = __builtin_convertvector(v[b][u], bf16x8);
+        const bf16x8 lo = __builtin_convertvector(v[b][u] - __builtin_convertvector(hi, f32x8), bf16x8);
+#pragma unroll
+        for (int tt = 0; tt < TP; ++tt) {
+          acc[tt][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[b][tt], hi, acc[tt][u], 0, 0, 0);
+          acc[tt][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[b][tt], lo, acc[tt][u], 0, 0, 0);
+          if constexpr (MODE == kFP8Corr) {
+            acc[tt][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ac[b][tt], hi, acc[tt][u], 0, 0, 0);
+            acc[tt][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ac[b][tt], lo, acc[tt][u], 0, 0, 0);
+          }
+        }
+      }
+  }
+#pragma unroll
+  for (int tt = 0; tt < TP; ++tt) {
+    const int a0 = 16 * (i0 + tt) + 4 * kg;
+    if (tt >= n_tt || a0 >= pt.L) continue;
+    const bool full = a0 + 4 <= pt.L;
+    const int valid = pt.L - a0;
+#pragma unroll
+    for (int u = 0; u < NT; ++u)
+      if (live[u])
+        store4(R + (int64_t)(first + 16 * u + n) * ly.r_d + s * ly.r_s + (a0 >> 2) * ly.r_b,
+               acc[tt][u] - x[tt][u], full, valid);
+  }
+}
+
 // Work item of a wave: its entry of the launch's work table (one scalar load).
 __device__ __forceinline__ WaveWork load_work(const WaveWork* __restrict__ wt, int item) {
   const int4* p = reinterpret_cast<const int4*>(wt + item);
@@ -251,7 +364,7 @@ k_fwd_mfma(DevPat pt, DevTiles tl, ChunkSched cs, const WaveWork* __restrict__ w
   if (cs.j0 + w.row >= pt.H) return;
   cs = resolve_epoch(cs);
   const int h = cs.perm[w.c * pt.H + cs.j0 + w.row];
-  fwd_item<MODE, NT>(pt, tl, ly, w, h, Q, X, R);
+  fwd_group<MODE, NT, kFwdTileGroup>(pt, tl, ly, w, h, Q, X, R);
 }
 
 __device__ __forceinline__ f32x4 step4(f32x4 q, f32x4& a, const f32x4& g, const StepArgs& st) {

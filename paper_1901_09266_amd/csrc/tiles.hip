@@ -23,14 +23,17 @@ struct Hull {
   int32_t lo = 0, ks = 0;
 };
 
-// Covering ranges of `n_rows` rows grouped by 16, given per-row sorted column lists.
+// Covering ranges of `n_rows` rows grouped by 16, given per-row sorted column
+// lists; the tiles of each run of `group` consecutive tiles share the range
+// that covers all of them (one wave multiplies them with the same operand).
 std::vector<Hull> hulls(int32_t n_rows, int32_t n_cols, const std::vector<int32_t>& ptr,
-                        const std::vector<int32_t>& idx) {
+                        const std::vector<int32_t>& idx, int32_t group) {
   const int32_t nt = (n_rows + 15) / 16;
   std::vector<Hull> out(nt);
   for (int32_t i = 0; i < nt; ++i) {
+    const int32_t g0 = i / group * group;
     int32_t lo = n_cols, hi = 0;
-    for (int32_t r = 16 * i; r < std::min(n_rows, 16 * i + 16); ++r)
+    for (int32_t r = 16 * g0; r < std::min(n_rows, 16 * (g0 + group)); ++r)
       if (ptr[r + 1] > ptr[r]) {
         lo = std::min(lo, idx[ptr[r]]);
         hi = std::max(hi, idx[ptr[r + 1] - 1] + 1);
@@ -68,8 +71,8 @@ int64_t packed_pos(int32_t row, int32_t col, const std::vector<Hull>& hs,
 dode_status tiles_prepare(dode_dar* d, std::string& err) {
   const dode_dims& dm = d->dims;
   const int64_t nnz = d->nnz;
-  const std::vector<Hull> fh = hulls(dm.L, dm.P, d->h_row_ptr, d->h_col);
-  const std::vector<Hull> gh = hulls(dm.P, dm.L, d->h_col_ptr, d->h_row);
+  const std::vector<Hull> fh = hulls(dm.L, dm.P, d->h_row_ptr, d->h_col, kFwdTileGroup);
+  const std::vector<Hull> gh = hulls(dm.P, dm.L, d->h_col_ptr, d->h_row, 1);
   const int32_t nLT = (int32_t)fh.size(), nPT = (int32_t)gh.size();
   std::vector<int32_t> meta;
   std::vector<int32_t> fko(nLT + 1, 0), gko(nPT + 1, 0);
