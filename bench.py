@@ -569,8 +569,10 @@ def schedule_sweep(args, dode, torch, config, form):
     Q = torch.zeros((inst.D, inst.T, inst.P), dtype=torch.float32, device="cuda")
     rows = []
     for tile in (16, 32, 64):
-        for order in (0, 1):
+        for order in (0, 1, 2):
             for slabs in (1, 2, 4):
+                if order == 2 and tile == 64:
+                    continue
                 p = dode.make_params(epochs=E, batch_rows=8192, eta=5.0, refine_steps=refine,
                                      day_tile=tile, adj_order=order, slabs=slabs)
                 plan = dode.spgd_plan_create(dar, inst.day_cluster, p, perm=perms, stream=0)

@@ -419,10 +419,19 @@ dode_status run_chunk(dode_plan* plan, const ChunkSched& cs, const CompSched* ks
     HIP_TRY(timed(plan, 0, s, [&] {
       return mfma_chunk_resid(dar, cs, wt.fwd, wt.n_fwd, plan->day_tile, ly, Q, X, R, corr, s);
     }));
+    if (corr && plan->adj_order == 2 && plan->d_kchunk_full) {
+      // refinement steps: the chunked adjoint over every departure interval
+      const ChunkList full = plan->chunks_full();
+      HIP_TRY(timed(plan, 1, s, [&] {
+        return mfma_adj_chunks(dar, full, wt.adj[2], wt.n_adj[2], plan->day_tile, ly, R, Q, A,
+                               plan->sa, true, s);
+      }));
+      return DODE_OK;
+    }
     if (o == 2 && ckl && !corr) {
       HIP_TRY(timed(plan, 1, s, [&] {
         return mfma_adj_chunks(dar, *ckl, wt.adj[2], wt.n_adj[2], plan->day_tile, ly, R, Q, A,
-                               plan->sa, s);
+                               plan->sa, false, s);
       }));
       return DODE_OK;
     }
@@ -582,8 +591,11 @@ dode_status build_wave_tables(dode_plan* plan, const std::vector<std::vector<int
     const int32_t H = dar->dims.H, T = dar->dims.T;
     const auto f = work_table(dar, plan->h_gc, plan->h_gf, plan->h_gn, true, H, false);
     const auto a = work_table(dar, plan->h_gc, plan->h_gf, plan->h_gn, false, T, false);
+    const auto a2 = work_table(dar, plan->h_gc, plan->h_gf, plan->h_gn, false,
+                               std::max<int32_t>(1, plan->full_chunks), true);
     HIP_TRY(upload_table(f, &plan->wt_full.fwd, &plan->wt_full.n_fwd));
     HIP_TRY(upload_table(a, &plan->wt_full.adj[0], &plan->wt_full.n_adj[0]));
+    HIP_TRY(upload_table(a2, &plan->wt_full.adj[2], &plan->wt_full.n_adj[2]));
   }
   return DODE_OK;
 }
@@ -1568,7 +1580,7 @@ dode_status spgd_plan_destroy(dode_plan* plan) {
   if (plan->last_stream) (void)hipStreamSynchronize(plan->last_stream);
   for (void* p : {(void*)plan->d_perm, (void*)plan->d_pos, (void*)plan->d_touched,
                   (void*)plan->d_kslot, (void*)plan->d_kdesc, (void*)plan->d_kcomp,
-                  (void*)plan->d_kchunk,
+                  (void*)plan->d_kchunk, (void*)plan->d_kchunk_full,
                   (void*)plan->d_slabs,
                   (void*)plan->d_dc, plan->d_R, (void*)plan->d_part, (void*)plan->d_groups,
                   (void*)plan->d_full,
@@ -1644,6 +1656,7 @@ dode_status spgd_plan_create(const dode_dar* dar, const int32_t* day_cluster, in
       }
   p->n_slabs = std::max<int32_t>(1, params->slabs);
   p->refine_steps = params->refine_steps;   // the work tables cover refinement steps
+  p->full_chunks = p->refine_steps > 0 ? (dm.T + kChunkT - 1) / kChunkT : 0;
   if (dode_status st = set_day_groups(p, params->day_tile ? params->day_tile : 32)) return st;
   HIP_TRY(up(&p->d_order, order.data(), (size_t)D * 4));
   HIP_TRY(up(&p->d_dc, dc_plan.data(), (size_t)D * 4));
@@ -1697,6 +1710,23 @@ dode_status spgd_plan_create(const dode_dar* dar, const int32_t* day_cluster, in
         dsc[kDescMask + 1] = (int32_t)(uint32_t)(mask >> 32);
       }
     HIP_TRY(up(&p->d_full, full.data(), full.size() * 4));
+    // the full batch is one component per cluster: chunks of kChunkT
+    // consecutive departure intervals with the intervals h = slot that reach them
+    std::vector<int32_t> fc((size_t)C * p->full_chunks * p->chunk_w, 0);
+    for (int32_t c = 0; c < C; ++c)
+      for (int32_t k = 0; k < p->full_chunks; ++k) {
+        int32_t* ck = fc.data() + ((size_t)c * p->full_chunks + k) * p->chunk_w;
+        const int32_t t0 = k * kChunkT, nt = std::min(kChunkT, dm.T - t0);
+        ck[0] = t0;
+        ck[1] = nt;
+        int32_t nh = 0;
+        for (int32_t h = t0; h <= t0 + nt - 1 + dm.K - 1 && h < dm.H; ++h, ++nh) {
+          ck[3 + 2 * nh] = h;
+          ck[4 + 2 * nh] = h;
+        }
+        ck[2] = nh;
+      }
+    HIP_TRY(up(&p->d_kchunk_full, fc.data(), fc.size() * 4));
   }
   const int64_t r_rows = p->refine_steps > 0 ? std::max(bh, dm.H) : bh;
   const int64_t nR = r_rows * p->ly.r_s + kStatePad, nX = dm.H * p->ly.x_h + kStatePad;

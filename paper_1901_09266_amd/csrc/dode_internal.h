@@ -336,6 +336,8 @@ struct dode_plan {
   int32_t kmt = 0, max_comp = 0;
   int32_t* d_kchunk = nullptr;    // [E][nch][C][max_chunks][chunk_w] (ChunkList)
   int32_t max_chunks = 0, chunk_w = 0;
+  int32_t* d_kchunk_full = nullptr;   // refinement steps: [C][full_chunks][chunk_w]
+  int32_t full_chunks = 0;
   bool one_launch = false;        // matrix-core minibatches as one launch each
   int32_t adj_order = 0;          // ChunkSched::order of the matrix-core adjoint
   // Day slabs: the matrix-core epoch runs every minibatch on the day groups of
@@ -435,6 +437,8 @@ struct dode_plan {
                      d_kcomp + ee * cs + (int64_t)j * C * max_comp * 4, j * bh, bh, kmt, max_comp,
                      e < 0 ? d_epoch : nullptr, ps, ss, ds, cs};
   }
+  // reached-interval chunks of the full-batch refinement steps
+  ChunkList chunks_full() const { return ChunkList{d_kchunk_full, full_chunks, chunk_w, nullptr, 0}; }
   // reached-interval chunks of minibatch j of epoch e (e < 0: the epoch in d_epoch)
   ChunkList chunks(int32_t e, int32_t j) const {
     const int64_t per_e = (int64_t)nch * C * max_chunks * chunk_w;
@@ -554,11 +558,11 @@ hipError_t mfma_chunk_resid(const dode_dar* dar, const ChunkSched& cs, const Wav
 hipError_t mfma_chunk_adj_step(const dode_dar* dar, const ChunkSched& cs, const WaveWork* wt,
                                int64_t n_items, int32_t day_tile, const Layout& ly, const float* R,
                                float* Q, float* A, const StepArgs& st, bool corr, hipStream_t s);
-// adjoint + step by reached-interval chunks (day tiles 16 and 32; not for the
-// refinement steps)
+// adjoint + step by reached-interval chunks (day tiles 16 and 32; corr: the
+// corrected FP8 values of refinement steps)
 hipError_t mfma_adj_chunks(const dode_dar* dar, const ChunkList& ck, const WaveWork* wt, int64_t n,
                            int32_t day_tile, const Layout& ly, const float* R, float* Q, float* A,
-                           const StepArgs& st, hipStream_t s);
+                           const StepArgs& st, bool corr, hipStream_t s);
 // one whole minibatch (forward, residual, adjoint, step) in one launch
 hipError_t mfma_minibatch(const dode_dar* dar, const CompSched& ks, const DayGroups& dg,
                           const Layout& ly, const float* X, float* R, float* Q, float* A,

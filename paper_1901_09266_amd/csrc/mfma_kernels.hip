@@ -548,7 +548,7 @@ k_adj_chunk(DevPat pt, DevTiles tl, ChunkList ck, const WaveWork* __restrict__ w
   int h = cr[3], sl = cr[4];
   for (int it0 = 0; it0 < n_it; it0 += CB) {
     f32x8 v[CB][NT];
-    bf16x8 wa[CB][G];
+    bf16x8 wa[CB][G], wc[MODE == kFP8Corr ? CB : 1][G];
     float sc[CB][G];
     bool use[CB][G];
 #pragma unroll
@@ -563,10 +563,15 @@ k_adj_chunk(DevPat pt, DevTiles tl, ChunkList ck, const WaveWork* __restrict__ w
         use[b][k] = in && k < n_t && lag >= 0 && lag < pt.K;
         if (use[b][k]) {
           const int64_t kidx = kbase + ((int64_t)lag * pt.T + t0 + k) * tl.kg_total + ks;
-          wa[b][k] = load_a<MODE>(tl.Gv, kidx, lane);
-          if constexpr (MODE == kFP8)
+          if constexpr (MODE != kBF16)
             sc[b][k] = tl.scale[(((int64_t)c * pt.K + lag) * pt.T + t0 + k) * tl.n_ptile +
                                 ((16 * j) >> 6)];
+          if constexpr (MODE == kFP8Corr) {
+            wa[b][k] = load_a_scaled(tl.Gv, kidx, lane, sc[b][k], sc[b][k]);
+            wc[b][k] = load_corr(tl.Gc, kidx, lane);
+          } else {
+            wa[b][k] = load_a<MODE>(tl.Gv, kidx, lane);
+          }
         }
       }
       if (in && it0 + b + 1 < n_it && ++ks == nks) {
@@ -580,7 +585,7 @@ k_adj_chunk(DevPat pt, DevTiles tl, ChunkList ck, const WaveWork* __restrict__ w
     for (int b = 0; b < CB; ++b)
 #pragma unroll
       for (int u = 0; u < NT; ++u) {
-        if constexpr (MODE == kBF16) {
+        if constexpr (MODE != kFP8) {
           const bf16x8 hi = __builtin_convertvector(v[b][u], bf16x8);
           const bf16x8 lo =
               __builtin_convertvector(v[b][u] - __builtin_convertvector(hi, f32x8), bf16x8);
@@ -589,6 +594,10 @@ k_adj_chunk(DevPat pt, DevTiles tl, ChunkList ck, const WaveWork* __restrict__ w
             if (use[b][k]) {
               acc[k][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[b][k], hi, acc[k][u], 0, 0, 0);
               acc[k][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[b][k], lo, acc[k][u], 0, 0, 0);
+              if constexpr (MODE == kFP8Corr) {
+                acc[k][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wc[b][k], hi, acc[k][u], 0, 0, 0);
+                acc[k][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wc[b][k], lo, acc[k][u], 0, 0, 0);
+              }
             }
         } else {
 #pragma unroll
@@ -811,12 +820,16 @@ hipError_t mfma_minibatch(const dode_dar* dar, const CompSched& ks, const DayGro
 
 hipError_t mfma_adj_chunks(const dode_dar* dar, const ChunkList& ck, const WaveWork* wt, int64_t n,
                            int32_t day_tile, const Layout& ly, const float* R, float* Q, float* A,
-                           const StepArgs& st, hipStream_t s) {
+                           const StepArgs& st, bool corr, hipStream_t s) {
   if (n > INT32_MAX || day_tile == 64) return hipErrorInvalidValue;
+  if (corr && !dar->has_corr) return hipErrorInvalidValue;
   const bool fp8 = dar->storage == DODE_FP8_E4M3;
-  if (day_tile == 16)
+  if (day_tile == 16) {
+    if (corr) return launch_adj_chunk<kFP8Corr, 1>(dar, ck, wt, n, ly, R, Q, A, st, s);
     return fp8 ? launch_adj_chunk<kFP8, 1>(dar, ck, wt, n, ly, R, Q, A, st, s)
                : launch_adj_chunk<kBF16, 1>(dar, ck, wt, n, ly, R, Q, A, st, s);
+  }
+  if (corr) return launch_adj_chunk<kFP8Corr, 2>(dar, ck, wt, n, ly, R, Q, A, st, s);
   return fp8 ? launch_adj_chunk<kFP8, 2>(dar, ck, wt, n, ly, R, Q, A, st, s)
              : launch_adj_chunk<kBF16, 2>(dar, ck, wt, n, ly, R, Q, A, st, s);
 }

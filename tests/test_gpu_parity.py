@@ -577,3 +577,34 @@ def test_one_launch_minibatch_equals_two_launches(name, storage):
     bh = chunk_h_blocks(inst.L, inst.H, batch_rows)
     _, _, ho = orc.spgd(inst, inst.x.astype(np.float64), perms, E, bh, optimizer=0, eta=5.0, W=Wq)
     assert np.max(np.abs(outs[(2, 32)][2].T - ho) / ho) <= 1e-3
+
+
+def test_refinement_orders_give_identical_results():
+    """An FP8 plan with 2 refinement steps per epoch: with the chunked adjoint
+    (order 2) the refinement steps also run chunked over every departure
+    interval; the results are the bits of the interval-major adjoint (order 0)
+    for both day tiles, and the one-launch minibatch path agrees too."""
+    inst = make_instance(P=45, L=70, T=24, K=5, sizes=(70, 33, 3), inc=0.15, pattern="corridor",
+                         demand="gamma", noise="mult5", x_dtype="f32", seed=66)
+    say("refinement orders")
+    E = 4
+    perms = make_perms(67, E, inst.C, inst.H)
+    dar = make_dar(inst, "fp8", correction=True)
+    X = dev(inst.x, torch.float32)
+    Q0 = torch.zeros((inst.D, inst.T, inst.P), dtype=torch.float32, device="cuda")
+    outs = {}
+    for tile, order, path in ((32, 0, 0), (32, 2, 0), (16, 2, 0), (16, 0, 0), (32, 2, 2)):
+        p = dode.make_params(epochs=E, batch_rows=6 * inst.L, eta=5.0, refine_steps=2,
+                             day_tile=tile, adj_order=order, kernel_path=path)
+        plan = dode.spgd_plan_create(dar, inst.day_cluster, p, perm=perms, stream=0)
+        dode.spgd_plan_load(plan, X, Q0)
+        loss = torch.zeros((E, inst.D), dtype=torch.float64, device="cuda")
+        dode.spgd_run(plan, 0, E, loss=loss)
+        Q = torch.empty_like(Q0)
+        A = torch.empty_like(Q0)
+        dode.spgd_plan_store(plan, Q, A)
+        torch.cuda.synchronize()
+        outs[(tile, order, path)] = (Q.cpu().numpy(), A.cpu().numpy(), loss.cpu().numpy())
+    for key in outs:
+        for a, b in zip(outs[key], outs[(32, 0, 0)]):
+            np.testing.assert_array_equal(a, b)
