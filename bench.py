@@ -71,19 +71,69 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def counted_traffic(config, form, kernel, variant=""):
-    """HBM bytes per launch of `kernel` ("fwd" or "adj") from the committed
-    FETCH_SIZE / WRITE_SIZE counter summary of this workload and form, or None
-    when there is none or the kernel sources changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", f"traffic_spgd_config{config}{variant}_{form}.md")
+DAR_SOURCES = ("paper_1901_09266_amd/csrc/dar_kernels.hip",)
+# wave64 VALU instructions a second over the chip: one per CU per cycle
+# (unpacked FP32, 4 cycles a wave on each of 4 SIMDs), 256 CUs at 2.4 GHz
+VALU_PEAK_GINST = 256 * 2.4
+
+
+def profile_values(name, sources, keys):
+    """`key: value` lines of a committed profile summary, or {} when it is
+    missing or any of `sources` changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
-        return None
+        return {}
+    h = hashlib.sha256()
+    for f in sources:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
     vals = {}
     with open(path) as fh:
         for line in fh:
             line = line.strip().strip("`")
-            if ":" in line and line.split(":", 1)[0] in ("source_sha256", "fwd_bytes_per_launch",
-                                                         "adj_bytes_per_launch"):
+            if ":" in line and line.split(":", 1)[0] in keys + ("source_sha256",):
+                k, v = line.split(":", 1)
+                vals[k] = v.strip()
+    return vals if vals.get("source_sha256") == h.hexdigest() else {}
+
+
+def alu_roofline(profile, kernel, ms_per_step, hbm_bytes):
+    """ALU roofline of a VALU-bound job: the wave instructions one step issues
+    (SQ_INSTS_VALU summed over its dispatches, from the committed counter
+    summary) over the live step time, against VALU_PEAK_GINST; the HBM
+    figure of the same step beside it.  Falls back to the HBM bound alone
+    when there is no summary for the current kernel source."""
+    hbm = hbm_bytes / (ms_per_step / 1e3) / 1e9
+    vals = profile_values(profile, DAR_SOURCES, ("valu_instructions_per_step",))
+    if "valu_instructions_per_step" not in vals:
+        return {"bound": "hbm", "kernel": kernel, "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(hbm / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_step": hbm_bytes, "note": "no VALU counter summary for this kernel source"}
+    inst = float(vals["valu_instructions_per_step"])
+    rate = inst / (ms_per_step / 1e3) / 1e9
+    return {"bound": "alu", "kernel": kernel, "achieved": round(rate, 1), "peak": VALU_PEAK_GINST,
+            "unit": "G VALU wave-instructions/s", "frac": round(rate / VALU_PEAK_GINST, 4),
+            "traffic": None, "valu_instructions_per_step": inst,
+            "hbm": {"achieved_GBs": round(hbm, 1), "frac": round(hbm / HBM_PEAK_GBS, 4),
+                    "bytes_per_step": hbm_bytes}}
+
+
+def counted_traffic(config, form, kernel, variant=""):
+    """HBM bytes per launch of `kernel` ("fwd", "adj", or the refinement
+    steps' "refine_fwd" / "refine_adj") from the committed FETCH_SIZE /
+    WRITE_SIZE counter summary of this workload and form, or None when there
+    is none or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_spgd_config{config}{variant}_{form}.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    keys = ("source_sha256", "fwd_bytes_per_launch", "adj_bytes_per_launch",
+            "refine_fwd_bytes_per_launch", "refine_adj_bytes_per_launch")
+    with open(path) as fh:
+        for line in fh:
+            line = line.strip().strip("`")
+            if ":" in line and line.split(":", 1)[0] in keys:
                 k, v = line.split(":", 1)
                 vals[k] = v.strip()
     if vals.get("source_sha256") != kernel_source_hash() or f"{kernel}_bytes_per_launch" not in vals:
@@ -307,11 +357,13 @@ def dar_bench(args):
     n_pairs = si.path_link.shape[0]
     C = int(si.day_cluster.max()) + 1
     days = [np.nonzero(si.day_cluster == c)[0] for c in range(C)]
-    outs = [torch.empty((K, H, n_pairs), dtype=torch.float32, device="cuda") for _ in range(C)]
+    # the days of each pattern are consecutive: one call for all patterns
+    ptr = np.concatenate([[0], np.cumsum([len(d) for d in days])]).astype(np.int32)
+    assert all(d[0] == ptr[c] and d[-1] == ptr[c + 1] - 1 for c, d in enumerate(days))
+    outs = torch.empty((C, K, H, n_pairs), dtype=torch.float32, device="cuda")
 
     def step():
-        for c in range(C):
-            dode.dode_dar_from_speeds(pp, pl, ln, sp[days[c][0]:days[c][-1] + 1], si.dt, H, K, Rr=outs[c])
+        dode.dode_dar_patterns_from_speeds(pp, pl, ln, sp, ptr, si.dt, H, K, Rr=outs)
 
     for _ in range(args.warmup):
         step()
@@ -327,17 +379,15 @@ def dar_bench(args):
     # algorithmic bytes per step: every day's speeds read once, every pattern's
     # ratios written once (the trajectory scratch is the implementation's)
     byts = D * si.L * H * 4 + C * K * H * n_pairs * 4
-    achieved = byts / (ms / args.steps / 1e3) / 1e9
     out = {"metric": "DAR construction days/sec", "value": round(D * args.steps / (ms / 1e3), 1),
            "unit": "days/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(ms / args.steps, 4), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": f"{si.path_ptr.shape[0] - 1} paths of 40 links on 500 corridor links, "
                                   f"H=288, K={K}, {D} days in {C} patterns (400..15)"},
-           "roofline": {"bound": "hbm", "kernel": "dode_dar_from_speeds (whole call, all patterns)",
-                        "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                        "bytes_per_step": byts}}
+           "roofline": alu_roofline("kernel_time_dar_from_speeds_corridor.md",
+                                    "dode_dar_patterns_from_speeds (one call, all patterns)",
+                                    ms / args.steps, byts)}
     if not args.skip_cpu:
         import oracle as orc
         sample = days[0][:300]     # about 10 s of the single-threaded oracle
@@ -376,25 +426,29 @@ def choice_bench(args):
     C = len(ci.sizes)
     days = [np.nonzero(ci.day_cluster == c)[0] for c in range(C)]
     f32 = torch.float32
-    Rr = [torch.empty((K, H, ci.n_pairs), dtype=f32, device="cuda") for _ in range(C)]
-    cost = [torch.empty((T, ci.n_paths), dtype=f32, device="cuda") for _ in range(C)]
+    assert T == H
+    ptr = np.concatenate([[0], np.cumsum([len(d) for d in days])]).astype(np.int32)
+    assert all(d[0] == ptr[c] and d[-1] == ptr[c + 1] - 1 for c, d in enumerate(days))
+    Rr = torch.empty((C, K, H, ci.n_pairs), dtype=f32, device="cuda")
+    cost = torch.empty((C, H, ci.n_paths), dtype=f32, device="cuda")
     W = [torch.empty((K, T, ci.nnz), dtype=f32, device="cuda") for _ in range(C)]
     ev = lambda: torch.cuda.Event(enable_timing=True)
     stage_ms = {"dar": 0.0, "assign": 0.0}
 
     def step(timed):
+        # one call for the ratios and costs of every pattern, then the assignment per pattern
+        e = [ev() for _ in range(3)] if timed else None
+        if timed:
+            e[0].record()
+        dode.dode_dar_patterns_from_speeds(pp, pl, ln, sp, ptr, ci.dt, H, K, Rr=Rr, cost=cost,
+                                           with_costs=True)
+        if timed:
+            e[1].record()
         for c in range(C):
-            s = sp[days[c][0]:days[c][-1] + 1]
-            e = [ev() for _ in range(3)] if timed else None
-            if timed:
-                e[0].record()
-            dode.dode_dar_costs_from_speeds(pp, pl, ln, s, ci.dt, H, K, Rr=Rr[c], cost=cost[c])
-            if timed:
-                e[1].record()
             dode.dar_from_costs(routes, Rr[c], cost[c], theta, W[c])
-            if timed:
-                e[2].record()
-                marks.append(e)
+        if timed:
+            e[2].record()
+            marks.append(e)
 
     for _ in range(args.warmup):
         step(False)
@@ -415,9 +469,7 @@ def choice_bench(args):
     spd = D * ci.L * H * 4
     byts = {"dar": spd + C * (K * H * ci.n_pairs + T * ci.n_paths) * 4,
             "assign": C * (K * T * ci.n_pairs + T * ci.n_paths + K * T * ci.nnz) * 4}
-    dom = max(per, key=per.get)
-    achieved = byts[dom] / (per[dom] / 1e3) / 1e9
-    names = {"dar": "dode_dar_costs_from_speeds", "assign": "dar_from_costs"}
+    names = {"dar": "dode_dar_patterns_from_speeds", "assign": "dar_from_costs"}
     out = {"metric": "Route-choice assignment from speeds days/sec",
            "value": round(D * args.steps / (ms / 1e3), 1), "unit": "days/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms / args.steps, 4),
@@ -427,10 +479,10 @@ def choice_bench(args):
                                   f"(freeway/arterial), H=288, K={K}, theta=0.01/s, {D} days in "
                                   f"{C} patterns (400..15)"},
            "stages_ms_per_step": {names[k]: round(v, 4) for k, v in per.items()},
-           "roofline": {"bound": "hbm", "kernel": f"{names[dom]} (whole call, all patterns)",
-                        "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                        "bytes_per_step": byts[dom]}}
+           # the ratio call dominates the step (over 90 %)
+           "roofline": alu_roofline("kernel_time_route_choice_corridor.md",
+                                    "dode_dar_patterns_from_speeds (whole call, all patterns)",
+                                    per["dar"], byts["dar"])}
     if not args.skip_cpu:
         import oracle as orc
         sample = days[0][:48]
@@ -661,16 +713,26 @@ def spgd_leg(args, dode, torch, config, form, compare, refine, pattern=None, per
     names = ["chunk_resid (forward + residual)", "chunk_adj_step (adjoint + Adagrad + projection)"]
     k = int(np.argmax(kms[:2]))
     ep_launch = kn[k] / args.steps               # launches of the dominant kernel per epoch
-    traffic = None if pattern == "bernoulli" else counted_traffic(
-        config, form, ("fwd", "adj")[k], "_perday" if per_day else "")
-    traffic_other = None if pattern == "bernoulli" else counted_traffic(
-        config, form, ("adj", "fwd")[k], "_perday" if per_day else "")
+    variant = "_perday" if per_day else ""
+    look = (lambda name: None) if pattern == "bernoulli" else (
+        lambda name: counted_traffic(config, form, name, variant))
+    traffic, traffic_other = look(("fwd", "adj")[k]), look(("adj", "fwd")[k])
+    # counted HBM bytes of one epoch: every minibatch's two launches, and the
+    # refinement steps' full-batch launches
+    epoch_traffic = None
+    if traffic is not None and traffic_other is not None:
+        epoch_traffic = (traffic + traffic_other) * (ep_launch - rf[form])
+        if rf[form]:
+            rfw, rad = look("refine_fwd"), look("refine_adj")
+            epoch_traffic = None if rfw is None or rad is None else \
+                epoch_traffic + (rfw + rad) * rf[form]
     sched_b = (head["fwd_bytes"] + head["adj_bytes"]) / args.steps
     roof = {"bound": "hbm", "kernel": "whole epoch (every minibatch launch of one epoch)",
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": (round((traffic + traffic_other) * ep_launch)
-                        if traffic is not None and traffic_other is not None else None),
+            "traffic": round(epoch_traffic) if epoch_traffic is not None else None,
+            "traffic_over_bytes": (round(epoch_traffic / B, 2) if epoch_traffic is not None
+                                   else None),
             "bytes_per_epoch": int(B),
             "bytes_basis": "survey 8(d): ratio nonzeros once + per day X read, Q read+write "
                            f"({ {'f64': 8, 'f32': 4}.get(form, 2)} B), A read+write (4 B)",
@@ -678,6 +740,7 @@ def spgd_leg(args, dode, torch, config, form, compare, refine, pattern=None, per
             "dominant_kernel": {
                 "name": names[k], "avg_launch_us": round(kms[k] / kn[k] * 1e3, 2),
                 "launches_per_epoch": ep_launch,
+                "of_which_refinement": rf[form],
                 "share_of_epoch": round(kms[k] / args.steps / ms_step, 4),
                 "schedule_bytes_per_launch": round((head["fwd_bytes"], head["adj_bytes"])[k] / kn[k]),
                 "schedule_GBps": round((head["fwd_bytes"], head["adj_bytes"])[k] / (kms[k] / 1e3) / 1e9, 1),

@@ -334,6 +334,25 @@ dode_status dode_dar_costs_from_speeds(int32_t n_paths, const int32_t* path_ptr,
                                        int32_t f64, void* Rr, void* cost, void* stream);
 
 /*
+ * The ratios of several traffic patterns in one call, and optionally their
+ * mean path costs (sections "Dynamic assignment ratio" and "Route choice
+ * portions"; eqs. "dar2"/"dar", "cost", "logit"): pattern q averages days
+ * pattern_ptr[q] .. pattern_ptr[q+1]-1 of speed [D][L][H_speed].
+ *   pattern_ptr host [n_patterns+1], from 0 to D, every pattern non-empty
+ *   Rr dev [n_patterns][K][H][n_pairs]; cost dev [n_patterns][H][n_paths] or NULL
+ * Each pattern's results are the bits of dode_dar_costs_from_speeds on its
+ * days.  The path tables and all D days' speeds are checked once for the job
+ * (one read-back, one synchronisation), the scratch is allocated once; errors
+ * as for dode_dar_from_speeds (DODE_ERR_SHAPE also for a malformed pattern_ptr).
+ */
+dode_status dode_dar_patterns_from_speeds(int32_t n_paths, const int32_t* path_ptr,
+                                          const int32_t* path_link, int64_t n_pairs, int32_t L,
+                                          const void* link_len, const void* speed,
+                                          int32_t n_patterns, const int32_t* pattern_ptr,
+                                          int32_t H_speed, double dt, int32_t H, int32_t K,
+                                          int32_t f64, void* Rr, void* cost, void* stream);
+
+/*
  * Mean path travel times of a traffic pattern (section "Route choice
  * portions", eqs. "logit" and "rt"; section "Link/path travel time",
  * eq. "cost").  Path tables, lengths and speeds as for dode_dar_from_speeds

@@ -10,7 +10,7 @@ from ._lib import (DodeError, Dar, SpgdParams, STORAGE, EXPORTS, lib, dar_create
                    spgd_plan_timing, spgd_plan_info, spgd_plan_schedule, dode_loss_bwd, Routes, dode_routes_create,
                    dar_from_logits,
                    dar_logits_bwd, dode_dar_from_speeds, dode_path_costs, dar_from_costs,
-                   dense_spgd_run, dode_dar_costs_from_speeds)
+                   dense_spgd_run, dode_dar_costs_from_speeds, dode_dar_patterns_from_speeds)
 
 __all__ = ["DodeError", "Dar", "SpgdParams", "STORAGE", "EXPORTS", "lib", "dar_create", "dar_info",
            "dar_set_values", "dode_apply", "dode_loss", "dode_loss_noalloc", "dode_grad",
@@ -19,4 +19,4 @@ __all__ = ["DodeError", "Dar", "SpgdParams", "STORAGE", "EXPORTS", "lib", "dar_c
            "spgd_plan_timing", "spgd_plan_info", "spgd_plan_schedule", "dode_loss_bwd", "Routes", "dode_routes_create",
            "dar_from_logits",
            "dar_logits_bwd", "dode_dar_from_speeds", "dode_path_costs", "dar_from_costs",
-           "dense_spgd_run", "dode_dar_costs_from_speeds"]
+           "dense_spgd_run", "dode_dar_costs_from_speeds", "dode_dar_patterns_from_speeds"]

@@ -32,7 +32,7 @@ EXPORTS = ["dode_last_error", "dode_spgd_defaults", "dar_create", "dar_create_ex
            "spgd_plan_schedule",
            "dode_loss_bwd", "dode_routes_create", "dode_routes_destroy", "dar_from_logits",
            "dar_logits_bwd", "dode_dar_from_speeds", "dode_path_costs", "dar_from_costs",
-           "dense_spgd_run", "dode_dar_costs_from_speeds"]
+           "dense_spgd_run", "dode_dar_costs_from_speeds", "dode_dar_patterns_from_speeds"]
 
 
 class DodeError(RuntimeError):
@@ -78,6 +78,8 @@ def lib():
                                            i32, vp, vp]
         L.dode_dar_costs_from_speeds.argtypes = [i32, vp, vp, i64, i32, vp, vp, i32, i32, dbl, i32,
                                                  i32, i32, vp, vp, vp]
+        L.dode_dar_patterns_from_speeds.argtypes = [i32, vp, vp, i64, i32, vp, vp, i32, P(i32), i32,
+                                                    dbl, i32, i32, i32, vp, vp, vp]
         L.dode_path_costs.argtypes = [i32, vp, vp, i64, i32, vp, vp, i32, i32, dbl, i32, i32, vp, vp]
         L.dar_from_costs.argtypes = [vp, i32, vp, vp, dbl, vp, vp, vp]
         L.dense_spgd_run.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp, i32, i32, i32, dbl, dbl,
@@ -508,6 +510,45 @@ def dode_dar_costs_from_speeds(path_ptr, path_link, link_len, speed, dt, H, K, R
         n_paths, path_ptr.data_ptr(), path_link.data_ptr(), n_pairs, L, link_len.data_ptr(),
         speed.data_ptr(), n_days, H_speed, float(dt), H, K, int(f64), Rr.data_ptr(),
         cost.data_ptr() if cost is not None else None, _stream(stream)))
+    return Rr, cost
+
+
+def dode_dar_patterns_from_speeds(path_ptr, path_link, link_len, speed, pattern_ptr, dt, H, K,
+                                  Rr=None, cost=None, with_costs=False, stream=None):
+    """The ratios (and with_costs the mean path costs) of several traffic
+    patterns in one call: pattern q holds days pattern_ptr[q] ..
+    pattern_ptr[q+1]-1 of speed [D][L][H_speed].  Returns (Rr [n_patterns][K][H]
+    [n_pairs], cost [n_patterns][H][n_paths] or None)."""
+    import torch
+    n_days, L, H_speed = speed.shape
+    f64 = speed.dtype == torch.float64
+    n_paths = path_ptr.numel() - 1
+    n_pairs = path_link.numel()
+    pp = np.ascontiguousarray(pattern_ptr, dtype=np.int32)
+    nq = pp.size - 1
+    if nq < 1 or pp[-1] != n_days:
+        raise ValueError(f"pattern_ptr must run from 0 to the {n_days} days of speed")
+    if Rr is None:
+        Rr = torch.empty((nq, K, H, n_pairs), dtype=speed.dtype, device=speed.device)
+    if with_costs and cost is None:
+        cost = torch.empty((nq, H, n_paths), dtype=speed.dtype, device=speed.device)
+    if not with_costs:
+        cost = None
+    for t in (path_ptr, path_link, link_len, speed, Rr) + ((cost,) if cost is not None else ()):
+        if not t.is_contiguous():
+            raise ValueError("arrays must be contiguous")
+    if link_len.dtype != speed.dtype or Rr.dtype != speed.dtype or (
+            cost is not None and cost.dtype != speed.dtype):
+        raise ValueError("link_len, speed, Rr and cost must share one dtype")
+    if tuple(Rr.shape) != (nq, K, H, n_pairs):
+        raise ValueError(f"Rr must be [{nq}][{K}][{H}][{n_pairs}]")
+    if cost is not None and tuple(cost.shape) != (nq, H, n_paths):
+        raise ValueError(f"cost must be [{nq}][{H}][{n_paths}]")
+    _check(lib().dode_dar_patterns_from_speeds(
+        n_paths, path_ptr.data_ptr(), path_link.data_ptr(), n_pairs, L, link_len.data_ptr(),
+        speed.data_ptr(), nq, pp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), H_speed,
+        float(dt), H, K, int(f64), Rr.data_ptr(), cost.data_ptr() if cost is not None else None,
+        _stream(stream)))
     return Rr, cost
 
 

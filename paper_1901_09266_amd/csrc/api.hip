@@ -1391,12 +1391,20 @@ dode_status check_paths_speeds(int32_t n_paths, const int32_t* path_ptr, const i
 
 }  // namespace
 
-dode_status dode_dar_costs_from_speeds(int32_t n_paths, const int32_t* path_ptr,
-                                       const int32_t* path_link, int64_t n_pairs, int32_t L,
-                                       const void* link_len, const void* speed, int32_t n_days,
-                                       int32_t H_speed, double dt, int32_t H, int32_t K,
-                                       int32_t f64, void* Rr, void* cost, void* stream) {
-  if (n_paths < 1 || n_pairs < 0 || L < 1 || n_days < 1 || H_speed < 1 || H < 1)
+dode_status dode_dar_patterns_from_speeds(int32_t n_paths, const int32_t* path_ptr,
+                                          const int32_t* path_link, int64_t n_pairs, int32_t L,
+                                          const void* link_len, const void* speed,
+                                          int32_t n_patterns, const int32_t* pattern_ptr,
+                                          int32_t H_speed, double dt, int32_t H, int32_t K,
+                                          int32_t f64, void* Rr, void* cost, void* stream) {
+  if (n_patterns < 1 || !pattern_ptr)
+    return fail(DODE_ERR_ARG, "n_patterns=%d must be >= 1 and pattern_ptr non-NULL", n_patterns);
+  if (pattern_ptr[0] != 0) return fail(DODE_ERR_SHAPE, "pattern_ptr[0] must be 0");
+  for (int32_t q = 0; q < n_patterns; ++q)
+    if (pattern_ptr[q + 1] <= pattern_ptr[q])
+      return fail(DODE_ERR_SHAPE, "pattern %d has no days (pattern_ptr must increase)", q);
+  const int32_t n_days = pattern_ptr[n_patterns];
+  if (n_paths < 1 || n_pairs < 0 || L < 1 || H_speed < 1 || H < 1)
     return fail(DODE_ERR_SHAPE, "n_paths=%d n_pairs=%lld L=%d n_days=%d H_speed=%d H=%d", n_paths,
                 (long long)n_pairs, L, n_days, H_speed, H);
   if (K < 1 || K > kMaxDarLags) return fail(DODE_ERR_SHAPE, "K=%d outside [1, %d]", K, kMaxDarLags);
@@ -1404,11 +1412,12 @@ dode_status dode_dar_costs_from_speeds(int32_t n_paths, const int32_t* path_ptr,
   if (!path_ptr || !path_link || !link_len || !speed || !Rr)
     return fail(DODE_ERR_ARG, "path_ptr, path_link, link_len, speed or Rr is NULL");
   hipStream_t s = as_stream(stream);
+  // one check of the path tables and of every day's speeds for the whole job
   if (dode_status st = check_paths_speeds(n_paths, path_ptr, path_link, n_pairs, L, link_len, speed,
                                           n_days, H_speed, f64 != 0, s))
     return st;
   // trajectory scratch (and path exit times) for a chunk of days, at most
-  // 4 GiB or DODE_DAR_SCRATCH_BYTES (at least one day)
+  // 4 GiB or DODE_DAR_SCRATCH_BYTES (at least one day), shared by the patterns
   const size_t ss = f64 ? 8 : 4;
   const size_t per_day = ((size_t)n_pairs + (cost ? (size_t)n_paths : 0)) * (H + 1) * ss;
   size_t limit = size_t(1) << 32;
@@ -1419,16 +1428,35 @@ dode_status dode_dar_costs_from_speeds(int32_t n_paths, const int32_t* path_ptr,
       return fail(DODE_ERR_ARG, "DODE_DAR_SCRATCH_BYTES='%s' is not a positive byte count", e);
     limit = (size_t)v;
   }
+  int32_t most = 0;
+  for (int32_t q = 0; q < n_patterns; ++q) most = std::max(most, pattern_ptr[q + 1] - pattern_ptr[q]);
   const size_t cap = std::max<size_t>(1, limit / std::max<size_t>(per_day, 1));
-  const int32_t chunk = (int32_t)std::min<size_t>((size_t)n_days, cap);
+  const int32_t chunk = (int32_t)std::min<size_t>((size_t)most, cap);
   DevBuf traj, sums;
   HIP_TRY(traj.alloc(std::max<size_t>(per_day * chunk, 16), s));
   void* exit_time = static_cast<uint8_t*>(traj.p) + (size_t)n_pairs * (H + 1) * ss * chunk;
   if (cost) HIP_TRY(sums.alloc((size_t)n_paths * H * 8, s));
-  HIP_TRY(dar_from_speeds(f64 != 0, n_paths, path_ptr, path_link, n_pairs, L, link_len, speed, n_days,
-                          H_speed, dt, H, K, traj.p, chunk, Rr, exit_time, sums.as<double>(), cost,
-                          s));
+  for (int32_t q = 0; q < n_patterns; ++q) {
+    const int32_t d0 = pattern_ptr[q], nd = pattern_ptr[q + 1] - d0;
+    const void* sp = static_cast<const uint8_t*>(speed) + (size_t)d0 * L * H_speed * ss;
+    void* rq = static_cast<uint8_t*>(Rr) + (size_t)q * K * H * n_pairs * ss;
+    void* cq = cost ? static_cast<uint8_t*>(cost) + (size_t)q * H * n_paths * ss : nullptr;
+    HIP_TRY(dar_from_speeds(f64 != 0, n_paths, path_ptr, path_link, n_pairs, L, link_len, sp, nd,
+                            H_speed, dt, H, K, traj.p, std::min(chunk, nd), rq, exit_time,
+                            sums.as<double>(), cq, s));
+  }
   return DODE_OK;
+}
+
+dode_status dode_dar_costs_from_speeds(int32_t n_paths, const int32_t* path_ptr,
+                                       const int32_t* path_link, int64_t n_pairs, int32_t L,
+                                       const void* link_len, const void* speed, int32_t n_days,
+                                       int32_t H_speed, double dt, int32_t H, int32_t K,
+                                       int32_t f64, void* Rr, void* cost, void* stream) {
+  if (n_days < 1) return fail(DODE_ERR_SHAPE, "n_days=%d must be >= 1", n_days);
+  const int32_t days[2] = {0, n_days};
+  return dode_dar_patterns_from_speeds(n_paths, path_ptr, path_link, n_pairs, L, link_len, speed,
+                                       1, days, H_speed, dt, H, K, f64, Rr, cost, stream);
 }
 
 dode_status dode_dar_from_speeds(int32_t n_paths, const int32_t* path_ptr,

@@ -236,3 +236,49 @@ def test_argument_checks():
         dode.dar_from_costs(r, Rr, cost, float("inf"), W)
     with pytest.raises(ValueError, match="cost"):
         dode.dar_from_costs(r, Rr, cost[:, :-1].contiguous(), THETA, W)
+
+
+@pytest.mark.parametrize("f64", [True, False])
+def test_patterns_in_one_call_equal_one_call_per_pattern(f64):
+    """dode_dar_patterns_from_speeds on three patterns of 4, 1 and 6 days
+    gives, pattern by pattern, the bits of dode_dar_costs_from_speeds on that
+    pattern's days (ratios and costs), also with a scratch cap that splits the
+    largest pattern; malformed pattern offsets are shape errors."""
+    ci = small(seed=5, days=(11,))
+    say("patterns in one call", f64)
+    t = torch.float64 if f64 else torch.float32
+    pp, pl = dev(ci.path_ptr, torch.int32), dev(ci.path_link, torch.int32)
+    ln, sp = dev(ci.link_len, t), dev(ci.speed, t)
+    ptr = np.array([0, 4, 5, 11], dtype=np.int32)
+    Rr, cost = dode.dode_dar_patterns_from_speeds(pp, pl, ln, sp, ptr, ci.dt, ci.H, ci.K,
+                                                  with_costs=True)
+    Rr_only, none = dode.dode_dar_patterns_from_speeds(pp, pl, ln, sp, ptr, ci.dt, ci.H, ci.K)
+    assert none is None
+    torch.cuda.synchronize()
+    for q in range(3):
+        r1, c1 = dode.dode_dar_costs_from_speeds(pp, pl, ln, sp[ptr[q]:ptr[q + 1]], ci.dt, ci.H,
+                                                 ci.K)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(Rr[q].cpu().numpy(), r1.cpu().numpy())
+        np.testing.assert_array_equal(Rr_only[q].cpu().numpy(), r1.cpu().numpy())
+        np.testing.assert_array_equal(cost[q].cpu().numpy(), c1.cpu().numpy())
+    for bad in ([0, 4, 4, 11], [1, 4, 5, 11], [0, 6, 5, 11]):
+        with pytest.raises((dode.DodeError, ValueError)):
+            dode.dode_dar_patterns_from_speeds(pp, pl, ln, sp, np.array(bad, np.int32), ci.dt,
+                                               ci.H, ci.K)
+
+
+def test_patterns_in_one_call_with_a_scratch_cap(monkeypatch):
+    """With the trajectory scratch capped at two days the patterns are split
+    into chunks: the same ratios as without the cap (days summed in order)."""
+    ci = small(seed=6, days=(9,))
+    say("patterns with scratch cap")
+    pp, pl = dev(ci.path_ptr, torch.int32), dev(ci.path_link, torch.int32)
+    ln, sp = dev(ci.link_len, torch.float64), dev(ci.speed, torch.float64)
+    ptr = np.array([0, 5, 9], dtype=np.int32)
+    full, _ = dode.dode_dar_patterns_from_speeds(pp, pl, ln, sp, ptr, ci.dt, ci.H, ci.K)
+    n_pairs = ci.path_link.shape[0]
+    monkeypatch.setenv("DODE_DAR_SCRATCH_BYTES", str(2 * n_pairs * (ci.H + 1) * 8))
+    capped, _ = dode.dode_dar_patterns_from_speeds(pp, pl, ln, sp, ptr, ci.dt, ci.H, ci.K)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(full.cpu().numpy(), capped.cpu().numpy())
