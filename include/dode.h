@@ -95,8 +95,12 @@ typedef struct {
                           tile, adjoint order, day slabs) by timing an epoch of
                           every candidate,
                           or reuse the choice made earlier in this process for
-                          the same shapes, storage and GPU (results are the
-                          same bits for every choice) */
+                          the same shapes, storage and GPU, or recorded for
+                          them in the file named by the environment variable
+                          DODE_SCHEDULE_CACHE (each new choice is appended
+                          there as "<key> TAB <day tile> <adj_order> <slabs>
+                          <ms>"; unreadable or invalid lines are skipped);
+                          results are the same bits for every choice */
   int32_t refine_steps;/* full-batch refinement steps after the minibatches of
                           every epoch: each is one step of Algorithm 1 with all
                           H intervals as its minibatch, computed with the
@@ -105,7 +109,11 @@ typedef struct {
   int32_t adj_order;   /* order of the matrix-core adjoint's work items when
                           day_tile != 0: 0 = by reached interval, OD tiles
                           fastest; 1 = by OD tile, reached intervals fastest
-                          (neighbouring waves share residual rows); same bits */
+                          (neighbouring waves share residual rows); 2 = as 1,
+                          with one wave per run of up to 6 consecutive reached
+                          intervals, which loads each residual row once for
+                          the run (also used by the refinement steps; not
+                          with day_tile 64, an argument error); same bits */
   int32_t slabs;       /* day slabs of a matrix-core epoch when day_tile != 0:
                           the epoch runs every minibatch on the first slab of
                           about D/slabs days, then on the next, so a slab's
@@ -476,11 +484,11 @@ dode_status spgd_plan_info(const dode_plan* plan, int32_t* day_tile, int32_t* n_
 
 /* Matrix-core schedule of a plan (any pointer may be NULL): the day tile,
  * adjoint item order and day slabs in use, the number of candidates timed at
- * load (0 when
- * given by the caller, or taken from this process's earlier choice for the
- * same P, L, T, H, K, b_h, storage, cluster sizes and GPU architecture), and
- * the time in milliseconds of the chosen candidate's trial minibatches (0 if
- * none ran).  A sparse-kernel plan reports day tile 0. */
+ * load (0 when given by the caller, or taken from this process's earlier
+ * choice or the DODE_SCHEDULE_CACHE file for the same P, L, T, H, K, b_h,
+ * storage, refinement steps, cluster sizes and GPU architecture), and the time
+ * in milliseconds of the chosen candidate's trial epoch (0 if none ran).  A
+ * sparse-kernel plan reports day tile 0. */
 dode_status spgd_plan_schedule(const dode_plan* plan, int32_t* day_tile, int32_t* adj_order,
                                int32_t* n_slabs, int32_t* n_timed, double* best_ms);
 

@@ -711,10 +711,51 @@ std::string tune_key(const dode_plan* plan) {
   return k;
 }
 
+// Schedule file named by DODE_SCHEDULE_CACHE (none when unset): one line per
+// choice, "<key>\t<day tile> <adjoint order> <slabs> <ms>".  Entries that do
+// not parse or name no valid schedule are skipped; the last valid entry of a
+// key wins.
+bool valid_schedule(const TunedSchedule& t) {
+  return (t.day_tile == 16 || t.day_tile == 32 || t.day_tile == 64) && t.adj_order >= 0 &&
+         t.adj_order <= 2 && !(t.adj_order == 2 && t.day_tile == 64) && t.n_slabs >= 1 &&
+         t.n_slabs <= 64;
+}
+
+bool read_schedule_file(const std::string& key, TunedSchedule* out) {
+  const char* path = getenv("DODE_SCHEDULE_CACHE");
+  if (!path || !*path) return false;
+  FILE* f = fopen(path, "r");
+  if (!f) return false;
+  bool found = false;
+  char line[1024];
+  while (fgets(line, sizeof line, f)) {
+    char* tab = strchr(line, '\t');
+    if (!tab || std::string(line, tab - line) != key) continue;
+    TunedSchedule t{};
+    if (sscanf(tab + 1, "%d %d %d", &t.day_tile, &t.adj_order, &t.n_slabs) == 3 &&
+        valid_schedule(t)) {
+      *out = t;
+      found = true;
+    }
+  }
+  fclose(f);
+  return found;
+}
+
+void append_schedule_file(const std::string& key, const TunedSchedule& t, double ms) {
+  const char* path = getenv("DODE_SCHEDULE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = fopen(path, "a");
+  if (!f) return;   // the choice still holds for this process
+  fprintf(f, "%s\t%d %d %d %.6f\n", key.c_str(), t.day_tile, t.adj_order, t.n_slabs, ms);
+  fclose(f);
+}
+
 // Choose the matrix-core schedule on the loaded state: every day tile
-// (16, 32, 64) with both adjoint item orders and 1, 2 or 4 day slabs, each
-// timed over one whole epoch (epoch 0) after one warm-up minibatch, fastest
-// kept and remembered for the same key.  The runs change the plan's Q and A:
+// (16, 32, 64) with the three adjoint item orders (no chunked adjoint with
+// 64-day waves) and 1, 2 or 4 day slabs, each timed over one whole epoch
+// (epoch 0) after one warm-up minibatch, fastest kept and remembered for the
+// same key in this process and in the schedule file.  The runs change the plan's Q and A:
 // the caller reloads them.
 dode_status tune_schedule(dode_plan* plan, hipStream_t s) {
   static const int32_t kTiles[] = {16, 32, 64};
@@ -723,12 +764,15 @@ dode_status tune_schedule(dode_plan* plan, hipStream_t s) {
   {
     std::lock_guard<std::mutex> lock(g_tune_mu);
     auto it = g_tuned.find(key);
-    if (it != g_tuned.end()) {
-      plan->adj_order = it->second.adj_order;
-      plan->n_slabs = it->second.n_slabs;
+    TunedSchedule known{};
+    if (it != g_tuned.end() || read_schedule_file(key, &known)) {
+      if (it != g_tuned.end()) known = it->second;
+      g_tuned[key] = known;
+      plan->adj_order = known.adj_order;
+      plan->n_slabs = known.n_slabs;
       plan->n_timed = 0;
       plan->tune_ms = 0.0;
-      return set_day_groups(plan, it->second.day_tile);
+      return set_day_groups(plan, known.day_tile);
     }
   }
   const bool timing = plan->timing;
@@ -777,6 +821,7 @@ dode_status tune_schedule(dode_plan* plan, hipStream_t s) {
   {
     std::lock_guard<std::mutex> lock(g_tune_mu);
     g_tuned[key] = best;
+    append_schedule_file(key, best, best_ms);
   }
   return set_day_groups(plan, best.day_tile);
 }

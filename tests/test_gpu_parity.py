@@ -458,6 +458,49 @@ def test_schedule_tuner_times_every_candidate_and_remembers():
     assert seen[2]["n_timed"] == want
 
 
+def test_schedule_file_is_read_and_appended(tmp_path, monkeypatch):
+    """DODE_SCHEDULE_CACHE: a plan whose key has a valid line in the file takes
+    that schedule without timing (the last valid line wins, invalid ones are
+    skipped); a plan of a new key tunes and appends its choice, which the file
+    then holds under the same key."""
+    inst = make_instance(P=37, L=54, T=24, K=3, sizes=(41, 23), inc=0.15, pattern="corridor",
+                         demand="gamma", noise="mult5", x_dtype="f32", seed=66)
+    say("schedule file")
+    perms = make_perms(67, 3, inst.C, inst.H)
+    X = dev(inst.x, torch.float32)
+    Q0 = torch.zeros((inst.D, inst.T, inst.P), dtype=torch.float32, device="cuda")
+    arch = torch.cuda.get_device_properties(0).gcnArchName
+    bh = 4
+    sizes = "".join(f"{n}," for n in np.bincount(inst.day_cluster))
+
+    def key(storage_code):
+        return f"{arch}|{inst.P},{inst.L},{inst.T},{inst.H},{inst.K}|{bh}|{storage_code}|0|{sizes}"
+
+    path = tmp_path / "schedules.txt"
+    # DODE_BF16 = 2, DODE_FP8_E4M3 = 3
+    path.write_text(f"{key(2)}\t32 1 1 0.5\n"
+                    f"{key(2)}\t64 2 1 0.1\n"       # invalid: no chunked 64-day waves
+                    f"{key(2)}\tgarbage\n"
+                    f"{key(2)}\t16 2 2 0.4\n"
+                    f"other-key\t64 0 1 0.2\n")
+    monkeypatch.setenv("DODE_SCHEDULE_CACHE", str(path))
+    got = []
+    for storage in ("bf16", "fp8"):
+        dar = make_dar(inst, storage)
+        p = dode.make_params(epochs=3, batch_rows=bh * inst.L, eta=5.0, day_tile=0)
+        plan = dode.spgd_plan_create(dar, inst.day_cluster, p, perm=perms, stream=0)
+        dode.spgd_plan_load(plan, X, Q0)
+        got.append(dode.spgd_plan_schedule(plan))
+    pick = ("day_tile", "adj_order", "slabs")
+    assert got[0]["n_timed"] == 0 and [got[0][k] for k in pick] == [16, 2, 2]
+    assert got[1]["n_timed"] > 0
+    lines = [ln.split("\t") for ln in path.read_text().splitlines()]
+    mine = [v.split() for k, v in lines if k == key(3)]
+    assert len(mine) == 1
+    assert [int(v) for v in mine[0][:3]] == [got[1][k] for k in pick]
+    assert abs(float(mine[0][3]) - got[1]["best_ms"]) <= 1e-5 * got[1]["best_ms"] + 1e-6
+
+
 def test_day_tile_rejected():
     inst = make_instance(P=10, L=12, T=6, K=2, sizes=(3,), inc=0.3, pattern="bernoulli", seed=63)
     dar = make_dar(inst, "bf16")
