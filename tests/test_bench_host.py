@@ -115,3 +115,26 @@ def test_epoch_bytes_is_the_touch_once_floor():
     assert bench.epoch_bytes(inst, "f32") == q32 + 8 * nblk * 6000 * 2
     # FP8 values: one byte per nonzero
     assert bench.epoch_bytes(inst, "fp8") == want - 8 * nblk * 6000
+
+
+def test_alu_roofline_follows_the_source_hash(monkeypatch, tmp_path):
+    """The ratio legs report the ALU bound from a committed VALU count only
+    while the kernel source hashes to the value recorded with it; otherwise
+    they fall back to the HBM figure and say why."""
+    import hashlib
+    src = tmp_path / "k.hip"
+    src.write_text("kernel text\n")
+    digest = hashlib.sha256(src.read_bytes()).hexdigest()
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    (prof / "p.md").write_text(f"# x\n\nsource_sha256: {digest}\n"
+                               "valu_instructions_per_step: 614400000000\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "DAR_SOURCES", ("k.hip",))
+    r = bench.alu_roofline("p.md", "kern", 1000.0, 8_000_000_000)
+    # 614.4e9 instructions in one second: exactly the ceiling
+    assert r["bound"] == "alu" and abs(r["frac"] - 1.0) < 1e-12
+    assert r["hbm"]["achieved_GBs"] == 8.0
+    src.write_text("kernel text, changed\n")
+    r = bench.alu_roofline("p.md", "kern", 1000.0, 8_000_000_000)
+    assert r["bound"] == "hbm" and "note" in r and r["achieved"] == 8.0
