@@ -158,8 +158,9 @@ def make_params(epochs=300, batch_rows=8192, eta=5.0, eps=1e-10, optimizer=0, ch
     one captured hipGraph per epoch; day_tile = days per matrix-core wave (16,
     32 or 64, or 0 to choose the schedule by timing at load); refine_steps =
     full-batch steps per epoch on corrected FP8 values; adj_order = item order
-    of the matrix-core adjoint (0 or 1) and slabs = day slabs per epoch when
-    day_tile is given."""
+    of the matrix-core adjoint (0, 1, or 2 for runs of consecutive reached
+    intervals per wave) and slabs = day slabs per epoch when day_tile is
+    given."""
     return SpgdParams(int(epochs), int(batch_rows), float(eta), float(eps), int(optimizer),
                       int(check_finite), int(kernel_path), int(use_graph), int(day_tile),
                       int(refine_steps), int(adj_order), int(slabs))

@@ -11,7 +11,7 @@
 // observation interval h2 is the share of the window inside it.
 //
 // Two kernels per chunk of days:
-//   k_trajectories  one thread per (four days, path, boundary b in 0..H): the travel
+//   k_trajectories  one thread per (eight days, path, boundary b in 0..H): the travel
 //                   time from the b*dt departure to the entry of every link of
 //                   the path, traj[day][pair][b] (pairs = (path, i) in path
 //                   order), and optionally the whole path's travel time (the
@@ -43,6 +43,7 @@
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kTrajDays = 8;   // days walked together by one trajectory thread
 
 template <typename S>
 __device__ __forceinline__ S link_time(const S* __restrict__ len, const S* __restrict__ speed_day,
@@ -52,9 +53,9 @@ __device__ __forceinline__ S link_time(const S* __restrict__ len, const S* __res
   return len[a] / speed_day[(int64_t)a * H_speed + h];
 }
 
-// One thread per (group of four days, path, boundary b), b fastest: the four
-// days' trajectories are walked together, so four independent chains of
-// speed gathers are in flight (days past the chunk repeat its last day and
+// One thread per (group of eight days, path, boundary b), b fastest: the
+// eight days' trajectories are walked together, so eight independent chains
+// of speed gathers are in flight (days past the chunk repeat its last day and
 // are not stored).
 template <typename S>
 __global__ void __launch_bounds__(kBlock)
@@ -62,7 +63,7 @@ k_trajectories(int32_t n_paths, const int32_t* __restrict__ path_ptr,
                const int32_t* __restrict__ path_link, int32_t L, const S* __restrict__ len,
                const S* __restrict__ speed, int32_t day0, int32_t n_days, int32_t H_speed, S dt,
                int32_t H, int64_t n_pairs, S* __restrict__ traj, S* __restrict__ exit_time) {
-  constexpr int kDays = 4;
+  constexpr int kDays = kTrajDays;
   const int64_t per_group = (int64_t)n_paths * (H + 1);
   const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int32_t n_groups = (n_days + kDays - 1) / kDays;
@@ -121,6 +122,14 @@ k_exit_sums(int32_t n_paths, int32_t H, int32_t n_days_chunk, const S* __restric
     sums[idx] = s;
 }
 
+// 1 / w for the window shares: the hardware reciprocal in FP32 (within 1 ulp;
+// the kernel is bound by its instruction count), the quotient in FP64.
+__device__ __forceinline__ float share_recip(float w) { return __builtin_amdgcn_rcpf(w); }
+__device__ __forceinline__ double share_recip(double w) { return 1.0 / w; }
+// min(max(x, 0), 1): one v_med3 in FP32
+__device__ __forceinline__ float clamp01(float x) { return __builtin_amdgcn_fmed3f(x, 0.f, 1.f); }
+__device__ __forceinline__ double clamp01(double x) { return x < 0.0 ? 0.0 : (x > 1.0 ? 1.0 : x); }
+
 template <typename S, int KMAX>
 __global__ void __launch_bounds__(kBlock)
 k_dar_windows(int64_t n_pairs, int32_t n_days_chunk, int32_t H, int32_t K, S dt,
@@ -136,48 +145,53 @@ k_dar_windows(int64_t n_pairs, int32_t n_days_chunk, int32_t H, int32_t K, S dt,
   for (int l = 0; l < KMAX; ++l) acc[l] = first_chunk || l >= K ? S(0) : Rr[((int64_t)l * H + h) * n_pairs + m];
   const int64_t day_stride = n_pairs * (H + 1);
   const S* tr = traj + m * (H + 1) + h;
-  constexpr int kDays = 4;   // loads of four days in flight together
-  for (int32_t d0 = 0; d0 < n_days_chunk; d0 += kDays) {
+  // interval h+l ends at (l+1)*dt relative to the departure
+  S edge[KMAX];
+#pragma unroll
+  for (int l = 0; l < KMAX; ++l) edge[l] = static_cast<S>(l + 1) * dt;
+  // One day's window [lo, hi] (relative to h*dt; observation interval h+l is
+  // [l*dt, (l+1)*dt)) added into acc.  Every lag is accumulated; lags past the
+  // day (l >= kk) are written as zeros below.
+  auto add_day = [&](S lo, S hi) {
+    // FIFO violation (hi < lo): the window between the two end points
+    const S a0 = fmin(lo, hi), w = fmax(lo, hi) - a0;
+    if (w <= S(0)) {   // all of the interval arrives at one instant
+      const int la = static_cast<int>(fmin(floor(a0 / dt), static_cast<S>(KMAX)));
+#pragma unroll
+      for (int ll = 0; ll < KMAX; ++ll)
+        if (ll == la) acc[ll] += S(1);
+      return;
+    }
+    const S inv_w = share_recip(w);
+    S f_prev = S(0);   // F(0) = 0: windows start at or after their departure
+#pragma unroll
+    for (int ll = 0; ll < KMAX; ++ll) {
+      const S f = clamp01((edge[ll] - a0) * inv_w);
+      acc[ll] += f - f_prev;
+      f_prev = f;
+    }
+  };
+  // days in order: groups of eight whose loads are in flight together, then
+  // the rest one by one
+  constexpr int kDays = 8;
+  const S* p = tr;
+  int32_t d = 0;
+  for (; d + kDays <= n_days_chunk; d += kDays, p += kDays * day_stride) {
     S lo[kDays], hi[kDays];
 #pragma unroll
     for (int u = 0; u < kDays; ++u) {
-      const int64_t d = min(d0 + u, n_days_chunk - 1);
-      // window relative to h*dt; observation interval h+l is [l*dt, (l+1)*dt)
-      lo[u] = tr[d * day_stride];
-      hi[u] = dt + tr[d * day_stride + 1];
+      lo[u] = p[u * day_stride];
+      hi[u] = dt + p[u * day_stride + 1];
     }
 #pragma unroll
-    for (int u = 0; u < kDays; ++u) {
-      if (d0 + u >= n_days_chunk) break;
-      S a0 = lo[u], b0 = hi[u];
-      if (b0 < a0) {   // FIFO violation: the window between the two end points
-        const S tmp = a0;
-        a0 = b0;
-        b0 = tmp;
-      }
-      const S w = b0 - a0;
-      if (w <= S(0)) {   // all of the interval arrives at one instant
-        const int64_t la = static_cast<int64_t>(floor(a0 / dt));
-#pragma unroll
-        for (int ll = 0; ll < KMAX; ++ll)
-          if (ll == la && ll < kk) acc[ll] += S(1);
-        continue;
-      }
-      const S inv_w = S(1) / w;
-      S f_prev = S(0);   // F(0) = 0: windows start at or after their departure
-#pragma unroll
-      for (int ll = 0; ll < KMAX; ++ll) {
-        const S x = (static_cast<S>(ll + 1) * dt - a0) * inv_w;
-        const S f = x < S(0) ? S(0) : (x > S(1) ? S(1) : x);
-        if (ll < kk) acc[ll] += f - f_prev;
-        f_prev = f;
-      }
-    }
+    for (int u = 0; u < kDays; ++u) add_day(lo[u], hi[u]);
   }
+  for (; d < n_days_chunk; ++d, p += day_stride) add_day(p[0], dt + p[1]);
 #pragma unroll
   for (int l = 0; l < KMAX; ++l) {
     if (l >= K) break;
-    Rr[((int64_t)l * H + h) * n_pairs + m] = last_chunk ? acc[l] / static_cast<S>(n_days_total) : acc[l];
+    const S v = l >= kk ? S(0) : (last_chunk ? acc[l] / static_cast<S>(n_days_total) : acc[l]);
+    Rr[((int64_t)l * H + h) * n_pairs + m] = v;
   }
 }
 
@@ -248,7 +262,7 @@ hipError_t run(int32_t n_paths, const int32_t* path_ptr, const int32_t* path_lin
                S* cost, hipStream_t s) {
   for (int32_t d0 = 0; d0 < n_days; d0 += chunk) {
     const int32_t nd = std::min(chunk, n_days - d0);
-    const int64_t n1 = (int64_t)((nd + 3) / 4) * n_paths * (H + 1);   // four days per thread
+    const int64_t n1 = (int64_t)((nd + kTrajDays - 1) / kTrajDays) * n_paths * (H + 1);
     hipLaunchKernelGGL(k_trajectories<S>, dim3(blocks_for(n1)), dim3(kBlock), 0, s, n_paths,
                        path_ptr, path_link, L, len, speed, d0, nd, H_speed, dt, H, n_pairs, traj,
                        cost ? exit_time : nullptr);
