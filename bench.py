@@ -187,7 +187,8 @@ def run_form(dode, torch, inst, form, perms, E_total, warmup, steps, bh, refine=
     params = dode.make_params(epochs=E_total, batch_rows=8192, eta=5.0, optimizer=0,
                               refine_steps=refine, day_tile=day_tile, adj_order=adj_order,
                               slabs=slabs,
-                              kernel_path=KERNEL_PATH.get(form, 0))
+                              kernel_path=KERNEL_PATH.get(
+                                  form, KERNEL_PATH.get("matrix-core", 0) if form in ("bf16", "fp8") else 0))
     plan = dode.spgd_plan_create(dar, inst.day_cluster, params, perm=perms, stream=0)
     dode.spgd_plan_load(plan, X, Q, A, stream=0)
     torch.cuda.synchronize()
@@ -870,7 +871,13 @@ def main():
                     help="time every matrix-core schedule candidate of the workload instead")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 512 MiB device copy first (reference for traffic counters)")
+    ap.add_argument("--kernel-path", type=int, default=None, choices=[0, 2, 3],
+                    help="matrix-core launch form of the timed form: 0 two launches per "
+                         "minibatch (default), 2 one per minibatch, 3 one per epoch (needs "
+                         "--schedule)")
     args = ap.parse_args()
+    if args.kernel_path is not None:
+        KERNEL_PATH["matrix-core"] = args.kernel_path
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the days are independent, "
               "so a multi-GPU run would only repeat the one-GPU kernel on each GPU's share of days.",

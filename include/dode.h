@@ -85,8 +85,16 @@ typedef struct {
                           launch per minibatch, else the sparse kernels),
                           1 = sparse pattern kernels, 2 = matrix-core tiles
                           with one launch per minibatch, one workgroup per
-                          independent part of it (same bits as 0; slower on
-                          the benchmark workloads) */
+                          independent part of it, 3 = matrix-core tiles with
+                          one cooperative launch per epoch whose resident
+                          workgroups meet at a grid barrier between the
+                          forward and adjoint phases of every minibatch (needs
+                          a given day_tile and one day slab; the chunked
+                          adjoint only with day_tile 16; refinement steps run
+                          as separate launches after it; spgd_run then waits
+                          for the stream once per call to check the barrier).
+                          2 and 3 give the same bits as 0 and are slower on
+                          the benchmark workloads */
   int32_t use_graph;   /* nonzero: spgd_run replays one captured hipGraph per epoch
                           (the epoch index lives in a device counter) */
   int32_t day_tile;    /* days of one cluster handled together by a matrix-core

@@ -154,7 +154,8 @@ def spgd_defaults() -> SpgdParams:
 def make_params(epochs=300, batch_rows=8192, eta=5.0, eps=1e-10, optimizer=0, check_finite=1,
                 kernel_path=0, use_graph=1, day_tile=32, refine_steps=0, adj_order=1, slabs=1):
     """kernel_path 0 = fastest for the storage type, 1 = sparse pattern kernels,
-    2 = matrix-core tiles with one launch per minibatch; use_graph 1 = replay
+    2 = matrix-core tiles with one launch per minibatch, 3 = one cooperative
+    launch per epoch with grid barriers (day_tile given); use_graph 1 = replay
     one captured hipGraph per epoch; day_tile = days per matrix-core wave (16,
     32 or 64, or 0 to choose the schedule by timing at load); refine_steps =
     full-batch steps per epoch on corrected FP8 values; adj_order = item order

@@ -286,8 +286,9 @@ dode_status check_params(const dode_spgd_params* p) {
   if (!(p->eps >= 0) || !std::isfinite(p->eps)) return fail(DODE_ERR_ARG, "eps must be >= 0");
   if (p->optimizer != 0 && p->optimizer != 1)
     return fail(DODE_ERR_ARG, "optimizer=%d (0 Adagrad, 1 fixed step)", p->optimizer);
-  if (p->kernel_path < 0 || p->kernel_path > 2)
-    return fail(DODE_ERR_ARG, "kernel_path=%d (0 best, 1 sparse, 2 tiles in one launch)",
+  if (p->kernel_path < 0 || p->kernel_path > 3)
+    return fail(DODE_ERR_ARG,
+                "kernel_path=%d (0 best, 1 sparse, 2 one launch per minibatch, 3 one per epoch)",
                 p->kernel_path);
   if (p->day_tile != 0 && p->day_tile != 16 && p->day_tile != 32 && p->day_tile != 64)
     return fail(DODE_ERR_ARG, "day_tile=%d (0 = tune, 16, 32 or 64)", p->day_tile);
@@ -468,7 +469,42 @@ dode_status run_refinement(dode_plan* plan, hipStream_t s) {
 
 // Every minibatch of epoch e (e < 0: the epoch in the device counter, for
 // graph capture), slab by slab, then the refinement steps.
+// Polls of a persistent launch's grid barrier before it gives up (about a
+// second); DODE_PERSIST_SPIN_LIMIT overrides it (tests of the error path).
+uint32_t persist_spin_limit() {
+  const char* v = getenv("DODE_PERSIST_SPIN_LIMIT");
+  return v && *v ? (uint32_t)strtoul(v, nullptr, 10) : (1u << 20);
+}
+
+// Every minibatch of epoch e in one cooperative launch (kernel_path 3).
+dode_status run_persistent(dode_plan* plan, int32_t e, hipStream_t s) {
+  if (!plan->d_mb) {
+    std::vector<PersistMinibatch> mb(plan->nch);
+    for (int32_t j = 0; j < plan->nch; ++j)
+      mb[j] = PersistMinibatch{plan->chunk_dev(j), plan->chunks(-1, j)};
+    HIP_TRY(hipMalloc(&plan->d_mb, mb.size() * sizeof(PersistMinibatch)));
+    HIP_TRY(hipMemcpy(plan->d_mb, mb.data(), mb.size() * sizeof(PersistMinibatch),
+                      hipMemcpyHostToDevice));
+    HIP_TRY(hipMalloc(&plan->d_bar, sizeof(PersistBarrier)));
+  }
+  HIP_TRY(fill_zero(false, plan->d_bar, sizeof(PersistBarrier) / 4, s));
+  const dode_plan::WaveTables& wt = plan->wt_mb[0];
+  const int o = plan->adj_order;
+  HIP_TRY(timed(plan, 1, s, [&] {
+    return mfma_epoch_persistent(plan->dar, plan->d_mb, plan->nch, e, wt.fwd, wt.n_fwd, wt.adj[o],
+                                 wt.n_adj[o], o, plan->day_tile, plan->ly,
+                                 static_cast<const float*>(plan->d_X), static_cast<float*>(plan->d_R),
+                                 static_cast<float*>(plan->d_Q), static_cast<float*>(plan->d_A),
+                                 plan->sa, plan->d_bar, persist_spin_limit(), s);
+  }));
+  return DODE_OK;
+}
+
 dode_status run_epoch(dode_plan* plan, int32_t e, hipStream_t s) {
+  if (plan->persistent && e >= 0) {
+    if (dode_status st = run_persistent(plan, e, s)) return st;
+    return run_refinement(plan, s);
+  }
   const int32_t ns = plan->use_mfma ? plan->n_slabs : 1;
   for (int32_t k = 0; k < ns; ++k)
     for (int32_t j = 0; j < plan->nch; ++j) {
@@ -1665,6 +1701,8 @@ dode_status spgd_plan_destroy(dode_plan* plan) {
   if (plan->graph) (void)hipGraphDestroy(plan->graph);
   if (plan->capture_stream) (void)hipStreamDestroy(plan->capture_stream);
   if (plan->d_epoch) (void)hipFree(plan->d_epoch);
+  if (plan->d_mb) (void)hipFree(plan->d_mb);
+  if (plan->d_bar) (void)hipFree(plan->d_bar);
   (void)hipSetDevice(cur);
   delete plan;
   return DODE_OK;
@@ -1742,12 +1780,20 @@ dode_status spgd_plan_create(const dode_dar* dar, const int32_t* day_cluster, in
   // 4.83 ms per epoch with 365 one-day clusters of 50 ODs and 200 links.
   // Refinement steps need the tiles.
   const int32_t max_days = *std::max_element(p->cluster_days.begin(), p->cluster_days.end());
-  if (params->kernel_path == 2 && !dar->has_tiles)
-    return fail(DODE_ERR_UNSUPPORTED, "kernel_path 2 needs BF16 or FP8 storage (matrix-core tiles)");
+  if (params->kernel_path >= 2 && !dar->has_tiles)
+    return fail(DODE_ERR_UNSUPPORTED, "kernel_path %d needs BF16 or FP8 storage (matrix-core tiles)",
+                params->kernel_path);
+  if (params->kernel_path == 3 && (params->day_tile == 0 || params->slabs > 1))
+    return fail(DODE_ERR_ARG,
+                "kernel_path 3 (one launch per epoch) needs a given day_tile and one day slab");
+  if (params->kernel_path == 3 && params->adj_order == 2 && params->day_tile != 16)
+    return fail(DODE_ERR_UNSUPPORTED,
+                "kernel_path 3 runs the chunked adjoint (adj_order 2) with 16-day waves only");
   p->use_mfma = dar->has_tiles &&
                 ((params->kernel_path == 0 && (max_days > kSparseDays || params->refine_steps > 0)) ||
-                 params->kernel_path == 2);
+                 params->kernel_path >= 2);
   p->one_launch = p->use_mfma && params->kernel_path == 2;
+  p->persistent = p->use_mfma && params->kernel_path == 3;
   const size_t ss = state_size(dar);
   if (p->use_mfma) {
     const int64_t pb = blocked_row_blocks(dm.P), lb = blocked_row_blocks(dm.L);
@@ -1760,7 +1806,7 @@ dode_status spgd_plan_create(const dode_dar* dar, const int32_t* day_cluster, in
   if (p->refine_steps > 0) {
     if (!p->use_mfma || !dar->has_corr)
       return fail(DODE_ERR_UNSUPPORTED,
-                  "refine_steps needs FP8 storage with correction tiles and kernel_path 0 or 2");
+                  "refine_steps needs FP8 storage with correction tiles and kernel_path 0, 2 or 3");
     // the whole row set as one minibatch: identity order, every departure
     // interval with every lag that stays inside the day
     std::vector<int32_t> full((size_t)2 * C * dm.H + (size_t)C * dm.T * (dm.K + 3), -1);
@@ -1883,7 +1929,7 @@ dode_status spgd_run(dode_plan* plan, int32_t epoch_begin, int32_t n_epochs, dou
   hipStream_t s = as_stream(stream);
   plan->last_stream = s;
   const int32_t D = plan->D;
-  const bool graph = plan->use_graph && !plan->timing && n_epochs > 0;
+  const bool graph = plan->use_graph && !plan->timing && !plan->persistent && n_epochs > 0;
   if (graph) {
     if (dode_status st = build_epoch_graph(plan)) return st;
     HIP_TRY(set_counter(plan->d_epoch, epoch_begin, s));
@@ -1903,6 +1949,14 @@ dode_status spgd_run(dode_plan* plan, int32_t epoch_begin, int32_t n_epochs, dou
         return r != hipSuccess ? r : permute_loss(plan->d_loss, plan->d_order, D, out, s);
       }));
     }
+  }
+  if (plan->persistent && n_epochs > 0) {
+    // a grid barrier that gave up leaves its error word set
+    PersistBarrier b{};
+    HIP_TRY(hipMemcpyAsync(&b, plan->d_bar, sizeof b, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (b.err)
+      return fail(DODE_ERR_HIP, "persistent epoch launch: a grid barrier waited past its limit");
   }
   return DODE_OK;
 }

@@ -322,6 +322,17 @@ struct WaveWork {
 constexpr int64_t kStatePad = 64;
 
 // Minibatch schedule and scratch of spgd_run (see spgd_plan_create).
+// Persistent epoch launch (kernel_path 3): the schedules of minibatch j in the
+// device-counter form (the kernel takes the epoch as an argument instead), and
+// the grid barrier's words (zeroed before each launch).
+struct PersistMinibatch {
+  ChunkSched cs;
+  ChunkList ck;
+};
+struct PersistBarrier {
+  unsigned count, gen, err, pad;
+};
+
 struct dode_plan {
   const dode_dar* dar = nullptr;
   int device = 0;
@@ -339,6 +350,11 @@ struct dode_plan {
   int32_t* d_kchunk_full = nullptr;   // refinement steps: [C][full_chunks][chunk_w]
   int32_t full_chunks = 0;
   bool one_launch = false;        // matrix-core minibatches as one launch each
+  // every minibatch of an epoch in one cooperative launch (kernel_path 3):
+  // the per-minibatch schedules and the grid barrier's words
+  bool persistent = false;
+  PersistMinibatch* d_mb = nullptr;
+  PersistBarrier* d_bar = nullptr;
   int32_t adj_order = 0;          // ChunkSched::order of the matrix-core adjoint
   // Day slabs: the matrix-core epoch runs every minibatch on the day groups of
   // slab 0, then on those of slab 1, ...  (days are independent, so the
@@ -564,6 +580,13 @@ hipError_t mfma_adj_chunks(const dode_dar* dar, const ChunkList& ck, const WaveW
                            int32_t day_tile, const Layout& ly, const float* R, float* Q, float* A,
                            const StepArgs& st, bool corr, hipStream_t s);
 // one whole minibatch (forward, residual, adjoint, step) in one launch
+// Persistent epoch launch (kernel_path 3); the structs are defined before the plan.
+hipError_t mfma_epoch_persistent(const dode_dar* dar, const PersistMinibatch* mb, int32_t nch,
+                                 int32_t epoch, const WaveWork* wt_fwd, int64_t n_fwd,
+                                 const WaveWork* wt_adj, int64_t n_adj, int32_t order,
+                                 int32_t day_tile, const Layout& ly, const float* X, float* R,
+                                 float* Q, float* A, const StepArgs& st, PersistBarrier* bar,
+                                 uint32_t spin_limit, hipStream_t s);
 hipError_t mfma_minibatch(const dode_dar* dar, const CompSched& ks, const DayGroups& dg,
                           const Layout& ly, const float* X, float* R, float* Q, float* A,
                           const StepArgs& st, hipStream_t s);

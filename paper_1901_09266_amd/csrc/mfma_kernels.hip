@@ -526,17 +526,14 @@ k_adj_mfma(DevPat pt, DevTiles tl, ChunkSched cs, const WaveWork* __restrict__ w
 // k-step) run in batches of CB whose loads are all issued before the first
 // product.
 template <int MODE, int NT>
-__global__ void __launch_bounds__(256)
-k_adj_chunk(DevPat pt, DevTiles tl, ChunkList ck, const WaveWork* __restrict__ wt, int n_items,
-            Layout ly, const float* __restrict__ R, float* __restrict__ Q, float* __restrict__ A,
-            StepArgs st) {
+__device__ __forceinline__ void adj_chunk_item(const DevPat& pt, const DevTiles& tl,
+                                               const Layout& ly, const ChunkList& ck,
+                                               const WaveWork& w, const float* __restrict__ R,
+                                               float* __restrict__ Q, float* __restrict__ A,
+                                               const StepArgs& st) {
   constexpr int CB = NT == 1 ? 1 : 2;   // 4 and 3 waves per SIMD
   constexpr int G = kChunkT;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int item = xcd_logical_block((n_items + 3) / 4) * 4 + wave;
-  if (item >= n_items) return;
-  const WaveWork w = load_work(wt, item);
-  ck = resolve_epoch(ck);
+  const int lane = threadIdx.x & 63;
   const int32_t* cr = ck.chunk + ((int64_t)w.c * ck.max_chunks + w.row) * ck.w;
   const int t0 = cr[0], n_t = cr[1], n_h = cr[2];
   if (n_t == 0) return;
@@ -649,6 +646,18 @@ k_adj_chunk(DevPat pt, DevTiles tl, ChunkList ck, const WaveWork* __restrict__ w
   }
 }
 
+template <int MODE, int NT>
+__global__ void __launch_bounds__(256)
+k_adj_chunk(DevPat pt, DevTiles tl, ChunkList ck, const WaveWork* __restrict__ wt, int n_items,
+            Layout ly, const float* __restrict__ R, float* __restrict__ Q, float* __restrict__ A,
+            StepArgs st) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int item = xcd_logical_block((n_items + 3) / 4) * 4 + wave;
+  if (item >= n_items) return;
+  const WaveWork w = load_work(wt, item);
+  adj_chunk_item<MODE, NT>(pt, tl, ly, resolve_epoch(ck), w, R, Q, A, st);
+}
+
 // One whole minibatch in one launch, one workgroup per (cluster, component,
 // day group).  A component is a maximal run of the minibatch's intervals whose
 // reached departure intervals overlap (sorted intervals less than K apart); the
@@ -691,6 +700,116 @@ k_minibatch_mfma(DevPat pt, DevTiles tl, CompSched ks, DayGroups dg, Layout ly,
     const int32_t* dsc = ks.desc + ((int64_t)c * ks.mt + d0 + b) * dw;
     const WaveWork w{c, first, cnt, d0 + b, j, tl.g_ks[j], tl.g_alo[j], tl.g_koff[j]};
     adj_item<MODE, NT>(pt, tl, ly, w, dsc, R, Q, A, st);
+  }
+}
+
+// Grid barrier of the persistent epoch kernel.  Every wave first waits until
+// its own stores have reached its XCD's L2 (a fence by one thread after a
+// workgroup barrier does not wait for the other waves' stores); the block's
+// first thread then writes the L2 back (device-scope release: the XCDs' L2s
+// are not coherent with each other), arrives on the counter, waits until the
+// last arrival moves the generation on, and invalidates its L2 and the L1 the
+// block's waves share (device-scope acquire).  The wait is bounded: after
+// `spin_limit` polls, or once any block has given up, the block sets the
+// error word and returns false, and every later barrier returns false at
+// once, so every block leaves the kernel; the host turns the error word into
+// an error.  The kernel must be launched with all its blocks resident (a
+// cooperative launch).
+__device__ bool grid_barrier(PersistBarrier* b, unsigned n_blocks, unsigned& gen,
+                             unsigned spin_limit) {
+  __shared__ int ok;
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int good = __hip_atomic_load(&b->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u;
+    if (good) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      const unsigned arrived =
+          __hip_atomic_fetch_add(&b->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (arrived == n_blocks - 1) {
+        __hip_atomic_store(&b->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&b->gen, gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        // relaxed polls (no cache invalidation while the other blocks work),
+        // one acquire fence once the generation has moved on
+        unsigned polls = 0;
+        while (__hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+          if (++polls > spin_limit ||
+              __hip_atomic_load(&b->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+            __hip_atomic_store(&b->err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            good = 0;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(8);
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    ok = good;
+  }
+  __syncthreads();
+  ++gen;
+  return ok != 0;
+}
+
+// The epoch held by a device-epoch schedule, taken from an argument instead.
+__device__ __forceinline__ ChunkSched at_epoch(ChunkSched cs, int e) {
+  cs.perm += e * cs.perm_e;
+  cs.pos += e * cs.perm_e;
+  cs.touched += e * cs.touched_e;
+  cs.epoch = nullptr;
+  return cs;
+}
+__device__ __forceinline__ ChunkList at_epoch(ChunkList ck, int e) {
+  ck.chunk += e * ck.chunk_e;
+  ck.epoch = nullptr;
+  return ck;
+}
+
+// Every minibatch of one epoch in one launch: the blocks stay resident and
+// walk the forward work table of minibatch j, meet at a grid barrier, walk the
+// adjoint work table (with the step and projection), meet again, and go on to
+// minibatch j + 1.  Each XCD takes one contiguous eighth of each table (its
+// blocks are those with blockIdx % 8 equal to it, items strided over them),
+// so items that share tiles run under one L2.  Every item does the
+// arithmetic of the separate forward and adjoint kernels, so the results are
+// the same bits.  (Handing out items from an atomic counter per phase and XCD
+// instead of the fixed stride made the epoch twice as slow.)
+template <int MODE, int NT, bool CHUNKED>
+__global__ void __launch_bounds__(256)
+k_epoch_persistent(DevPat pt, DevTiles tl, const PersistMinibatch* __restrict__ mb, int nch,
+                   int epoch, const WaveWork* __restrict__ wt_fwd, int n_fwd,
+                   const WaveWork* __restrict__ wt_adj, int n_adj, Layout ly,
+                   const float* __restrict__ X, float* __restrict__ R, float* __restrict__ Q,
+                   float* __restrict__ A, StepArgs st, PersistBarrier* bar, unsigned spin_limit) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int xcd = blockIdx.x % kXcds, local = blockIdx.x / kXcds;
+  const int stride = (gridDim.x / kXcds) * 4;
+  const int f_lo = (int)((int64_t)n_fwd * xcd / kXcds), f_hi = (int)((int64_t)n_fwd * (xcd + 1) / kXcds);
+  const int a_lo = (int)((int64_t)n_adj * xcd / kXcds), a_hi = (int)((int64_t)n_adj * (xcd + 1) / kXcds);
+  unsigned gen = 0;
+  for (int j = 0; j < nch; ++j) {
+    const ChunkSched cs = at_epoch(mb[j].cs, epoch);
+    for (int item = f_lo + local * 4 + wave; item < f_hi; item += stride) {
+      const WaveWork w = load_work(wt_fwd, item);
+      if (cs.j0 + w.row >= pt.H) continue;
+      const int h = cs.perm[w.c * pt.H + cs.j0 + w.row];
+      fwd_group<MODE, NT, kFwdTileGroup>(pt, tl, ly, w, h, Q, X, R);
+    }
+    if (!grid_barrier(bar, gridDim.x, gen, spin_limit)) return;
+    if constexpr (CHUNKED) {
+      const ChunkList ck = at_epoch(mb[j].ck, epoch);
+      for (int item = a_lo + local * 4 + wave; item < a_hi; item += stride)
+        adj_chunk_item<MODE, NT>(pt, tl, ly, ck, load_work(wt_adj, item), R, Q, A, st);
+    } else {
+      for (int item = a_lo + local * 4 + wave; item < a_hi; item += stride) {
+        const WaveWork w = load_work(wt_adj, item);
+        const int32_t* dsc = cs.touched + ((int64_t)w.c * cs.max_touched + w.row) * desc_width(pt.K);
+        if (dsc[kDescT] < 0) continue;
+        adj_item<MODE, NT>(pt, tl, ly, w, dsc, R, Q, A, st);
+      }
+    }
+    if (j + 1 < nch && !grid_barrier(bar, gridDim.x, gen, spin_limit)) return;
   }
 }
 
@@ -848,4 +967,65 @@ hipError_t mfma_adj_chunks(const dode_dar* dar, const ChunkList& ck, const WaveW
   if (corr) return launch_adj_chunk<kFP8Corr, 2>(dar, ck, wt, n, ly, R, Q, A, st, s);
   return fp8 ? launch_adj_chunk<kFP8, 2>(dar, ck, wt, n, ly, R, Q, A, st, s)
              : launch_adj_chunk<kBF16, 2>(dar, ck, wt, n, ly, R, Q, A, st, s);
+}
+
+template <int MODE, int NT, bool CHUNKED>
+hipError_t launch_persistent(const dode_dar* dar, const PersistMinibatch* mb, int nch, int epoch,
+                             const WaveWork* wt_fwd, int64_t n_fwd, const WaveWork* wt_adj,
+                             int64_t n_adj, const Layout& ly, const float* X, float* R, float* Q,
+                             float* A, const StepArgs& st, PersistBarrier* bar,
+                             unsigned spin_limit, hipStream_t s) {
+  auto kern = k_epoch_persistent<MODE, NT, CHUNKED>;
+  int per_cu = 0, dev = 0, n_cu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0);
+  if (e == hipSuccess) e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  // every block resident; no more blocks than the larger table has waves,
+  // and a multiple of the XCD count
+  const int64_t need = (std::max(n_fwd, n_adj) + 3) / 4;
+  int64_t blocks = std::min<int64_t>((int64_t)per_cu * n_cu, need);
+  blocks = std::max<int64_t>(kXcds, blocks / kXcds * kXcds);
+  if (blocks > (int64_t)per_cu * n_cu) return hipErrorCooperativeLaunchTooLarge;
+  DevPat pt = dar->pat();
+  DevTiles tl = dar->tiles;
+  int nf = (int)n_fwd, na = (int)n_adj;
+  void* args[] = {&pt, &tl, &mb, &nch, &epoch, &wt_fwd, &nf, &wt_adj, &na,
+                  const_cast<Layout*>(&ly), &X, &R, &Q, &A, const_cast<StepArgs*>(&st), &bar,
+                  &spin_limit};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3((unsigned)blocks),
+                                    dim3(256), args, 0, s);
+}
+
+template <int NT, bool CHUNKED>
+hipError_t persistent_mode(const dode_dar* dar, const PersistMinibatch* mb, int nch, int epoch,
+                           const WaveWork* wt_fwd, int64_t n_fwd, const WaveWork* wt_adj,
+                           int64_t n_adj, const Layout& ly, const float* X, float* R, float* Q,
+                           float* A, const StepArgs& st, PersistBarrier* bar, unsigned spin_limit,
+                           hipStream_t s) {
+  if (dar->storage != DODE_FP8_E4M3)
+    return launch_persistent<kBF16, NT, CHUNKED>(dar, mb, nch, epoch, wt_fwd, n_fwd, wt_adj, n_adj,
+                                                 ly, X, R, Q, A, st, bar, spin_limit, s);
+  return launch_persistent<kFP8, NT, CHUNKED>(dar, mb, nch, epoch, wt_fwd, n_fwd, wt_adj, n_adj,
+                                              ly, X, R, Q, A, st, bar, spin_limit, s);
+}
+
+hipError_t mfma_epoch_persistent(const dode_dar* dar, const PersistMinibatch* mb, int32_t nch,
+                                 int32_t epoch, const WaveWork* wt_fwd, int64_t n_fwd,
+                                 const WaveWork* wt_adj, int64_t n_adj, int32_t order,
+                                 int32_t day_tile, const Layout& ly, const float* X, float* R,
+                                 float* Q, float* A, const StepArgs& st, PersistBarrier* bar,
+                                 uint32_t spin_limit, hipStream_t s) {
+  if (n_fwd > INT32_MAX || n_adj > INT32_MAX || (order == 2 && day_tile == 64))
+    return hipErrorInvalidValue;
+#define PERSIST_ARGS dar, mb, nch, epoch, wt_fwd, n_fwd, wt_adj, n_adj, ly, X, R, Q, A, st, bar, spin_limit, s
+  const bool chunked = order == 2;
+  switch (day_tile) {
+    case 16: return chunked ? persistent_mode<1, true>(PERSIST_ARGS)
+                            : persistent_mode<1, false>(PERSIST_ARGS);
+    case 64: return persistent_mode<4, false>(PERSIST_ARGS);
+    default: return chunked ? persistent_mode<2, true>(PERSIST_ARGS)
+                            : persistent_mode<2, false>(PERSIST_ARGS);
+  }
+#undef PERSIST_ARGS
 }

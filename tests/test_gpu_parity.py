@@ -622,6 +622,94 @@ def test_one_launch_minibatch_equals_two_launches(name, storage):
     assert np.max(np.abs(outs[(2, 32)][2].T - ho) / ho) <= 1e-3
 
 
+def run_paths(inst, storage, E, perms, batch_rows, configs, refine=0):
+    """Q, A and the loss history of one plan per (kernel_path, day_tile,
+    adj_order) in `configs`."""
+    dar = make_dar(inst, storage, correction=refine > 0)
+    X = dev(inst.x, torch.float32)
+    Q0 = torch.zeros((inst.D, inst.T, inst.P), dtype=torch.float32, device="cuda")
+    outs = {}
+    for path, tile, order in configs:
+        p = dode.make_params(epochs=E, batch_rows=batch_rows, eta=5.0, kernel_path=path,
+                             day_tile=tile, adj_order=order, refine_steps=refine)
+        plan = dode.spgd_plan_create(dar, inst.day_cluster, p, perm=perms, stream=0)
+        dode.spgd_plan_load(plan, X, Q0)
+        loss = torch.zeros((E, inst.D), dtype=torch.float64, device="cuda")
+        dode.spgd_run(plan, 0, 2, loss=loss[:2])
+        dode.spgd_run(plan, 2, E - 2, loss=loss[2:])
+        Q = torch.empty_like(Q0)
+        A = torch.empty_like(Q0)
+        dode.spgd_plan_store(plan, Q, A)
+        torch.cuda.synchronize()
+        outs[(path, tile, order)] = (Q.cpu().numpy(), A.cpu().numpy(), loss.cpu().numpy())
+    return outs
+
+
+@pytest.mark.parametrize("storage", ["bf16", "fp8"])
+@pytest.mark.parametrize("name", ["long components", "H past T", "corridor"])
+def test_persistent_epoch_equals_separate_launches(name, storage):
+    """kernel_path 3 runs every minibatch of an epoch in one cooperative launch
+    with grid barriers between the forward and adjoint phases; the items are
+    those of the separate launches, so the demand, the accumulator and the
+    loss history agree bit for bit, for each adjoint order and day tile (the
+    run is split over two spgd_run calls, so the epoch argument is exercised)."""
+    kw = dict(ONE_LAUNCH_SHAPES[name])
+    inst = make_instance(demand="gamma", noise="mult5", x_dtype="f32", seed=97, **kw)
+    say("persistent epoch vs separate launches", name, storage)
+    E = 5
+    perms = make_perms(98, E, inst.C, inst.H)
+    batch_rows = 8192 if inst.L >= 200 else 7 * inst.L
+    configs = [(0, 32, 2), (3, 32, 1), (3, 16, 2), (3, 16, 0), (3, 64, 1)]
+    outs = run_paths(inst, storage, E, perms, batch_rows, configs)
+    for key in configs[1:]:
+        for a, b in zip(outs[key], outs[configs[0]]):
+            np.testing.assert_array_equal(a, b)
+
+
+def test_persistent_epoch_with_refinement():
+    """kernel_path 3 with 2 refinement steps per epoch (run as separate launches
+    after the persistent minibatch launch) gives the bits of kernel_path 0."""
+    inst = make_instance(P=40, L=120, T=36, K=4, sizes=(30, 9), inc=0.12, pattern="corridor",
+                         demand="gamma", noise="mult5", x_dtype="f32", seed=99)
+    say("persistent epoch with refinement")
+    E = 4
+    perms = make_perms(100, E, inst.C, inst.H)
+    configs = [(0, 32, 1), (3, 32, 1), (3, 16, 2)]
+    outs = run_paths(inst, "fp8", E, perms, 6 * inst.L, configs, refine=2)
+    for key in configs[1:]:
+        for a, b in zip(outs[key], outs[configs[0]]):
+            np.testing.assert_array_equal(a, b)
+
+
+def test_persistent_epoch_barrier_error_is_reported(monkeypatch):
+    """The grid barrier's wait is bounded: with a spin limit of zero polls every
+    waiting block gives up at once, the launch ends, and spgd_run reports the
+    error instead of hanging."""
+    inst = make_instance(P=20, L=40, T=24, K=4, sizes=(40,), inc=0.2, pattern="corridor",
+                         demand="gamma", noise="mult5", x_dtype="f32", seed=101)
+    say("persistent epoch barrier error path")
+    perms = make_perms(102, 2, inst.C, inst.H)
+    dar = make_dar(inst, "bf16")
+    p = dode.make_params(epochs=2, batch_rows=4 * inst.L, eta=5.0, kernel_path=3, day_tile=32)
+    plan = dode.spgd_plan_create(dar, inst.day_cluster, p, perm=perms, stream=0)
+    Q0 = torch.zeros((inst.D, inst.T, inst.P), dtype=torch.float32, device="cuda")
+    dode.spgd_plan_load(plan, dev(inst.x, torch.float32), Q0)
+    monkeypatch.setenv("DODE_PERSIST_SPIN_LIMIT", "0")
+    with pytest.raises(dode.DodeError, match="grid barrier"):
+        dode.spgd_run(plan, 0, 1)
+    monkeypatch.delenv("DODE_PERSIST_SPIN_LIMIT")
+    torch.cuda.synchronize()
+
+
+def test_persistent_epoch_rejected_without_a_fixed_schedule():
+    inst = make_instance(P=10, L=12, T=6, K=2, sizes=(5,), inc=0.3, pattern="bernoulli", seed=103)
+    dar = make_dar(inst, "bf16")
+    for kw in (dict(day_tile=0), dict(day_tile=32, slabs=2), dict(day_tile=32, adj_order=2)):
+        with pytest.raises(dode.DodeError, match="kernel_path 3"):
+            dode.spgd_plan_create(dar, inst.day_cluster, dode.make_params(kernel_path=3, **kw),
+                                  stream=0)
+
+
 def test_refinement_orders_give_identical_results():
     """An FP8 plan with 2 refinement steps per epoch: with the chunked adjoint
     (order 2) the refinement steps also run chunked over every departure
