@@ -119,26 +119,35 @@ def alu_roofline(profile, kernel, ms_per_step, hbm_bytes):
                     "bytes_per_step": hbm_bytes}}
 
 
+TRAFFIC_KEYS = ("fwd_bytes_per_launch", "adj_bytes_per_launch", "refine_fwd_bytes_per_launch",
+                "refine_adj_bytes_per_launch", "minibatch_bytes_per_epoch",
+                "refine_bytes_per_step", "schedule")
+
+
 def counted_traffic(config, form, kernel, variant=""):
-    """HBM bytes per launch of `kernel` ("fwd", "adj", or the refinement
-    steps' "refine_fwd" / "refine_adj") from the committed FETCH_SIZE /
-    WRITE_SIZE counter summary of this workload and form, or None when there
-    is none or the kernel sources changed since it was taken."""
+    """A figure of the committed FETCH_SIZE / WRITE_SIZE counter summary of
+    this workload and form: HBM bytes per launch of `kernel` ("fwd", "adj",
+    or the refinement steps' "refine_fwd" / "refine_adj"), the minibatch
+    launches' bytes per epoch ("minibatch"), the bytes of one refinement step
+    ("refine"), or the schedule the counters were taken at ("schedule", a
+    string); None when there is no summary or figure, or the kernel sources
+    changed since it was taken."""
     path = os.path.join(ROOT, "profiles", f"traffic_spgd_config{config}{variant}_{form}.md")
     if not os.path.exists(path):
         return None
     vals = {}
-    keys = ("source_sha256", "fwd_bytes_per_launch", "adj_bytes_per_launch",
-            "refine_fwd_bytes_per_launch", "refine_adj_bytes_per_launch")
+    keys = ("source_sha256",) + TRAFFIC_KEYS
     with open(path) as fh:
         for line in fh:
             line = line.strip().strip("`")
             if ":" in line and line.split(":", 1)[0] in keys:
                 k, v = line.split(":", 1)
                 vals[k] = v.strip()
-    if vals.get("source_sha256") != kernel_source_hash() or f"{kernel}_bytes_per_launch" not in vals:
+    key = {"minibatch": "minibatch_bytes_per_epoch", "refine": "refine_bytes_per_step",
+           "schedule": "schedule"}.get(kernel, f"{kernel}_bytes_per_launch")
+    if vals.get("source_sha256") != kernel_source_hash() or key not in vals:
         return None
-    return float(vals[f"{kernel}_bytes_per_launch"])
+    return vals[key] if kernel == "schedule" else float(vals[key])
 
 
 def launch_bytes(inst, perms, bh, esz, epochs, s_state=4, refine=0):
@@ -718,15 +727,23 @@ def spgd_leg(args, dode, torch, config, form, compare, refine, pattern=None, per
     look = (lambda name: None) if pattern == "bernoulli" else (
         lambda name: counted_traffic(config, form, name, variant))
     traffic, traffic_other = look(("fwd", "adj")[k]), look(("adj", "fwd")[k])
-    # counted HBM bytes of one epoch: every minibatch's two launches, and the
-    # refinement steps' full-batch launches
+    # counted HBM bytes of one epoch: every minibatch's launches (per epoch, as
+    # counted at the summary's schedule), and the refinement steps' launches
     epoch_traffic = None
-    if traffic is not None and traffic_other is not None:
+    mb_epoch, rf_step = look("minibatch"), look("refine")
+    if mb_epoch is not None:
+        epoch_traffic = mb_epoch + ((rf_step if rf_step is not None else float("nan")) * rf[form]
+                                    if rf[form] else 0.0)
+        if epoch_traffic != epoch_traffic:
+            epoch_traffic = None
+    elif traffic is not None and traffic_other is not None:
         epoch_traffic = (traffic + traffic_other) * (ep_launch - rf[form])
         if rf[form]:
             rfw, rad = look("refine_fwd"), look("refine_adj")
             epoch_traffic = None if rfw is None or rad is None else \
                 epoch_traffic + (rfw + rad) * rf[form]
+    sch = head["schedule"] or {}
+    timed_sched = f"{sch.get('day_tile')},{sch.get('adj_order')},{sch.get('slabs')}"
     sched_b = (head["fwd_bytes"] + head["adj_bytes"]) / args.steps
     roof = {"bound": "hbm", "kernel": "whole epoch (every minibatch launch of one epoch)",
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -734,6 +751,8 @@ def spgd_leg(args, dode, torch, config, form, compare, refine, pattern=None, per
             "traffic": round(epoch_traffic) if epoch_traffic is not None else None,
             "traffic_over_bytes": (round(epoch_traffic / B, 2) if epoch_traffic is not None
                                    else None),
+            "traffic_schedule": look("schedule"),
+            "timed_schedule": timed_sched,
             "bytes_per_epoch": int(B),
             "bytes_basis": "survey 8(d): ratio nonzeros once + per day X read, Q read+write "
                            f"({ {'f64': 8, 'f32': 4}.get(form, 2)} B), A read+write (4 B)",
@@ -745,7 +764,9 @@ def spgd_leg(args, dode, torch, config, form, compare, refine, pattern=None, per
                 "share_of_epoch": round(kms[k] / args.steps / ms_step, 4),
                 "schedule_bytes_per_launch": round((head["fwd_bytes"], head["adj_bytes"])[k] / kn[k]),
                 "schedule_GBps": round((head["fwd_bytes"], head["adj_bytes"])[k] / (kms[k] / 1e3) / 1e9, 1),
-                "counted_bytes_per_launch": round(traffic) if traffic is not None else None},
+                "counted_bytes_per_launch": round(traffic) if traffic is not None else None,
+                "note": ("the day slabs' launches run at the same time on their own streams, so "
+                         "launch durations overlap" if sch.get("slabs", 1) > 1 else None)},
             "schedule_model": {
                 "bytes_per_epoch": int(sched_b),
                 "frac": round(sched_b / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),

@@ -123,10 +123,13 @@ typedef struct {
                           the run (also used by the refinement steps; not
                           with day_tile 64, an argument error); same bits */
   int32_t slabs;       /* day slabs of a matrix-core epoch when day_tile != 0:
-                          the epoch runs every minibatch on the first slab of
-                          about D/slabs days, then on the next, so a slab's
-                          demand and accumulator rows can stay in the last-level
-                          cache; 0 or 1 = all days together; same bits */
+                          the day groups split into `slabs` parts of about
+                          D/slabs days, each with its own launches of every
+                          minibatch, run at the same time on streams of their
+                          own (forked from and joined to the run's stream in
+                          every epoch, also inside the epoch graph), so one
+                          part's launches fill the others' ramp and tail;
+                          0 or 1 = all days together; same bits */
 } dode_spgd_params;
 
 /* Message of the last failing call on this thread ("" if none). */

@@ -467,8 +467,6 @@ dode_status run_refinement(dode_plan* plan, hipStream_t s) {
   return DODE_OK;
 }
 
-// Every minibatch of epoch e (e < 0: the epoch in the device counter, for
-// graph capture), slab by slab, then the refinement steps.
 // Polls of a persistent launch's grid barrier before it gives up (about a
 // second); DODE_PERSIST_SPIN_LIMIT overrides it (tests of the error path).
 uint32_t persist_spin_limit() {
@@ -500,18 +498,46 @@ dode_status run_persistent(dode_plan* plan, int32_t e, hipStream_t s) {
   return DODE_OK;
 }
 
+// Every minibatch of epoch e (e < 0: the epoch in the device counter, for
+// graph capture), then the refinement steps.  With day slabs, slab k runs its
+// minibatches on its own stream, all slabs at the same time: their days are
+// disjoint, and one slab's launches fill the others' ramp and tail.
 dode_status run_epoch(dode_plan* plan, int32_t e, hipStream_t s) {
   if (plan->persistent && e >= 0) {
     if (dode_status st = run_persistent(plan, e, s)) return st;
     return run_refinement(plan, s);
   }
   const int32_t ns = plan->use_mfma ? plan->n_slabs : 1;
-  for (int32_t k = 0; k < ns; ++k)
+  const bool fork = ns > 1;
+  if (fork) {
+    // side stream k-1 runs slab k; the days of different slabs are disjoint
+    while ((int32_t)plan->side_streams.size() < ns - 1) {
+      hipStream_t t = nullptr;
+      HIP_TRY(hipStreamCreateWithFlags(&t, hipStreamNonBlocking));
+      plan->side_streams.push_back(t);
+    }
+    while ((int32_t)plan->slab_events.size() < ns) {
+      hipEvent_t ev = nullptr;
+      HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      plan->slab_events.push_back(ev);
+    }
+    HIP_TRY(hipEventRecord(plan->slab_events[0], s));
+    for (int32_t k = 1; k < ns; ++k)
+      HIP_TRY(hipStreamWaitEvent(plan->side_streams[k - 1], plan->slab_events[0], 0));
+  }
+  for (int32_t k = 0; k < ns; ++k) {
+    hipStream_t sk = fork && k > 0 ? plan->side_streams[k - 1] : s;
     for (int32_t j = 0; j < plan->nch; ++j) {
       const CompSched ks = plan->comps(e, j);
       const ChunkList ckl = plan->chunks(e, j);
       const ChunkSched cs = e < 0 ? plan->chunk_dev(j) : plan->chunk(e, j);
-      if (dode_status st = run_chunk(plan, cs, &ks, &ckl, s, false, ns > 1 ? k : -1)) return st;
+      if (dode_status st = run_chunk(plan, cs, &ks, &ckl, sk, false, ns > 1 ? k : -1)) return st;
+    }
+  }
+  if (fork)
+    for (int32_t k = 1; k < ns; ++k) {
+      HIP_TRY(hipEventRecord(plan->slab_events[k], plan->side_streams[k - 1]));
+      HIP_TRY(hipStreamWaitEvent(s, plan->slab_events[k], 0));
     }
   return run_refinement(plan, s);
 }
@@ -1700,6 +1726,8 @@ dode_status spgd_plan_destroy(dode_plan* plan) {
   if (plan->graph_exec) (void)hipGraphExecDestroy(plan->graph_exec);
   if (plan->graph) (void)hipGraphDestroy(plan->graph);
   if (plan->capture_stream) (void)hipStreamDestroy(plan->capture_stream);
+  for (hipStream_t t : plan->side_streams) (void)hipStreamDestroy(t);
+  for (hipEvent_t ev : plan->slab_events) (void)hipEventDestroy(ev);
   if (plan->d_epoch) (void)hipFree(plan->d_epoch);
   if (plan->d_mb) (void)hipFree(plan->d_mb);
   if (plan->d_bar) (void)hipFree(plan->d_bar);

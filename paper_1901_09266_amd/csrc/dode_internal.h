@@ -356,11 +356,13 @@ struct dode_plan {
   PersistMinibatch* d_mb = nullptr;
   PersistBarrier* d_bar = nullptr;
   int32_t adj_order = 0;          // ChunkSched::order of the matrix-core adjoint
-  // Day slabs: the matrix-core epoch runs every minibatch on the day groups of
-  // slab 0, then on those of slab 1, ...  (days are independent, so the
-  // results do not depend on the slabs); a slab's demand and accumulator rows
-  // can then stay in the last-level cache across its minibatches.
+  // Day slabs: the day groups split into n_slabs parts, each with its own
+  // launches of every minibatch; slab 0 runs on the run's stream and slab k on
+  // side stream k-1, forked and joined in every epoch, so the slabs' launches
+  // overlap (days are independent, so the results do not depend on the slabs).
   int32_t n_slabs = 1;
+  std::vector<hipStream_t> side_streams;
+  std::vector<hipEvent_t> slab_events;   // [0] fork, [1 + k] join of side stream k
   int32_t* d_slabs = nullptr;      // per slab: cluster | first | count | cbase | cgroups
   std::vector<int64_t> slab_off;   // offset of slab k in d_slabs (elements)
   std::vector<int32_t> slab_n;     // groups of slab k

@@ -97,6 +97,24 @@ def test_traffic_lookup_follows_the_source_hash(monkeypatch, tmp_path):
     assert bench.counted_traffic(3, "bf16", "adj") is None
 
 
+def test_traffic_per_epoch_and_schedule(monkeypatch, tmp_path):
+    """The per-epoch figures a summary records with the schedule it was taken
+    at: the minibatch launches' bytes per epoch, one refinement step's bytes,
+    and the schedule string; all refused once the sources change."""
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "profiles" / "traffic_spgd_config5_fp8.md").write_text(
+        "source_sha256: " + "ab" * 32 + "\nfwd_bytes_per_launch: 10\nadj_bytes_per_launch: 20\n"
+        "minibatch_bytes_per_epoch: 3480\nrefine_bytes_per_step: 77\nschedule: 64,1,2\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "ab" * 32)
+    assert bench.counted_traffic(5, "fp8", "minibatch") == 3480
+    assert bench.counted_traffic(5, "fp8", "refine") == 77
+    assert bench.counted_traffic(5, "fp8", "schedule") == "64,1,2"
+    assert bench.counted_traffic(5, "fp8", "refine_fwd") is None
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "cd" * 32)
+    assert bench.counted_traffic(5, "fp8", "minibatch") is None
+
+
 def test_epoch_bytes_is_the_touch_once_floor():
     """The headline roofline's bytes per epoch: each cluster's ratio nonzeros
     once (the lag band has sum_t min(K, H - t) blocks) plus, per day, X read
