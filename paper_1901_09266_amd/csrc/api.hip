@@ -511,16 +511,9 @@ dode_status run_epoch(dode_plan* plan, int32_t e, hipStream_t s) {
   const bool fork = ns > 1;
   if (fork) {
     // side stream k-1 runs slab k; the days of different slabs are disjoint
-    while ((int32_t)plan->side_streams.size() < ns - 1) {
-      hipStream_t t = nullptr;
-      HIP_TRY(hipStreamCreateWithFlags(&t, hipStreamNonBlocking));
-      plan->side_streams.push_back(t);
-    }
-    while ((int32_t)plan->slab_events.size() < ns) {
-      hipEvent_t ev = nullptr;
-      HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-      plan->slab_events.push_back(ev);
-    }
+    // (set_slabs made the streams and events, outside any graph capture)
+    if ((int32_t)plan->side_streams.size() < ns - 1 || (int32_t)plan->slab_events.size() < ns)
+      return fail(DODE_ERR_HIP, "day slab streams missing");
     HIP_TRY(hipEventRecord(plan->slab_events[0], s));
     for (int32_t k = 1; k < ns; ++k)
       HIP_TRY(hipStreamWaitEvent(plan->side_streams[k - 1], plan->slab_events[0], 0));
@@ -669,6 +662,17 @@ dode_status set_slabs(dode_plan* plan, int32_t n) {
   const int32_t G = (int32_t)plan->h_gc.size();
   n = std::max<int32_t>(1, std::min<int32_t>(n, G));
   drop_epoch_graph(plan);
+  // the streams and events of concurrent slabs (run_epoch forks and joins them)
+  while ((int32_t)plan->side_streams.size() < n - 1) {
+    hipStream_t t = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&t, hipStreamNonBlocking));
+    plan->side_streams.push_back(t);
+  }
+  while ((int32_t)plan->slab_events.size() < n) {
+    hipEvent_t ev = nullptr;
+    HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    plan->slab_events.push_back(ev);
+  }
   if (plan->d_slabs) HIP_TRY(hipFree(plan->d_slabs));
   plan->d_slabs = nullptr;
   plan->slab_off.clear();
