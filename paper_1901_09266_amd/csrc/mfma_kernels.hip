@@ -247,10 +247,9 @@ __device__ __forceinline__ void fwd_group(const DevPat& pt, const DevTiles& tl, 
   const int c = w.c, s = w.row, i0 = w.tile;
   const int first = w.first, cnt = w.count;
   const int n_tt = min(TP, tl.nLT - i0);   // tiles of this group (the last may be short)
-  // The observed rows X are fetched before the product in BF16 mode and after
-  // it in the FP8 modes, where the registers they would hold keep the FP8
-  // refinement forward at 4 waves per SIMD (measured faster; neutral in BF16).
-  constexpr bool kLateX = MODE != kBF16;
+  // The observed rows X are fetched after the product: the registers they
+  // would hold across it cost occupancy (measured faster in every mode with
+  // the benchmark schedules).
   bool live[NT];
   const float* qcol[NT];
   f32x4 x[TP][NT];
@@ -259,12 +258,6 @@ __device__ __forceinline__ void fwd_group(const DevPat& pt, const DevTiles& tl, 
     live[u] = 16 * u + n < cnt;
     const int64_t du = live[u] ? first + 16 * u + n : first;
     qcol[u] = Q + du * ly.q_d;
-    if constexpr (!kLateX) {
-#pragma unroll
-      for (int tt = 0; tt < TP; ++tt)
-        x[tt][u] = tt < n_tt ? load4(X + du * ly.x_d + h * ly.x_h + ((16 * (i0 + tt) + 4 * kg) >> 2) * ly.x_b)
-                             : f32x4{0.f, 0.f, 0.f, 0.f};
-    }
   }
   const int l_lo = h - pt.T + 1 > 0 ? h - pt.T + 1 : 0;
   const int l_hi = h < pt.K - 1 ? h : pt.K - 1;
@@ -336,15 +329,13 @@ __device__ __forceinline__ void fwd_group(const DevPat& pt, const DevTiles& tl, 
         }
       }
   }
-  if constexpr (kLateX) {
 #pragma unroll
-    for (int u = 0; u < NT; ++u) {
-      const int64_t du = live[u] ? first + 16 * u + n : first;
+  for (int u = 0; u < NT; ++u) {
+    const int64_t du = live[u] ? first + 16 * u + n : first;
 #pragma unroll
-      for (int tt = 0; tt < TP; ++tt)
-        x[tt][u] = tt < n_tt ? load4(X + du * ly.x_d + h * ly.x_h + ((16 * (i0 + tt) + 4 * kg) >> 2) * ly.x_b)
-                             : f32x4{0.f, 0.f, 0.f, 0.f};
-    }
+    for (int tt = 0; tt < TP; ++tt)
+      x[tt][u] = tt < n_tt ? load4(X + du * ly.x_d + h * ly.x_h + ((16 * (i0 + tt) + 4 * kg) >> 2) * ly.x_b)
+                           : f32x4{0.f, 0.f, 0.f, 0.f};
   }
 #pragma unroll
   for (int tt = 0; tt < TP; ++tt) {
