@@ -402,8 +402,9 @@ def dar_bench(args):
         import oracle as orc
         sample = days[0][:300]     # about 10 s of the single-threaded oracle
         t1 = time.perf_counter()
+        # the walk in binary32, as the FP32 GPU run takes its interval decisions
         Ro = orc.dar_from_speeds(si.path_ptr, si.path_link, si.link_len,
-                                 si.speed[sample].astype(np.float64), si.dt, H, K)
+                                 si.speed[sample].astype(np.float64), si.dt, H, K, walk="f32")
         dt_cpu = time.perf_counter() - t1
         out["cpu_baseline"] = {"value": round(len(sample) / dt_cpu, 3), "unit": "days/s", "cores": 1,
                                "kind": "oracle", "sample": f"{len(sample)} days of pattern 0, {dt_cpu:.1f}s"}
@@ -499,8 +500,8 @@ def choice_bench(args):
         sp64 = ci.speed[sample].astype(np.float64)
         ln64 = ci.link_len.astype(np.float32).astype(np.float64)
         t1 = time.perf_counter()
-        Ro = orc.dar_from_speeds(ci.path_ptr, ci.path_link, ln64, sp64, ci.dt, H, K)
-        co = orc.path_costs(ci.path_ptr, ci.path_link, ln64, sp64, ci.dt, T)
+        Ro = orc.dar_from_speeds(ci.path_ptr, ci.path_link, ln64, sp64, ci.dt, H, K, walk="f32")
+        co = orc.path_costs(ci.path_ptr, ci.path_link, ln64, sp64, ci.dt, T, walk="f32")
         Wo = orc.rho_from_portions(ci.P, ci.L, T, H, K, ci.path_od, ci.path_ptr, ci.path_link,
                                    ci.row_ptr, ci.col_idx, Ro,
                                    orc.logit_portions(ci.P, ci.path_od, theta, co))

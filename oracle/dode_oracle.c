@@ -404,6 +404,14 @@ int orc_logits_backward(const orc_dims* dm, int32_t n_paths, const int32_t* path
  * they are traversed; pair m = path_ptr[k] + i is the i-th link of path k.
  * Output Rr[K][H][n_pairs] = the mean over the n_days days of each day's
  * ratios (one averaged ratio set per traffic pattern).
+ *
+ * walk_f32 = 1 takes the walk's interval decisions (which speed a link is
+ * crossed at) in binary32, the precision of a single-precision GPU run, so
+ * that both sides pick the same speeds: the departure time t0 = h*dt, the
+ * travel time so far r and each link time len/speed are binary32 values, and
+ * a link is entered at the binary32 sum t0 + r (tau_i(t0) = t0 + r_i, the same
+ * recursion as eq. "cost" with the departure time taken out).  The windows,
+ * shares and day means stay in binary64.  walk_f32 = 0 is the binary64 walk.
  * ---------------------------------------------------------------------- */
 static double link_time(const double* len, const double* speed_day, int32_t H_speed, double dt,
                         int32_t a, double t) {
@@ -411,6 +419,15 @@ static double link_time(const double* len, const double* speed_day, int32_t H_sp
   if (h < 0) h = 0;
   if (h >= H_speed) h = H_speed - 1;
   return len[a] / speed_day[IDX2(a, h, H_speed)];
+}
+
+/* the link time of link_time with every operation in binary32 */
+static float link_time_f32(const double* len, const double* speed_day, int32_t H_speed, float dt,
+                           int32_t a, float t) {
+  int64_t h = (int64_t)floorf(t / dt);
+  if (h < 0) h = 0;
+  if (h >= H_speed) h = H_speed - 1;
+  return (float)len[a] / (float)speed_day[IDX2(a, h, H_speed)];
 }
 
 /* overlap length of [lo, hi] with [h2*dt, (h2+1)*dt) */
@@ -421,8 +438,10 @@ static double overlap(double lo, double hi, int64_t h2, double dt) {
 
 int orc_dar_from_speeds(int32_t n_paths, const int32_t* path_ptr, const int32_t* path_link,
                         int32_t L, const double* len, const double* speed, int32_t n_days,
-                        int32_t H_speed, double dt, int32_t H, int32_t K, double* Rr) {
+                        int32_t H_speed, double dt, int32_t H, int32_t K, int32_t walk_f32,
+                        double* Rr) {
   const int64_t n_pairs = path_ptr[n_paths];
+  const float dt32 = (float)dt;
   memset(Rr, 0, sizeof(double) * (size_t)K * H * n_pairs);
   if (n_days < 1) return 0;
   for (int32_t d = 0; d < n_days; ++d) {
@@ -431,8 +450,14 @@ int orc_dar_from_speeds(int32_t n_paths, const int32_t* path_ptr, const int32_t*
       for (int32_t h = 0; h < H; ++h) {
         /* the two boundary trajectories of departure interval h */
         double s = h * dt, e = (h + 1) * dt;
+        const float s0 = (float)h * dt32, e0 = (float)(h + 1) * dt32;
+        float rs = 0.0f, re = 0.0f; /* binary32 travel times so far */
         for (int32_t m = path_ptr[k]; m < path_ptr[k + 1]; ++m) {
           const int32_t a = path_link[m];
+          if (walk_f32) {
+            s = (double)s0 + (double)rs;
+            e = (double)e0 + (double)re;
+          }
           double lo = s, hi = e;
           if (hi < lo) { const double tmp = lo; lo = hi; hi = tmp; }
           const double w = hi - lo;
@@ -446,8 +471,13 @@ int orc_dar_from_speeds(int32_t n_paths, const int32_t* path_ptr, const int32_t*
               Rr[IDX2(IDX2(h2 - h, h, H), m, n_pairs)] += overlap(lo, hi, h2, dt) / w / n_days;
             }
           }
-          s += link_time(len, sp, H_speed, dt, a, s);
-          e += link_time(len, sp, H_speed, dt, a, e);
+          if (walk_f32) {
+            rs += link_time_f32(len, sp, H_speed, dt32, a, s0 + rs);
+            re += link_time_f32(len, sp, H_speed, dt32, a, e0 + re);
+          } else {
+            s += link_time(len, sp, H_speed, dt, a, s);
+            e += link_time(len, sp, H_speed, dt, a, e);
+          }
         }
       }
   }
@@ -464,11 +494,15 @@ int orc_dar_from_speeds(int32_t n_paths, const int32_t* path_ptr, const int32_t*
  * in which the vehicle enters it (the link time of orc_dar_from_speeds).  The
  * portions of interval t use the departure at the interval's start, t1 = t*dt
  * (eq. "rt" holds them constant over the interval), and c~ is the mean of the
- * n_days days' costs.  Output cost[T][n_paths].
+ * n_days days' costs.  Output cost[T][n_paths].  walk_f32 as for
+ * orc_dar_from_speeds: the day's travel time is walked in binary32 (departure
+ * time, travel time so far and link times binary32, links entered at their
+ * binary32 sum) and summed over the days in binary64.
  * ---------------------------------------------------------------------- */
 int orc_path_costs(int32_t n_paths, const int32_t* path_ptr, const int32_t* path_link, int32_t L,
                    const double* len, const double* speed, int32_t n_days, int32_t H_speed,
-                   double dt, int32_t T, double* cost) {
+                   double dt, int32_t T, int32_t walk_f32, double* cost) {
+  const float dt32 = (float)dt;
   memset(cost, 0, sizeof(double) * (size_t)T * n_paths);
   if (n_days < 1) return 0;
   for (int32_t t = 0; t < T; ++t)
@@ -476,6 +510,14 @@ int orc_path_costs(int32_t n_paths, const int32_t* path_ptr, const int32_t* path
       double sum = 0.0;
       for (int32_t d = 0; d < n_days; ++d) {
         const double* sp = speed + (int64_t)d * L * H_speed;
+        if (walk_f32) {
+          const float t0 = (float)t * dt32;
+          float r = 0.0f; /* travel time so far */
+          for (int32_t m = path_ptr[k]; m < path_ptr[k + 1]; ++m)
+            r += link_time_f32(len, sp, H_speed, dt32, path_link[m], t0 + r);
+          sum += (double)r;
+          continue;
+        }
         const double t1 = t * dt;
         double tau = t1; /* entry time of the current link */
         for (int32_t m = path_ptr[k]; m < path_ptr[k + 1]; ++m)

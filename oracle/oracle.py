@@ -98,9 +98,9 @@ def lib():
                                           iptr, dptr, dptr]
         i32 = ctypes.c_int32
         L.orc_dar_from_speeds.argtypes = [i32, iptr, iptr, i32, dptr, dptr, i32, i32,
-                                          ctypes.c_double, i32, i32, dptr]
+                                          ctypes.c_double, i32, i32, i32, dptr]
         L.orc_path_costs.argtypes = [i32, iptr, iptr, i32, dptr, dptr, i32, i32, ctypes.c_double,
-                                     i32, dptr]
+                                     i32, i32, dptr]
         L.orc_logit_portions.argtypes = [i32, i32, iptr, i32, ctypes.c_double, dptr, dptr]
         L.orc_logit_portions.restype = None
         L.orc_dense_loss.argtypes = [i32, i32, dptr, dptr, dptr]
@@ -371,11 +371,21 @@ def fixed_step_eta(inst, c=0, iters=200):
     return 1.0 / lam
 
 
-def dar_from_speeds(path_ptr, path_link, link_len, speed, dt, H, K):
+def _walk_flag(walk):
+    if walk not in ("f64", "f32"):
+        raise ValueError(f"walk must be 'f64' or 'f32', not {walk!r}")
+    return 1 if walk == "f32" else 0
+
+
+def dar_from_speeds(path_ptr, path_link, link_len, speed, dt, H, K, walk="f64"):
     """Dynamic assignment ratios from link speeds (eqs. "dar", "cost"; see
     orc_dar_from_speeds): speed is [n_days][L][H_speed] (or [L][H_speed] for
     one day), link_len [L] in the same distance unit, dt in the time unit of
-    length/speed.  Returns Rr[K][H][n_pairs], the mean over the days."""
+    length/speed.  Returns Rr[K][H][n_pairs], the mean over the days.
+
+    walk="f32" decides which interval's speed each link is crossed at in
+    binary32 (lengths and speeds rounded to binary32, travel times summed in
+    binary32), as a single-precision run does; the rest stays FP64."""
     path_ptr, pp = _i(np.asarray(path_ptr))
     path_link, plp = _i(np.asarray(path_link))
     sp = np.asarray(speed, dtype=np.float64)
@@ -389,16 +399,17 @@ def dar_from_speeds(path_ptr, path_link, link_len, speed, dt, H, K):
     out = np.zeros((K, H, n_pairs))
     _, op = _d(out)
     rc = lib().orc_dar_from_speeds(n_paths, pp, plp, L, lnp, spp, n_days, H_speed,
-                                   ctypes.c_double(dt), H, K, op)
+                                   ctypes.c_double(dt), H, K, _walk_flag(walk), op)
     if rc != 0:
         raise RuntimeError(f"orc_dar_from_speeds failed ({rc})")
     return out
 
 
-def path_costs(path_ptr, path_link, link_len, speed, dt, T):
+def path_costs(path_ptr, path_link, link_len, speed, dt, T, walk="f64"):
     """Mean path travel time per departure interval (eqs. "cost", "logit",
     "rt"; see orc_path_costs): speed [n_days][L][H_speed] (or [L][H_speed]),
-    departures at t*dt for t < T.  Returns cost[T][n_paths]."""
+    departures at t*dt for t < T.  Returns cost[T][n_paths].  walk as for
+    dar_from_speeds (each day's travel time walked in binary32)."""
     path_ptr, pp = _i(np.asarray(path_ptr))
     path_link, plp = _i(np.asarray(path_link))
     sp = np.asarray(speed, dtype=np.float64)
@@ -411,7 +422,7 @@ def path_costs(path_ptr, path_link, link_len, speed, dt, T):
     out = np.zeros((T, n_paths))
     _, op = _d(out)
     rc = lib().orc_path_costs(n_paths, pp, plp, L, lnp, spp, n_days, H_speed, ctypes.c_double(dt),
-                              T, op)
+                              T, _walk_flag(walk), op)
     if rc != 0:
         raise RuntimeError(f"orc_path_costs failed ({rc})")
     return out

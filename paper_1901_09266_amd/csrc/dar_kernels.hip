@@ -63,6 +63,9 @@ k_trajectories(int32_t n_paths, const int32_t* __restrict__ path_ptr,
                const int32_t* __restrict__ path_link, int32_t L, const S* __restrict__ len,
                const S* __restrict__ speed, int32_t day0, int32_t n_days, int32_t H_speed, S dt,
                int32_t H, int64_t n_pairs, S* __restrict__ traj, S* __restrict__ exit_time) {
+  // The entry time t0 + r is a sum of its own, never fused with the product
+  // b * dt: which interval's speed a link takes is decided by the rounded sum.
+#pragma clang fp contract(off)
   constexpr int kDays = kTrajDays;
   const int64_t per_group = (int64_t)n_paths * (H + 1);
   const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -201,6 +204,7 @@ k_path_cost_slices(int32_t n_paths, const int32_t* __restrict__ path_ptr,
                    const int32_t* __restrict__ path_link, int32_t L, const S* __restrict__ len,
                    const S* __restrict__ speed, int32_t n_days, int32_t per_slice, int32_t n_slices,
                    int32_t H_speed, S dt, int32_t T, double* __restrict__ partial) {
+#pragma clang fp contract(off)   // as in k_trajectories
   const int64_t per = (int64_t)n_paths * T;
   const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (idx >= per * n_slices) return;

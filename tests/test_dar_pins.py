@@ -136,3 +136,53 @@ def test_fifo_violation_and_zero_window():
     sp[0, 0], sp[0, 1] = 0.5, 4.0 / 3.0
     R = orc.dar_from_speeds(pp, pl, ln, sp, dt, H, K)
     assert R[1, 0, 1] == pytest.approx(1.0) and R[:, 0, 1].sum() == pytest.approx(1.0)
+
+
+def binary32_boundary_path():
+    """Three links; the first takes 5 - 1e-9 minutes at speed 1, which is
+    5 exactly once rounded to binary32, so a binary32 walk enters the second
+    link at the 5-minute boundary (interval 1, speed 0.5) and a binary64 walk
+    just before it (interval 0, speed 1)."""
+    dt, H, K = 5.0, 6, 4
+    pp, pl, ln = one_path([5.0 - 1e-9, 1.0, 1.0])
+    sp = np.ones((3, H))
+    sp[1, 1] = 0.5
+    assert np.float32(ln[0]) == np.float32(5.0) and ln[0] < 5.0
+    return dt, H, K, pp, pl, ln, sp
+
+
+def test_binary32_walk_decides_in_binary32():
+    """walk="f32" takes the entry interval from the binary32 travel times.
+    Departure interval 0 at the third link: the departure at 0 enters it at
+    5 + 1/0.5 = 7 in binary32 (6 - 1e-9 in binary64), the one at 5 at
+    5 + 5 + 1 = 11 (12 - 1e-9: link 1 entered at 10 - 1e-9, in interval 1).
+    The windows [7, 11] and [6, 12] split over intervals 1 and 2 as 3:1 and
+    4:2; the path costs of the departure at 0 (all three links) are 8 and
+    7 - 1e-9."""
+    dt, H, K, pp, pl, ln, sp = binary32_boundary_path()
+    R32 = orc.dar_from_speeds(pp, pl, ln, sp, dt, H, K, walk="f32")
+    R64 = orc.dar_from_speeds(pp, pl, ln, sp, dt, H, K)
+    assert (R32[1, 0, 2], R32[2, 0, 2]) == (0.75, 0.25)
+    assert R64[1, 0, 2] == pytest.approx(4.0 / 6.0, abs=1e-9)
+    assert R64[2, 0, 2] == pytest.approx(2.0 / 6.0, abs=1e-9)
+    c32 = orc.path_costs(pp, pl, ln, sp, dt, 2, walk="f32")
+    c64 = orc.path_costs(pp, pl, ln, sp, dt, 2)
+    assert c32[0, 0] == 8.0 and c64[0, 0] == pytest.approx(7.0, abs=1e-8)
+    with pytest.raises(ValueError):
+        orc.path_costs(pp, pl, ln, sp, dt, 2, walk="f16")
+
+
+def test_binary32_walk_equals_binary64_when_exact():
+    """Lengths in quarter units and speeds in {0.5, 1, 2, 4}: every travel
+    time is a short binary fraction, exact in binary32, so both walks take the
+    same decisions and give the same bits."""
+    rng = np.random.default_rng(21)
+    si = make_speed_instance(L=64, P=12, H=48, sizes=(3,), inc=0.1, seed=22)
+    ln = rng.integers(1, 24, size=si.link_len.shape) * 0.25
+    sp = np.array([0.5, 1.0, 2.0, 4.0])[rng.integers(0, 4, size=si.speed.shape)]
+    R32 = orc.dar_from_speeds(si.path_ptr, si.path_link, ln, sp, si.dt, si.H, 8, walk="f32")
+    R64 = orc.dar_from_speeds(si.path_ptr, si.path_link, ln, sp, si.dt, si.H, 8)
+    assert np.array_equal(R32, R64) and R64.max() > 0
+    c32 = orc.path_costs(si.path_ptr, si.path_link, ln, sp, si.dt, si.H, walk="f32")
+    c64 = orc.path_costs(si.path_ptr, si.path_link, ln, sp, si.dt, si.H)
+    assert np.array_equal(c32, c64)

@@ -84,10 +84,12 @@ int main(void) {
   for (int i = 0; i < 2 * 7 * 6; ++i) speed[i] = 0.05 + speed[i];
   speed[0] = 0.01; speed[1] = 5.0;   /* overtaking on link 0 of day 0 */
   double* Rs = arr((size_t)dm.K * dm.H * 6);
-  if (orc_dar_from_speeds(3, pair_ptr, pair_link, 7, len, speed, 2, 6, 5.0, dm.H, dm.K, Rs)) return 6;
+  if (orc_dar_from_speeds(3, pair_ptr, pair_link, 7, len, speed, 2, 6, 5.0, dm.H, dm.K, 1, Rs)) return 6;
+  if (orc_dar_from_speeds(3, pair_ptr, pair_link, 7, len, speed, 2, 6, 5.0, dm.H, dm.K, 0, Rs)) return 6;
   double* cost = arr((size_t)dm.T * 3);
   double* port = arr((size_t)dm.T * 3);
-  if (orc_path_costs(3, pair_ptr, pair_link, 7, len, speed, 2, 6, 5.0, dm.T, cost)) return 7;
+  if (orc_path_costs(3, pair_ptr, pair_link, 7, len, speed, 2, 6, 5.0, dm.T, 1, cost)) return 7;
+  if (orc_path_costs(3, pair_ptr, pair_link, 7, len, speed, 2, 6, 5.0, dm.T, 0, cost)) return 7;
   orc_logit_portions(dm.P, 3, path_od, dm.T, 0.6, cost, port);
   if (orc_rho_from_portions(&dm, 3, path_od, pair_ptr, pair_link, Rs, port, row_ptr, col, Wr)) return 8;
 
