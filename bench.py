@@ -57,9 +57,11 @@ FORMS = {
 }
 
 
+# the kernels and the order their launches take their items in
 KERNEL_SOURCES = ("paper_1901_09266_amd/csrc/mfma_kernels.hip",
                   "paper_1901_09266_amd/csrc/plain_kernels.hip",
-                  "paper_1901_09266_amd/csrc/dode_internal.h")
+                  "paper_1901_09266_amd/csrc/dode_internal.h",
+                  "paper_1901_09266_amd/csrc/work_tables.hip")
 
 
 def kernel_source_hash():

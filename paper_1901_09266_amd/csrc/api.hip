@@ -565,41 +565,6 @@ void drop_epoch_graph(dode_plan* plan) {
   plan->graph = nullptr;
 }
 
-// Work table of a grouped matrix-core launch over a group list (cluster,
-// first day, day count per group; a cluster's groups are consecutive): items
-// (cluster, row u, group, tile k) with k fastest, u over per_cluster rows and
-// k over n_tiles, the order the launches have always used (all day groups of
-// a cluster that need the same assignment tiles run back to back).  fwd: rows
-// are minibatch slots, tiles link tiles; adjoint: rows are descriptor
-// indices, tiles OD tiles, swapped when `tile_major` (the OD-tile-major order).
-std::vector<WaveWork> work_table(const dode_dar* dar, const std::vector<int32_t>& gc,
-                                 const std::vector<int32_t>& gf, const std::vector<int32_t>& gn,
-                                 bool fwd, int32_t rows, bool tile_major) {
-  const int32_t nLT = dar->tiles.nLT, nPT = dar->tiles.nPT;
-  const std::vector<int32_t>& m = dar->h_tile_meta;
-  const int32_t* ks = fwd ? m.data() + nLT : m.data() + 3 * nLT + nPT;
-  const int32_t* lo = fwd ? m.data() : m.data() + 3 * nLT;
-  const int32_t* ko = fwd ? m.data() + 2 * nLT : m.data() + 3 * nLT + 2 * nPT;
-  // forward waves take a group of kFwdTileGroup link tiles (tile = its first)
-  const int32_t step = fwd ? kFwdTileGroup : 1;
-  const int32_t n_tiles = fwd ? (nLT + step - 1) / step : nPT;
-  const int32_t per = tile_major ? n_tiles : rows, inner = tile_major ? rows : n_tiles;
-  std::vector<WaveWork> out;
-  out.reserve((size_t)gc.size() * rows * n_tiles);
-  for (size_t g0 = 0; g0 < gc.size();) {
-    size_t g1 = g0 + 1;
-    while (g1 < gc.size() && gc[g1] == gc[g0]) ++g1;
-    for (int32_t u = 0; u < per; ++u)
-      for (size_t g = g0; g < g1; ++g)
-        for (int32_t k = 0; k < inner; ++k) {
-          const int32_t row = tile_major ? k : u, tile = (tile_major ? u : k) * step;
-          out.push_back(WaveWork{gc[g0], gf[g], gn[g], row, tile, ks[tile], lo[tile], ko[tile]});
-        }
-    g0 = g1;
-  }
-  return out;
-}
-
 void free_tables(dode_plan::WaveTables& t) {
   for (WaveWork* p : {t.fwd, t.adj[0], t.adj[1], t.adj[2]})
     if (p) (void)hipFree(p);
@@ -630,11 +595,13 @@ dode_status build_wave_tables(dode_plan* plan, const std::vector<std::vector<int
   if (!dar->has_tiles) return DODE_OK;
   for (size_t k = 0; k < slab_gc.size(); ++k) {
     dode_plan::WaveTables t;
-    const auto f = work_table(dar, slab_gc[k], slab_gf[k], slab_gn[k], true, plan->bh, false);
-    const auto a0 = work_table(dar, slab_gc[k], slab_gf[k], slab_gn[k], false, plan->mt, false);
-    const auto a1 = work_table(dar, slab_gc[k], slab_gf[k], slab_gn[k], false, plan->kmt, true);
-    const auto a2 =
-        work_table(dar, slab_gc[k], slab_gf[k], slab_gn[k], false, plan->max_chunks, true);
+    // the chunked adjoint with the day groups fastest (measured faster: its
+    // items read up to kChunkT intervals' tiles, shared by the day groups)
+    const auto f = work_table(dar, slab_gc[k], slab_gf[k], slab_gn[k], true, plan->bh, false, false);
+    const auto a0 = work_table(dar, slab_gc[k], slab_gf[k], slab_gn[k], false, plan->mt, false, false);
+    const auto a1 = work_table(dar, slab_gc[k], slab_gf[k], slab_gn[k], false, plan->kmt, true, false);
+    const auto a2 = work_table(dar, slab_gc[k], slab_gf[k], slab_gn[k], false, plan->max_chunks,
+                               true, true);
     hipError_t e = upload_table(f, &t.fwd, &t.n_fwd);
     if (e == hipSuccess) e = upload_table(a0, &t.adj[0], &t.n_adj[0]);
     if (e == hipSuccess) e = upload_table(a1, &t.adj[1], &t.n_adj[1]);
@@ -644,10 +611,12 @@ dode_status build_wave_tables(dode_plan* plan, const std::vector<std::vector<int
   }
   if (plan->refine_steps > 0) {
     const int32_t H = dar->dims.H, T = dar->dims.T;
-    const auto f = work_table(dar, plan->h_gc, plan->h_gf, plan->h_gn, true, H, false);
-    const auto a = work_table(dar, plan->h_gc, plan->h_gf, plan->h_gn, false, T, false);
+    // full-batch steps: the day groups fastest, so the groups of a cluster
+    // read each tile while it is in L2 (the tiles of every interval do not fit)
+    const auto f = work_table(dar, plan->h_gc, plan->h_gf, plan->h_gn, true, H, false, true);
+    const auto a = work_table(dar, plan->h_gc, plan->h_gf, plan->h_gn, false, T, false, true);
     const auto a2 = work_table(dar, plan->h_gc, plan->h_gf, plan->h_gn, false,
-                               std::max<int32_t>(1, plan->full_chunks), true);
+                               std::max<int32_t>(1, plan->full_chunks), true, true);
     HIP_TRY(upload_table(f, &plan->wt_full.fwd, &plan->wt_full.n_fwd));
     HIP_TRY(upload_table(a, &plan->wt_full.adj[0], &plan->wt_full.n_adj[0]));
     HIP_TRY(upload_table(a2, &plan->wt_full.adj[2], &plan->wt_full.n_adj[2]));

@@ -318,6 +318,11 @@ struct WaveWork {
   int32_t c, first, count, row, tile, nks, lo, koff;
 };
 
+// Work table of one grouped launch over a day-group list (work_tables.hip).
+std::vector<WaveWork> work_table(const dode_dar* dar, const std::vector<int32_t>& gc,
+                                 const std::vector<int32_t>& gf, const std::vector<int32_t>& gn,
+                                 bool fwd, int32_t rows, bool tile_major, bool group_fastest);
+
 // Zeroed elements past the end of each plan state array (X, Q, A, R).
 constexpr int64_t kStatePad = 64;
 
