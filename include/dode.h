@@ -117,13 +117,13 @@ typedef struct {
   int32_t adj_order;   /* order of the matrix-core adjoint's work items when
                           day_tile != 0: 0 = by reached interval, OD tiles
                           fastest; 1 = by OD tile, reached intervals fastest
-                          (neighbouring waves share residual rows); 2 = by
-                          OD tile, one wave per run of up to 6 consecutive
-                          reached intervals, which loads each residual row
-                          once for the run, day groups fastest (neighbouring
-                          waves share the run's tiles; also used by the
-                          refinement steps; not with day_tile 64, an argument
-                          error); same bits */
+                          (neighbouring waves share residual rows); 2 = one
+                          wave per run of up to 6 consecutive reached
+                          intervals, which loads each residual row once for
+                          the run; by run, then OD tile, day groups fastest
+                          (neighbouring waves share the run's tiles; also
+                          used by the refinement steps; not with day_tile 64,
+                          an argument error); same bits */
   int32_t slabs;       /* day slabs of a matrix-core epoch when day_tile != 0:
                           the day groups split into `slabs` parts of about
                           D/slabs days, each with its own launches of every

@@ -595,13 +595,14 @@ dode_status build_wave_tables(dode_plan* plan, const std::vector<std::vector<int
   if (!dar->has_tiles) return DODE_OK;
   for (size_t k = 0; k < slab_gc.size(); ++k) {
     dode_plan::WaveTables t;
-    // the chunked adjoint with the day groups fastest (measured faster: its
-    // items read up to kChunkT intervals' tiles, shared by the day groups)
+    // the chunked adjoint by chunk, then OD tile, with the day groups fastest
+    // (measured fastest: neighbouring waves share the up to kChunkT
+    // intervals' tiles, and the OD tiles of a chunk its residual rows)
     const auto f = work_table(dar, slab_gc[k], slab_gf[k], slab_gn[k], true, plan->bh, false, false);
     const auto a0 = work_table(dar, slab_gc[k], slab_gf[k], slab_gn[k], false, plan->mt, false, false);
     const auto a1 = work_table(dar, slab_gc[k], slab_gf[k], slab_gn[k], false, plan->kmt, true, false);
     const auto a2 = work_table(dar, slab_gc[k], slab_gf[k], slab_gn[k], false, plan->max_chunks,
-                               true, true);
+                               false, true);
     hipError_t e = upload_table(f, &t.fwd, &t.n_fwd);
     if (e == hipSuccess) e = upload_table(a0, &t.adj[0], &t.n_adj[0]);
     if (e == hipSuccess) e = upload_table(a1, &t.adj[1], &t.n_adj[1]);
@@ -616,7 +617,7 @@ dode_status build_wave_tables(dode_plan* plan, const std::vector<std::vector<int
     const auto f = work_table(dar, plan->h_gc, plan->h_gf, plan->h_gn, true, H, false, true);
     const auto a = work_table(dar, plan->h_gc, plan->h_gf, plan->h_gn, false, T, false, true);
     const auto a2 = work_table(dar, plan->h_gc, plan->h_gf, plan->h_gn, false,
-                               std::max<int32_t>(1, plan->full_chunks), true, true);
+                               std::max<int32_t>(1, plan->full_chunks), false, true);
     HIP_TRY(upload_table(f, &plan->wt_full.fwd, &plan->wt_full.n_fwd));
     HIP_TRY(upload_table(a, &plan->wt_full.adj[0], &plan->wt_full.n_adj[0]));
     HIP_TRY(upload_table(a2, &plan->wt_full.adj[2], &plan->wt_full.n_adj[2]));
