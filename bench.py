@@ -717,8 +717,8 @@ def spgd_leg(args, dode, torch, config, form, compare, refine, pattern=None, per
     runs = np.array(head["ms_runs"]) / args.steps
     ms_step = float(np.median(runs))            # the median of the five timed runs
     value = inst.D / (ms_step / 1e3)
-    # Roofline: the survey's algorithmic bytes of one epoch (every array
-    # touched once) over the measured epoch time.
+    # Roofline: the algorithmic bytes of one epoch (every array touched
+    # once) over the measured epoch time.
     B = epoch_bytes(inst, form)
     B_q32 = epoch_bytes(inst, form, s_q=4)
     achieved = B / (ms_step / 1e3) / 1e9
@@ -757,7 +757,7 @@ def spgd_leg(args, dode, torch, config, form, compare, refine, pattern=None, per
             "traffic_schedule": look("schedule"),
             "timed_schedule": timed_sched,
             "bytes_per_epoch": int(B),
-            "bytes_basis": "survey 8(d): ratio nonzeros once + per day X read, Q read+write "
+            "bytes_basis": "touch-once bytes: ratio nonzeros once + per day X read, Q read+write "
                            f"({ {'f64': 8, 'f32': 4}.get(form, 2)} B), A read+write (4 B)",
             "frac_if_q_fp32": round(B_q32 / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
             "dominant_kernel": {

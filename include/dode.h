@@ -54,7 +54,7 @@ typedef enum {
   DODE_ERR_NONFINITE = 4,   /* NaN or Inf in the observations or values */
   DODE_ERR_OOM = 5,         /* device allocation failed */
   DODE_ERR_HIP = 6,         /* a HIP runtime call failed */
-  DODE_ERR_UNSUPPORTED = 7  /* valid request this build does not implement */
+  DODE_ERR_UNSUPPORTED = 7  /* valid request the library does not implement */
 } dode_status;
 
 typedef enum {
