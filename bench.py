@@ -768,8 +768,11 @@ def spgd_leg(args, dode, torch, config, form, compare, refine, pattern=None, per
                 "schedule_bytes_per_launch": round((head["fwd_bytes"], head["adj_bytes"])[k] / kn[k]),
                 "schedule_GBps": round((head["fwd_bytes"], head["adj_bytes"])[k] / (kms[k] / 1e3) / 1e9, 1),
                 "counted_bytes_per_launch": round(traffic) if traffic is not None else None,
-                "note": ("the day slabs' launches run at the same time on their own streams, so "
-                         "launch durations overlap" if sch.get("slabs", 1) > 1 else None)},
+                "counted_GBps": (round(traffic / (kms[k] / kn[k] / 1e3) / 1e9, 1)
+                                 if traffic is not None else None),
+                "note": ("per-launch times from a pass with the day slabs one after another "
+                         "(each launch alone); in the timed epochs the slabs' launches share "
+                         "the GPU" if sch.get("slabs", 1) > 1 else None)},
             "schedule_model": {
                 "bytes_per_epoch": int(sched_b),
                 "frac": round(sched_b / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),

@@ -481,7 +481,8 @@ dode_status spgd_run(dode_plan* plan, int32_t epoch_begin, int32_t n_epochs, dou
 
 /*
  * Kernel timing of a plan.  enable != 0 makes later spgd_run calls record a
- * HIP event pair around every kernel launch on the run's stream; the summed
+ * HIP event pair around every kernel launch on the run's stream (day slabs
+ * then run one after another on that stream, each launch alone); the summed
  * durations in milliseconds (host [3]: forward-residual launches, adjoint-step
  * launches or whole-minibatch launches of the one-launch path, loss kernels)
  * and the launch counts (host [3]) are returned and reset by the next call

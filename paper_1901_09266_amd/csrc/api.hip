@@ -501,14 +501,16 @@ dode_status run_persistent(dode_plan* plan, int32_t e, hipStream_t s) {
 // Every minibatch of epoch e (e < 0: the epoch in the device counter, for
 // graph capture), then the refinement steps.  With day slabs, slab k runs its
 // minibatches on its own stream, all slabs at the same time: their days are
-// disjoint, and one slab's launches fill the others' ramp and tail.
+// disjoint, and one slab's launches fill the others' ramp and tail.  While
+// kernel timing is on the slabs run one after another on `s`, so each event
+// pair brackets one launch running alone.
 dode_status run_epoch(dode_plan* plan, int32_t e, hipStream_t s) {
   if (plan->persistent && e >= 0) {
     if (dode_status st = run_persistent(plan, e, s)) return st;
     return run_refinement(plan, s);
   }
   const int32_t ns = plan->use_mfma ? plan->n_slabs : 1;
-  const bool fork = ns > 1;
+  const bool fork = ns > 1 && !plan->timing;
   if (fork) {
     // side stream k-1 runs slab k; the days of different slabs are disjoint
     // (set_slabs made the streams and events, outside any graph capture)

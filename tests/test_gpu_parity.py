@@ -739,3 +739,43 @@ def test_refinement_orders_give_identical_results():
     for key in outs:
         for a, b in zip(outs[key], outs[(32, 0, 0)]):
             np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("slabs", [1, 2])
+def test_kernel_timing_keeps_the_bits(slabs):
+    """With kernel timing on, every launch gets an event pair (and day slabs
+    run one after another on the run's stream); the demand, the accumulator
+    and the loss history are the same bits as without timing, and the launch
+    counts are those of the schedule."""
+    inst = make_instance(demand="gamma", noise="mult5", x_dtype="f32", seed=131,
+                         **ONE_LAUNCH_SHAPES["corridor"])
+    say("kernel timing keeps the bits", slabs)
+    E = 5
+    perms = make_perms(132, E, inst.C, inst.H)
+    dar = make_dar(inst, "bf16")
+    X = dev(inst.x, torch.float32)
+    Q0 = torch.zeros((inst.D, inst.T, inst.P), dtype=torch.float32, device="cuda")
+    outs = []
+    for timing in (False, True):
+        p = dode.make_params(epochs=E, batch_rows=8192, eta=5.0, day_tile=32, adj_order=2,
+                             slabs=slabs)
+        plan = dode.spgd_plan_create(dar, inst.day_cluster, p, perm=perms, stream=0)
+        dode.spgd_plan_load(plan, X, Q0)
+        assert dode.spgd_plan_schedule(plan)["slabs"] == slabs
+        loss = torch.zeros((E, inst.D), dtype=torch.float64, device="cuda")
+        dode.spgd_run(plan, 0, 2, loss=loss[:2])
+        if timing:
+            dode.spgd_plan_timing(plan, True)
+        dode.spgd_run(plan, 2, E - 2, loss=loss[2:])
+        if timing:
+            ms, n = dode.spgd_plan_timing(plan, False)
+            nch = dode.spgd_plan_info(plan)["n_minibatches"]
+            assert n[0] == n[1] == (E - 2) * nch * slabs
+            assert ms[0] > 0 and ms[1] > 0
+        Q = torch.empty_like(Q0)
+        A = torch.empty_like(Q0)
+        dode.spgd_plan_store(plan, Q, A)
+        torch.cuda.synchronize()
+        outs.append((Q.cpu().numpy(), A.cpu().numpy(), loss.cpu().numpy()))
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
