@@ -58,8 +58,28 @@ def quantize_bf16(v):
     return np.ldexp(np.round(m * 256.0), e - 8)   # np.round is round-half-even
 
 
+def fp8_values(W, col_idx):
+    """(FP8 values, corrected values) of one cluster's [K][T][nnz] values: one
+    FP32 scale per (lag, interval, 64-OD group); the corrected value of
+    refinement steps is h + c with h = bf16(fp32(scale * code)), c = bf16(w - h)."""
+    tiles = col_idx // 64
+    Wq, Wr = np.zeros_like(W), np.zeros_like(W)
+    for tile in np.unique(tiles):
+        sel = tiles == tile
+        Ws = W[:, :, sel]
+        amax = np.abs(Ws).max(axis=2, keepdims=True)
+        sc = np.where(amax > 0, (amax / 448.0).astype(np.float32).astype(np.float64), 1.0)
+        code = quantize_e4m3(Ws / sc)
+        Wq[:, :, sel] = code * sc
+        prod = (code.astype(np.float32) * sc.astype(np.float32)).astype(np.float64)
+        h = quantize_bf16(prod)
+        Wr[:, :, sel] = h + quantize_bf16(Ws - h)
+    return Wq, Wr
+
+
 def dequantized_values(inst, storage):
-    """The values the library holds for each storage type, computed here from FP64."""
+    """The values the library holds for each storage type, computed here from FP64
+    ("fp8corr": the corrected values of refinement steps)."""
     out = []
     for W in inst.W:
         if storage in ("f64",):
@@ -69,24 +89,7 @@ def dequantized_values(inst, storage):
         elif storage == "bf16":
             out.append(quantize_bf16(W))
         elif storage in ("fp8", "fp8corr"):
-            # one FP32 scale per (lag, interval, 64-OD group); "fp8corr" is the
-            # corrected value h + c of refinement steps: h = bf16(fp32(scale *
-            # code)), c = bf16(w - h)
-            K, T, nnz = W.shape
-            tiles = inst.col_idx // 64
-            Wq = np.zeros_like(W)
-            for tile in np.unique(tiles):
-                sel = tiles == tile
-                amax = np.abs(W[:, :, sel]).max(axis=2, keepdims=True)
-                sc = np.where(amax > 0, (amax / 448.0).astype(np.float32).astype(np.float64), 1.0)
-                code = quantize_e4m3(W[:, :, sel] / sc)
-                if storage == "fp8":
-                    Wq[:, :, sel] = code * sc
-                else:
-                    prod = (code.astype(np.float32) * sc.astype(np.float32)).astype(np.float64)
-                    h = quantize_bf16(prod)
-                    Wq[:, :, sel] = h + quantize_bf16(W[:, :, sel] - h)
-            out.append(Wq)
+            out.append(fp8_values(W, inst.col_idx)[0 if storage == "fp8" else 1])
     return out
 
 
