@@ -15,7 +15,7 @@
   the first and last day of three clusters (the largest, a middle one and
   the smallest).
 The config-3 plan runs the schedule the benchmark times there (32-day
-waves, chunked adjoint).
+waves, chunked adjoint, two day slabs).
 
 Bars: per-day loss after every epoch within 1e-4 relative (the FP32
 arithmetic of the kernels against FP64 on the same values), the demand
@@ -57,7 +57,7 @@ def test_config3_full_shape_bf16_plan():
     E = 3
     perms = make_perms(inst.seed + 1, E, inst.C, inst.H)
     bh = chunk_h_blocks(inst.L, inst.H, 8192)
-    Qg, hg, info = run_plan(inst, "bf16", E, perms, adj_order=2, day_tile=32)
+    Qg, hg, info = run_plan(inst, "bf16", E, perms, adj_order=2, day_tile=32, slabs=2)
     assert info["day_tile"] == 32 and info["minibatch_intervals"] == bh == 16
     sample = np.concatenate([[d[0], d[-1]] for d in (inst.days_of(c) for c in range(inst.C))])
     Wq = dequantized_values(inst, "bf16")
