@@ -289,13 +289,11 @@ struct DayGroups {
   int32_t tile;             // days per group: 16, 32 or 64 (MFMA column tiles of a wave)
 };
 
-// Work item order of the grouped kernels: (cluster, row u, group of the
-// cluster, tile k), k fastest.  All day groups of a cluster that need the same
-// assignment tiles (same cluster and row) run back to back, so the tiles are
-// fetched from HBM about once per XCD and then served by its L2; the rows of
-// consecutive groups are adjacent in the interval-major state.  `per_cluster`
-// is the row count (b_h or the reached-interval count), `n_tiles` the tiles per
-// row.  Returns the group and writes its cluster, u and k.
+// Item order of the one-launch-per-minibatch kernel's workgroups: (cluster,
+// row u, group of the cluster, tile k), k fastest (the separate launches take
+// theirs from host-built work tables instead).  `per_cluster` is the row
+// count, `n_tiles` the tiles per row.  Returns the group and writes its
+// cluster, u and k.
 __device__ __forceinline__ int decode_item(const DayGroups& dg, int item, int per_cluster,
                                            int n_tiles, int& c, int& u, int& k) {
   k = item % n_tiles;
@@ -365,6 +363,7 @@ struct dode_plan {
   // launches of every minibatch; slab 0 runs on the run's stream and slab k on
   // side stream k-1, forked and joined in every epoch, so the slabs' launches
   // overlap (days are independent, so the results do not depend on the slabs).
+  // With kernel timing on, the slabs run one after another on the run's stream.
   int32_t n_slabs = 1;
   std::vector<hipStream_t> side_streams;
   std::vector<hipEvent_t> slab_events;   // [0] fork, [1 + k] join of side stream k

@@ -129,16 +129,14 @@ __device__ __forceinline__ void store4(float* __restrict__ p, const f32x4& v, bo
 
 // Forward product and residual of the minibatch rows:
 //   R[d][s][a] = sum_l rho_c[l][h-l][a, :] . Q_d[h-l][:] - X_d[h][a],  h = perm[j0+s].
-// One wave per item (cluster, slot s, day group g, link tile i) in the order of
-// decode_item; 4 items per block; blocks remapped so each XCD walks a
-// contiguous range of items.  A wave covers NT 16-day column tiles; its
-// (lag, k-step) iterations run in batches of kBatch k-steps (3 for 32-day
-// waves, which keeps 4 waves per SIMD; 8/NT otherwise) whose operand loads
-// are all issued before the first product, so a batch costs one memory round
-// trip.  Column n of tile u is day first+16u+n; past the group's end it reads
-// day `first` and its result is dropped.
-// One forward item: link tile i of minibatch slot s (interval h) for day
-// group g of cluster c, written to the residual rows R[.][s].
+// A wave covers NT 16-day column tiles; its (lag, k-step) iterations run in
+// batches of kBatch k-steps whose operand loads are all issued before the
+// first product, so a batch costs one memory round trip.  Column n of tile u
+// is day first+16u+n; past the group's end it reads day `first` and its
+// result is dropped.
+// One forward item (the one-launch-per-minibatch kernel): link tile i of
+// minibatch slot s (interval h) for day group g of cluster c, written to the
+// residual rows R[.][s].
 template <int MODE, int NT>
 __device__ __forceinline__ void fwd_item(const DevPat& pt, const DevTiles& tl, const Layout& ly,
                                          const WaveWork& w, int h, const float* __restrict__ Q,
@@ -228,9 +226,6 @@ __device__ __forceinline__ void fwd_item(const DevPat& pt, const DevTiles& tl, c
              acc[u] - x[u], full, valid);
 }
 
-// Forward product and residual of the minibatch rows, one wave per item
-// (cluster, slot s, day group g, link tile i) in the order of decode_item;
-// 4 items per block, blocks remapped so each XCD walks a contiguous range.
 // Forward product and residual for a group of TP link tiles i0..i0+TP-1
 // (kFwdTileGroup) of one minibatch slot and day group: the tiles share their
 // OD range, so each demand operand (and its head/tail split) is loaded once
@@ -358,6 +353,9 @@ __device__ __forceinline__ WaveWork load_work(const WaveWork* __restrict__ wt, i
   return WaveWork{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
 }
 
+// Forward product and residual of the minibatch rows, one wave per entry of
+// the launch's work table (slot, day group, link-tile group of a cluster), 4
+// per block; blocks remapped so each XCD walks a contiguous range of the table.
 template <int MODE, int NT>
 __global__ void __launch_bounds__(256)
 k_fwd_mfma(DevPat pt, DevTiles tl, ChunkSched cs, const WaveWork* __restrict__ wt, int n_items,
@@ -391,10 +389,8 @@ __device__ __forceinline__ f32x4 step4(f32x4 q, f32x4& a, const f32x4& g, const 
 
 // Adjoint of the minibatch and the fused Adagrad step + projection:
 //   g_d[t][p] = sum_{l: t+l in minibatch} rho_c[l][t][:, p] . R_d[slot(t+l)][:]
-// One wave per item (cluster, reached interval index ti, day group g, OD tile
-// j) in the order of decode_item; same block remapping, batching and day
-// columns as the forward kernel.  The demand and accumulator rows are fetched
-// before the product.
+// Same batching and day columns as the forward product.  The demand and
+// accumulator rows are fetched before the product.
 // One adjoint item: OD tile j of the reached departure interval described by
 // dsc, for day group g of cluster c, with the step and projection fused.
 template <int MODE, int NT>
@@ -490,8 +486,9 @@ __device__ __forceinline__ void adj_item(const DevPat& pt, const DevTiles& tl, c
 }
 
 // Adjoint of the minibatch and the fused Adagrad step + projection, one wave
-// per item (cluster, reached interval index ti, day group g, OD tile j) in the
-// order of decode_item; same block remapping as the forward kernel.
+// per entry of the launch's work table (reached interval index, day group, OD
+// tile of a cluster), 4 per block; blocks remapped so each XCD walks a
+// contiguous range of the table.
 template <int MODE, int NT>
 __global__ void __launch_bounds__(256)
 k_adj_mfma(DevPat pt, DevTiles tl, ChunkSched cs, const WaveWork* __restrict__ wt, int n_items,
@@ -637,6 +634,9 @@ __device__ __forceinline__ void adj_chunk_item(const DevPat& pt, const DevTiles&
   }
 }
 
+// Chunked adjoint and step, one wave per entry of the launch's work table
+// (chunk, OD tile, day group of a cluster), 4 per block; blocks remapped so
+// each XCD walks a contiguous range of the table.
 template <int MODE, int NT>
 __global__ void __launch_bounds__(256)
 k_adj_chunk(DevPat pt, DevTiles tl, ChunkList ck, const WaveWork* __restrict__ wt, int n_items,
