@@ -675,6 +675,17 @@ def epoch_bytes(inst, form, s_q=None):
                            2 * inst.T * inst.P * s_a))
 
 
+def refine_step_bytes(inst, s_q=2):
+    """Algorithmic bytes of one full-batch refinement step, touched once: each
+    cluster's ratio nonzeros read once as the FP8 code and its bf16 correction
+    (3 bytes), every day's observations read once, its demand read and written
+    at s_q bytes per value and its accumulator read and written in FP32."""
+    nblk_all = sum(min(inst.K, inst.H - t) for t in range(inst.T) if t < inst.H)
+    return float(inst.C * nblk_all * inst.nnz * 3 +
+                 inst.D * (inst.H * inst.L * 4 + 2 * inst.T * inst.P * s_q +
+                           2 * inst.T * inst.P * 4))
+
+
 def spgd_leg(args, dode, torch, config, form, compare, refine, pattern=None, per_day=False,
              check=True, cpu=True, epochs=300):
     """Time one SPGD form (and the plain form beside it) on one workload, and
@@ -719,8 +730,10 @@ def spgd_leg(args, dode, torch, config, form, compare, refine, pattern=None, per
     value = inst.D / (ms_step / 1e3)
     # Roofline: the algorithmic bytes of one epoch (every array touched
     # once) over the measured epoch time.
-    B = epoch_bytes(inst, form)
-    B_q32 = epoch_bytes(inst, form, s_q=4)
+    # the refinement steps count in the time and in the bytes
+    B_mb = epoch_bytes(inst, form)
+    B = B_mb + rf[form] * refine_step_bytes(inst)
+    B_q32 = epoch_bytes(inst, form, s_q=4) + rf[form] * refine_step_bytes(inst, s_q=4)
     achieved = B / (ms_step / 1e3) / 1e9
     kms, kn = head["kernel_ms"], head["kernel_n"]
     names = ["chunk_resid (forward + residual)", "chunk_adj_step (adjoint + Adagrad + projection)"]
@@ -758,7 +771,11 @@ def spgd_leg(args, dode, torch, config, form, compare, refine, pattern=None, per
             "timed_schedule": timed_sched,
             "bytes_per_epoch": int(B),
             "bytes_basis": "touch-once bytes: ratio nonzeros once + per day X read, Q read+write "
-                           f"({ {'f64': 8, 'f32': 4}.get(form, 2)} B), A read+write (4 B)",
+                           f"({ {'f64': 8, 'f32': 4}.get(form, 2)} B), A read+write (4 B)" +
+                           (f"; plus {rf[form]} refinement steps, each the same with the ratio "
+                            "nonzeros at 3 B (FP8 code + bf16 correction)" if rf[form] else ""),
+            "frac_without_refinement_bytes": (round(B_mb / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+                                              if rf[form] else None),
             "frac_if_q_fp32": round(B_q32 / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
             "dominant_kernel": {
                 "name": names[k], "avg_launch_us": round(kms[k] / kn[k] * 1e3, 2),

@@ -156,3 +156,17 @@ def test_alu_roofline_follows_the_source_hash(monkeypatch, tmp_path):
     src.write_text("kernel text, changed\n")
     r = bench.alu_roofline("p.md", "kern", 1000.0, 8_000_000_000)
     assert r["bound"] == "hbm" and "note" in r and r["achieved"] == 8.0
+
+
+def test_refinement_step_bytes():
+    """A full-batch refinement step touches every array once like an epoch,
+    with the ratio nonzeros read as the FP8 code and its bf16 correction (3
+    bytes).  At the config-5 shapes (400 OD, 1500 links, 12 clusters of 48000
+    nonzeros per block, 1095 days): 2.96 GB of ratios + 1095 days x (1.728 MB
+    of observations + 0.4608 MB of demand + 0.9216 MB of accumulator)."""
+    inst = SimpleNamespace(P=400, L=1500, T=288, H=288, K=6, nnz=48000, C=12, D=1095)
+    nblk = 1713
+    want = 12 * nblk * 48000 * 3 + 1095 * (288 * 1500 * 4 + 2 * 288 * 400 * 2 + 2 * 288 * 400 * 4)
+    assert bench.refine_step_bytes(inst) == want
+    assert abs(want - 6.3656e9) < 1e6
+    assert bench.refine_step_bytes(inst, s_q=4) == want + 1095 * 2 * 288 * 400 * 2
